@@ -1,0 +1,190 @@
+/*
+ * salprior -- C-ABI of the MI355X (gfx950) saliency -> Kalman prior -> MRF weight path.
+ *
+ * The method follows Akamine, Fukuchi, Kimura, Takagi, "Fully automatic extraction of
+ * salient objects from videos in near real-time" (arXiv:1008.0502):
+ *   - the saliency map of each frame from intensity, colour-opponent, orientation and
+ *     motion features (Section 3; GPU steps in Section 7.2: pixel-wise features,
+ *     Gaussian pyramids, normalisation by global and local extrema, weighted sum);
+ *   - the saliency-based prior with a near-zero prior on the frame edge (Section 5);
+ *   - the Kalman update of the prior from the previous frame (Section 6);
+ *   - the unary (t-link) and pairwise (n-link) capacities of the MRF whose minimum cut
+ *     gives the segmentation (Section 4, Eqs. 1-4).  The cut itself is not part of
+ *     this library.
+ *
+ * Conventions for every call:
+ *   - All image/map pointers are DEVICE pointers on the context's GPU, row-major,
+ *     tightly packed, owned by the caller, and must stay valid until the work
+ *     enqueued on the context's HIP stream has run.  RGB frames are uint8 [H][W][3].
+ *   - Calls enqueue asynchronously on the context's stream and never synchronise
+ *     (saliency_backward copies a few scalars host->device first).  Device faults
+ *     surface at the caller's next synchronisation.
+ *   - Return 0 on success or a negative SP_E* code; sp_last_error() (per host thread)
+ *     then describes the failure.  No C++ exception crosses this interface.  A failed
+ *     call leaves the context usable.
+ */
+#ifndef SALPRIOR_H
+#define SALPRIOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SP_OK 0
+#define SP_EINVAL (-1) /* bad argument (NULL, non-finite or out-of-range parameter) */
+#define SP_ESHAPE (-2) /* frame too small / too large for the requested pyramid */
+#define SP_ENOMEM (-3) /* device allocation failed */
+#define SP_EHIP (-4)   /* a HIP runtime call failed; the message names it */
+#define SP_ESTATE (-5) /* call not valid in the context's state (e.g. no tape) */
+
+#define SP_NCHANNELS 8 /* I, RG, BY, O0, O45, O90, O135, M */
+#define SP_MAX_LEVELS 12
+
+typedef struct sp_ctx sp_ctx;
+typedef struct sp_batch sp_batch;
+
+/* Parameters.  sp_default_params() fills the defaults noted below. */
+typedef struct sp_params {
+  int32_t depth;       /* pyramid depth D; <= 0: floor(log2(min(H, W))) - 1 */
+  int32_t n_centers;   /* number of centre levels, 1..4 (default 2: {1, 2}) */
+  int32_t centers[4];
+  int32_t n_deltas;    /* number of centre-surround offsets, 1..4 (default 2: {2, 3}) */
+  int32_t deltas[4];   /* pairs (c, c + delta) whose surround exceeds D are dropped */
+  float weights[8];    /* channel weights of the saliency sum, order as SP_NCHANNELS (1) */
+  double q;            /* Kalman process variance Q = sigma_2^2 of Section 6 (1e-3) */
+  double r;            /* Kalman observation-side variance R = sigma_1^2 (1e-1) */
+  float eps;           /* near-zero prior: border value and clamp of q (1e-4) */
+  int32_t border;      /* width of the border ring whose prior is eps (1) */
+  float lambda;        /* contrast weight of the pairwise capacity (1) */
+  float potts;         /* constant of the generalised Potts prior (0) */
+  int32_t lm_block;    /* block edge of the local maxima in N(.): must be 8 */
+  float flat_tol;      /* a map whose range is <= flat_tol normalises to 0 (1e-5) */
+  float gabor_lambda;  /* Gabor wavelength in pixels (4) */
+  float gabor_sigma;   /* Gabor envelope sigma (2) */
+  int32_t gabor_radius;/* Gabor kernel radius, 1..8 (6: a 13x13 kernel) */
+  int32_t record_tape; /* >0: frames the adjoint tape can hold (0: no tape) */
+} sp_params;
+
+/* Geometry of a context, as derived by sp_create. */
+typedef struct sp_geometry {
+  int32_t H, W;          /* level-0 size */
+  int32_t depth;         /* D */
+  int32_t top;           /* deepest level any pair uses */
+  int32_t c_min, c_max;  /* smallest and largest centre level with a pair */
+  int32_t n_pairs;
+  int32_t pair_c[16], pair_s[16];
+  int32_t level_h[SP_MAX_LEVELS + 1], level_w[SP_MAX_LEVELS + 1];
+  int32_t Hc, Wc;        /* size of the saliency map = level c_max */
+} sp_geometry;
+
+/* Fills p with the defaults listed in sp_params.  p must not be NULL. */
+void sp_default_params(sp_params* p);
+
+/* Creates a context for H x W frames on the current HIP device, enqueuing on
+ * hip_stream (a hipStream_t; NULL = the default stream).  Validates p against H and W
+ * and allocates every buffer the context will use (scratch, pyramid, Kalman state,
+ * tape); no later call allocates device memory.  *out receives the context. */
+int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx** out);
+
+/* Frees everything the context owns (after synchronising its stream).  NULL is a no-op. */
+int sp_destroy(sp_ctx* ctx);
+
+/* Changes the stream later calls enqueue on. */
+int sp_set_stream(sp_ctx* ctx, void* hip_stream);
+
+/* Copies the context's geometry to *out. */
+int sp_get_geometry(const sp_ctx* ctx, sp_geometry* out);
+
+/* Replaces the channel weights and the Kalman variances (finite, q >= 0, r >= 0,
+ * q + r > 0).  Takes effect from the next call; the gain sequence restarts only on
+ * sp_reset. */
+int sp_set_weights(sp_ctx* ctx, const float* weights8, double q, double r);
+
+/* Starts a new clip: the next prior_update is step t = 0 (prior = observation) and the
+ * tape is emptied. */
+int sp_reset(sp_ctx* ctx);
+
+/* Step index the next prior_update will run (frames updated since sp_reset). */
+int64_t sp_step_index(const sp_ctx* ctx);
+
+/* Saliency map of one frame (Section 3; Section 7.2).
+ *   rgb_t    [H][W][3] uint8, frame t.
+ *   rgb_prev [H][W][3] uint8, frame t-1, or NULL (first frame: the motion feature is 0).
+ *   S_out    [Hc][Wc] float: S = sum_k w_k C_k.
+ *   C_out    [8][Hc][Wc] float conspicuity maps, or NULL.
+ * When the context records a tape, the checkpoint of this frame's pyramid level c_min
+ * and S are stored for the adjoint. */
+int saliency_forward(sp_ctx* ctx, const uint8_t* rgb_t, const uint8_t* rgb_prev, float* S_out, float* C_out);
+
+/* Kalman prior update (Section 6) from a saliency map (Section 5).
+ *   S          [Hc][Wc] float, normally the S_out of saliency_forward for this frame.
+ *   seg_prev   [H][W] uint8 labels {0,1} of the previous frame (the caller's graph cut),
+ *              or NULL: the previous prior stands in for it.
+ *   prior_out  [H][W] float receives p-hat(A_{x,t} = 1); may be NULL (the context keeps
+ *              its own copy as the Kalman state).
+ * q_t = clamp(upsample(S / max S), eps, 1 - eps) with q = eps on the border ring and
+ * q = 0.5 when max S <= flat_tol; t = 0: prior = q_0; t >= 1: f = G * prev,
+ * prior = f + K_t (q_t - f), K_t = (P_{t-1} + Q) / (P_{t-1} + Q + R), P_t = R K_t,
+ * prior = eps on the border ring.  Advances the step index. */
+int prior_update(sp_ctx* ctx, const float* S, const uint8_t* seg_prev, float* prior_out);
+
+/* MRF capacities (Section 4, Eqs. 1-4) of one frame and its prior.
+ *   rgb_t        [H][W][3] uint8.
+ *   prior        [H][W] float p(A_x = 1).
+ *   unary_out    [2][H][W] float: U0 = -ln(1 - min(p, 1-eps)) (cost of label 0,
+ *                background) and U1 = -ln max(p, eps) (cost of label 1, object).
+ *   pairwise_out [4][H][W] float: capacity between (y, x) and its E, S, SE, SW
+ *                neighbour, potts + lambda * exp(-beta ||dC||^2) / ||dx||, 0 outside.
+ *   beta_out     [1] float or NULL: beta = 1 / (2 mean ||dC||^2) over all 8-neighbour
+ *                pairs (0 for a constant frame). */
+int mrf_weights(sp_ctx* ctx, const uint8_t* rgb_t, const float* prior, float* unary_out, float* pairwise_out,
+                float* beta_out);
+
+/* Adjoint of the clip recorded since sp_reset (requires record_tape >= T and exactly T
+ * prior updates since the reset).
+ *   grad_prior [T][H][W] float: dL/d prior_t for every recorded step.
+ *   grad_w [8], grad_q [1], grad_r [1] float (device): dL/dw, dL/dQ, dL/dR.
+ * The conspicuity maps are recomputed from the checkpointed pyramid level c_min. */
+int saliency_backward(sp_ctx* ctx, const float* grad_prior, int32_t T, float* grad_w, float* grad_q,
+                      float* grad_r);
+
+/* Fitting loss helper: loss = mean over [T][H][W] of (prior - mask)^2 and its gradient.
+ *   prior [T][H][W] float, mask [T][H][W] uint8 {0,1}, loss [1] float,
+ *   grad_prior [T][H][W] float or NULL. */
+int sp_mse_mask_loss(sp_ctx* ctx, const float* prior, const uint8_t* mask, int32_t T, float* loss,
+                     float* grad_prior);
+
+/* Checkpoint / resume of the Kalman state: the prior of the last step plus the step
+ * index and variance.  sp_state_size gives the byte size; buffers are device memory. */
+int sp_state_size(const sp_ctx* ctx, size_t* bytes);
+int sp_get_state(sp_ctx* ctx, void* dev_buf, size_t bytes);
+int sp_set_state(sp_ctx* ctx, const void* dev_buf, size_t bytes);
+
+/* Batched form: n independent streams of possibly different sizes, one frame each per
+ * step, every phase of the step in one launch over all streams, the step captured once
+ * in a HIP graph and replayed.  Each stream keeps its Kalman state on the device.
+ *   H[n], W[n]: host arrays.  p: shared parameters (record_tape must be 0). */
+int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32_t* W, void* hip_stream,
+                    sp_batch** out);
+
+/* One step.  rgb_ptrs: DEVICE array of n device pointers to this step's frames (read
+ * when the step runs; the frames must stay valid until the next step has run, which
+ * reads them as the previous frames).  prior_ptrs: DEVICE array of n device pointers
+ * receiving the priors, or NULL (then read them with sp_batch_prior). */
+int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* prior_ptrs);
+
+/* Device pointer to stream i's current prior (valid until the next step). */
+int sp_batch_prior(sp_batch* b, int32_t i, const float** prior);
+int sp_batch_reset(sp_batch* b);
+int sp_batch_destroy(sp_batch* b);
+
+/* Description of the last error on this host thread ("" if none). */
+const char* sp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SALPRIOR_H */

@@ -1,0 +1,118 @@
+"""ctypes declarations of the salprior C-ABI (include/salprior.h).
+
+Loading fails loudly when the built library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsalprior.so")
+
+SP_OK, SP_EINVAL, SP_ESHAPE, SP_ENOMEM, SP_EHIP, SP_ESTATE = 0, -1, -2, -3, -4, -5
+ERROR_NAMES = {SP_EINVAL: "SP_EINVAL", SP_ESHAPE: "SP_ESHAPE", SP_ENOMEM: "SP_ENOMEM",
+               SP_EHIP: "SP_EHIP", SP_ESTATE: "SP_ESTATE"}
+MAX_LEVELS = 12
+
+c_int32 = ctypes.c_int32
+c_float = ctypes.c_float
+c_double = ctypes.c_double
+c_void_p = ctypes.c_void_p
+c_size_t = ctypes.c_size_t
+
+
+class sp_params(ctypes.Structure):
+    _fields_ = [
+        ("depth", c_int32),
+        ("n_centers", c_int32),
+        ("centers", c_int32 * 4),
+        ("n_deltas", c_int32),
+        ("deltas", c_int32 * 4),
+        ("weights", c_float * 8),
+        ("q", c_double),
+        ("r", c_double),
+        ("eps", c_float),
+        ("border", c_int32),
+        ("lambda_", c_float),
+        ("potts", c_float),
+        ("lm_block", c_int32),
+        ("flat_tol", c_float),
+        ("gabor_lambda", c_float),
+        ("gabor_sigma", c_float),
+        ("gabor_radius", c_int32),
+        ("record_tape", c_int32),
+    ]
+
+
+class sp_geometry(ctypes.Structure):
+    _fields_ = [
+        ("H", c_int32), ("W", c_int32), ("depth", c_int32), ("top", c_int32),
+        ("c_min", c_int32), ("c_max", c_int32), ("n_pairs", c_int32),
+        ("pair_c", c_int32 * 16), ("pair_s", c_int32 * 16),
+        ("level_h", c_int32 * (MAX_LEVELS + 1)), ("level_w", c_int32 * (MAX_LEVELS + 1)),
+        ("Hc", c_int32), ("Wc", c_int32),
+    ]
+
+
+# (name, restype, argtypes) of every exported symbol, in header order.
+SIGNATURES = [
+    ("sp_default_params", None, [ctypes.POINTER(sp_params)]),
+    ("sp_create", c_int32, [ctypes.POINTER(sp_params), c_int32, c_int32, c_void_p, ctypes.POINTER(c_void_p)]),
+    ("sp_destroy", c_int32, [c_void_p]),
+    ("sp_set_stream", c_int32, [c_void_p, c_void_p]),
+    ("sp_get_geometry", c_int32, [c_void_p, ctypes.POINTER(sp_geometry)]),
+    ("sp_set_weights", c_int32, [c_void_p, ctypes.POINTER(c_float), c_double, c_double]),
+    ("sp_reset", c_int32, [c_void_p]),
+    ("sp_step_index", ctypes.c_int64, [c_void_p]),
+    ("saliency_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("prior_update", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("mrf_weights", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("saliency_backward", c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    ("sp_mse_mask_loss", c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    ("sp_state_size", c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
+    ("sp_get_state", c_int32, [c_void_p, c_void_p, c_size_t]),
+    ("sp_set_state", c_int32, [c_void_p, c_void_p, c_size_t]),
+    ("sp_batch_create", c_int32, [ctypes.POINTER(sp_params), c_int32, ctypes.POINTER(c_int32),
+                                  ctypes.POINTER(c_int32), c_void_p, ctypes.POINTER(c_void_p)]),
+    ("sp_batch_step", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("sp_batch_prior", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
+    ("sp_batch_reset", c_int32, [c_void_p]),
+    ("sp_batch_destroy", c_int32, [c_void_p]),
+    ("sp_last_error", ctypes.c_char_p, []),
+]
+
+_LIB = None
+
+
+class SalpriorError(RuntimeError):
+    def __init__(self, code: int, where: str, message: str):
+        super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsalprior.so (after torch, so both share one HIP runtime)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"salprior HIP library not built: {path} is missing "
+                           "(run `python -m paper_1008_0502_amd.build`)")
+    try:
+        import torch  # noqa: F401  -- load torch's HIP runtime first
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def check(rc: int, where: str) -> None:
+    if rc != SP_OK:
+        msg = _LIB.sp_last_error().decode(errors="replace") if _LIB is not None else ""
+        raise SalpriorError(rc, where, msg)

@@ -1,0 +1,288 @@
+"""Thin PyTorch binding of the salprior C-ABI.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libsalprior.so.  PyTorch provides device memory (output tensors) and the current
+HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+CHANNELS = ("I", "RG", "BY", "O0", "O45", "O90", "O135", "M")
+
+
+@dataclasses.dataclass
+class Params:
+    """Mirror of struct sp_params (defaults as sp_default_params)."""
+    depth: int = 0
+    centers: Tuple[int, ...] = (1, 2)
+    deltas: Tuple[int, ...] = (2, 3)
+    weights: Tuple[float, ...] = (1.0,) * 8
+    q: float = 1e-3
+    r: float = 1e-1
+    eps: float = 1e-4
+    border: int = 1
+    lam: float = 1.0
+    potts: float = 0.0
+    lm_block: int = 8
+    flat_tol: float = 1e-5
+    gabor_lambda: float = 4.0
+    gabor_sigma: float = 2.0
+    gabor_radius: int = 6
+    record_tape: int = 0
+
+    def to_c(self) -> _lib.sp_params:
+        p = _lib.sp_params()
+        p.depth = int(self.depth)
+        if not 1 <= len(self.centers) <= 4 or not 1 <= len(self.deltas) <= 4:
+            raise ValueError("1..4 centre levels and 1..4 offsets are supported")
+        p.n_centers = len(self.centers)
+        for i, c in enumerate(self.centers):
+            p.centers[i] = int(c)
+        p.n_deltas = len(self.deltas)
+        for i, d in enumerate(self.deltas):
+            p.deltas[i] = int(d)
+        if len(self.weights) != 8:
+            raise ValueError("8 channel weights are required")
+        for i, w in enumerate(self.weights):
+            p.weights[i] = float(w)
+        p.q, p.r = float(self.q), float(self.r)
+        p.eps = float(self.eps)
+        p.border = int(self.border)
+        p.lambda_ = float(self.lam)
+        p.potts = float(self.potts)
+        p.lm_block = int(self.lm_block)
+        p.flat_tol = float(self.flat_tol)
+        p.gabor_lambda = float(self.gabor_lambda)
+        p.gabor_sigma = float(self.gabor_sigma)
+        p.gabor_radius = int(self.gabor_radius)
+        p.record_tape = int(self.record_tape)
+        return p
+
+
+@dataclasses.dataclass
+class Geometry:
+    H: int
+    W: int
+    depth: int
+    top: int
+    c_min: int
+    c_max: int
+    pairs: List[Tuple[int, int]]
+    sizes: List[Tuple[int, int]]
+    Hc: int
+    Wc: int
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _need(t: torch.Tensor, name: str, dtype: torch.dtype, shape: Sequence[int], device: torch.device) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device} (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """One video stream of H x W frames on the current CUDA (HIP) device."""
+
+    def __init__(self, H: int, W: int, params: Optional[Params] = None, device=None):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("salprior needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self.params = params or Params()
+        self._handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            cp = self.params.to_c()
+            check(self.lib.sp_create(ctypes.byref(cp), int(H), int(W), _stream(), ctypes.byref(self._handle)),
+                  "sp_create")
+        g = _lib.sp_geometry()
+        check(self.lib.sp_get_geometry(self._handle, ctypes.byref(g)), "sp_get_geometry")
+        self.geometry = Geometry(
+            H=g.H, W=g.W, depth=g.depth, top=g.top, c_min=g.c_min, c_max=g.c_max,
+            pairs=[(g.pair_c[i], g.pair_s[i]) for i in range(g.n_pairs)],
+            sizes=[(g.level_h[l], g.level_w[l]) for l in range(g.depth + 1)], Hc=g.Hc, Wc=g.Wc)
+        self.H, self.W = H, W
+
+    # -- lifecycle ----------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            check(self.lib.sp_destroy(self._handle), "sp_destroy")
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind_stream(self) -> None:
+        check(self.lib.sp_set_stream(self._handle, _stream()), "sp_set_stream")
+
+    def reset(self) -> None:
+        check(self.lib.sp_reset(self._handle), "sp_reset")
+
+    @property
+    def step_index(self) -> int:
+        return int(self.lib.sp_step_index(self._handle))
+
+    def set_weights(self, weights: Sequence[float], q: float, r: float) -> None:
+        w = (ctypes.c_float * 8)(*[float(x) for x in weights])
+        self._bind_stream()
+        check(self.lib.sp_set_weights(self._handle, w, float(q), float(r)), "sp_set_weights")
+        self.params = dataclasses.replace(self.params, weights=tuple(float(x) for x in weights), q=q, r=r)
+
+    # -- the four calls -----------------------------------------------------
+    def saliency_forward(self, rgb_t: torch.Tensor, rgb_prev: Optional[torch.Tensor] = None,
+                         S_out: Optional[torch.Tensor] = None, C_out: Optional[torch.Tensor] = None,
+                         want_C: bool = False):
+        g = self.geometry
+        _need(rgb_t, "rgb_t", torch.uint8, (g.H, g.W, 3), self.device)
+        if rgb_prev is not None:
+            _need(rgb_prev, "rgb_prev", torch.uint8, (g.H, g.W, 3), self.device)
+        if S_out is None:
+            S_out = torch.empty((g.Hc, g.Wc), dtype=torch.float32, device=self.device)
+        _need(S_out, "S_out", torch.float32, (g.Hc, g.Wc), self.device)
+        if C_out is None and want_C:
+            C_out = torch.empty((8, g.Hc, g.Wc), dtype=torch.float32, device=self.device)
+        if C_out is not None:
+            _need(C_out, "C_out", torch.float32, (8, g.Hc, g.Wc), self.device)
+        self._bind_stream()
+        check(self.lib.saliency_forward(self._handle, _ptr(rgb_t), _ptr(rgb_prev), _ptr(S_out), _ptr(C_out)),
+              "saliency_forward")
+        return S_out, C_out
+
+    def prior_update(self, S: torch.Tensor, seg_prev: Optional[torch.Tensor] = None,
+                     prior_out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        g = self.geometry
+        _need(S, "S", torch.float32, (g.Hc, g.Wc), self.device)
+        if seg_prev is not None:
+            _need(seg_prev, "seg_prev", torch.uint8, (g.H, g.W), self.device)
+        if prior_out is None:
+            prior_out = torch.empty((g.H, g.W), dtype=torch.float32, device=self.device)
+        _need(prior_out, "prior_out", torch.float32, (g.H, g.W), self.device)
+        self._bind_stream()
+        check(self.lib.prior_update(self._handle, _ptr(S), _ptr(seg_prev), _ptr(prior_out)), "prior_update")
+        return prior_out
+
+    def mrf_weights(self, rgb_t: torch.Tensor, prior: torch.Tensor, unary_out=None, pairwise_out=None,
+                    beta_out=None):
+        g = self.geometry
+        _need(rgb_t, "rgb_t", torch.uint8, (g.H, g.W, 3), self.device)
+        _need(prior, "prior", torch.float32, (g.H, g.W), self.device)
+        if unary_out is None:
+            unary_out = torch.empty((2, g.H, g.W), dtype=torch.float32, device=self.device)
+        if pairwise_out is None:
+            pairwise_out = torch.empty((4, g.H, g.W), dtype=torch.float32, device=self.device)
+        if beta_out is None:
+            beta_out = torch.empty((1,), dtype=torch.float32, device=self.device)
+        _need(unary_out, "unary_out", torch.float32, (2, g.H, g.W), self.device)
+        _need(pairwise_out, "pairwise_out", torch.float32, (4, g.H, g.W), self.device)
+        _need(beta_out, "beta_out", torch.float32, (1,), self.device)
+        self._bind_stream()
+        check(self.lib.mrf_weights(self._handle, _ptr(rgb_t), _ptr(prior), _ptr(unary_out), _ptr(pairwise_out),
+                                   _ptr(beta_out)), "mrf_weights")
+        return unary_out, pairwise_out, beta_out
+
+    def saliency_backward(self, grad_prior: torch.Tensor):
+        g = self.geometry
+        T = grad_prior.shape[0]
+        _need(grad_prior, "grad_prior", torch.float32, (T, g.H, g.W), self.device)
+        gw = torch.empty(8, dtype=torch.float32, device=self.device)
+        gq = torch.empty(1, dtype=torch.float32, device=self.device)
+        gr = torch.empty(1, dtype=torch.float32, device=self.device)
+        self._bind_stream()
+        check(self.lib.saliency_backward(self._handle, _ptr(grad_prior), int(T), _ptr(gw), _ptr(gq), _ptr(gr)),
+              "saliency_backward")
+        return gw, gq, gr
+
+    def mse_mask_loss(self, prior: torch.Tensor, mask: torch.Tensor, want_grad: bool = True):
+        g = self.geometry
+        T = prior.shape[0]
+        _need(prior, "prior", torch.float32, (T, g.H, g.W), self.device)
+        _need(mask, "mask", torch.uint8, (T, g.H, g.W), self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty_like(prior) if want_grad else None
+        self._bind_stream()
+        check(self.lib.sp_mse_mask_loss(self._handle, _ptr(prior), _ptr(mask), int(T), _ptr(loss), _ptr(grad)),
+              "sp_mse_mask_loss")
+        return loss, grad
+
+    # -- checkpoint / resume ------------------------------------------------
+    def state_size(self) -> int:
+        n = ctypes.c_size_t()
+        check(self.lib.sp_state_size(self._handle, ctypes.byref(n)), "sp_state_size")
+        return int(n.value)
+
+    def get_state(self) -> torch.Tensor:
+        buf = torch.empty(self.state_size(), dtype=torch.uint8, device=self.device)
+        self._bind_stream()
+        check(self.lib.sp_get_state(self._handle, _ptr(buf), buf.numel()), "sp_get_state")
+        return buf
+
+    def set_state(self, buf: torch.Tensor) -> None:
+        _need(buf, "state", torch.uint8, (self.state_size(),), self.device)
+        self._bind_stream()
+        check(self.lib.sp_set_state(self._handle, _ptr(buf), buf.numel()), "sp_set_state")
+
+    # -- convenience: a whole clip -------------------------------------------
+    def run_clip(self, frames: torch.Tensor, with_mrf: bool = False, want_C: bool = False, segs=None):
+        """frames: uint8 [T][H][W][3] on the device.  Resets, then runs every frame."""
+        T = frames.shape[0]
+        g = self.geometry
+        self.reset()
+        S = torch.empty((T, g.Hc, g.Wc), dtype=torch.float32, device=self.device)
+        C = torch.empty((T, 8, g.Hc, g.Wc), dtype=torch.float32, device=self.device) if want_C else None
+        P = torch.empty((T, g.H, g.W), dtype=torch.float32, device=self.device)
+        U = torch.empty((T, 2, g.H, g.W), dtype=torch.float32, device=self.device) if with_mrf else None
+        PW = torch.empty((T, 4, g.H, g.W), dtype=torch.float32, device=self.device) if with_mrf else None
+        B = torch.empty((T, 1), dtype=torch.float32, device=self.device) if with_mrf else None
+        for t in range(T):
+            self.saliency_forward(frames[t], frames[t - 1] if t > 0 else None, S[t], None if C is None else C[t])
+            seg = None if segs is None else segs[t]
+            self.prior_update(S[t], seg, P[t])
+            if with_mrf:
+                self.mrf_weights(frames[t], P[t], U[t], PW[t], B[t])
+        return {"S": S, "C": C, "pi": P, "unary": U, "pairwise": PW, "beta": B}
+
+
+class SaliencyPrior(torch.autograd.Function):
+    """prior[T][H][W] = path(frames; w, q, r), differentiable in w (8), q and r.
+
+    forward(ctx_obj, frames, w, q, r): ctx_obj is a Context created with
+    record_tape >= T.  The backward calls the hand-written adjoint kernels."""
+
+    @staticmethod
+    def forward(ctx, sp: Context, frames: torch.Tensor, w: torch.Tensor, q: torch.Tensor, r: torch.Tensor):
+        sp.set_weights(w.detach().float().cpu().tolist(), float(q), float(r))
+        out = sp.run_clip(frames)
+        ctx.sp = sp
+        ctx.T = frames.shape[0]
+        return out["pi"]
+
+    @staticmethod
+    def backward(ctx, grad_pi: torch.Tensor):
+        sp: Context = ctx.sp
+        gw, gq, gr = sp.saliency_backward(grad_pi.contiguous().float())
+        return None, None, gw, gq.reshape(()), gr.reshape(())

@@ -1,0 +1,1011 @@
+// Host runtime of the salprior C-ABI: parameter validation, geometry, device memory
+// layout, job tables, Kalman gain bookkeeping, the adjoint driver and the batched
+// graph-replayed step.  Every device buffer is allocated in sp_create /
+// sp_batch_create; the per-frame calls only enqueue kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "salprior.h"
+#include "sp_internal.h"
+#include "sp_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return fail(SP_EHIP, "%s: %s (%d)", #expr, hipGetErrorString(e_), (int)e_); \
+  } while (0)
+
+constexpr int kTile = 16;   // tile edge of every tiled phase
+
+// ---------------------------------------------------------------- geometry
+struct Geo {
+  int H = 0, W = 0, depth = 0, top = 0, c_min = 0, c_max = 0, n_pairs = 0;
+  int pc[SP_MAXP] = {}, ps[SP_MAXP] = {};
+  int Hl[SP_MAXL] = {}, Wl[SP_MAXL] = {};
+  unsigned used = 0;   // bit l: level l is a centre or surround
+};
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+int validate_params(const sp_params* p) {
+  if (!p) return fail(SP_EINVAL, "params is NULL");
+  if (p->n_centers < 1 || p->n_centers > 4) return fail(SP_EINVAL, "n_centers must be 1..4 (got %d)", p->n_centers);
+  if (p->n_deltas < 1 || p->n_deltas > 4) return fail(SP_EINVAL, "n_deltas must be 1..4 (got %d)", p->n_deltas);
+  for (int i = 0; i < p->n_centers; ++i)
+    if (p->centers[i] < 1 || p->centers[i] > SP_MAX_LEVELS)
+      return fail(SP_EINVAL, "centre levels must be 1..%d (got %d)", SP_MAX_LEVELS, p->centers[i]);
+  for (int i = 0; i < p->n_deltas; ++i)
+    if (p->deltas[i] < 1 || p->deltas[i] > SP_MAX_LEVELS)
+      return fail(SP_EINVAL, "centre-surround offsets must be 1..%d (got %d)", SP_MAX_LEVELS, p->deltas[i]);
+  for (int k = 0; k < SP_NCH; ++k)
+    if (!is_fin(p->weights[k])) return fail(SP_EINVAL, "weight %d is not finite", k);
+  if (!is_fin(p->q) || !is_fin(p->r) || p->q < 0 || p->r < 0 || !(p->q + p->r > 0))
+    return fail(SP_EINVAL, "Kalman variances must be finite, >= 0 and not both 0 (q=%g r=%g)", p->q, p->r);
+  if (!is_fin(p->eps) || !(p->eps > 0.f) || !(p->eps < 0.5f)) return fail(SP_EINVAL, "eps must be in (0, 0.5)");
+  if (p->border < 0) return fail(SP_EINVAL, "border must be >= 0");
+  if (!is_fin(p->lambda) || p->lambda < 0 || !is_fin(p->potts) || p->potts < 0)
+    return fail(SP_EINVAL, "lambda and potts must be finite and >= 0");
+  if (p->lm_block != 8) return fail(SP_EINVAL, "lm_block must be 8 (got %d)", p->lm_block);
+  if (!is_fin(p->flat_tol) || p->flat_tol < 0) return fail(SP_EINVAL, "flat_tol must be finite and >= 0");
+  if (!is_fin(p->gabor_lambda) || !(p->gabor_lambda > 0) || !is_fin(p->gabor_sigma) || !(p->gabor_sigma > 0))
+    return fail(SP_EINVAL, "Gabor wavelength and sigma must be finite and > 0");
+  if (p->gabor_radius < 1 || p->gabor_radius > SP_MAXR) return fail(SP_EINVAL, "gabor_radius must be 1..%d", SP_MAXR);
+  if (p->record_tape < 0 || p->record_tape > (1 << 20)) return fail(SP_EINVAL, "record_tape must be 0..2^20");
+  return SP_OK;
+}
+
+int make_geo(const sp_params& p, int H, int W, Geo& g) {
+  if (H < 1 || W < 1) return fail(SP_ESHAPE, "frame must be at least 1x1 (got %dx%d)", H, W);
+  if ((long long)H * W > (1LL << 28) || H > 65535 || W > 65535)
+    return fail(SP_ESHAPE, "frame %dx%d exceeds the 2^28-pixel / 65535-edge limit", H, W);
+  g.H = H;
+  g.W = W;
+  int D = p.depth;
+  if (D <= 0) {
+    int m = std::min(H, W), lg = 0;
+    while ((2 << lg) <= m) ++lg;   // floor(log2 m)
+    D = lg - 1;
+  }
+  if (D < 1) return fail(SP_ESHAPE, "frame %dx%d too small for a pyramid", H, W);
+  if (D > SP_MAX_LEVELS) return fail(SP_ESHAPE, "pyramid depth %d exceeds %d", D, SP_MAX_LEVELS);
+  g.depth = D;
+  g.Hl[0] = H;
+  g.Wl[0] = W;
+  for (int l = 1; l <= D; ++l) {
+    g.Hl[l] = (g.Hl[l - 1] + 1) / 2;
+    g.Wl[l] = (g.Wl[l - 1] + 1) / 2;
+  }
+  g.n_pairs = 0;
+  g.c_min = 1 << 30;
+  g.c_max = -1;
+  g.top = 0;
+  for (int i = 0; i < p.n_centers; ++i)
+    for (int j = 0; j < p.n_deltas; ++j) {
+      const int c = p.centers[i], s = c + p.deltas[j];
+      if (s > D) continue;
+      if (g.n_pairs >= SP_MAXP) return fail(SP_EINVAL, "more than %d centre-surround pairs", SP_MAXP);
+      g.pc[g.n_pairs] = c;
+      g.ps[g.n_pairs] = s;
+      ++g.n_pairs;
+      g.c_min = std::min(g.c_min, c);
+      g.c_max = std::max(g.c_max, c);
+      g.top = std::max(g.top, s);
+      g.used |= (1u << c) | (1u << s);
+    }
+  if (g.n_pairs == 0) return fail(SP_ESHAPE, "no centre-surround pair fits pyramid depth %d", D);
+  if (g.c_max - g.c_min > 2)
+    return fail(SP_ESHAPE, "centre levels may span at most 2 octaves (got %d..%d)", g.c_min, g.c_max);
+  for (int a = 0; a < g.n_pairs; ++a)
+    for (int b = 0; b < a; ++b)
+      if (g.pc[a] == g.pc[b] && g.ps[a] == g.ps[b]) return fail(SP_EINVAL, "duplicate centre-surround pair");
+  return SP_OK;
+}
+
+int ntiles(int h, int w) { return ((h + kTile - 1) / kTile) * ((w + kTile - 1) / kTile); }
+
+void add_tiles(std::vector<Job>& v, int stream, int a, int h, int w) {
+  int tid = 0;
+  for (int y0 = 0; y0 < h; y0 += kTile)
+    for (int x0 = 0; x0 < w; x0 += kTile)
+      v.push_back(Job{stream, a, y0, x0, std::min(kTile, h - y0), std::min(kTile, w - x0), tid++, 0});
+}
+
+// ---------------------------------------------------------------- device memory layout
+struct Bump {
+  char* base = nullptr;   // null during the sizing pass
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+void fill_taps(StreamDesc& sd, const sp_params& p) {
+  const int R = p.gabor_radius;
+  const double s2 = 2.0 * (double)p.gabor_sigma * (double)p.gabor_sigma;
+  const double k = 2.0 * M_PI / (double)p.gabor_lambda;
+  const double alpha = k * std::cos(M_PI / 4.0);
+  double g[2 * SP_MAXR + 1], sg = 0, sgc = 0;
+  for (int u = -R; u <= R; ++u) {
+    g[u + R] = std::exp(-(double)(u * u) / s2);
+    sg += g[u + R];
+    sgc += g[u + R] * std::cos(k * u);
+  }
+  const double c0 = sgc / sg;
+  double sc = 0, ss = 0;
+  for (int u = -R; u <= R; ++u) {
+    sc += g[u + R] * std::cos(alpha * u);
+    ss += g[u + R] * std::sin(alpha * u);
+  }
+  for (int u = -R; u <= R; ++u) {
+    const double gu = g[u + R];
+    sd.gf[0][u + R] = (float)gu;
+    sd.gf[1][u + R] = (float)(gu * (std::cos(k * u) - c0));
+    sd.gf[2][u + R] = (float)(gu * std::cos(alpha * u));
+    sd.gf[3][u + R] = (float)(gu * std::sin(alpha * u));
+  }
+  sd.c45 = (float)((sc * sc - ss * ss) / (sg * sg));
+  sd.gr = R;
+}
+
+// Fills the geometry/parameter part of a stream description and takes its scratch
+// from `bump`.  Levels below `first_level` get no base storage (level c_min of a
+// recompute stream reads its checkpoint instead).
+void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump, int first_level, bool rgb_parts) {
+  std::memset(&sd, 0, sizeof sd);
+  sd.H = g.H;
+  sd.W = g.W;
+  sd.top = g.top;
+  sd.c_min = g.c_min;
+  sd.c_max = g.c_max;
+  sd.n_pairs = g.n_pairs;
+  sd.border = p.border;
+  for (int i = 0; i < g.n_pairs; ++i) {
+    sd.pc[i] = g.pc[i];
+    sd.ps[i] = g.ps[i];
+  }
+  for (int l = 0; l < SP_MAXL; ++l) {
+    sd.Hl[l] = g.Hl[l];
+    sd.Wl[l] = g.Wl[l];
+    sd.ntiles_lvl[l] = (l <= g.depth) ? ntiles(g.Hl[l], g.Wl[l]) : 0;
+  }
+  int off = 0;
+  for (int i = 0; i < g.n_pairs; ++i) {
+    sd.cs_off[i] = off;
+    off += SP_NCH * sd.ntiles_lvl[g.pc[i]];
+  }
+  sd.n_cmax_tiles = sd.ntiles_lvl[g.c_max];
+  for (int k = 0; k < SP_NCH; ++k) sd.w[k] = p.weights[k];
+  sd.eps = p.eps;
+  sd.flat_tol = p.flat_tol;
+  sd.lam = p.lambda;
+  sd.potts = p.potts;
+  fill_taps(sd, p);
+  for (int l = std::max(1, first_level); l <= g.top; ++l)
+    sd.base[l] = bump.take<float>((size_t)4 * g.Hl[l] * g.Wl[l]);
+  for (int l = 1; l <= g.top; ++l)
+    if (g.used & (1u << l)) sd.gab[l] = bump.take<float>((size_t)4 * g.Hl[l] * g.Wl[l]);
+  if (rgb_parts) {
+    const long long px = (long long)g.H * g.W;
+    int nb = (int)std::min<long long>(256, std::max<long long>(1, (px + 8191) / 8192));
+    const int rows = (g.H + nb - 1) / nb;
+    sd.n_rgb = (g.H + rows - 1) / rows;
+    sd.rgb_max_part = bump.take<uint32_t>(sd.n_rgb);
+    sd.rgb_d2_part = bump.take<unsigned long long>(sd.n_rgb);
+  }
+  sd.cs_part = bump.take<float>((size_t)3 * off);
+  sd.fbar = bump.take<float>((size_t)SP_NCH * g.Hl[g.c_max] * g.Wl[g.c_max]);
+  sd.fbar_part = bump.take<float>((size_t)3 * SP_NCH * sd.n_cmax_tiles);
+  sd.s_part = bump.take<float>((size_t)2 * sd.n_cmax_tiles);
+}
+
+void rgb_jobs(std::vector<Job>& v, int s, const StreamDesc& sd) {
+  const int rows = (sd.H + sd.n_rgb - 1) / sd.n_rgb;
+  for (int i = 0; i < sd.n_rgb; ++i) {
+    const int y0 = i * rows;
+    v.push_back(Job{s, i, y0, 0, std::min(rows, sd.H - y0), sd.W, i, 0});
+  }
+}
+
+// ---------------------------------------------------------------- job tables
+struct Phase {
+  int kind = 0, flag = 0;
+  size_t off = 0;             // first job in the device table
+  int n = 0;                  // jobs
+  std::vector<int> upto;      // upto[s]: jobs of streams < s (stream-major tables)
+};
+
+struct JobStore {
+  std::vector<Job> host;
+  Job* dev = nullptr;
+  Phase add(int kind, int flag, const std::vector<Job>& jobs, int n_streams) {
+    Phase ph;
+    ph.kind = kind;
+    ph.flag = flag;
+    ph.off = host.size();
+    ph.n = (int)jobs.size();
+    ph.upto.assign(n_streams + 1, 0);
+    for (const Job& j : jobs) ph.upto[j.stream + 1]++;
+    for (int s = 0; s < n_streams; ++s) ph.upto[s + 1] += ph.upto[s];
+    host.insert(host.end(), jobs.begin(), jobs.end());
+    return ph;
+  }
+};
+
+// Per-stream phase program of the forward saliency map.
+enum ProgPart { PROG_ALL, PROG_RECOMPUTE };
+
+double now_gain(int64_t t, double Pprev, double Q, double R, double* P) {
+  if (t == 0) {
+    *P = R;
+    return 1.0;
+  }
+  const double a = Pprev + Q;
+  const double K = a / (a + R);
+  *P = R * K;
+  return K;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+struct sp_ctx {
+  sp_params p{};
+  Geo g;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  StreamDesc h_sd{};
+  StreamDesc* d_sd = nullptr;
+  JobStore jobs;
+  std::vector<Phase> fwd, prior, mrf, bwd;
+  // Kalman state
+  int64_t t = 0;
+  double P = 0.0;
+  float* pi_state[2] = {nullptr, nullptr};
+  int cur = 0;
+  // tape
+  int cap = 0;
+  int64_t tape_valid_from = 0;   // tape covers steps since the last reset only
+  bool tape_ok = true;
+  float* ckpt = nullptr;          // [cap][4][Hcmin][Wcmin]
+  float* S_tape = nullptr;        // [cap][Hc][Wc]
+  float* f_tape = nullptr;        // [cap][H][W]
+  float* ms_tape = nullptr;       // [cap][2]
+  double* K_tape = nullptr;       // [cap]
+  double* P_tape = nullptr;       // [cap]
+  std::vector<float> Kf;          // host copy of K_t (float) per recorded step
+  std::vector<char> uses_pi;      // step t read the previous prior
+  // adjoint workspace
+  float* nu[2] = {nullptr, nullptr};
+  float* gu = nullptr;
+  float* gs_all = nullptr;        // [cap][Hc][Wc]
+  float* gk_part = nullptr;       // [cap][n_lvl0_tiles]
+  float* dot_part = nullptr;      // [cap][n_cmax_tiles][8]
+  float* cx = nullptr;            // [cap][8]
+  double* gK_scratch = nullptr;   // [cap]
+  int n_lvl0_tiles = 0;
+  int CH = 0;                     // frames per recompute chunk
+  StreamDesc* d_rsd = nullptr;    // [CH] recompute streams
+  StepIO* d_rio = nullptr;        // [cap] io of every tape frame (ckpt pointers)
+  int* d_frame_ids = nullptr;     // [cap] = 0..cap-1
+  std::vector<Phase> rec;         // recompute phases (stream-major, CH streams)
+  // loss helper
+  float* loss_part = nullptr;
+  int loss_nblk = 1024;
+};
+
+namespace {
+
+int run_phase(sp_ctx* c, const Phase& ph, const StreamDesc* sds, const StepIO* ios, const StepIO* io0, int n_jobs,
+              const float* aux = nullptr) {
+  hipError_t e = sp_launch(ph.kind, c->jobs.dev + ph.off, n_jobs, sds, ios, io0, ph.flag, aux, c->stream);
+  if (e != hipSuccess) return fail(SP_EHIP, "kernel launch (phase kind %d): %s", ph.kind, hipGetErrorString(e));
+  return SP_OK;
+}
+
+void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& kinds, const StreamDesc& sd,
+                        const Geo& g, int s, ProgPart which) {
+  auto push = [&](int kind, std::vector<Job> v) {
+    parts.push_back(std::move(v));
+    kinds.push_back(kind);
+  };
+  if (which == PROG_ALL) {
+    std::vector<Job> v;
+    rgb_jobs(v, s, sd);
+    push(JOB_RGB, v);
+    v.clear();
+    add_tiles(v, s, 1, g.Hl[1], g.Wl[1]);
+    push(JOB_FEAT, v);
+  }
+  const int from = (which == PROG_ALL) ? 1 : g.c_min;
+  for (int l = from; l < g.top; ++l) {
+    std::vector<Job> v;
+    add_tiles(v, s, l, g.Hl[l + 1], g.Wl[l + 1]);
+    push(JOB_DOWN, v);
+  }
+  std::vector<Job> v;
+  for (int l = 1; l <= g.top; ++l)
+    if (g.used & (1u << l)) add_tiles(v, s, l, g.Hl[l], g.Wl[l]);
+  push(JOB_GABOR, v);
+  v.clear();
+  for (int c = 0; c <= g.top; ++c) {
+    bool has = false;
+    for (int i = 0; i < g.n_pairs; ++i) has |= (g.pc[i] == c);
+    if (has) add_tiles(v, s, c, g.Hl[c], g.Wl[c]);
+  }
+  push(JOB_CSSTATS, v);
+  v.clear();
+  for (int k = 0; k < SP_NCH; ++k) add_tiles(v, s, k, g.Hl[g.c_max], g.Wl[g.c_max]);
+  push(JOB_CSAPPLY, v);
+  v.clear();
+  add_tiles(v, s, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
+  push(which == PROG_ALL ? JOB_CONSP : JOB_CONSP_DOT, v);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sp_last_error(void) { return g_err.c_str(); }
+
+void sp_default_params(sp_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->depth = 0;
+  p->n_centers = 2;
+  p->centers[0] = 1;
+  p->centers[1] = 2;
+  p->n_deltas = 2;
+  p->deltas[0] = 2;
+  p->deltas[1] = 3;
+  for (int k = 0; k < 8; ++k) p->weights[k] = 1.f;
+  p->q = 1e-3;
+  p->r = 1e-1;
+  p->eps = 1e-4f;
+  p->border = 1;
+  p->lambda = 1.f;
+  p->potts = 0.f;
+  p->lm_block = 8;
+  p->flat_tol = 1e-5f;
+  p->gabor_lambda = 4.f;
+  p->gabor_sigma = 2.f;
+  p->gabor_radius = 6;
+  p->record_tape = 0;
+}
+
+int sp_destroy(sp_ctx* c) {
+  g_err.clear();
+  if (!c) return SP_OK;
+  if (c->stream || c->arena) (void)hipStreamSynchronize(c->stream);
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->jobs.dev) (void)hipFree(c->jobs.dev);
+  delete c;
+  return SP_OK;
+}
+
+int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(SP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_params(p);
+  if (rc) return rc;
+  Geo g;
+  rc = make_geo(*p, H, W, g);
+  if (rc) return rc;
+  sp_ctx* c = new (std::nothrow) sp_ctx();
+  if (!c) return fail(SP_ENOMEM, "host allocation failed");
+  c->p = *p;
+  c->g = g;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(SP_EHIP, "hipGetDevice failed (no GPU?)");
+  }
+  c->cap = p->record_tape;
+  c->n_lvl0_tiles = ntiles(H, W);
+  const int Hc = g.Hl[g.c_max], Wc = g.Wl[g.c_max];
+  const size_t HW = (size_t)H * W;
+  c->CH = c->cap > 0 ? std::min(c->cap, 32) : 0;
+  // two passes over the layout: size, then place
+  for (int pass = 0; pass < 2; ++pass) {
+    Bump b;
+    b.base = c->arena;
+    layout_stream(c->h_sd, g, *p, b, 1, true);
+    c->d_sd = b.take<StreamDesc>(1);
+    c->pi_state[0] = b.take<float>(HW);
+    c->pi_state[1] = b.take<float>(HW);
+    c->loss_part = b.take<float>(c->loss_nblk);
+    std::vector<StreamDesc> rsd(c->CH);
+    if (c->cap > 0) {
+      c->ckpt = b.take<float>((size_t)c->cap * 4 * g.Hl[g.c_min] * g.Wl[g.c_min]);
+      c->S_tape = b.take<float>((size_t)c->cap * Hc * Wc);
+      c->f_tape = b.take<float>((size_t)c->cap * HW);
+      c->ms_tape = b.take<float>((size_t)c->cap * 2);
+      c->K_tape = b.take<double>(c->cap);
+      c->P_tape = b.take<double>(c->cap);
+      c->nu[0] = b.take<float>(HW);
+      c->nu[1] = b.take<float>(HW);
+      c->gu = b.take<float>(HW);
+      c->gs_all = b.take<float>((size_t)c->cap * Hc * Wc);
+      c->gk_part = b.take<float>((size_t)c->cap * c->n_lvl0_tiles);
+      c->dot_part = b.take<float>((size_t)c->cap * c->h_sd.n_cmax_tiles * SP_NCH);
+      c->cx = b.take<float>((size_t)c->cap * SP_NCH);
+      c->gK_scratch = b.take<double>(c->cap);
+      c->d_rsd = b.take<StreamDesc>(c->CH);
+      c->d_rio = b.take<StepIO>(c->cap);
+      c->d_frame_ids = b.take<int>(c->cap);
+      for (int i = 0; i < c->CH; ++i) layout_stream(rsd[i], g, *p, b, g.c_min + 1, false);
+    }
+    if (pass == 0) {
+      c->arena_bytes = b.off + 256;
+      if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(SP_ENOMEM, "hipMalloc of %zu bytes failed", c->arena_bytes);
+      }
+    } else {
+      // upload static tables
+      hipError_t e = hipMemcpyAsync(c->d_sd, &c->h_sd, sizeof(StreamDesc), hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess && c->cap > 0) {
+        e = hipMemcpyAsync(c->d_rsd, rsd.data(), sizeof(StreamDesc) * c->CH, hipMemcpyHostToDevice, c->stream);
+        std::vector<StepIO> rio(c->cap);
+        std::vector<int> ids(c->cap);
+        const size_t cstride = (size_t)4 * g.Hl[g.c_min] * g.Wl[g.c_min];
+        for (int t = 0; t < c->cap; ++t) {
+          std::memset(&rio[t], 0, sizeof(StepIO));
+          rio[t].ckpt = c->ckpt + (size_t)t * cstride;
+          ids[t] = t;
+        }
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(c->d_rio, rio.data(), sizeof(StepIO) * c->cap, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(c->d_frame_ids, ids.data(), sizeof(int) * c->cap, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) {
+        sp_destroy(c);
+        return fail(SP_EHIP, "uploading stream tables: %s", hipGetErrorString(e));
+      }
+    }
+  }
+  // job tables
+  {
+    std::vector<std::vector<Job>> parts;
+    std::vector<int> kinds;
+    build_forward_jobs(parts, kinds, c->h_sd, g, 0, PROG_ALL);
+    for (size_t i = 0; i < parts.size(); ++i) c->fwd.push_back(c->jobs.add(kinds[i], 0, parts[i], 1));
+    std::vector<Job> v;
+    add_tiles(v, 0, 0, Hc, Wc);
+    c->prior.push_back(c->jobs.add(JOB_SMAX, 0, v, 1));
+    v.clear();
+    add_tiles(v, 0, 0, H, W);
+    c->prior.push_back(c->jobs.add(JOB_KALMAN, 0, v, 1));
+    v.clear();
+    rgb_jobs(v, 0, c->h_sd);
+    c->mrf.push_back(c->jobs.add(JOB_RGB, 1, v, 1));
+    v.clear();
+    add_tiles(v, 0, 0, H, W);
+    c->mrf.push_back(c->jobs.add(JOB_MRF, 0, v, 1));
+    v.clear();
+    add_tiles(v, 0, 0, H, W);
+    c->bwd.push_back(c->jobs.add(JOB_BWD_NU, 0, v, 1));
+    v.clear();
+    add_tiles(v, 0, 0, Hc, Wc);
+    c->bwd.push_back(c->jobs.add(JOB_BWD_GS, 0, v, 1));
+    if (c->CH > 0) {
+      std::vector<std::vector<Job>> all;
+      std::vector<int> kk;
+      for (int s = 0; s < c->CH; ++s) {
+        std::vector<std::vector<Job>> ps;
+        std::vector<int> ks;
+        build_forward_jobs(ps, ks, c->h_sd, g, s, PROG_RECOMPUTE);
+        if (all.empty()) {
+          all.resize(ps.size());
+          kk = ks;
+        }
+        for (size_t i = 0; i < ps.size(); ++i) all[i].insert(all[i].end(), ps[i].begin(), ps[i].end());
+      }
+      for (size_t i = 0; i < all.size(); ++i) c->rec.push_back(c->jobs.add(kk[i], 0, all[i], c->CH));
+    }
+    if (hipMalloc(&c->jobs.dev, sizeof(Job) * c->jobs.host.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      sp_destroy(c);
+      return fail(SP_ENOMEM, "hipMalloc of the job tables failed");
+    }
+    if (hipMemcpy(c->jobs.dev, c->jobs.host.data(), sizeof(Job) * c->jobs.host.size(), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      sp_destroy(c);
+      return fail(SP_EHIP, "uploading job tables failed");
+    }
+  }
+  *out = c;
+  return SP_OK;
+}
+
+int sp_set_stream(sp_ctx* c, void* hip_stream) {
+  g_err.clear();
+  if (!c) return fail(SP_EINVAL, "ctx is NULL");
+  c->stream = (hipStream_t)hip_stream;
+  return SP_OK;
+}
+
+int sp_get_geometry(const sp_ctx* c, sp_geometry* out) {
+  g_err.clear();
+  if (!c || !out) return fail(SP_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  const Geo& g = c->g;
+  out->H = g.H;
+  out->W = g.W;
+  out->depth = g.depth;
+  out->top = g.top;
+  out->c_min = g.c_min;
+  out->c_max = g.c_max;
+  out->n_pairs = g.n_pairs;
+  for (int i = 0; i < g.n_pairs; ++i) {
+    out->pair_c[i] = g.pc[i];
+    out->pair_s[i] = g.ps[i];
+  }
+  for (int l = 0; l <= g.depth && l <= SP_MAX_LEVELS; ++l) {
+    out->level_h[l] = g.Hl[l];
+    out->level_w[l] = g.Wl[l];
+  }
+  out->Hc = g.Hl[g.c_max];
+  out->Wc = g.Wl[g.c_max];
+  return SP_OK;
+}
+
+int sp_set_weights(sp_ctx* c, const float* w, double q, double r) {
+  g_err.clear();
+  if (!c || !w) return fail(SP_EINVAL, "NULL argument");
+  for (int k = 0; k < SP_NCH; ++k)
+    if (!std::isfinite(w[k])) return fail(SP_EINVAL, "weight %d is not finite", k);
+  if (!is_fin(q) || !is_fin(r) || q < 0 || r < 0 || !(q + r > 0))
+    return fail(SP_EINVAL, "Kalman variances must be finite, >= 0 and not both 0");
+  for (int k = 0; k < SP_NCH; ++k) {
+    c->p.weights[k] = w[k];
+    c->h_sd.w[k] = w[k];
+  }
+  c->p.q = q;
+  c->p.r = r;
+  HIPCHK(hipMemcpyAsync(c->d_sd, &c->h_sd, sizeof(StreamDesc), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SP_OK;
+}
+
+int sp_reset(sp_ctx* c) {
+  g_err.clear();
+  if (!c) return fail(SP_EINVAL, "ctx is NULL");
+  c->t = 0;
+  c->P = 0.0;
+  c->cur = 0;
+  c->tape_ok = true;
+  c->Kf.clear();
+  c->uses_pi.clear();
+  return SP_OK;
+}
+
+int64_t sp_step_index(const sp_ctx* c) { return c ? c->t : -1; }
+
+int saliency_forward(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, float* S_out, float* C_out) {
+  g_err.clear();
+  if (!c || !rgb_t || !S_out) return fail(SP_EINVAL, "ctx, rgb_t and S_out must not be NULL");
+  StepIO io;
+  std::memset(&io, 0, sizeof io);
+  io.rgb = rgb_t;
+  io.rgb_prev = rgb_prev;
+  io.S_out = S_out;
+  io.C_out = C_out;
+  if (c->cap > 0) {
+    if (c->t >= c->cap) return fail(SP_ESTATE, "tape holds %d frames; call sp_reset before frame %lld", c->cap,
+                                    (long long)c->t);
+    const Geo& g = c->g;
+    io.ckpt = c->ckpt + (size_t)c->t * 4 * g.Hl[g.c_min] * g.Wl[g.c_min];
+    io.S_tape = c->S_tape + (size_t)c->t * g.Hl[g.c_max] * g.Wl[g.c_max];
+  }
+  for (const Phase& ph : c->fwd) {
+    int rc = run_phase(c, ph, c->d_sd, nullptr, &io, ph.n);
+    if (rc) return rc;
+  }
+  return SP_OK;
+}
+
+int prior_update(sp_ctx* c, const float* S, const uint8_t* seg_prev, float* prior_out) {
+  g_err.clear();
+  if (!c || !S) return fail(SP_EINVAL, "ctx and S must not be NULL");
+  if (c->cap > 0 && c->t >= c->cap)
+    return fail(SP_ESTATE, "tape holds %d frames; call sp_reset first", c->cap);
+  StepIO io;
+  std::memset(&io, 0, sizeof io);
+  io.S_in = S;
+  io.seg_prev = seg_prev;
+  io.pi_prev = c->pi_state[c->cur];
+  io.pi_next = c->pi_state[c->cur ^ 1];
+  io.prior_out = prior_out;
+  double Pn = 0.0;
+  const double K = now_gain(c->t, c->P, c->p.q, c->p.r, &Pn);
+  io.K = (float)K;
+  io.t = (int32_t)std::min<int64_t>(c->t, 0x7fffffff);
+  if (c->cap > 0) {
+    const Geo& g = c->g;
+    io.f_tape = c->f_tape + (size_t)c->t * g.H * g.W;
+    io.ms_tape = c->ms_tape + (size_t)c->t * 2;
+  }
+  for (const Phase& ph : c->prior) {
+    int rc = run_phase(c, ph, c->d_sd, nullptr, &io, ph.n);
+    if (rc) return rc;
+  }
+  if (c->cap > 0) {
+    // gains and variances of the recorded steps (host -> device, from values that stay
+    // alive in the context until the next reset)
+    c->Kf.push_back((float)K);
+    c->uses_pi.push_back(seg_prev == nullptr && c->t > 0);
+  }
+  c->P = Pn;
+  c->cur ^= 1;
+  c->t += 1;
+  return SP_OK;
+}
+
+int mrf_weights(sp_ctx* c, const uint8_t* rgb_t, const float* prior, float* unary_out, float* pairwise_out,
+                float* beta_out) {
+  g_err.clear();
+  if (!c || !rgb_t || !prior || !unary_out || !pairwise_out)
+    return fail(SP_EINVAL, "ctx, rgb_t, prior, unary_out and pairwise_out must not be NULL");
+  StepIO io;
+  std::memset(&io, 0, sizeof io);
+  io.rgb = rgb_t;
+  io.unary = unary_out;
+  io.pairwise = pairwise_out;
+  io.beta_out = beta_out;
+  for (const Phase& ph : c->mrf) {
+    int rc = run_phase(c, ph, c->d_sd, nullptr, &io, ph.n, prior);
+    if (rc) return rc;
+  }
+  return SP_OK;
+}
+
+int saliency_backward(sp_ctx* c, const float* grad_prior, int32_t T, float* grad_w, float* grad_q, float* grad_r) {
+  g_err.clear();
+  if (!c || !grad_prior || !grad_w || !grad_q || !grad_r) return fail(SP_EINVAL, "NULL argument");
+  if (c->cap <= 0) return fail(SP_ESTATE, "context was created without a tape (record_tape = 0)");
+  if (!c->tape_ok) return fail(SP_ESTATE, "tape invalidated by sp_set_state; call sp_reset");
+  if (T < 1 || T != c->t || (size_t)T != c->Kf.size())
+    return fail(SP_ESTATE, "backward of %d steps, but %lld prior updates were recorded since the reset", T,
+                (long long)c->t);
+  const Geo& g = c->g;
+  const size_t HW = (size_t)g.H * g.W;
+  const int Hc = g.Hl[g.c_max], Wc = g.Wl[g.c_max];
+  // host gains -> device tape (FP64), for the scalar sweep
+  {
+    std::vector<double> Kd(T), Pd(T);
+    double P = 0.0;
+    for (int t = 0; t < T; ++t) Kd[t] = now_gain(t, P, c->p.q, c->p.r, &P), Pd[t] = P;
+    HIPCHK(hipMemcpyAsync(c->K_tape, Kd.data(), sizeof(double) * T, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->P_tape, Pd.data(), sizeof(double) * T, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  // reverse sweep over the steps
+  for (int t = T - 1; t >= 0; --t) {
+    BwdIO b;
+    std::memset(&b, 0, sizeof b);
+    b.grad = grad_prior + (size_t)t * HW;
+    b.nu_next = (t + 1 < T) ? c->nu[(t + 1) & 1] : nullptr;
+    b.nu_out = c->nu[t & 1];
+    b.gu = c->gu;
+    b.gs = c->gs_all + (size_t)t * Hc * Wc;
+    b.gk_part = c->gk_part + (size_t)t * c->n_lvl0_tiles;
+    b.f = (t > 0) ? c->f_tape + (size_t)t * HW : nullptr;
+    b.S = c->S_tape + (size_t)t * Hc * Wc;
+    b.ms = c->ms_tape + (size_t)t * 2;
+    b.K = (t > 0) ? c->Kf[t] : 1.f;
+    b.carry = (t + 1 < T && c->uses_pi[t + 1]) ? 1.f - c->Kf[t + 1] : 0.f;
+    b.t = t;
+    for (const Phase& ph : c->bwd) {
+      hipError_t e = sp_launch_bwd(ph.kind, c->jobs.dev + ph.off, ph.n, c->d_sd, nullptr, &b, c->stream);
+      if (e != hipSuccess) return fail(SP_EHIP, "adjoint launch: %s", hipGetErrorString(e));
+    }
+  }
+  // conspicuity maps recomputed from the checkpoints, dotted with the saliency adjoint
+  for (int t0 = 0; t0 < T; t0 += c->CH) {
+    const int n = std::min(c->CH, T - t0);
+    const StepIO* ios = c->d_rio + t0;
+    const int* fid = c->d_frame_ids + t0;
+    for (const Phase& ph : c->rec) {
+      const int nj = ph.upto[n];
+      hipError_t e;
+      if (ph.kind == JOB_CONSP_DOT)
+        e = sp_launch_consp_dot(c->jobs.dev + ph.off, nj, c->d_rsd, ios, c->gs_all, c->ms_tape, fid, c->dot_part,
+                                c->cx, c->stream);
+      else
+        e = sp_launch(ph.kind, c->jobs.dev + ph.off, nj, c->d_rsd, ios, nullptr, 0, nullptr, c->stream);
+      if (e != hipSuccess) return fail(SP_EHIP, "recompute launch: %s", hipGetErrorString(e));
+    }
+  }
+  const float* wdev = reinterpret_cast<const float*>(reinterpret_cast<const char*>(c->d_sd) + offsetof(StreamDesc, w));
+  hipError_t e = sp_launch_bwd_final(T, c->n_lvl0_tiles, c->h_sd.n_cmax_tiles, c->gk_part, c->dot_part, c->cx,
+                                     c->ms_tape, c->K_tape, c->P_tape, c->p.q, c->p.r, wdev, c->p.flat_tol,
+                                     c->gK_scratch, grad_w, grad_q, grad_r, c->stream);
+  if (e != hipSuccess) return fail(SP_EHIP, "adjoint reduction launch: %s", hipGetErrorString(e));
+  return SP_OK;
+}
+
+int sp_mse_mask_loss(sp_ctx* c, const float* prior, const uint8_t* mask, int32_t T, float* loss, float* grad_prior) {
+  g_err.clear();
+  if (!c || !prior || !mask || !loss) return fail(SP_EINVAL, "NULL argument");
+  if (T < 1) return fail(SP_EINVAL, "T must be >= 1");
+  const size_t n = (size_t)T * c->g.H * c->g.W;
+  const int nblk = (int)std::min<size_t>(c->loss_nblk, (n + SP_BLOCK - 1) / SP_BLOCK);
+  hipError_t e = sp_launch_loss(prior, mask, n, grad_prior, c->loss_part, nblk, loss, c->stream);
+  if (e != hipSuccess) return fail(SP_EHIP, "loss launch: %s", hipGetErrorString(e));
+  return SP_OK;
+}
+
+int sp_state_size(const sp_ctx* c, size_t* bytes) {
+  g_err.clear();
+  if (!c || !bytes) return fail(SP_EINVAL, "NULL argument");
+  *bytes = (size_t)c->g.H * c->g.W * sizeof(float) + 2 * sizeof(double);
+  return SP_OK;
+}
+
+int sp_get_state(sp_ctx* c, void* buf, size_t bytes) {
+  g_err.clear();
+  size_t need = 0;
+  int rc = sp_state_size(c, &need);
+  if (rc) return rc;
+  if (!buf || bytes < need) return fail(SP_EINVAL, "state buffer needs %zu bytes", need);
+  const size_t HW = (size_t)c->g.H * c->g.W;
+  HIPCHK(hipMemcpyAsync(buf, c->pi_state[c->cur], HW * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  double sc[2] = {(double)c->t, c->P};
+  HIPCHK(hipMemcpyAsync((char*)buf + HW * sizeof(float), sc, sizeof sc, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SP_OK;
+}
+
+int sp_set_state(sp_ctx* c, const void* buf, size_t bytes) {
+  g_err.clear();
+  size_t need = 0;
+  int rc = sp_state_size(c, &need);
+  if (rc) return rc;
+  if (!buf || bytes < need) return fail(SP_EINVAL, "state buffer needs %zu bytes", need);
+  const size_t HW = (size_t)c->g.H * c->g.W;
+  double sc[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(sc, (const char*)buf + HW * sizeof(float), sizeof sc, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (!(sc[0] >= 0) || !std::isfinite(sc[1]) || sc[1] < 0) return fail(SP_EINVAL, "state buffer holds an invalid header");
+  HIPCHK(hipMemcpyAsync(c->pi_state[c->cur], buf, HW * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  c->t = (int64_t)sc[0];
+  c->P = sc[1];
+  c->tape_ok = false;
+  return SP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batched step
+struct sp_batch {
+  sp_params p{};
+  int n = 0;
+  hipStream_t stream = nullptr;     // caller's stream: graph launches go here
+  hipStream_t cap_stream = nullptr; // private stream used only to capture the graph
+  char* arena = nullptr;
+  std::vector<Geo> geo;
+  std::vector<StreamDesc> h_sd;
+  StreamDesc* d_sd = nullptr;
+  StepIO* d_io = nullptr;
+  BatchState* d_st = nullptr;
+  std::vector<BatchState> h_st;
+  const uint8_t** d_in = nullptr;   // [n] frame pointers of the current step
+  JobStore jobs;
+  std::vector<Phase> phases;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  long long steps = 0;
+};
+
+namespace {
+
+int batch_enqueue(sp_batch* b, hipStream_t st) {
+  hipError_t e = sp_launch_batch_begin(b->n, b->d_st, b->d_in, b->d_io, b->p.q, b->p.r, st);
+  if (e != hipSuccess) return fail(SP_EHIP, "batch begin launch: %s", hipGetErrorString(e));
+  for (const Phase& ph : b->phases) {
+    e = sp_launch(ph.kind, b->jobs.dev + ph.off, ph.n, b->d_sd, b->d_io, nullptr, ph.flag, nullptr, st);
+    if (e != hipSuccess) return fail(SP_EHIP, "batch phase launch (kind %d): %s", ph.kind, hipGetErrorString(e));
+  }
+  return SP_OK;
+}
+
+void batch_free(sp_batch* b) {
+  if (!b) return;
+  if (b->stream || b->arena) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->arena) (void)hipFree(b->arena);
+  if (b->jobs.dev) (void)hipFree(b->jobs.dev);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32_t* W, void* hip_stream,
+                    sp_batch** out) {
+  g_err.clear();
+  if (!out) return fail(SP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > 4096) return fail(SP_EINVAL, "batch size must be 1..4096 (got %d)", n);
+  if (!H || !W) return fail(SP_EINVAL, "H and W must not be NULL");
+  int rc = validate_params(p);
+  if (rc) return rc;
+  if (p->record_tape != 0) return fail(SP_EINVAL, "the batched step keeps no tape (record_tape must be 0)");
+  sp_batch* b = new (std::nothrow) sp_batch();
+  if (!b) return fail(SP_ENOMEM, "host allocation failed");
+  b->p = *p;
+  b->n = n;
+  b->stream = (hipStream_t)hip_stream;
+  b->geo.resize(n);
+  for (int i = 0; i < n; ++i) {
+    rc = make_geo(*p, H[i], W[i], b->geo[i]);
+    if (rc) {
+      batch_free(b);
+      return fail(rc, "stream %d: %s", i, g_err.c_str());
+    }
+  }
+  b->h_sd.resize(n);
+  b->h_st.resize(n);
+  size_t bytes = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    Bump bm;
+    bm.base = b->arena;
+    for (int i = 0; i < n; ++i) {
+      layout_stream(b->h_sd[i], b->geo[i], *p, bm, 1, true);
+      const Geo& g = b->geo[i];
+      BatchState& s = b->h_st[i];
+      std::memset(&s, 0, sizeof s);
+      s.pi[0] = bm.take<float>((size_t)g.H * g.W);
+      s.pi[1] = bm.take<float>((size_t)g.H * g.W);
+      s.S = bm.take<float>((size_t)g.Hl[g.c_max] * g.Wl[g.c_max]);
+    }
+    b->d_sd = bm.take<StreamDesc>(n);
+    b->d_io = bm.take<StepIO>(n);
+    b->d_st = bm.take<BatchState>(n);
+    b->d_in = bm.take<const uint8_t*>(n);
+    if (pass == 0) {
+      bytes = bm.off + 256;
+      if (hipMalloc(&b->arena, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return fail(SP_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+      }
+    }
+  }
+  // phase program: one launch per phase over every stream
+  int maxtop = 0;
+  for (const Geo& g : b->geo) maxtop = std::max(maxtop, g.top);
+  std::vector<Job> rgb, feat, gab, css, csa, cons, kal;
+  std::vector<std::vector<Job>> down(std::max(0, maxtop - 1));
+  for (int i = 0; i < n; ++i) {
+    const Geo& g = b->geo[i];
+    rgb_jobs(rgb, i, b->h_sd[i]);
+    add_tiles(feat, i, 1, g.Hl[1], g.Wl[1]);
+    for (int l = 1; l < g.top; ++l) add_tiles(down[l - 1], i, l, g.Hl[l + 1], g.Wl[l + 1]);
+    for (int l = 1; l <= g.top; ++l)
+      if (g.used & (1u << l)) add_tiles(gab, i, l, g.Hl[l], g.Wl[l]);
+    for (int c = 0; c <= g.top; ++c) {
+      bool has = false;
+      for (int k = 0; k < g.n_pairs; ++k) has |= (g.pc[k] == c);
+      if (has) add_tiles(css, i, c, g.Hl[c], g.Wl[c]);
+    }
+    for (int k = 0; k < SP_NCH; ++k) add_tiles(csa, i, k, g.Hl[g.c_max], g.Wl[g.c_max]);
+    add_tiles(cons, i, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
+    add_tiles(kal, i, 0, g.H, g.W);
+  }
+  b->phases.push_back(b->jobs.add(JOB_RGB, 0, rgb, n));
+  b->phases.push_back(b->jobs.add(JOB_FEAT, 0, feat, n));
+  for (auto& d : down)
+    if (!d.empty()) b->phases.push_back(b->jobs.add(JOB_DOWN, 0, d, n));
+  b->phases.push_back(b->jobs.add(JOB_GABOR, 0, gab, n));
+  b->phases.push_back(b->jobs.add(JOB_CSSTATS, 0, css, n));
+  b->phases.push_back(b->jobs.add(JOB_CSAPPLY, 0, csa, n));
+  b->phases.push_back(b->jobs.add(JOB_CONSP, 0, cons, n));
+  b->phases.push_back(b->jobs.add(JOB_KALMAN, 0, kal, n));
+  hipError_t e = hipMalloc(&b->jobs.dev, sizeof(Job) * b->jobs.host.size());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    batch_free(b);
+    return fail(SP_ENOMEM, "hipMalloc of the job tables failed");
+  }
+  e = hipMemcpy(b->jobs.dev, b->jobs.host.data(), sizeof(Job) * b->jobs.host.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_sd, b->h_sd.data(), sizeof(StreamDesc) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_st, b->h_st.data(), sizeof(BatchState) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return fail(SP_EHIP, "batch set-up: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return SP_OK;
+}
+
+int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* prior_ptrs) {
+  g_err.clear();
+  if (!b || !rgb_ptrs) return fail(SP_EINVAL, "batch and rgb_ptrs must not be NULL");
+  if (!b->exec) {
+    // capture the whole step once on the private stream
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = batch_enqueue(b, b->cap_stream);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
+    if (rc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(SP_EHIP, "graph capture: %s", hipGetErrorString(e));
+    b->graph = gr;
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIPCHK(hipMemcpyAsync(b->d_in, rgb_ptrs, sizeof(void*) * b->n, hipMemcpyDeviceToDevice, b->stream));
+  HIPCHK(hipGraphLaunch(b->exec, b->stream));
+  b->steps += 1;
+  if (prior_ptrs) {
+    hipError_t e = sp_launch_batch_copy_out(b->n, b->d_st, b->d_sd, prior_ptrs, b->stream);
+    if (e != hipSuccess) return fail(SP_EHIP, "copy-out launch: %s", hipGetErrorString(e));
+  }
+  return SP_OK;
+}
+
+int sp_batch_prior(sp_batch* b, int32_t i, const float** prior) {
+  g_err.clear();
+  if (!b || !prior) return fail(SP_EINVAL, "NULL argument");
+  if (i < 0 || i >= b->n) return fail(SP_EINVAL, "stream index %d out of range", i);
+  if (b->steps == 0) return fail(SP_ESTATE, "no step has run since the reset");
+  *prior = b->h_st[i].pi[b->steps & 1];
+  return SP_OK;
+}
+
+int sp_batch_reset(sp_batch* b) {
+  g_err.clear();
+  if (!b) return fail(SP_EINVAL, "batch is NULL");
+  hipError_t e = sp_launch_batch_reset(b->n, b->d_st, b->stream);
+  if (e != hipSuccess) return fail(SP_EHIP, "reset launch: %s", hipGetErrorString(e));
+  b->steps = 0;
+  return SP_OK;
+}
+
+int sp_batch_destroy(sp_batch* b) {
+  g_err.clear();
+  batch_free(b);
+  return SP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Internal data structures shared by the HIP kernels and the host runtime.
+//
+// Every kernel consumes a table of jobs (one workgroup per job).  A job names the
+// stream it belongs to and a rectangular tile of some map, so one launch can serve
+// one stream (the plain per-frame calls) or many streams of uneven size (the
+// batched step) with the same code.
+#pragma once
+#include <stdint.h>
+
+#define SP_MAXL 13          // pyramid levels 0..12
+#define SP_MAXP 16          // centre-surround pairs
+#define SP_MAXR 8           // largest Gabor radius
+#define SP_NCH 8            // channels: I, RG, BY, O0, O45, O90, O135, M
+#define SP_BLOCK 256        // threads per workgroup of every tiled kernel (4 wave64)
+
+// Base channels are stored per level as [4][H_l][W_l] in the order I, RG, BY, M;
+// orientation maps per used level as [4][H_l][W_l] in the order O0, O45, O90, O135.
+enum { BASE_I = 0, BASE_RG = 1, BASE_BY = 2, BASE_M = 3 };
+
+enum JobKind : int32_t {
+  JOB_RGB = 0,      // colour max (+ colour-difference sums) partials over a band of rows
+  JOB_FEAT,         // level-0 features -> level 1 (blur + decimate)
+  JOB_DOWN,         // level a -> level a+1 for the 4 base channels
+  JOB_GABOR,        // 4 orientation maps of level a
+  JOB_CSSTATS,      // centre-surround maps of centre level a: min/max/block-max partials
+  JOB_CSAPPLY,      // channel a: across-scale sum at c_max (+ its partials)
+  JOB_CONSP,        // conspicuity, saliency, max/argmax partials at c_max
+  JOB_SMAX,         // max/argmax partials of a given saliency map
+  JOB_KALMAN,       // observation + Kalman update at level 0
+  JOB_MRF,          // unary + pairwise capacities at level 0
+  JOB_BWD_NU,       // adjoint sweep at level 0
+  JOB_BWD_GS,       // upsample transpose at c_max
+  JOB_CONSP_DOT,    // recomputed conspicuity dotted with the saliency adjoint
+  JOB_LOSS,         // masked MSE partials
+};
+
+struct Job {
+  int32_t stream;   // index into the stream table
+  int32_t a;        // kind-specific: level, channel or row band
+  int32_t y0, x0;   // tile origin (in the map the kind works on)
+  int32_t th, tw;   // tile size
+  int32_t tid;      // index of this tile among the tiles of its map (partials slot)
+  int32_t pad;
+};
+
+// Static description of one stream: geometry, scratch pointers, parameters.
+struct StreamDesc {
+  int32_t H, W, top, c_min, c_max, n_pairs, border, n_rgb;
+  int32_t pc[SP_MAXP], ps[SP_MAXP];
+  int32_t Hl[SP_MAXL], Wl[SP_MAXL];
+  int32_t ntiles_lvl[SP_MAXL];   // number of CS tiles of a map at level l
+  int32_t cs_off[SP_MAXP];       // offset (in partial triples) of pair p: [8][ntiles(c_p)]
+  int32_t n_cmax_tiles;          // tiles of the c_max grid (fbar / consp / smax partials)
+  int32_t gr;                    // Gabor radius
+  float* base[SP_MAXL];          // [4][H_l][W_l] per level (levels 1..top)
+  float* gab[SP_MAXL];           // [4][H_l][W_l] per used level
+  uint32_t* rgb_max_part;        // [n_rgb]
+  unsigned long long* rgb_d2_part;  // [n_rgb]
+  float* cs_part;                // triples (min, max, sum of block maxima)
+  float* fbar;                   // [8][Hc][Wc]
+  float* fbar_part;              // [8][n_cmax_tiles] triples
+  float* s_part;                 // [n_cmax_tiles] pairs (max, index as float bits)
+  float w[SP_NCH];
+  float eps, flat_tol, lam, potts;
+  float c45;                     // DC weight of the diagonal Gabor kernels
+  float gf[4][2 * SP_MAXR + 1];  // 1-D Gabor factors: g, g*(cos - c0), g*cos(a u), g*sin(a u)
+};
+
+// Per-step, per-stream inputs and outputs.
+struct StepIO {
+  const uint8_t* rgb;        // [H][W][3] frame t
+  const uint8_t* rgb_prev;   // frame t-1 (null: t = 0, motion is zero)
+  float* S_out;              // [Hc][Wc]
+  float* C_out;              // [8][Hc][Wc] or null
+  float* ckpt;               // base channels of level c_min: overrides base[c_min] when set
+  float* S_tape;             // copy of S for the adjoint (or null)
+  const float* S_in;         // saliency map read by the prior update
+  const uint8_t* seg_prev;   // previous segmentation (null: use the previous prior)
+  const float* pi_prev;      // [H][W] prior of step t-1 (unused at t = 0)
+  float* pi_next;            // [H][W] prior of step t (Kalman state)
+  float* prior_out;          // [H][W] extra copy for the caller (or null)
+  float* f_tape;             // [H][W] prediction f_t (or null)
+  float* ms_tape;            // [2]: max S and its first argmax (or null)
+  float* unary;              // [2][H][W]
+  float* pairwise;           // [4][H][W]
+  float* beta_out;           // [1] or null
+  float K;                   // Kalman gain of this step
+  int32_t t;                 // step index
+  int32_t pad[2];
+};
+
+// Arguments of the adjoint sweep (one frame at a time).
+struct BwdIO {
+  const float* grad;         // [H][W] dL/dpi_t
+  const float* nu_next;      // [H][W] masked adjoint of step t+1 (null: none)
+  float* nu_out;             // [H][W]
+  float* gu;                 // [H][W] adjoint of the unclamped observation
+  float* gs;                 // [Hc][Wc] adjoint of S_t (before the 1/m and argmax terms)
+  float* gk_part;            // per level-0 tile partial of sum nu (q - f)
+  const float* f;            // [H][W] f_t (null at t = 0)
+  const float* S;            // [Hc][Wc] S_t
+  const float* ms;           // [2] m_t, argmax
+  float K;                   // K_t (1 at t = 0)
+  float carry;               // 1 - K_{t+1} (0 when no step reads pi_t)
+  int32_t t, pad;
+};
+
+// Device-resident per-stream state of the batched step.
+struct BatchState {
+  long long t;               // steps done since the reset
+  double P;                  // Kalman variance after the last step
+  float* pi[2];              // prior ping-pong
+  float* S;                  // saliency map scratch [Hc][Wc]
+  const uint8_t* last_rgb;   // frame of the last step (next step's previous frame)
+  int32_t cur, pad;
+};

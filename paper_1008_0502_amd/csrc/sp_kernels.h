@@ -1,0 +1,23 @@
+// Launchers of the HIP kernels (implemented in sp_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "sp_internal.h"
+
+hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios,
+                     const StepIO* io0, int flag, const float* aux, hipStream_t st);
+hipError_t sp_launch_bwd(int kind, const Job* jobs, int n, const StreamDesc* sds, const BwdIO* bios,
+                         const BwdIO* b0, hipStream_t st);
+hipError_t sp_launch_consp_dot(const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios,
+                               const float* gs_all, const float* ms_all, const int* frame_of,
+                               float* dot_part, float* cx_out, hipStream_t st);
+hipError_t sp_launch_bwd_final(int T, int n_lvl0_tiles, int n_cmax_tiles, const float* gk_part,
+                               const float* dot_part, const float* cx, const float* ms_all, const double* Kd,
+                               const double* Pd, double Q, double R, const float* w, float flat_tol,
+                               double* gK_scratch, float* grad_w, float* grad_q, float* grad_r, hipStream_t st);
+hipError_t sp_launch_loss(const float* prior, const uint8_t* mask, size_t n, float* grad, float* part, int nblk,
+                          float* loss, hipStream_t st);
+hipError_t sp_launch_batch_begin(int n, BatchState* st, const uint8_t* const* in_ptrs, StepIO* ios, double Q,
+                                 double R, hipStream_t stream);
+hipError_t sp_launch_batch_reset(int n, BatchState* st, hipStream_t stream);
+hipError_t sp_launch_batch_copy_out(int n, const BatchState* st, const StreamDesc* sds, float* const* out,
+                                    hipStream_t stream);
