@@ -181,6 +181,17 @@ int sp_batch_prior(sp_batch* b, int32_t i, const float** prior);
 int sp_batch_reset(sp_batch* b);
 int sp_batch_destroy(sp_batch* b);
 
+/* Measurement hook: while enabled, every kernel launch of the context is bracketed by
+ * a pair of HIP events recorded on the context's stream (one pair per launch, up to
+ * 65536 pairs).  sp_profile_read synchronises the stream and returns, per kernel kind
+ * 0..SP_NKINDS-1, the summed device time in ms and the number of launches since the
+ * last read (arrays of length n >= SP_NKINDS), then clears the record. */
+#define SP_NKINDS 14
+int sp_profile_enable(sp_ctx* ctx, int32_t enable);
+int sp_profile_read(sp_ctx* ctx, int32_t n, float* total_ms, int32_t* launches);
+/* Name of the kernel behind kind k (static string; "" if out of range). */
+const char* sp_kernel_name(int32_t k);
+
 /* Description of the last error on this host thread ("" if none). */
 const char* sp_last_error(void);
 

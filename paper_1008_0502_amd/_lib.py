@@ -14,6 +14,7 @@ SP_OK, SP_EINVAL, SP_ESHAPE, SP_ENOMEM, SP_EHIP, SP_ESTATE = 0, -1, -2, -3, -4, 
 ERROR_NAMES = {SP_EINVAL: "SP_EINVAL", SP_ESHAPE: "SP_ESHAPE", SP_ENOMEM: "SP_ENOMEM",
                SP_EHIP: "SP_EHIP", SP_ESTATE: "SP_ESTATE"}
 MAX_LEVELS = 12
+NKINDS = 14
 
 c_int32 = ctypes.c_int32
 c_float = ctypes.c_float
@@ -79,6 +80,9 @@ SIGNATURES = [
     ("sp_batch_prior", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
     ("sp_batch_reset", c_int32, [c_void_p]),
     ("sp_batch_destroy", c_int32, [c_void_p]),
+    ("sp_profile_enable", c_int32, [c_void_p, c_int32]),
+    ("sp_profile_read", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_float), ctypes.POINTER(c_int32)]),
+    ("sp_kernel_name", ctypes.c_char_p, [c_int32]),
     ("sp_last_error", ctypes.c_char_p, []),
 ]
 

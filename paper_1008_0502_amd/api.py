@@ -278,11 +278,80 @@ class SaliencyPrior(torch.autograd.Function):
         sp.set_weights(w.detach().float().cpu().tolist(), float(q), float(r))
         out = sp.run_clip(frames)
         ctx.sp = sp
-        ctx.T = frames.shape[0]
+        ctx.meta = [(x.device, x.dtype, x.shape) for x in (w, q, r)]
         return out["pi"]
 
     @staticmethod
     def backward(ctx, grad_pi: torch.Tensor):
         sp: Context = ctx.sp
         gw, gq, gr = sp.saliency_backward(grad_pi.contiguous().float())
-        return None, None, gw, gq.reshape(()), gr.reshape(())
+        grads = [g.to(device=d, dtype=t).reshape(s) for g, (d, t, s) in zip((gw, gq, gr), ctx.meta)]
+        return None, None, grads[0], grads[1], grads[2]
+
+
+def profile_enable(ctx: "Context", on: bool = True) -> None:
+    """Measurement hook of the library: events around every launch of ctx."""
+    check(ctx.lib.sp_profile_enable(ctx._handle, 1 if on else 0), "sp_profile_enable")
+
+
+def profile_read(ctx: "Context"):
+    """{kernel name: (total ms, launches)} since the last read (synchronises)."""
+    n = _lib.NKINDS
+    ms = (ctypes.c_float * n)()
+    cnt = (ctypes.c_int32 * n)()
+    check(ctx.lib.sp_profile_read(ctx._handle, n, ms, cnt), "sp_profile_read")
+    out = {}
+    for k in range(n):
+        if cnt[k]:
+            out[ctx.lib.sp_kernel_name(k).decode()] = (float(ms[k]), int(cnt[k]))
+    return out
+
+
+class Batch:
+    """Many streams of possibly different sizes advanced together, one frame each per
+    step; the step is one replay of a captured HIP graph."""
+
+    def __init__(self, sizes: Sequence[Tuple[int, int]], params: Optional[Params] = None):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("salprior needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.params = params or Params()
+        self.sizes = [(int(h), int(w)) for h, w in sizes]
+        n = len(self.sizes)
+        Hs = (ctypes.c_int32 * n)(*[h for h, _ in self.sizes])
+        Ws = (ctypes.c_int32 * n)(*[w for _, w in self.sizes])
+        self._handle = ctypes.c_void_p()
+        cp = self.params.to_c()
+        check(self.lib.sp_batch_create(ctypes.byref(cp), n, Hs, Ws, _stream(), ctypes.byref(self._handle)),
+              "sp_batch_create")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            check(self.lib.sp_batch_destroy(self._handle), "sp_batch_destroy")
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def pointer_table(frames: Sequence[torch.Tensor]) -> torch.Tensor:
+        """Device int64 tensor holding the data pointers of the given frames."""
+        ptrs = torch.tensor([f.data_ptr() for f in frames], dtype=torch.int64)
+        return ptrs.to(frames[0].device)
+
+    def step(self, rgb_ptrs: torch.Tensor, prior_ptrs: Optional[torch.Tensor] = None) -> None:
+        """rgb_ptrs / prior_ptrs: device int64 tensors of n pointers (see pointer_table)."""
+        n = len(self.sizes)
+        if rgb_ptrs.dtype != torch.int64 or rgb_ptrs.numel() != n or not rgb_ptrs.is_cuda:
+            raise ValueError(f"rgb_ptrs must be a device int64 tensor of {n} pointers")
+        if prior_ptrs is not None and (prior_ptrs.dtype != torch.int64 or prior_ptrs.numel() != n
+                                       or not prior_ptrs.is_cuda):
+            raise ValueError(f"prior_ptrs must be a device int64 tensor of {n} pointers")
+        check(self.lib.sp_batch_step(self._handle, _ptr(rgb_ptrs), _ptr(prior_ptrs)), "sp_batch_step")
+
+    def reset(self) -> None:
+        check(self.lib.sp_batch_reset(self._handle), "sp_batch_reset")

@@ -319,13 +319,33 @@ struct sp_ctx {
   // loss helper
   float* loss_part = nullptr;
   int loss_nblk = 1024;
+  // measurement hook
+  bool prof = false;
+  std::vector<hipEvent_t> ev;     // pairs
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
 };
 
 namespace {
 
+// Brackets a launch with a pair of events when the measurement hook is on.
+template <class F>
+hipError_t timed(sp_ctx* c, int kind, F&& launch) {
+  const bool rec = c->prof && c->ev_used < c->ev_kind.size();
+  if (rec) (void)hipEventRecord(c->ev[2 * c->ev_used], c->stream);
+  hipError_t e = launch();
+  if (rec) {
+    (void)hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
+    c->ev_kind[c->ev_used++] = kind;
+  }
+  return e;
+}
+
 int run_phase(sp_ctx* c, const Phase& ph, const StreamDesc* sds, const StepIO* ios, const StepIO* io0, int n_jobs,
               const float* aux = nullptr) {
-  hipError_t e = sp_launch(ph.kind, c->jobs.dev + ph.off, n_jobs, sds, ios, io0, ph.flag, aux, c->stream);
+  hipError_t e = timed(c, ph.kind, [&] {
+    return sp_launch(ph.kind, c->jobs.dev + ph.off, n_jobs, sds, ios, io0, ph.flag, aux, c->stream);
+  });
   if (e != hipSuccess) return fail(SP_EHIP, "kernel launch (phase kind %d): %s", ph.kind, hipGetErrorString(e));
   return SP_OK;
 }
@@ -404,6 +424,7 @@ int sp_destroy(sp_ctx* c) {
   g_err.clear();
   if (!c) return SP_OK;
   if (c->stream || c->arena) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->arena) (void)hipFree(c->arena);
   if (c->jobs.dev) (void)hipFree(c->jobs.dev);
   delete c;
@@ -729,7 +750,9 @@ int saliency_backward(sp_ctx* c, const float* grad_prior, int32_t T, float* grad
     b.carry = (t + 1 < T && c->uses_pi[t + 1]) ? 1.f - c->Kf[t + 1] : 0.f;
     b.t = t;
     for (const Phase& ph : c->bwd) {
-      hipError_t e = sp_launch_bwd(ph.kind, c->jobs.dev + ph.off, ph.n, c->d_sd, nullptr, &b, c->stream);
+      hipError_t e = timed(c, ph.kind, [&] {
+        return sp_launch_bwd(ph.kind, c->jobs.dev + ph.off, ph.n, c->d_sd, nullptr, &b, c->stream);
+      });
       if (e != hipSuccess) return fail(SP_EHIP, "adjoint launch: %s", hipGetErrorString(e));
     }
   }
@@ -740,19 +763,21 @@ int saliency_backward(sp_ctx* c, const float* grad_prior, int32_t T, float* grad
     const int* fid = c->d_frame_ids + t0;
     for (const Phase& ph : c->rec) {
       const int nj = ph.upto[n];
-      hipError_t e;
-      if (ph.kind == JOB_CONSP_DOT)
-        e = sp_launch_consp_dot(c->jobs.dev + ph.off, nj, c->d_rsd, ios, c->gs_all, c->ms_tape, fid, c->dot_part,
-                                c->cx, c->stream);
-      else
-        e = sp_launch(ph.kind, c->jobs.dev + ph.off, nj, c->d_rsd, ios, nullptr, 0, nullptr, c->stream);
+      hipError_t e = timed(c, ph.kind, [&] {
+        if (ph.kind == JOB_CONSP_DOT)
+          return sp_launch_consp_dot(c->jobs.dev + ph.off, nj, c->d_rsd, ios, c->gs_all, c->ms_tape, fid,
+                                     c->dot_part, c->cx, c->stream);
+        return sp_launch(ph.kind, c->jobs.dev + ph.off, nj, c->d_rsd, ios, nullptr, 0, nullptr, c->stream);
+      });
       if (e != hipSuccess) return fail(SP_EHIP, "recompute launch: %s", hipGetErrorString(e));
     }
   }
   const float* wdev = reinterpret_cast<const float*>(reinterpret_cast<const char*>(c->d_sd) + offsetof(StreamDesc, w));
-  hipError_t e = sp_launch_bwd_final(T, c->n_lvl0_tiles, c->h_sd.n_cmax_tiles, c->gk_part, c->dot_part, c->cx,
-                                     c->ms_tape, c->K_tape, c->P_tape, c->p.q, c->p.r, wdev, c->p.flat_tol,
-                                     c->gK_scratch, grad_w, grad_q, grad_r, c->stream);
+  hipError_t e = timed(c, JOB_LOSS + 1, [&] {
+    return sp_launch_bwd_final(T, c->n_lvl0_tiles, c->h_sd.n_cmax_tiles, c->gk_part, c->dot_part, c->cx,
+                               c->ms_tape, c->K_tape, c->P_tape, c->p.q, c->p.r, wdev, c->p.flat_tol,
+                               c->gK_scratch, grad_w, grad_q, grad_r, c->stream);
+  });
   if (e != hipSuccess) return fail(SP_EHIP, "adjoint reduction launch: %s", hipGetErrorString(e));
   return SP_OK;
 }
@@ -763,7 +788,9 @@ int sp_mse_mask_loss(sp_ctx* c, const float* prior, const uint8_t* mask, int32_t
   if (T < 1) return fail(SP_EINVAL, "T must be >= 1");
   const size_t n = (size_t)T * c->g.H * c->g.W;
   const int nblk = (int)std::min<size_t>(c->loss_nblk, (n + SP_BLOCK - 1) / SP_BLOCK);
-  hipError_t e = sp_launch_loss(prior, mask, n, grad_prior, c->loss_part, nblk, loss, c->stream);
+  hipError_t e = timed(c, JOB_LOSS, [&] {
+    return sp_launch_loss(prior, mask, n, grad_prior, c->loss_part, nblk, loss, c->stream);
+  });
   if (e != hipSuccess) return fail(SP_EHIP, "loss launch: %s", hipGetErrorString(e));
   return SP_OK;
 }
@@ -805,6 +832,50 @@ int sp_set_state(sp_ctx* c, const void* buf, size_t bytes) {
   c->P = sc[1];
   c->tape_ok = false;
   return SP_OK;
+}
+
+int sp_profile_enable(sp_ctx* c, int32_t enable) {
+  g_err.clear();
+  if (!c) return fail(SP_EINVAL, "ctx is NULL");
+  if (enable && c->ev.empty()) {
+    const size_t pairs = 65536;
+    c->ev.resize(2 * pairs, nullptr);
+    for (size_t i = 0; i < c->ev.size(); ++i) HIPCHK(hipEventCreate(&c->ev[i]));
+    c->ev_kind.assign(pairs, 0);
+  }
+  c->prof = enable != 0;
+  c->ev_used = 0;
+  return SP_OK;
+}
+
+int sp_profile_read(sp_ctx* c, int32_t n, float* total_ms, int32_t* launches) {
+  g_err.clear();
+  if (!c || !total_ms || !launches) return fail(SP_EINVAL, "NULL argument");
+  if (n < SP_NKINDS) return fail(SP_EINVAL, "arrays must hold %d kinds", SP_NKINDS);
+  for (int k = 0; k < n; ++k) {
+    total_ms[k] = 0.f;
+    launches[k] = 0;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    const int k = c->ev_kind[i];
+    if (k >= 0 && k < n) {
+      total_ms[k] += ms;
+      launches[k] += 1;
+    }
+  }
+  c->ev_used = 0;
+  return SP_OK;
+}
+
+const char* sp_kernel_name(int32_t k) {
+  static const char* names[SP_NKINDS] = {"k_rgb", "k_feat", "k_down", "k_gabor", "k_csstats", "k_csapply",
+                                         "k_consp", "k_smax", "k_kalman", "k_mrf", "k_bwd_nu", "k_bwd_gs",
+                                         "k_consp_dot", "k_loss"};
+  if (k == SP_NKINDS) return "k_bwd_final";
+  return (k >= 0 && k < SP_NKINDS) ? names[k] : "";
 }
 
 }  // extern "C"
