@@ -1,14 +1,16 @@
 #!/usr/bin/env python3
 """Throughput of the saliency -> Kalman prior -> MRF weight path on one MI355X.
 
-Prints ONE JSON line.  A step is one 640x480 frame (config-1 generator, seed 2) through
-the whole forward path: saliency_forward + prior_update + mrf_weights, inputs resident
-in HBM.  Beside the headline it reports, on the same GPU:
-  * saliency + prior only (no MRF capacities),
-  * fwd+bwd: a 120-frame clip forward with tape, masked-MSE loss and the adjoint,
-  * batched: 16 streams of 640x480 per step (one graph replay), and the mixed batch of
-    64 streams (16 each of 160x120, 320x240, 640x480, 1280x720),
-  * the roofline of the dominant kernel, timed live with HIP events on its stream,
+Prints ONE JSON line.  A step is one replay of the batched step over 16 streams of
+640x480 frames (config-1 generator, seeds 6000+i): every stream's saliency map, Kalman
+prior and MRF capacities, each phase one launch over all streams, inputs resident in
+HBM; value = frames per second over the 16 streams.  Beside the headline it reports, on
+the same GPU:
+  * plain: one 640x480 stream, one frame per sp_step call (and through the three
+    separate calls, and saliency + prior only),
+  * fwd+bwd: a 120-frame 640x480 clip forward with tape, masked-MSE loss and adjoint,
+  * the mixed batch of 64 streams (16 each of 160x120, 320x240, 640x480, 1280x720),
+  * the roofline of the step's dominant kernel, timed live with HIP events,
   * the FP64 CPU oracle on a bounded sample (cpu_baseline).
 """
 from __future__ import annotations
@@ -32,37 +34,50 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def alg_bytes(kind: str, g, launches: int) -> float:
-    """Algorithmic bytes moved by ONE launch of a kernel kind (each input and output
-    array counted once) for geometry g of the plain step; per-kernel formulas."""
-    Hh, Ww = g.H, g.W
-    px = Hh * Ww
-    sizes = g.sizes
+def tail_source(g, lo=1, src=8192, alt=4096, hb=4096, vcap=8192):
+    """Source level of the tail pyramid job (mirror of the library's rule)."""
+    used = {c for c, _ in g.pairs} | {s for _, s in g.pairs}
+    sz = lambda l: g.sizes[l][0] * g.sizes[l][1]
+    for L0 in range(lo, g.top):
+        ok = sz(L0) <= src
+        for l in range(L0 + 1, g.top + 1):
+            ok &= sz(l) <= (alt if (l - L0) % 2 else src)
+            ok &= g.sizes[l - 1][0] * g.sizes[l][1] <= hb
+            if l in used:
+                ok &= 4 * sz(l) <= vcap
+            if not ok:
+                break
+        if ok:
+            return L0
+    return g.top
+
+
+def alg_bytes_per_stream(g, mrf: bool, prior_copy: bool):
+    """Algorithmic bytes one step moves per stream, per kernel (each array read or
+    written once), summed over that kernel's launches in the step."""
+    px = g.H * g.W
     used = sorted({c for c, _ in g.pairs} | {s for _, s in g.pairs})
-    pxl = lambda l: sizes[l][0] * sizes[l][1]
+    pxl = lambda l: g.sizes[l][0] * g.sizes[l][1]
     pc = pxl(g.c_max)
-    if kind == "k_rgb":
-        return 3.0 * px
-    if kind == "k_feat":
-        return 6.0 * px + 16.0 * pxl(1)
-    if kind == "k_down":
-        tot = sum(16.0 * pxl(l) + 16.0 * pxl(l + 1) for l in range(1, g.top))
-        return tot / max(1, g.top - 1)
-    if kind == "k_gabor":
-        return sum(20.0 * pxl(l) for l in used)
-    if kind == "k_csstats":
-        return sum(32.0 * pxl(l) for l in used)
-    if kind == "k_csapply":
-        return sum(32.0 * pxl(l) for l in used) + 32.0 * pc
-    if kind == "k_consp":
-        return 36.0 * pc
-    if kind == "k_smax":
-        return 4.0 * pc
-    if kind == "k_kalman":
-        return 12.0 * px + 4.0 * pc
-    if kind == "k_mrf":
-        return 31.0 * px
-    return float("nan")
+    L0 = tail_source(g)
+    mid = sum(16.0 * pxl(j) + 16.0 * pxl(j + 1) + (20.0 * pxl(j) if j in used else 0.0) for j in range(1, L0))
+    tail = 0.0
+    if L0 < g.top:
+        tail += 16.0 * pxl(L0) + sum(16.0 * pxl(l) for l in range(L0 + 1, g.top + 1))
+        tail += sum(4.0 * pxl(L0) + 16.0 * pxl(l) for l in used if l > L0)
+    if L0 in used:
+        tail += 20.0 * pxl(L0)
+    lev = sum(32.0 * pxl(l) for l in used)
+    return {
+        "k_rgb": 3.0 * px,
+        "k_feat": 6.0 * px + 16.0 * pxl(1) + (16.0 * px if mrf else 0.0),
+        "k_pyr": mid,
+        "k_pyr_tail": tail,
+        "k_csstats": lev,
+        "k_csapply": lev + 32.0 * pc,
+        "k_consp": 36.0 * pc,
+        "k_kalman": 4.0 * pc + 8.0 * px + (4.0 * px if prior_copy else 0.0) + (8.0 * px if mrf else 0.0),
+    }
 
 
 def source_hash() -> str:
@@ -112,14 +127,91 @@ def cpu_baseline(frames_np, budget_s: float):
                       f"Kalman update and MRF capacities in FP64 NumPy, one thread, {dt:.1f} s"}
 
 
+def pmc_summarize(fetch_db: str, write_db: str) -> None:
+    """HBM traffic per launch of each kernel of the batched step from two rocprofv3 --pmc
+    runs of --pmc-workload (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by
+    what the counter reads for the 256 MiB calibration copy."""
+    import re
+    import sqlite3
+
+    def per_kernel(db, counter):
+        con = sqlite3.connect(db)
+        cur = con.cursor()
+        rows = cur.execute(
+            "select k.name, p.value from rocpd_pmc_event p join rocpd_kernel_dispatch d on p.event_id = d.event_id "
+            "join rocpd_info_kernel_symbol k on d.kernel_id = k.id join rocpd_info_pmc i on p.pmc_id = i.id "
+            "where i.name = ?", (counter,)).fetchall()
+        out = {}
+        for name, val in rows:
+            out.setdefault(name, []).append(float(val))
+        return out
+
+    fetch = per_kernel(fetch_db, "FETCH_SIZE")
+    write = per_kernel(write_db, "WRITE_SIZE")
+    copy_bytes = 64 * 1024 * 1024 * 4
+    cal_f = [v for n, vs in fetch.items() if "copy" in n.lower() or "elementwise" in n.lower() for v in vs]
+    cal_w = [v for n, vs in write.items() if "copy" in n.lower() or "elementwise" in n.lower() for v in vs]
+    kf = copy_bytes / (max(cal_f) * 1024.0)
+    kw = copy_bytes / (max(cal_w) * 1024.0)
+    kernels = {}
+    names = {"k_rgb": "k_rgb", "k_feat": "k_feat", "k_pyr<false>": "k_pyr", "k_pyr<true>": "k_pyr_tail",
+             "k_csstats": "k_csstats", "k_csapply": "k_csapply", "k_consp": "k_consp", "k_kalman": "k_kalman"}
+    for raw in set(fetch) | set(write):
+        short = re.sub(r"\(anonymous namespace\)::", "", raw)
+        short = re.sub(r"\(.*\)$", "", short).replace("void ", "").replace(" ", "")
+        key = names.get(short)
+        if key is None:
+            continue
+        f = fetch.get(raw, [0.0])
+        w = write.get(raw, [0.0])
+        fb = sum(f) / len(f) * 1024.0 * kf
+        wb = sum(w) / len(w) * 1024.0 * kw
+        kernels[key] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb}
+    out = {"source_hash": source_hash(), "workload": "batched step, 16 streams of 640x480, MRF on",
+           "calibration": {"copy_bytes": copy_bytes, "fetch_scale": kf, "write_scale": kw},
+           "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", "traffic_batched16_640x480.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def roofline_of(prof, bytes_per_step, n_steps):
+    """Roofline record of the kernel with the largest device time per step."""
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    ms, cnt = prof[dom]
+    avg_s = ms / cnt * 1e-3
+    per_launch = bytes_per_step[dom] / (cnt / n_steps)
+    achieved = per_launch / avg_s / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_batched16_640x480.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            if tj.get("source_hash") == source_hash() and dom in tj.get("kernels", {}):
+                traffic = tj["kernels"][dom]["hbm_bytes_per_launch"]
+        except Exception:
+            traffic = None
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dom,
+            "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--skip", default="", help="comma list of legs to skip: bwd,batched,mixed,cpu,profile")
+    ap.add_argument("--skip", default="", help="comma list of legs to skip: plain,bwd,mixed,cpu,profile")
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="short run for rocprofv3 --pmc: a 256 MiB copy (calibration) then 5 batched steps")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write profiles/traffic_batched16_640x480.json from two rocprofv3 --pmc databases")
     args = ap.parse_args()
+    if args.pmc_summarize:
+        pmc_summarize(*args.pmc_summarize)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(independent streams would shard one group per GPU with no communication).",
@@ -134,34 +226,6 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    log("generating the 640x480 clip")
-    clip = synth.Clip(synth.config1_spec(H=H, W=W, T=T_CLIP, seed=2))
-    frames_np, masks_np = clip.stack()
-    frames = torch.from_numpy(frames_np).to(dev)
-    masks = torch.from_numpy(masks_np).to(dev)
-
-    # ------------------------------------------------------------ plain step
-    ctx = Context(H, W, Params())
-    g = ctx.geometry
-    lib, h = ctx.lib, ctx._handle
-    S = torch.empty((g.Hc, g.Wc), dtype=torch.float32, device=dev)
-    P = torch.empty((H, W), dtype=torch.float32, device=dev)
-    U = torch.empty((2, H, W), dtype=torch.float32, device=dev)
-    PW = torch.empty((4, H, W), dtype=torch.float32, device=dev)
-    B = torch.empty((1,), dtype=torch.float32, device=dev)
-    fp = [frames[t].data_ptr() for t in range(T_CLIP)]
-    sp, pp, up, pwp, bp = S.data_ptr(), P.data_ptr(), U.data_ptr(), PW.data_ptr(), B.data_ptr()
-    stream = torch.cuda.current_stream().cuda_stream
-    lib.sp_set_stream(h, stream)
-
-    def step(i, mrf=True):
-        t = i % T_CLIP
-        rc = lib.saliency_forward(h, fp[t], fp[t - 1] if t else None, sp, None)
-        rc |= lib.prior_update(h, sp, None, pp)
-        if mrf:
-            rc |= lib.mrf_weights(h, fp[t], pp, up, pwp, bp)
-        if rc:
-            raise RuntimeError(lib.sp_last_error().decode())
 
     def timed(fn, n):
         torch.cuda.synchronize()
@@ -171,63 +235,126 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    log(f"plain step: warmup {args.warmup}, timed {args.steps}")
-    timed(step, args.warmup)
-    dt = timed(step, args.steps)
-    ms_step = dt / args.steps * 1e3
-    value = args.steps / dt
-    dt2 = timed(lambda i: step(i, mrf=False), args.steps)
-    fps_sp = args.steps / dt2
+    if args.pmc_workload:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        bf = [torch.from_numpy(synth.Clip(synth.config1_spec(H=H, W=W, T=2, seed=6000 + i)).stack()[0]).to(dev)
+              for i in range(16)]
+        tabs = [Batch.pointer_table([f[t] for f in bf]) for t in range(2)]
+        b = Batch([(H, W)] * 16, Params(), mrf=True)
+        for i in range(5):
+            b.step(tabs[i % 2])
+        torch.cuda.synchronize()
+        b.close()
+        log("pmc workload done")
+        return
 
-    roof = None
-    kernels = {}
+    # ------------------------------------------------------------ headline: batched 16 x 640x480
+    NS, NF = 16, 8
+    log(f"generating {NS} streams x {NF} frames of 640x480")
+    bframes = [torch.from_numpy(synth.Clip(synth.config1_spec(H=H, W=W, T=NF, seed=6000 + i)).stack()[0]).to(dev)
+               for i in range(NS)]
+    tables = [Batch.pointer_table([bf[t] for bf in bframes]) for t in range(NF)]
+    bt = Batch([(H, W)] * NS, Params(), mrf=True)
+    tune_report = bt.autotune(tables[0], steps=5)
+    log("autotune: " + tune_report.strip().replace("\n", "; "))
+    bstep = lambda i: bt.step(tables[i % NF])
+    log(f"batched step: warmup {args.warmup}, timed {args.steps}")
+    timed(bstep, args.warmup)
+    dt = timed(bstep, args.steps)
+    ms_step = dt / args.steps * 1e3
+    value = NS * args.steps / dt
+    log(f"batched: {value:.1f} frames/s ({ms_step:.4f} ms/step)")
+    g = Context(H, W, Params()).geometry
+    roof, kernels = None, {}
     if "profile" not in skip:
-        nprof = min(args.steps, 200)
-        profile_enable(ctx, True)
-        timed(step, nprof)
-        prof = profile_read(ctx)
-        profile_enable(ctx, False)
+        nprof = min(args.steps, 100)
+        profile_enable(bt, True)
+        timed(bstep, nprof)
+        prof = profile_read(bt)
+        profile_enable(bt, False)
+        per_stream = alg_bytes_per_stream(g, mrf=True, prior_copy=False)
+        bytes_step = {k: NS * v for k, v in per_stream.items()}
         for name, (ms, cnt) in prof.items():
-            kernels[name] = {"avg_us": ms / cnt * 1e3, "launches_per_step": cnt / nprof,
-                             "us_per_step": ms / nprof * 1e3}
-        dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
-        ms, cnt = prof[dom]
-        avg_s = ms / cnt * 1e-3
-        ab = alg_bytes(dom, g, cnt)
-        achieved = ab / avg_s / 1e9
-        traffic = None
-        tfile = os.path.join(ROOT, "profiles", "traffic_640x480.json")
-        if os.path.exists(tfile):
-            try:
-                tj = json.load(open(tfile))
-                if tj.get("source_hash") == source_hash() and dom in tj.get("kernels", {}):
-                    traffic = tj["kernels"][dom]["hbm_bytes_per_launch"]
-            except Exception:
-                traffic = None
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dom,
-                "alg_bytes_per_launch": ab, "avg_launch_us": round(avg_s * 1e6, 3)}
-    log(f"plain: {value:.1f} frames/s ({ms_step:.4f} ms/frame); saliency+prior only {fps_sp:.1f}")
+            kernels[name] = {"avg_us": round(ms / cnt * 1e3, 3), "launches_per_step": cnt / nprof,
+                             "us_per_step": round(ms / nprof * 1e3, 3),
+                             "alg_GBps": round(bytes_step.get(name, float("nan")) / (ms / nprof * 1e-3) / 1e9, 2)}
+        roof = roofline_of(prof, bytes_step, nprof)
+    bt.close()
+
+    # ------------------------------------------------------------ plain single stream (config 3 size)
+    plain = None
+    clip = synth.Clip(synth.config1_spec(H=H, W=W, T=T_CLIP, seed=2))
+    frames_np, masks_np = clip.stack()
+    frames = torch.from_numpy(frames_np).to(dev)
+    masks = torch.from_numpy(masks_np).to(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    fp = [frames[t].data_ptr() for t in range(T_CLIP)]
+    if "plain" not in skip:
+        ctx = Context(H, W, Params())
+        lib, h = ctx.lib, ctx._handle
+        S = torch.empty((g.Hc, g.Wc), dtype=torch.float32, device=dev)
+        P = torch.empty((H, W), dtype=torch.float32, device=dev)
+        U = torch.empty((2, H, W), dtype=torch.float32, device=dev)
+        PW = torch.empty((4, H, W), dtype=torch.float32, device=dev)
+        B = torch.empty((1,), dtype=torch.float32, device=dev)
+        sp, pp, up, pwp, bp = S.data_ptr(), P.data_ptr(), U.data_ptr(), PW.data_ptr(), B.data_ptr()
+        lib.sp_set_stream(h, stream)
+
+        def step(i, mrf=True):
+            t = i % T_CLIP
+            rc = lib.sp_step(h, fp[t], fp[t - 1] if t else None, None, sp, None, pp,
+                             up if mrf else None, pwp if mrf else None, bp if mrf else None)
+            if rc:
+                raise RuntimeError(lib.sp_last_error().decode())
+
+        def step_calls(i):
+            t = i % T_CLIP
+            rc = lib.saliency_forward(h, fp[t], fp[t - 1] if t else None, sp, None)
+            rc |= lib.prior_update(h, sp, None, pp)
+            rc |= lib.mrf_weights(h, fp[t], pp, up, pwp, bp)
+            if rc:
+                raise RuntimeError(lib.sp_last_error().decode())
+
+        n = max(args.steps, 100)
+        timed(step, args.warmup)
+        d1 = timed(step, n)
+        d2 = timed(lambda i: step(i, mrf=False), n)
+        d3 = timed(step_calls, n)
+        plain = {"frames_per_s": round(n / d1, 2), "ms_per_frame": round(d1 / n * 1e3, 5),
+                 "saliency_prior_only_frames_per_s": round(n / d2, 2),
+                 "three_calls_frames_per_s": round(n / d3, 2)}
+        if "profile" not in skip:
+            profile_enable(ctx, True)
+            timed(step, 100)
+            pr = profile_read(ctx)
+            profile_enable(ctx, False)
+            plain["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 3) for k, v in pr.items()}
+            pb = alg_bytes_per_stream(g, mrf=True, prior_copy=True)
+            plain["roofline"] = roofline_of(pr, pb, 100)
+        ctx.close()
+        log(f"plain: {plain['frames_per_s']} frames/s")
 
     # ------------------------------------------------------------ fwd + bwd (config 3)
     fb = None
     if "bwd" not in skip:
         tctx = Context(H, W, Params(record_tape=T_CLIP))
-        th = tctx._handle
+        lib, th = tctx.lib, tctx._handle
         lib.sp_set_stream(th, stream)
         Ps = torch.empty((T_CLIP, H, W), dtype=torch.float32, device=dev)
         Ss = torch.empty((T_CLIP, g.Hc, g.Wc), dtype=torch.float32, device=dev)
         loss = torch.empty((1,), dtype=torch.float32, device=dev)
         grad = torch.empty_like(Ps)
-        gw = torch.empty(8, device=dev)
-        gq = torch.empty(1, device=dev)
-        gr = torch.empty(1, device=dev)
+        gw, gq, gr = (torch.empty(8, device=dev), torch.empty(1, device=dev), torch.empty(1, device=dev))
 
         def clip_fb(_):
             lib.sp_reset(th)
             for t in range(T_CLIP):
-                rc = lib.saliency_forward(th, fp[t], fp[t - 1] if t else None, Ss[t].data_ptr(), None)
-                rc |= lib.prior_update(th, Ss[t].data_ptr(), None, Ps[t].data_ptr())
+                rc = lib.sp_step(th, fp[t], fp[t - 1] if t else None, None, Ss[t].data_ptr(), None,
+                                 Ps[t].data_ptr(), None, None, None)
                 if rc:
                     raise RuntimeError(lib.sp_last_error().decode())
             rc = lib.sp_mse_mask_loss(th, Ps.data_ptr(), masks.data_ptr(), T_CLIP, loss.data_ptr(), grad.data_ptr())
@@ -235,41 +362,31 @@ def main():
             if rc:
                 raise RuntimeError(lib.sp_last_error().decode())
 
-        log("fwd+bwd clip")
         timed(clip_fb, 1)
         reps = 3
         dtb = timed(clip_fb, reps)
-        fb = {"frames_per_s": reps * T_CLIP / dtb, "ms_per_clip": dtb / reps * 1e3, "clip_frames": T_CLIP,
-              "loss": float(loss.item())}
+        fb = {"frames_per_s": round(reps * T_CLIP / dtb, 2), "ms_per_clip": round(dtb / reps * 1e3, 4),
+              "clip_frames": T_CLIP, "loss": float(loss.item())}
         tctx.close()
-        log(f"fwd+bwd: {fb['frames_per_s']:.1f} frames/s")
+        log(f"fwd+bwd: {fb['frames_per_s']} frames/s")
 
-    # ------------------------------------------------------------ batched 16 x 640x480
-    def run_batch(sizes, seeds, n_frames, steps, warm):
-        bframes = []
-        for (hh, ww), sd in zip(sizes, seeds):
-            f, _ = synth.Clip(synth.config1_spec(H=hh, W=ww, T=n_frames, seed=sd)).stack()
-            bframes.append(torch.from_numpy(f).to(dev))
-        tables = [Batch.pointer_table([bf[t] for bf in bframes]) for t in range(n_frames)]
-        bt = Batch(sizes, Params())
-        fn = lambda i: bt.step(tables[i % n_frames])
-        timed(fn, warm)
-        dtx = timed(fn, steps)
-        bt.close()
-        return {"frames_per_s": len(sizes) * steps / dtx, "ms_per_step": dtx / steps * 1e3, "streams": len(sizes),
-                "steps": steps}
-
-    batched = mixed = None
-    if "batched" not in skip:
-        log("batched 16 x 640x480")
-        batched = run_batch([(H, W)] * 16, [6000 + i for i in range(16)], 8, 60, 5)
-        log(f"batched: {batched['frames_per_s']:.1f} frames/s")
+    # ------------------------------------------------------------ mixed batch of 64 streams (config 4)
+    mixed = None
     if "mixed" not in skip:
-        log("batched 64 mixed streams")
         sizes = [(120, 160)] * 16 + [(240, 320)] * 16 + [(480, 640)] * 16 + [(720, 1280)] * 16
-        mixed = run_batch(sizes, [1000 + i for i in range(64)], 4, 30, 3)
-        mixed["mpx_per_s"] = sum(hh * ww for hh, ww in sizes) * mixed["frames_per_s"] / 64 / 1e6
-        log(f"mixed: {mixed['frames_per_s']:.1f} frames/s")
+        mf = [torch.from_numpy(synth.Clip(synth.config1_spec(H=hh, W=ww, T=4, seed=1000 + i)).stack()[0]).to(dev)
+              for i, (hh, ww) in enumerate(sizes)]
+        mtab = [Batch.pointer_table([f[t] for f in mf]) for t in range(4)]
+        mb = Batch(sizes, Params())
+        mb.autotune(mtab[0], steps=3)
+        fn = lambda i: mb.step(mtab[i % 4])
+        timed(fn, 3)
+        steps = 30
+        dtm = timed(fn, steps)
+        mb.close()
+        mixed = {"frames_per_s": round(64 * steps / dtm, 2), "ms_per_step": round(dtm / steps * 1e3, 4),
+                 "mpx_per_s": round(sum(hh * ww for hh, ww in sizes) * steps / dtm / 1e6, 1), "streams": 64}
+        log(f"mixed: {mixed['frames_per_s']} frames/s")
 
     cpu = None
     if "cpu" not in skip:
@@ -289,16 +406,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "640x480 single stream, config-1 generator seed 2, 120-frame clip cycled; "
-                               "per step saliency_forward + prior_update + mrf_weights",
-                   "H": H, "W": W, "depth": g.depth, "pairs": g.pairs, "c_max": g.c_max,
+        "config": {"workload": "batched step: 16 streams of 640x480 (config-1 generator, seeds 6000+i, 8 frames "
+                               "cycled), one graph replay per step computing every stream's saliency map, Kalman "
+                               "prior and MRF capacities",
+                   "streams": NS, "H": H, "W": W, "depth": g.depth, "pairs": g.pairs, "c_max": g.c_max,
                    "parallelism": "single GPU"},
-        "fwd_saliency_prior_frames_per_s": round(fps_sp, 2),
-        "fwd_bwd": fb,
-        "batched_16x640x480": batched,
-        "batched_mixed64": mixed,
         "roofline": roof,
         "kernels": kernels,
+        "autotune": tune_report.strip().splitlines(),
+        "plain_640x480": plain,
+        "fwd_bwd_640x480": fb,
+        "batched_mixed64": mixed,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),
     }

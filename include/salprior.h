@@ -143,6 +143,15 @@ int prior_update(sp_ctx* ctx, const float* S, const uint8_t* seg_prev, float* pr
 int mrf_weights(sp_ctx* ctx, const uint8_t* rgb_t, const float* prior, float* unary_out, float* pairwise_out,
                 float* beta_out);
 
+/* The whole per-frame path in one call, with fewer kernel launches than the three
+ * calls above: saliency_forward, then prior_update on S_out, then (when unary_out and
+ * pairwise_out are both given) mrf_weights on the new prior.  The pairwise capacities
+ * are computed in the feature pass and the unary ones in the prior pass.  Arguments
+ * as in those calls (S_out required; C_out, seg_prev, prior_out, unary_out,
+ * pairwise_out, beta_out optional).  Records the tape like the separate calls. */
+int sp_step(sp_ctx* ctx, const uint8_t* rgb_t, const uint8_t* rgb_prev, const uint8_t* seg_prev, float* S_out,
+            float* C_out, float* prior_out, float* unary_out, float* pairwise_out, float* beta_out);
+
 /* Adjoint of the clip recorded since sp_reset (requires record_tape >= T and exactly T
  * prior updates since the reset).
  *   grad_prior [T][H][W] float: dL/d prior_t for every recorded step.
@@ -166,9 +175,12 @@ int sp_set_state(sp_ctx* ctx, const void* dev_buf, size_t bytes);
 /* Batched form: n independent streams of possibly different sizes, one frame each per
  * step, every phase of the step in one launch over all streams, the step captured once
  * in a HIP graph and replayed.  Each stream keeps its Kalman state on the device.
- *   H[n], W[n]: host arrays.  p: shared parameters (record_tape must be 0). */
-int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32_t* W, void* hip_stream,
-                    sp_batch** out);
+ *   H[n], W[n]: host arrays.  p: shared parameters (record_tape must be 0).
+ *   flags: SP_BATCH_MRF also computes every stream's MRF capacities each step into
+ *   buffers the batch owns (read them with sp_batch_outputs). */
+#define SP_BATCH_MRF 1
+int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32_t* W, int32_t flags,
+                    void* hip_stream, sp_batch** out);
 
 /* One step.  rgb_ptrs: DEVICE array of n device pointers to this step's frames (read
  * when the step runs; the frames must stay valid until the next step has run, which
@@ -178,6 +190,11 @@ int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* pri
 
 /* Device pointer to stream i's current prior (valid until the next step). */
 int sp_batch_prior(sp_batch* b, int32_t i, const float** prior);
+/* Device pointers to stream i's saliency map [Hc][Wc] and, with SP_BATCH_MRF, its
+ * unary [2][H][W], pairwise [4][H][W] capacities and beta [1] of the last step (any
+ * output pointer may be NULL; the MRF ones are NULL without SP_BATCH_MRF). */
+int sp_batch_outputs(sp_batch* b, int32_t i, const float** S, const float** unary, const float** pairwise,
+                     const float** beta);
 int sp_batch_reset(sp_batch* b);
 int sp_batch_destroy(sp_batch* b);
 
@@ -186,11 +203,28 @@ int sp_batch_destroy(sp_batch* b);
  * 65536 pairs).  sp_profile_read synchronises the stream and returns, per kernel kind
  * 0..SP_NKINDS-1, the summed device time in ms and the number of launches since the
  * last read (arrays of length n >= SP_NKINDS), then clears the record. */
-#define SP_NKINDS 14
+#define SP_NKINDS 17
 int sp_profile_enable(sp_ctx* ctx, int32_t enable);
 int sp_profile_read(sp_ctx* ctx, int32_t n, float* total_ms, int32_t* launches);
+/* The same measurement hook for a batch: while enabled, sp_batch_step launches the
+ * step's phases one by one (the same kernels as the graph) bracketed by events. */
+int sp_batch_profile_enable(sp_batch* b, int32_t enable);
+int sp_batch_profile_read(sp_batch* b, int32_t n, float* total_ms, int32_t* launches);
 /* Name of the kernel behind kind k (static string; "" if out of range). */
 const char* sp_kernel_name(int32_t k);
+
+/* Autotuner.  Times the candidate launch shapes of the batch -- the width (16, 32 or 64
+ * pixels) of the level-0 update tiles per resolution, and the XCD-aware order of the
+ * job tables on or off -- over `steps` eager steps each on the given frames (device
+ * array of n device pointers, as in sp_batch_step), keeps the fastest, records the
+ * choice per resolution for batches and contexts created later in this process, and
+ * resets the batch.  The candidates compute identical results.  report (may be NULL)
+ * receives a text summary.  Synchronises. */
+int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps, char* report, size_t report_len);
+/* The same for one context, timing the fused step on rgb_t (rgb_prev may be NULL);
+ * resets the context. */
+int sp_autotune(sp_ctx* ctx, const uint8_t* rgb_t, const uint8_t* rgb_prev, int32_t steps, char* report,
+                size_t report_len);
 
 /* Description of the last error on this host thread ("" if none). */
 const char* sp_last_error(void);

@@ -14,7 +14,7 @@ SP_OK, SP_EINVAL, SP_ESHAPE, SP_ENOMEM, SP_EHIP, SP_ESTATE = 0, -1, -2, -3, -4, 
 ERROR_NAMES = {SP_EINVAL: "SP_EINVAL", SP_ESHAPE: "SP_ESHAPE", SP_ENOMEM: "SP_ENOMEM",
                SP_EHIP: "SP_EHIP", SP_ESTATE: "SP_ESTATE"}
 MAX_LEVELS = 12
-NKINDS = 14
+NKINDS = 17
 
 c_int32 = ctypes.c_int32
 c_float = ctypes.c_float
@@ -69,19 +69,27 @@ SIGNATURES = [
     ("saliency_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("prior_update", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("mrf_weights", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("sp_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                          c_void_p, c_void_p]),
     ("saliency_backward", c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     ("sp_mse_mask_loss", c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     ("sp_state_size", c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
     ("sp_get_state", c_int32, [c_void_p, c_void_p, c_size_t]),
     ("sp_set_state", c_int32, [c_void_p, c_void_p, c_size_t]),
     ("sp_batch_create", c_int32, [ctypes.POINTER(sp_params), c_int32, ctypes.POINTER(c_int32),
-                                  ctypes.POINTER(c_int32), c_void_p, ctypes.POINTER(c_void_p)]),
+                                  ctypes.POINTER(c_int32), c_int32, c_void_p, ctypes.POINTER(c_void_p)]),
     ("sp_batch_step", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("sp_batch_prior", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
+    ("sp_batch_outputs", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                   ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     ("sp_batch_reset", c_int32, [c_void_p]),
     ("sp_batch_destroy", c_int32, [c_void_p]),
     ("sp_profile_enable", c_int32, [c_void_p, c_int32]),
     ("sp_profile_read", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_float), ctypes.POINTER(c_int32)]),
+    ("sp_batch_autotune", c_int32, [c_void_p, c_void_p, c_int32, ctypes.c_char_p, c_size_t]),
+    ("sp_autotune", c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_char_p, c_size_t]),
+    ("sp_batch_profile_enable", c_int32, [c_void_p, c_int32]),
+    ("sp_batch_profile_read", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_float), ctypes.POINTER(c_int32)]),
     ("sp_kernel_name", ctypes.c_char_p, [c_int32]),
     ("sp_last_error", ctypes.c_char_p, []),
 ]

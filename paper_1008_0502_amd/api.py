@@ -205,6 +205,45 @@ class Context:
                                    _ptr(beta_out)), "mrf_weights")
         return unary_out, pairwise_out, beta_out
 
+    def step(self, rgb_t: torch.Tensor, rgb_prev: Optional[torch.Tensor] = None,
+             seg_prev: Optional[torch.Tensor] = None, S_out: Optional[torch.Tensor] = None,
+             C_out: Optional[torch.Tensor] = None, prior_out: Optional[torch.Tensor] = None,
+             unary_out: Optional[torch.Tensor] = None, pairwise_out: Optional[torch.Tensor] = None,
+             beta_out: Optional[torch.Tensor] = None):
+        """Whole per-frame path in one call (sp_step); returns (S, prior)."""
+        g = self.geometry
+        _need(rgb_t, "rgb_t", torch.uint8, (g.H, g.W, 3), self.device)
+        if rgb_prev is not None:
+            _need(rgb_prev, "rgb_prev", torch.uint8, (g.H, g.W, 3), self.device)
+        if seg_prev is not None:
+            _need(seg_prev, "seg_prev", torch.uint8, (g.H, g.W), self.device)
+        if S_out is None:
+            S_out = torch.empty((g.Hc, g.Wc), dtype=torch.float32, device=self.device)
+        _need(S_out, "S_out", torch.float32, (g.Hc, g.Wc), self.device)
+        if C_out is not None:
+            _need(C_out, "C_out", torch.float32, (8, g.Hc, g.Wc), self.device)
+        if prior_out is None:
+            prior_out = torch.empty((g.H, g.W), dtype=torch.float32, device=self.device)
+        _need(prior_out, "prior_out", torch.float32, (g.H, g.W), self.device)
+        if unary_out is not None:
+            _need(unary_out, "unary_out", torch.float32, (2, g.H, g.W), self.device)
+        if pairwise_out is not None:
+            _need(pairwise_out, "pairwise_out", torch.float32, (4, g.H, g.W), self.device)
+        if beta_out is not None:
+            _need(beta_out, "beta_out", torch.float32, (1,), self.device)
+        self._bind_stream()
+        check(self.lib.sp_step(self._handle, _ptr(rgb_t), _ptr(rgb_prev), _ptr(seg_prev), _ptr(S_out), _ptr(C_out),
+                               _ptr(prior_out), _ptr(unary_out), _ptr(pairwise_out), _ptr(beta_out)), "sp_step")
+        return S_out, prior_out
+
+    def autotune(self, rgb_t: torch.Tensor, rgb_prev: Optional[torch.Tensor] = None, steps: int = 10) -> str:
+        """Pick the fastest launch shapes for this resolution; resets the context."""
+        buf = ctypes.create_string_buffer(4096)
+        self._bind_stream()
+        check(self.lib.sp_autotune(self._handle, _ptr(rgb_t), _ptr(rgb_prev), int(steps), buf, len(buf)),
+              "sp_autotune")
+        return buf.value.decode()
+
     def saliency_backward(self, grad_prior: torch.Tensor):
         g = self.geometry
         T = grad_prior.shape[0]
@@ -289,21 +328,26 @@ class SaliencyPrior(torch.autograd.Function):
         return None, None, grads[0], grads[1], grads[2]
 
 
-def profile_enable(ctx: "Context", on: bool = True) -> None:
-    """Measurement hook of the library: events around every launch of ctx."""
-    check(ctx.lib.sp_profile_enable(ctx._handle, 1 if on else 0), "sp_profile_enable")
+def profile_enable(ctx, on: bool = True) -> None:
+    """Measurement hook of the library: events around every launch of a Context or
+    Batch (a profiled batch launches its phases eagerly instead of replaying the graph)."""
+    fn = ctx.lib.sp_batch_profile_enable if isinstance(ctx, Batch) else ctx.lib.sp_profile_enable
+    check(fn(ctx._handle, 1 if on else 0), "profile_enable")
 
 
-def profile_read(ctx: "Context"):
+def profile_read(ctx):
     """{kernel name: (total ms, launches)} since the last read (synchronises)."""
     n = _lib.NKINDS
     ms = (ctypes.c_float * n)()
     cnt = (ctypes.c_int32 * n)()
-    check(ctx.lib.sp_profile_read(ctx._handle, n, ms, cnt), "sp_profile_read")
+    fn = ctx.lib.sp_batch_profile_read if isinstance(ctx, Batch) else ctx.lib.sp_profile_read
+    check(fn(ctx._handle, n, ms, cnt), "profile_read")
     out = {}
     for k in range(n):
         if cnt[k]:
-            out[ctx.lib.sp_kernel_name(k).decode()] = (float(ms[k]), int(cnt[k]))
+            name = ctx.lib.sp_kernel_name(k).decode()
+            t0, c0 = out.get(name, (0.0, 0))
+            out[name] = (t0 + float(ms[k]), c0 + int(cnt[k]))
     return out
 
 
@@ -311,7 +355,7 @@ class Batch:
     """Many streams of possibly different sizes advanced together, one frame each per
     step; the step is one replay of a captured HIP graph."""
 
-    def __init__(self, sizes: Sequence[Tuple[int, int]], params: Optional[Params] = None):
+    def __init__(self, sizes: Sequence[Tuple[int, int]], params: Optional[Params] = None, mrf: bool = False):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("salprior needs a ROCm GPU; torch.cuda.is_available() is False")
@@ -322,8 +366,9 @@ class Batch:
         Ws = (ctypes.c_int32 * n)(*[w for _, w in self.sizes])
         self._handle = ctypes.c_void_p()
         cp = self.params.to_c()
-        check(self.lib.sp_batch_create(ctypes.byref(cp), n, Hs, Ws, _stream(), ctypes.byref(self._handle)),
-              "sp_batch_create")
+        check(self.lib.sp_batch_create(ctypes.byref(cp), n, Hs, Ws, 1 if mrf else 0, _stream(),
+                                       ctypes.byref(self._handle)), "sp_batch_create")
+        self.mrf = mrf
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     def close(self) -> None:
@@ -355,3 +400,17 @@ class Batch:
 
     def reset(self) -> None:
         check(self.lib.sp_batch_reset(self._handle), "sp_batch_reset")
+
+    def autotune(self, rgb_ptrs: torch.Tensor, steps: int = 5) -> str:
+        """Pick the fastest launch shapes for these frames (results do not change)."""
+        buf = ctypes.create_string_buffer(4096)
+        check(self.lib.sp_batch_autotune(self._handle, _ptr(rgb_ptrs), int(steps), buf, len(buf)),
+              "sp_batch_autotune")
+        return buf.value.decode()
+
+    def output_pointers(self, i: int):
+        """Device pointers (ints) of stream i's S, unary, pairwise and beta buffers."""
+        ptrs = [ctypes.c_void_p() for _ in range(4)]
+        check(self.lib.sp_batch_outputs(self._handle, int(i), *[ctypes.byref(p) for p in ptrs]),
+              "sp_batch_outputs")
+        return [p.value for p in ptrs]

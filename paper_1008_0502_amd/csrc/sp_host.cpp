@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -48,6 +50,12 @@ struct Geo {
 };
 
 bool is_fin(double v) { return std::isfinite(v); }
+
+constexpr size_t kMaxDynLds = 150 * 1024;   // dynamic LDS of the across-scale-sum job (gfx950: 160 KB per CU)
+
+size_t csapply_lds_bytes(const Geo& g) {
+  return sizeof(float) * (size_t)csapply_layout(g.pc, g.ps, g.n_pairs, g.c_max).total;
+}
 
 int validate_params(const sp_params* p) {
   if (!p) return fail(SP_EINVAL, "params is NULL");
@@ -120,16 +128,115 @@ int make_geo(const sp_params& p, int H, int W, Geo& g) {
   for (int a = 0; a < g.n_pairs; ++a)
     for (int b = 0; b < a; ++b)
       if (g.pc[a] == g.pc[b] && g.ps[a] == g.ps[b]) return fail(SP_EINVAL, "duplicate centre-surround pair");
+  if (csapply_lds_bytes(g) > kMaxDynLds)
+    return fail(SP_ESHAPE, "centre-surround configuration needs %zu bytes of LDS per workgroup (max %zu)",
+                csapply_lds_bytes(g), kMaxDynLds);
   return SP_OK;
 }
 
 int ntiles(int h, int w) { return ((h + kTile - 1) / kTile) * ((w + kTile - 1) / kTile); }
 
-void add_tiles(std::vector<Job>& v, int stream, int a, int h, int w) {
+void add_tiles(std::vector<Job>& v, int stream, int a, int h, int w, int kind = 0) {
   int tid = 0;
   for (int y0 = 0; y0 < h; y0 += kTile)
     for (int x0 = 0; x0 < w; x0 += kTile)
-      v.push_back(Job{stream, a, y0, x0, std::min(kTile, h - y0), std::min(kTile, w - x0), tid++, 0});
+      v.push_back(Job{stream, a, y0, x0, std::min(kTile, h - y0), std::min(kTile, w - x0), tid++, kind});
+}
+
+void add_tiles_wh(std::vector<Job>& v, int stream, int a, int h, int w, int th, int tw, int kind) {
+  int tid = 0;
+  for (int y0 = 0; y0 < h; y0 += th)
+    for (int x0 = 0; x0 < w; x0 += tw)
+      v.push_back(Job{stream, a, y0, x0, std::min(th, h - y0), std::min(tw, w - x0), tid++, kind});
+}
+
+// Tuning knobs that never change results: the width of the level-0 update tiles and
+// the XCD-aware order of the job tables.
+struct Tune {
+  int kalman_tw = 32;   // 16, 32 or 64
+  bool xcd = false;
+};
+
+// Choices of the autotuner per resolution, reused by later contexts and batches.
+std::map<std::pair<int, int>, int>& tune_cache_tw() {
+  static std::map<std::pair<int, int>, int> m;
+  return m;
+}
+bool& tune_cache_xcd() {
+  static bool x = false;
+  return x;
+}
+std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+Tune cached_tune(int H, int W) {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  Tune t;
+  auto it = tune_cache_tw().find({H, W});
+  if (it != tune_cache_tw().end()) t.kalman_tw = it->second;
+  t.xcd = tune_cache_xcd();
+  return t;
+}
+
+// Reorders a launch's jobs so that workgroups dispatched round-robin over the 8 XCDs
+// get contiguous runs of tiles (neighbouring tiles share halos in that XCD's L2).
+void xcd_order(std::vector<Job>& v) {
+  const size_t n = v.size();
+  if (n < 16) return;
+  std::vector<Job> out;
+  out.reserve(n);
+  std::vector<size_t> start(9);
+  for (int x = 0; x <= 8; ++x) start[x] = n * x / 8;
+  for (size_t k = 0;; ++k) {
+    bool any = false;
+    for (int x = 0; x < 8; ++x)
+      if (start[x] + k < start[x + 1]) {
+        out.push_back(v[start[x] + k]);
+        any = true;
+      }
+    if (!any) break;
+  }
+  v.swap(out);
+}
+
+// Source level of the tail job: the first level >= lo from which every higher level
+// (and the Gabor maps of the used ones) fits the LDS buffers of one workgroup.
+int tail_source(const Geo& g, int lo) {
+  auto sz = [&](int l) { return (long long)g.Hl[l] * g.Wl[l]; };
+  for (int L0 = lo; L0 < g.top; ++L0) {
+    bool ok = sz(L0) <= SP_TAIL_SRC;
+    for (int l = L0 + 1; ok && l <= g.top; ++l) {
+      ok &= sz(l) <= (((l - L0) & 1) ? SP_TAIL_ALT : SP_TAIL_SRC);
+      ok &= (long long)g.Hl[l - 1] * g.Wl[l] <= SP_TAIL_HB;
+      if (g.used & (1u << l)) ok &= 4 * sz(l) <= SP_TAIL_V;
+    }
+    if (ok) return L0;
+  }
+  return g.top;
+}
+
+// Pyramid stages of one stream above level lo (level lo already computed):
+// DOWN(j -> j+1) + GABOR(j) for j < L0, then TAIL(L0) + GABOR(L0).
+// Returns the middle stages and the final stage; *big says whether it has tail jobs.
+void pyramid_stages(const Geo& g, int s, int lo, std::vector<std::vector<Job>>& mid, std::vector<Job>& fin,
+                    bool* big) {
+  const int L0 = tail_source(g, lo);
+  mid.clear();
+  fin.clear();
+  for (int j = lo; j < L0; ++j) {
+    std::vector<Job> v;
+    add_tiles(v, s, j, g.Hl[j + 1], g.Wl[j + 1], JOB_DOWN);
+    if (g.used & (1u << j)) add_tiles(v, s, j, g.Hl[j], g.Wl[j], JOB_GABOR);
+    mid.push_back(std::move(v));
+  }
+  *big = L0 < g.top;
+  if (*big) {
+    for (int l = g.top; l > L0; --l)   // the largest Gabor level first: it is the longest job
+      if (g.used & (1u << l)) fin.push_back(Job{s, L0, 0, 0, g.Hl[l], g.Wl[l], l, JOB_TAILGAB});
+    for (int ch = 0; ch < 4; ++ch) fin.push_back(Job{s, L0, 0, 0, g.Hl[L0], g.Wl[L0], ch, JOB_TAIL});
+  }
+  if (g.used & (1u << L0)) add_tiles(fin, s, L0, g.Hl[L0], g.Wl[L0], JOB_GABOR);
 }
 
 // ---------------------------------------------------------------- device memory layout
@@ -144,6 +251,13 @@ struct Bump {
     return p;
   }
 };
+
+// Pixels per colour-statistics workgroup: 1024 * G with at most 256 workgroups.
+int rgb_chunk(const Geo& g) {
+  const long long px = (long long)g.H * g.W;
+  const long long G = std::max<long long>(1, (px + 256 * 1024 - 1) / (256 * 1024));
+  return (int)(1024 * G);
+}
 
 void fill_taps(StreamDesc& sd, const sp_params& p) {
   const int R = p.gabor_radius;
@@ -200,6 +314,7 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
     off += SP_NCH * sd.ntiles_lvl[g.pc[i]];
   }
   sd.n_cmax_tiles = sd.ntiles_lvl[g.c_max];
+  sd.used = g.used;
   for (int k = 0; k < SP_NCH; ++k) sd.w[k] = p.weights[k];
   sd.eps = p.eps;
   sd.flat_tol = p.flat_tol;
@@ -211,10 +326,7 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
   for (int l = 1; l <= g.top; ++l)
     if (g.used & (1u << l)) sd.gab[l] = bump.take<float>((size_t)4 * g.Hl[l] * g.Wl[l]);
   if (rgb_parts) {
-    const long long px = (long long)g.H * g.W;
-    int nb = (int)std::min<long long>(256, std::max<long long>(1, (px + 8191) / 8192));
-    const int rows = (g.H + nb - 1) / nb;
-    sd.n_rgb = (g.H + rows - 1) / rows;
+    sd.n_rgb = (int)((g.H * (long long)g.W + rgb_chunk(g) - 1) / rgb_chunk(g));
     sd.rgb_max_part = bump.take<uint32_t>(sd.n_rgb);
     sd.rgb_d2_part = bump.take<unsigned long long>(sd.n_rgb);
   }
@@ -224,17 +336,19 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
   sd.s_part = bump.take<float>((size_t)2 * sd.n_cmax_tiles);
 }
 
-void rgb_jobs(std::vector<Job>& v, int s, const StreamDesc& sd) {
-  const int rows = (sd.H + sd.n_rgb - 1) / sd.n_rgb;
+void rgb_jobs(std::vector<Job>& v, int s, const StreamDesc& sd, const Geo& g) {
+  const int chunk = rgb_chunk(g);
+  const int px = sd.H * sd.W;
   for (int i = 0; i < sd.n_rgb; ++i) {
-    const int y0 = i * rows;
-    v.push_back(Job{s, i, y0, 0, std::min(rows, sd.H - y0), sd.W, i, 0});
+    const int p0 = i * chunk;
+    v.push_back(Job{s, i, p0, 0, std::min(chunk, px - p0), 1, i, JOB_RGB});
   }
 }
 
 // ---------------------------------------------------------------- job tables
 struct Phase {
   int kind = 0, flag = 0;
+  size_t lds = 0;             // dynamic LDS bytes of the launch
   size_t off = 0;             // first job in the device table
   int n = 0;                  // jobs
   std::vector<int> upto;      // upto[s]: jobs of streams < s (stream-major tables)
@@ -243,6 +357,7 @@ struct Phase {
 struct JobStore {
   std::vector<Job> host;
   Job* dev = nullptr;
+  size_t cap = 0;   // jobs the device buffer holds
   Phase add(int kind, int flag, const std::vector<Job>& jobs, int n_streams) {
     Phase ph;
     ph.kind = kind;
@@ -256,6 +371,27 @@ struct JobStore {
     return ph;
   }
 };
+
+// Uploads the host job table, growing the device buffer when needed (set-up calls only).
+int upload_jobs(JobStore& js, hipStream_t st) {
+  const size_t n = std::max<size_t>(1, js.host.size());
+  if (n > js.cap) {
+    if (js.dev) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(js.dev);
+      js.dev = nullptr;
+      js.cap = 0;
+    }
+    if (hipMalloc(&js.dev, sizeof(Job) * n) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SP_ENOMEM, "hipMalloc of the job tables failed");
+    }
+    js.cap = n;
+  }
+  HIPCHK(hipMemcpyAsync(js.dev, js.host.data(), sizeof(Job) * js.host.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SP_OK;
+}
 
 // Per-stream phase program of the forward saliency map.
 enum ProgPart { PROG_ALL, PROG_RECOMPUTE };
@@ -272,6 +408,60 @@ double now_gain(int64_t t, double Pprev, double Q, double R, double* P) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- measurement hook
+// One pair of events per launch, recorded on the launch stream.
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;   // pairs
+  std::vector<int> kind;
+  size_t used = 0;
+  int enable(bool en) {
+    if (en && ev.empty()) {
+      const size_t pairs = 65536;
+      ev.assign(2 * pairs, nullptr);
+      for (size_t i = 0; i < ev.size(); ++i) HIPCHK(hipEventCreate(&ev[i]));
+      kind.assign(pairs, 0);
+    }
+    on = en;
+    used = 0;
+    return SP_OK;
+  }
+  template <class F>
+  hipError_t timed(hipStream_t st, int k, F&& launch) {
+    const bool rec = on && used < kind.size();
+    if (rec) (void)hipEventRecord(ev[2 * used], st);
+    hipError_t e = launch();
+    if (rec) {
+      (void)hipEventRecord(ev[2 * used + 1], st);
+      kind[used++] = k;
+    }
+    return e;
+  }
+  int read(hipStream_t st, int n, float* total_ms, int32_t* launches) {
+    if (!total_ms || !launches) return fail(SP_EINVAL, "NULL argument");
+    if (n < SP_NKINDS) return fail(SP_EINVAL, "arrays must hold %d kinds", SP_NKINDS);
+    for (int k = 0; k < n; ++k) {
+      total_ms[k] = 0.f;
+      launches[k] = 0;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < used; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      if (kind[i] >= 0 && kind[i] < n) {
+        total_ms[kind[i]] += ms;
+        launches[kind[i]] += 1;
+      }
+    }
+    used = 0;
+    return SP_OK;
+  }
+  void destroy() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  }
+};
 
 // ---------------------------------------------------------------- context
 struct sp_ctx {
@@ -316,35 +506,28 @@ struct sp_ctx {
   StepIO* d_rio = nullptr;        // [cap] io of every tape frame (ckpt pointers)
   int* d_frame_ids = nullptr;     // [cap] = 0..cap-1
   std::vector<Phase> rec;         // recompute phases (stream-major, CH streams)
+  float* S_scratch = nullptr;     // [Hc][Wc] saliency map of the autotuner's steps
   // loss helper
   float* loss_part = nullptr;
   int loss_nblk = 1024;
-  // measurement hook
-  bool prof = false;
-  std::vector<hipEvent_t> ev;     // pairs
-  std::vector<int> ev_kind;
-  size_t ev_used = 0;
+  Profiler prof;
+  Tune tune;
 };
 
 namespace {
 
+int ctx_build_tables(sp_ctx* c);
+
 // Brackets a launch with a pair of events when the measurement hook is on.
 template <class F>
 hipError_t timed(sp_ctx* c, int kind, F&& launch) {
-  const bool rec = c->prof && c->ev_used < c->ev_kind.size();
-  if (rec) (void)hipEventRecord(c->ev[2 * c->ev_used], c->stream);
-  hipError_t e = launch();
-  if (rec) {
-    (void)hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
-    c->ev_kind[c->ev_used++] = kind;
-  }
-  return e;
+  return c->prof.timed(c->stream, kind, launch);
 }
 
 int run_phase(sp_ctx* c, const Phase& ph, const StreamDesc* sds, const StepIO* ios, const StepIO* io0, int n_jobs,
               const float* aux = nullptr) {
   hipError_t e = timed(c, ph.kind, [&] {
-    return sp_launch(ph.kind, c->jobs.dev + ph.off, n_jobs, sds, ios, io0, ph.flag, aux, c->stream);
+    return sp_launch(ph.kind, c->jobs.dev + ph.off, n_jobs, sds, ios, io0, ph.flag, aux, c->stream, ph.lds);
   });
   if (e != hipSuccess) return fail(SP_EHIP, "kernel launch (phase kind %d): %s", ph.kind, hipGetErrorString(e));
   return SP_OK;
@@ -358,23 +541,20 @@ void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& 
   };
   if (which == PROG_ALL) {
     std::vector<Job> v;
-    rgb_jobs(v, s, sd);
+    rgb_jobs(v, s, sd, g);
     push(JOB_RGB, v);
     v.clear();
-    add_tiles(v, s, 1, g.Hl[1], g.Wl[1]);
+    add_tiles(v, s, 1, g.Hl[1], g.Wl[1], JOB_FEAT);
     push(JOB_FEAT, v);
   }
   const int from = (which == PROG_ALL) ? 1 : g.c_min;
-  for (int l = from; l < g.top; ++l) {
-    std::vector<Job> v;
-    add_tiles(v, s, l, g.Hl[l + 1], g.Wl[l + 1]);
-    push(JOB_DOWN, v);
-  }
+  std::vector<std::vector<Job>> mid;
+  std::vector<Job> fin;
+  bool big = false;
+  pyramid_stages(g, s, from, mid, fin, &big);
+  for (auto& m : mid) push(JOB_DOWN, m);
+  if (!fin.empty()) push(big ? JOB_TAIL : JOB_DOWN, fin);
   std::vector<Job> v;
-  for (int l = 1; l <= g.top; ++l)
-    if (g.used & (1u << l)) add_tiles(v, s, l, g.Hl[l], g.Wl[l]);
-  push(JOB_GABOR, v);
-  v.clear();
   for (int c = 0; c <= g.top; ++c) {
     bool has = false;
     for (int i = 0; i < g.n_pairs; ++i) has |= (g.pc[i] == c);
@@ -424,7 +604,7 @@ int sp_destroy(sp_ctx* c) {
   g_err.clear();
   if (!c) return SP_OK;
   if (c->stream || c->arena) (void)hipStreamSynchronize(c->stream);
-  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->prof.destroy();
   if (c->arena) (void)hipFree(c->arena);
   if (c->jobs.dev) (void)hipFree(c->jobs.dev);
   delete c;
@@ -463,6 +643,7 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
     c->pi_state[0] = b.take<float>(HW);
     c->pi_state[1] = b.take<float>(HW);
     c->loss_part = b.take<float>(c->loss_nblk);
+    c->S_scratch = b.take<float>((size_t)Hc * Wc);
     std::vector<StreamDesc> rsd(c->CH);
     if (c->cap > 0) {
       c->ckpt = b.take<float>((size_t)c->cap * 4 * g.Hl[g.c_min] * g.Wl[g.c_min]);
@@ -517,20 +698,56 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
       }
     }
   }
-  // job tables
+  if (sp_csapply_reserve_lds(csapply_lds_bytes(g)) != hipSuccess) {
+    sp_destroy(c);
+    return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", csapply_lds_bytes(g));
+  }
+  c->tune = cached_tune(H, W);
+  int rc2 = ctx_build_tables(c);
+  if (rc2) {
+    std::string msg = g_err;
+    sp_destroy(c);
+    g_err = msg;
+    return rc2;
+  }
+  *out = c;
+  return SP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// (Re)builds every job table of a context from its geometry and tuning knobs.
+int ctx_build_tables(sp_ctx* c) {
+  const Geo& g = c->g;
+  const int H = g.H, W = g.W, Hc = g.Hl[g.c_max], Wc = g.Wl[g.c_max];
+  c->jobs.host.clear();
+  c->fwd.clear();
+  c->prior.clear();
+  c->mrf.clear();
+  c->bwd.clear();
+  c->rec.clear();
+  auto order = [&](std::vector<Job> v) {
+    if (c->tune.xcd) xcd_order(v);
+    return v;
+  };
   {
     std::vector<std::vector<Job>> parts;
     std::vector<int> kinds;
     build_forward_jobs(parts, kinds, c->h_sd, g, 0, PROG_ALL);
-    for (size_t i = 0; i < parts.size(); ++i) c->fwd.push_back(c->jobs.add(kinds[i], 0, parts[i], 1));
+    for (size_t i = 0; i < parts.size(); ++i) {
+      c->fwd.push_back(c->jobs.add(kinds[i], 0, order(parts[i]), 1));
+      if (kinds[i] == JOB_CSAPPLY) c->fwd.back().lds = csapply_lds_bytes(g);
+    }
     std::vector<Job> v;
     add_tiles(v, 0, 0, Hc, Wc);
     c->prior.push_back(c->jobs.add(JOB_SMAX, 0, v, 1));
     v.clear();
-    add_tiles(v, 0, 0, H, W);
-    c->prior.push_back(c->jobs.add(JOB_KALMAN, 0, v, 1));
+    add_tiles_wh(v, 0, 0, H, W, 16, c->tune.kalman_tw, JOB_KALMAN);
+    c->prior.push_back(c->jobs.add(JOB_KALMAN, 0, order(v), 1));
     v.clear();
-    rgb_jobs(v, 0, c->h_sd);
+    rgb_jobs(v, 0, c->h_sd, g);
     c->mrf.push_back(c->jobs.add(JOB_RGB, 1, v, 1));
     v.clear();
     add_tiles(v, 0, 0, H, W);
@@ -554,22 +771,18 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
         }
         for (size_t i = 0; i < ps.size(); ++i) all[i].insert(all[i].end(), ps[i].begin(), ps[i].end());
       }
-      for (size_t i = 0; i < all.size(); ++i) c->rec.push_back(c->jobs.add(kk[i], 0, all[i], c->CH));
-    }
-    if (hipMalloc(&c->jobs.dev, sizeof(Job) * c->jobs.host.size()) != hipSuccess) {
-      (void)hipGetLastError();
-      sp_destroy(c);
-      return fail(SP_ENOMEM, "hipMalloc of the job tables failed");
-    }
-    if (hipMemcpy(c->jobs.dev, c->jobs.host.data(), sizeof(Job) * c->jobs.host.size(), hipMemcpyHostToDevice) !=
-        hipSuccess) {
-      sp_destroy(c);
-      return fail(SP_EHIP, "uploading job tables failed");
+      for (size_t i = 0; i < all.size(); ++i) {
+        c->rec.push_back(c->jobs.add(kk[i], 0, all[i], c->CH));
+        if (kk[i] == JOB_CSAPPLY) c->rec.back().lds = csapply_lds_bytes(g);
+      }
     }
   }
-  *out = c;
-  return SP_OK;
+  return upload_jobs(c->jobs, c->stream);
 }
+
+}  // namespace
+
+extern "C" {
 
 int sp_set_stream(sp_ctx* c, void* hip_stream) {
   g_err.clear();
@@ -695,6 +908,124 @@ int prior_update(sp_ctx* c, const float* S, const uint8_t* seg_prev, float* prio
   return SP_OK;
 }
 
+int sp_step(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, const uint8_t* seg_prev, float* S_out,
+            float* C_out, float* prior_out, float* unary_out, float* pairwise_out, float* beta_out) {
+  g_err.clear();
+  if (!c || !rgb_t || !S_out) return fail(SP_EINVAL, "ctx, rgb_t and S_out must not be NULL");
+  if ((unary_out == nullptr) != (pairwise_out == nullptr))
+    return fail(SP_EINVAL, "unary_out and pairwise_out must be given together");
+  if (c->cap > 0 && c->t >= c->cap)
+    return fail(SP_ESTATE, "tape holds %d frames; call sp_reset first", c->cap);
+  const bool mrf = unary_out != nullptr;
+  const Geo& g = c->g;
+  StepIO io;
+  std::memset(&io, 0, sizeof io);
+  io.rgb = rgb_t;
+  io.rgb_prev = rgb_prev;
+  io.S_out = S_out;
+  io.C_out = C_out;
+  io.S_in = S_out;
+  io.seg_prev = seg_prev;
+  io.pi_prev = c->pi_state[c->cur];
+  io.pi_next = c->pi_state[c->cur ^ 1];
+  io.prior_out = prior_out;
+  if (mrf) {
+    io.unary = unary_out;
+    io.pairwise = pairwise_out;
+    io.beta_out = beta_out;
+  }
+  double Pn = 0.0;
+  const double K = now_gain(c->t, c->P, c->p.q, c->p.r, &Pn);
+  io.K = (float)K;
+  io.t = (int32_t)std::min<int64_t>(c->t, 0x7fffffff);
+  if (c->cap > 0) {
+    io.ckpt = c->ckpt + (size_t)c->t * 4 * g.Hl[g.c_min] * g.Wl[g.c_min];
+    io.S_tape = c->S_tape + (size_t)c->t * g.Hl[g.c_max] * g.Wl[g.c_max];
+    io.f_tape = c->f_tape + (size_t)c->t * g.H * g.W;
+    io.ms_tape = c->ms_tape + (size_t)c->t * 2;
+  }
+  for (const Phase& ph0 : c->fwd) {
+    Phase ph = ph0;
+    if (ph.kind == JOB_RGB) ph.flag = mrf ? 1 : 0;
+    int rc = run_phase(c, ph, c->d_sd, nullptr, &io, ph.n);
+    if (rc) return rc;
+  }
+  int rc = run_phase(c, c->prior.back(), c->d_sd, nullptr, &io, c->prior.back().n);   // the Kalman phase
+  if (rc) return rc;
+  if (c->cap > 0) {
+    c->Kf.push_back((float)K);
+    c->uses_pi.push_back(seg_prev == nullptr && c->t > 0);
+  }
+  c->P = Pn;
+  c->cur ^= 1;
+  c->t += 1;
+  return SP_OK;
+}
+
+int sp_autotune(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, int32_t steps, char* report,
+                size_t report_len) {
+  g_err.clear();
+  if (!c || !rgb_t) return fail(SP_EINVAL, "ctx and rgb_t must not be NULL");
+  if (steps < 1 || steps > 1000) return fail(SP_EINVAL, "steps must be 1..1000");
+  if (c->cap > 0) return fail(SP_ESTATE, "autotune a context without a tape");
+  const Geo& g = c->g;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float* S_out = c->S_scratch;   // the state is reset at the end
+  std::string rep;
+  char line[160];
+  auto time_it = [&](double* ms) -> int {
+    int r = ctx_build_tables(c);
+    if (r) return r;
+    r = sp_step(c, rgb_t, rgb_prev, nullptr, S_out, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (r) return r;
+    HIPCHK(hipEventRecord(e0, c->stream));
+    for (int i = 0; i < steps && !r; ++i)
+      r = sp_step(c, rgb_t, rgb_prev, nullptr, S_out, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (r) return r;
+    HIPCHK(hipEventRecord(e1, c->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, e0, e1));
+    *ms = f / steps;
+    return SP_OK;
+  };
+  int rc = SP_OK;
+  double best = 1e30, t = 0;
+  Tune bt = c->tune;
+  for (int x = 0; x < 2 && !rc; ++x)
+    for (int tw : {16, 32, 64}) {
+      c->tune.xcd = x != 0;
+      c->tune.kalman_tw = tw;
+      rc = time_it(&t);
+      if (rc) break;
+      snprintf(line, sizeof line, "%dx%d xcd_order=%d kalman tile 16x%d: %.4f ms/frame\n", g.H, g.W, x, tw, t);
+      rep += line;
+      if (t < best) {
+        best = t;
+        bt = c->tune;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  c->tune = bt;
+  rc = ctx_build_tables(c);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    tune_cache_tw()[{g.H, g.W}] = bt.kalman_tw;
+    tune_cache_xcd() = bt.xcd;
+  }
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return sp_reset(c);
+}
+
 int mrf_weights(sp_ctx* c, const uint8_t* rgb_t, const float* prior, float* unary_out, float* pairwise_out,
                 float* beta_out) {
   g_err.clear();
@@ -767,13 +1098,13 @@ int saliency_backward(sp_ctx* c, const float* grad_prior, int32_t T, float* grad
         if (ph.kind == JOB_CONSP_DOT)
           return sp_launch_consp_dot(c->jobs.dev + ph.off, nj, c->d_rsd, ios, c->gs_all, c->ms_tape, fid,
                                      c->dot_part, c->cx, c->stream);
-        return sp_launch(ph.kind, c->jobs.dev + ph.off, nj, c->d_rsd, ios, nullptr, 0, nullptr, c->stream);
+        return sp_launch(ph.kind, c->jobs.dev + ph.off, nj, c->d_rsd, ios, nullptr, 0, nullptr, c->stream, ph.lds);
       });
       if (e != hipSuccess) return fail(SP_EHIP, "recompute launch: %s", hipGetErrorString(e));
     }
   }
   const float* wdev = reinterpret_cast<const float*>(reinterpret_cast<const char*>(c->d_sd) + offsetof(StreamDesc, w));
-  hipError_t e = timed(c, JOB_LOSS + 1, [&] {
+  hipError_t e = timed(c, JOB_BWD_FINAL, [&] {
     return sp_launch_bwd_final(T, c->n_lvl0_tiles, c->h_sd.n_cmax_tiles, c->gk_part, c->dot_part, c->cx,
                                c->ms_tape, c->K_tape, c->P_tape, c->p.q, c->p.r, wdev, c->p.flat_tol,
                                c->gK_scratch, grad_w, grad_q, grad_r, c->stream);
@@ -837,44 +1168,23 @@ int sp_set_state(sp_ctx* c, const void* buf, size_t bytes) {
 int sp_profile_enable(sp_ctx* c, int32_t enable) {
   g_err.clear();
   if (!c) return fail(SP_EINVAL, "ctx is NULL");
-  if (enable && c->ev.empty()) {
-    const size_t pairs = 65536;
-    c->ev.resize(2 * pairs, nullptr);
-    for (size_t i = 0; i < c->ev.size(); ++i) HIPCHK(hipEventCreate(&c->ev[i]));
-    c->ev_kind.assign(pairs, 0);
-  }
-  c->prof = enable != 0;
-  c->ev_used = 0;
-  return SP_OK;
+  return c->prof.enable(enable != 0);
 }
+
+static_assert(JOB_NKINDS == SP_NKINDS, "kernel kinds and the public SP_NKINDS disagree");
 
 int sp_profile_read(sp_ctx* c, int32_t n, float* total_ms, int32_t* launches) {
   g_err.clear();
-  if (!c || !total_ms || !launches) return fail(SP_EINVAL, "NULL argument");
-  if (n < SP_NKINDS) return fail(SP_EINVAL, "arrays must hold %d kinds", SP_NKINDS);
-  for (int k = 0; k < n; ++k) {
-    total_ms[k] = 0.f;
-    launches[k] = 0;
-  }
-  HIPCHK(hipStreamSynchronize(c->stream));
-  for (size_t i = 0; i < c->ev_used; ++i) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
-    const int k = c->ev_kind[i];
-    if (k >= 0 && k < n) {
-      total_ms[k] += ms;
-      launches[k] += 1;
-    }
-  }
-  c->ev_used = 0;
-  return SP_OK;
+  if (!c) return fail(SP_EINVAL, "ctx is NULL");
+  return c->prof.read(c->stream, n, total_ms, launches);
 }
 
 const char* sp_kernel_name(int32_t k) {
-  static const char* names[SP_NKINDS] = {"k_rgb", "k_feat", "k_down", "k_gabor", "k_csstats", "k_csapply",
+  // launch kinds: a pyramid launch is timed under the kind of its phase (k_pyr small
+  // for DOWN/GABOR stages, k_pyr tail for the final stage with tail jobs)
+  static const char* names[SP_NKINDS] = {"k_rgb", "k_feat", "k_pyr", "k_pyr", "k_csstats", "k_csapply",
                                          "k_consp", "k_smax", "k_kalman", "k_mrf", "k_bwd_nu", "k_bwd_gs",
-                                         "k_consp_dot", "k_loss"};
-  if (k == SP_NKINDS) return "k_bwd_final";
+                                         "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_bwd_final"};
   return (k >= 0 && k < SP_NKINDS) ? names[k] : "";
 }
 
@@ -899,15 +1209,85 @@ struct sp_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   long long steps = 0;
+  Profiler prof;
+  bool mrf = false;
+  std::vector<Tune> tune;   // per stream
+  bool xcd = false;
 };
 
 namespace {
+
+// (Re)builds the batch's phase program: one launch per phase over every stream.  Drops
+// the captured graph, which is captured again on the next step.
+int batch_build_tables(sp_batch* b) {
+  const int n = b->n;
+  if (b->exec) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->jobs.host.clear();
+  b->phases.clear();
+  std::vector<Job> rgb, feat, fin, css, csa, cons, kal;
+  std::vector<std::vector<Job>> mids;
+  bool any_big = false;
+  for (int i = 0; i < n; ++i) {
+    const Geo& g = b->geo[i];
+    rgb_jobs(rgb, i, b->h_sd[i], g);
+    add_tiles(feat, i, 1, g.Hl[1], g.Wl[1], JOB_FEAT);
+    std::vector<std::vector<Job>> mid;
+    std::vector<Job> f;
+    bool big = false;
+    pyramid_stages(g, i, 1, mid, f, &big);
+    any_big |= big;
+    if (mids.size() < mid.size()) mids.resize(mid.size());
+    for (size_t j = 0; j < mid.size(); ++j) mids[j].insert(mids[j].end(), mid[j].begin(), mid[j].end());
+    fin.insert(fin.end(), f.begin(), f.end());
+    for (int c = 0; c <= g.top; ++c) {
+      bool has = false;
+      for (int k = 0; k < g.n_pairs; ++k) has |= (g.pc[k] == c);
+      if (has) add_tiles(css, i, c, g.Hl[c], g.Wl[c]);
+    }
+    for (int k = 0; k < SP_NCH; ++k) add_tiles(csa, i, k, g.Hl[g.c_max], g.Wl[g.c_max]);
+    add_tiles(cons, i, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
+    add_tiles_wh(kal, i, 0, g.H, g.W, 16, b->tune[i].kalman_tw, JOB_KALMAN);
+  }
+  // tail jobs first in the final pyramid launch: they are the longest workgroups
+  std::stable_sort(fin.begin(), fin.end(), [](const Job& a, const Job& c) {
+    return (a.kind == JOB_TAIL || a.kind == JOB_TAILGAB) > (c.kind == JOB_TAIL || c.kind == JOB_TAILGAB);
+  });
+  auto order = [&](std::vector<Job> v) {
+    if (b->xcd) xcd_order(v);
+    return v;
+  };
+  b->phases.push_back(b->jobs.add(JOB_RGB, b->mrf ? 1 : 0, order(rgb), n));
+  b->phases.push_back(b->jobs.add(JOB_FEAT, 0, order(feat), n));
+  for (auto& d : mids)
+    if (!d.empty()) b->phases.push_back(b->jobs.add(JOB_DOWN, 0, order(d), n));
+  if (!fin.empty()) b->phases.push_back(b->jobs.add(any_big ? JOB_TAIL : JOB_DOWN, 0, fin, n));
+  b->phases.push_back(b->jobs.add(JOB_CSSTATS, 0, order(css), n));
+  b->phases.push_back(b->jobs.add(JOB_CSAPPLY, 0, order(csa), n));
+  {
+    size_t lds = 0;
+    for (const Geo& g : b->geo) lds = std::max(lds, csapply_lds_bytes(g));
+    b->phases.back().lds = lds;
+  }
+  b->phases.push_back(b->jobs.add(JOB_CONSP, 0, order(cons), n));
+  b->phases.push_back(b->jobs.add(JOB_KALMAN, 0, order(kal), n));
+  return upload_jobs(b->jobs, b->stream);
+}
 
 int batch_enqueue(sp_batch* b, hipStream_t st) {
   hipError_t e = sp_launch_batch_begin(b->n, b->d_st, b->d_in, b->d_io, b->p.q, b->p.r, st);
   if (e != hipSuccess) return fail(SP_EHIP, "batch begin launch: %s", hipGetErrorString(e));
   for (const Phase& ph : b->phases) {
-    e = sp_launch(ph.kind, b->jobs.dev + ph.off, ph.n, b->d_sd, b->d_io, nullptr, ph.flag, nullptr, st);
+    e = b->prof.timed(st, ph.kind, [&] {
+      return sp_launch(ph.kind, b->jobs.dev + ph.off, ph.n, b->d_sd, b->d_io, nullptr, ph.flag, nullptr, st, ph.lds);
+    });
     if (e != hipSuccess) return fail(SP_EHIP, "batch phase launch (kind %d): %s", ph.kind, hipGetErrorString(e));
   }
   return SP_OK;
@@ -919,6 +1299,7 @@ void batch_free(sp_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  b->prof.destroy();
   if (b->arena) (void)hipFree(b->arena);
   if (b->jobs.dev) (void)hipFree(b->jobs.dev);
   delete b;
@@ -928,8 +1309,8 @@ void batch_free(sp_batch* b) {
 
 extern "C" {
 
-int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32_t* W, void* hip_stream,
-                    sp_batch** out) {
+int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32_t* W, int32_t flags,
+                    void* hip_stream, sp_batch** out) {
   g_err.clear();
   if (!out) return fail(SP_EINVAL, "out is NULL");
   *out = nullptr;
@@ -938,6 +1319,8 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
   int rc = validate_params(p);
   if (rc) return rc;
   if (p->record_tape != 0) return fail(SP_EINVAL, "the batched step keeps no tape (record_tape must be 0)");
+  if (flags & ~SP_BATCH_MRF) return fail(SP_EINVAL, "unknown batch flags 0x%x", flags);
+  const bool mrf = (flags & SP_BATCH_MRF) != 0;
   sp_batch* b = new (std::nothrow) sp_batch();
   if (!b) return fail(SP_ENOMEM, "host allocation failed");
   b->p = *p;
@@ -965,6 +1348,11 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
       s.pi[0] = bm.take<float>((size_t)g.H * g.W);
       s.pi[1] = bm.take<float>((size_t)g.H * g.W);
       s.S = bm.take<float>((size_t)g.Hl[g.c_max] * g.Wl[g.c_max]);
+      if (mrf) {
+        s.unary = bm.take<float>((size_t)2 * g.H * g.W);
+        s.pairwise = bm.take<float>((size_t)4 * g.H * g.W);
+        s.beta = bm.take<float>(1);
+      }
     }
     b->d_sd = bm.take<StreamDesc>(n);
     b->d_io = bm.take<StepIO>(n);
@@ -979,44 +1367,26 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
       }
     }
   }
-  // phase program: one launch per phase over every stream
-  int maxtop = 0;
-  for (const Geo& g : b->geo) maxtop = std::max(maxtop, g.top);
-  std::vector<Job> rgb, feat, gab, css, csa, cons, kal;
-  std::vector<std::vector<Job>> down(std::max(0, maxtop - 1));
-  for (int i = 0; i < n; ++i) {
-    const Geo& g = b->geo[i];
-    rgb_jobs(rgb, i, b->h_sd[i]);
-    add_tiles(feat, i, 1, g.Hl[1], g.Wl[1]);
-    for (int l = 1; l < g.top; ++l) add_tiles(down[l - 1], i, l, g.Hl[l + 1], g.Wl[l + 1]);
-    for (int l = 1; l <= g.top; ++l)
-      if (g.used & (1u << l)) add_tiles(gab, i, l, g.Hl[l], g.Wl[l]);
-    for (int c = 0; c <= g.top; ++c) {
-      bool has = false;
-      for (int k = 0; k < g.n_pairs; ++k) has |= (g.pc[k] == c);
-      if (has) add_tiles(css, i, c, g.Hl[c], g.Wl[c]);
+  b->mrf = mrf;
+  b->tune.resize(n);
+  for (int i = 0; i < n; ++i) b->tune[i] = cached_tune(H[i], W[i]);
+  b->xcd = n > 0 ? b->tune[0].xcd : false;
+  {
+    size_t lds = 0;
+    for (const Geo& g : b->geo) lds = std::max(lds, csapply_lds_bytes(g));
+    if (sp_csapply_reserve_lds(lds) != hipSuccess) {
+      batch_free(b);
+      return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", lds);
     }
-    for (int k = 0; k < SP_NCH; ++k) add_tiles(csa, i, k, g.Hl[g.c_max], g.Wl[g.c_max]);
-    add_tiles(cons, i, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
-    add_tiles(kal, i, 0, g.H, g.W);
   }
-  b->phases.push_back(b->jobs.add(JOB_RGB, 0, rgb, n));
-  b->phases.push_back(b->jobs.add(JOB_FEAT, 0, feat, n));
-  for (auto& d : down)
-    if (!d.empty()) b->phases.push_back(b->jobs.add(JOB_DOWN, 0, d, n));
-  b->phases.push_back(b->jobs.add(JOB_GABOR, 0, gab, n));
-  b->phases.push_back(b->jobs.add(JOB_CSSTATS, 0, css, n));
-  b->phases.push_back(b->jobs.add(JOB_CSAPPLY, 0, csa, n));
-  b->phases.push_back(b->jobs.add(JOB_CONSP, 0, cons, n));
-  b->phases.push_back(b->jobs.add(JOB_KALMAN, 0, kal, n));
-  hipError_t e = hipMalloc(&b->jobs.dev, sizeof(Job) * b->jobs.host.size());
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
+  rc = batch_build_tables(b);
+  if (rc) {
+    std::string msg = g_err;
     batch_free(b);
-    return fail(SP_ENOMEM, "hipMalloc of the job tables failed");
+    g_err = msg;
+    return rc;
   }
-  e = hipMemcpy(b->jobs.dev, b->jobs.host.data(), sizeof(Job) * b->jobs.host.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_sd, b->h_sd.data(), sizeof(StreamDesc) * n, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(b->d_sd, b->h_sd.data(), sizeof(StreamDesc) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_st, b->h_st.data(), sizeof(BatchState) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -1030,11 +1400,26 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
 int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* prior_ptrs) {
   g_err.clear();
   if (!b || !rgb_ptrs) return fail(SP_EINVAL, "batch and rgb_ptrs must not be NULL");
+  if (b->prof.on) {
+    // measurement: the same phases, launched one by one with events around each
+    HIPCHK(hipMemcpyAsync(b->d_in, rgb_ptrs, sizeof(void*) * b->n, hipMemcpyDeviceToDevice, b->stream));
+    int rc = batch_enqueue(b, b->stream);
+    if (rc) return rc;
+    b->steps += 1;
+    if (prior_ptrs) {
+      hipError_t e = sp_launch_batch_copy_out(b->n, b->d_st, b->d_sd, prior_ptrs, b->stream);
+      if (e != hipSuccess) return fail(SP_EHIP, "copy-out launch: %s", hipGetErrorString(e));
+    }
+    return SP_OK;
+  }
   if (!b->exec) {
     // capture the whole step once on the private stream
     HIPCHK(hipStreamSynchronize(b->stream));
     HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    const bool was = b->prof.on;
+    b->prof.on = false;
     int rc = batch_enqueue(b, b->cap_stream);
+    b->prof.on = was;
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
     if (rc) {
@@ -1064,12 +1449,121 @@ int sp_batch_prior(sp_batch* b, int32_t i, const float** prior) {
   return SP_OK;
 }
 
+int sp_batch_outputs(sp_batch* b, int32_t i, const float** S, const float** unary, const float** pairwise,
+                     const float** beta) {
+  g_err.clear();
+  if (!b) return fail(SP_EINVAL, "batch is NULL");
+  if (i < 0 || i >= b->n) return fail(SP_EINVAL, "stream index %d out of range", i);
+  if (S) *S = b->h_st[i].S;
+  if (unary) *unary = b->h_st[i].unary;
+  if (pairwise) *pairwise = b->h_st[i].pairwise;
+  if (beta) *beta = b->h_st[i].beta;
+  return SP_OK;
+}
+
 int sp_batch_reset(sp_batch* b) {
   g_err.clear();
   if (!b) return fail(SP_EINVAL, "batch is NULL");
   hipError_t e = sp_launch_batch_reset(b->n, b->d_st, b->stream);
   if (e != hipSuccess) return fail(SP_EHIP, "reset launch: %s", hipGetErrorString(e));
   b->steps = 0;
+  return SP_OK;
+}
+
+int sp_batch_profile_enable(sp_batch* b, int32_t enable) {
+  g_err.clear();
+  if (!b) return fail(SP_EINVAL, "batch is NULL");
+  return b->prof.enable(enable != 0);
+}
+
+int sp_batch_profile_read(sp_batch* b, int32_t n, float* total_ms, int32_t* launches) {
+  g_err.clear();
+  if (!b) return fail(SP_EINVAL, "batch is NULL");
+  return b->prof.read(b->stream, n, total_ms, launches);
+}
+
+int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps, char* report, size_t report_len) {
+  g_err.clear();
+  if (!b || !rgb_ptrs) return fail(SP_EINVAL, "batch and rgb_ptrs must not be NULL");
+  if (steps < 1 || steps > 1000) return fail(SP_EINVAL, "steps must be 1..1000");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  HIPCHK(hipMemcpyAsync(b->d_in, rgb_ptrs, sizeof(void*) * b->n, hipMemcpyDeviceToDevice, b->stream));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const bool was = b->prof.on;
+  b->prof.on = false;
+  std::string rep;
+  int rc = SP_OK;
+  auto time_it = [&](double* ms) -> int {
+    int r = batch_build_tables(b);
+    if (r) return r;
+    r = batch_enqueue(b, b->stream);   // warm-up
+    if (r) return r;
+    HIPCHK(hipEventRecord(e0, b->stream));
+    for (int i = 0; i < steps && !r; ++i) r = batch_enqueue(b, b->stream);
+    if (r) return r;
+    HIPCHK(hipEventRecord(e1, b->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, e0, e1));
+    *ms = f / steps;
+    return SP_OK;
+  };
+  char line[160];
+  double best = 1e30, t = 0;
+  bool best_x = b->xcd;
+  for (int x = 0; x < 2 && !rc; ++x) {
+    b->xcd = x != 0;
+    rc = time_it(&t);
+    snprintf(line, sizeof line, "xcd_order=%d: %.4f ms/step\n", x, t);
+    rep += line;
+    if (!rc && t < best) {
+      best = t;
+      best_x = b->xcd;
+    }
+  }
+  b->xcd = best_x;
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  for (int i = 0; i < b->n; ++i) groups[{b->geo[i].H, b->geo[i].W}].push_back(i);
+  for (auto& kv : groups) {
+    if (rc) break;
+    int best_tw = b->tune[kv.second[0]].kalman_tw;
+    double bt = 1e30;
+    for (int tw : {16, 32, 64}) {
+      for (int i : kv.second) b->tune[i].kalman_tw = tw;
+      rc = time_it(&t);
+      if (rc) break;
+      snprintf(line, sizeof line, "%dx%d kalman tile 16x%d: %.4f ms/step\n", kv.first.first, kv.first.second, tw, t);
+      rep += line;
+      if (t < bt) {
+        bt = t;
+        best_tw = tw;
+      }
+    }
+    for (int i : kv.second) b->tune[i].kalman_tw = best_tw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->prof.on = was;
+  if (rc) return rc;
+  rc = batch_build_tables(b);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    tune_cache_xcd() = b->xcd;
+    for (int i = 0; i < b->n; ++i) tune_cache_tw()[{b->geo[i].H, b->geo[i].W}] = b->tune[i].kalman_tw;
+  }
+  snprintf(line, sizeof line, "chosen: xcd_order=%d\n", (int)b->xcd);
+  rep += line;
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  hipError_t e = sp_launch_batch_reset(b->n, b->d_st, b->stream);
+  if (e != hipSuccess) return fail(SP_EHIP, "reset launch: %s", hipGetErrorString(e));
+  b->steps = 0;
+  HIPCHK(hipStreamSynchronize(b->stream));
   return SP_OK;
 }
 

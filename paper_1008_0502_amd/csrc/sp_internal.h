@@ -5,6 +5,7 @@
 // one stream (the plain per-frame calls) or many streams of uneven size (the
 // batched step) with the same code.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #define SP_MAXL 13          // pyramid levels 0..12
@@ -32,7 +33,17 @@ enum JobKind : int32_t {
   JOB_BWD_GS,       // upsample transpose at c_max
   JOB_CONSP_DOT,    // recomputed conspicuity dotted with the saliency adjoint
   JOB_LOSS,         // masked MSE partials
+  JOB_TAIL,         // one channel: every level above a small source level, in LDS
+  JOB_TAILGAB,      // Gabor maps of one level above the tail source (intensity chain in LDS)
+  JOB_BWD_FINAL,    // reduction of the adjoint partials (timing id only)
+  JOB_NKINDS
 };
+
+// Capacities of the LDS buffers of the tail job (floats).
+#define SP_TAIL_SRC 8192   // source level
+#define SP_TAIL_ALT 4096   // every other level above it
+#define SP_TAIL_HB 4096    // horizontal intermediate
+#define SP_TAIL_V 8192     // 4 vertical Gabor passes of one level
 
 struct Job {
   int32_t stream;   // index into the stream table
@@ -40,7 +51,7 @@ struct Job {
   int32_t y0, x0;   // tile origin (in the map the kind works on)
   int32_t th, tw;   // tile size
   int32_t tid;      // index of this tile among the tiles of its map (partials slot)
-  int32_t pad;
+  int32_t kind;     // JobKind (kernels that serve several kinds switch on it)
 };
 
 // Static description of one stream: geometry, scratch pointers, parameters.
@@ -52,6 +63,7 @@ struct StreamDesc {
   int32_t cs_off[SP_MAXP];       // offset (in partial triples) of pair p: [8][ntiles(c_p)]
   int32_t n_cmax_tiles;          // tiles of the c_max grid (fbar / consp / smax partials)
   int32_t gr;                    // Gabor radius
+  uint32_t used;                 // bit l: level l is a centre or a surround level
   float* base[SP_MAXL];          // [4][H_l][W_l] per level (levels 1..top)
   float* gab[SP_MAXL];           // [4][H_l][W_l] per used level
   uint32_t* rgb_max_part;        // [n_rgb]
@@ -111,6 +123,46 @@ struct BatchState {
   double P;                  // Kalman variance after the last step
   float* pi[2];              // prior ping-pong
   float* S;                  // saliency map scratch [Hc][Wc]
+  float* unary;              // [2][H][W] or null
+  float* pairwise;           // [4][H][W] or null
+  float* beta;               // [1] or null
   const uint8_t* last_rgb;   // frame of the last step (next step's previous frame)
   int32_t cur, pad;
 };
+
+// LDS layout (in floats) of the across-scale-sum job: centre values of the c_max tile
+// and of the regions one and two levels finer, the reduction temporary, and one
+// surround footprint per pair.  Shared by the kernel and the host (which sizes the
+// dynamic LDS of the launch with it).
+#define SP_CA_T 16
+struct CaLayout {
+  int x0, x1, x2, tm, foot0, total;   // foot0: first footprint; pair p follows pairs < p
+};
+
+// Footprint capacity (floats) of pair (c, s) for the region of centre level c.
+__host__ __device__ inline int csapply_foot_cap(int r, int d) {
+  const int n1 = 2 * SP_CA_T + 3, n2 = 2 * n1 + 3;
+  const int n = (r == 0) ? SP_CA_T : ((r == 1) ? n1 : n2);
+  const int e = ((n - 1) >> d) + 3;
+  return e * e;
+}
+
+__host__ __device__ inline CaLayout csapply_layout(const int32_t* pc, const int32_t* ps, int n_pairs, int c_max) {
+  bool has[3] = {false, false, false};
+  for (int p = 0; p < n_pairs; ++p) has[c_max - pc[p]] = true;
+  const int n1 = 2 * SP_CA_T + 3, n2 = 2 * n1 + 3;
+  CaLayout L;
+  int o = 0;
+  L.x0 = o;
+  if (has[0]) o += SP_CA_T * SP_CA_T;
+  L.x1 = o;
+  if (has[1] || has[2]) o += n1 * n1;
+  L.x2 = o;
+  if (has[2]) o += n2 * n2;
+  L.tm = o;
+  o += has[2] ? n2 * n1 : ((has[1]) ? n1 * SP_CA_T : 0);
+  L.foot0 = o;
+  for (int p = 0; p < n_pairs; ++p) o += csapply_foot_cap(c_max - pc[p], ps[p] - pc[p]);
+  L.total = o;
+  return L;
+}

@@ -4,7 +4,8 @@
 #include "sp_internal.h"
 
 hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios,
-                     const StepIO* io0, int flag, const float* aux, hipStream_t st);
+                     const StepIO* io0, int flag, const float* aux, hipStream_t st, size_t lds = 0);
+hipError_t sp_csapply_reserve_lds(size_t bytes);
 hipError_t sp_launch_bwd(int kind, const Job* jobs, int n, const StreamDesc* sds, const BwdIO* bios,
                          const BwdIO* b0, hipStream_t st);
 hipError_t sp_launch_consp_dot(const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios,

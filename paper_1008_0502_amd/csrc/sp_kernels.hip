@@ -70,6 +70,31 @@ __device__ __forceinline__ uint32_t wave_max_u(uint32_t v) {
   return (uint32_t)max(max(r0, r1), max(r2, r3));
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL));
+  const int hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int LANE>
+__device__ __forceinline__ double readlane_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), LANE);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), LANE);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Wave-uniform FP64 sum (every lane active).
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (readlane_d<0>(v) + readlane_d<16>(v)) + (readlane_d<32>(v) + readlane_d<48>(v));
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
@@ -141,21 +166,12 @@ __device__ __forceinline__ float bilinear(const float* X, int Ws, const Tap& ty,
   return (1.f - ty.w) * top + ty.w * bot;
 }
 
-// N(.) parameters of one map from its partial triples (min, max, sum of block maxima).
+// N(.) parameters of one map from its partial triples (min, max, sum of block maxima):
+// N(X) = (X - mn) / (mx - mn) * (1 - mbar)^2 with mbar the mean block maximum of the
+// rescaled map after removing one instance of the global maximum.
 struct NParams { float mn, inv, scale; int flat; };
 
-__device__ NParams nparams_from_parts(const float* parts, int n, int nb, float flat_tol,
-                                      float* sh4, double* sh256) {
-  float mn = INFINITY, mx = -INFINITY;
-  double sb = 0.0;
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-    mn = fminf(mn, parts[3 * i]);
-    mx = fmaxf(mx, parts[3 * i + 1]);
-    sb += (double)parts[3 * i + 2];
-  }
-  mn = block_reduce<OpMin>(mn, sh4);
-  mx = block_reduce<OpMax>(mx, sh4);
-  sb = block_sum_d(sb, sh256);
+__device__ NParams make_nparams(float mn, float mx, double sb, int nb, float flat_tol) {
   NParams p;
   p.mn = mn;
   p.flat = (mx - mn <= flat_tol) ? 1 : 0;
@@ -169,6 +185,21 @@ __device__ NParams nparams_from_parts(const float* parts, int n, int nb, float f
     p.scale = (float)((1.0 - mbar) * (1.0 - mbar));
   }
   return p;
+}
+
+// One wavefront reduces the partials of one map (no workgroup barrier).
+__device__ NParams nparams_wave(const float* parts, int n, int nb, float flat_tol) {
+  float mn = INFINITY, mx = -INFINITY;
+  double sb = 0.0;
+  for (int i = lane_id(); i < n; i += 64) {
+    mn = fminf(mn, parts[3 * i]);
+    mx = fmaxf(mx, parts[3 * i + 1]);
+    sb += (double)parts[3 * i + 2];
+  }
+  mn = wave_reduce<OpMin>(mn);
+  mx = wave_reduce<OpMax>(mx);
+  sb = wave_sum_d(sb);
+  return make_nparams(mn, mx, sb, nb, flat_tol);
 }
 
 __device__ __forceinline__ float napply(const NParams& p, float v) {
@@ -206,48 +237,70 @@ __device__ __forceinline__ bool on_border(int y, int x, int H, int W, int b) {
 #define IOF(field) (ios ? ios[J.stream].field : io0.field)
 
 // ---------------------------------------------------------------- colour statistics
-// Largest R+G+B over a band of rows; optionally the sum of squared colour
-// differences over the 8-neighbour pairs whose first pixel lies in the band.
+// Largest R+G+B over a contiguous run of pixels; optionally the sum of squared colour
+// differences over the 8-neighbour pairs (E, S, SE, SW) whose first pixel is in the run.
+// Four pixels (12 bytes) per thread and iteration, loaded as three dwords when aligned.
 __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
                                                   const StepIO* __restrict__ ios, StepIO io0, int want_d2) {
   __shared__ unsigned long long sh[SP_BLOCK];
-  __shared__ float sh4[4];
+  __shared__ uint32_t shm[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const uint8_t* __restrict__ rgb = IOF(rgb);
   const int W = sd.W, H = sd.H;
+  const int p0 = J.y0, np = J.th;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(rgb) & 3) == 0) && ((p0 & 3) == 0);
   uint32_t mx = 0;
   unsigned long long d2 = 0;
-  const int n = J.th * W;
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-    const int y = J.y0 + i / W, x = i % W;
-    const uint8_t* p = rgb + ((size_t)y * W + x) * 3;
-    const int r = p[0], g = p[1], b = p[2];
-    mx = max(mx, (uint32_t)(r + g + b));
-    if (want_d2) {
-      if (x + 1 < W) {
-        const int dr = r - p[3], dg = g - p[4], db = b - p[5];
-        d2 += (unsigned)(dr * dr + dg * dg + db * db);
+  for (int g = threadIdx.x; 4 * g < np; g += SP_BLOCK) {
+    const int p = p0 + 4 * g;
+    const int cnt = min(4, np - 4 * g);
+    uint32_t b[12];
+    if (aligned && cnt == 4) {
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(rgb + (size_t)3 * p);
+      const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        b[i] = (w0 >> (8 * i)) & 0xff;
+        b[4 + i] = (w1 >> (8 * i)) & 0xff;
+        b[8 + i] = (w2 >> (8 * i)) & 0xff;
       }
-      if (y + 1 < H) {
-        const uint8_t* q = p + (size_t)3 * W;
-        int dr = r - q[0], dg = g - q[1], db = b - q[2];
-        d2 += (unsigned)(dr * dr + dg * dg + db * db);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) b[i] = (i < 3 * cnt) ? rgb[(size_t)3 * p + i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < cnt) mx = max(mx, b[3 * j] + b[3 * j + 1] + b[3 * j + 2]);
+    if (want_d2) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= cnt) break;
+        const int q = p + j, y = q / W, x = q - y * W;
+        const int r = (int)b[3 * j], gg = (int)b[3 * j + 1], bb = (int)b[3 * j + 2];
         if (x + 1 < W) {
-          dr = r - q[3]; dg = g - q[4]; db = b - q[5];
+          const uint8_t* e = rgb + (size_t)3 * (q + 1);
+          const int dr = r - e[0], dg = gg - e[1], db = bb - e[2];
           d2 += (unsigned)(dr * dr + dg * dg + db * db);
         }
-        if (x > 0) {
-          dr = r - q[-3]; dg = g - q[-2]; db = b - q[-1];
+        if (y + 1 < H) {
+          const uint8_t* e = rgb + (size_t)3 * (q + W);
+          int dr = r - e[0], dg = gg - e[1], db = bb - e[2];
           d2 += (unsigned)(dr * dr + dg * dg + db * db);
+          if (x + 1 < W) {
+            dr = r - e[3]; dg = gg - e[4]; db = bb - e[5];
+            d2 += (unsigned)(dr * dr + dg * dg + db * db);
+          }
+          if (x > 0) {
+            dr = r - e[-3]; dg = gg - e[-2]; db = bb - e[-1];
+            d2 += (unsigned)(dr * dr + dg * dg + db * db);
+          }
         }
       }
     }
   }
-  (void)sh4;
   mx = wave_max_u(mx);
-  __shared__ uint32_t shm[4];
   if (lane_id() == 0) shm[wave_id()] = mx;
   const unsigned long long tot = want_d2 ? block_sum_u64(d2, sh) : 0ull;
   __syncthreads();
@@ -268,6 +321,42 @@ __device__ __forceinline__ void down_region(float (*F)[RH][RW], float (*Hb)[RH][
   }
 }
 
+__device__ __forceinline__ float beta_from_parts(const StreamDesc& sd, unsigned long long* sh) {
+  unsigned long long s = 0;
+  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) s += sd.rgb_d2_part[i];
+  s = block_sum_u64(s, sh);
+  const int H = sd.H, W = sd.W;
+  const unsigned long long cnt = (unsigned long long)H * (W - 1) + (unsigned long long)(H - 1) * W +
+                                 2ull * (unsigned long long)(H - 1) * (W - 1);
+  const double mean = cnt ? (double)s / (double)cnt : 0.0;
+  return (mean > 0.0) ? (float)(1.0 / (2.0 * mean)) : 0.f;
+}
+
+// Contrast-sensitive capacities of pixel (y, x) towards its E, S, SE, SW neighbours.
+__device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, int y, int x, float beta, float lam,
+                                            float potts, float* pairw, size_t plane) {
+  const size_t o = (size_t)y * W + x;
+  const uint8_t* p = rgb + o * 3;
+  const int r = p[0], g = p[1], b = p[2];
+  const int dys[4] = {0, 1, 1, 1}, dxs[4] = {1, 0, 1, -1};
+  const float dist[4] = {1.f, 1.f, 1.41421356237f, 1.41421356237f};
+#pragma unroll
+  for (int dd = 0; dd < 4; ++dd) {
+    const int y2 = y + dys[dd], x2 = x + dxs[dd];
+    float wv = 0.f;
+    if (y2 < H && x2 >= 0 && x2 < W) {
+      const uint8_t* q = rgb + ((size_t)y2 * W + x2) * 3;
+      const int dr = r - q[0], dg = g - q[1], db = b - q[2];
+      const float d2 = (float)(dr * dr + dg * dg + db * db);
+      wv = potts + lam * expf(-beta * d2) / dist[dd];
+    }
+    pairw[dd * plane + o] = wv;
+  }
+}
+
+// Level-0 features of the region a level-1 tile needs, then one blur + decimation.
+// With io.pairwise set it also writes the pairwise capacities of the tile's level-0
+// pixels (rows 2*y0 .. 2*(y0+th)-1).
 template <int TH, int TW>
 __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
                                                    const StreamDesc* __restrict__ sds,
@@ -276,11 +365,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
   __shared__ float F[4][RH][RW];
   __shared__ float Hb[4][RH][TW];
   __shared__ uint32_t shm[4];
+  __shared__ unsigned long long sh[SP_BLOCK];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const uint8_t* __restrict__ rgb = IOF(rgb);
   const uint8_t* __restrict__ prev = IOF(rgb_prev);
   float* ckpt = IOF(ckpt);
+  float* pairw = IOF(pairwise);
   uint32_t smax = 0;
   for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) smax = max(smax, sd.rgb_max_part[i]);
   smax = wave_max_u(smax);
@@ -335,91 +426,115 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
       }
     }
   }
+  if (pairw) {
+    const float beta = beta_from_parts(sd, sh);
+    const int ylo = 2 * J.y0, yhi = min(H, 2 * (J.y0 + J.th));
+    const int xlo = 2 * J.x0, xhi = min(W, 2 * (J.x0 + J.tw));
+    const int cw = xhi - xlo, n = (yhi - ylo) * cw;
+    for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
+      const int yy = i / cw, xx = i - yy * cw;
+      pairwise_at(rgb, H, W, ylo + yy, xlo + xx, beta, sd.lam, sd.potts, pairw, (size_t)H * W);
+    }
+    if (J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) IOF(beta_out)[0] = beta;
+  }
 }
 
-template <int TH, int TW>
-__global__ __launch_bounds__(SP_BLOCK) void k_down(const Job* __restrict__ jobs,
-                                                   const StreamDesc* __restrict__ sds,
-                                                   const StepIO* __restrict__ ios, StepIO io0) {
-  constexpr int RH = 2 * TH + 3, RW = 2 * TW + 3;
-  __shared__ float F[4][RH][RW];
-  __shared__ float Hb[4][RH][TW];
-  const Job J = jobs[blockIdx.x];
-  const StreamDesc& sd = sds[J.stream];
-  float* ckpt = IOF(ckpt);
+// ---- jobs of the pyramid kernel (one of DOWN, GABOR, TAIL per workgroup)
+constexpr int DT = 16, DR = 2 * DT + 3;                         // down tile and its source region
+constexpr int DOWN_LDS = 4 * DR * DR + 4 * DR * DT;             // floats
+constexpr int GT = 16, GRM = GT + 2 * SP_MAXR;                  // Gabor tile and its region
+constexpr int GAB_LDS = GRM * (GRM + 1) + 4 * GT * (GRM + 1) + 4 * (2 * SP_MAXR + 1);
+constexpr int TAIL_LDS = SP_TAIL_SRC + SP_TAIL_ALT + SP_TAIL_HB + SP_TAIL_V + 4 * (2 * SP_MAXR + 1);
+static_assert(DOWN_LDS >= GAB_LDS, "LDS of the small pyramid kernel");
+
+__device__ __forceinline__ float* level_dst(const StreamDesc& sd, float* ckpt, int l) {
+  return (l == sd.c_min && ckpt) ? ckpt : sd.base[l];
+}
+
+// level a -> a+1 of the 4 base channels for one 16x16 tile of level a+1
+__device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float* smem) {
+  float* F = smem;                 // [4][DR][DR]
+  float* Hb = smem + 4 * DR * DR;  // [4][DR][DT]
   const int l = J.a;
   const int Hs = sd.Hl[l], Ws = sd.Wl[l];
   const float* src = base_ptr(sd, ckpt, l);
   const size_t splane = (size_t)Hs * Ws;
   const int Y0 = 2 * J.y0 - 2, X0 = 2 * J.x0 - 2;
-  for (int i = threadIdx.x; i < RH * RW; i += SP_BLOCK) {
-    const int ry = i / RW, rx = i - ry * RW;
-    const int y = clampi(Y0 + ry, 0, Hs - 1), x = clampi(X0 + rx, 0, Ws - 1);
-    const size_t o = (size_t)y * Ws + x;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) F[c][ry][rx] = src[c * splane + o];
+  for (int i = threadIdx.x; i < DR * DR; i += SP_BLOCK) {
+    const int ry = i / DR, rx = i - ry * DR;
+    const size_t o = (size_t)clampi(Y0 + ry, 0, Hs - 1) * Ws + clampi(X0 + rx, 0, Ws - 1);
+    const float v0 = src[o], v1 = src[splane + o], v2 = src[2 * splane + o], v3 = src[3 * splane + o];
+    F[i] = v0;
+    F[DR * DR + i] = v1;
+    F[2 * DR * DR + i] = v2;
+    F[3 * DR * DR + i] = v3;
   }
   __syncthreads();
-  down_region<TH, TW, RH, RW>(F, Hb, 4);
+  for (int i = threadIdx.x; i < 4 * DR * DT; i += SP_BLOCK) {
+    const int cr = i / DT, j = i - cr * DT;     // cr = c * DR + r
+    const float* row = F + cr * DR + 2 * j;
+    Hb[i] = kB0 * row[0] + kB1 * row[1] + kB2 * row[2] + kB1 * row[3] + kB0 * row[4];
+  }
   __syncthreads();
   const int Hd = sd.Hl[l + 1], Wd = sd.Wl[l + 1];
-  float* dst = (l + 1 == sd.c_min && ckpt) ? ckpt : sd.base[l + 1];
+  float* dst = level_dst(sd, ckpt, l + 1);
   const size_t plane = (size_t)Hd * Wd;
-  for (int i = threadIdx.x; i < TH * TW; i += SP_BLOCK) {
-    const int yy = i / TW, xx = i - yy * TW;
-    const int y = J.y0 + yy, x = J.x0 + xx;
-    if (yy < J.th && xx < J.tw && y < Hd && x < Wd) {
+  const int yy = threadIdx.x / DT, xx = threadIdx.x % DT;
+  const int y = J.y0 + yy, x = J.x0 + xx;
+  if (yy < J.th && xx < J.tw && y < Hd && x < Wd) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float v = kB0 * Hb[c][2 * yy][xx] + kB1 * Hb[c][2 * yy + 1][xx] + kB2 * Hb[c][2 * yy + 2][xx] +
-                        kB1 * Hb[c][2 * yy + 3][xx] + kB0 * Hb[c][2 * yy + 4][xx];
-        dst[c * plane + (size_t)y * Wd + x] = v;
-      }
+    for (int c = 0; c < 4; ++c) {
+      const float* col = Hb + (c * DR + 2 * yy) * DT + xx;
+      const float v = kB0 * col[0] + kB1 * col[DT] + kB2 * col[2 * DT] + kB1 * col[3 * DT] + kB0 * col[4 * DT];
+      dst[c * plane + (size_t)y * Wd + x] = v;
     }
   }
 }
 
-// ---------------------------------------------------------------- Gabor orientation maps
 // 13x13 (radius R) zero-DC even Gabor kernels applied as separable rank-1 terms:
 //   O0 = H[gm] V[g], O90 = H[g] V[gm],
 //   O45 = H[gc] V[gc] - H[gs] V[gs] - c45 H[g] V[g], O135 = same with + H[gs] V[gs].
-__global__ __launch_bounds__(SP_BLOCK) void k_gabor(const Job* __restrict__ jobs,
-                                                    const StreamDesc* __restrict__ sds,
-                                                    const StepIO* __restrict__ ios, StepIO io0) {
-  constexpr int T = 16, RM = T + 2 * SP_MAXR;
-  __shared__ float Ir[RM][RM + 1];
-  __shared__ float V[4][T][RM + 1];
-  __shared__ float taps[4][2 * SP_MAXR + 1];
-  const Job J = jobs[blockIdx.x];
-  const StreamDesc& sd = sds[J.stream];
-  float* ckpt = IOF(ckpt);
-  const int l = J.a, R = sd.gr, n = 2 * R + 1, RR = T + 2 * R;
+__device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt, float* smem) {
+  float* Ir = smem;                            // [GRM][GRM+1]
+  float* V = Ir + GRM * (GRM + 1);             // [4][GT][GRM+1]
+  float* taps = V + 4 * GT * (GRM + 1);        // [4][2*SP_MAXR+1]
+  const int l = J.a, R = sd.gr, n = 2 * R + 1, RR = GT + 2 * R;
   const int Hs = sd.Hl[l], Ws = sd.Wl[l];
   const float* I = base_ptr(sd, ckpt, l);
-  if ((int)threadIdx.x < 4 * n) taps[threadIdx.x / n][threadIdx.x % n] = sd.gf[threadIdx.x / n][threadIdx.x % n];
+  if ((int)threadIdx.x < 4 * n) taps[(threadIdx.x / n) * (2 * SP_MAXR + 1) + threadIdx.x % n] =
+      sd.gf[threadIdx.x / n][threadIdx.x % n];
   for (int i = threadIdx.x; i < RR * RR; i += SP_BLOCK) {
     const int ry = i / RR, rx = i - ry * RR;
     const int y = clampi(J.y0 - R + ry, 0, Hs - 1), x = clampi(J.x0 - R + rx, 0, Ws - 1);
-    Ir[ry][rx] = I[(size_t)y * Ws + x];
+    Ir[ry * (GRM + 1) + rx] = I[(size_t)y * Ws + x];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 4 * T * RR; i += SP_BLOCK) {
-    const int f = i / (T * RR), rem = i - f * T * RR, yy = rem / RR, xr = rem - yy * RR;
+  for (int i = threadIdx.x; i < 4 * GT * RR; i += SP_BLOCK) {
+    const int f = i / (GT * RR), rem = i - f * GT * RR, yy = rem / RR, xr = rem - yy * RR;
+    const float* tp = taps + f * (2 * SP_MAXR + 1);
     float acc = 0.f;
-    for (int v = 0; v < n; ++v) acc += taps[f][v] * Ir[yy + v][xr];
-    V[f][yy][xr] = acc;
+    for (int v = 0; v < n; ++v) acc += tp[v] * Ir[(yy + v) * (GRM + 1) + xr];
+    V[(f * GT + yy) * (GRM + 1) + xr] = acc;
   }
   __syncthreads();
-  const int yy = threadIdx.x / T, xx = threadIdx.x % T;
+  const int yy = threadIdx.x / GT, xx = threadIdx.x % GT;
   const int y = J.y0 + yy, x = J.x0 + xx;
+  const float* t0 = taps;
+  const float* t1 = taps + (2 * SP_MAXR + 1);
+  const float* t2 = taps + 2 * (2 * SP_MAXR + 1);
+  const float* t3 = taps + 3 * (2 * SP_MAXR + 1);
+  const float* V0 = V + (0 * GT + yy) * (GRM + 1) + xx;
+  const float* V1 = V + (1 * GT + yy) * (GRM + 1) + xx;
+  const float* V2 = V + (2 * GT + yy) * (GRM + 1) + xx;
+  const float* V3 = V + (3 * GT + yy) * (GRM + 1) + xx;
   float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
   for (int u = 0; u < n; ++u) {
-    const float vg = V[0][yy][xx + u];
-    A += taps[1][u] * vg;
-    B += taps[0][u] * vg;
-    C += taps[0][u] * V[1][yy][xx + u];
-    D += taps[2][u] * V[2][yy][xx + u];
-    E += taps[3][u] * V[3][yy][xx + u];
+    const float vg = V0[u];
+    A += t1[u] * vg;
+    B += t0[u] * vg;
+    C += t0[u] * V1[u];
+    D += t2[u] * V2[u];
+    E += t3[u] * V3[u];
   }
   if (yy < J.th && xx < J.tw && y < Hs && x < Ws) {
     const size_t plane = (size_t)Hs * Ws, o = (size_t)y * Ws + x;
@@ -431,20 +546,183 @@ __global__ __launch_bounds__(SP_BLOCK) void k_gabor(const Job* __restrict__ jobs
   }
 }
 
+// Gabor maps of a whole (small) level held in LDS.
+__device__ void gabor_lds(const float* I, int h, int w, float* V, const float* taps, int R, float c45, float* out) {
+  const int n = h * w, nt = 2 * R + 1;
+  for (int i = threadIdx.x; i < 4 * n; i += SP_BLOCK) {
+    const int f = i / n, pix = i - f * n, y = pix / w, x = pix - y * w;
+    const float* tp = taps + f * (2 * SP_MAXR + 1);
+    float acc = 0.f;
+    for (int v = 0; v < nt; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
+    V[i] = acc;
+  }
+  __syncthreads();
+  const float* t0 = taps;
+  const float* t1 = taps + (2 * SP_MAXR + 1);
+  const float* t2 = taps + 2 * (2 * SP_MAXR + 1);
+  const float* t3 = taps + 3 * (2 * SP_MAXR + 1);
+  for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK) {
+    const int y = pix / w, x = pix - y * w;
+    float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
+    for (int u = 0; u < nt; ++u) {
+      const int o = y * w + clampi(x + u - R, 0, w - 1);
+      const float vg = V[o];
+      A += t1[u] * vg;
+      B += t0[u] * vg;
+      C += t0[u] * V[n + o];
+      D += t2[u] * V[2 * n + o];
+      E += t3[u] * V[3 * n + o];
+    }
+    out[pix] = A;
+    out[n + pix] = D - E - c45 * B;
+    out[2 * n + pix] = C;
+    out[3 * n + pix] = D + E - c45 * B;
+  }
+  __syncthreads();
+}
+
+// Levels above source level a of one base channel, computed in LDS.  TAIL jobs
+// (channel tid) compute and store every level up to the top; TAILGAB jobs rebuild the
+// intensity chain up to level tid and store only that level's Gabor maps, so the
+// Gabor work of the small levels runs in parallel workgroups.
+__device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float* smem) {
+  float* SA = smem;
+  float* SB = SA + SP_TAIL_SRC;
+  float* HB = SB + SP_TAIL_ALT;
+  float* V = HB + SP_TAIL_HB;
+  float* taps = V + SP_TAIL_V;
+  const bool gab = J.kind == JOB_TAILGAB;
+  const int ch = gab ? 0 : J.tid, L0 = J.a, R = sd.gr, nt = 2 * R + 1;
+  const int last = gab ? J.tid : sd.top;
+  if (gab && (int)threadIdx.x < 4 * nt)
+    taps[(threadIdx.x / nt) * (2 * SP_MAXR + 1) + threadIdx.x % nt] = sd.gf[threadIdx.x / nt][threadIdx.x % nt];
+  int cH = sd.Hl[L0], cW = sd.Wl[L0];
+  {
+    const float* src = base_ptr(sd, ckpt, L0) + (size_t)ch * cH * cW;
+    for (int i = threadIdx.x; i < cH * cW; i += SP_BLOCK) SA[i] = src[i];
+  }
+  float* cur = SA;
+  float* nxt = SB;
+  for (int l = L0; l < last; ++l) {
+    const int nH = sd.Hl[l + 1], nW = sd.Wl[l + 1];
+    __syncthreads();
+    for (int i = threadIdx.x; i < cH * nW; i += SP_BLOCK) {
+      const int r = i / nW, j = i - r * nW;
+      const float* row = cur + r * cW;
+      float acc = 0.f;
+#pragma unroll
+      for (int t = -2; t <= 2; ++t) acc += binom(t) * row[clampi(2 * j + t, 0, cW - 1)];
+      HB[i] = acc;
+    }
+    __syncthreads();
+    float* dst = gab ? nullptr : level_dst(sd, ckpt, l + 1) + (size_t)ch * nH * nW;
+    for (int i = threadIdx.x; i < nH * nW; i += SP_BLOCK) {
+      const int r = i / nW, j = i - r * nW;
+      float acc = 0.f;
+#pragma unroll
+      for (int t = -2; t <= 2; ++t) acc += binom(t) * HB[clampi(2 * r + t, 0, cH - 1) * nW + j];
+      nxt[i] = acc;
+      if (dst) dst[i] = acc;
+    }
+    __syncthreads();
+    if (gab && l + 1 == last) gabor_lds(nxt, nH, nW, V, taps, R, sd.c45, sd.gab[l + 1]);
+    float* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    cH = nH;
+    cW = nW;
+  }
+}
+
+template <bool BIG>
+__global__ __launch_bounds__(SP_BLOCK) void k_pyr(const Job* __restrict__ jobs,
+                                                  const StreamDesc* __restrict__ sds,
+                                                  const StepIO* __restrict__ ios, StepIO io0) {
+  __shared__ float smem[BIG ? TAIL_LDS : DOWN_LDS];
+  const Job J = jobs[blockIdx.x];
+  const StreamDesc& sd = sds[J.stream];
+  float* ckpt = IOF(ckpt);
+  if (J.kind == JOB_DOWN) {
+    down_job(J, sd, ckpt, smem);
+  } else if (J.kind == JOB_GABOR) {
+    gabor_job(J, sd, ckpt, smem);
+  } else if (BIG && (J.kind == JOB_TAIL || J.kind == JOB_TAILGAB)) {
+    tail_job(J, sd, ckpt, smem);
+  }
+}
+
 // ---------------------------------------------------------------- centre-surround statistics
-// Tile of the centre level c; each wavefront takes 8x8 blocks of the tile.
+// A 16x16 tile of the centre level c: the 8 centre maps and, per pair (c, s), the
+// footprint of the tile on level s are staged in LDS; each wavefront then takes one
+// 8x8 block and reduces min, max and block maximum of every map with DPP.
+constexpr int CS_T = 16;
+constexpr int CS_F = CS_T / 2 + 2;      // footprint edge on a coarser level (offset >= 1)
+
+struct Foot { int y0, x0, h, w; };      // footprint of rows/cols on the surround level
+
+__device__ __forceinline__ Foot footprint(int y0, int ny, int x0, int nx, int d, int Hs, int Ws) {
+  Foot f;
+  f.y0 = min(y0 >> d, Hs - 1);
+  f.x0 = min(x0 >> d, Ws - 1);
+  f.h = min(((y0 + ny - 1) >> d) + 1, Hs - 1) - f.y0 + 1;
+  f.w = min(((x0 + nx - 1) >> d) + 1, Ws - 1) - f.x0 + 1;
+  return f;
+}
+
+__device__ __forceinline__ float bilinear_lds(const float* X, int ld, const Tap& ty, const Tap& tx, int fy0, int fx0) {
+  const float* r0 = X + (ty.i0 - fy0) * ld - fx0;
+  const float* r1 = X + (ty.i1 - fy0) * ld - fx0;
+  const float top = (1.f - tx.w) * r0[tx.i0] + tx.w * r0[tx.i1];
+  const float bot = (1.f - tx.w) * r1[tx.i0] + tx.w * r1[tx.i1];
+  return (1.f - ty.w) * top + ty.w * bot;
+}
+
 __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jobs,
                                                       const StreamDesc* __restrict__ sds,
                                                       const StepIO* __restrict__ ios, StepIO io0) {
-  __shared__ float acc[4][4 * SP_NCH][3];      // [wave][pair-in-centre * 8 + k][min, max, sum]
+  __shared__ float cen[SP_NCH][CS_T * CS_T];
+  __shared__ float sur[4][SP_NCH][CS_F * CS_F];
+  __shared__ float acc[4][4 * SP_NCH][3];   // [wave][pair-in-centre * 8 + k][min, max, sum]
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const float* ckpt = IOF(ckpt);
   const int c = J.a, Hc = sd.Hl[c], Wc = sd.Wl[c];
   const int lane = lane_id(), w = wave_id();
-  const int nbx = (J.tw + 7) >> 3, nby = (J.th + 7) >> 3, nbk = nbx * nby;
+  __shared__ int plist[4];
+  __shared__ Foot fp[4];
   int npc = 0;
-  for (int p = 0; p < sd.n_pairs; ++p) npc += (sd.pc[p] == c);
+  for (int p = 0; p < sd.n_pairs; ++p)
+    if (sd.pc[p] == c && npc < 4) {
+      if (threadIdx.x == 0) {
+        const int s = sd.ps[p];
+        plist[npc] = p;
+        fp[npc] = footprint(J.y0, J.th, J.x0, J.tw, s - c, sd.Hl[s], sd.Wl[s]);
+      }
+      ++npc;
+    }
+  __syncthreads();
+  // stage the centre tile of all channels
+  const float* cptr[SP_NCH];
+#pragma unroll
+  for (int k = 0; k < SP_NCH; ++k) cptr[k] = chan_ptr(sd, ckpt, k, c);
+  for (int i = threadIdx.x; i < CS_T * CS_T; i += SP_BLOCK) {
+    const int yy = i / CS_T, xx = i - yy * CS_T;
+    const size_t o = (size_t)min(J.y0 + yy, Hc - 1) * Wc + min(J.x0 + xx, Wc - 1);
+    float v[SP_NCH];
+#pragma unroll
+    for (int k = 0; k < SP_NCH; ++k) v[k] = cptr[k][o];
+#pragma unroll
+    for (int k = 0; k < SP_NCH; ++k) cen[k][i] = v[k];
+  }
+  // stage the surround footprints
+  for (int q = 0; q < npc; ++q) {
+    const int s = sd.ps[plist[q]], Ws = sd.Wl[s];
+    const int nf = fp[q].h * fp[q].w;
+    for (int i = threadIdx.x; i < SP_NCH * nf; i += SP_BLOCK) {
+      const int k = i / nf, r = i - k * nf, fy = r / fp[q].w, fx = r - fy * fp[q].w;
+      sur[q][k][fy * CS_F + fx] = chan_ptr(sd, ckpt, k, s)[(size_t)(fp[q].y0 + fy) * Ws + fp[q].x0 + fx];
+    }
+  }
   for (int i = threadIdx.x; i < 4 * npc * SP_NCH; i += SP_BLOCK) {
     const int ww = i / (npc * SP_NCH), m = i - ww * npc * SP_NCH;
     acc[ww][m][0] = INFINITY;
@@ -452,38 +730,34 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
     acc[ww][m][2] = 0.f;
   }
   __syncthreads();
-  for (int bk = w; bk < nbk; bk += 4) {
-    const int by = bk / nbx, bx = bk - by * nbx;
-    const int y = J.y0 + 8 * by + (lane >> 3), x = J.x0 + 8 * bx + (lane & 7);
-    const bool exists = (J.y0 + 8 * by < Hc) && (J.x0 + 8 * bx < Wc);
-    const bool valid = y < Hc && x < Wc;
-    const int yc = min(y, Hc - 1), xc = min(x, Wc - 1);
-    int m = 0;
-    for (int p = 0; p < sd.n_pairs; ++p) {
-      if (sd.pc[p] != c) continue;
-      const int s = sd.ps[p], d = s - c;
-      const int Hs = sd.Hl[s], Ws = sd.Wl[s];
-      const Tap ty = bilinear_tap(yc, d, Hs), tx = bilinear_tap(xc, d, Ws);
-      for (int k = 0; k < SP_NCH; ++k, ++m) {
-        const float xcv = chan_ptr(sd, ckpt, k, c)[(size_t)yc * Wc + xc];
-        const float up = bilinear(chan_ptr(sd, ckpt, k, s), Ws, ty, tx);
-        const float F = fabsf(xcv - up);
+  const int nbx = (J.tw + 7) >> 3, nby = (J.th + 7) >> 3;
+  if (w < nbx * nby) {
+    const int by = w / nbx, bx = w - by * nbx;
+    const int yy = 8 * by + (lane >> 3), xx = 8 * bx + (lane & 7);
+    const int y = J.y0 + yy, x = J.x0 + xx;
+    const bool valid = yy < J.th && xx < J.tw;
+    const int yc = min(y, J.y0 + J.th - 1), xc = min(x, J.x0 + J.tw - 1);
+    for (int q = 0; q < npc; ++q) {
+      const int s = sd.ps[plist[q]], d = s - c;
+      const Tap ty = bilinear_tap(yc, d, sd.Hl[s]), tx = bilinear_tap(xc, d, sd.Wl[s]);
+#pragma unroll
+      for (int k = 0; k < SP_NCH; ++k) {
+        const float up = bilinear_lds(sur[q][k], CS_F, ty, tx, fp[q].y0, fp[q].x0);
+        const float F = fabsf(cen[k][(yc - J.y0) * CS_T + (xc - J.x0)] - up);
         const float bmn = wave_reduce<OpMin>(valid ? F : INFINITY);
         const float bmx = wave_reduce<OpMax>(valid ? F : -INFINITY);
-        if (lane == 0 && exists) {
-          acc[w][m][0] = fminf(acc[w][m][0], bmn);
-          acc[w][m][1] = fmaxf(acc[w][m][1], bmx);
-          acc[w][m][2] += bmx;
+        if (lane == 0) {
+          acc[w][q * SP_NCH + k][0] = bmn;
+          acc[w][q * SP_NCH + k][1] = bmx;
+          acc[w][q * SP_NCH + k][2] = bmx;
         }
       }
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < npc * SP_NCH; i += SP_BLOCK) {
-    const int pi = i / SP_NCH, k = i - pi * SP_NCH;
-    int p = 0, seen = -1;
-    for (; p < sd.n_pairs; ++p)
-      if (sd.pc[p] == c && ++seen == pi) break;
+    const int q = i / SP_NCH, k = i - q * SP_NCH;
+    const int p = plist[q];
     const float mn = fminf(fminf(acc[0][i][0], acc[1][i][0]), fminf(acc[2][i][0], acc[3][i][0]));
     const float mx = fmaxf(fmaxf(acc[0][i][1], acc[1][i][1]), fmaxf(acc[2][i][1], acc[3][i][1]));
     const float sm = (acc[0][i][2] + acc[1][i][2]) + (acc[2][i][2] + acc[3][i][2]);
@@ -495,11 +769,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
 }
 
 // ---------------------------------------------------------------- across-scale sum
-// Computes N(F(c,s)) for every pair on the region of level c that the c_max tile
-// needs, reduces it (blur + decimate with clamp) up to c_max, and sums it.
-constexpr int CA_T = 16;                // c_max tile edge
-constexpr int CA_R1 = 2 * CA_T + 3;     // 35: region one level finer
-constexpr int CA_R2 = 2 * CA_R1 + 3;    // 73: region two levels finer
+// F-bar_k on a 16x16 tile of c_max = sum over pairs of REDUCE^(c_max - c)(N(F(c, s))).
+// Every input is staged in (dynamically sized) LDS in one round trip; N(F) of all pairs
+// that share a centre level are summed before that level is reduced (REDUCE is
+// linear), and the sum from two levels down is folded into the level above it.
+constexpr int CA_T = SP_CA_T;           // c_max tile edge
 
 struct Range { int lo, n; };            // contiguous valid rows (or columns)
 
@@ -509,10 +783,10 @@ __device__ __forceinline__ Range finer_range(Range r, int n_finer) {
   return Range{lo, hi - lo + 1};
 }
 
-// out (rows ro x cols co of the coarse level) = decimated blur of in (rows ri x cols ci
-// of the finer level of size nh x nw), indices clamped to the finer map.
+// out (+)= decimated blur of in: out covers rows ro x cols co of the coarse level, in
+// covers rows ri x cols ci of the finer level (size nh x nw); indices clamped to it.
 __device__ void reduce_lds(const float* in, int ldi, Range ri, Range ci, float* tmp, int ldt,
-                           float* out, int ldo, Range ro, Range co, int nh, int nw) {
+                           float* out, int ldo, Range ro, Range co, int nh, int nw, bool add) {
   for (int i = threadIdx.x; i < ri.n * co.n; i += SP_BLOCK) {
     const int r = i / co.n, j = i - r * co.n;
     const int X = co.lo + j;
@@ -528,7 +802,7 @@ __device__ void reduce_lds(const float* in, int ldi, Range ri, Range ci, float* 
     float acc = 0.f;
 #pragma unroll
     for (int t = -2; t <= 2; ++t) acc += binom(t) * tmp[(clampi(2 * Y + t, 0, nh - 1) - ri.lo) * ldt + j];
-    out[r * ldo + j] = acc;
+    out[r * ldo + j] = add ? out[r * ldo + j] + acc : acc;
   }
   __syncthreads();
 }
@@ -536,98 +810,127 @@ __device__ void reduce_lds(const float* in, int ldi, Range ri, Range ci, float* 
 __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jobs,
                                                       const StreamDesc* __restrict__ sds,
                                                       const StepIO* __restrict__ ios, StepIO io0) {
-  __shared__ float R0[CA_R2 * CA_R2];
-  __shared__ float Tm[CA_R2 * CA_R1];
-  __shared__ float R1b[CA_R1 * CA_R1];
-  __shared__ float fb[CA_T * CA_T];
-  __shared__ float sh4[4];
-  __shared__ double sh256[SP_BLOCK];
+  extern __shared__ float dyn[];
   __shared__ NParams np[SP_MAXP];
+  __shared__ float fb[CA_T * CA_T];
+  __shared__ float wacc[4][3];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const float* ckpt = IOF(ckpt);
   const int k = J.a, cm = sd.c_max;
   const int Hm = sd.Hl[cm], Wm = sd.Wl[cm];
-  for (int p = 0; p < sd.n_pairs; ++p) {
+  const CaLayout L = csapply_layout(sd.pc, sd.ps, sd.n_pairs, cm);
+  unsigned hm = 0;
+  for (int p = 0; p < sd.n_pairs; ++p) hm |= 1u << (cm - sd.pc[p]);
+  const bool has0 = (hm & 1u) != 0, has1 = (hm & 2u) != 0, has2 = (hm & 4u) != 0;
+  // regions of the tile on the centre levels (r = c_max - c)
+  const Range rg0{J.y0, J.th}, cg0{J.x0, J.tw};
+  Range rg1 = rg0, cg1 = cg0, rg2 = rg0, cg2 = cg0;
+  if (has1 || has2) {
+    rg1 = finer_range(rg0, sd.Hl[cm - 1]);
+    cg1 = finer_range(cg0, sd.Wl[cm - 1]);
+  }
+  if (has2) {
+    rg2 = finer_range(rg1, sd.Hl[cm - 2]);
+    cg2 = finer_range(cg1, sd.Wl[cm - 2]);
+  }
+  float* X0 = dyn + L.x0;
+  float* X1 = dyn + L.x1;
+  float* X2 = dyn + L.x2;
+  // ---- one round trip: N parameters (one wavefront per pair), centre regions, footprints
+  for (int p = wave_id(); p < sd.n_pairs; p += 4) {
     const int c = sd.pc[p];
     const int nt = sd.ntiles_lvl[c];
     const float* parts = sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)k * nt);
-    const NParams q = nparams_from_parts(parts, nt, nblocks8(sd.Hl[c], sd.Wl[c]), sd.flat_tol, sh4, sh256);
-    if (threadIdx.x == 0) np[p] = q;
+    const NParams q = nparams_wave(parts, nt, nblocks8(sd.Hl[c], sd.Wl[c]), sd.flat_tol);
+    if (lane_id() == 0) np[p] = q;
   }
-  for (int i = threadIdx.x; i < CA_T * CA_T; i += SP_BLOCK) fb[i] = 0.f;
-  __syncthreads();
-  const Range tr{J.y0, J.th}, tc{J.x0, J.tw};
-  for (int p = 0; p < sd.n_pairs; ++p) {
-    const NParams q = np[p];
-    if (q.flat) continue;
-    const int c = sd.pc[p], s = sd.ps[p], d = s - c, r = cm - c;
-    const int Hc = sd.Hl[c], Wc = sd.Wl[c], Hs = sd.Hl[s], Ws = sd.Wl[s];
+  auto stage = [&](int r, Range rr, Range cc, float* X) {
+    const int c = cm - r, Wc = sd.Wl[c];
     const float* Xc = chan_ptr(sd, ckpt, k, c);
-    const float* Xs = chan_ptr(sd, ckpt, k, s);
-    if (r == 0) {
-      for (int i = threadIdx.x; i < J.th * J.tw; i += SP_BLOCK) {
-        const int yy = i / J.tw, xx = i - yy * J.tw;
-        const int y = J.y0 + yy, x = J.x0 + xx;
-        if (y < Hm && x < Wm) {
-          const Tap ty = bilinear_tap(y, d, Hs), tx = bilinear_tap(x, d, Ws);
-          const float F = fabsf(Xc[(size_t)y * Wc + x] - bilinear(Xs, Ws, ty, tx));
-          fb[yy * CA_T + xx] += napply(q, F);
-        }
+    const int n = rr.n * cc.n;
+    for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
+      const int yy = i / cc.n, xx = i - yy * cc.n;
+      X[i] = Xc[(size_t)(rr.lo + yy) * Wc + cc.lo + xx];
+    }
+  };
+  if (has0) stage(0, rg0, cg0, X0);
+  if (has1) stage(1, rg1, cg1, X1);
+  if (has2) stage(2, rg2, cg2, X2);
+  if (!has1 && has2)
+    for (int i = threadIdx.x; i < rg1.n * cg1.n; i += SP_BLOCK) X1[i] = 0.f;
+  for (int i = threadIdx.x; i < CA_T * CA_T; i += SP_BLOCK) fb[i] = 0.f;
+  {
+    int off = L.foot0;
+    for (int p = 0; p < sd.n_pairs; ++p) {
+      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], Ws = sd.Wl[s];
+      const Range rr = (r == 0) ? rg0 : ((r == 1) ? rg1 : rg2);
+      const Range cc = (r == 0) ? cg0 : ((r == 1) ? cg1 : cg2);
+      const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], Ws);
+      const float* Xs = chan_ptr(sd, ckpt, k, s);
+      float* dst = dyn + off;
+      for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK) {
+        const int fy = i / f.w, fx = i - fy * f.w;
+        dst[i] = Xs[(size_t)(f.y0 + fy) * Ws + f.x0 + fx];
       }
-      __syncthreads();
-      continue;
+      off += csapply_foot_cap(r, s - c);
     }
-    // region ranges, finest first
-    Range rr1 = finer_range(tr, sd.Hl[cm - 1]), cr1 = finer_range(tc, sd.Wl[cm - 1]);
-    Range rr0 = rr1, cr0 = cr1;
-    if (r == 2) {
-      rr0 = finer_range(rr1, sd.Hl[cm - 2]);
-      cr0 = finer_range(cr1, sd.Wl[cm - 2]);
+  }
+  __syncthreads();
+  // ---- N(F) summed over the pairs of each centre level, in place of the centre values
+  auto nsum = [&](int r, Range rr, Range cc, float* X) {
+    const int c = cm - r;
+    const int n = rr.n * cc.n;
+    for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
+      const int yy = i / cc.n, xx = i - yy * cc.n;
+      const int y = rr.lo + yy, x = cc.lo + xx;
+      const float xc = X[i];
+      float acc = 0.f;
+      int off = L.foot0;
+      for (int p = 0; p < sd.n_pairs; ++p) {
+        const int cp = sd.pc[p], sp = sd.ps[p], d = sp - cp;
+        const int cap = csapply_foot_cap(cm - cp, d);
+        if (cp == c && !np[p].flat) {
+          const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, d, sd.Hl[sp], sd.Wl[sp]);
+          const Tap ty = bilinear_tap(y, d, sd.Hl[sp]), tx = bilinear_tap(x, d, sd.Wl[sp]);
+          acc += napply(np[p], fabsf(xc - bilinear_lds(dyn + off, f.w, ty, tx, f.y0, f.x0)));
+        }
+        off += cap;
+      }
+      X[i] = acc;
     }
-    const int ld0 = cr0.n;
-    for (int i = threadIdx.x; i < rr0.n * cr0.n; i += SP_BLOCK) {
-      const int yy = i / cr0.n, xx = i - yy * cr0.n;
-      const int y = rr0.lo + yy, x = cr0.lo + xx;
-      const Tap ty = bilinear_tap(y, d, Hs), tx = bilinear_tap(x, d, Ws);
-      const float F = fabsf(Xc[(size_t)y * Wc + x] - bilinear(Xs, Ws, ty, tx));
-      R0[yy * ld0 + xx] = napply(q, F);
-    }
-    __syncthreads();
-    if (r == 1) {
-      reduce_lds(R0, ld0, rr0, cr0, Tm, tc.n, R1b, CA_T, tr, tc, sd.Hl[cm - 1], sd.Wl[cm - 1]);
-    } else {
-      reduce_lds(R0, ld0, rr0, cr0, Tm, cr1.n, R1b, cr1.n, rr1, cr1, sd.Hl[cm - 2], sd.Wl[cm - 2]);
-      reduce_lds(R1b, cr1.n, rr1, cr1, Tm, tc.n, R0, CA_T, tr, tc, sd.Hl[cm - 1], sd.Wl[cm - 1]);
-    }
-    const float* res = (r == 1) ? R1b : R0;
+  };
+  if (has0) nsum(0, rg0, cg0, X0);
+  if (has1) nsum(1, rg1, cg1, X1);
+  if (has2) nsum(2, rg2, cg2, X2);
+  __syncthreads();
+  // ---- reduce: two levels down -> one level down (added), one level down -> tile
+  float* tm = dyn + L.tm;
+  if (has2)
+    reduce_lds(X2, cg2.n, rg2, cg2, tm, cg1.n, X1, cg1.n, rg1, cg1, sd.Hl[cm - 2], sd.Wl[cm - 2], true);
+  if (has1 || has2)
+    reduce_lds(X1, cg1.n, rg1, cg1, tm, cg0.n, fb, CA_T, rg0, cg0, sd.Hl[cm - 1], sd.Wl[cm - 1], true);
+  if (has0) {
     for (int i = threadIdx.x; i < J.th * J.tw; i += SP_BLOCK) {
       const int yy = i / J.tw, xx = i - yy * J.tw;
-      fb[yy * CA_T + xx] += res[yy * CA_T + xx];
+      fb[yy * CA_T + xx] += X0[i];
     }
     __syncthreads();
   }
-  // store F-bar and its partial statistics (8x8 blocks per wavefront)
+  // ---- store F-bar and its partial statistics (one 8x8 block per wavefront)
   const int lane = lane_id(), w = wave_id();
-  const int nbx = (J.tw + 7) >> 3, nby = (J.th + 7) >> 3, nbk = nbx * nby;
+  const int nbx = (J.tw + 7) >> 3, nby = (J.th + 7) >> 3;
   float wmn = INFINITY, wmx = -INFINITY, wsum = 0.f;
-  for (int bk = w; bk < nbk; bk += 4) {
-    const int by = bk / nbx, bx = bk - by * nbx;
+  if (w < nbx * nby) {
+    const int by = w / nbx, bx = w - by * nbx;
     const int yy = 8 * by + (lane >> 3), xx = 8 * bx + (lane & 7);
-    const int y = J.y0 + yy, x = J.x0 + xx;
-    const bool exists = (J.y0 + 8 * by < Hm) && (J.x0 + 8 * bx < Wm);
-    const bool valid = y < Hm && x < Wm && yy < J.th && xx < J.tw;
+    const bool valid = yy < J.th && xx < J.tw;
     const float v = valid ? fb[yy * CA_T + xx] : 0.f;
-    if (valid) sd.fbar[(size_t)k * Hm * Wm + (size_t)y * Wm + x] = v;
-    const float bmn = wave_reduce<OpMin>(valid ? v : INFINITY);
-    const float bmx = wave_reduce<OpMax>(valid ? v : -INFINITY);
-    if (exists) {
-      wmn = fminf(wmn, bmn);
-      wmx = fmaxf(wmx, bmx);
-      wsum += bmx;
-    }
+    if (valid) sd.fbar[(size_t)k * Hm * Wm + (size_t)(J.y0 + yy) * Wm + J.x0 + xx] = v;
+    wmn = wave_reduce<OpMin>(valid ? v : INFINITY);
+    wmx = wave_reduce<OpMax>(valid ? v : -INFINITY);
+    wsum = wmx;
   }
-  __shared__ float wacc[4][3];
   if (lane == 0) {
     wacc[w][0] = wmn;
     wacc[w][1] = wmx;
@@ -643,13 +946,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
 }
 
 // ---------------------------------------------------------------- conspicuity and saliency
-__device__ void consp_nparams(const StreamDesc& sd, NParams* np, float* sh4, double* sh256) {
+__device__ void consp_nparams(const StreamDesc& sd, NParams* np) {
   const int cm = sd.c_max;
   const int nb = nblocks8(sd.Hl[cm], sd.Wl[cm]);
-  for (int k = 0; k < SP_NCH; ++k) {
-    const NParams q = nparams_from_parts(sd.fbar_part + 3 * (size_t)k * sd.n_cmax_tiles, sd.n_cmax_tiles, nb,
-                                         sd.flat_tol, sh4, sh256);
-    if (threadIdx.x == 0) np[k] = q;
+  for (int k = wave_id(); k < SP_NCH; k += 4) {
+    const NParams q = nparams_wave(sd.fbar_part + 3 * (size_t)k * sd.n_cmax_tiles, sd.n_cmax_tiles, nb,
+                                   sd.flat_tol);
+    if (lane_id() == 0) np[k] = q;
   }
   __syncthreads();
 }
@@ -672,23 +975,26 @@ __global__ __launch_bounds__(SP_BLOCK) void k_consp(const Job* __restrict__ jobs
                                                     const StepIO* __restrict__ ios, StepIO io0) {
   __shared__ float sh4[4];
   __shared__ int shi4[4];
-  __shared__ double sh256[SP_BLOCK];
   __shared__ NParams np[SP_NCH];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   float* S_out = IOF(S_out);
   float* C_out = IOF(C_out);
   float* S_tape = IOF(S_tape);
-  consp_nparams(sd, np, sh4, sh256);
   const int cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const size_t plane = (size_t)Hm * Wm;
   const int yy = threadIdx.x / CA_T, xx = threadIdx.x % CA_T;
   const int y = J.y0 + yy, x = J.x0 + xx;
-  const bool valid = yy < J.th && xx < J.tw && y < Hm && x < Wm;
-  float S = 0.f;
+  const bool valid = yy < J.th && xx < J.tw;
   const size_t o = (size_t)min(y, Hm - 1) * Wm + min(x, Wm - 1);
+  float fv[SP_NCH];
+#pragma unroll
+  for (int k = 0; k < SP_NCH; ++k) fv[k] = sd.fbar[k * plane + o];
+  consp_nparams(sd, np);
+  float S = 0.f;
+#pragma unroll
   for (int k = 0; k < SP_NCH; ++k) {
-    const float Ck = napply(np[k], sd.fbar[k * plane + o]);
+    const float Ck = napply(np[k], fv[k]);
     if (valid && C_out) C_out[k * plane + o] = Ck;
     S += sd.w[k] * Ck;
   }
@@ -710,7 +1016,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_smax(const Job* __restrict__ jobs,
   const int cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const int yy = threadIdx.x / CA_T, xx = threadIdx.x % CA_T;
   const int y = J.y0 + yy, x = J.x0 + xx;
-  const bool valid = yy < J.th && xx < J.tw && y < Hm && x < Wm;
+  const bool valid = yy < J.th && xx < J.tw;
   const size_t o = (size_t)min(y, Hm - 1) * Wm + min(x, Wm - 1);
   smax_partial(S_in[o], (int)o, valid, sd.s_part + 2 * (size_t)J.tid, sh4, shi4);
 }
@@ -718,12 +1024,14 @@ __global__ __launch_bounds__(SP_BLOCK) void k_smax(const Job* __restrict__ jobs,
 // ---------------------------------------------------------------- Kalman prior update
 // q = clamp(up(S / max S), eps, 1 - eps) (0.5 if S is flat), eps on the border ring;
 // f = G * pi_{t-1} (or G * seg_{t-1}); pi_t = f + K_t (q - f); eps on the border ring.
-constexpr int KT = 16;
+// With io.unary set it also writes the unary capacities of pi_t.
+constexpr int KT = 16;        // tile rows of the level-0 update
+constexpr int KTW_MAX = 64;   // widest tile (the width is chosen per stream by the host)
 __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ jobs,
                                                      const StreamDesc* __restrict__ sds,
                                                      const StepIO* __restrict__ ios, StepIO io0) {
-  __shared__ float reg[KT + 4][KT + 4];
-  __shared__ float hb[KT + 4][KT];
+  __shared__ float reg[KT + 4][KTW_MAX + 4];
+  __shared__ float hb[KT + 4][KTW_MAX];
   __shared__ float sh4[4];
   __shared__ int shi4[4];
   const Job J = jobs[blockIdx.x];
@@ -735,48 +1043,63 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   float* pout = IOF(prior_out);
   float* ftape = IOF(f_tape);
   float* mstape = IOF(ms_tape);
+  float* unary = IOF(unary);
   const float K = IOF(K);
   const int t = IOF(t);
   const int H = sd.H, W = sd.W, cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
+  const int tw = J.tw, rw = tw + 4;
+  if (t > 0) {
+    for (int i = threadIdx.x; i < (KT + 4) * rw; i += SP_BLOCK) {
+      const int ry = i / rw, rx = i - ry * rw;
+      const int y = clampi(J.y0 - 2 + ry, 0, H - 1), x = clampi(J.x0 - 2 + rx, 0, W - 1);
+      const size_t o = (size_t)y * W + x;
+      reg[ry][rx] = seg ? (float)seg[o] : pprev[o];
+    }
+  }
   float m;
   int xs;
   smax_from_parts(sd.s_part, sd.n_cmax_tiles, &m, &xs, sh4, shi4);
   const bool flat = !(m > sd.flat_tol);
   if (t > 0) {
-    for (int i = threadIdx.x; i < (KT + 4) * (KT + 4); i += SP_BLOCK) {
-      const int ry = i / (KT + 4), rx = i - ry * (KT + 4);
-      const int y = clampi(J.y0 - 2 + ry, 0, H - 1), x = clampi(J.x0 - 2 + rx, 0, W - 1);
-      const size_t o = (size_t)y * W + x;
-      reg[ry][rx] = seg ? (float)seg[o] : pprev[o];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < (KT + 4) * KT; i += SP_BLOCK) {
-      const int r = i / KT, j = i - r * KT;
+    for (int i = threadIdx.x; i < (KT + 4) * tw; i += SP_BLOCK) {
+      const int r = i / tw, j = i - r * tw;
       hb[r][j] = kB0 * reg[r][j] + kB1 * reg[r][j + 1] + kB2 * reg[r][j + 2] + kB1 * reg[r][j + 3] + kB0 * reg[r][j + 4];
     }
     __syncthreads();
   }
-  const int yy = threadIdx.x / KT, xx = threadIdx.x % KT;
-  const int y = J.y0 + yy, x = J.x0 + xx;
-  if (yy < J.th && xx < J.tw && y < H && x < W) {
-    const bool ring = on_border(y, x, H, W, sd.border);
-    float q = 0.5f;
-    if (!flat) {
-      const float u = observe_u(S, Hm, Wm, cm, m, y, x);
-      q = fminf(fmaxf(u, sd.eps), 1.f - sd.eps);
+  // 16 threads per tile row; each takes tw/16 consecutive pixels
+  const int yy = threadIdx.x >> 4, px = (tw + 15) >> 4, x0 = (threadIdx.x & 15) * px;
+  const int y = J.y0 + yy;
+  if (yy < J.th && y < H) {
+    const bool rowring = y < sd.border || y >= H - sd.border;
+    const Tap ty = bilinear_tap(y, cm, Hm);
+    for (int k = 0; k < px; ++k) {
+      const int xx = x0 + k, x = J.x0 + xx;
+      if (xx >= tw || x >= W) break;
+      const bool ring = rowring || x < sd.border || x >= W - sd.border;
+      float q = 0.5f;
+      if (!flat) {
+        const Tap tx = bilinear_tap(x, cm, Wm);
+        const float u = bilinear(S, Wm, ty, tx) / m;
+        q = fminf(fmaxf(u, sd.eps), 1.f - sd.eps);
+      }
+      if (ring) q = sd.eps;
+      float pi = q;
+      const size_t o = (size_t)y * W + x;
+      if (t > 0) {
+        const float f = kB0 * hb[yy][xx] + kB1 * hb[yy + 1][xx] + kB2 * hb[yy + 2][xx] + kB1 * hb[yy + 3][xx] +
+                        kB0 * hb[yy + 4][xx];
+        pi = f + K * (q - f);
+        if (ftape) ftape[o] = f;
+      }
+      if (ring) pi = sd.eps;
+      pnext[o] = pi;
+      if (pout) pout[o] = pi;
+      if (unary) {
+        unary[o] = -log1pf(-fminf(pi, 1.f - sd.eps));
+        unary[(size_t)H * W + o] = -logf(fmaxf(pi, sd.eps));
+      }
     }
-    if (ring) q = sd.eps;
-    float pi = q;
-    const size_t o = (size_t)y * W + x;
-    if (t > 0) {
-      const float f = kB0 * hb[yy][xx] + kB1 * hb[yy + 1][xx] + kB2 * hb[yy + 2][xx] + kB1 * hb[yy + 3][xx] +
-                      kB0 * hb[yy + 4][xx];
-      pi = f + K * (q - f);
-      if (ftape) ftape[o] = f;
-    }
-    if (ring) pi = sd.eps;
-    pnext[o] = pi;
-    if (pout) pout[o] = pi;
   }
   if (mstape && J.tid == 0 && threadIdx.x == 0) {
     mstape[0] = m;
@@ -797,13 +1120,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_mrf(const Job* __restrict__ jobs,
   float* pairw = IOF(pairwise);
   float* beta_out = IOF(beta_out);
   const int H = sd.H, W = sd.W;
-  unsigned long long s = 0;
-  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) s += sd.rgb_d2_part[i];
-  s = block_sum_u64(s, sh);
-  const unsigned long long cnt = (unsigned long long)H * (W - 1) + (unsigned long long)(H - 1) * W +
-                                 2ull * (unsigned long long)(H - 1) * (W - 1);
-  const double mean = cnt ? (double)s / (double)cnt : 0.0;
-  const float beta = (mean > 0.0) ? (float)(1.0 / (2.0 * mean)) : 0.f;
+  const float beta = beta_from_parts(sd, sh);
   const int yy = threadIdx.x / 16, xx = threadIdx.x % 16;
   const int y = J.y0 + yy, x = J.x0 + xx;
   if (yy < J.th && xx < J.tw && y < H && x < W) {
@@ -811,22 +1128,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_mrf(const Job* __restrict__ jobs,
     const float pi = prior[o];
     unary[o] = -log1pf(-fminf(pi, 1.f - sd.eps));
     unary[plane + o] = -logf(fmaxf(pi, sd.eps));
-    const uint8_t* p = rgb + o * 3;
-    const int r = p[0], g = p[1], b = p[2];
-    const int dys[4] = {0, 1, 1, 1}, dxs[4] = {1, 0, 1, -1};
-    const float dist[4] = {1.f, 1.f, 1.41421356237f, 1.41421356237f};
-#pragma unroll
-    for (int dd = 0; dd < 4; ++dd) {
-      const int y2 = y + dys[dd], x2 = x + dxs[dd];
-      float wv = 0.f;
-      if (y2 < H && x2 >= 0 && x2 < W) {
-        const uint8_t* q = rgb + ((size_t)y2 * W + x2) * 3;
-        const int dr = r - q[0], dg = g - q[1], db = b - q[2];
-        const float d2 = (float)(dr * dr + dg * dg + db * db);
-        wv = sd.potts + sd.lam * expf(-beta * d2) / dist[dd];
-      }
-      pairw[dd * plane + o] = wv;
-    }
+    pairwise_at(rgb, H, W, y, x, beta, sd.lam, sd.potts, pairw, plane);
   }
   if (beta_out && J.tid == 0 && threadIdx.x == 0) beta_out[0] = beta;
 }
@@ -948,11 +1250,10 @@ __global__ __launch_bounds__(SP_BLOCK) void k_consp_dot(const Job* __restrict__ 
                                                         const int* __restrict__ frame_of,
                                                         float* __restrict__ dot_part, float* __restrict__ cx_out) {
   __shared__ float sh4[4];
-  __shared__ double sh256[SP_BLOCK];
   __shared__ NParams np[SP_NCH];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
-  consp_nparams(sd, np, sh4, sh256);
+  consp_nparams(sd, np);
   const int f = frame_of[J.stream];
   const int cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const size_t plane = (size_t)Hm * Wm;
@@ -1065,21 +1366,30 @@ __global__ void k_batch_begin(int n, BatchState* __restrict__ st, const uint8_t*
     K = a / (a + R);
     P = R * K;
   }
-  StepIO io;
-  memset(&io, 0, sizeof io);
-  io.rgb = in_ptrs[i];
-  io.rgb_prev = (s.t == 0) ? nullptr : s.last_rgb;
-  io.S_out = s.S;
-  io.S_in = s.S;
-  io.pi_prev = s.pi[s.cur];
-  io.pi_next = s.pi[s.cur ^ 1];
-  io.K = (float)K;
-  io.t = (int32_t)(s.t < 0x7fffffff ? s.t : 0x7fffffff);
-  ios[i] = io;
+  StepIO* io = ios + i;
+  const uint8_t* cur = in_ptrs[i];
+  io->rgb = cur;
+  io->rgb_prev = (s.t == 0) ? nullptr : s.last_rgb;
+  io->S_out = s.S;
+  io->C_out = nullptr;
+  io->ckpt = nullptr;
+  io->S_tape = nullptr;
+  io->S_in = s.S;
+  io->seg_prev = nullptr;
+  io->pi_prev = s.cur ? s.pi[1] : s.pi[0];
+  io->pi_next = s.cur ? s.pi[0] : s.pi[1];
+  io->prior_out = nullptr;
+  io->f_tape = nullptr;
+  io->ms_tape = nullptr;
+  io->unary = s.unary;
+  io->pairwise = s.pairwise;
+  io->beta_out = s.beta;
+  io->K = (float)K;
+  io->t = (int32_t)(s.t < 0x7fffffff ? s.t : 0x7fffffff);
   s.t += 1;
   s.P = P;
   s.cur ^= 1;
-  s.last_rgb = io.rgb;
+  s.last_rgb = cur;
   st[i] = s;
 }
 
@@ -1097,7 +1407,7 @@ __global__ void k_batch_copy_out(const BatchState* __restrict__ st, const Stream
                                  float* const* __restrict__ out) {
   const int s = blockIdx.y;
   const size_t n = (size_t)sds[s].H * sds[s].W;
-  const float* src = st[s].pi[st[s].cur];
+  const float* src = st[s].cur ? st[s].pi[1] : st[s].pi[0];
   float* dst = out[s];
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -1109,7 +1419,7 @@ __global__ void k_batch_copy_out(const BatchState* __restrict__ st, const Stream
 static inline hipError_t chk() { return hipGetLastError(); }
 
 hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios,
-                     const StepIO* io0, int flag, const float* aux, hipStream_t st) {
+                     const StepIO* io0, int flag, const float* aux, hipStream_t st, size_t lds) {
   if (n <= 0) return hipSuccess;
   const dim3 g(n), b(SP_BLOCK);
   StepIO z{};
@@ -1117,10 +1427,11 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
   switch (kind) {
     case JOB_RGB: hipLaunchKernelGGL(k_rgb, g, b, 0, st, jobs, sds, ios, io, flag); break;
     case JOB_FEAT: hipLaunchKernelGGL((k_feat<16, 16>), g, b, 0, st, jobs, sds, ios, io); break;
-    case JOB_DOWN: hipLaunchKernelGGL((k_down<16, 16>), g, b, 0, st, jobs, sds, ios, io); break;
-    case JOB_GABOR: hipLaunchKernelGGL(k_gabor, g, b, 0, st, jobs, sds, ios, io); break;
+    case JOB_DOWN:   // pyramid launch without tail jobs (DOWN and GABOR jobs)
+    case JOB_GABOR: hipLaunchKernelGGL(k_pyr<false>, g, b, 0, st, jobs, sds, ios, io); break;
+    case JOB_TAIL: hipLaunchKernelGGL(k_pyr<true>, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSSTATS: hipLaunchKernelGGL(k_csstats, g, b, 0, st, jobs, sds, ios, io); break;
-    case JOB_CSAPPLY: hipLaunchKernelGGL(k_csapply, g, b, 0, st, jobs, sds, ios, io); break;
+    case JOB_CSAPPLY: hipLaunchKernelGGL(k_csapply, g, b, lds, st, jobs, sds, ios, io); break;
     case JOB_CONSP: hipLaunchKernelGGL(k_consp, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_SMAX: hipLaunchKernelGGL(k_smax, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_KALMAN: hipLaunchKernelGGL(k_kalman, g, b, 0, st, jobs, sds, ios, io); break;
@@ -1187,4 +1498,10 @@ hipError_t sp_launch_batch_copy_out(int n, const BatchState* st, const StreamDes
                                     hipStream_t stream) {
   hipLaunchKernelGGL(k_batch_copy_out, dim3(64, n), dim3(SP_BLOCK), 0, stream, st, sds, out);
   return chk();
+}
+
+hipError_t sp_csapply_reserve_lds(size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csapply), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
 }

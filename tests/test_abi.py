@@ -132,9 +132,10 @@ def test_create_rejects_bad_shapes_and_nulls(lib):
     Hs = (ctypes.c_int32 * 2)(120, 240)
     Ws = (ctypes.c_int32 * 2)(160, 320)
     lib.sp_default_params(ctypes.byref(p))
-    assert lib.sp_batch_create(ctypes.byref(p), 0, Hs, Ws, None, ctypes.byref(hb)) == _lib.SP_EINVAL
+    assert lib.sp_batch_create(ctypes.byref(p), 0, Hs, Ws, 0, None, ctypes.byref(hb)) == _lib.SP_EINVAL
+    assert lib.sp_batch_create(ctypes.byref(p), 2, Hs, Ws, 8, None, ctypes.byref(hb)) == _lib.SP_EINVAL
     p.record_tape = 4
-    assert lib.sp_batch_create(ctypes.byref(p), 2, Hs, Ws, None, ctypes.byref(hb)) == _lib.SP_EINVAL
+    assert lib.sp_batch_create(ctypes.byref(p), 2, Hs, Ws, 0, None, ctypes.byref(hb)) == _lib.SP_EINVAL
 
 
 def test_product_path_has_no_cpu_fallback():

@@ -80,3 +80,77 @@ def test_batch_of_one_large_stream_and_prior_pointer():
     assert torch.equal(out, ref)
     ctx.close()
     b.close()
+
+
+def _copy_from(ptr, like):
+    import ctypes
+    import torch
+    out = torch.empty_like(like)
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    assert hip.hipMemcpy(out.data_ptr(), ptr, out.numel() * out.element_size(), 3) == 0
+    return out
+
+
+def test_batched_step_with_mrf_equals_fused_plain_step():
+    print("\n[case] batch with MRF capacities (3 streams) vs the fused plain step, 4 steps", flush=True)
+    torch = _torch()
+    from paper_1008_0502_amd.api import Batch, Context, Params
+    sizes = [(240, 320), (120, 160), (97, 131)]
+    T = 4
+    clips = []
+    for i, (H, W) in enumerate(sizes):
+        spec = synth.config2_spec(H=H, W=W, T=T, seed=40 + i)
+        clips.append(torch.from_numpy(synth.Clip(spec).stack()[0]).cuda())
+    pp = Params()
+    ctxs = [Context(H, W, pp) for (H, W) in sizes]
+    b = Batch(sizes, pp, mrf=True)
+    for t in range(T):
+        b.step(Batch.pointer_table([c[t] for c in clips]))
+        torch.cuda.synchronize()
+        for i, ((H, W), ctx) in enumerate(zip(sizes, ctxs)):
+            g = ctx.geometry
+            U = torch.empty((2, H, W), device="cuda")
+            PW = torch.empty((4, H, W), device="cuda")
+            B = torch.empty((1,), device="cuda")
+            S, P = ctx.step(clips[i][t], clips[i][t - 1] if t else None, unary_out=U, pairwise_out=PW, beta_out=B)
+            torch.cuda.synchronize()
+            pS, pU, pPW, pB = b.output_pointers(i)
+            assert torch.equal(_copy_from(pS, S), S), (t, i, "S")
+            assert torch.equal(_copy_from(pU, U), U), (t, i, "unary")
+            assert torch.equal(_copy_from(pPW, PW), PW), (t, i, "pairwise")
+            assert torch.equal(_copy_from(pB, B), B), (t, i, "beta")
+    for c in ctxs:
+        c.close()
+    b.close()
+
+
+def test_autotuner_keeps_results_identical():
+    print("\n[case] autotuned batch and context give the same priors as untuned ones", flush=True)
+    torch = _torch()
+    from paper_1008_0502_amd.api import Batch, Context, Params
+    sizes = [(240, 320), (120, 160), (240, 320)]
+    T = 3
+    clips = [torch.from_numpy(synth.Clip(synth.config1_spec(H=H, W=W, T=T, seed=70 + i)).stack()[0]).cuda()
+             for i, (H, W) in enumerate(sizes)]
+    pp = Params()
+    ref = []
+    for (H, W), c in zip(sizes, clips):
+        ctx = Context(H, W, pp)
+        ref.append(ctx.run_clip(c)["pi"].cpu().numpy())
+        ctx.close()
+    b = Batch(sizes, pp)
+    rep = b.autotune(Batch.pointer_table([c[0] for c in clips]), steps=2)
+    print(rep, flush=True)
+    assert "chosen" in rep
+    outs = [torch.empty((T, H, W), device="cuda") for (H, W) in sizes]
+    for t in range(T):
+        b.step(Batch.pointer_table([c[t] for c in clips]), Batch.pointer_table([o[t] for o in outs]))
+    torch.cuda.synchronize()
+    for i in range(len(sizes)):
+        assert np.array_equal(outs[i].cpu().numpy(), ref[i]), i
+    b.close()
+    ctx = Context(240, 320, pp)
+    print(ctx.autotune(clips[0][1], clips[0][0], steps=3), flush=True)
+    assert np.array_equal(ctx.run_clip(clips[0])["pi"].cpu().numpy(), ref[0])
+    ctx.close()

@@ -247,3 +247,35 @@ def test_api_errors_on_gpu():
     with pytest.raises(SalpriorError):
         tctx.saliency_backward(torch.zeros((1, 32, 40), device="cuda"))  # wrong T
     tctx.close()
+
+
+def test_fused_step_equals_separate_calls():
+    banner("sp_step (fused whole path) vs saliency_forward + prior_update + mrf_weights: bitwise")
+    torch = _torch()
+    from paper_1008_0502_amd.api import Context
+    frames, _ = synth.Clip(synth.config2_spec(H=240, W=320, T=5, seed=21)).stack()
+    fr = torch.from_numpy(frames).cuda()
+    pp = params(depth=6, centers=(2, 3), deltas=(3, 4))
+    a = Context(240, 320, pp)
+    ref = a.run_clip(fr, with_mrf=True, want_C=True)
+    b = Context(240, 320, pp)
+    g = b.geometry
+    S = torch.empty((5, g.Hc, g.Wc), device="cuda")
+    C = torch.empty((5, 8, g.Hc, g.Wc), device="cuda")
+    P = torch.empty((5, 240, 320), device="cuda")
+    U = torch.empty((5, 2, 240, 320), device="cuda")
+    PW = torch.empty((5, 4, 240, 320), device="cuda")
+    B = torch.empty((5, 1), device="cuda")
+    for t in range(5):
+        b.step(fr[t], fr[t - 1] if t else None, S_out=S[t], C_out=C[t], prior_out=P[t], unary_out=U[t],
+               pairwise_out=PW[t], beta_out=B[t])
+    torch.cuda.synchronize()
+    for key, got in (("S", S), ("C", C), ("pi", P), ("unary", U), ("pairwise", PW), ("beta", B)):
+        assert torch.equal(got, ref[key]), key
+    # without the MRF outputs the prior is unchanged
+    b.reset()
+    for t in range(5):
+        b.step(fr[t], fr[t - 1] if t else None, S_out=S[t], prior_out=P[t])
+    assert torch.equal(P, ref["pi"])
+    a.close()
+    b.close()
