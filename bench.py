@@ -137,10 +137,8 @@ def pmc_summarize(fetch_db: str, write_db: str) -> None:
     def per_kernel(db, counter):
         con = sqlite3.connect(db)
         cur = con.cursor()
-        rows = cur.execute(
-            "select k.name, p.value from rocpd_pmc_event p join rocpd_kernel_dispatch d on p.event_id = d.event_id "
-            "join rocpd_info_kernel_symbol k on d.kernel_id = k.id join rocpd_info_pmc i on p.pmc_id = i.id "
-            "where i.name = ?", (counter,)).fetchall()
+        rows = cur.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                           (counter,)).fetchall()
         out = {}
         for name, val in rows:
             out.setdefault(name, []).append(float(val))
@@ -149,13 +147,14 @@ def pmc_summarize(fetch_db: str, write_db: str) -> None:
     fetch = per_kernel(fetch_db, "FETCH_SIZE")
     write = per_kernel(write_db, "WRITE_SIZE")
     copy_bytes = 64 * 1024 * 1024 * 4
-    cal_f = [v for n, vs in fetch.items() if "copy" in n.lower() or "elementwise" in n.lower() for v in vs]
-    cal_w = [v for n, vs in write.items() if "copy" in n.lower() or "elementwise" in n.lower() for v in vs]
+    cal_f = [v for n, vs in fetch.items() if "copybuffer" in n.lower() for v in vs]
+    cal_w = [v for n, vs in write.items() if "copybuffer" in n.lower() for v in vs]
     kf = copy_bytes / (max(cal_f) * 1024.0)
     kw = copy_bytes / (max(cal_w) * 1024.0)
     kernels = {}
-    names = {"k_rgb": "k_rgb", "k_feat": "k_feat", "k_pyr<false>": "k_pyr", "k_pyr<true>": "k_pyr_tail",
-             "k_csstats": "k_csstats", "k_csapply": "k_csapply", "k_consp": "k_consp", "k_kalman": "k_kalman"}
+    names = {"k_rgb": "k_rgb", "k_feat<16,16>": "k_feat", "k_pyr<false>": "k_pyr", "k_pyr<true>": "k_pyr_tail",
+             "k_csstats": "k_csstats", "k_csfinal": "k_csfinal", "k_csapply": "k_csapply", "k_consp": "k_consp",
+             "k_kalman": "k_kalman"}
     for raw in set(fetch) | set(write):
         short = re.sub(r"\(anonymous namespace\)::", "", raw)
         short = re.sub(r"\(.*\)$", "", short).replace("void ", "").replace(" ", "")
@@ -170,7 +169,7 @@ def pmc_summarize(fetch_db: str, write_db: str) -> None:
     out = {"source_hash": source_hash(), "workload": "batched step, 16 streams of 640x480, MRF on",
            "calibration": {"copy_bytes": copy_bytes, "fetch_scale": kf, "write_scale": kw},
            "kernels": kernels}
-    path = os.path.join(ROOT, "profiles", "traffic_batched16_640x480.json")
+    path = os.environ.get("SALPRIOR_TRAFFIC_OUT", os.path.join(ROOT, "profiles", "traffic_batched16_640x480.json"))
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
