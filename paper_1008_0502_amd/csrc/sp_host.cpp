@@ -253,10 +253,21 @@ struct Bump {
 };
 
 // Pixels per colour-statistics workgroup: 1024 * G with at most 256 workgroups.
-int rgb_chunk(const Geo& g) {
-  const long long px = (long long)g.H * g.W;
-  const long long G = std::max<long long>(1, (px + 256 * 1024 - 1) / (256 * 1024));
-  return (int)(1024 * G);
+// Colour-statistics tiles: rows x columns, at most SP_RGB_TR x SP_RGB_TC, with the
+// row count lowered (down to 2) while a frame would give fewer than 192 workgroups.
+struct RgbTiling {
+  int tr, tc, nrt, nct;
+  int count() const { return nrt * nct; }
+};
+
+RgbTiling rgb_tiling(const Geo& g) {
+  RgbTiling t;
+  t.nct = (g.W + SP_RGB_TC - 1) / SP_RGB_TC;
+  t.tc = (g.W + t.nct - 1) / t.nct;
+  t.tr = SP_RGB_TR;
+  while (t.tr > 2 && ((g.H + t.tr - 1) / t.tr) * t.nct < 192) t.tr /= 2;
+  t.nrt = (g.H + t.tr - 1) / t.tr;
+  return t;
 }
 
 void fill_taps(StreamDesc& sd, const sp_params& p) {
@@ -326,7 +337,7 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
   for (int l = 1; l <= g.top; ++l)
     if (g.used & (1u << l)) sd.gab[l] = bump.take<float>((size_t)4 * g.Hl[l] * g.Wl[l]);
   if (rgb_parts) {
-    sd.n_rgb = (int)((g.H * (long long)g.W + rgb_chunk(g) - 1) / rgb_chunk(g));
+    sd.n_rgb = rgb_tiling(g).count();
     sd.rgb_max_part = bump.take<uint32_t>(sd.n_rgb);
     sd.rgb_d2_part = bump.take<unsigned long long>(sd.n_rgb);
   }
@@ -334,15 +345,18 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
   sd.fbar = bump.take<float>((size_t)SP_NCH * g.Hl[g.c_max] * g.Wl[g.c_max]);
   sd.fbar_part = bump.take<float>((size_t)3 * SP_NCH * sd.n_cmax_tiles);
   sd.s_part = bump.take<float>((size_t)2 * sd.n_cmax_tiles);
+  sd.cs_np = bump.take<float>((size_t)4 * SP_NCH * std::max(1, g.n_pairs));
 }
 
 void rgb_jobs(std::vector<Job>& v, int s, const StreamDesc& sd, const Geo& g) {
-  const int chunk = rgb_chunk(g);
-  const int px = sd.H * sd.W;
-  for (int i = 0; i < sd.n_rgb; ++i) {
-    const int p0 = i * chunk;
-    v.push_back(Job{s, i, p0, 0, std::min(chunk, px - p0), 1, i, JOB_RGB});
-  }
+  const RgbTiling t = rgb_tiling(g);
+  if (t.count() != sd.n_rgb) throw std::logic_error("colour tiling and partial buffer disagree");
+  for (int i = 0; i < t.nrt; ++i)
+    for (int j = 0; j < t.nct; ++j) {
+      const int y0 = i * t.tr, x0 = j * t.tc;
+      v.push_back(Job{s, i * t.nct + j, y0, x0, std::min(t.tr, g.H - y0), std::min(t.tc, g.W - x0),
+                      i * t.nct + j, JOB_RGB});
+    }
 }
 
 // ---------------------------------------------------------------- job tables
@@ -561,6 +575,9 @@ void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& 
     if (has) add_tiles(v, s, c, g.Hl[c], g.Wl[c]);
   }
   push(JOB_CSSTATS, v);
+  v.clear();
+  for (int p = 0; p < g.n_pairs; ++p) v.push_back(Job{s, p, 0, 0, 1, 1, p, JOB_CSFINAL});
+  push(JOB_CSFINAL, v);
   v.clear();
   for (int k = 0; k < SP_NCH; ++k) add_tiles(v, s, k, g.Hl[g.c_max], g.Wl[g.c_max]);
   push(JOB_CSAPPLY, v);
@@ -1184,7 +1201,8 @@ const char* sp_kernel_name(int32_t k) {
   // for DOWN/GABOR stages, k_pyr tail for the final stage with tail jobs)
   static const char* names[SP_NKINDS] = {"k_rgb", "k_feat", "k_pyr", "k_pyr", "k_csstats", "k_csapply",
                                          "k_consp", "k_smax", "k_kalman", "k_mrf", "k_bwd_nu", "k_bwd_gs",
-                                         "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_bwd_final"};
+                                         "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_csfinal",
+                                         "k_bwd_final"};
   return (k >= 0 && k < SP_NKINDS) ? names[k] : "";
 }
 
@@ -1232,11 +1250,12 @@ int batch_build_tables(sp_batch* b) {
   }
   b->jobs.host.clear();
   b->phases.clear();
-  std::vector<Job> rgb, feat, fin, css, csa, cons, kal;
+  std::vector<Job> rgb, feat, fin, css, csf, csa, cons, kal;
   std::vector<std::vector<Job>> mids;
   bool any_big = false;
   for (int i = 0; i < n; ++i) {
     const Geo& g = b->geo[i];
+    for (int p = 0; p < g.n_pairs; ++p) csf.push_back(Job{i, p, 0, 0, 1, 1, p, JOB_CSFINAL});
     rgb_jobs(rgb, i, b->h_sd[i], g);
     add_tiles(feat, i, 1, g.Hl[1], g.Wl[1], JOB_FEAT);
     std::vector<std::vector<Job>> mid;
@@ -1270,6 +1289,7 @@ int batch_build_tables(sp_batch* b) {
     if (!d.empty()) b->phases.push_back(b->jobs.add(JOB_DOWN, 0, order(d), n));
   if (!fin.empty()) b->phases.push_back(b->jobs.add(any_big ? JOB_TAIL : JOB_DOWN, 0, fin, n));
   b->phases.push_back(b->jobs.add(JOB_CSSTATS, 0, order(css), n));
+  b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, n));
   b->phases.push_back(b->jobs.add(JOB_CSAPPLY, 0, order(csa), n));
   {
     size_t lds = 0;

@@ -13,13 +13,15 @@
 #define SP_MAXR 8           // largest Gabor radius
 #define SP_NCH 8            // channels: I, RG, BY, O0, O45, O90, O135, M
 #define SP_BLOCK 256        // threads per workgroup of every tiled kernel (4 wave64)
+#define SP_RGB_TR 8         // most rows of a colour-statistics tile
+#define SP_RGB_TC 512       // most columns of a colour-statistics tile
 
 // Base channels are stored per level as [4][H_l][W_l] in the order I, RG, BY, M;
 // orientation maps per used level as [4][H_l][W_l] in the order O0, O45, O90, O135.
 enum { BASE_I = 0, BASE_RG = 1, BASE_BY = 2, BASE_M = 3 };
 
 enum JobKind : int32_t {
-  JOB_RGB = 0,      // colour max (+ colour-difference sums) partials over a band of rows
+  JOB_RGB = 0,      // colour max (+ colour-difference sums) partials over a tile of pixels
   JOB_FEAT,         // level-0 features -> level 1 (blur + decimate)
   JOB_DOWN,         // level a -> level a+1 for the 4 base channels
   JOB_GABOR,        // 4 orientation maps of level a
@@ -35,6 +37,7 @@ enum JobKind : int32_t {
   JOB_LOSS,         // masked MSE partials
   JOB_TAIL,         // one channel: every level above a small source level, in LDS
   JOB_TAILGAB,      // Gabor maps of one level above the tail source (intensity chain in LDS)
+  JOB_CSFINAL,      // pair a: N(.) parameters of its 8 centre-surround maps from the partials
   JOB_BWD_FINAL,    // reduction of the adjoint partials (timing id only)
   JOB_NKINDS
 };
@@ -72,6 +75,7 @@ struct StreamDesc {
   float* fbar;                   // [8][Hc][Wc]
   float* fbar_part;              // [8][n_cmax_tiles] triples
   float* s_part;                 // [n_cmax_tiles] pairs (max, index as float bits)
+  float* cs_np;                  // [n_pairs][8][4] N(.) parameters of the centre-surround maps
   float w[SP_NCH];
   float eps, flat_tol, lam, potts;
   float c45;                     // DC weight of the diagonal Gabor kernels

@@ -191,7 +191,21 @@ __device__ NParams make_nparams(float mn, float mx, double sb, int nb, float fla
 __device__ NParams nparams_wave(const float* parts, int n, int nb, float flat_tol) {
   float mn = INFINITY, mx = -INFINITY;
   double sb = 0.0;
-  for (int i = lane_id(); i < n; i += 64) {
+  int i = lane_id();
+  for (; i + 192 < n; i += 256) {   // four partials per lane in flight
+    float a[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) a[u][f] = parts[3 * (i + 64 * u) + f];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      mn = fminf(mn, a[u][0]);
+      mx = fmaxf(mx, a[u][1]);
+      sb += (double)a[u][2];
+    }
+  }
+  for (; i < n; i += 64) {
     mn = fminf(mn, parts[3 * i]);
     mx = fmaxf(mx, parts[3 * i + 1]);
     sb += (double)parts[3 * i + 2];
@@ -200,6 +214,22 @@ __device__ NParams nparams_wave(const float* parts, int n, int nb, float flat_to
   mx = wave_reduce<OpMax>(mx);
   sb = wave_sum_d(sb);
   return make_nparams(mn, mx, sb, nb, flat_tol);
+}
+
+__device__ __forceinline__ void store_np(float* dst, const NParams& p) {
+  dst[0] = p.mn;
+  dst[1] = p.inv;
+  dst[2] = p.scale;
+  dst[3] = p.flat ? 1.f : 0.f;
+}
+
+__device__ __forceinline__ NParams load_np(const float* src) {
+  NParams p;
+  p.mn = src[0];
+  p.inv = src[1];
+  p.scale = src[2];
+  p.flat = src[3] != 0.f;
+  return p;
 }
 
 __device__ __forceinline__ float napply(const NParams& p, float v) {
@@ -237,72 +267,81 @@ __device__ __forceinline__ bool on_border(int y, int x, int H, int W, int b) {
 #define IOF(field) (ios ? ios[J.stream].field : io0.field)
 
 // ---------------------------------------------------------------- colour statistics
-// Largest R+G+B over a contiguous run of pixels; optionally the sum of squared colour
-// differences over the 8-neighbour pairs (E, S, SE, SW) whose first pixel is in the run.
-// Four pixels (12 bytes) per thread and iteration, loaded as three dwords when aligned.
+__device__ __forceinline__ uint32_t rgb_d2i(uint32_t a, uint32_t b) {
+  const int dr = (int)(a & 0xff) - (int)(b & 0xff);
+  const int dg = (int)((a >> 8) & 0xff) - (int)((b >> 8) & 0xff);
+  const int db = (int)(a >> 16) - (int)(b >> 16);
+  return (uint32_t)(dr * dr + dg * dg + db * db);
+}
+
+// Largest R+G+B over a tile of th x tw pixels; with want_d2 also the sum of squared
+// colour differences over the 8-neighbour pairs (E, S, SE, SW) whose first pixel is in
+// the tile, so that every unordered pair of the frame is counted once.  The tile and,
+// for the differences, its left/right neighbour columns and the row below are staged
+// in LDS as packed colours (R | G << 8 | B << 16), read from global memory in groups of
+// four pixels (three aligned dwords) where the frame allows it.
 __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
                                                   const StepIO* __restrict__ ios, StepIO io0, int want_d2) {
+  constexpr int LW = SP_RGB_TC + 8;
+  __shared__ uint32_t Pk[SP_RGB_TR + 1][LW];
   __shared__ unsigned long long sh[SP_BLOCK];
   __shared__ uint32_t shm[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const uint8_t* __restrict__ rgb = IOF(rgb);
   const int W = sd.W, H = sd.H;
-  const int p0 = J.y0, np = J.th;
-  const bool aligned = ((reinterpret_cast<uintptr_t>(rgb) & 3) == 0) && ((p0 & 3) == 0);
-  uint32_t mx = 0;
-  unsigned long long d2 = 0;
-  for (int g = threadIdx.x; 4 * g < np; g += SP_BLOCK) {
-    const int p = p0 + 4 * g;
-    const int cnt = min(4, np - 4 * g);
-    uint32_t b[12];
-    if (aligned && cnt == 4) {
-      const uint32_t* w = reinterpret_cast<const uint32_t*>(rgb + (size_t)3 * p);
+  const int y0 = J.y0, x0 = J.x0, th = J.th, tw = J.tw;
+  const long long HW = (long long)H * W;
+  const bool al = (reinterpret_cast<uintptr_t>(rgb) & 3) == 0;
+  const int nr = th + ((want_d2 && y0 + th < H) ? 1 : 0);
+  const int xs = want_d2 ? max(x0 - 1, 0) : x0;              // first staged column
+  const int xe = want_d2 ? min(x0 + tw, W - 1) : x0 + tw - 1;  // last staged column
+  // a staged row starts at the 4-pixel group holding (y, xs): at most 3 leading pixels
+  const int NG = (xe - xs + 3) / 4 + 1;
+  for (int i = threadIdx.x; i < nr * NG; i += SP_BLOCK) {
+    const int r = i / NG, gi = i - r * NG;
+    const long long rowp = (long long)(y0 + r) * W;
+    const long long q = ((rowp + xs) & ~3LL) + 4 * gi;
+    if (q > rowp + xe) continue;
+    uint32_t c[4];
+    if (al && q + 3 < HW) {
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(rgb + 3 * q);
       const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        b[i] = (w0 >> (8 * i)) & 0xff;
-        b[4 + i] = (w1 >> (8 * i)) & 0xff;
-        b[8 + i] = (w2 >> (8 * i)) & 0xff;
-      }
+      c[0] = w0 & 0xffffffu;
+      c[1] = (w0 >> 24) | ((w1 & 0xffffu) << 8);
+      c[2] = (w1 >> 16) | ((w2 & 0xffu) << 16);
+      c[3] = w2 >> 8;
     } else {
 #pragma unroll
-      for (int i = 0; i < 12; ++i) b[i] = (i < 3 * cnt) ? rgb[(size_t)3 * p + i] : 0u;
+      for (int j = 0; j < 4; ++j) {
+        const long long o = 3 * (q + j);
+        c[j] = (q + j < HW) ? ((uint32_t)rgb[o] | ((uint32_t)rgb[o + 1] << 8) | ((uint32_t)rgb[o + 2] << 16)) : 0u;
+      }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (j < cnt) mx = max(mx, b[3 * j] + b[3 * j + 1] + b[3 * j + 2]);
+    for (int j = 0; j < 4; ++j) Pk[r][4 * gi + j] = c[j];
+  }
+  __syncthreads();
+  uint32_t mx = 0, d2 = 0;
+  for (int i = threadIdx.x; i < th * tw; i += SP_BLOCK) {
+    const int r = i / tw, x = x0 + (i - r * tw), y = y0 + r;
+    const int k0 = x - xs + (int)(((long long)y * W + xs) & 3);
+    const uint32_t a = Pk[r][k0];
+    mx = max(mx, (a & 0xffu) + ((a >> 8) & 0xffu) + (a >> 16));
     if (want_d2) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (j >= cnt) break;
-        const int q = p + j, y = q / W, x = q - y * W;
-        const int r = (int)b[3 * j], gg = (int)b[3 * j + 1], bb = (int)b[3 * j + 2];
-        if (x + 1 < W) {
-          const uint8_t* e = rgb + (size_t)3 * (q + 1);
-          const int dr = r - e[0], dg = gg - e[1], db = bb - e[2];
-          d2 += (unsigned)(dr * dr + dg * dg + db * db);
-        }
-        if (y + 1 < H) {
-          const uint8_t* e = rgb + (size_t)3 * (q + W);
-          int dr = r - e[0], dg = gg - e[1], db = bb - e[2];
-          d2 += (unsigned)(dr * dr + dg * dg + db * db);
-          if (x + 1 < W) {
-            dr = r - e[3]; dg = gg - e[4]; db = bb - e[5];
-            d2 += (unsigned)(dr * dr + dg * dg + db * db);
-          }
-          if (x > 0) {
-            dr = r - e[-3]; dg = gg - e[-2]; db = bb - e[-1];
-            d2 += (unsigned)(dr * dr + dg * dg + db * db);
-          }
-        }
+      if (x + 1 < W) d2 += rgb_d2i(a, Pk[r][k0 + 1]);
+      if (y + 1 < H) {
+        const int k1 = x - xs + (int)(((long long)(y + 1) * W + xs) & 3);
+        d2 += rgb_d2i(a, Pk[r + 1][k1]);
+        if (x + 1 < W) d2 += rgb_d2i(a, Pk[r + 1][k1 + 1]);
+        if (x > 0) d2 += rgb_d2i(a, Pk[r + 1][k1 - 1]);
       }
     }
   }
   mx = wave_max_u(mx);
   if (lane_id() == 0) shm[wave_id()] = mx;
-  const unsigned long long tot = want_d2 ? block_sum_u64(d2, sh) : 0ull;
+  const unsigned long long tot = want_d2 ? block_sum_u64((unsigned long long)d2, sh) : 0ull;
   __syncthreads();
   if (threadIdx.x == 0) {
     sd.rgb_max_part[J.a] = max(max(shm[0], shm[1]), max(shm[2], shm[3]));
@@ -332,6 +371,14 @@ __device__ __forceinline__ float beta_from_parts(const StreamDesc& sd, unsigned 
   return (mean > 0.0) ? (float)(1.0 / (2.0 * mean)) : 0.f;
 }
 
+// One contrast-sensitive capacity: Potts constant plus the colour term over the
+// neighbour's distance (1 or sqrt 2).  Shared by every kernel that writes capacities so
+// the fused and the separate MRF calls agree bit for bit.
+__device__ __forceinline__ float pair_cap(float potts, float lam, float beta, float d2, bool diag) {
+  const float w = lam * expf(-beta * d2);
+  return potts + (diag ? w * 0.70710678118654752f : w);
+}
+
 // Contrast-sensitive capacities of pixel (y, x) towards its E, S, SE, SW neighbours.
 __device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, int y, int x, float beta, float lam,
                                             float potts, float* pairw, size_t plane) {
@@ -339,7 +386,6 @@ __device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, in
   const uint8_t* p = rgb + o * 3;
   const int r = p[0], g = p[1], b = p[2];
   const int dys[4] = {0, 1, 1, 1}, dxs[4] = {1, 0, 1, -1};
-  const float dist[4] = {1.f, 1.f, 1.41421356237f, 1.41421356237f};
 #pragma unroll
   for (int dd = 0; dd < 4; ++dd) {
     const int y2 = y + dys[dd], x2 = x + dxs[dd];
@@ -348,15 +394,24 @@ __device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, in
       const uint8_t* q = rgb + ((size_t)y2 * W + x2) * 3;
       const int dr = r - q[0], dg = g - q[1], db = b - q[2];
       const float d2 = (float)(dr * dr + dg * dg + db * db);
-      wv = potts + lam * expf(-beta * d2) / dist[dd];
+      wv = pair_cap(potts, lam, beta, d2, dd >= 2);
     }
     pairw[dd * plane + o] = wv;
   }
 }
 
+// Squared colour distance of two pixels packed as R | G << 8 | B << 16.
+__device__ __forceinline__ float rgb_d2(uint32_t a, uint32_t b) {
+  const int dr = (int)(a & 0xff) - (int)(b & 0xff);
+  const int dg = (int)((a >> 8) & 0xff) - (int)((b >> 8) & 0xff);
+  const int db = (int)(a >> 16) - (int)(b >> 16);
+  return (float)(dr * dr + dg * dg + db * db);
+}
+
 // Level-0 features of the region a level-1 tile needs, then one blur + decimation.
 // With io.pairwise set it also writes the pairwise capacities of the tile's level-0
-// pixels (rows 2*y0 .. 2*(y0+th)-1).
+// pixels (rows 2*y0 .. 2*(y0+th)-1) from the same staged region: every E, S, SE, SW
+// neighbour of those pixels lies inside it.
 template <int TH, int TW>
 __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
                                                    const StreamDesc* __restrict__ sds,
@@ -366,6 +421,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
   __shared__ float Hb[4][RH][TW];
   __shared__ uint32_t shm[4];
   __shared__ unsigned long long sh[SP_BLOCK];
+  static_assert(4 * RH * TW >= RH * RW, "packed colours fit in the row-blur buffer");
+  uint32_t* Pk = reinterpret_cast<uint32_t*>(&Hb[0][0][0]);  // packed colours until the blur
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const uint8_t* __restrict__ rgb = IOF(rgb);
@@ -407,6 +464,29 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
     F[1][ry][rx] = rg;
     F[2][ry][rx] = by;
     F[3][ry][rx] = M;
+    if (pairw) Pk[i] = (uint32_t)R8 | ((uint32_t)G8 << 8) | ((uint32_t)B8 << 16);
+  }
+  if (pairw) {
+    // beta_from_parts synchronises the block before and after its reduction
+    const float beta = beta_from_parts(sd, sh);
+    const int ylo = 2 * J.y0, yhi = min(H, 2 * (J.y0 + J.th));
+    const int xlo = 2 * J.x0, xhi = min(W, 2 * (J.x0 + J.tw));
+    const int cw = xhi - xlo, n = (yhi - ylo) * cw;
+    const size_t plane = (size_t)H * W;
+    const float lam = sd.lam, potts = sd.potts;
+    for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
+      const int yy = i / cw, xx = i - yy * cw;
+      const int y = ylo + yy, x = xlo + xx;
+      const int r = (y - Y0) * RW + (x - X0);
+      const uint32_t c0 = Pk[r];
+      const size_t o = (size_t)y * W + x;
+      const bool e = x + 1 < W, s = y + 1 < H;
+      pairw[o] = e ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + 1]), false) : 0.f;
+      pairw[plane + o] = s ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW]), false) : 0.f;
+      pairw[2 * plane + o] = (s && e) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW + 1]), true) : 0.f;
+      pairw[3 * plane + o] = (s && x > 0) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW - 1]), true) : 0.f;
+    }
+    if (J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) IOF(beta_out)[0] = beta;
   }
   __syncthreads();
   down_region<TH, TW, RH, RW>(F, Hb, 4);
@@ -425,17 +505,6 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
         dst[c * plane + (size_t)y * W1 + x] = v;
       }
     }
-  }
-  if (pairw) {
-    const float beta = beta_from_parts(sd, sh);
-    const int ylo = 2 * J.y0, yhi = min(H, 2 * (J.y0 + J.th));
-    const int xlo = 2 * J.x0, xhi = min(W, 2 * (J.x0 + J.tw));
-    const int cw = xhi - xlo, n = (yhi - ylo) * cw;
-    for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-      const int yy = i / cw, xx = i - yy * cw;
-      pairwise_at(rgb, H, W, ylo + yy, xlo + xx, beta, sd.lam, sd.potts, pairw, (size_t)H * W);
-    }
-    if (J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) IOF(beta_out)[0] = beta;
   }
 }
 
@@ -768,6 +837,19 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
   }
 }
 
+// N(.) parameters of the 8 maps of one pair (job a = pair), two maps per wavefront.
+__global__ __launch_bounds__(SP_BLOCK) void k_csfinal(const Job* __restrict__ jobs,
+                                                      const StreamDesc* __restrict__ sds,
+                                                      const StepIO* __restrict__ ios, StepIO io0) {
+  const Job J = jobs[blockIdx.x];
+  const StreamDesc& sd = sds[J.stream];
+  const int p = J.a, c = sd.pc[p], nt = sd.ntiles_lvl[c], nb = nblocks8(sd.Hl[c], sd.Wl[c]);
+  for (int k = wave_id(); k < SP_NCH; k += 4) {
+    const NParams q = nparams_wave(sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)k * nt), nt, nb, sd.flat_tol);
+    if (lane_id() == 0) store_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k), q);
+  }
+}
+
 // ---------------------------------------------------------------- across-scale sum
 // F-bar_k on a 16x16 tile of c_max = sum over pairs of REDUCE^(c_max - c)(N(F(c, s))).
 // Every input is staged in (dynamically sized) LDS in one round trip; N(F) of all pairs
@@ -838,13 +920,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
   float* X1 = dyn + L.x1;
   float* X2 = dyn + L.x2;
   // ---- one round trip: N parameters (one wavefront per pair), centre regions, footprints
-  for (int p = wave_id(); p < sd.n_pairs; p += 4) {
-    const int c = sd.pc[p];
-    const int nt = sd.ntiles_lvl[c];
-    const float* parts = sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)k * nt);
-    const NParams q = nparams_wave(parts, nt, nblocks8(sd.Hl[c], sd.Wl[c]), sd.flat_tol);
-    if (lane_id() == 0) np[p] = q;
-  }
+  for (int p = threadIdx.x; p < sd.n_pairs; p += SP_BLOCK) np[p] = load_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k));
   auto stage = [&](int r, Range rr, Range cc, float* X) {
     const int c = cm - r, Wc = sd.Wl[c];
     const float* Xc = chan_ptr(sd, ckpt, k, c);
@@ -1431,6 +1507,7 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
     case JOB_GABOR: hipLaunchKernelGGL(k_pyr<false>, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_TAIL: hipLaunchKernelGGL(k_pyr<true>, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSSTATS: hipLaunchKernelGGL(k_csstats, g, b, 0, st, jobs, sds, ios, io); break;
+    case JOB_CSFINAL: hipLaunchKernelGGL(k_csfinal, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSAPPLY: hipLaunchKernelGGL(k_csapply, g, b, lds, st, jobs, sds, ios, io); break;
     case JOB_CONSP: hipLaunchKernelGGL(k_consp, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_SMAX: hipLaunchKernelGGL(k_smax, g, b, 0, st, jobs, sds, ios, io); break;
