@@ -120,16 +120,40 @@ __device__ double block_sum_d(double v, double* sh256) {
   return r;
 }
 
+// Exact 64-bit sum over the workgroup: butterfly within each wavefront, then the four
+// wavefront sums (two barriers).
 __device__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh256) {
-  sh256[threadIdx.x] = v;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane_id() == 0) sh256[wave_id()] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh256[threadIdx.x] += sh256[threadIdx.x + s];
-    __syncthreads();
-  }
-  const unsigned long long r = sh256[0];
+  const unsigned long long r = (sh256[0] + sh256[1]) + (sh256[2] + sh256[3]);
   __syncthreads();
   return r;
+}
+
+// ---------------------------------------------------------------- LDS staging
+// Direct global -> LDS loads (global_load_lds_dword): each active lane fetches one float
+// into LDS at the wavefront's uniform base + 4 * lane, without a VGPR round trip and
+// without a wait per element, so a staging loop keeps all its loads in flight.  A loop
+// over a flat index i = threadIdx.x + k * SP_BLOCK passes the lane's own destination
+// (region + i); since i - lane is the same for the whole wavefront, the base is
+// region + i - lane.  The copy is complete after lds_wait() and a barrier.
+typedef __attribute__((address_space(3))) void lds_void;
+__device__ __forceinline__ void lds_load(float* dst_of_lane, const float* src) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void*)(dst_of_lane - lane_id()), 4, 0, 0);
+}
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Global-memory views of device pointers.  Pointers read from the stream and step
+// descriptors are generic to the compiler, which then emits flat memory instructions;
+// those count against the LDS counter as well, so each LDS wait would also wait for
+// every outstanding global store.  Cast to the global address space they become
+// global_load / global_store.
+template <class T>
+using gp = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gp<T> G(T* p) {
+  return (gp<T>)p;
 }
 
 // ---------------------------------------------------------------- stream helpers
@@ -158,7 +182,8 @@ __device__ __forceinline__ Tap bilinear_tap(int y, int d, int n) {
   return t;
 }
 
-__device__ __forceinline__ float bilinear(const float* X, int Ws, const Tap& ty, const Tap& tx) {
+template <class Ptr>
+__device__ __forceinline__ float bilinear(Ptr X, int Ws, const Tap& ty, const Tap& tx) {
   const float a = X[(size_t)ty.i0 * Ws + tx.i0], b = X[(size_t)ty.i0 * Ws + tx.i1];
   const float c = X[(size_t)ty.i1 * Ws + tx.i0], e = X[(size_t)ty.i1 * Ws + tx.i1];
   const float top = (1.f - tx.w) * a + tx.w * b;
@@ -289,11 +314,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
   __shared__ uint32_t shm[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
-  const uint8_t* __restrict__ rgb = IOF(rgb);
+  const gp<const uint8_t> rgb = G(IOF(rgb));
   const int W = sd.W, H = sd.H;
   const int y0 = J.y0, x0 = J.x0, th = J.th, tw = J.tw;
   const long long HW = (long long)H * W;
-  const bool al = (reinterpret_cast<uintptr_t>(rgb) & 3) == 0;
+  const bool al = (reinterpret_cast<uintptr_t>(IOF(rgb)) & 3) == 0;
   const int nr = th + ((want_d2 && y0 + th < H) ? 1 : 0);
   const int xs = want_d2 ? max(x0 - 1, 0) : x0;              // first staged column
   const int xe = want_d2 ? min(x0 + tw, W - 1) : x0 + tw - 1;  // last staged column
@@ -306,7 +331,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
     if (q > rowp + xe) continue;
     uint32_t c[4];
     if (al && q + 3 < HW) {
-      const uint32_t* w = reinterpret_cast<const uint32_t*>(rgb + 3 * q);
+      const gp<const uint32_t> w = (gp<const uint32_t>)(rgb + 3 * q);
       const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
       c[0] = w0 & 0xffffffu;
       c[1] = (w0 >> 24) | ((w1 & 0xffffu) << 8);
@@ -344,8 +369,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
   const unsigned long long tot = want_d2 ? block_sum_u64((unsigned long long)d2, sh) : 0ull;
   __syncthreads();
   if (threadIdx.x == 0) {
-    sd.rgb_max_part[J.a] = max(max(shm[0], shm[1]), max(shm[2], shm[3]));
-    if (want_d2) sd.rgb_d2_part[J.a] = tot;
+    G(sd.rgb_max_part)[J.a] = max(max(shm[0], shm[1]), max(shm[2], shm[3]));
+    if (want_d2) G(sd.rgb_d2_part)[J.a] = tot;
   }
 }
 
@@ -428,7 +453,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
   const uint8_t* __restrict__ rgb = IOF(rgb);
   const uint8_t* __restrict__ prev = IOF(rgb_prev);
   float* ckpt = IOF(ckpt);
-  float* pairw = IOF(pairwise);
+  const gp<float> pairw = G(IOF(pairwise));
   uint32_t smax = 0;
   for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) smax = max(smax, sd.rgb_max_part[i]);
   smax = wave_max_u(smax);
@@ -437,34 +462,53 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
   smax = max(max(shm[0], shm[1]), max(shm[2], shm[3]));
   const int H = sd.H, W = sd.W;
   const int Y0 = 2 * J.y0 - 2, X0 = 2 * J.x0 - 2;
-  for (int i = threadIdx.x; i < RH * RW; i += SP_BLOCK) {
-    const int ry = i / RW, rx = i - ry * RW;
-    const int y = clampi(Y0 + ry, 0, H - 1), x = clampi(X0 + rx, 0, W - 1);
-    const size_t o = ((size_t)y * W + x) * 3;
-    const int R8 = rgb[o], G8 = rgb[o + 1], B8 = rgb[o + 2];
-    const int S8 = R8 + G8 + B8;
-    const float I = (float)S8 / 765.f;
-    float rg = 0.f, by = 0.f;
-    if ((uint32_t)(10 * S8) > smax) {
-      const float inv = 3.f / (float)S8;
-      const float rp = (float)R8 * inv, gp = (float)G8 * inv, bp = (float)B8 * inv;
-      const float Rc = fmaxf(0.f, rp - (gp + bp) * 0.5f);
-      const float Gc = fmaxf(0.f, gp - (rp + bp) * 0.5f);
-      const float Bc = fmaxf(0.f, bp - (rp + gp) * 0.5f);
-      const float Yc = fmaxf(0.f, fminf(rp, gp) - bp);
-      rg = Rc - Gc;
-      by = Bc - Yc;
+  // four region pixels per thread and pass: all their byte loads are issued (through
+  // global-address-space pointers, with no branch in between) before the first is used
+  constexpr int FU = 4;
+  typedef const __attribute__((address_space(1))) uint8_t* gbytes;
+  const gbytes grgb = (gbytes)rgb;
+  const gbytes gprev = (gbytes)prev;
+  for (int i0 = threadIdx.x; i0 < RH * RW; i0 += FU * SP_BLOCK) {
+    uint32_t cv[FU], pv[FU];
+    size_t o[FU];
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int i = min(i0 + u * SP_BLOCK, RH * RW - 1);
+      const int ry = i / RW, rx = i - ry * RW;
+      const int y = clampi(Y0 + ry, 0, H - 1), x = clampi(X0 + rx, 0, W - 1);
+      o[u] = ((size_t)y * W + x) * 3;
+      cv[u] = (uint32_t)grgb[o[u]] | ((uint32_t)grgb[o[u] + 1] << 8) | ((uint32_t)grgb[o[u] + 2] << 16);
     }
-    float M = 0.f;
     if (prev) {
-      const int P8 = prev[o] + prev[o + 1] + prev[o + 2];
-      M = fabsf(I - (float)P8 / 765.f);
+#pragma unroll
+      for (int u = 0; u < FU; ++u) pv[u] = (uint32_t)gprev[o[u]] + (uint32_t)gprev[o[u] + 1] + (uint32_t)gprev[o[u] + 2];
     }
-    F[0][ry][rx] = I;
-    F[1][ry][rx] = rg;
-    F[2][ry][rx] = by;
-    F[3][ry][rx] = M;
-    if (pairw) Pk[i] = (uint32_t)R8 | ((uint32_t)G8 << 8) | ((uint32_t)B8 << 16);
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int i = i0 + u * SP_BLOCK;
+      if (i >= RH * RW) break;
+      const int ry = i / RW, rx = i - ry * RW;
+      const int R8 = (int)(cv[u] & 0xff), G8 = (int)((cv[u] >> 8) & 0xff), B8 = (int)(cv[u] >> 16);
+      const int S8 = R8 + G8 + B8;
+      const float I = (float)S8 / 765.f;
+      float rg = 0.f, by = 0.f;
+      if ((uint32_t)(10 * S8) > smax) {
+        const float inv = 3.f / (float)S8;
+        const float rp = (float)R8 * inv, gp = (float)G8 * inv, bp = (float)B8 * inv;
+        const float Rc = fmaxf(0.f, rp - (gp + bp) * 0.5f);
+        const float Gc = fmaxf(0.f, gp - (rp + bp) * 0.5f);
+        const float Bc = fmaxf(0.f, bp - (rp + gp) * 0.5f);
+        const float Yc = fmaxf(0.f, fminf(rp, gp) - bp);
+        rg = Rc - Gc;
+        by = Bc - Yc;
+      }
+      const float M = prev ? fabsf(I - (float)pv[u] / 765.f) : 0.f;
+      F[0][ry][rx] = I;
+      F[1][ry][rx] = rg;
+      F[2][ry][rx] = by;
+      F[3][ry][rx] = M;
+      if (pairw) Pk[i] = cv[u];
+    }
   }
   if (pairw) {
     // beta_from_parts synchronises the block before and after its reduction
@@ -486,13 +530,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
       pairw[2 * plane + o] = (s && e) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW + 1]), true) : 0.f;
       pairw[3 * plane + o] = (s && x > 0) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW - 1]), true) : 0.f;
     }
-    if (J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) IOF(beta_out)[0] = beta;
+    if (J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) G(IOF(beta_out))[0] = beta;
   }
   __syncthreads();
   down_region<TH, TW, RH, RW>(F, Hb, 4);
   __syncthreads();
   const int H1 = sd.Hl[1], W1 = sd.Wl[1];
-  float* dst = (sd.c_min == 1 && ckpt) ? ckpt : sd.base[1];
+  const gp<float> dst = G((sd.c_min == 1 && ckpt) ? ckpt : sd.base[1]);
   const size_t plane = (size_t)H1 * W1;
   for (int i = threadIdx.x; i < TH * TW; i += SP_BLOCK) {
     const int yy = i / TW, xx = i - yy * TW;
@@ -516,8 +560,8 @@ constexpr int GAB_LDS = GRM * (GRM + 1) + 4 * GT * (GRM + 1) + 4 * (2 * SP_MAXR 
 constexpr int TAIL_LDS = SP_TAIL_SRC + SP_TAIL_ALT + SP_TAIL_HB + SP_TAIL_V + 4 * (2 * SP_MAXR + 1);
 static_assert(DOWN_LDS >= GAB_LDS, "LDS of the small pyramid kernel");
 
-__device__ __forceinline__ float* level_dst(const StreamDesc& sd, float* ckpt, int l) {
-  return (l == sd.c_min && ckpt) ? ckpt : sd.base[l];
+__device__ __forceinline__ gp<float> level_dst(const StreamDesc& sd, float* ckpt, int l) {
+  return G((l == sd.c_min && ckpt) ? ckpt : sd.base[l]);
 }
 
 // level a -> a+1 of the 4 base channels for one 16x16 tile of level a+1
@@ -532,12 +576,10 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   for (int i = threadIdx.x; i < DR * DR; i += SP_BLOCK) {
     const int ry = i / DR, rx = i - ry * DR;
     const size_t o = (size_t)clampi(Y0 + ry, 0, Hs - 1) * Ws + clampi(X0 + rx, 0, Ws - 1);
-    const float v0 = src[o], v1 = src[splane + o], v2 = src[2 * splane + o], v3 = src[3 * splane + o];
-    F[i] = v0;
-    F[DR * DR + i] = v1;
-    F[2 * DR * DR + i] = v2;
-    F[3 * DR * DR + i] = v3;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lds_load(F + c * DR * DR + i, src + c * splane + o);
   }
+  lds_wait();
   __syncthreads();
   for (int i = threadIdx.x; i < 4 * DR * DT; i += SP_BLOCK) {
     const int cr = i / DT, j = i - cr * DT;     // cr = c * DR + r
@@ -546,7 +588,7 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   }
   __syncthreads();
   const int Hd = sd.Hl[l + 1], Wd = sd.Wl[l + 1];
-  float* dst = level_dst(sd, ckpt, l + 1);
+  const gp<float> dst = level_dst(sd, ckpt, l + 1);
   const size_t plane = (size_t)Hd * Wd;
   const int yy = threadIdx.x / DT, xx = threadIdx.x % DT;
   const int y = J.y0 + yy, x = J.x0 + xx;
@@ -564,7 +606,7 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
 //   O0 = H[gm] V[g], O90 = H[g] V[gm],
 //   O45 = H[gc] V[gc] - H[gs] V[gs] - c45 H[g] V[g], O135 = same with + H[gs] V[gs].
 __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt, float* smem) {
-  float* Ir = smem;                            // [GRM][GRM+1]
+  float* Ir = smem;                            // [RR][RR] (flat, RR <= GRM)
   float* V = Ir + GRM * (GRM + 1);             // [4][GT][GRM+1]
   float* taps = V + 4 * GT * (GRM + 1);        // [4][2*SP_MAXR+1]
   const int l = J.a, R = sd.gr, n = 2 * R + 1, RR = GT + 2 * R;
@@ -575,14 +617,15 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
   for (int i = threadIdx.x; i < RR * RR; i += SP_BLOCK) {
     const int ry = i / RR, rx = i - ry * RR;
     const int y = clampi(J.y0 - R + ry, 0, Hs - 1), x = clampi(J.x0 - R + rx, 0, Ws - 1);
-    Ir[ry * (GRM + 1) + rx] = I[(size_t)y * Ws + x];
+    lds_load(Ir + i, I + (size_t)y * Ws + x);
   }
+  lds_wait();
   __syncthreads();
   for (int i = threadIdx.x; i < 4 * GT * RR; i += SP_BLOCK) {
     const int f = i / (GT * RR), rem = i - f * GT * RR, yy = rem / RR, xr = rem - yy * RR;
     const float* tp = taps + f * (2 * SP_MAXR + 1);
     float acc = 0.f;
-    for (int v = 0; v < n; ++v) acc += tp[v] * Ir[(yy + v) * (GRM + 1) + xr];
+    for (int v = 0; v < n; ++v) acc += tp[v] * Ir[(yy + v) * RR + xr];
     V[(f * GT + yy) * (GRM + 1) + xr] = acc;
   }
   __syncthreads();
@@ -607,16 +650,16 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
   }
   if (yy < J.th && xx < J.tw && y < Hs && x < Ws) {
     const size_t plane = (size_t)Hs * Ws, o = (size_t)y * Ws + x;
-    float* G = sd.gab[l];
-    G[o] = A;
-    G[plane + o] = D - E - sd.c45 * B;
-    G[2 * plane + o] = C;
-    G[3 * plane + o] = D + E - sd.c45 * B;
+    const gp<float> Go = G(sd.gab[l]);
+    Go[o] = A;
+    Go[plane + o] = D - E - sd.c45 * B;
+    Go[2 * plane + o] = C;
+    Go[3 * plane + o] = D + E - sd.c45 * B;
   }
 }
 
 // Gabor maps of a whole (small) level held in LDS.
-__device__ void gabor_lds(const float* I, int h, int w, float* V, const float* taps, int R, float c45, float* out) {
+__device__ void gabor_lds(const float* I, int h, int w, float* V, const float* taps, int R, float c45, gp<float> out) {
   const int n = h * w, nt = 2 * R + 1;
   for (int i = threadIdx.x; i < 4 * n; i += SP_BLOCK) {
     const int f = i / n, pix = i - f * n, y = pix / w, x = pix - y * w;
@@ -668,7 +711,8 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   int cH = sd.Hl[L0], cW = sd.Wl[L0];
   {
     const float* src = base_ptr(sd, ckpt, L0) + (size_t)ch * cH * cW;
-    for (int i = threadIdx.x; i < cH * cW; i += SP_BLOCK) SA[i] = src[i];
+    for (int i = threadIdx.x; i < cH * cW; i += SP_BLOCK) lds_load(SA + i, src + i);
+    lds_wait();
   }
   float* cur = SA;
   float* nxt = SB;
@@ -684,7 +728,7 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
       HB[i] = acc;
     }
     __syncthreads();
-    float* dst = gab ? nullptr : level_dst(sd, ckpt, l + 1) + (size_t)ch * nH * nW;
+    const gp<float> dst = gab ? nullptr : level_dst(sd, ckpt, l + 1) + (size_t)ch * nH * nW;
     for (int i = threadIdx.x; i < nH * nW; i += SP_BLOCK) {
       const int r = i / nW, j = i - r * nW;
       float acc = 0.f;
@@ -694,7 +738,7 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
       if (dst) dst[i] = acc;
     }
     __syncthreads();
-    if (gab && l + 1 == last) gabor_lds(nxt, nH, nW, V, taps, R, sd.c45, sd.gab[l + 1]);
+    if (gab && l + 1 == last) gabor_lds(nxt, nH, nW, V, taps, R, sd.c45, G(sd.gab[l + 1]));
     float* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -777,21 +821,20 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
   for (int i = threadIdx.x; i < CS_T * CS_T; i += SP_BLOCK) {
     const int yy = i / CS_T, xx = i - yy * CS_T;
     const size_t o = (size_t)min(J.y0 + yy, Hc - 1) * Wc + min(J.x0 + xx, Wc - 1);
-    float v[SP_NCH];
 #pragma unroll
-    for (int k = 0; k < SP_NCH; ++k) v[k] = cptr[k][o];
-#pragma unroll
-    for (int k = 0; k < SP_NCH; ++k) cen[k][i] = v[k];
+    for (int k = 0; k < SP_NCH; ++k) lds_load(&cen[k][i], cptr[k] + o);
   }
   // stage the surround footprints
   for (int q = 0; q < npc; ++q) {
     const int s = sd.ps[plist[q]], Ws = sd.Wl[s];
     const int nf = fp[q].h * fp[q].w;
+    // flat [k][nf] with row stride fp.w, so that the destination follows the loop index
     for (int i = threadIdx.x; i < SP_NCH * nf; i += SP_BLOCK) {
       const int k = i / nf, r = i - k * nf, fy = r / fp[q].w, fx = r - fy * fp[q].w;
-      sur[q][k][fy * CS_F + fx] = chan_ptr(sd, ckpt, k, s)[(size_t)(fp[q].y0 + fy) * Ws + fp[q].x0 + fx];
+      lds_load(&sur[q][0][0] + i, chan_ptr(sd, ckpt, k, s) + (size_t)(fp[q].y0 + fy) * Ws + fp[q].x0 + fx);
     }
   }
+  lds_wait();
   for (int i = threadIdx.x; i < 4 * npc * SP_NCH; i += SP_BLOCK) {
     const int ww = i / (npc * SP_NCH), m = i - ww * npc * SP_NCH;
     acc[ww][m][0] = INFINITY;
@@ -811,7 +854,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
       const Tap ty = bilinear_tap(yc, d, sd.Hl[s]), tx = bilinear_tap(xc, d, sd.Wl[s]);
 #pragma unroll
       for (int k = 0; k < SP_NCH; ++k) {
-        const float up = bilinear_lds(sur[q][k], CS_F, ty, tx, fp[q].y0, fp[q].x0);
+        const float up = bilinear_lds(&sur[q][0][0] + k * fp[q].h * fp[q].w, fp[q].w, ty, tx, fp[q].y0, fp[q].x0);
         const float F = fabsf(cen[k][(yc - J.y0) * CS_T + (xc - J.x0)] - up);
         const float bmn = wave_reduce<OpMin>(valid ? F : INFINITY);
         const float bmx = wave_reduce<OpMax>(valid ? F : -INFINITY);
@@ -830,7 +873,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
     const float mn = fminf(fminf(acc[0][i][0], acc[1][i][0]), fminf(acc[2][i][0], acc[3][i][0]));
     const float mx = fmaxf(fmaxf(acc[0][i][1], acc[1][i][1]), fmaxf(acc[2][i][1], acc[3][i][1]));
     const float sm = (acc[0][i][2] + acc[1][i][2]) + (acc[2][i][2] + acc[3][i][2]);
-    float* out = sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)k * sd.ntiles_lvl[c] + J.tid);
+    const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)k * sd.ntiles_lvl[c] + J.tid);
     out[0] = mn;
     out[1] = mx;
     out[2] = sm;
@@ -889,11 +932,19 @@ __device__ void reduce_lds(const float* in, int ldi, Range ri, Range ci, float* 
   __syncthreads();
 }
 
+// One non-flat pair of a centre level as the per-pixel loop needs it (flat maps add 0).
+struct CaPair {
+  int off, fy0, fx0, fw;   // staged footprint: LDS offset, origin on level s, row length
+  int d, Hs, Ws, fh;       // s - c and the size of level s; footprint rows
+  float mn, inv, scale, pad;
+};
+
 __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jobs,
                                                       const StreamDesc* __restrict__ sds,
                                                       const StepIO* __restrict__ ios, StepIO io0) {
   extern __shared__ float dyn[];
-  __shared__ NParams np[SP_MAXP];
+  __shared__ CaPair cpt[3][4];
+  __shared__ int ncp[3];
   __shared__ float fb[CA_T * CA_T];
   __shared__ float wacc[4][3];
   const Job J = jobs[blockIdx.x];
@@ -919,15 +970,46 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
   float* X0 = dyn + L.x0;
   float* X1 = dyn + L.x1;
   float* X2 = dyn + L.x2;
-  // ---- one round trip: N parameters (one wavefront per pair), centre regions, footprints
-  for (int p = threadIdx.x; p < sd.n_pairs; p += SP_BLOCK) np[p] = load_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k));
+  // ---- table of the non-flat pairs per centre level (footprints keep the layout's slots)
+  if (threadIdx.x == 0) {
+    int cnt[3] = {0, 0, 0};
+    int off = L.foot0;
+    for (int p = 0; p < sd.n_pairs; ++p) {
+      const int c = sd.pc[p], r = cm - c, s = sd.ps[p];
+      const NParams q = load_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k));
+      if (!q.flat && cnt[r] < 4) {
+        const Range rr = (r == 0) ? rg0 : ((r == 1) ? rg1 : rg2);
+        const Range cc = (r == 0) ? cg0 : ((r == 1) ? cg1 : cg2);
+        const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], sd.Wl[s]);
+        CaPair& P = cpt[r][cnt[r]++];
+        P.off = off;
+        P.fy0 = f.y0;
+        P.fx0 = f.x0;
+        P.fw = f.w;
+        P.fh = f.h;
+        P.d = s - c;
+        P.Hs = sd.Hl[s];
+        P.Ws = sd.Wl[s];
+        P.mn = q.mn;
+        P.inv = q.inv;
+        P.scale = q.scale;
+        P.pad = 0.f;
+      }
+      off += csapply_foot_cap(r, s - c);
+    }
+    ncp[0] = cnt[0];
+    ncp[1] = cnt[1];
+    ncp[2] = cnt[2];
+  }
+  __syncthreads();
+  // ---- one round trip: centre regions and footprints
   auto stage = [&](int r, Range rr, Range cc, float* X) {
     const int c = cm - r, Wc = sd.Wl[c];
     const float* Xc = chan_ptr(sd, ckpt, k, c);
     const int n = rr.n * cc.n;
     for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
       const int yy = i / cc.n, xx = i - yy * cc.n;
-      X[i] = Xc[(size_t)(rr.lo + yy) * Wc + cc.lo + xx];
+      lds_load(X + i, Xc + (size_t)(rr.lo + yy) * Wc + cc.lo + xx);
     }
   };
   if (has0) stage(0, rg0, cg0, X0);
@@ -936,42 +1018,31 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
   if (!has1 && has2)
     for (int i = threadIdx.x; i < rg1.n * cg1.n; i += SP_BLOCK) X1[i] = 0.f;
   for (int i = threadIdx.x; i < CA_T * CA_T; i += SP_BLOCK) fb[i] = 0.f;
-  {
-    int off = L.foot0;
-    for (int p = 0; p < sd.n_pairs; ++p) {
-      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], Ws = sd.Wl[s];
-      const Range rr = (r == 0) ? rg0 : ((r == 1) ? rg1 : rg2);
-      const Range cc = (r == 0) ? cg0 : ((r == 1) ? cg1 : cg2);
-      const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], Ws);
-      const float* Xs = chan_ptr(sd, ckpt, k, s);
-      float* dst = dyn + off;
-      for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK) {
-        const int fy = i / f.w, fx = i - fy * f.w;
-        dst[i] = Xs[(size_t)(f.y0 + fy) * Ws + f.x0 + fx];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < ncp[r]; ++q) {
+      const CaPair& P = cpt[r][q];
+      const float* Xs = chan_ptr(sd, ckpt, k, cm - r + P.d);
+      float* dst = dyn + P.off;
+      for (int i = threadIdx.x; i < P.fh * P.fw; i += SP_BLOCK) {
+        const int fy = i / P.fw, fx = i - fy * P.fw;
+        lds_load(dst + i, Xs + (size_t)(P.fy0 + fy) * P.Ws + P.fx0 + fx);
       }
-      off += csapply_foot_cap(r, s - c);
     }
-  }
+  lds_wait();
   __syncthreads();
   // ---- N(F) summed over the pairs of each centre level, in place of the centre values
   auto nsum = [&](int r, Range rr, Range cc, float* X) {
-    const int c = cm - r;
-    const int n = rr.n * cc.n;
+    const int n = rr.n * cc.n, nq = ncp[r];
     for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
       const int yy = i / cc.n, xx = i - yy * cc.n;
       const int y = rr.lo + yy, x = cc.lo + xx;
       const float xc = X[i];
       float acc = 0.f;
-      int off = L.foot0;
-      for (int p = 0; p < sd.n_pairs; ++p) {
-        const int cp = sd.pc[p], sp = sd.ps[p], d = sp - cp;
-        const int cap = csapply_foot_cap(cm - cp, d);
-        if (cp == c && !np[p].flat) {
-          const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, d, sd.Hl[sp], sd.Wl[sp]);
-          const Tap ty = bilinear_tap(y, d, sd.Hl[sp]), tx = bilinear_tap(x, d, sd.Wl[sp]);
-          acc += napply(np[p], fabsf(xc - bilinear_lds(dyn + off, f.w, ty, tx, f.y0, f.x0)));
-        }
-        off += cap;
+      for (int q = 0; q < nq; ++q) {
+        const CaPair& P = cpt[r][q];
+        const Tap ty = bilinear_tap(y, P.d, P.Hs), tx = bilinear_tap(x, P.d, P.Ws);
+        const NParams np{P.mn, P.inv, P.scale, 0};
+        acc += napply(np, fabsf(xc - bilinear_lds(dyn + P.off, P.fw, ty, tx, P.fy0, P.fx0)));
       }
       X[i] = acc;
     }
@@ -1002,7 +1073,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
     const int yy = 8 * by + (lane >> 3), xx = 8 * bx + (lane & 7);
     const bool valid = yy < J.th && xx < J.tw;
     const float v = valid ? fb[yy * CA_T + xx] : 0.f;
-    if (valid) sd.fbar[(size_t)k * Hm * Wm + (size_t)(J.y0 + yy) * Wm + J.x0 + xx] = v;
+    if (valid) G(sd.fbar)[(size_t)k * Hm * Wm + (size_t)(J.y0 + yy) * Wm + J.x0 + xx] = v;
     wmn = wave_reduce<OpMin>(valid ? v : INFINITY);
     wmx = wave_reduce<OpMax>(valid ? v : -INFINITY);
     wsum = wmx;
@@ -1014,7 +1085,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    float* out = sd.fbar_part + 3 * ((size_t)k * sd.n_cmax_tiles + J.tid);
+    const gp<float> out = G(sd.fbar_part) + 3 * ((size_t)k * sd.n_cmax_tiles + J.tid);
     out[0] = fminf(fminf(wacc[0][0], wacc[1][0]), fminf(wacc[2][0], wacc[3][0]));
     out[1] = fmaxf(fmaxf(wacc[0][1], wacc[1][1]), fmaxf(wacc[2][1], wacc[3][1]));
     out[2] = (wacc[0][2] + wacc[1][2]) + (wacc[2][2] + wacc[3][2]);
@@ -1054,9 +1125,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_consp(const Job* __restrict__ jobs
   __shared__ NParams np[SP_NCH];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
-  float* S_out = IOF(S_out);
-  float* C_out = IOF(C_out);
-  float* S_tape = IOF(S_tape);
+  const gp<float> S_out = G(IOF(S_out));
+  const gp<float> C_out = G(IOF(C_out));
+  const gp<float> S_tape = G(IOF(S_tape));
   const int cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const size_t plane = (size_t)Hm * Wm;
   const int yy = threadIdx.x / CA_T, xx = threadIdx.x % CA_T;
@@ -1065,7 +1136,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_consp(const Job* __restrict__ jobs
   const size_t o = (size_t)min(y, Hm - 1) * Wm + min(x, Wm - 1);
   float fv[SP_NCH];
 #pragma unroll
-  for (int k = 0; k < SP_NCH; ++k) fv[k] = sd.fbar[k * plane + o];
+  for (int k = 0; k < SP_NCH; ++k) fv[k] = G(sd.fbar)[k * plane + o];
   consp_nparams(sd, np);
   float S = 0.f;
 #pragma unroll
@@ -1106,20 +1177,20 @@ constexpr int KTW_MAX = 64;   // widest tile (the width is chosen per stream by 
 __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ jobs,
                                                      const StreamDesc* __restrict__ sds,
                                                      const StepIO* __restrict__ ios, StepIO io0) {
-  __shared__ float reg[KT + 4][KTW_MAX + 4];
+  __shared__ float reg[(KT + 4) * (KTW_MAX + 4)];   // flat, row stride tw + 4
   __shared__ float hb[KT + 4][KTW_MAX];
   __shared__ float sh4[4];
   __shared__ int shi4[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
-  const float* S = IOF(S_in);
-  const uint8_t* seg = IOF(seg_prev);
+  const gp<const float> S = G(IOF(S_in));
+  const gp<const uint8_t> seg = G(IOF(seg_prev));
   const float* pprev = IOF(pi_prev);
-  float* pnext = IOF(pi_next);
-  float* pout = IOF(prior_out);
-  float* ftape = IOF(f_tape);
-  float* mstape = IOF(ms_tape);
-  float* unary = IOF(unary);
+  const gp<float> pnext = G(IOF(pi_next));
+  const gp<float> pout = G(IOF(prior_out));
+  const gp<float> ftape = G(IOF(f_tape));
+  const gp<float> mstape = G(IOF(ms_tape));
+  const gp<float> unary = G(IOF(unary));
   const float K = IOF(K);
   const int t = IOF(t);
   const int H = sd.H, W = sd.W, cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
@@ -1129,8 +1200,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
       const int ry = i / rw, rx = i - ry * rw;
       const int y = clampi(J.y0 - 2 + ry, 0, H - 1), x = clampi(J.x0 - 2 + rx, 0, W - 1);
       const size_t o = (size_t)y * W + x;
-      reg[ry][rx] = seg ? (float)seg[o] : pprev[o];
+      if (seg)
+        reg[i] = (float)seg[o];
+      else
+        lds_load(reg + i, pprev + o);
     }
+    lds_wait();
   }
   float m;
   int xs;
@@ -1139,7 +1214,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   if (t > 0) {
     for (int i = threadIdx.x; i < (KT + 4) * tw; i += SP_BLOCK) {
       const int r = i / tw, j = i - r * tw;
-      hb[r][j] = kB0 * reg[r][j] + kB1 * reg[r][j + 1] + kB2 * reg[r][j + 2] + kB1 * reg[r][j + 3] + kB0 * reg[r][j + 4];
+      const float* g = reg + r * rw + j;
+      hb[r][j] = kB0 * g[0] + kB1 * g[1] + kB2 * g[2] + kB1 * g[3] + kB0 * g[4];
     }
     __syncthreads();
   }
