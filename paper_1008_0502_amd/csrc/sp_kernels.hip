@@ -156,6 +156,27 @@ __device__ __forceinline__ gp<T> G(T* p) {
   return (gp<T>)p;
 }
 
+// Row and column of the flat index i = threadIdx.x + k * SP_BLOCK over rows of length
+// w, advanced by SP_BLOCK per step: the quotient and remainder of the start and of the
+// stride are taken once, so a staging loop does no integer division per element.
+struct Walk2 {
+  int r, c, dr, dc, w;
+  __device__ __forceinline__ Walk2(int start, int w_) : w(max(w_, 1)) {
+    r = start / w;
+    c = start - r * w;
+    dr = SP_BLOCK / w;
+    dc = SP_BLOCK - dr * w;
+  }
+  __device__ __forceinline__ void next() {
+    r += dr;
+    c += dc;
+    if (c >= w) {
+      c -= w;
+      ++r;
+    }
+  }
+};
+
 // ---------------------------------------------------------------- stream helpers
 __device__ __forceinline__ const float* base_ptr(const StreamDesc& sd, const float* ckpt, int l) {
   return (l == sd.c_min && ckpt) ? ckpt : sd.base[l];
@@ -324,8 +345,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
   const int xe = want_d2 ? min(x0 + tw, W - 1) : x0 + tw - 1;  // last staged column
   // a staged row starts at the 4-pixel group holding (y, xs): at most 3 leading pixels
   const int NG = (xe - xs + 3) / 4 + 1;
-  for (int i = threadIdx.x; i < nr * NG; i += SP_BLOCK) {
-    const int r = i / NG, gi = i - r * NG;
+  Walk2 wk(threadIdx.x, NG);
+  for (int i = threadIdx.x; i < nr * NG; i += SP_BLOCK, wk.next()) {
+    const int r = wk.r, gi = wk.c;
     const long long rowp = (long long)(y0 + r) * W;
     const long long q = ((rowp + xs) & ~3LL) + 4 * gi;
     if (q > rowp + xe) continue;
@@ -349,8 +371,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
   }
   __syncthreads();
   uint32_t mx = 0, d2 = 0;
-  for (int i = threadIdx.x; i < th * tw; i += SP_BLOCK) {
-    const int r = i / tw, x = x0 + (i - r * tw), y = y0 + r;
+  Walk2 wk2(threadIdx.x, tw);
+  for (int i = threadIdx.x; i < th * tw; i += SP_BLOCK, wk2.next()) {
+    const int r = wk2.r, x = x0 + wk2.c, y = y0 + r;
     const int k0 = x - xs + (int)(((long long)y * W + xs) & 3);
     const uint32_t a = Pk[r][k0];
     mx = max(mx, (a & 0xffu) + ((a >> 8) & 0xffu) + (a >> 16));
@@ -518,8 +541,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
     const int cw = xhi - xlo, n = (yhi - ylo) * cw;
     const size_t plane = (size_t)H * W;
     const float lam = sd.lam, potts = sd.potts;
-    for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-      const int yy = i / cw, xx = i - yy * cw;
+    Walk2 wk(threadIdx.x, cw);
+    for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
+      const int yy = wk.r, xx = wk.c;
       const int y = ylo + yy, x = xlo + xx;
       const int r = (y - Y0) * RW + (x - X0);
       const uint32_t c0 = Pk[r];
@@ -614,15 +638,17 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
   const float* I = base_ptr(sd, ckpt, l);
   if ((int)threadIdx.x < 4 * n) taps[(threadIdx.x / n) * (2 * SP_MAXR + 1) + threadIdx.x % n] =
       sd.gf[threadIdx.x / n][threadIdx.x % n];
-  for (int i = threadIdx.x; i < RR * RR; i += SP_BLOCK) {
-    const int ry = i / RR, rx = i - ry * RR;
+  Walk2 wk(threadIdx.x, RR);
+  for (int i = threadIdx.x; i < RR * RR; i += SP_BLOCK, wk.next()) {
+    const int ry = wk.r, rx = wk.c;
     const int y = clampi(J.y0 - R + ry, 0, Hs - 1), x = clampi(J.x0 - R + rx, 0, Ws - 1);
     lds_load(Ir + i, I + (size_t)y * Ws + x);
   }
   lds_wait();
   __syncthreads();
-  for (int i = threadIdx.x; i < 4 * GT * RR; i += SP_BLOCK) {
-    const int f = i / (GT * RR), rem = i - f * GT * RR, yy = rem / RR, xr = rem - yy * RR;
+  Walk2 wk2(threadIdx.x, RR);
+  for (int i = threadIdx.x; i < 4 * GT * RR; i += SP_BLOCK, wk2.next()) {
+    const int f = wk2.r / GT, yy = wk2.r % GT, xr = wk2.c;
     const float* tp = taps + f * (2 * SP_MAXR + 1);
     float acc = 0.f;
     for (int v = 0; v < n; ++v) acc += tp[v] * Ir[(yy + v) * RR + xr];
@@ -661,20 +687,24 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
 // Gabor maps of a whole (small) level held in LDS.
 __device__ void gabor_lds(const float* I, int h, int w, float* V, const float* taps, int R, float c45, gp<float> out) {
   const int n = h * w, nt = 2 * R + 1;
-  for (int i = threadIdx.x; i < 4 * n; i += SP_BLOCK) {
-    const int f = i / n, pix = i - f * n, y = pix / w, x = pix - y * w;
+  for (int f = 0; f < 4; ++f) {
     const float* tp = taps + f * (2 * SP_MAXR + 1);
-    float acc = 0.f;
-    for (int v = 0; v < nt; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
-    V[i] = acc;
+    Walk2 wk(threadIdx.x, w);
+    for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK, wk.next()) {
+      const int y = wk.r, x = wk.c;
+      float acc = 0.f;
+      for (int v = 0; v < nt; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
+      V[f * n + pix] = acc;
+    }
   }
   __syncthreads();
   const float* t0 = taps;
   const float* t1 = taps + (2 * SP_MAXR + 1);
   const float* t2 = taps + 2 * (2 * SP_MAXR + 1);
   const float* t3 = taps + 3 * (2 * SP_MAXR + 1);
-  for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK) {
-    const int y = pix / w, x = pix - y * w;
+  Walk2 wk(threadIdx.x, w);
+  for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK, wk.next()) {
+    const int y = wk.r, x = wk.c;
     float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
     for (int u = 0; u < nt; ++u) {
       const int o = y * w + clampi(x + u - R, 0, w - 1);
@@ -719,8 +749,9 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   for (int l = L0; l < last; ++l) {
     const int nH = sd.Hl[l + 1], nW = sd.Wl[l + 1];
     __syncthreads();
-    for (int i = threadIdx.x; i < cH * nW; i += SP_BLOCK) {
-      const int r = i / nW, j = i - r * nW;
+    Walk2 wk(threadIdx.x, nW);
+    for (int i = threadIdx.x; i < cH * nW; i += SP_BLOCK, wk.next()) {
+      const int r = wk.r, j = wk.c;
       const float* row = cur + r * cW;
       float acc = 0.f;
 #pragma unroll
@@ -729,8 +760,9 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
     }
     __syncthreads();
     const gp<float> dst = gab ? nullptr : level_dst(sd, ckpt, l + 1) + (size_t)ch * nH * nW;
-    for (int i = threadIdx.x; i < nH * nW; i += SP_BLOCK) {
-      const int r = i / nW, j = i - r * nW;
+    Walk2 wk2(threadIdx.x, nW);
+    for (int i = threadIdx.x; i < nH * nW; i += SP_BLOCK, wk2.next()) {
+      const int r = wk2.r, j = wk2.c;
       float acc = 0.f;
 #pragma unroll
       for (int t = -2; t <= 2; ++t) acc += binom(t) * HB[clampi(2 * r + t, 0, cH - 1) * nW + j];
@@ -827,11 +859,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
   // stage the surround footprints
   for (int q = 0; q < npc; ++q) {
     const int s = sd.ps[plist[q]], Ws = sd.Wl[s];
-    const int nf = fp[q].h * fp[q].w;
-    // flat [k][nf] with row stride fp.w, so that the destination follows the loop index
-    for (int i = threadIdx.x; i < SP_NCH * nf; i += SP_BLOCK) {
-      const int k = i / nf, r = i - k * nf, fy = r / fp[q].w, fx = r - fy * fp[q].w;
-      lds_load(&sur[q][0][0] + i, chan_ptr(sd, ckpt, k, s) + (size_t)(fp[q].y0 + fy) * Ws + fp[q].x0 + fx);
+    // [k][CS_F][CS_F]: the destination follows the loop index; lanes outside the
+    // footprint stay idle
+    for (int i = threadIdx.x; i < SP_NCH * CS_F * CS_F; i += SP_BLOCK) {
+      const int k = i / (CS_F * CS_F), r = i - k * (CS_F * CS_F), fy = r / CS_F, fx = r - fy * CS_F;
+      if (fy < fp[q].h && fx < fp[q].w)
+        lds_load(&sur[q][0][0] + i, chan_ptr(sd, ckpt, k, s) + (size_t)(fp[q].y0 + fy) * Ws + fp[q].x0 + fx);
     }
   }
   lds_wait();
@@ -854,7 +887,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
       const Tap ty = bilinear_tap(yc, d, sd.Hl[s]), tx = bilinear_tap(xc, d, sd.Wl[s]);
 #pragma unroll
       for (int k = 0; k < SP_NCH; ++k) {
-        const float up = bilinear_lds(&sur[q][0][0] + k * fp[q].h * fp[q].w, fp[q].w, ty, tx, fp[q].y0, fp[q].x0);
+        const float up = bilinear_lds(sur[q][k], CS_F, ty, tx, fp[q].y0, fp[q].x0);
         const float F = fabsf(cen[k][(yc - J.y0) * CS_T + (xc - J.x0)] - up);
         const float bmn = wave_reduce<OpMin>(valid ? F : INFINITY);
         const float bmx = wave_reduce<OpMax>(valid ? F : -INFINITY);
@@ -912,8 +945,9 @@ __device__ __forceinline__ Range finer_range(Range r, int n_finer) {
 // covers rows ri x cols ci of the finer level (size nh x nw); indices clamped to it.
 __device__ void reduce_lds(const float* in, int ldi, Range ri, Range ci, float* tmp, int ldt,
                            float* out, int ldo, Range ro, Range co, int nh, int nw, bool add) {
-  for (int i = threadIdx.x; i < ri.n * co.n; i += SP_BLOCK) {
-    const int r = i / co.n, j = i - r * co.n;
+  Walk2 wk(threadIdx.x, co.n);
+  for (int i = threadIdx.x; i < ri.n * co.n; i += SP_BLOCK, wk.next()) {
+    const int r = wk.r, j = wk.c;
     const int X = co.lo + j;
     float acc = 0.f;
 #pragma unroll
@@ -921,8 +955,9 @@ __device__ void reduce_lds(const float* in, int ldi, Range ri, Range ci, float* 
     tmp[r * ldt + j] = acc;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < ro.n * co.n; i += SP_BLOCK) {
-    const int r = i / co.n, j = i - r * co.n;
+  Walk2 wk2(threadIdx.x, co.n);
+  for (int i = threadIdx.x; i < ro.n * co.n; i += SP_BLOCK, wk2.next()) {
+    const int r = wk2.r, j = wk2.c;
     const int Y = ro.lo + r;
     float acc = 0.f;
 #pragma unroll
@@ -1007,8 +1042,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
     const int c = cm - r, Wc = sd.Wl[c];
     const float* Xc = chan_ptr(sd, ckpt, k, c);
     const int n = rr.n * cc.n;
-    for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-      const int yy = i / cc.n, xx = i - yy * cc.n;
+    Walk2 wk(threadIdx.x, cc.n);
+    for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
+      const int yy = wk.r, xx = wk.c;
       lds_load(X + i, Xc + (size_t)(rr.lo + yy) * Wc + cc.lo + xx);
     }
   };
@@ -1023,8 +1059,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
       const CaPair& P = cpt[r][q];
       const float* Xs = chan_ptr(sd, ckpt, k, cm - r + P.d);
       float* dst = dyn + P.off;
-      for (int i = threadIdx.x; i < P.fh * P.fw; i += SP_BLOCK) {
-        const int fy = i / P.fw, fx = i - fy * P.fw;
+      Walk2 wk(threadIdx.x, P.fw);
+      for (int i = threadIdx.x; i < P.fh * P.fw; i += SP_BLOCK, wk.next()) {
+        const int fy = wk.r, fx = wk.c;
         lds_load(dst + i, Xs + (size_t)(P.fy0 + fy) * P.Ws + P.fx0 + fx);
       }
     }
@@ -1033,8 +1070,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
   // ---- N(F) summed over the pairs of each centre level, in place of the centre values
   auto nsum = [&](int r, Range rr, Range cc, float* X) {
     const int n = rr.n * cc.n, nq = ncp[r];
-    for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-      const int yy = i / cc.n, xx = i - yy * cc.n;
+    Walk2 wk(threadIdx.x, cc.n);
+    for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
+      const int yy = wk.r, xx = wk.c;
       const int y = rr.lo + yy, x = cc.lo + xx;
       const float xc = X[i];
       float acc = 0.f;
@@ -1058,8 +1096,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
   if (has1 || has2)
     reduce_lds(X1, cg1.n, rg1, cg1, tm, cg0.n, fb, CA_T, rg0, cg0, sd.Hl[cm - 1], sd.Wl[cm - 1], true);
   if (has0) {
-    for (int i = threadIdx.x; i < J.th * J.tw; i += SP_BLOCK) {
-      const int yy = i / J.tw, xx = i - yy * J.tw;
+    Walk2 wk(threadIdx.x, J.tw);
+    for (int i = threadIdx.x; i < J.th * J.tw; i += SP_BLOCK, wk.next()) {
+      const int yy = wk.r, xx = wk.c;
       fb[yy * CA_T + xx] += X0[i];
     }
     __syncthreads();
@@ -1178,12 +1217,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
                                                      const StreamDesc* __restrict__ sds,
                                                      const StepIO* __restrict__ ios, StepIO io0) {
   __shared__ float reg[(KT + 4) * (KTW_MAX + 4)];   // flat, row stride tw + 4
+  __shared__ float Sl[(KT + 1) * (KTW_MAX + 1)];    // footprint of the tile on level c_max
   __shared__ float hb[KT + 4][KTW_MAX];
   __shared__ float sh4[4];
   __shared__ int shi4[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
-  const gp<const float> S = G(IOF(S_in));
   const gp<const uint8_t> seg = G(IOF(seg_prev));
   const float* pprev = IOF(pi_prev);
   const gp<float> pnext = G(IOF(pi_next));
@@ -1196,8 +1235,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   const int H = sd.H, W = sd.W, cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const int tw = J.tw, rw = tw + 4;
   if (t > 0) {
-    for (int i = threadIdx.x; i < (KT + 4) * rw; i += SP_BLOCK) {
-      const int ry = i / rw, rx = i - ry * rw;
+    Walk2 wk(threadIdx.x, rw);
+    for (int i = threadIdx.x; i < (KT + 4) * rw; i += SP_BLOCK, wk.next()) {
+      const int ry = wk.r, rx = wk.c;
       const int y = clampi(J.y0 - 2 + ry, 0, H - 1), x = clampi(J.x0 - 2 + rx, 0, W - 1);
       const size_t o = (size_t)y * W + x;
       if (seg)
@@ -1205,15 +1245,27 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
       else
         lds_load(reg + i, pprev + o);
     }
-    lds_wait();
   }
+  // the saliency samples of the tile: its footprint on level c_max, flat with row
+  // stride f.w
+  const Foot sf = footprint(J.y0, J.th, J.x0, tw, cm, Hm, Wm);
+  {
+    const float* Sg = IOF(S_in);
+    Walk2 wk(threadIdx.x, sf.w);
+    for (int i = threadIdx.x; i < sf.h * sf.w; i += SP_BLOCK, wk.next()) {
+      const int fy = wk.r, fx = wk.c;
+      lds_load(Sl + i, Sg + (size_t)(sf.y0 + fy) * Wm + sf.x0 + fx);
+    }
+  }
+  lds_wait();
   float m;
   int xs;
   smax_from_parts(sd.s_part, sd.n_cmax_tiles, &m, &xs, sh4, shi4);
   const bool flat = !(m > sd.flat_tol);
   if (t > 0) {
-    for (int i = threadIdx.x; i < (KT + 4) * tw; i += SP_BLOCK) {
-      const int r = i / tw, j = i - r * tw;
+    Walk2 wk(threadIdx.x, tw);
+    for (int i = threadIdx.x; i < (KT + 4) * tw; i += SP_BLOCK, wk.next()) {
+      const int r = wk.r, j = wk.c;
       const float* g = reg + r * rw + j;
       hb[r][j] = kB0 * g[0] + kB1 * g[1] + kB2 * g[2] + kB1 * g[3] + kB0 * g[4];
     }
@@ -1232,7 +1284,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
       float q = 0.5f;
       if (!flat) {
         const Tap tx = bilinear_tap(x, cm, Wm);
-        const float u = bilinear(S, Wm, ty, tx) / m;
+        const float u = bilinear_lds(Sl, sf.w, ty, tx, sf.y0, sf.x0) / m;
         q = fminf(fmaxf(u, sd.eps), 1.f - sd.eps);
       }
       if (ring) q = sd.eps;
