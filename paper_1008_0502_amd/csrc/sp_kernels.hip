@@ -588,6 +588,17 @@ __device__ __forceinline__ gp<float> level_dst(const StreamDesc& sd, float* ckpt
   return G((l == sd.c_min && ckpt) ? ckpt : sd.base[l]);
 }
 
+// The four 1-D Gabor factors in LDS as [4][2*SP_MAXR+1], zero beyond the n = 2R+1
+// taps: the tap loops below run over the full length, unrolled and without branches, so
+// all their LDS reads issue together; a zero tap adds exactly nothing.
+__device__ __forceinline__ void load_taps(const StreamDesc& sd, int n, float* taps) {
+  constexpr int NT = 2 * SP_MAXR + 1;
+  if ((int)threadIdx.x < 4 * NT) {
+    const int f = threadIdx.x / NT, v = threadIdx.x - f * NT;
+    taps[threadIdx.x] = (v < n) ? sd.gf[f][v] : 0.f;
+  }
+}
+
 // level a -> a+1 of the 4 base channels for one 16x16 tile of level a+1
 __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float* smem) {
   float* F = smem;                 // [4][DR][DR]
@@ -636,8 +647,7 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
   const int l = J.a, R = sd.gr, n = 2 * R + 1, RR = GT + 2 * R;
   const int Hs = sd.Hl[l], Ws = sd.Wl[l];
   const float* I = base_ptr(sd, ckpt, l);
-  if ((int)threadIdx.x < 4 * n) taps[(threadIdx.x / n) * (2 * SP_MAXR + 1) + threadIdx.x % n] =
-      sd.gf[threadIdx.x / n][threadIdx.x % n];
+  load_taps(sd, n, taps);
   Walk2 wk(threadIdx.x, RR);
   for (int i = threadIdx.x; i < RR * RR; i += SP_BLOCK, wk.next()) {
     const int ry = wk.r, rx = wk.c;
@@ -651,7 +661,8 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
     const int f = wk2.r / GT, yy = wk2.r % GT, xr = wk2.c;
     const float* tp = taps + f * (2 * SP_MAXR + 1);
     float acc = 0.f;
-    for (int v = 0; v < n; ++v) acc += tp[v] * Ir[(yy + v) * RR + xr];
+#pragma unroll
+    for (int v = 0; v < 2 * SP_MAXR + 1; ++v) acc += tp[v] * Ir[(yy + min(v, n - 1)) * RR + xr];
     V[(f * GT + yy) * (GRM + 1) + xr] = acc;
   }
   __syncthreads();
@@ -666,13 +677,15 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
   const float* V2 = V + (2 * GT + yy) * (GRM + 1) + xx;
   const float* V3 = V + (3 * GT + yy) * (GRM + 1) + xx;
   float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
-  for (int u = 0; u < n; ++u) {
-    const float vg = V0[u];
+#pragma unroll
+  for (int u = 0; u < 2 * SP_MAXR + 1; ++u) {
+    const int uc = min(u, n - 1);
+    const float vg = V0[uc];
     A += t1[u] * vg;
     B += t0[u] * vg;
-    C += t0[u] * V1[u];
-    D += t2[u] * V2[u];
-    E += t3[u] * V3[u];
+    C += t0[u] * V1[uc];
+    D += t2[u] * V2[uc];
+    E += t3[u] * V3[uc];
   }
   if (yy < J.th && xx < J.tw && y < Hs && x < Ws) {
     const size_t plane = (size_t)Hs * Ws, o = (size_t)y * Ws + x;
@@ -693,7 +706,8 @@ __device__ void gabor_lds(const float* I, int h, int w, float* V, const float* t
     for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK, wk.next()) {
       const int y = wk.r, x = wk.c;
       float acc = 0.f;
-      for (int v = 0; v < nt; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
+#pragma unroll
+      for (int v = 0; v < 2 * SP_MAXR + 1; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
       V[f * n + pix] = acc;
     }
   }
@@ -706,7 +720,8 @@ __device__ void gabor_lds(const float* I, int h, int w, float* V, const float* t
   for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK, wk.next()) {
     const int y = wk.r, x = wk.c;
     float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
-    for (int u = 0; u < nt; ++u) {
+#pragma unroll
+    for (int u = 0; u < 2 * SP_MAXR + 1; ++u) {
       const int o = y * w + clampi(x + u - R, 0, w - 1);
       const float vg = V[o];
       A += t1[u] * vg;
@@ -736,8 +751,7 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   const bool gab = J.kind == JOB_TAILGAB;
   const int ch = gab ? 0 : J.tid, L0 = J.a, R = sd.gr, nt = 2 * R + 1;
   const int last = gab ? J.tid : sd.top;
-  if (gab && (int)threadIdx.x < 4 * nt)
-    taps[(threadIdx.x / nt) * (2 * SP_MAXR + 1) + threadIdx.x % nt] = sd.gf[threadIdx.x / nt][threadIdx.x % nt];
+  if (gab) load_taps(sd, nt, taps);
   int cH = sd.Hl[L0], cW = sd.Wl[L0];
   {
     const float* src = base_ptr(sd, ckpt, L0) + (size_t)ch * cH * cW;
