@@ -155,6 +155,7 @@ void add_tiles_wh(std::vector<Job>& v, int stream, int a, int h, int w, int th, 
 struct Tune {
   int kalman_tw = 32;   // 16, 32 or 64
   bool xcd = false;
+  int ca_nc = 2;        // channels per workgroup of the across-scale sum: 1, 2, 4 or 8
 };
 
 // Choices of the autotuner per resolution, reused by later contexts and batches.
@@ -166,6 +167,10 @@ bool& tune_cache_xcd() {
   static bool x = false;
   return x;
 }
+int& tune_cache_nc() {
+  static int nc = 2;
+  return nc;
+}
 std::mutex& tune_mutex() {
   static std::mutex m;
   return m;
@@ -176,7 +181,17 @@ Tune cached_tune(int H, int W) {
   auto it = tune_cache_tw().find({H, W});
   if (it != tune_cache_tw().end()) t.kalman_tw = it->second;
   t.xcd = tune_cache_xcd();
+  t.ca_nc = tune_cache_nc();
   return t;
+}
+
+// Channels per workgroup of the across-scale sum: the largest power of two up to the
+// preference whose LDS (one block per channel) fits the dynamic limit.
+int csapply_nc(const Geo& g, int pref) {
+  const size_t per = csapply_lds_bytes(g);
+  int nc = 8;
+  while (nc > 1 && (nc > pref || nc * per > kMaxDynLds)) nc /= 2;
+  return nc;
 }
 
 // Reorders a launch's jobs so that workgroups dispatched round-robin over the 8 XCDs
@@ -548,7 +563,7 @@ int run_phase(sp_ctx* c, const Phase& ph, const StreamDesc* sds, const StepIO* i
 }
 
 void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& kinds, const StreamDesc& sd,
-                        const Geo& g, int s, ProgPart which) {
+                        const Geo& g, int s, ProgPart which, int nc) {
   auto push = [&](int kind, std::vector<Job> v) {
     parts.push_back(std::move(v));
     kinds.push_back(kind);
@@ -579,7 +594,7 @@ void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& 
   for (int p = 0; p < g.n_pairs; ++p) v.push_back(Job{s, p, 0, 0, 1, 1, p, JOB_CSFINAL});
   push(JOB_CSFINAL, v);
   v.clear();
-  for (int k = 0; k < SP_NCH; ++k) add_tiles(v, s, k, g.Hl[g.c_max], g.Wl[g.c_max]);
+  for (int k = 0; k < SP_NCH; k += nc) add_tiles(v, s, k, g.Hl[g.c_max], g.Wl[g.c_max]);
   push(JOB_CSAPPLY, v);
   v.clear();
   add_tiles(v, s, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
@@ -752,10 +767,13 @@ int ctx_build_tables(sp_ctx* c) {
   {
     std::vector<std::vector<Job>> parts;
     std::vector<int> kinds;
-    build_forward_jobs(parts, kinds, c->h_sd, g, 0, PROG_ALL);
+    const int nc = csapply_nc(g, c->tune.ca_nc);
+    if (sp_csapply_reserve_lds(nc * csapply_lds_bytes(g)) != hipSuccess)
+      return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", nc * csapply_lds_bytes(g));
+    build_forward_jobs(parts, kinds, c->h_sd, g, 0, PROG_ALL, nc);
     for (size_t i = 0; i < parts.size(); ++i) {
-      c->fwd.push_back(c->jobs.add(kinds[i], 0, order(parts[i]), 1));
-      if (kinds[i] == JOB_CSAPPLY) c->fwd.back().lds = csapply_lds_bytes(g);
+      c->fwd.push_back(c->jobs.add(kinds[i], kinds[i] == JOB_CSAPPLY ? nc : 0, order(parts[i]), 1));
+      if (kinds[i] == JOB_CSAPPLY) c->fwd.back().lds = nc * csapply_lds_bytes(g);
     }
     std::vector<Job> v;
     add_tiles(v, 0, 0, Hc, Wc);
@@ -781,7 +799,7 @@ int ctx_build_tables(sp_ctx* c) {
       for (int s = 0; s < c->CH; ++s) {
         std::vector<std::vector<Job>> ps;
         std::vector<int> ks;
-        build_forward_jobs(ps, ks, c->h_sd, g, s, PROG_RECOMPUTE);
+        build_forward_jobs(ps, ks, c->h_sd, g, s, PROG_RECOMPUTE, nc);
         if (all.empty()) {
           all.resize(ps.size());
           kk = ks;
@@ -789,8 +807,8 @@ int ctx_build_tables(sp_ctx* c) {
         for (size_t i = 0; i < ps.size(); ++i) all[i].insert(all[i].end(), ps[i].begin(), ps[i].end());
       }
       for (size_t i = 0; i < all.size(); ++i) {
-        c->rec.push_back(c->jobs.add(kk[i], 0, all[i], c->CH));
-        if (kk[i] == JOB_CSAPPLY) c->rec.back().lds = csapply_lds_bytes(g);
+        c->rec.push_back(c->jobs.add(kk[i], kk[i] == JOB_CSAPPLY ? nc : 0, all[i], c->CH));
+        if (kk[i] == JOB_CSAPPLY) c->rec.back().lds = nc * csapply_lds_bytes(g);
       }
     }
   }
@@ -1025,6 +1043,19 @@ int sp_autotune(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, int32_
         bt = c->tune;
       }
     }
+  for (int nc : {1, 2, 4, 8}) {
+    if (rc || nc == bt.ca_nc || csapply_nc(g, nc) != nc) continue;
+    c->tune = bt;
+    c->tune.ca_nc = nc;
+    rc = time_it(&t);
+    if (rc) break;
+    snprintf(line, sizeof line, "%dx%d across-scale channels per workgroup %d: %.4f ms/frame\n", g.H, g.W, nc, t);
+    rep += line;
+    if (t < best) {
+      best = t;
+      bt = c->tune;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
@@ -1035,6 +1066,7 @@ int sp_autotune(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, int32_
     std::lock_guard<std::mutex> lk(tune_mutex());
     tune_cache_tw()[{g.H, g.W}] = bt.kalman_tw;
     tune_cache_xcd() = bt.xcd;
+    tune_cache_nc() = bt.ca_nc;
   }
   if (report && report_len) {
     std::strncpy(report, rep.c_str(), report_len - 1);
@@ -1115,7 +1147,7 @@ int saliency_backward(sp_ctx* c, const float* grad_prior, int32_t T, float* grad
         if (ph.kind == JOB_CONSP_DOT)
           return sp_launch_consp_dot(c->jobs.dev + ph.off, nj, c->d_rsd, ios, c->gs_all, c->ms_tape, fid,
                                      c->dot_part, c->cx, c->stream);
-        return sp_launch(ph.kind, c->jobs.dev + ph.off, nj, c->d_rsd, ios, nullptr, 0, nullptr, c->stream, ph.lds);
+        return sp_launch(ph.kind, c->jobs.dev + ph.off, nj, c->d_rsd, ios, nullptr, ph.flag, nullptr, c->stream, ph.lds);
       });
       if (e != hipSuccess) return fail(SP_EHIP, "recompute launch: %s", hipGetErrorString(e));
     }
@@ -1231,6 +1263,7 @@ struct sp_batch {
   bool mrf = false;
   std::vector<Tune> tune;   // per stream
   bool xcd = false;
+  int ca_nc = 2;            // preferred channels per across-scale workgroup (one value per launch)
 };
 
 namespace {
@@ -1253,6 +1286,8 @@ int batch_build_tables(sp_batch* b) {
   std::vector<Job> rgb, feat, fin, css, csf, csa, cons, kal;
   std::vector<std::vector<Job>> mids;
   bool any_big = false;
+  int nc = 8;   // one channel-group size for the whole across-scale launch
+  for (int i = 0; i < n; ++i) nc = std::min(nc, csapply_nc(b->geo[i], b->ca_nc));
   for (int i = 0; i < n; ++i) {
     const Geo& g = b->geo[i];
     for (int p = 0; p < g.n_pairs; ++p) csf.push_back(Job{i, p, 0, 0, 1, 1, p, JOB_CSFINAL});
@@ -1271,7 +1306,7 @@ int batch_build_tables(sp_batch* b) {
       for (int k = 0; k < g.n_pairs; ++k) has |= (g.pc[k] == c);
       if (has) add_tiles(css, i, c, g.Hl[c], g.Wl[c]);
     }
-    for (int k = 0; k < SP_NCH; ++k) add_tiles(csa, i, k, g.Hl[g.c_max], g.Wl[g.c_max]);
+    for (int k = 0; k < SP_NCH; k += nc) add_tiles(csa, i, k, g.Hl[g.c_max], g.Wl[g.c_max]);
     add_tiles(cons, i, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
     add_tiles_wh(kal, i, 0, g.H, g.W, 16, b->tune[i].kalman_tw, JOB_KALMAN);
   }
@@ -1290,11 +1325,13 @@ int batch_build_tables(sp_batch* b) {
   if (!fin.empty()) b->phases.push_back(b->jobs.add(any_big ? JOB_TAIL : JOB_DOWN, 0, fin, n));
   b->phases.push_back(b->jobs.add(JOB_CSSTATS, 0, order(css), n));
   b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, n));
-  b->phases.push_back(b->jobs.add(JOB_CSAPPLY, 0, order(csa), n));
+  b->phases.push_back(b->jobs.add(JOB_CSAPPLY, nc, order(csa), n));
   {
     size_t lds = 0;
     for (const Geo& g : b->geo) lds = std::max(lds, csapply_lds_bytes(g));
-    b->phases.back().lds = lds;
+    b->phases.back().lds = nc * lds;
+    if (sp_csapply_reserve_lds(nc * lds) != hipSuccess)
+      return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", nc * lds);
   }
   b->phases.push_back(b->jobs.add(JOB_CONSP, 0, order(cons), n));
   b->phases.push_back(b->jobs.add(JOB_KALMAN, 0, order(kal), n));
@@ -1391,6 +1428,7 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
   b->tune.resize(n);
   for (int i = 0; i < n; ++i) b->tune[i] = cached_tune(H[i], W[i]);
   b->xcd = n > 0 ? b->tune[0].xcd : false;
+  b->ca_nc = n > 0 ? b->tune[0].ca_nc : 2;
   {
     size_t lds = 0;
     for (const Geo& g : b->geo) lds = std::max(lds, csapply_lds_bytes(g));
@@ -1563,6 +1601,26 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
     }
     for (int i : kv.second) b->tune[i].kalman_tw = best_tw;
   }
+  {
+    int best_nc = b->ca_nc;
+    double bt = 1e30;
+    for (int nc : {1, 2, 4, 8}) {
+      if (rc) break;
+      bool ok = true;
+      for (const Geo& g : b->geo) ok &= csapply_nc(g, nc) == nc;
+      if (!ok) continue;
+      b->ca_nc = nc;
+      rc = time_it(&t);
+      if (rc) break;
+      snprintf(line, sizeof line, "across-scale channels per workgroup %d: %.4f ms/step\n", nc, t);
+      rep += line;
+      if (t < bt) {
+        bt = t;
+        best_nc = nc;
+      }
+    }
+    b->ca_nc = best_nc;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->prof.on = was;
@@ -1572,9 +1630,10 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
   {
     std::lock_guard<std::mutex> lk(tune_mutex());
     tune_cache_xcd() = b->xcd;
+    tune_cache_nc() = b->ca_nc;
     for (int i = 0; i < b->n; ++i) tune_cache_tw()[{b->geo[i].H, b->geo[i].W}] = b->tune[i].kalman_tw;
   }
-  snprintf(line, sizeof line, "chosen: xcd_order=%d\n", (int)b->xcd);
+  snprintf(line, sizeof line, "chosen: xcd_order=%d, across-scale channels %d\n", (int)b->xcd, b->ca_nc);
   rep += line;
   if (report && report_len) {
     std::strncpy(report, rep.c_str(), report_len - 1);

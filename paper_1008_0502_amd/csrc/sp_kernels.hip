@@ -955,53 +955,35 @@ __device__ __forceinline__ Range finer_range(Range r, int n_finer) {
   return Range{lo, hi - lo + 1};
 }
 
-// out (+)= decimated blur of in: out covers rows ro x cols co of the coarse level, in
-// covers rows ri x cols ci of the finer level (size nh x nw); indices clamped to it.
-__device__ void reduce_lds(const float* in, int ldi, Range ri, Range ci, float* tmp, int ldt,
-                           float* out, int ldo, Range ro, Range co, int nh, int nw, bool add) {
-  Walk2 wk(threadIdx.x, co.n);
-  for (int i = threadIdx.x; i < ri.n * co.n; i += SP_BLOCK, wk.next()) {
-    const int r = wk.r, j = wk.c;
-    const int X = co.lo + j;
-    float acc = 0.f;
-#pragma unroll
-    for (int t = -2; t <= 2; ++t) acc += binom(t) * in[r * ldi + clampi(2 * X + t, 0, nw - 1) - ci.lo];
-    tmp[r * ldt + j] = acc;
-  }
-  __syncthreads();
-  Walk2 wk2(threadIdx.x, co.n);
-  for (int i = threadIdx.x; i < ro.n * co.n; i += SP_BLOCK, wk2.next()) {
-    const int r = wk2.r, j = wk2.c;
-    const int Y = ro.lo + r;
-    float acc = 0.f;
-#pragma unroll
-    for (int t = -2; t <= 2; ++t) acc += binom(t) * tmp[(clampi(2 * Y + t, 0, nh - 1) - ri.lo) * ldt + j];
-    out[r * ldo + j] = add ? out[r * ldo + j] + acc : acc;
-  }
-  __syncthreads();
-}
-
-// One non-flat pair of a centre level as the per-pixel loop needs it (flat maps add 0).
+// One pair of a centre level as the per-pixel loop needs it.  Its footprint sits at the
+// same offset in the LDS block of every channel of the workgroup.
 struct CaPair {
-  int off, fy0, fx0, fw;   // staged footprint: LDS offset, origin on level s, row length
+  int off, fy0, fx0, fw;   // staged footprint: LDS offset in a channel block, origin on level s, row length
   int d, Hs, Ws, fh;       // s - c and the size of level s; footprint rows
-  float mn, inv, scale, pad;
 };
 
+// NC consecutive channels (from job a) of one c_max tile per workgroup: the sampling
+// geometry (bilinear taps, LDS offsets) is computed once per pixel and pair and applied
+// to every channel.  Each channel owns a block of L.total floats of dynamic LDS with the
+// layout of csapply_layout.  A flat map has zero N parameters (inv = scale = 0), which
+// adds exactly 0.
+template <int NC>
 __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jobs,
                                                       const StreamDesc* __restrict__ sds,
                                                       const StepIO* __restrict__ ios, StepIO io0) {
   extern __shared__ float dyn[];
   __shared__ CaPair cpt[3][4];
+  __shared__ float cnp[3][4][NC][3];   // N parameters (mn, inv, scale) per level, pair and channel
   __shared__ int ncp[3];
-  __shared__ float fb[CA_T * CA_T];
-  __shared__ float wacc[4][3];
+  __shared__ float fb[NC][CA_T * CA_T];
+  __shared__ float wacc[4][NC][3];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const float* ckpt = IOF(ckpt);
-  const int k = J.a, cm = sd.c_max;
+  const int k0 = J.a, cm = sd.c_max;
   const int Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const CaLayout L = csapply_layout(sd.pc, sd.ps, sd.n_pairs, cm);
+  const int CS = L.total;   // floats per channel block
   unsigned hm = 0;
   for (int p = 0; p < sd.n_pairs; ++p) hm |= 1u << (cm - sd.pc[p]);
   const bool has0 = (hm & 1u) != 0, has1 = (hm & 2u) != 0, has2 = (hm & 4u) != 0;
@@ -1016,21 +998,18 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
     rg2 = finer_range(rg1, sd.Hl[cm - 2]);
     cg2 = finer_range(cg1, sd.Wl[cm - 2]);
   }
-  float* X0 = dyn + L.x0;
-  float* X1 = dyn + L.x1;
-  float* X2 = dyn + L.x2;
-  // ---- table of the non-flat pairs per centre level (footprints keep the layout's slots)
+  // ---- table of the pairs per centre level
   if (threadIdx.x == 0) {
     int cnt[3] = {0, 0, 0};
     int off = L.foot0;
     for (int p = 0; p < sd.n_pairs; ++p) {
       const int c = sd.pc[p], r = cm - c, s = sd.ps[p];
-      const NParams q = load_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k));
-      if (!q.flat && cnt[r] < 4) {
+      if (cnt[r] < 4) {
         const Range rr = (r == 0) ? rg0 : ((r == 1) ? rg1 : rg2);
         const Range cc = (r == 0) ? cg0 : ((r == 1) ? cg1 : cg2);
         const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], sd.Wl[s]);
-        CaPair& P = cpt[r][cnt[r]++];
+        const int q = cnt[r]++;
+        CaPair& P = cpt[r][q];
         P.off = off;
         P.fy0 = f.y0;
         P.fx0 = f.x0;
@@ -1039,10 +1018,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
         P.d = s - c;
         P.Hs = sd.Hl[s];
         P.Ws = sd.Wl[s];
-        P.mn = q.mn;
-        P.inv = q.inv;
-        P.scale = q.scale;
-        P.pad = 0.f;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const NParams np = load_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k0 + j));
+          cnp[r][q][j][0] = np.mn;
+          cnp[r][q][j][1] = np.flat ? 0.f : np.inv;
+          cnp[r][q][j][2] = np.flat ? 0.f : np.scale;
+        }
       }
       off += csapply_foot_cap(r, s - c);
     }
@@ -1050,98 +1032,155 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
     ncp[1] = cnt[1];
     ncp[2] = cnt[2];
   }
+  for (int i = threadIdx.x; i < NC * CA_T * CA_T; i += SP_BLOCK) (&fb[0][0])[i] = 0.f;
   __syncthreads();
-  // ---- one round trip: centre regions and footprints
-  auto stage = [&](int r, Range rr, Range cc, float* X) {
-    const int c = cm - r, Wc = sd.Wl[c];
-    const float* Xc = chan_ptr(sd, ckpt, k, c);
+  // ---- one round trip: centre regions and footprints of every channel
+  auto stage = [&](Range rr, Range cc, int c, int xoff) {
+    const int Wc = sd.Wl[c];
     const int n = rr.n * cc.n;
-    Walk2 wk(threadIdx.x, cc.n);
-    for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
-      const int yy = wk.r, xx = wk.c;
-      lds_load(X + i, Xc + (size_t)(rr.lo + yy) * Wc + cc.lo + xx);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const float* Xc = chan_ptr(sd, ckpt, k0 + j, c);
+      float* X = dyn + j * CS + xoff;
+      Walk2 wk(threadIdx.x, cc.n);
+      for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next())
+        lds_load(X + i, Xc + (size_t)(rr.lo + wk.r) * Wc + cc.lo + wk.c);
     }
   };
-  if (has0) stage(0, rg0, cg0, X0);
-  if (has1) stage(1, rg1, cg1, X1);
-  if (has2) stage(2, rg2, cg2, X2);
+  if (has0) stage(rg0, cg0, cm, L.x0);
+  if (has1) stage(rg1, cg1, cm - 1, L.x1);
+  if (has2) stage(rg2, cg2, cm - 2, L.x2);
   if (!has1 && has2)
-    for (int i = threadIdx.x; i < rg1.n * cg1.n; i += SP_BLOCK) X1[i] = 0.f;
-  for (int i = threadIdx.x; i < CA_T * CA_T; i += SP_BLOCK) fb[i] = 0.f;
+    for (int j = 0; j < NC; ++j)
+      for (int i = threadIdx.x; i < rg1.n * cg1.n; i += SP_BLOCK) dyn[j * CS + L.x1 + i] = 0.f;
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < ncp[r]; ++q) {
       const CaPair& P = cpt[r][q];
-      const float* Xs = chan_ptr(sd, ckpt, k, cm - r + P.d);
-      float* dst = dyn + P.off;
-      Walk2 wk(threadIdx.x, P.fw);
-      for (int i = threadIdx.x; i < P.fh * P.fw; i += SP_BLOCK, wk.next()) {
-        const int fy = wk.r, fx = wk.c;
-        lds_load(dst + i, Xs + (size_t)(P.fy0 + fy) * P.Ws + P.fx0 + fx);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const float* Xs = chan_ptr(sd, ckpt, k0 + j, cm - r + P.d);
+        float* dst = dyn + j * CS + P.off;
+        Walk2 wk(threadIdx.x, P.fw);
+        for (int i = threadIdx.x; i < P.fh * P.fw; i += SP_BLOCK, wk.next())
+          lds_load(dst + i, Xs + (size_t)(P.fy0 + wk.r) * P.Ws + P.fx0 + wk.c);
       }
     }
   lds_wait();
   __syncthreads();
   // ---- N(F) summed over the pairs of each centre level, in place of the centre values
-  auto nsum = [&](int r, Range rr, Range cc, float* X) {
+  auto nsum = [&](int r, Range rr, Range cc, int xoff) {
     const int n = rr.n * cc.n, nq = ncp[r];
     Walk2 wk(threadIdx.x, cc.n);
     for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
-      const int yy = wk.r, xx = wk.c;
-      const int y = rr.lo + yy, x = cc.lo + xx;
-      const float xc = X[i];
-      float acc = 0.f;
+      const int y = rr.lo + wk.r, x = cc.lo + wk.c;
+      float xc[NC], acc[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        xc[j] = dyn[j * CS + xoff + i];
+        acc[j] = 0.f;
+      }
       for (int q = 0; q < nq; ++q) {
         const CaPair& P = cpt[r][q];
         const Tap ty = bilinear_tap(y, P.d, P.Hs), tx = bilinear_tap(x, P.d, P.Ws);
-        const NParams np{P.mn, P.inv, P.scale, 0};
-        acc += napply(np, fabsf(xc - bilinear_lds(dyn + P.off, P.fw, ty, tx, P.fy0, P.fx0)));
+        const int o0 = P.off + (ty.i0 - P.fy0) * P.fw - P.fx0, o1 = P.off + (ty.i1 - P.fy0) * P.fw - P.fx0;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float* B = dyn + j * CS;
+          // explicit fused multiply-adds: the result must not depend on NC through the
+          // compiler's contraction choices
+          const float top = fmaf(tx.w, B[o0 + tx.i1], (1.f - tx.w) * B[o0 + tx.i0]);
+          const float bot = fmaf(tx.w, B[o1 + tx.i1], (1.f - tx.w) * B[o1 + tx.i0]);
+          const float up = fmaf(ty.w, bot, (1.f - ty.w) * top);
+          const float v = fabsf(xc[j] - up);
+          acc[j] = fmaf((v - cnp[r][q][j][0]) * cnp[r][q][j][1], cnp[r][q][j][2], acc[j]);
+        }
       }
-      X[i] = acc;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) dyn[j * CS + xoff + i] = acc[j];
     }
   };
-  if (has0) nsum(0, rg0, cg0, X0);
-  if (has1) nsum(1, rg1, cg1, X1);
-  if (has2) nsum(2, rg2, cg2, X2);
+  if (has0) nsum(0, rg0, cg0, L.x0);
+  if (has1) nsum(1, rg1, cg1, L.x1);
+  if (has2) nsum(2, rg2, cg2, L.x2);
   __syncthreads();
   // ---- reduce: two levels down -> one level down (added), one level down -> tile
-  float* tm = dyn + L.tm;
+  auto reduce = [&](int xin, int ldi, Range ri, Range ci, int xout_dyn, float* fbo, int ldo, Range ro, Range co,
+                    int nh, int nw) {
+    const int ldt = co.n;
+    Walk2 wk(threadIdx.x, co.n);
+    for (int i = threadIdx.x; i < ri.n * co.n; i += SP_BLOCK, wk.next()) {
+      const int r = wk.r, X = co.lo + wk.c;
+      int ix[5];
+#pragma unroll
+      for (int t = -2; t <= 2; ++t) ix[t + 2] = xin + r * ldi + clampi(2 * X + t, 0, nw - 1) - ci.lo;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const float* in = dyn + j * CS;
+        float acc = 0.f;
+#pragma unroll
+        for (int t = -2; t <= 2; ++t) acc = fmaf(binom(t), in[ix[t + 2]], acc);
+        dyn[j * CS + L.tm + r * ldt + wk.c] = acc;
+      }
+    }
+    __syncthreads();
+    Walk2 wk2(threadIdx.x, co.n);
+    for (int i = threadIdx.x; i < ro.n * co.n; i += SP_BLOCK, wk2.next()) {
+      const int r = wk2.r, c = wk2.c, Y = ro.lo + r;
+      int iy[5];
+#pragma unroll
+      for (int t = -2; t <= 2; ++t) iy[t + 2] = L.tm + (clampi(2 * Y + t, 0, nh - 1) - ri.lo) * ldt + c;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const float* tm = dyn + j * CS;
+        float acc = 0.f;
+#pragma unroll
+        for (int t = -2; t <= 2; ++t) acc = fmaf(binom(t), tm[iy[t + 2]], acc);
+        float* out = fbo ? fbo + j * (CA_T * CA_T) : dyn + j * CS + xout_dyn;
+        out[r * ldo + c] += acc;
+      }
+    }
+    __syncthreads();
+  };
   if (has2)
-    reduce_lds(X2, cg2.n, rg2, cg2, tm, cg1.n, X1, cg1.n, rg1, cg1, sd.Hl[cm - 2], sd.Wl[cm - 2], true);
+    reduce(L.x2, cg2.n, rg2, cg2, L.x1, nullptr, cg1.n, rg1, cg1, sd.Hl[cm - 2], sd.Wl[cm - 2]);
   if (has1 || has2)
-    reduce_lds(X1, cg1.n, rg1, cg1, tm, cg0.n, fb, CA_T, rg0, cg0, sd.Hl[cm - 1], sd.Wl[cm - 1], true);
+    reduce(L.x1, cg1.n, rg1, cg1, 0, &fb[0][0], CA_T, rg0, cg0, sd.Hl[cm - 1], sd.Wl[cm - 1]);
   if (has0) {
     Walk2 wk(threadIdx.x, J.tw);
-    for (int i = threadIdx.x; i < J.th * J.tw; i += SP_BLOCK, wk.next()) {
-      const int yy = wk.r, xx = wk.c;
-      fb[yy * CA_T + xx] += X0[i];
-    }
+    for (int i = threadIdx.x; i < J.th * J.tw; i += SP_BLOCK, wk.next())
+#pragma unroll
+      for (int j = 0; j < NC; ++j) fb[j][wk.r * CA_T + wk.c] += dyn[j * CS + L.x0 + i];
     __syncthreads();
   }
   // ---- store F-bar and its partial statistics (one 8x8 block per wavefront)
   const int lane = lane_id(), w = wave_id();
   const int nbx = (J.tw + 7) >> 3, nby = (J.th + 7) >> 3;
-  float wmn = INFINITY, wmx = -INFINITY, wsum = 0.f;
-  if (w < nbx * nby) {
-    const int by = w / nbx, bx = w - by * nbx;
-    const int yy = 8 * by + (lane >> 3), xx = 8 * bx + (lane & 7);
-    const bool valid = yy < J.th && xx < J.tw;
-    const float v = valid ? fb[yy * CA_T + xx] : 0.f;
-    if (valid) G(sd.fbar)[(size_t)k * Hm * Wm + (size_t)(J.y0 + yy) * Wm + J.x0 + xx] = v;
-    wmn = wave_reduce<OpMin>(valid ? v : INFINITY);
-    wmx = wave_reduce<OpMax>(valid ? v : -INFINITY);
-    wsum = wmx;
-  }
-  if (lane == 0) {
-    wacc[w][0] = wmn;
-    wacc[w][1] = wmx;
-    wacc[w][2] = wsum;
+  const bool act = w < nbx * nby;
+  const int by = act ? w / nbx : 0, bx = act ? w - by * nbx : 0;
+  const int yy = 8 * by + (lane >> 3), xx = 8 * bx + (lane & 7);
+  const bool valid = act && yy < J.th && xx < J.tw;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    float wmn = INFINITY, wmx = -INFINITY;
+    if (act) {
+      const float v = valid ? fb[j][yy * CA_T + xx] : 0.f;
+      if (valid) G(sd.fbar)[(size_t)(k0 + j) * Hm * Wm + (size_t)(J.y0 + yy) * Wm + J.x0 + xx] = v;
+      wmn = wave_reduce<OpMin>(valid ? v : INFINITY);
+      wmx = wave_reduce<OpMax>(valid ? v : -INFINITY);
+    }
+    if (lane == 0) {
+      wacc[w][j][0] = wmn;
+      wacc[w][j][1] = wmx;
+      wacc[w][j][2] = act ? wmx : 0.f;
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const gp<float> out = G(sd.fbar_part) + 3 * ((size_t)k * sd.n_cmax_tiles + J.tid);
-    out[0] = fminf(fminf(wacc[0][0], wacc[1][0]), fminf(wacc[2][0], wacc[3][0]));
-    out[1] = fmaxf(fmaxf(wacc[0][1], wacc[1][1]), fmaxf(wacc[2][1], wacc[3][1]));
-    out[2] = (wacc[0][2] + wacc[1][2]) + (wacc[2][2] + wacc[3][2]);
+  if ((int)threadIdx.x < NC) {
+    const int j = threadIdx.x;
+    const gp<float> out = G(sd.fbar_part) + 3 * ((size_t)(k0 + j) * sd.n_cmax_tiles + J.tid);
+    out[0] = fminf(fminf(wacc[0][j][0], wacc[1][j][0]), fminf(wacc[2][j][0], wacc[3][j][0]));
+    out[1] = fmaxf(fmaxf(wacc[0][j][1], wacc[1][j][1]), fmaxf(wacc[2][j][1], wacc[3][j][1]));
+    out[2] = (wacc[0][j][2] + wacc[1][j][2]) + (wacc[2][j][2] + wacc[3][j][2]);
   }
 }
 
@@ -1650,7 +1689,16 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
     case JOB_TAIL: hipLaunchKernelGGL(k_pyr<true>, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSSTATS: hipLaunchKernelGGL(k_csstats, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSFINAL: hipLaunchKernelGGL(k_csfinal, g, b, 0, st, jobs, sds, ios, io); break;
-    case JOB_CSAPPLY: hipLaunchKernelGGL(k_csapply, g, b, lds, st, jobs, sds, ios, io); break;
+    case JOB_CSAPPLY:   // flag: channels per workgroup
+      if (flag == 8)
+        hipLaunchKernelGGL(k_csapply<8>, g, b, lds, st, jobs, sds, ios, io);
+      else if (flag == 4)
+        hipLaunchKernelGGL(k_csapply<4>, g, b, lds, st, jobs, sds, ios, io);
+      else if (flag == 2)
+        hipLaunchKernelGGL(k_csapply<2>, g, b, lds, st, jobs, sds, ios, io);
+      else
+        hipLaunchKernelGGL(k_csapply<1>, g, b, lds, st, jobs, sds, ios, io);
+      break;
     case JOB_CONSP: hipLaunchKernelGGL(k_consp, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_SMAX: hipLaunchKernelGGL(k_smax, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_KALMAN: hipLaunchKernelGGL(k_kalman, g, b, 0, st, jobs, sds, ios, io); break;
@@ -1721,6 +1769,11 @@ hipError_t sp_launch_batch_copy_out(int n, const BatchState* st, const StreamDes
 
 hipError_t sp_csapply_reserve_lds(size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csapply), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  const void* fns[4] = {reinterpret_cast<const void*>(&k_csapply<1>), reinterpret_cast<const void*>(&k_csapply<2>),
+                        reinterpret_cast<const void*>(&k_csapply<4>), reinterpret_cast<const void*>(&k_csapply<8>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
