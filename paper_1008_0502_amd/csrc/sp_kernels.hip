@@ -812,8 +812,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pyr(const Job* __restrict__ jobs,
 
 // ---------------------------------------------------------------- centre-surround statistics
 // A 16x16 tile of the centre level c: the 8 centre maps and, per pair (c, s), the
-// footprint of the tile on level s are staged in LDS; each wavefront then takes one
-// 8x8 block and reduces min, max and block maximum of every map with DPP.
+// footprint of the tile on level s are staged in LDS; each wavefront then takes two
+// channels, reduces every map's four 8x8 blocks (a 2x2 quad per lane, DPP within each
+// 16-lane row) and writes the tile's (min, max, sum of block maxima).
 constexpr int CS_T = 16;
 constexpr int CS_F = CS_T / 2 + 2;      // footprint edge on a coarser level (offset >= 1)
 
@@ -841,7 +842,6 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
                                                       const StepIO* __restrict__ ios, StepIO io0) {
   __shared__ float cen[SP_NCH][CS_T * CS_T];
   __shared__ float sur[4][SP_NCH][CS_F * CS_F];
-  __shared__ float acc[4][4 * SP_NCH][3];   // [wave][pair-in-centre * 8 + k][min, max, sum]
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const float* ckpt = IOF(ckpt);
@@ -882,48 +882,66 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
     }
   }
   lds_wait();
-  for (int i = threadIdx.x; i < 4 * npc * SP_NCH; i += SP_BLOCK) {
-    const int ww = i / (npc * SP_NCH), m = i - ww * npc * SP_NCH;
-    acc[ww][m][0] = INFINITY;
-    acc[ww][m][1] = -INFINITY;
-    acc[ww][m][2] = 0.f;
-  }
   __syncthreads();
-  const int nbx = (J.tw + 7) >> 3, nby = (J.th + 7) >> 3;
-  if (w < nbx * nby) {
-    const int by = w / nbx, bx = w - by * nbx;
-    const int yy = 8 * by + (lane >> 3), xx = 8 * bx + (lane & 7);
-    const int y = J.y0 + yy, x = J.x0 + xx;
-    const bool valid = yy < J.th && xx < J.tw;
-    const int yc = min(y, J.y0 + J.th - 1), xc = min(x, J.x0 + J.tw - 1);
-    for (int q = 0; q < npc; ++q) {
-      const int s = sd.ps[plist[q]], d = s - c;
-      const Tap ty = bilinear_tap(yc, d, sd.Hl[s]), tx = bilinear_tap(xc, d, sd.Wl[s]);
+  // Wavefront w takes channels 2w and 2w+1 of every pair; its 64 lanes cover the tile as
+  // four 16-lane rows, one 8x8 block per row and a 2x2 pixel quad per lane.  Pixels
+  // beyond a ragged edge repeat the last valid row/column of their block (no effect on
+  // min and max); blocks with no valid pixel are left out.
+  const int blk = lane >> 4, by = blk >> 1, bx = blk & 1;
+  const int qy = 8 * by + 2 * ((lane >> 2) & 3), qx = 8 * bx + 2 * (lane & 3);
+  int yc[2], xc[2];
 #pragma unroll
-      for (int k = 0; k < SP_NCH; ++k) {
-        const float up = bilinear_lds(sur[q][k], CS_F, ty, tx, fp[q].y0, fp[q].x0);
-        const float F = fabsf(cen[k][(yc - J.y0) * CS_T + (xc - J.x0)] - up);
-        const float bmn = wave_reduce<OpMin>(valid ? F : INFINITY);
-        const float bmx = wave_reduce<OpMax>(valid ? F : -INFINITY);
-        if (lane == 0) {
-          acc[w][q * SP_NCH + k][0] = bmn;
-          acc[w][q * SP_NCH + k][1] = bmx;
-          acc[w][q * SP_NCH + k][2] = bmx;
+  for (int u = 0; u < 2; ++u) {
+    yc[u] = J.y0 + min(qy + u, J.th - 1);
+    xc[u] = J.x0 + min(qx + u, J.tw - 1);
+  }
+  bool bval[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bval[i] = 8 * (i >> 1) < J.th && 8 * (i & 1) < J.tw;
+  for (int q = 0; q < npc; ++q) {
+    const int p = plist[q], s = sd.ps[p], d = s - c;
+    const Foot f = fp[q];
+    Tap ty[2], tx[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      ty[u] = bilinear_tap(yc[u], d, sd.Hl[s]);
+      tx[u] = bilinear_tap(xc[u], d, sd.Wl[s]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int k = 2 * w + kk;
+      float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const float up = bilinear_lds(sur[q][k], CS_F, ty[u], tx[v], f.y0, f.x0);
+          const float F = fabsf(cen[k][(yc[u] - J.y0) * CS_T + (xc[v] - J.x0)] - up);
+          mn = fminf(mn, F);
+          mx = fmaxf(mx, F);
         }
+      // 8x8 block minimum and maximum: DPP within each 16-lane row
+      mn = fminf(mn, dpp_f<0xB1>(mn));
+      mx = fmaxf(mx, dpp_f<0xB1>(mx));
+      mn = fminf(mn, dpp_f<0x4E>(mn));
+      mx = fmaxf(mx, dpp_f<0x4E>(mx));
+      mn = fminf(mn, dpp_f<0x141>(mn));
+      mx = fmaxf(mx, dpp_f<0x141>(mx));
+      mn = fminf(mn, dpp_f<0x140>(mn));
+      mx = fmaxf(mx, dpp_f<0x140>(mx));
+      float bmn[4], bmx[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        bmn[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i)) : INFINITY;
+        bmx[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i)) : -INFINITY;
+      }
+      if (lane == 0) {
+        const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)k * sd.ntiles_lvl[c] + J.tid);
+        out[0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
+        out[1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
+        out[2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) + ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
       }
     }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < npc * SP_NCH; i += SP_BLOCK) {
-    const int q = i / SP_NCH, k = i - q * SP_NCH;
-    const int p = plist[q];
-    const float mn = fminf(fminf(acc[0][i][0], acc[1][i][0]), fminf(acc[2][i][0], acc[3][i][0]));
-    const float mx = fmaxf(fmaxf(acc[0][i][1], acc[1][i][1]), fmaxf(acc[2][i][1], acc[3][i][1]));
-    const float sm = (acc[0][i][2] + acc[1][i][2]) + (acc[2][i][2] + acc[3][i][2]);
-    const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)k * sd.ntiles_lvl[c] + J.tid);
-    out[0] = mn;
-    out[1] = mx;
-    out[2] = sm;
   }
 }
 
