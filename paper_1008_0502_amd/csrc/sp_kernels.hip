@@ -343,31 +343,47 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
   const int nr = th + ((want_d2 && y0 + th < H) ? 1 : 0);
   const int xs = want_d2 ? max(x0 - 1, 0) : x0;              // first staged column
   const int xe = want_d2 ? min(x0 + tw, W - 1) : x0 + tw - 1;  // last staged column
-  // a staged row starts at the 4-pixel group holding (y, xs): at most 3 leading pixels
+  // a staged row starts at the 4-pixel group holding (y, xs): at most 3 leading pixels.
+  // Up to RU groups per thread are loaded before any is stored, so their global loads
+  // are in flight together.
   const int NG = (xe - xs + 3) / 4 + 1;
+  constexpr int RU = 4;
   Walk2 wk(threadIdx.x, NG);
-  for (int i = threadIdx.x; i < nr * NG; i += SP_BLOCK, wk.next()) {
-    const int r = wk.r, gi = wk.c;
-    const long long rowp = (long long)(y0 + r) * W;
-    const long long q = ((rowp + xs) & ~3LL) + 4 * gi;
-    if (q > rowp + xe) continue;
-    uint32_t c[4];
-    if (al && q + 3 < HW) {
-      const gp<const uint32_t> w = (gp<const uint32_t>)(rgb + 3 * q);
-      const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-      c[0] = w0 & 0xffffffu;
-      c[1] = (w0 >> 24) | ((w1 & 0xffffu) << 8);
-      c[2] = (w1 >> 16) | ((w2 & 0xffu) << 16);
-      c[3] = w2 >> 8;
-    } else {
+  for (int i0 = threadIdx.x; i0 < nr * NG; i0 += RU * SP_BLOCK) {
+    uint32_t c[RU][4];
+    int slot[RU];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const long long o = 3 * (q + j);
-        c[j] = (q + j < HW) ? ((uint32_t)rgb[o] | ((uint32_t)rgb[o + 1] << 8) | ((uint32_t)rgb[o + 2] << 16)) : 0u;
+    for (int u = 0; u < RU; ++u) {
+      const int r = wk.r, gi = wk.c;
+      wk.next();
+      slot[u] = -1;
+      c[u][0] = c[u][1] = c[u][2] = c[u][3] = 0u;
+      if (i0 + u * SP_BLOCK >= nr * NG) continue;
+      const long long rowp = (long long)(y0 + r) * W;
+      const long long q = ((rowp + xs) & ~3LL) + 4 * gi;
+      if (q > rowp + xe) continue;
+      slot[u] = r * LW + 4 * gi;
+      if (al && q + 3 < HW) {
+        const gp<const uint32_t> w = (gp<const uint32_t>)(rgb + 3 * q);
+        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+        c[u][0] = w0 & 0xffffffu;
+        c[u][1] = (w0 >> 24) | ((w1 & 0xffffu) << 8);
+        c[u][2] = (w1 >> 16) | ((w2 & 0xffu) << 16);
+        c[u][3] = w2 >> 8;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const long long o = 3 * (q + j);
+          c[u][j] = (q + j < HW) ? ((uint32_t)rgb[o] | ((uint32_t)rgb[o + 1] << 8) | ((uint32_t)rgb[o + 2] << 16)) : 0u;
+        }
       }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Pk[r][4 * gi + j] = c[j];
+    for (int u = 0; u < RU; ++u)
+      if (slot[u] >= 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) (&Pk[0][0])[slot[u] + j] = c[u][j];
+      }
   }
   __syncthreads();
   uint32_t mx = 0, d2 = 0;
@@ -1016,39 +1032,42 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
     rg2 = finer_range(rg1, sd.Hl[cm - 2]);
     cg2 = finer_range(cg1, sd.Wl[cm - 2]);
   }
-  // ---- table of the pairs per centre level
-  if (threadIdx.x == 0) {
-    int cnt[3] = {0, 0, 0};
-    int off = L.foot0;
-    for (int p = 0; p < sd.n_pairs; ++p) {
-      const int c = sd.pc[p], r = cm - c, s = sd.ps[p];
-      if (cnt[r] < 4) {
-        const Range rr = (r == 0) ? rg0 : ((r == 1) ? rg1 : rg2);
-        const Range cc = (r == 0) ? cg0 : ((r == 1) ? cg1 : cg2);
-        const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], sd.Wl[s]);
-        const int q = cnt[r]++;
-        CaPair& P = cpt[r][q];
-        P.off = off;
-        P.fy0 = f.y0;
-        P.fx0 = f.x0;
-        P.fw = f.w;
-        P.fh = f.h;
-        P.d = s - c;
-        P.Hs = sd.Hl[s];
-        P.Ws = sd.Wl[s];
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          const NParams np = load_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k0 + j));
-          cnp[r][q][j][0] = np.mn;
-          cnp[r][q][j][1] = np.flat ? 0.f : np.inv;
-          cnp[r][q][j][2] = np.flat ? 0.f : np.scale;
-        }
-      }
-      off += csapply_foot_cap(r, s - c);
+  // ---- table of the pairs per centre level: thread p fills pair p (its slot and LDS
+  // offset follow from the pairs before it), so the loads of all pairs overlap
+  if ((int)threadIdx.x < sd.n_pairs) {
+    const int p = threadIdx.x;
+    const int c = sd.pc[p], r = cm - c, s = sd.ps[p];
+    int q = 0, off = L.foot0;
+    for (int pp = 0; pp < p; ++pp) {
+      q += (sd.pc[pp] == c) ? 1 : 0;
+      off += csapply_foot_cap(cm - sd.pc[pp], sd.ps[pp] - sd.pc[pp]);
     }
-    ncp[0] = cnt[0];
-    ncp[1] = cnt[1];
-    ncp[2] = cnt[2];
+    if (q < 4) {
+      const Range rr = (r == 0) ? rg0 : ((r == 1) ? rg1 : rg2);
+      const Range cc = (r == 0) ? cg0 : ((r == 1) ? cg1 : cg2);
+      const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], sd.Wl[s]);
+      CaPair& P = cpt[r][q];
+      P.off = off;
+      P.fy0 = f.y0;
+      P.fx0 = f.x0;
+      P.fw = f.w;
+      P.fh = f.h;
+      P.d = s - c;
+      P.Hs = sd.Hl[s];
+      P.Ws = sd.Wl[s];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const NParams np = load_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k0 + j));
+        cnp[r][q][j][0] = np.mn;
+        cnp[r][q][j][1] = np.flat ? 0.f : np.inv;
+        cnp[r][q][j][2] = np.flat ? 0.f : np.scale;
+      }
+    }
+  }
+  if (threadIdx.x < 3) {
+    int n = 0;
+    for (int p = 0; p < sd.n_pairs; ++p) n += (cm - sd.pc[p] == (int)threadIdx.x) ? 1 : 0;
+    ncp[threadIdx.x] = min(n, 4);
   }
   for (int i = threadIdx.x; i < NC * CA_T * CA_T; i += SP_BLOCK) (&fb[0][0])[i] = 0.f;
   __syncthreads();
