@@ -863,19 +863,6 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
   const float* ckpt = IOF(ckpt);
   const int c = J.a, Hc = sd.Hl[c], Wc = sd.Wl[c];
   const int lane = lane_id(), w = wave_id();
-  __shared__ int plist[4];
-  __shared__ Foot fp[4];
-  int npc = 0;
-  for (int p = 0; p < sd.n_pairs; ++p)
-    if (sd.pc[p] == c && npc < 4) {
-      if (threadIdx.x == 0) {
-        const int s = sd.ps[p];
-        plist[npc] = p;
-        fp[npc] = footprint(J.y0, J.th, J.x0, J.tw, s - c, sd.Hl[s], sd.Wl[s]);
-      }
-      ++npc;
-    }
-  __syncthreads();
   // stage the centre tile of all channels
   const float* cptr[SP_NCH];
 #pragma unroll
@@ -886,15 +873,19 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
 #pragma unroll
     for (int k = 0; k < SP_NCH; ++k) lds_load(&cen[k][i], cptr[k] + o);
   }
-  // stage the surround footprints
-  for (int q = 0; q < npc; ++q) {
-    const int s = sd.ps[plist[q]], Ws = sd.Wl[s];
+  // stage the surround footprints of the pairs of centre c (slot q in pair order; the
+  // footprint geometry is scalar work, recomputed below instead of kept in LDS)
+  int npc = 0;
+  for (int p = 0; p < sd.n_pairs && npc < 4; ++p) {
+    if (sd.pc[p] != c) continue;
+    const int s = sd.ps[p], Ws = sd.Wl[s], q = npc++;
+    const Foot f = footprint(J.y0, J.th, J.x0, J.tw, s - c, sd.Hl[s], Ws);
     // [k][CS_F][CS_F]: the destination follows the loop index; lanes outside the
     // footprint stay idle
     for (int i = threadIdx.x; i < SP_NCH * CS_F * CS_F; i += SP_BLOCK) {
       const int k = i / (CS_F * CS_F), r = i - k * (CS_F * CS_F), fy = r / CS_F, fx = r - fy * CS_F;
-      if (fy < fp[q].h && fx < fp[q].w)
-        lds_load(&sur[q][0][0] + i, chan_ptr(sd, ckpt, k, s) + (size_t)(fp[q].y0 + fy) * Ws + fp[q].x0 + fx);
+      if (fy < f.h && fx < f.w)
+        lds_load(&sur[q][0][0] + i, chan_ptr(sd, ckpt, k, s) + (size_t)(f.y0 + fy) * Ws + f.x0 + fx);
     }
   }
   lds_wait();
@@ -914,9 +905,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
   bool bval[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) bval[i] = 8 * (i >> 1) < J.th && 8 * (i & 1) < J.tw;
-  for (int q = 0; q < npc; ++q) {
-    const int p = plist[q], s = sd.ps[p], d = s - c;
-    const Foot f = fp[q];
+  int q = -1;
+  for (int p = 0; p < sd.n_pairs && q + 1 < npc; ++p) {
+    if (sd.pc[p] != c) continue;
+    ++q;
+    const int s = sd.ps[p], d = s - c;
+    const Foot f = footprint(J.y0, J.th, J.x0, J.tw, d, sd.Hl[s], sd.Wl[s]);
     Tap ty[2], tx[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -1032,8 +1026,47 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
     rg2 = finer_range(rg1, sd.Hl[cm - 2]);
     cg2 = finer_range(cg1, sd.Wl[cm - 2]);
   }
-  // ---- table of the pairs per centre level: thread p fills pair p (its slot and LDS
-  // offset follow from the pairs before it), so the loads of all pairs overlap
+  // ---- one round trip: centre regions and every pair's footprint for each channel of
+  // the group (the geometry is scalar work), then the pair table, whose N-parameter
+  // loads queue behind the staging loads
+  auto stage = [&](Range rr, Range cc, int c, int xoff) {
+    const int Wc = sd.Wl[c];
+    const int n = rr.n * cc.n;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const float* Xc = chan_ptr(sd, ckpt, k0 + j, c);
+      float* X = dyn + j * CS + xoff;
+      Walk2 wk(threadIdx.x, cc.n);
+      for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next())
+        lds_load(X + i, Xc + (size_t)(rr.lo + wk.r) * Wc + cc.lo + wk.c);
+    }
+  };
+  if (has0) stage(rg0, cg0, cm, L.x0);
+  if (has1) stage(rg1, cg1, cm - 1, L.x1);
+  if (has2) stage(rg2, cg2, cm - 2, L.x2);
+  if (!has1 && has2)
+    for (int j = 0; j < NC; ++j)
+      for (int i = threadIdx.x; i < rg1.n * cg1.n; i += SP_BLOCK) dyn[j * CS + L.x1 + i] = 0.f;
+  {
+    int off = L.foot0;
+    for (int p = 0; p < sd.n_pairs; ++p) {
+      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], Ws = sd.Wl[s];
+      const Range rr = (r == 0) ? rg0 : ((r == 1) ? rg1 : rg2);
+      const Range cc = (r == 0) ? cg0 : ((r == 1) ? cg1 : cg2);
+      const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], Ws);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const float* Xs = chan_ptr(sd, ckpt, k0 + j, s);
+        float* dst = dyn + j * CS + off;
+        Walk2 wk(threadIdx.x, f.w);
+        for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK, wk.next())
+          lds_load(dst + i, Xs + (size_t)(f.y0 + wk.r) * Ws + f.x0 + wk.c);
+      }
+      off += csapply_foot_cap(r, s - c);
+    }
+  }
+  // pair table: thread p fills pair p (its slot and LDS offset follow from the pairs
+  // before it)
   if ((int)threadIdx.x < sd.n_pairs) {
     const int p = threadIdx.x;
     const int c = sd.pc[p], r = cm - c, s = sd.ps[p];
@@ -1070,38 +1103,6 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
     ncp[threadIdx.x] = min(n, 4);
   }
   for (int i = threadIdx.x; i < NC * CA_T * CA_T; i += SP_BLOCK) (&fb[0][0])[i] = 0.f;
-  __syncthreads();
-  // ---- one round trip: centre regions and footprints of every channel
-  auto stage = [&](Range rr, Range cc, int c, int xoff) {
-    const int Wc = sd.Wl[c];
-    const int n = rr.n * cc.n;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const float* Xc = chan_ptr(sd, ckpt, k0 + j, c);
-      float* X = dyn + j * CS + xoff;
-      Walk2 wk(threadIdx.x, cc.n);
-      for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next())
-        lds_load(X + i, Xc + (size_t)(rr.lo + wk.r) * Wc + cc.lo + wk.c);
-    }
-  };
-  if (has0) stage(rg0, cg0, cm, L.x0);
-  if (has1) stage(rg1, cg1, cm - 1, L.x1);
-  if (has2) stage(rg2, cg2, cm - 2, L.x2);
-  if (!has1 && has2)
-    for (int j = 0; j < NC; ++j)
-      for (int i = threadIdx.x; i < rg1.n * cg1.n; i += SP_BLOCK) dyn[j * CS + L.x1 + i] = 0.f;
-  for (int r = 0; r < 3; ++r)
-    for (int q = 0; q < ncp[r]; ++q) {
-      const CaPair& P = cpt[r][q];
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const float* Xs = chan_ptr(sd, ckpt, k0 + j, cm - r + P.d);
-        float* dst = dyn + j * CS + P.off;
-        Walk2 wk(threadIdx.x, P.fw);
-        for (int i = threadIdx.x; i < P.fh * P.fw; i += SP_BLOCK, wk.next())
-          lds_load(dst + i, Xs + (size_t)(P.fy0 + wk.r) * P.Ws + P.fx0 + wk.c);
-      }
-    }
   lds_wait();
   __syncthreads();
   // ---- N(F) summed over the pairs of each centre level, in place of the centre values
