@@ -122,11 +122,11 @@ __device__ double block_sum_d(double v, double* sh256) {
 
 // Exact 64-bit sum over the workgroup: butterfly within each wavefront, then the four
 // wavefront sums (two barriers).
-__device__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh256) {
+__device__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh4) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if (lane_id() == 0) sh256[wave_id()] = v;
+  if (lane_id() == 0) sh4[wave_id()] = v;
   __syncthreads();
-  const unsigned long long r = (sh256[0] + sh256[1]) + (sh256[2] + sh256[3]);
+  const unsigned long long r = (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
   __syncthreads();
   return r;
 }
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
                                                   const StepIO* __restrict__ ios, StepIO io0, int want_d2) {
   constexpr int LW = SP_RGB_TC + 8;
   __shared__ uint32_t Pk[SP_RGB_TR + 1][LW];
-  __shared__ unsigned long long sh[SP_BLOCK];
+  __shared__ unsigned long long sh[4];
   __shared__ uint32_t shm[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
@@ -475,17 +475,22 @@ __device__ __forceinline__ float rgb_d2(uint32_t a, uint32_t b) {
 // Level-0 features of the region a level-1 tile needs, then one blur + decimation.
 // With io.pairwise set it also writes the pairwise capacities of the tile's level-0
 // pixels (rows 2*y0 .. 2*(y0+th)-1) from the same staged region: every E, S, SE, SW
-// neighbour of those pixels lies inside it.
+// neighbour of those pixels lies inside it.  All region bytes are loaded into
+// registers at once (no branch between the loads); the features then go through LDS
+// in two halves of the tile (TH/2 output rows, TH+3 region rows each), which keeps the
+// launch at 8 workgroups per CU.
 template <int TH, int TW>
 __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
                                                    const StreamDesc* __restrict__ sds,
                                                    const StepIO* __restrict__ ios, StepIO io0) {
-  constexpr int RH = 2 * TH + 3, RW = 2 * TW + 3;
-  __shared__ float F[4][RH][RW];
-  __shared__ float Hb[4][RH][TW];
+  constexpr int RH = 2 * TH + 3, RW = 2 * TW + 3;   // region of the whole tile
+  constexpr int HR = TH + 3;                        // region rows of one half
+  constexpr int NP = (RH * RW + SP_BLOCK - 1) / SP_BLOCK;
+  __shared__ float F[4][HR][RW];
+  __shared__ float Hb[4][HR][TW];
   __shared__ uint32_t shm[4];
-  __shared__ unsigned long long sh[SP_BLOCK];
-  static_assert(4 * RH * TW >= RH * RW, "packed colours fit in the row-blur buffer");
+  __shared__ unsigned long long sh[4];
+  static_assert(4 * HR * TW >= HR * RW, "packed colours fit in the row-blur buffer");
   uint32_t* Pk = reinterpret_cast<uint32_t*>(&Hb[0][0][0]);  // packed colours until the blur
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
@@ -493,26 +498,17 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
   const uint8_t* __restrict__ prev = IOF(rgb_prev);
   float* ckpt = IOF(ckpt);
   const gp<float> pairw = G(IOF(pairwise));
-  uint32_t smax = 0;
-  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) smax = max(smax, sd.rgb_max_part[i]);
-  smax = wave_max_u(smax);
-  if (lane_id() == 0) shm[wave_id()] = smax;
-  __syncthreads();
-  smax = max(max(shm[0], shm[1]), max(shm[2], shm[3]));
   const int H = sd.H, W = sd.W;
   const int Y0 = 2 * J.y0 - 2, X0 = 2 * J.x0 - 2;
-  // four region pixels per thread and pass: all their byte loads are issued (through
-  // global-address-space pointers, with no branch in between) before the first is used
-  constexpr int FU = 4;
   typedef const __attribute__((address_space(1))) uint8_t* gbytes;
   const gbytes grgb = (gbytes)rgb;
   const gbytes gprev = (gbytes)prev;
-  for (int i0 = threadIdx.x; i0 < RH * RW; i0 += FU * SP_BLOCK) {
-    uint32_t cv[FU], pv[FU];
-    size_t o[FU];
+  uint32_t cv[NP], pv[NP];
+  {
+    size_t o[NP];
 #pragma unroll
-    for (int u = 0; u < FU; ++u) {
-      const int i = min(i0 + u * SP_BLOCK, RH * RW - 1);
+    for (int u = 0; u < NP; ++u) {
+      const int i = min((int)threadIdx.x + u * SP_BLOCK, RH * RW - 1);
       const int ry = i / RW, rx = i - ry * RW;
       const int y = clampi(Y0 + ry, 0, H - 1), x = clampi(X0 + rx, 0, W - 1);
       o[u] = ((size_t)y * W + x) * 3;
@@ -520,81 +516,106 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
     }
     if (prev) {
 #pragma unroll
-      for (int u = 0; u < FU; ++u) pv[u] = (uint32_t)gprev[o[u]] + (uint32_t)gprev[o[u] + 1] + (uint32_t)gprev[o[u] + 2];
+      for (int u = 0; u < NP; ++u) pv[u] = (uint32_t)gprev[o[u]] + (uint32_t)gprev[o[u] + 1] + (uint32_t)gprev[o[u] + 2];
     }
+  }
+  // largest R+G+B of the frame, from the colour-statistics partials
+  uint32_t smax = 0;
+  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) smax = max(smax, sd.rgb_max_part[i]);
+  smax = wave_max_u(smax);
+  if (lane_id() == 0) shm[wave_id()] = smax;
+  __syncthreads();
+  smax = max(max(shm[0], shm[1]), max(shm[2], shm[3]));
+  float fI[NP], fRG[NP], fBY[NP], fM[NP];
 #pragma unroll
-    for (int u = 0; u < FU; ++u) {
-      const int i = i0 + u * SP_BLOCK;
-      if (i >= RH * RW) break;
-      const int ry = i / RW, rx = i - ry * RW;
-      const int R8 = (int)(cv[u] & 0xff), G8 = (int)((cv[u] >> 8) & 0xff), B8 = (int)(cv[u] >> 16);
-      const int S8 = R8 + G8 + B8;
-      const float I = (float)S8 / 765.f;
-      float rg = 0.f, by = 0.f;
-      if ((uint32_t)(10 * S8) > smax) {
-        const float inv = 3.f / (float)S8;
-        const float rp = (float)R8 * inv, gp = (float)G8 * inv, bp = (float)B8 * inv;
-        const float Rc = fmaxf(0.f, rp - (gp + bp) * 0.5f);
-        const float Gc = fmaxf(0.f, gp - (rp + bp) * 0.5f);
-        const float Bc = fmaxf(0.f, bp - (rp + gp) * 0.5f);
-        const float Yc = fmaxf(0.f, fminf(rp, gp) - bp);
-        rg = Rc - Gc;
-        by = Bc - Yc;
-      }
-      const float M = prev ? fabsf(I - (float)pv[u] / 765.f) : 0.f;
-      F[0][ry][rx] = I;
-      F[1][ry][rx] = rg;
-      F[2][ry][rx] = by;
-      F[3][ry][rx] = M;
-      if (pairw) Pk[i] = cv[u];
+  for (int u = 0; u < NP; ++u) {
+    const int R8 = (int)(cv[u] & 0xff), G8 = (int)((cv[u] >> 8) & 0xff), B8 = (int)(cv[u] >> 16);
+    const int S8 = R8 + G8 + B8;
+    const float I = (float)S8 / 765.f;
+    float rg = 0.f, by = 0.f;
+    if ((uint32_t)(10 * S8) > smax) {
+      const float inv = 3.f / (float)S8;
+      const float rp = (float)R8 * inv, gp = (float)G8 * inv, bp = (float)B8 * inv;
+      const float Rc = fmaxf(0.f, rp - (gp + bp) * 0.5f);
+      const float Gc = fmaxf(0.f, gp - (rp + bp) * 0.5f);
+      const float Bc = fmaxf(0.f, bp - (rp + gp) * 0.5f);
+      const float Yc = fmaxf(0.f, fminf(rp, gp) - bp);
+      rg = Rc - Gc;
+      by = Bc - Yc;
     }
+    fI[u] = I;
+    fRG[u] = rg;
+    fBY[u] = by;
+    fM[u] = prev ? fabsf(I - (float)pv[u] / 765.f) : 0.f;
   }
-  if (pairw) {
-    // beta_from_parts synchronises the block before and after its reduction
-    const float beta = beta_from_parts(sd, sh);
-    const int ylo = 2 * J.y0, yhi = min(H, 2 * (J.y0 + J.th));
-    const int xlo = 2 * J.x0, xhi = min(W, 2 * (J.x0 + J.tw));
-    const int cw = xhi - xlo, n = (yhi - ylo) * cw;
-    const size_t plane = (size_t)H * W;
-    const float lam = sd.lam, potts = sd.potts;
-    Walk2 wk(threadIdx.x, cw);
-    for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
-      const int yy = wk.r, xx = wk.c;
-      const int y = ylo + yy, x = xlo + xx;
-      const int r = (y - Y0) * RW + (x - X0);
-      const uint32_t c0 = Pk[r];
-      const size_t o = (size_t)y * W + x;
-      const bool e = x + 1 < W, s = y + 1 < H;
-      pairw[o] = e ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + 1]), false) : 0.f;
-      pairw[plane + o] = s ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW]), false) : 0.f;
-      pairw[2 * plane + o] = (s && e) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW + 1]), true) : 0.f;
-      pairw[3 * plane + o] = (s && x > 0) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW - 1]), true) : 0.f;
-    }
-    if (J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) G(IOF(beta_out))[0] = beta;
-  }
-  __syncthreads();
-  down_region<TH, TW, RH, RW>(F, Hb, 4);
-  __syncthreads();
+  float beta = 0.f;
   const int H1 = sd.Hl[1], W1 = sd.Wl[1];
   const gp<float> dst = G((sd.c_min == 1 && ckpt) ? ckpt : sd.base[1]);
-  const size_t plane = (size_t)H1 * W1;
-  for (int i = threadIdx.x; i < TH * TW; i += SP_BLOCK) {
-    const int yy = i / TW, xx = i - yy * TW;
-    const int y = J.y0 + yy, x = J.x0 + xx;
-    if (yy < J.th && xx < J.tw && y < H1 && x < W1) {
+  const size_t plane1 = (size_t)H1 * W1;
+  for (int h = 0; h < 2; ++h) {
+    if (h == 1 && J.th <= TH / 2) break;
+    const int r0 = h * TH;   // first region row of this half
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float v = kB0 * Hb[c][2 * yy][xx] + kB1 * Hb[c][2 * yy + 1][xx] + kB2 * Hb[c][2 * yy + 2][xx] +
-                        kB1 * Hb[c][2 * yy + 3][xx] + kB0 * Hb[c][2 * yy + 4][xx];
-        dst[c * plane + (size_t)y * W1 + x] = v;
+    for (int u = 0; u < NP; ++u) {
+      const int i = threadIdx.x + u * SP_BLOCK;
+      const int ry = i / RW, rx = i - ry * RW;
+      if (i < RH * RW && ry >= r0 && ry < r0 + HR) {
+        const int r = ry - r0;
+        F[0][r][rx] = fI[u];
+        F[1][r][rx] = fRG[u];
+        F[2][r][rx] = fBY[u];
+        F[3][r][rx] = fM[u];
+        if (pairw) Pk[r * RW + rx] = cv[u];
       }
     }
+    if (pairw) {
+      if (h == 0)
+        beta = beta_from_parts(sd, sh);   // synchronises the block before and after its reduction
+      else
+        __syncthreads();
+      // level-0 rows of this half: 2*y0 + r0 .. +TH-1 (region rows r0+2 .. r0+TH+1)
+      const int ylo = 2 * J.y0 + r0, yhi = min(min(H, 2 * (J.y0 + J.th)), ylo + TH);
+      const int xlo = 2 * J.x0, xhi = min(W, 2 * (J.x0 + J.tw));
+      const int cw = xhi - xlo, n = max(0, yhi - ylo) * cw;
+      const size_t plane = (size_t)H * W;
+      const float lam = sd.lam, potts = sd.potts;
+      Walk2 wk(threadIdx.x, cw);
+      for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
+        const int y = ylo + wk.r, x = xlo + wk.c;
+        const int r = (y - Y0 - r0) * RW + (x - X0);
+        const uint32_t c0 = Pk[r];
+        const size_t o = (size_t)y * W + x;
+        const bool e = x + 1 < W, s = y + 1 < H;
+        pairw[o] = e ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + 1]), false) : 0.f;
+        pairw[plane + o] = s ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW]), false) : 0.f;
+        pairw[2 * plane + o] = (s && e) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW + 1]), true) : 0.f;
+        pairw[3 * plane + o] = (s && x > 0) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW - 1]), true) : 0.f;
+      }
+      if (h == 0 && J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) G(IOF(beta_out))[0] = beta;
+    }
+    __syncthreads();
+    down_region<TH / 2, TW, HR, RW>(F, Hb, 4);
+    __syncthreads();
+    for (int i = threadIdx.x; i < (TH / 2) * TW; i += SP_BLOCK) {
+      const int yr = i / TW, xx = i - yr * TW;
+      const int yy = h * (TH / 2) + yr;
+      const int y = J.y0 + yy, x = J.x0 + xx;
+      if (yy < J.th && xx < J.tw && y < H1 && x < W1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float v = kB0 * Hb[c][2 * yr][xx] + kB1 * Hb[c][2 * yr + 1][xx] + kB2 * Hb[c][2 * yr + 2][xx] +
+                          kB1 * Hb[c][2 * yr + 3][xx] + kB0 * Hb[c][2 * yr + 4][xx];
+          dst[c * plane1 + (size_t)y * W1 + x] = v;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
 // ---- jobs of the pyramid kernel (one of DOWN, GABOR, TAIL per workgroup)
 constexpr int DT = 16, DR = 2 * DT + 3;                         // down tile and its source region
-constexpr int DOWN_LDS = 4 * DR * DR + 4 * DR * DT;             // floats
+constexpr int DOWN_LDS = 4 * DR * DR;                           // floats (the row pass reuses it)
 constexpr int GT = 16, GRM = GT + 2 * SP_MAXR;                  // Gabor tile and its region
 constexpr int GAB_LDS = GRM * (GRM + 1) + 4 * GT * (GRM + 1) + 4 * (2 * SP_MAXR + 1);
 constexpr int TAIL_LDS = SP_TAIL_SRC + SP_TAIL_ALT + SP_TAIL_HB + SP_TAIL_V + 4 * (2 * SP_MAXR + 1);
@@ -617,8 +638,7 @@ __device__ __forceinline__ void load_taps(const StreamDesc& sd, int n, float* ta
 
 // level a -> a+1 of the 4 base channels for one 16x16 tile of level a+1
 __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float* smem) {
-  float* F = smem;                 // [4][DR][DR]
-  float* Hb = smem + 4 * DR * DR;  // [4][DR][DT]
+  float* F = smem;                 // [4][DR][DR]; then the row pass [4][DR][DT] in its place
   const int l = J.a;
   const int Hs = sd.Hl[l], Ws = sd.Wl[l];
   const float* src = base_ptr(sd, ckpt, l);
@@ -632,12 +652,27 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   }
   lds_wait();
   __syncthreads();
-  for (int i = threadIdx.x; i < 4 * DR * DT; i += SP_BLOCK) {
-    const int cr = i / DT, j = i - cr * DT;     // cr = c * DR + r
-    const float* row = F + cr * DR + 2 * j;
-    Hb[i] = kB0 * row[0] + kB1 * row[1] + kB2 * row[2] + kB1 * row[3] + kB0 * row[4];
+  // row pass of each channel into registers, then into the start of that channel's own
+  // staged region (no longer read): the launch keeps 8 workgroups per CU
+  constexpr int NH = (DR * DT + SP_BLOCK - 1) / SP_BLOCK;
+  for (int c = 0; c < 4; ++c) {
+    float hv[NH];
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      const int i = threadIdx.x + k * SP_BLOCK;
+      const int r = min(i / DT, DR - 1), j = i % DT;
+      const float* row = F + (c * DR + r) * DR + 2 * j;
+      hv[k] = kB0 * row[0] + kB1 * row[1] + kB2 * row[2] + kB1 * row[3] + kB0 * row[4];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      const int i = threadIdx.x + k * SP_BLOCK;
+      if (i < DR * DT) F[c * DR * DR + i] = hv[k];
+    }
   }
   __syncthreads();
+  const float* Hb = F;   // channel c's row pass at c * DR * DR, [DR][DT]
   const int Hd = sd.Hl[l + 1], Wd = sd.Wl[l + 1];
   const gp<float> dst = level_dst(sd, ckpt, l + 1);
   const size_t plane = (size_t)Hd * Wd;
@@ -646,7 +681,7 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   if (yy < J.th && xx < J.tw && y < Hd && x < Wd) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const float* col = Hb + (c * DR + 2 * yy) * DT + xx;
+      const float* col = Hb + c * DR * DR + 2 * yy * DT + xx;
       const float v = kB0 * col[0] + kB1 * col[DT] + kB2 * col[2 * DT] + kB1 * col[3 * DT] + kB0 * col[4 * DT];
       dst[c * plane + (size_t)y * Wd + x] = v;
     }
@@ -810,7 +845,7 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
 }
 
 template <bool BIG>
-__global__ __launch_bounds__(SP_BLOCK) void k_pyr(const Job* __restrict__ jobs,
+__global__ __launch_bounds__(SP_BLOCK) __attribute__((amdgpu_waves_per_eu(BIG ? 1 : 8))) void k_pyr(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
                                                   const StepIO* __restrict__ ios, StepIO io0) {
   __shared__ float smem[BIG ? TAIL_LDS : DOWN_LDS];
@@ -1348,10 +1383,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
       lds_load(Sl + i, Sg + (size_t)(sf.y0 + fy) * Wm + sf.x0 + fx);
     }
   }
-  lds_wait();
+  // the partial maxima are read while the staging loads are still in flight
   float m;
   int xs;
   smax_from_parts(sd.s_part, sd.n_cmax_tiles, &m, &xs, sh4, shi4);
+  lds_wait();
+  __syncthreads();
   const bool flat = !(m > sd.flat_tol);
   if (t > 0) {
     Walk2 wk(threadIdx.x, tw);
@@ -1407,7 +1444,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_mrf(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
                                                   const StepIO* __restrict__ ios, StepIO io0,
                                                   const float* __restrict__ prior) {
-  __shared__ unsigned long long sh[SP_BLOCK];
+  __shared__ unsigned long long sh[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const uint8_t* rgb = IOF(rgb);
