@@ -247,8 +247,13 @@ void pyramid_stages(const Geo& g, int s, int lo, std::vector<std::vector<Job>>& 
   }
   *big = L0 < g.top;
   if (*big) {
-    for (int l = g.top; l > L0; --l)   // the largest Gabor level first: it is the longest job
-      if (g.used & (1u << l)) fin.push_back(Job{s, L0, 0, 0, g.Hl[l], g.Wl[l], l, JOB_TAILGAB});
+    for (int l = g.top; l > L0; --l)   // Gabor maps of the small used levels, in row bands of ~256 pixels
+      if (g.used & (1u << l)) {
+        const int nb = std::max(1, std::min(8, g.Hl[l] * g.Wl[l] / 256));
+        const int rows = (g.Hl[l] + nb - 1) / nb;
+        for (int y0 = 0; y0 < g.Hl[l]; y0 += rows)
+          fin.push_back(Job{s, L0, y0, 0, std::min(rows, g.Hl[l] - y0), g.Wl[l], l, JOB_TAILGAB});
+      }
     for (int ch = 0; ch < 4; ++ch) fin.push_back(Job{s, L0, 0, 0, g.Hl[L0], g.Wl[L0], ch, JOB_TAIL});
   }
   if (g.used & (1u << L0)) add_tiles(fin, s, L0, g.Hl[L0], g.Wl[L0], JOB_GABOR);

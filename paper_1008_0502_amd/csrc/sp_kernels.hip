@@ -749,13 +749,16 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
 }
 
 // Gabor maps of a whole (small) level held in LDS.
-__device__ void gabor_lds(const float* I, int h, int w, float* V, const float* taps, int R, float c45, gp<float> out) {
-  const int n = h * w, nt = 2 * R + 1;
+// Rows [y0, y0 + nr) only: the vertical pass of an output row reads the whole level (in
+// LDS), so a band needs no halo of its own.
+__device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V, const float* taps, int R, float c45,
+                          gp<float> out) {
+  const int n = nr * w, plane = h * w;
   for (int f = 0; f < 4; ++f) {
     const float* tp = taps + f * (2 * SP_MAXR + 1);
     Walk2 wk(threadIdx.x, w);
     for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK, wk.next()) {
-      const int y = wk.r, x = wk.c;
+      const int y = y0 + wk.r, x = wk.c;
       float acc = 0.f;
 #pragma unroll
       for (int v = 0; v < 2 * SP_MAXR + 1; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
@@ -769,7 +772,7 @@ __device__ void gabor_lds(const float* I, int h, int w, float* V, const float* t
   const float* t3 = taps + 3 * (2 * SP_MAXR + 1);
   Walk2 wk(threadIdx.x, w);
   for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK, wk.next()) {
-    const int y = wk.r, x = wk.c;
+    const int y = wk.r, x = wk.c;   // y relative to the band
     float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
 #pragma unroll
     for (int u = 0; u < 2 * SP_MAXR + 1; ++u) {
@@ -781,18 +784,19 @@ __device__ void gabor_lds(const float* I, int h, int w, float* V, const float* t
       D += t2[u] * V[2 * n + o];
       E += t3[u] * V[3 * n + o];
     }
-    out[pix] = A;
-    out[n + pix] = D - E - c45 * B;
-    out[2 * n + pix] = C;
-    out[3 * n + pix] = D + E - c45 * B;
+    const int go = y0 * w + pix;
+    out[go] = A;
+    out[plane + go] = D - E - c45 * B;
+    out[2 * plane + go] = C;
+    out[3 * plane + go] = D + E - c45 * B;
   }
   __syncthreads();
 }
 
 // Levels above source level a of one base channel, computed in LDS.  TAIL jobs
 // (channel tid) compute and store every level up to the top; TAILGAB jobs rebuild the
-// intensity chain up to level tid and store only that level's Gabor maps, so the
-// Gabor work of the small levels runs in parallel workgroups.
+// intensity chain up to level tid and store that level's Gabor maps for the row band
+// y0 .. y0+th-1, so the Gabor work of the small levels runs in parallel workgroups.
 __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float* smem) {
   float* SA = smem;
   float* SB = SA + SP_TAIL_SRC;
@@ -835,7 +839,7 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
       if (dst) dst[i] = acc;
     }
     __syncthreads();
-    if (gab && l + 1 == last) gabor_lds(nxt, nH, nW, V, taps, R, sd.c45, G(sd.gab[l + 1]));
+    if (gab && l + 1 == last) gabor_lds(nxt, nH, nW, J.y0, J.th, V, taps, R, sd.c45, G(sd.gab[l + 1]));
     float* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -1399,38 +1403,36 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
     }
     __syncthreads();
   }
-  // 16 threads per tile row; each takes tw/16 consecutive pixels
-  const int yy = threadIdx.x >> 4, px = (tw + 15) >> 4, x0 = (threadIdx.x & 15) * px;
-  const int y = J.y0 + yy;
-  if (yy < J.th && y < H) {
-    const bool rowring = y < sd.border || y >= H - sd.border;
-    const Tap ty = bilinear_tap(y, cm, Hm);
-    for (int k = 0; k < px; ++k) {
-      const int xx = x0 + k, x = J.x0 + xx;
-      if (xx >= tw || x >= W) break;
-      const bool ring = rowring || x < sd.border || x >= W - sd.border;
-      float q = 0.5f;
-      if (!flat) {
-        const Tap tx = bilinear_tap(x, cm, Wm);
-        const float u = bilinear_lds(Sl, sf.w, ty, tx, sf.y0, sf.x0) / m;
-        q = fminf(fmaxf(u, sd.eps), 1.f - sd.eps);
-      }
-      if (ring) q = sd.eps;
-      float pi = q;
-      const size_t o = (size_t)y * W + x;
-      if (t > 0) {
-        const float f = kB0 * hb[yy][xx] + kB1 * hb[yy + 1][xx] + kB2 * hb[yy + 2][xx] + kB1 * hb[yy + 3][xx] +
-                        kB0 * hb[yy + 4][xx];
-        pi = f + K * (q - f);
-        if (ftape) ftape[o] = f;
-      }
-      if (ring) pi = sd.eps;
-      pnext[o] = pi;
-      if (pout) pout[o] = pi;
-      if (unary) {
-        unary[o] = -log1pf(-fminf(pi, 1.f - sd.eps));
-        unary[(size_t)H * W + o] = -logf(fmaxf(pi, sd.eps));
-      }
+  // consecutive lanes take consecutive pixels of a row, so every store of a wavefront
+  // covers a contiguous run
+  const float eps = sd.eps;
+  Walk2 wk2(threadIdx.x, tw);
+  for (int i = threadIdx.x; i < J.th * tw; i += SP_BLOCK, wk2.next()) {
+    const int yy = wk2.r, xx = wk2.c;
+    const int y = J.y0 + yy, x = J.x0 + xx;
+    if (y >= H || x >= W) continue;
+    const bool ring = y < sd.border || y >= H - sd.border || x < sd.border || x >= W - sd.border;
+    float q = 0.5f;
+    if (!flat) {
+      const Tap ty = bilinear_tap(y, cm, Hm), tx = bilinear_tap(x, cm, Wm);
+      const float u = bilinear_lds(Sl, sf.w, ty, tx, sf.y0, sf.x0) / m;
+      q = fminf(fmaxf(u, eps), 1.f - eps);
+    }
+    if (ring) q = eps;
+    float pi = q;
+    const size_t o = (size_t)y * W + x;
+    if (t > 0) {
+      const float f = kB0 * hb[yy][xx] + kB1 * hb[yy + 1][xx] + kB2 * hb[yy + 2][xx] + kB1 * hb[yy + 3][xx] +
+                      kB0 * hb[yy + 4][xx];
+      pi = f + K * (q - f);
+      if (ftape) ftape[o] = f;
+    }
+    if (ring) pi = eps;
+    pnext[o] = pi;
+    if (pout) pout[o] = pi;
+    if (unary) {
+      unary[o] = -log1pf(-fminf(pi, 1.f - eps));
+      unary[(size_t)H * W + o] = -logf(fmaxf(pi, eps));
     }
   }
   if (mstape && J.tid == 0 && threadIdx.x == 0) {
