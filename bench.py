@@ -68,6 +68,7 @@ def alg_bytes_per_stream(g, mrf: bool, prior_copy: bool):
     if L0 in used:
         tail += 20.0 * pxl(L0)
     lev = sum(32.0 * pxl(l) for l in used)
+    npairs = len(g.pairs)
     return {
         "k_rgb": 3.0 * px,
         "k_feat": 6.0 * px + 16.0 * pxl(1) + (16.0 * px if mrf else 0.0),
@@ -75,6 +76,10 @@ def alg_bytes_per_stream(g, mrf: bool, prior_copy: bool):
         "k_pyr_tail": tail,
         "k_csstats": lev,
         "k_csapply": lev + 32.0 * pc,
+        # reduced-map path (every centre at c_max or one level below): maps, partials and
+        # reductions to c_max in one pass, then their normalised sum
+        "k_csg": lev + 32.0 * npairs * pc,
+        "k_csmix": 32.0 * npairs * pc + 32.0 * pc,
         "k_consp": 36.0 * pc,
         "k_kalman": 4.0 * pc + 8.0 * px + (4.0 * px if prior_copy else 0.0) + (8.0 * px if mrf else 0.0),
     }
@@ -154,11 +159,11 @@ def pmc_summarize(fetch_db: str, write_db: str) -> None:
     kernels = {}
     names = {"k_rgb": "k_rgb", "k_feat<16,16>": "k_feat", "k_pyr<false>": "k_pyr", "k_pyr<true>": "k_pyr_tail",
              "k_csstats": "k_csstats", "k_csfinal": "k_csfinal", "k_csapply": "k_csapply", "k_consp": "k_consp",
-             "k_kalman": "k_kalman"}
+             "k_kalman": "k_kalman", "k_csg": "k_csg", "k_csmix": "k_csmix"}
     for raw in set(fetch) | set(write):
         short = re.sub(r"\(anonymous namespace\)::", "", raw)
         short = re.sub(r"\(.*\)$", "", short).replace("void ", "").replace(" ", "")
-        key = names.get(short)
+        key = names.get(short) or names.get(re.sub(r"<.*>$", "", short))
         if key is None:
             continue
         f = fetch.get(raw, [0.0])

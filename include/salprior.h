@@ -203,7 +203,7 @@ int sp_batch_destroy(sp_batch* b);
  * 65536 pairs).  sp_profile_read synchronises the stream and returns, per kernel kind
  * 0..SP_NKINDS-1, the summed device time in ms and the number of launches since the
  * last read (arrays of length n >= SP_NKINDS), then clears the record. */
-#define SP_NKINDS 18
+#define SP_NKINDS 20
 int sp_profile_enable(sp_ctx* ctx, int32_t enable);
 int sp_profile_read(sp_ctx* ctx, int32_t n, float* total_ms, int32_t* launches);
 /* The same measurement hook for a batch: while enabled, sp_batch_step launches the

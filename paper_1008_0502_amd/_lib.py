@@ -14,7 +14,7 @@ SP_OK, SP_EINVAL, SP_ESHAPE, SP_ENOMEM, SP_EHIP, SP_ESTATE = 0, -1, -2, -3, -4, 
 ERROR_NAMES = {SP_EINVAL: "SP_EINVAL", SP_ESHAPE: "SP_ESHAPE", SP_ENOMEM: "SP_ENOMEM",
                SP_EHIP: "SP_EHIP", SP_ESTATE: "SP_ESTATE"}
 MAX_LEVELS = 12
-NKINDS = 18
+NKINDS = 20
 
 c_int32 = ctypes.c_int32
 c_float = ctypes.c_float

@@ -53,6 +53,18 @@ bool is_fin(double v) { return std::isfinite(v); }
 
 constexpr size_t kMaxDynLds = 150 * 1024;   // dynamic LDS of the across-scale-sum job (gfx950: 160 KB per CU)
 
+// Reduced-map path: every pair has its centre at c_max or one level below.
+bool gpath_ok(const Geo& g) {
+  if (g.n_pairs < 1) return false;
+  for (int p = 0; p < g.n_pairs; ++p)
+    if (g.c_max - g.pc[p] > 1) return false;
+  return true;
+}
+
+size_t csg_lds_bytes(const Geo& g) {
+  return sizeof(float) * (size_t)csg_layout(g.pc, g.ps, g.n_pairs, g.c_max).total;
+}
+
 size_t csapply_lds_bytes(const Geo& g) {
   return sizeof(float) * (size_t)csapply_layout(g.pc, g.ps, g.n_pairs, g.c_max).total;
 }
@@ -128,9 +140,10 @@ int make_geo(const sp_params& p, int H, int W, Geo& g) {
   for (int a = 0; a < g.n_pairs; ++a)
     for (int b = 0; b < a; ++b)
       if (g.pc[a] == g.pc[b] && g.ps[a] == g.ps[b]) return fail(SP_EINVAL, "duplicate centre-surround pair");
-  if (csapply_lds_bytes(g) > kMaxDynLds)
-    return fail(SP_ESHAPE, "centre-surround configuration needs %zu bytes of LDS per workgroup (max %zu)",
-                csapply_lds_bytes(g), kMaxDynLds);
+  const size_t ca_lds = gpath_ok(g) ? csg_lds_bytes(g) : csapply_lds_bytes(g);
+  if (ca_lds > kMaxDynLds)
+    return fail(SP_ESHAPE, "centre-surround configuration needs %zu bytes of LDS per workgroup (max %zu)", ca_lds,
+                kMaxDynLds);
   return SP_OK;
 }
 
@@ -188,7 +201,7 @@ Tune cached_tune(int H, int W) {
 // Channels per workgroup of the across-scale sum: the largest power of two up to the
 // preference whose LDS (one block per channel) fits the dynamic limit.
 int csapply_nc(const Geo& g, int pref) {
-  const size_t per = csapply_lds_bytes(g);
+  const size_t per = gpath_ok(g) ? csg_lds_bytes(g) : csapply_lds_bytes(g);
   int nc = 8;
   while (nc > 1 && (nc > pref || nc * per > kMaxDynLds)) nc /= 2;
   return nc;
@@ -339,12 +352,15 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
     sd.Wl[l] = g.Wl[l];
     sd.ntiles_lvl[l] = (l <= g.depth) ? ntiles(g.Hl[l], g.Wl[l]) : 0;
   }
+  sd.n_cmax_tiles = sd.ntiles_lvl[g.c_max];
+  sd.gpath = gpath_ok(g) ? 1 : 0;
   int off = 0;
   for (int i = 0; i < g.n_pairs; ++i) {
+    // partials per map: one per c_max tile (reduced-map path) or per centre-level tile
+    sd.cs_nt[i] = sd.gpath ? sd.n_cmax_tiles : sd.ntiles_lvl[g.pc[i]];
     sd.cs_off[i] = off;
-    off += SP_NCH * sd.ntiles_lvl[g.pc[i]];
+    off += SP_NCH * sd.cs_nt[i];
   }
-  sd.n_cmax_tiles = sd.ntiles_lvl[g.c_max];
   sd.used = g.used;
   for (int k = 0; k < SP_NCH; ++k) sd.w[k] = p.weights[k];
   sd.eps = p.eps;
@@ -366,6 +382,7 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
   sd.fbar_part = bump.take<float>((size_t)3 * SP_NCH * sd.n_cmax_tiles);
   sd.s_part = bump.take<float>((size_t)2 * sd.n_cmax_tiles);
   sd.cs_np = bump.take<float>((size_t)4 * SP_NCH * std::max(1, g.n_pairs));
+  if (sd.gpath) sd.gmap = bump.take<float>((size_t)g.n_pairs * SP_NCH * g.Hl[g.c_max] * g.Wl[g.c_max]);
 }
 
 void rgb_jobs(std::vector<Job>& v, int s, const StreamDesc& sd, const Geo& g) {
@@ -589,18 +606,29 @@ void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& 
   for (auto& m : mid) push(JOB_DOWN, m);
   if (!fin.empty()) push(big ? JOB_TAIL : JOB_DOWN, fin);
   std::vector<Job> v;
-  for (int c = 0; c <= g.top; ++c) {
-    bool has = false;
-    for (int i = 0; i < g.n_pairs; ++i) has |= (g.pc[i] == c);
-    if (has) add_tiles(v, s, c, g.Hl[c], g.Wl[c]);
+  const bool gp = gpath_ok(g);
+  if (gp) {
+    for (int k = 0; k < SP_NCH; k += nc) add_tiles(v, s, k, g.Hl[g.c_max], g.Wl[g.c_max], JOB_CSG);
+    push(JOB_CSG, v);
+  } else {
+    for (int c = 0; c <= g.top; ++c) {
+      bool has = false;
+      for (int i = 0; i < g.n_pairs; ++i) has |= (g.pc[i] == c);
+      if (has) add_tiles(v, s, c, g.Hl[c], g.Wl[c]);
+    }
+    push(JOB_CSSTATS, v);
   }
-  push(JOB_CSSTATS, v);
   v.clear();
   for (int p = 0; p < g.n_pairs; ++p) v.push_back(Job{s, p, 0, 0, 1, 1, p, JOB_CSFINAL});
   push(JOB_CSFINAL, v);
   v.clear();
-  for (int k = 0; k < SP_NCH; k += nc) add_tiles(v, s, k, g.Hl[g.c_max], g.Wl[g.c_max]);
-  push(JOB_CSAPPLY, v);
+  if (gp) {
+    add_tiles(v, s, 0, g.Hl[g.c_max], g.Wl[g.c_max], JOB_CSMIX);
+    push(JOB_CSMIX, v);
+  } else {
+    for (int k = 0; k < SP_NCH; k += nc) add_tiles(v, s, k, g.Hl[g.c_max], g.Wl[g.c_max]);
+    push(JOB_CSAPPLY, v);
+  }
   v.clear();
   add_tiles(v, s, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
   push(which == PROG_ALL ? JOB_CONSP : JOB_CONSP_DOT, v);
@@ -773,12 +801,14 @@ int ctx_build_tables(sp_ctx* c) {
     std::vector<std::vector<Job>> parts;
     std::vector<int> kinds;
     const int nc = csapply_nc(g, c->tune.ca_nc);
-    if (sp_csapply_reserve_lds(nc * csapply_lds_bytes(g)) != hipSuccess)
-      return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", nc * csapply_lds_bytes(g));
+    const size_t ca_lds = nc * (gpath_ok(g) ? csg_lds_bytes(g) : csapply_lds_bytes(g));
+    if (sp_csapply_reserve_lds(ca_lds) != hipSuccess)
+      return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", ca_lds);
     build_forward_jobs(parts, kinds, c->h_sd, g, 0, PROG_ALL, nc);
     for (size_t i = 0; i < parts.size(); ++i) {
-      c->fwd.push_back(c->jobs.add(kinds[i], kinds[i] == JOB_CSAPPLY ? nc : 0, order(parts[i]), 1));
-      if (kinds[i] == JOB_CSAPPLY) c->fwd.back().lds = nc * csapply_lds_bytes(g);
+      const bool grp = kinds[i] == JOB_CSAPPLY || kinds[i] == JOB_CSG;
+      c->fwd.push_back(c->jobs.add(kinds[i], grp ? nc : 0, order(parts[i]), 1));
+      if (grp) c->fwd.back().lds = ca_lds;
     }
     std::vector<Job> v;
     add_tiles(v, 0, 0, Hc, Wc);
@@ -812,8 +842,9 @@ int ctx_build_tables(sp_ctx* c) {
         for (size_t i = 0; i < ps.size(); ++i) all[i].insert(all[i].end(), ps[i].begin(), ps[i].end());
       }
       for (size_t i = 0; i < all.size(); ++i) {
-        c->rec.push_back(c->jobs.add(kk[i], kk[i] == JOB_CSAPPLY ? nc : 0, all[i], c->CH));
-        if (kk[i] == JOB_CSAPPLY) c->rec.back().lds = nc * csapply_lds_bytes(g);
+        const bool grp = kk[i] == JOB_CSAPPLY || kk[i] == JOB_CSG;
+        c->rec.push_back(c->jobs.add(kk[i], grp ? nc : 0, all[i], c->CH));
+        if (grp) c->rec.back().lds = ca_lds;
       }
     }
   }
@@ -1238,7 +1269,7 @@ const char* sp_kernel_name(int32_t k) {
   // for DOWN/GABOR stages, k_pyr tail for the final stage with tail jobs)
   static const char* names[SP_NKINDS] = {"k_rgb", "k_feat", "k_pyr", "k_pyr", "k_csstats", "k_csapply",
                                          "k_consp", "k_smax", "k_kalman", "k_mrf", "k_bwd_nu", "k_bwd_gs",
-                                         "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_csfinal",
+                                         "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_csfinal", "k_csg", "k_csmix",
                                          "k_bwd_final"};
   return (k >= 0 && k < SP_NKINDS) ? names[k] : "";
 }
@@ -1288,7 +1319,7 @@ int batch_build_tables(sp_batch* b) {
   }
   b->jobs.host.clear();
   b->phases.clear();
-  std::vector<Job> rgb, feat, fin, css, csf, csa, cons, kal;
+  std::vector<Job> rgb, feat, fin, css, csf, csa, csg, csm, cons, kal;
   std::vector<std::vector<Job>> mids;
   bool any_big = false;
   int nc = 8;   // one channel-group size for the whole across-scale launch
@@ -1306,12 +1337,17 @@ int batch_build_tables(sp_batch* b) {
     if (mids.size() < mid.size()) mids.resize(mid.size());
     for (size_t j = 0; j < mid.size(); ++j) mids[j].insert(mids[j].end(), mid[j].begin(), mid[j].end());
     fin.insert(fin.end(), f.begin(), f.end());
-    for (int c = 0; c <= g.top; ++c) {
-      bool has = false;
-      for (int k = 0; k < g.n_pairs; ++k) has |= (g.pc[k] == c);
-      if (has) add_tiles(css, i, c, g.Hl[c], g.Wl[c]);
+    if (gpath_ok(g)) {
+      for (int k = 0; k < SP_NCH; k += nc) add_tiles(csg, i, k, g.Hl[g.c_max], g.Wl[g.c_max], JOB_CSG);
+      add_tiles(csm, i, 0, g.Hl[g.c_max], g.Wl[g.c_max], JOB_CSMIX);
+    } else {
+      for (int c = 0; c <= g.top; ++c) {
+        bool has = false;
+        for (int k = 0; k < g.n_pairs; ++k) has |= (g.pc[k] == c);
+        if (has) add_tiles(css, i, c, g.Hl[c], g.Wl[c]);
+      }
+      for (int k = 0; k < SP_NCH; k += nc) add_tiles(csa, i, k, g.Hl[g.c_max], g.Wl[g.c_max]);
     }
-    for (int k = 0; k < SP_NCH; k += nc) add_tiles(csa, i, k, g.Hl[g.c_max], g.Wl[g.c_max]);
     add_tiles(cons, i, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
     add_tiles_wh(kal, i, 0, g.H, g.W, 16, b->tune[i].kalman_tw, JOB_KALMAN);
   }
@@ -1328,16 +1364,26 @@ int batch_build_tables(sp_batch* b) {
   for (auto& d : mids)
     if (!d.empty()) b->phases.push_back(b->jobs.add(JOB_DOWN, 0, order(d), n));
   if (!fin.empty()) b->phases.push_back(b->jobs.add(any_big ? JOB_TAIL : JOB_DOWN, 0, fin, n));
-  b->phases.push_back(b->jobs.add(JOB_CSSTATS, 0, order(css), n));
-  b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, n));
-  b->phases.push_back(b->jobs.add(JOB_CSAPPLY, nc, order(csa), n));
-  {
-    size_t lds = 0;
-    for (const Geo& g : b->geo) lds = std::max(lds, csapply_lds_bytes(g));
-    b->phases.back().lds = nc * lds;
-    if (sp_csapply_reserve_lds(nc * lds) != hipSuccess)
-      return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", nc * lds);
+  size_t lds_a = 0, lds_g = 0;
+  for (const Geo& g : b->geo) {
+    if (gpath_ok(g))
+      lds_g = std::max(lds_g, csg_lds_bytes(g));
+    else
+      lds_a = std::max(lds_a, csapply_lds_bytes(g));
   }
+  if (sp_csapply_reserve_lds(nc * std::max(lds_a, lds_g)) != hipSuccess)
+    return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", nc * std::max(lds_a, lds_g));
+  if (!css.empty()) b->phases.push_back(b->jobs.add(JOB_CSSTATS, 0, order(css), n));
+  if (!csg.empty()) {
+    b->phases.push_back(b->jobs.add(JOB_CSG, nc, order(csg), n));
+    b->phases.back().lds = nc * lds_g;
+  }
+  b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, n));
+  if (!csa.empty()) {
+    b->phases.push_back(b->jobs.add(JOB_CSAPPLY, nc, order(csa), n));
+    b->phases.back().lds = nc * lds_a;
+  }
+  if (!csm.empty()) b->phases.push_back(b->jobs.add(JOB_CSMIX, 0, order(csm), n));
   b->phases.push_back(b->jobs.add(JOB_CONSP, 0, order(cons), n));
   b->phases.push_back(b->jobs.add(JOB_KALMAN, 0, order(kal), n));
   return upload_jobs(b->jobs, b->stream);

@@ -38,6 +38,9 @@ enum JobKind : int32_t {
   JOB_TAIL,         // one channel: every level above a small source level, in LDS
   JOB_TAILGAB,      // Gabor maps of one level above the tail source (intensity chain in LDS)
   JOB_CSFINAL,      // pair a: N(.) parameters of its 8 centre-surround maps from the partials
+  JOB_CSG,          // channels a..: centre-surround maps of a c_max tile, their partials and
+                    // their reduction to c_max (pairs with c_max - c <= 1)
+  JOB_CSMIX,        // c_max tile: F-bar as the sum of the normalised reduced maps (+ partials)
   JOB_BWD_FINAL,    // reduction of the adjoint partials (timing id only)
   JOB_NKINDS
 };
@@ -63,7 +66,9 @@ struct StreamDesc {
   int32_t pc[SP_MAXP], ps[SP_MAXP];
   int32_t Hl[SP_MAXL], Wl[SP_MAXL];
   int32_t ntiles_lvl[SP_MAXL];   // number of CS tiles of a map at level l
-  int32_t cs_off[SP_MAXP];       // offset (in partial triples) of pair p: [8][ntiles(c_p)]
+  int32_t cs_off[SP_MAXP];       // offset (in partial triples) of pair p: [8][cs_nt[p]]
+  int32_t cs_nt[SP_MAXP];        // partial triples per map of pair p
+  int32_t gpath;                 // 1: every pair has c_max - c <= 1 (reduced-map path)
   int32_t n_cmax_tiles;          // tiles of the c_max grid (fbar / consp / smax partials)
   int32_t gr;                    // Gabor radius
   uint32_t used;                 // bit l: level l is a centre or a surround level
@@ -76,6 +81,7 @@ struct StreamDesc {
   float* fbar_part;              // [8][n_cmax_tiles] triples
   float* s_part;                 // [n_cmax_tiles] pairs (max, index as float bits)
   float* cs_np;                  // [n_pairs][8][4] N(.) parameters of the centre-surround maps
+  float* gmap;                   // [n_pairs][8][Hc][Wc] maps reduced to c_max (reduced-map path)
   float w[SP_NCH];
   float eps, flat_tol, lam, potts;
   float c45;                     // DC weight of the diagonal Gabor kernels
@@ -165,6 +171,36 @@ __host__ __device__ inline CaLayout csapply_layout(const int32_t* pc, const int3
   if (has[2]) o += n2 * n2;
   L.tm = o;
   o += has[2] ? n2 * n1 : ((has[1]) ? n1 * SP_CA_T : 0);
+  L.foot0 = o;
+  for (int p = 0; p < n_pairs; ++p) o += csapply_foot_cap(c_max - pc[p], ps[p] - pc[p]);
+  L.total = o;
+  return L;
+}
+
+// LDS of the reduced-map job, per channel: the centre region of the level below c_max
+// (x1), its centre-surround map for one pair at a time (fq), the row pass of the
+// reduction (tm), the c_max tile (x0) and one surround footprint per pair.
+struct CgLayout {
+  int x1, fq, tm, x0, foot0, total;
+};
+
+__host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t* ps, int n_pairs, int c_max) {
+  bool has0 = false, has1 = false;
+  for (int p = 0; p < n_pairs; ++p) {
+    has0 |= (c_max - pc[p]) == 0;
+    has1 |= (c_max - pc[p]) == 1;
+  }
+  const int n1 = 2 * SP_CA_T + 3;
+  CgLayout L;
+  int o = 0;
+  L.x1 = o;
+  if (has1) o += n1 * n1;
+  L.fq = o;
+  if (has1) o += n1 * n1;
+  L.tm = o;
+  if (has1) o += n1 * SP_CA_T;
+  L.x0 = o;
+  if (has0) o += SP_CA_T * SP_CA_T;
   L.foot0 = o;
   for (int p = 0; p < n_pairs; ++p) o += csapply_foot_cap(c_max - pc[p], ps[p] - pc[p]);
   L.total = o;

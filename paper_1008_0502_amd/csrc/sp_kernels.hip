@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csfinal(const Job* __restrict__ jo
                                                       const StepIO* __restrict__ ios, StepIO io0) {
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
-  const int p = J.a, c = sd.pc[p], nt = sd.ntiles_lvl[c], nb = nblocks8(sd.Hl[c], sd.Wl[c]);
+  const int p = J.a, c = sd.pc[p], nt = sd.cs_nt[p], nb = nblocks8(sd.Hl[c], sd.Wl[c]);
   for (int k = wave_id(); k < SP_NCH; k += 4) {
     const NParams q = nparams_wave(sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)k * nt), nt, nb, sd.flat_tol);
     if (lane_id() == 0) store_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k), q);
@@ -1258,6 +1258,323 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
     out[0] = fminf(fminf(wacc[0][j][0], wacc[1][j][0]), fminf(wacc[2][j][0], wacc[3][j][0]));
     out[1] = fmaxf(fmaxf(wacc[0][j][1], wacc[1][j][1]), fmaxf(wacc[2][j][1], wacc[3][j][1]));
     out[2] = (wacc[0][j][2] + wacc[1][j][2]) + (wacc[2][j][2] + wacc[3][j][2]);
+  }
+}
+
+// ---------------------------------------------------------------- reduced-map path
+// N(.) is affine in F on every map and REDUCE is linear with weights summing to one, so
+// REDUCE(N(F)) = N(REDUCE(F)).  When every pair has c_max - c <= 1 the
+// centre-surround maps are computed once per c_max tile: their partial statistics are
+// taken on the pixels the tile owns (the tile's footprint on level c), and their
+// reduction to c_max (REDUCE once for c = c_max - 1, the map itself for c = c_max) is
+// stored.  k_csmix then forms F-bar at c_max as the sum of N(reduced map) over pairs.
+//
+// One workgroup per c_max tile and group of NC channels (from job a).  Each channel
+// owns a block of CgLayout.total floats of dynamic LDS.
+template <int NC>
+__global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
+                                                  const StreamDesc* __restrict__ sds,
+                                                  const StepIO* __restrict__ ios, StepIO io0) {
+  extern __shared__ float dyn[];
+  __shared__ float wred[4][NC][3];
+  const Job J = jobs[blockIdx.x];
+  const StreamDesc& sd = sds[J.stream];
+  const float* ckpt = IOF(ckpt);
+  const int k0 = J.a, cm = sd.c_max;
+  const int Hm = sd.Hl[cm], Wm = sd.Wl[cm];
+  const CgLayout L = csg_layout(sd.pc, sd.ps, sd.n_pairs, cm);
+  const int CS = L.total;
+  bool has0 = false, has1 = false;
+  for (int p = 0; p < sd.n_pairs; ++p) {
+    has0 |= (cm - sd.pc[p]) == 0;
+    has1 |= (cm - sd.pc[p]) == 1;
+  }
+  const Range rg0{J.y0, J.th}, cg0{J.x0, J.tw};
+  Range rg1 = rg0, cg1 = cg0;
+  if (has1) {
+    rg1 = finer_range(rg0, sd.Hl[cm - 1]);
+    cg1 = finer_range(cg0, sd.Wl[cm - 1]);
+  }
+  const gp<float> gmap = G(sd.gmap);
+  const size_t plane = (size_t)Hm * Wm;
+  // ---- one round trip: the c_max tile, the region of the level below and every pair's
+  // footprint, for each channel of the group
+  auto stage = [&](Range rr, Range cc, int c, int xoff) {
+    const int Wc = sd.Wl[c];
+    const int n = rr.n * cc.n;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const float* Xc = chan_ptr(sd, ckpt, k0 + j, c);
+      float* X = dyn + j * CS + xoff;
+      Walk2 wk(threadIdx.x, cc.n);
+      for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next())
+        lds_load(X + i, Xc + (size_t)(rr.lo + wk.r) * Wc + cc.lo + wk.c);
+    }
+  };
+  if (has0) stage(rg0, cg0, cm, L.x0);
+  if (has1) stage(rg1, cg1, cm - 1, L.x1);
+  {
+    int off = L.foot0;
+    for (int p = 0; p < sd.n_pairs; ++p) {
+      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], Ws = sd.Wl[s];
+      const Range rr = (r == 0) ? rg0 : rg1, cc = (r == 0) ? cg0 : cg1;
+      const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], Ws);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const float* Xs = chan_ptr(sd, ckpt, k0 + j, s);
+        float* dst = dyn + j * CS + off;
+        Walk2 wk(threadIdx.x, f.w);
+        for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK, wk.next())
+          lds_load(dst + i, Xs + (size_t)(f.y0 + wk.r) * Ws + f.x0 + wk.c);
+      }
+      off += csapply_foot_cap(r, s - c);
+    }
+  }
+  lds_wait();
+  __syncthreads();
+  const int lane = lane_id(), w = wave_id();
+  const int sy = (lane >> 2) & 3, sx = lane & 3;
+  // ---- pairs with c = c_max: one wavefront per map covers the tile's four 8x8 blocks
+  // (a 2x2 quad per lane, DPP inside each 16-lane row); the map is its own reduction
+  if (has0) {
+    const int blk = lane >> 4, by = blk >> 1, bx = blk & 1;
+    const int qy = 8 * by + 2 * sy, qx = 8 * bx + 2 * sx;
+    bool bval[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bval[i] = 8 * (i >> 1) < J.th && 8 * (i & 1) < J.tw;
+    int m = 0, off = L.foot0;
+    for (int p = 0; p < sd.n_pairs; ++p) {
+      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], d = s - c;
+      if (r == 0) {
+        const Foot f = footprint(J.y0, J.th, J.x0, J.tw, d, sd.Hl[s], sd.Wl[s]);
+        int yl[2], xl[2];
+        Tap ty[2], tx[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          yl[u] = min(qy + u, J.th - 1);
+          xl[u] = min(qx + u, J.tw - 1);
+          ty[u] = bilinear_tap(J.y0 + yl[u], d, sd.Hl[s]);
+          tx[u] = bilinear_tap(J.x0 + xl[u], d, sd.Wl[s]);
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j, ++m) {
+          if ((m & 3) != w) continue;   // wave-uniform
+          const float* B = dyn + j * CS;
+          float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+              const float up = bilinear_lds(B + off, f.w, ty[u], tx[v], f.y0, f.x0);
+              const float F = fabsf(B[L.x0 + yl[u] * J.tw + xl[v]] - up);
+              mn = fminf(mn, F);
+              mx = fmaxf(mx, F);
+              if (qy + u < J.th && qx + v < J.tw)
+                gmap[((size_t)p * SP_NCH + k0 + j) * plane + (size_t)(J.y0 + qy + u) * Wm + J.x0 + qx + v] = F;
+            }
+          mn = fminf(mn, dpp_f<0xB1>(mn));
+          mx = fmaxf(mx, dpp_f<0xB1>(mx));
+          mn = fminf(mn, dpp_f<0x4E>(mn));
+          mx = fmaxf(mx, dpp_f<0x4E>(mx));
+          mn = fminf(mn, dpp_f<0x141>(mn));
+          mx = fmaxf(mx, dpp_f<0x141>(mx));
+          mn = fminf(mn, dpp_f<0x140>(mn));
+          mx = fmaxf(mx, dpp_f<0x140>(mx));
+          float bmn[4], bmx[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            bmn[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i)) : INFINITY;
+            bmx[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i)) : -INFINITY;
+          }
+          if (lane == 0) {
+            const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)(k0 + j) * sd.cs_nt[p] + J.tid);
+            out[0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
+            out[1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
+            out[2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) +
+                     ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
+          }
+        }
+      }
+      off += csapply_foot_cap(r, d);
+    }
+  }
+  // ---- pairs with c = c_max - 1, one at a time: the map on the whole region, its
+  // statistics on the 2*th x 2*tw pixels the tile owns (wavefront w: block row w, a 2x2
+  // quad per lane), then REDUCE to the tile
+  if (has1) {
+    const int c1 = cm - 1, H1 = sd.Hl[c1], W1 = sd.Wl[c1];
+    const int oh = min(2 * J.th, H1 - 2 * J.y0), ow = min(2 * J.tw, W1 - 2 * J.x0);
+    const int oy0 = 2 * J.y0 - rg1.lo, ox0 = 2 * J.x0 - cg1.lo;   // region offset of the owned pixels
+    const int bx = lane >> 4, qy = 8 * w + 2 * sy, qx = 8 * bx + 2 * sx;
+    int ro[2], co[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      ro[u] = oy0 + min(qy + u, oh - 1);
+      co[u] = ox0 + min(qx + u, ow - 1);
+    }
+    const bool rowval = 8 * w < oh;
+    bool bval[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bval[i] = rowval && 8 * i < ow;
+    const int n = rg1.n * cg1.n;
+    int off = L.foot0;
+    for (int p = 0; p < sd.n_pairs; ++p) {
+      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], d = s - c;
+      if (r == 1) {
+        const Foot f = footprint(rg1.lo, rg1.n, cg1.lo, cg1.n, d, sd.Hl[s], sd.Wl[s]);
+        // the map on the region
+        Walk2 wk(threadIdx.x, cg1.n);
+        for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
+          const Tap ty = bilinear_tap(rg1.lo + wk.r, d, sd.Hl[s]), tx = bilinear_tap(cg1.lo + wk.c, d, sd.Wl[s]);
+          const int o0 = off + (ty.i0 - f.y0) * f.w - f.x0, o1 = off + (ty.i1 - f.y0) * f.w - f.x0;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            float* B = dyn + j * CS;
+            const float top = fmaf(tx.w, B[o0 + tx.i1], (1.f - tx.w) * B[o0 + tx.i0]);
+            const float bot = fmaf(tx.w, B[o1 + tx.i1], (1.f - tx.w) * B[o1 + tx.i0]);
+            B[L.fq + i] = fabsf(B[L.x1 + i] - fmaf(ty.w, bot, (1.f - ty.w) * top));
+          }
+        }
+        __syncthreads();
+        // statistics of the owned pixels
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float* FQ = dyn + j * CS + L.fq;
+          float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+              const float F = FQ[ro[u] * cg1.n + co[v]];
+              mn = fminf(mn, F);
+              mx = fmaxf(mx, F);
+            }
+          mn = fminf(mn, dpp_f<0xB1>(mn));
+          mx = fmaxf(mx, dpp_f<0xB1>(mx));
+          mn = fminf(mn, dpp_f<0x4E>(mn));
+          mx = fmaxf(mx, dpp_f<0x4E>(mx));
+          mn = fminf(mn, dpp_f<0x141>(mn));
+          mx = fmaxf(mx, dpp_f<0x141>(mx));
+          mn = fminf(mn, dpp_f<0x140>(mn));
+          mx = fmaxf(mx, dpp_f<0x140>(mx));
+          float bmn[4], bmx[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            bmn[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i)) : INFINITY;
+            bmx[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i)) : -INFINITY;
+          }
+          if (lane == 0) {
+            wred[w][j][0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
+            wred[w][j][1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
+            wred[w][j][2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) +
+                            ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
+          }
+        }
+        // REDUCE to the tile: row pass (region rows x tile columns), then column pass
+        {
+          Walk2 wr(threadIdx.x, cg0.n);
+          for (int i = threadIdx.x; i < rg1.n * cg0.n; i += SP_BLOCK, wr.next()) {
+            const int X = cg0.lo + wr.c;
+            int ix[5];
+#pragma unroll
+            for (int t = -2; t <= 2; ++t) ix[t + 2] = wr.r * cg1.n + clampi(2 * X + t, 0, W1 - 1) - cg1.lo;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              const float* FQ = dyn + j * CS + L.fq;
+              float acc = 0.f;
+#pragma unroll
+              for (int t = -2; t <= 2; ++t) acc = fmaf(binom(t), FQ[ix[t + 2]], acc);
+              dyn[j * CS + L.tm + wr.r * cg0.n + wr.c] = acc;
+            }
+          }
+        }
+        __syncthreads();
+        {
+          Walk2 wc(threadIdx.x, cg0.n);
+          for (int i = threadIdx.x; i < rg0.n * cg0.n; i += SP_BLOCK, wc.next()) {
+            const int Y = rg0.lo + wc.r;
+            int iy[5];
+#pragma unroll
+            for (int t = -2; t <= 2; ++t) iy[t + 2] = (clampi(2 * Y + t, 0, H1 - 1) - rg1.lo) * cg0.n + wc.c;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              const float* TM = dyn + j * CS + L.tm;
+              float acc = 0.f;
+#pragma unroll
+              for (int t = -2; t <= 2; ++t) acc = fmaf(binom(t), TM[iy[t + 2]], acc);
+              gmap[((size_t)p * SP_NCH + k0 + j) * plane + (size_t)Y * Wm + cg0.lo + wc.c] = acc;
+            }
+          }
+        }
+        if ((int)threadIdx.x < NC) {
+          const int j = threadIdx.x;
+          const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)(k0 + j) * sd.cs_nt[p] + J.tid);
+          out[0] = fminf(fminf(wred[0][j][0], wred[1][j][0]), fminf(wred[2][j][0], wred[3][j][0]));
+          out[1] = fmaxf(fmaxf(wred[0][j][1], wred[1][j][1]), fmaxf(wred[2][j][1], wred[3][j][1]));
+          out[2] = (wred[0][j][2] + wred[1][j][2]) + (wred[2][j][2] + wred[3][j][2]);
+        }
+        __syncthreads();   // fq, tm and wred are reused by the next pair
+      }
+      off += csapply_foot_cap(r, d);
+    }
+  }
+}
+
+// F-bar_k on a 16x16 c_max tile = sum over pairs of N(reduced map), all 8 channels; then
+// its partial statistics (one 8x8 block per wavefront).
+__global__ __launch_bounds__(SP_BLOCK) void k_csmix(const Job* __restrict__ jobs,
+                                                    const StreamDesc* __restrict__ sds,
+                                                    const StepIO* __restrict__ ios, StepIO io0) {
+  __shared__ float nps[SP_MAXP][SP_NCH][3];
+  __shared__ float wacc[4][SP_NCH][3];
+  const Job J = jobs[blockIdx.x];
+  const StreamDesc& sd = sds[J.stream];
+  const int cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
+  const size_t plane = (size_t)Hm * Wm;
+  for (int i = threadIdx.x; i < sd.n_pairs * SP_NCH; i += SP_BLOCK) {
+    const NParams q = load_np(sd.cs_np + 4 * (size_t)i);
+    (&nps[0][0][0])[3 * i] = q.mn;
+    (&nps[0][0][0])[3 * i + 1] = q.flat ? 0.f : q.inv;
+    (&nps[0][0][0])[3 * i + 2] = q.flat ? 0.f : q.scale;
+  }
+  const int lane = lane_id(), w = wave_id();
+  const int by = w >> 1, bx = w & 1;
+  const int yy = 8 * by + (lane >> 3), xx = 8 * bx + (lane & 7);
+  const bool bvalid = 8 * by < J.th && 8 * bx < J.tw;
+  const bool valid = yy < J.th && xx < J.tw;
+  const size_t o = (size_t)(J.y0 + min(yy, J.th - 1)) * Wm + J.x0 + min(xx, J.tw - 1);
+  const gp<const float> gmap = G((const float*)sd.gmap);
+  __syncthreads();
+  float acc[SP_NCH];
+#pragma unroll
+  for (int k = 0; k < SP_NCH; ++k) acc[k] = 0.f;
+  for (int p = 0; p < sd.n_pairs; ++p) {
+    float g[SP_NCH];
+#pragma unroll
+    for (int k = 0; k < SP_NCH; ++k) g[k] = gmap[((size_t)p * SP_NCH + k) * plane + o];
+#pragma unroll
+    for (int k = 0; k < SP_NCH; ++k)
+      acc[k] = fmaf((g[k] - nps[p][k][0]) * nps[p][k][1], nps[p][k][2], acc[k]);
+  }
+  const gp<float> fbar = G(sd.fbar);
+#pragma unroll
+  for (int k = 0; k < SP_NCH; ++k) {
+    if (valid) fbar[(size_t)k * plane + o] = acc[k];
+    const float wmn = wave_reduce<OpMin>(valid ? acc[k] : INFINITY);
+    const float wmx = wave_reduce<OpMax>(valid ? acc[k] : -INFINITY);
+    if (lane == 0) {
+      wacc[w][k][0] = wmn;
+      wacc[w][k][1] = wmx;
+      wacc[w][k][2] = bvalid ? wmx : 0.f;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < SP_NCH) {
+    const int k = threadIdx.x;
+    const gp<float> out = G(sd.fbar_part) + 3 * ((size_t)k * sd.n_cmax_tiles + J.tid);
+    out[0] = fminf(fminf(wacc[0][k][0], wacc[1][k][0]), fminf(wacc[2][k][0], wacc[3][k][0]));
+    out[1] = fmaxf(fmaxf(wacc[0][k][1], wacc[1][k][1]), fmaxf(wacc[2][k][1], wacc[3][k][1]));
+    out[2] = (wacc[0][k][2] + wacc[1][k][2]) + (wacc[2][k][2] + wacc[3][k][2]);
   }
 }
 
@@ -1766,6 +2083,17 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
     case JOB_TAIL: hipLaunchKernelGGL(k_pyr<true>, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSSTATS: hipLaunchKernelGGL(k_csstats, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSFINAL: hipLaunchKernelGGL(k_csfinal, g, b, 0, st, jobs, sds, ios, io); break;
+    case JOB_CSG:   // flag: channels per workgroup
+      if (flag == 8)
+        hipLaunchKernelGGL(k_csg<8>, g, b, lds, st, jobs, sds, ios, io);
+      else if (flag == 4)
+        hipLaunchKernelGGL(k_csg<4>, g, b, lds, st, jobs, sds, ios, io);
+      else if (flag == 2)
+        hipLaunchKernelGGL(k_csg<2>, g, b, lds, st, jobs, sds, ios, io);
+      else
+        hipLaunchKernelGGL(k_csg<1>, g, b, lds, st, jobs, sds, ios, io);
+      break;
+    case JOB_CSMIX: hipLaunchKernelGGL(k_csmix, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSAPPLY:   // flag: channels per workgroup
       if (flag == 8)
         hipLaunchKernelGGL(k_csapply<8>, g, b, lds, st, jobs, sds, ios, io);
@@ -1846,8 +2174,10 @@ hipError_t sp_launch_batch_copy_out(int n, const BatchState* st, const StreamDes
 
 hipError_t sp_csapply_reserve_lds(size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
-  const void* fns[4] = {reinterpret_cast<const void*>(&k_csapply<1>), reinterpret_cast<const void*>(&k_csapply<2>),
-                        reinterpret_cast<const void*>(&k_csapply<4>), reinterpret_cast<const void*>(&k_csapply<8>)};
+  const void* fns[8] = {reinterpret_cast<const void*>(&k_csapply<1>), reinterpret_cast<const void*>(&k_csapply<2>),
+                        reinterpret_cast<const void*>(&k_csapply<4>), reinterpret_cast<const void*>(&k_csapply<8>),
+                        reinterpret_cast<const void*>(&k_csg<1>),     reinterpret_cast<const void*>(&k_csg<2>),
+                        reinterpret_cast<const void*>(&k_csg<4>),     reinterpret_cast<const void*>(&k_csg<8>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
