@@ -2,7 +2,7 @@
 """Throughput of the saliency -> Kalman prior -> MRF weight path on one MI355X.
 
 Prints ONE JSON line.  A step is one replay of the batched step over 16 streams of
-640x480 frames (config-1 generator, seeds 6000+i): every stream's saliency map, Kalman
+640x480 frames (single-ellipse generator, seeds 6000+i): every stream's saliency map, Kalman
 prior and MRF capacities, each phase one launch over all streams, inputs resident in
 HBM; value = frames per second over the 16 streams.  Beside the headline it reports, on
 the same GPU:
@@ -128,7 +128,7 @@ def cpu_baseline(frames_np, budget_s: float):
     if limiter is not None:
         limiter.unregister() if hasattr(limiter, "unregister") else None
     return {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} frames of the 640x480 clip (config-1 generator, seed 2): saliency, observation, "
+            "sample": f"{n} frames of the 640x480 clip (single-ellipse generator, seed 2): saliency, observation, "
                       f"Kalman update and MRF capacities in FP64 NumPy, one thread, {dt:.1f} s"}
 
 
@@ -207,7 +207,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--skip", default="", help="comma list of legs to skip: plain,bwd,mixed,cpu,profile")
+    ap.add_argument("--skip", default="", help="comma list of legs to skip: batched,plain,bwd,mixed,cpu,profile")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="short run for rocprofv3 --pmc: a 256 MiB copy (calibration) then 5 batched steps")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -245,7 +245,7 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        bf = [torch.from_numpy(synth.Clip(synth.config1_spec(H=H, W=W, T=2, seed=6000 + i)).stack()[0]).to(dev)
+        bf = [torch.from_numpy(synth.Clip(synth.single_ellipse_spec(H=H, W=W, T=2, seed=6000 + i)).stack()[0]).to(dev)
               for i in range(16)]
         tabs = [Batch.pointer_table([f[t] for f in bf]) for t in range(2)]
         b = Batch([(H, W)] * 16, Params(), mrf=True)
@@ -258,40 +258,42 @@ def main():
 
     # ------------------------------------------------------------ headline: batched 16 x 640x480
     NS, NF = 16, 8
-    log(f"generating {NS} streams x {NF} frames of 640x480")
-    bframes = [torch.from_numpy(synth.Clip(synth.config1_spec(H=H, W=W, T=NF, seed=6000 + i)).stack()[0]).to(dev)
-               for i in range(NS)]
-    tables = [Batch.pointer_table([bf[t] for bf in bframes]) for t in range(NF)]
-    bt = Batch([(H, W)] * NS, Params(), mrf=True)
-    tune_report = bt.autotune(tables[0], steps=5)
-    log("autotune: " + tune_report.strip().replace("\n", "; "))
-    bstep = lambda i: bt.step(tables[i % NF])
-    log(f"batched step: warmup {args.warmup}, timed {args.steps}")
-    timed(bstep, args.warmup)
-    dt = timed(bstep, args.steps)
-    ms_step = dt / args.steps * 1e3
-    value = NS * args.steps / dt
-    log(f"batched: {value:.1f} frames/s ({ms_step:.4f} ms/step)")
-    g = Context(H, W, Params()).geometry
+    value, ms_step, tune_report = None, None, ""
     roof, kernels = None, {}
-    if "profile" not in skip:
-        nprof = min(args.steps, 100)
-        profile_enable(bt, True)
-        timed(bstep, nprof)
-        prof = profile_read(bt)
-        profile_enable(bt, False)
-        per_stream = alg_bytes_per_stream(g, mrf=True, prior_copy=False)
-        bytes_step = {k: NS * v for k, v in per_stream.items()}
-        for name, (ms, cnt) in prof.items():
-            kernels[name] = {"avg_us": round(ms / cnt * 1e3, 3), "launches_per_step": cnt / nprof,
-                             "us_per_step": round(ms / nprof * 1e3, 3),
-                             "alg_GBps": round(bytes_step.get(name, float("nan")) / (ms / nprof * 1e-3) / 1e9, 2)}
-        roof = roofline_of(prof, bytes_step, nprof)
-    bt.close()
+    g = Context(H, W, Params()).geometry
+    if "batched" not in skip:   # skipped only to trace the other legs on their own
+        log(f"generating {NS} streams x {NF} frames of 640x480")
+        bframes = [torch.from_numpy(synth.Clip(synth.single_ellipse_spec(H=H, W=W, T=NF, seed=6000 + i)).stack()[0]).to(dev)
+                   for i in range(NS)]
+        tables = [Batch.pointer_table([bf[t] for bf in bframes]) for t in range(NF)]
+        bt = Batch([(H, W)] * NS, Params(), mrf=True)
+        tune_report = bt.autotune(tables[0], steps=5)
+        log("autotune: " + tune_report.strip().replace("\n", "; "))
+        bstep = lambda i: bt.step(tables[i % NF])
+        log(f"batched step: warmup {args.warmup}, timed {args.steps}")
+        timed(bstep, args.warmup)
+        dt = timed(bstep, args.steps)
+        ms_step = dt / args.steps * 1e3
+        value = NS * args.steps / dt
+        log(f"batched: {value:.1f} frames/s ({ms_step:.4f} ms/step)")
+        if "profile" not in skip:
+            nprof = min(args.steps, 100)
+            profile_enable(bt, True)
+            timed(bstep, nprof)
+            prof = profile_read(bt)
+            profile_enable(bt, False)
+            per_stream = alg_bytes_per_stream(g, mrf=True, prior_copy=False)
+            bytes_step = {k: NS * v for k, v in per_stream.items()}
+            for name, (ms, cnt) in prof.items():
+                kernels[name] = {"avg_us": round(ms / cnt * 1e3, 3), "launches_per_step": cnt / nprof,
+                                 "us_per_step": round(ms / nprof * 1e3, 3),
+                                 "alg_GBps": round(bytes_step.get(name, float("nan")) / (ms / nprof * 1e-3) / 1e9, 2)}
+            roof = roofline_of(prof, bytes_step, nprof)
+        bt.close()
 
-    # ------------------------------------------------------------ plain single stream (config 3 size)
+    # ------------------------------------------------------------ plain single stream, 640x480
     plain = None
-    clip = synth.Clip(synth.config1_spec(H=H, W=W, T=T_CLIP, seed=2))
+    clip = synth.Clip(synth.single_ellipse_spec(H=H, W=W, T=T_CLIP, seed=2))
     frames_np, masks_np = clip.stack()
     frames = torch.from_numpy(frames_np).to(dev)
     masks = torch.from_numpy(masks_np).to(dev)
@@ -342,7 +344,7 @@ def main():
         ctx.close()
         log(f"plain: {plain['frames_per_s']} frames/s")
 
-    # ------------------------------------------------------------ fwd + bwd (config 3)
+    # ------------------------------------------------------------ fwd + bwd, 640x480
     fb = None
     if "bwd" not in skip:
         tctx = Context(H, W, Params(record_tape=T_CLIP))
@@ -374,11 +376,11 @@ def main():
         tctx.close()
         log(f"fwd+bwd: {fb['frames_per_s']} frames/s")
 
-    # ------------------------------------------------------------ mixed batch of 64 streams (config 4)
+    # ------------------------------------------------------------ mixed batch of 64 streams of four sizes
     mixed = None
     if "mixed" not in skip:
         sizes = [(120, 160)] * 16 + [(240, 320)] * 16 + [(480, 640)] * 16 + [(720, 1280)] * 16
-        mf = [torch.from_numpy(synth.Clip(synth.config1_spec(H=hh, W=ww, T=4, seed=1000 + i)).stack()[0]).to(dev)
+        mf = [torch.from_numpy(synth.Clip(synth.single_ellipse_spec(H=hh, W=ww, T=4, seed=1000 + i)).stack()[0]).to(dev)
               for i, (hh, ww) in enumerate(sizes)]
         mtab = [Batch.pointer_table([f[t] for f in mf]) for t in range(4)]
         mb = Batch(sizes, Params())
@@ -399,18 +401,18 @@ def main():
 
     out = {
         "metric": "frames/s saliency+Kalman prior at 640x480 (fwd, fwd+bwd, batched); HBM GB/s",
-        "value": round(value, 2),
+        "value": None if value is None else round(value, 2),
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": None if ms_step is None else round(ms_step, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "batched step: 16 streams of 640x480 (config-1 generator, seeds 6000+i, 8 frames "
+        "config": {"workload": "batched step: 16 streams of 640x480 (single-ellipse generator, seeds 6000+i, 8 frames "
                                "cycled), one graph replay per step computing every stream's saliency map, Kalman "
                                "prior and MRF capacities",
                    "streams": NS, "H": H, "W": W, "depth": g.depth, "pairs": g.pairs, "c_max": g.c_max,

@@ -208,19 +208,19 @@ class Clip:
 
 
 # -- the named workloads -------------------------------------------------------
-def config1_spec(H: int = 120, W: int = 160, T: int = 30, seed: int = 0) -> ClipSpec:
+def single_ellipse_spec(H: int = 120, W: int = 160, T: int = 30, seed: int = 0) -> ClipSpec:
     """Uniform-noise background, one saturated 15x10 ellipse, 2 px/frame."""
     return ClipSpec(H=H, W=W, T=T, background="uniform", n_objects=1, axes=(15.0, 10.0),
                     speed=2.0, colours="saturated", seed=seed)
 
 
-def config2_spec(H: int = 240, W: int = 320, T: int = 300, seed: int = 1) -> ClipSpec:
+def three_ellipse_spec(H: int = 240, W: int = 320, T: int = 300, seed: int = 1) -> ClipSpec:
     """Perlin background, three random-colour ellipses, radii 10-40, speed <= 4."""
     return ClipSpec(H=H, W=W, T=T, background="perlin", n_objects=3, axes=None,
                     axes_range=(10.0, 40.0), speed=None, max_speed=4.0, colours="hsv", seed=seed)
 
 
-def config5_spec(H: int = 1080, W: int = 1920, T: int = 1000, seed: int = 5) -> ClipSpec:
+def five_ellipse_spec(H: int = 1080, W: int = 1920, T: int = 1000, seed: int = 5) -> ClipSpec:
     """Perlin background, five random-colour ellipses, speed <= 8; radii scaled
     from the 240-row family by H/240."""
     s = H / 240.0
@@ -232,12 +232,12 @@ def config5_spec(H: int = 1080, W: int = 1920, T: int = 1000, seed: int = 5) -> 
 def mixed_batch_specs(T: int = 60, per_size: int = 16, base_seed: int = 1000,
                       sizes: Sequence[Tuple[int, int]] = ((120, 160), (240, 320), (480, 640), (720, 1280))
                       ) -> List[ClipSpec]:
-    """Many streams of uneven resolution, config-1 generator, seeds base_seed + i."""
+    """Many streams of uneven resolution, single-ellipse generator, seeds base_seed + i."""
     specs = []
     i = 0
     for (H, W) in sizes:
         for _ in range(per_size):
-            specs.append(config1_spec(H=H, W=W, T=T, seed=base_seed + i))
+            specs.append(single_ellipse_spec(H=H, W=W, T=T, seed=base_seed + i))
             i += 1
     return specs
 

@@ -89,7 +89,7 @@ def check(label, gpu, ref, tol=1e-3):
 
 
 def small_clip(H=64, W=80, T=10, seed=3):
-    spec = synth.config1_spec(H=H, W=W, T=T, seed=seed)
+    spec = synth.single_ellipse_spec(H=H, W=W, T=T, seed=seed)
     spec.axes = (9.0, 6.0)
     spec.speed = 1.5
     return synth.Clip(spec).stack()
@@ -126,18 +126,18 @@ def test_adjoint_with_segmentation_feedback():
     check("seg-feedback", gpu, ref)
 
 
-def test_adjoint_config1_clip():
-    banner("adjoint config 1: 160x120 x 30 frames")
-    frames, masks = synth.Clip(synth.config1_spec(T=30)).stack()
+def test_adjoint_single_ellipse_clip():
+    banner("adjoint 160x120 x 30 frames")
+    frames, masks = synth.Clip(synth.single_ellipse_spec(T=30)).stack()
     pp = params()
     gpu = gpu_grad(frames, masks, pp, np.ones(8), 1e-3, 1e-1)
     ref = oracle_grads(frames, masks, pp, np.ones(8), 1e-3, 1e-1)
-    check("config1", gpu, ref)
+    check("160x120", gpu, ref)
 
 
 def test_adjoint_640x480_sampled():
-    banner("adjoint at 640x480 (config-3 size), 6 frames, tape chunking over recompute streams")
-    frames, masks = synth.Clip(synth.config1_spec(H=480, W=640, T=6, seed=2)).stack()
+    banner("adjoint at 640x480, 6 frames, tape chunking over recompute streams")
+    frames, masks = synth.Clip(synth.single_ellipse_spec(H=480, W=640, T=6, seed=2)).stack()
     pp = params()
     gpu = gpu_grad(frames, masks, pp, W8, 1e-3, 1e-1)
     ref = oracle_grads(frames, masks, pp, W8, 1e-3, 1e-1, fd=False)

@@ -26,7 +26,7 @@ def test_batched_step_equals_plain_streams():
     T = 7
     clips = []
     for i, (H, W) in enumerate(sizes):
-        spec = synth.config1_spec(H=H, W=W, T=T, seed=1000 + i)
+        spec = synth.single_ellipse_spec(H=H, W=W, T=T, seed=1000 + i)
         spec.axes = (min(15.0, W / 4), min(10.0, H / 4))
         f, _ = synth.Clip(spec).stack()
         clips.append(torch.from_numpy(f).cuda())
@@ -60,7 +60,7 @@ def test_batch_of_one_large_stream_and_prior_pointer():
     import ctypes
     from paper_1008_0502_amd.api import Batch, Context, Params
     sizes = [(720, 1280), (120, 160)]
-    clips = [torch.from_numpy(synth.Clip(synth.config1_spec(H=H, W=W, T=3, seed=7 + i)).stack()[0]).cuda()
+    clips = [torch.from_numpy(synth.Clip(synth.single_ellipse_spec(H=H, W=W, T=3, seed=7 + i)).stack()[0]).cuda()
              for i, (H, W) in enumerate(sizes)]
     pp = Params()
     b = Batch(sizes, pp)
@@ -100,7 +100,7 @@ def test_batched_step_with_mrf_equals_fused_plain_step():
     T = 4
     clips = []
     for i, (H, W) in enumerate(sizes):
-        spec = synth.config2_spec(H=H, W=W, T=T, seed=40 + i)
+        spec = synth.three_ellipse_spec(H=H, W=W, T=T, seed=40 + i)
         clips.append(torch.from_numpy(synth.Clip(spec).stack()[0]).cuda())
     pp = Params()
     ctxs = [Context(H, W, pp) for (H, W) in sizes]
@@ -131,7 +131,7 @@ def test_autotuner_keeps_results_identical():
     from paper_1008_0502_amd.api import Batch, Context, Params
     sizes = [(240, 320), (120, 160), (240, 320)]
     T = 3
-    clips = [torch.from_numpy(synth.Clip(synth.config1_spec(H=H, W=W, T=T, seed=70 + i)).stack()[0]).cuda()
+    clips = [torch.from_numpy(synth.Clip(synth.single_ellipse_spec(H=H, W=W, T=T, seed=70 + i)).stack()[0]).cuda()
              for i, (H, W) in enumerate(sizes)]
     pp = Params()
     ref = []

@@ -80,29 +80,29 @@ def params(**kw):
 
 
 # ---------------------------------------------------------------- named workloads (small sizes)
-def test_config1_clip_160x120():
-    banner("config 1: 160x120, 30 frames, uniform-noise background")
-    clip = synth.Clip(synth.config1_spec(T=30))
+def test_single_ellipse_clip_160x120():
+    banner("160x120, 30 frames, uniform-noise background")
+    clip = synth.Clip(synth.single_ellipse_spec(T=30))
     frames, _ = clip.stack()
     pp = params(q=1e-3, r=1e-1)
     gpu, ref = run_both(frames, pp, with_mrf=True)
-    check_clip(gpu, ref, frames, pp, label="config1")
-    check_mrf(gpu, frames, pp, label="config1")
+    check_clip(gpu, ref, frames, pp, label="160x120")
+    check_mrf(gpu, frames, pp, label="160x120")
 
 
-def test_config2_clip_320x240_with_mrf():
-    banner("config 2: 320x240 Perlin background, 3 ellipses, depth 6, c in {2,3}, surround +{3,4}; 8 frames")
-    clip = synth.Clip(synth.config2_spec(T=8))
+def test_three_ellipse_clip_320x240_with_mrf():
+    banner("320x240 Perlin background, 3 ellipses, depth 6, c in {2,3}, surround +{3,4}; 8 frames")
+    clip = synth.Clip(synth.three_ellipse_spec(T=8))
     frames, _ = clip.stack()
     pp = params(depth=6, centers=(2, 3), deltas=(3, 4))
     gpu, ref = run_both(frames, pp, with_mrf=True)
-    check_clip(gpu, ref, frames, pp, label="config2")
-    check_mrf(gpu, frames, pp, label="config2")
+    check_clip(gpu, ref, frames, pp, label="320x240")
+    check_mrf(gpu, frames, pp, label="320x240")
 
 
-def test_config3_size_640x480_sampled_frames():
-    banner("config 3 size: 640x480, first 3 frames (bench configuration)")
-    clip = synth.Clip(synth.config1_spec(H=480, W=640, T=3, seed=2))
+def test_640x480_sampled_frames():
+    banner("640x480, first 3 frames (bench frame size)")
+    clip = synth.Clip(synth.single_ellipse_spec(H=480, W=640, T=3, seed=2))
     frames, _ = clip.stack()
     pp = params()
     gpu, ref = run_both(frames, pp, with_mrf=True)
@@ -110,9 +110,9 @@ def test_config3_size_640x480_sampled_frames():
     check_mrf(gpu, frames[:1], pp, label="640x480")
 
 
-def test_config5_size_1080p_two_frames():
-    banner("config 5 size: 1920x1080, depth 9, c in {2,3,4}, surround +{3,4}; 2 frames")
-    clip = synth.Clip(synth.config5_spec(T=2))
+def test_five_ellipse_1080p_two_frames():
+    banner("1920x1080, depth 9, c in {2,3,4}, surround +{3,4}; 2 frames")
+    clip = synth.Clip(synth.five_ellipse_spec(T=2))
     frames, _ = clip.stack()
     pp = params(depth=9, centers=(2, 3, 4), deltas=(3, 4))
     gpu, ref = run_both(frames, pp)
@@ -123,7 +123,7 @@ def test_config5_size_1080p_two_frames():
 @pytest.mark.parametrize("H,W", [(97, 131), (33, 47), (130, 18)])
 def test_ragged_sizes(H, W):
     banner(f"ragged {H}x{W}")
-    spec = synth.config1_spec(H=H, W=W, T=4, seed=H + W)
+    spec = synth.single_ellipse_spec(H=H, W=W, T=4, seed=H + W)
     spec.axes = (min(15.0, W / 4), min(10.0, H / 4))
     frames, _ = synth.Clip(spec).stack()
     pp = params()
@@ -161,7 +161,7 @@ def test_constant_frames_are_flat():
 
 def test_three_octave_centres_and_nondefault_params():
     banner("centres {1,2,3} (two-level across-scale reduction), border 2, Gabor radius 4, random weights")
-    spec = synth.config2_spec(H=120, W=160, T=5, seed=12)
+    spec = synth.three_ellipse_spec(H=120, W=160, T=5, seed=12)
     frames, _ = synth.Clip(spec).stack()
     rng = np.random.default_rng(0)
     w = tuple(float(x) for x in rng.uniform(0.3, 1.7, 8))
@@ -174,7 +174,7 @@ def test_three_octave_centres_and_nondefault_params():
 
 def test_segmentation_feedback_path():
     banner("previous segmentation supplied to the prior update")
-    clip = synth.Clip(synth.config1_spec(T=6, seed=3))
+    clip = synth.Clip(synth.single_ellipse_spec(T=6, seed=3))
     frames, masks = clip.stack()
     segs = [None] + [masks[t - 1] for t in range(1, 6)]
     segs[3] = None
@@ -187,7 +187,7 @@ def test_determinism_and_state_resume():
     banner("bitwise determinism and checkpoint/resume of the Kalman state")
     torch = _torch()
     from paper_1008_0502_amd.api import Context
-    frames, _ = synth.Clip(synth.config1_spec(T=10, seed=9)).stack()
+    frames, _ = synth.Clip(synth.single_ellipse_spec(T=10, seed=9)).stack()
     fr = torch.from_numpy(frames).cuda()
     ctx = Context(120, 160, params())
     a = ctx.run_clip(fr)["pi"].cpu().numpy()
@@ -253,7 +253,7 @@ def test_fused_step_equals_separate_calls():
     banner("sp_step (fused whole path) vs saliency_forward + prior_update + mrf_weights: bitwise")
     torch = _torch()
     from paper_1008_0502_amd.api import Context
-    frames, _ = synth.Clip(synth.config2_spec(H=240, W=320, T=5, seed=21)).stack()
+    frames, _ = synth.Clip(synth.three_ellipse_spec(H=240, W=320, T=5, seed=21)).stack()
     fr = torch.from_numpy(frames).cuda()
     pp = params(depth=6, centers=(2, 3), deltas=(3, 4))
     a = Context(240, 320, pp)

@@ -419,7 +419,7 @@ def test_pyramid_linear_and_bilinear_exact_at_samples():
 
 # ---------------------------------------------------------------- P9 transpose symmetry
 def test_transpose_symmetry_of_whole_path():
-    spec = synth.config1_spec(H=40, W=56, T=3, seed=4)
+    spec = synth.single_ellipse_spec(H=40, W=56, T=3, seed=4)
     fr, _ = synth.Clip(spec).stack()
     frT = np.ascontiguousarray(fr.transpose(0, 2, 1, 3))
     p = O.OracleParams(depth=3, centers=(1,), deltas=(1, 2))
@@ -478,7 +478,7 @@ def test_mrf_properties_and_brute_force_beta():
 
 # ---------------------------------------------------------------- P6, P12 gradients
 def _small_problem(seed=3, H=24, W=32, T=8):
-    spec = synth.config1_spec(H=H, W=W, T=T, seed=seed)
+    spec = synth.single_ellipse_spec(H=H, W=W, T=T, seed=seed)
     spec.axes = (6.0, 4.0)
     spec.speed = 1.5
     fr, masks = synth.Clip(spec).stack()
