@@ -691,6 +691,9 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
 // 13x13 (radius R) zero-DC even Gabor kernels applied as separable rank-1 terms:
 //   O0 = H[gm] V[g], O90 = H[g] V[gm],
 //   O45 = H[gc] V[gc] - H[gs] V[gs] - c45 H[g] V[g], O135 = same with + H[gs] V[gs].
+// NT: taps per pass the loops are unrolled to (2R+1 for the radius they are built for,
+// else the padded maximum).
+template <int NT>
 __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt, float* smem) {
   float* Ir = smem;                            // [RR][RR] (flat, RR <= GRM)
   float* V = Ir + GRM * (GRM + 1);             // [4][GT][GRM+1]
@@ -713,7 +716,7 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
     const float* tp = taps + f * (2 * SP_MAXR + 1);
     float acc = 0.f;
 #pragma unroll
-    for (int v = 0; v < 2 * SP_MAXR + 1; ++v) acc += tp[v] * Ir[(yy + min(v, n - 1)) * RR + xr];
+    for (int v = 0; v < NT; ++v) acc += tp[v] * Ir[(yy + min(v, n - 1)) * RR + xr];
     V[(f * GT + yy) * (GRM + 1) + xr] = acc;
   }
   __syncthreads();
@@ -729,7 +732,7 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
   const float* V3 = V + (3 * GT + yy) * (GRM + 1) + xx;
   float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
 #pragma unroll
-  for (int u = 0; u < 2 * SP_MAXR + 1; ++u) {
+  for (int u = 0; u < NT; ++u) {
     const int uc = min(u, n - 1);
     const float vg = V0[uc];
     A += t1[u] * vg;
@@ -751,6 +754,7 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
 // Gabor maps of a whole (small) level held in LDS.
 // Rows [y0, y0 + nr) only: the vertical pass of an output row reads the whole level (in
 // LDS), so a band needs no halo of its own.
+template <int NT>
 __device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V, const float* taps, int R, float c45,
                           gp<float> out) {
   const int n = nr * w, plane = h * w;
@@ -761,7 +765,7 @@ __device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V
       const int y = y0 + wk.r, x = wk.c;
       float acc = 0.f;
 #pragma unroll
-      for (int v = 0; v < 2 * SP_MAXR + 1; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
+      for (int v = 0; v < NT; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
       V[f * n + pix] = acc;
     }
   }
@@ -775,7 +779,7 @@ __device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V
     const int y = wk.r, x = wk.c;   // y relative to the band
     float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
 #pragma unroll
-    for (int u = 0; u < 2 * SP_MAXR + 1; ++u) {
+    for (int u = 0; u < NT; ++u) {
       const int o = y * w + clampi(x + u - R, 0, w - 1);
       const float vg = V[o];
       A += t1[u] * vg;
@@ -839,7 +843,12 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
       if (dst) dst[i] = acc;
     }
     __syncthreads();
-    if (gab && l + 1 == last) gabor_lds(nxt, nH, nW, J.y0, J.th, V, taps, R, sd.c45, G(sd.gab[l + 1]));
+    if (gab && l + 1 == last) {
+      if (R == 6)
+        gabor_lds<13>(nxt, nH, nW, J.y0, J.th, V, taps, R, sd.c45, G(sd.gab[l + 1]));
+      else
+        gabor_lds<2 * SP_MAXR + 1>(nxt, nH, nW, J.y0, J.th, V, taps, R, sd.c45, G(sd.gab[l + 1]));
+    }
     float* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -859,7 +868,10 @@ __global__ __launch_bounds__(SP_BLOCK) __attribute__((amdgpu_waves_per_eu(BIG ? 
   if (J.kind == JOB_DOWN) {
     down_job(J, sd, ckpt, smem);
   } else if (J.kind == JOB_GABOR) {
-    gabor_job(J, sd, ckpt, smem);
+    if (sd.gr == 6)   // the default radius: loops unrolled to exactly 13 taps
+      gabor_job<13>(J, sd, ckpt, smem);
+    else
+      gabor_job<2 * SP_MAXR + 1>(J, sd, ckpt, smem);
   } else if (BIG && (J.kind == JOB_TAIL || J.kind == JOB_TAILGAB)) {
     tail_job(J, sd, ckpt, smem);
   }
