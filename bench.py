@@ -164,6 +164,8 @@ def pmc_summarize(fetch_db: str, write_db: str) -> None:
         short = re.sub(r"\(anonymous namespace\)::", "", raw)
         short = re.sub(r"\(.*\)$", "", short).replace("void ", "").replace(" ", "")
         key = names.get(short) or names.get(re.sub(r"<.*>$", "", short))
+        if short.startswith("k_pyr<"):
+            key = "k_pyr_tail" if short.startswith("k_pyr<true") else "k_pyr"
         if key is None:
             continue
         f = fetch.get(raw, [0.0])

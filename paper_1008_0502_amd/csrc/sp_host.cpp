@@ -255,7 +255,7 @@ void pyramid_stages(const Geo& g, int s, int lo, std::vector<std::vector<Job>>& 
   for (int j = lo; j < L0; ++j) {
     std::vector<Job> v;
     add_tiles(v, s, j, g.Hl[j + 1], g.Wl[j + 1], JOB_DOWN);
-    if (g.used & (1u << j)) add_tiles(v, s, j, g.Hl[j], g.Wl[j], JOB_GABOR);
+    if (g.used & (1u << j)) add_tiles_wh(v, s, j, g.Hl[j], g.Wl[j], 16, 32, JOB_GABOR);
     mid.push_back(std::move(v));
   }
   *big = L0 < g.top;
@@ -269,7 +269,7 @@ void pyramid_stages(const Geo& g, int s, int lo, std::vector<std::vector<Job>>& 
       }
     for (int ch = 0; ch < 4; ++ch) fin.push_back(Job{s, L0, 0, 0, g.Hl[L0], g.Wl[L0], ch, JOB_TAIL});
   }
-  if (g.used & (1u << L0)) add_tiles(fin, s, L0, g.Hl[L0], g.Wl[L0], JOB_GABOR);
+  if (g.used & (1u << L0)) add_tiles_wh(fin, s, L0, g.Hl[L0], g.Wl[L0], 16, 32, JOB_GABOR);
 }
 
 // ---------------------------------------------------------------- device memory layout
@@ -807,7 +807,8 @@ int ctx_build_tables(sp_ctx* c) {
     build_forward_jobs(parts, kinds, c->h_sd, g, 0, PROG_ALL, nc);
     for (size_t i = 0; i < parts.size(); ++i) {
       const bool grp = kinds[i] == JOB_CSAPPLY || kinds[i] == JOB_CSG;
-      c->fwd.push_back(c->jobs.add(kinds[i], grp ? nc : 0, order(parts[i]), 1));
+      const bool pyr = kinds[i] == JOB_DOWN || kinds[i] == JOB_TAIL;   // flag: Gabor radius
+      c->fwd.push_back(c->jobs.add(kinds[i], grp ? nc : (pyr ? c->p.gabor_radius : 0), order(parts[i]), 1));
       if (grp) c->fwd.back().lds = ca_lds;
     }
     std::vector<Job> v;
@@ -843,7 +844,8 @@ int ctx_build_tables(sp_ctx* c) {
       }
       for (size_t i = 0; i < all.size(); ++i) {
         const bool grp = kk[i] == JOB_CSAPPLY || kk[i] == JOB_CSG;
-        c->rec.push_back(c->jobs.add(kk[i], grp ? nc : 0, all[i], c->CH));
+        const bool pyr = kk[i] == JOB_DOWN || kk[i] == JOB_TAIL;
+        c->rec.push_back(c->jobs.add(kk[i], grp ? nc : (pyr ? c->p.gabor_radius : 0), all[i], c->CH));
         if (grp) c->rec.back().lds = ca_lds;
       }
     }
@@ -1362,8 +1364,8 @@ int batch_build_tables(sp_batch* b) {
   b->phases.push_back(b->jobs.add(JOB_RGB, b->mrf ? 1 : 0, order(rgb), n));
   b->phases.push_back(b->jobs.add(JOB_FEAT, 0, order(feat), n));
   for (auto& d : mids)
-    if (!d.empty()) b->phases.push_back(b->jobs.add(JOB_DOWN, 0, order(d), n));
-  if (!fin.empty()) b->phases.push_back(b->jobs.add(any_big ? JOB_TAIL : JOB_DOWN, 0, fin, n));
+    if (!d.empty()) b->phases.push_back(b->jobs.add(JOB_DOWN, b->p.gabor_radius, order(d), n));
+  if (!fin.empty()) b->phases.push_back(b->jobs.add(any_big ? JOB_TAIL : JOB_DOWN, b->p.gabor_radius, fin, n));
   size_t lds_a = 0, lds_g = 0;
   for (const Geo& g : b->geo) {
     if (gpath_ok(g))

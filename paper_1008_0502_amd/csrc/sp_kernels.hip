@@ -616,8 +616,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
 // ---- jobs of the pyramid kernel (one of DOWN, GABOR, TAIL per workgroup)
 constexpr int DT = 16, DR = 2 * DT + 3;                         // down tile and its source region
 constexpr int DOWN_LDS = 4 * DR * DR;                           // floats (the row pass reuses it)
-constexpr int GT = 16, GRM = GT + 2 * SP_MAXR;                  // Gabor tile and its region
-constexpr int GAB_LDS = GRM * (GRM + 1) + 4 * GT * (GRM + 1) + 4 * (2 * SP_MAXR + 1);
+constexpr int GT = 16, GW = 32;                                 // Gabor tile: rows x columns
+constexpr int GRM = GT + 2 * SP_MAXR, GCM = GW + 2 * SP_MAXR;    // its largest region
+constexpr int GAB_LDS = GRM * GCM + 4 * GT * (GCM + 1) + 4 * (2 * SP_MAXR + 1);
 constexpr int TAIL_LDS = SP_TAIL_SRC + SP_TAIL_ALT + SP_TAIL_HB + SP_TAIL_V + 4 * (2 * SP_MAXR + 1);
 static_assert(DOWN_LDS >= GAB_LDS, "LDS of the small pyramid kernel");
 
@@ -691,63 +692,77 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
 // 13x13 (radius R) zero-DC even Gabor kernels applied as separable rank-1 terms:
 //   O0 = H[gm] V[g], O90 = H[g] V[gm],
 //   O45 = H[gc] V[gc] - H[gs] V[gs] - c45 H[g] V[g], O135 = same with + H[gs] V[gs].
-// NT: taps per pass the loops are unrolled to (2R+1 for the radius they are built for,
-// else the padded maximum).
-template <int NT>
+// RC > 0: built for radius RC (every extent and offset a compile-time constant); RC = 0:
+// any radius, loops unrolled over the zero-padded maximum of taps.
+template <int RC>
 __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt, float* smem) {
-  float* Ir = smem;                            // [RR][RR] (flat, RR <= GRM)
-  float* V = Ir + GRM * (GRM + 1);             // [4][GT][GRM+1]
-  float* taps = V + 4 * GT * (GRM + 1);        // [4][2*SP_MAXR+1]
-  const int l = J.a, R = sd.gr, n = 2 * R + 1, RR = GT + 2 * R;
+  constexpr int NT = RC > 0 ? 2 * RC + 1 : 2 * SP_MAXR + 1;
+  float* Ir = smem;                            // [RRr][RRc] (flat)
+  float* V = Ir + GRM * GCM;                   // [4][GT][GCM+1]
+  float* taps = V + 4 * GT * (GCM + 1);        // [4][2*SP_MAXR+1]
+  const int l = J.a, R = RC > 0 ? RC : sd.gr, n = 2 * R + 1, RRr = GT + 2 * R, RRc = GW + 2 * R;
   const int Hs = sd.Hl[l], Ws = sd.Wl[l];
   const float* I = base_ptr(sd, ckpt, l);
   load_taps(sd, n, taps);
-  Walk2 wk(threadIdx.x, RR);
-  for (int i = threadIdx.x; i < RR * RR; i += SP_BLOCK, wk.next()) {
-    const int ry = wk.r, rx = wk.c;
-    const int y = clampi(J.y0 - R + ry, 0, Hs - 1), x = clampi(J.x0 - R + rx, 0, Ws - 1);
+  Walk2 wk(threadIdx.x, RRc);
+  for (int i = threadIdx.x; i < RRr * RRc; i += SP_BLOCK, wk.next()) {
+    const int y = clampi(J.y0 - R + wk.r, 0, Hs - 1), x = clampi(J.x0 - R + wk.c, 0, Ws - 1);
     lds_load(Ir + i, I + (size_t)y * Ws + x);
   }
   lds_wait();
   __syncthreads();
-  Walk2 wk2(threadIdx.x, RR);
-  for (int i = threadIdx.x; i < 4 * GT * RR; i += SP_BLOCK, wk2.next()) {
-    const int f = wk2.r / GT, yy = wk2.r % GT, xr = wk2.c;
-    const float* tp = taps + f * (2 * SP_MAXR + 1);
-    float acc = 0.f;
+  // vertical pass: the four factors of one (row, column) from one read of its column
+  Walk2 wk2(threadIdx.x, RRc);
+#pragma unroll 1
+  for (int i = threadIdx.x; i < GT * RRc; i += SP_BLOCK, wk2.next()) {
+    const int yy = wk2.r, xr = wk2.c;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
-    for (int v = 0; v < NT; ++v) acc += tp[v] * Ir[(yy + min(v, n - 1)) * RR + xr];
-    V[(f * GT + yy) * (GRM + 1) + xr] = acc;
+    for (int v = 0; v < NT; ++v) {
+      const float iv = Ir[(yy + (RC > 0 ? v : min(v, n - 1))) * RRc + xr];
+      a0 += taps[v] * iv;
+      a1 += taps[(2 * SP_MAXR + 1) + v] * iv;
+      a2 += taps[2 * (2 * SP_MAXR + 1) + v] * iv;
+      a3 += taps[3 * (2 * SP_MAXR + 1) + v] * iv;
+    }
+    V[(0 * GT + yy) * (GCM + 1) + xr] = a0;
+    V[(1 * GT + yy) * (GCM + 1) + xr] = a1;
+    V[(2 * GT + yy) * (GCM + 1) + xr] = a2;
+    V[(3 * GT + yy) * (GCM + 1) + xr] = a3;
   }
   __syncthreads();
-  const int yy = threadIdx.x / GT, xx = threadIdx.x % GT;
-  const int y = J.y0 + yy, x = J.x0 + xx;
   const float* t0 = taps;
   const float* t1 = taps + (2 * SP_MAXR + 1);
   const float* t2 = taps + 2 * (2 * SP_MAXR + 1);
   const float* t3 = taps + 3 * (2 * SP_MAXR + 1);
-  const float* V0 = V + (0 * GT + yy) * (GRM + 1) + xx;
-  const float* V1 = V + (1 * GT + yy) * (GRM + 1) + xx;
-  const float* V2 = V + (2 * GT + yy) * (GRM + 1) + xx;
-  const float* V3 = V + (3 * GT + yy) * (GRM + 1) + xx;
-  float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
+  const size_t plane = (size_t)Hs * Ws;
+  const gp<float> Go = G(sd.gab[l]);
+#pragma unroll 1
+  for (int i = threadIdx.x; i < GT * GW; i += SP_BLOCK) {
+    const int yy = i / GW, xx = i % GW;
+    const int y = J.y0 + yy, x = J.x0 + xx;
+    const float* V0 = V + (0 * GT + yy) * (GCM + 1) + xx;
+    const float* V1 = V + (1 * GT + yy) * (GCM + 1) + xx;
+    const float* V2 = V + (2 * GT + yy) * (GCM + 1) + xx;
+    const float* V3 = V + (3 * GT + yy) * (GCM + 1) + xx;
+    float A = 0.f, B = 0.f, C = 0.f, D = 0.f, E = 0.f;
 #pragma unroll
-  for (int u = 0; u < NT; ++u) {
-    const int uc = min(u, n - 1);
-    const float vg = V0[uc];
-    A += t1[u] * vg;
-    B += t0[u] * vg;
-    C += t0[u] * V1[uc];
-    D += t2[u] * V2[uc];
-    E += t3[u] * V3[uc];
-  }
-  if (yy < J.th && xx < J.tw && y < Hs && x < Ws) {
-    const size_t plane = (size_t)Hs * Ws, o = (size_t)y * Ws + x;
-    const gp<float> Go = G(sd.gab[l]);
-    Go[o] = A;
-    Go[plane + o] = D - E - sd.c45 * B;
-    Go[2 * plane + o] = C;
-    Go[3 * plane + o] = D + E - sd.c45 * B;
+    for (int u = 0; u < NT; ++u) {
+      const int uc = RC > 0 ? u : min(u, n - 1);
+      const float vg = V0[uc];
+      A += t1[u] * vg;
+      B += t0[u] * vg;
+      C += t0[u] * V1[uc];
+      D += t2[u] * V2[uc];
+      E += t3[u] * V3[uc];
+    }
+    if (yy < J.th && xx < J.tw && y < Hs && x < Ws) {
+      const size_t o = (size_t)y * Ws + x;
+      Go[o] = A;
+      Go[plane + o] = D - E - sd.c45 * B;
+      Go[2 * plane + o] = C;
+      Go[3 * plane + o] = D + E - sd.c45 * B;
+    }
   }
 }
 
@@ -758,15 +773,23 @@ template <int NT>
 __device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V, const float* taps, int R, float c45,
                           gp<float> out) {
   const int n = nr * w, plane = h * w;
-  for (int f = 0; f < 4; ++f) {
-    const float* tp = taps + f * (2 * SP_MAXR + 1);
+  {
     Walk2 wk(threadIdx.x, w);
     for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK, wk.next()) {
       const int y = y0 + wk.r, x = wk.c;
-      float acc = 0.f;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
-      for (int v = 0; v < NT; ++v) acc += tp[v] * I[clampi(y + v - R, 0, h - 1) * w + x];
-      V[f * n + pix] = acc;
+      for (int v = 0; v < NT; ++v) {
+        const float iv = I[clampi(y + v - R, 0, h - 1) * w + x];
+        a0 += taps[v] * iv;
+        a1 += taps[(2 * SP_MAXR + 1) + v] * iv;
+        a2 += taps[2 * (2 * SP_MAXR + 1) + v] * iv;
+        a3 += taps[3 * (2 * SP_MAXR + 1) + v] * iv;
+      }
+      V[pix] = a0;
+      V[n + pix] = a1;
+      V[2 * n + pix] = a2;
+      V[3 * n + pix] = a3;
     }
   }
   __syncthreads();
@@ -801,6 +824,7 @@ __device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V
 // (channel tid) compute and store every level up to the top; TAILGAB jobs rebuild the
 // intensity chain up to level tid and store that level's Gabor maps for the row band
 // y0 .. y0+th-1, so the Gabor work of the small levels runs in parallel workgroups.
+template <int RC>
 __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float* smem) {
   float* SA = smem;
   float* SB = SA + SP_TAIL_SRC;
@@ -843,12 +867,9 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
       if (dst) dst[i] = acc;
     }
     __syncthreads();
-    if (gab && l + 1 == last) {
-      if (R == 6)
-        gabor_lds<13>(nxt, nH, nW, J.y0, J.th, V, taps, R, sd.c45, G(sd.gab[l + 1]));
-      else
-        gabor_lds<2 * SP_MAXR + 1>(nxt, nH, nW, J.y0, J.th, V, taps, R, sd.c45, G(sd.gab[l + 1]));
-    }
+    if (gab && l + 1 == last)
+      gabor_lds<(RC > 0 ? 2 * RC + 1 : 2 * SP_MAXR + 1)>(nxt, nH, nW, J.y0, J.th, V, taps, R, sd.c45,
+                                                     G(sd.gab[l + 1]));
     float* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -857,10 +878,11 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   }
 }
 
-template <bool BIG>
-__global__ __launch_bounds__(SP_BLOCK) __attribute__((amdgpu_waves_per_eu(BIG ? 1 : 8))) void k_pyr(const Job* __restrict__ jobs,
-                                                  const StreamDesc* __restrict__ sds,
-                                                  const StepIO* __restrict__ ios, StepIO io0) {
+// RC: the Gabor radius the launch is built for (every stream of a launch shares it), or
+// 0 for any radius.  The default radius keeps 8 workgroups per CU.
+template <bool BIG, int RC>
+__global__ __launch_bounds__(SP_BLOCK) __attribute__((amdgpu_waves_per_eu((!BIG && RC > 0) ? 6 : 1))) void k_pyr(
+    const Job* __restrict__ jobs, const StreamDesc* __restrict__ sds, const StepIO* __restrict__ ios, StepIO io0) {
   __shared__ float smem[BIG ? TAIL_LDS : DOWN_LDS];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
@@ -868,12 +890,9 @@ __global__ __launch_bounds__(SP_BLOCK) __attribute__((amdgpu_waves_per_eu(BIG ? 
   if (J.kind == JOB_DOWN) {
     down_job(J, sd, ckpt, smem);
   } else if (J.kind == JOB_GABOR) {
-    if (sd.gr == 6)   // the default radius: loops unrolled to exactly 13 taps
-      gabor_job<13>(J, sd, ckpt, smem);
-    else
-      gabor_job<2 * SP_MAXR + 1>(J, sd, ckpt, smem);
+    gabor_job<RC>(J, sd, ckpt, smem);
   } else if (BIG && (J.kind == JOB_TAIL || J.kind == JOB_TAILGAB)) {
-    tail_job(J, sd, ckpt, smem);
+    tail_job<RC>(J, sd, ckpt, smem);
   }
 }
 
@@ -2091,8 +2110,18 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
     case JOB_RGB: hipLaunchKernelGGL(k_rgb, g, b, 0, st, jobs, sds, ios, io, flag); break;
     case JOB_FEAT: hipLaunchKernelGGL((k_feat<16, 16>), g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_DOWN:   // pyramid launch without tail jobs (DOWN and GABOR jobs)
-    case JOB_GABOR: hipLaunchKernelGGL(k_pyr<false>, g, b, 0, st, jobs, sds, ios, io); break;
-    case JOB_TAIL: hipLaunchKernelGGL(k_pyr<true>, g, b, 0, st, jobs, sds, ios, io); break;
+    case JOB_GABOR:   // flag: the Gabor radius of the launch
+      if (flag == 6)
+        hipLaunchKernelGGL((k_pyr<false, 6>), g, b, 0, st, jobs, sds, ios, io);
+      else
+        hipLaunchKernelGGL((k_pyr<false, 0>), g, b, 0, st, jobs, sds, ios, io);
+      break;
+    case JOB_TAIL:
+      if (flag == 6)
+        hipLaunchKernelGGL((k_pyr<true, 6>), g, b, 0, st, jobs, sds, ios, io);
+      else
+        hipLaunchKernelGGL((k_pyr<true, 0>), g, b, 0, st, jobs, sds, ios, io);
+      break;
     case JOB_CSSTATS: hipLaunchKernelGGL(k_csstats, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSFINAL: hipLaunchKernelGGL(k_csfinal, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSG:   // flag: channels per workgroup
