@@ -287,18 +287,18 @@ struct Bump {
 
 // Pixels per colour-statistics workgroup: 1024 * G with at most 256 workgroups.
 // Colour-statistics tiles: rows x columns, at most SP_RGB_TR x SP_RGB_TC, with the
-// row count lowered (down to 2) while a frame would give fewer than 192 workgroups.
+// row count lowered (down to 2) while a frame would give fewer than min_tiles workgroups.
 struct RgbTiling {
   int tr, tc, nrt, nct;
   int count() const { return nrt * nct; }
 };
 
-RgbTiling rgb_tiling(const Geo& g) {
+RgbTiling rgb_tiling(const Geo& g, int min_tiles = 192) {
   RgbTiling t;
   t.nct = (g.W + SP_RGB_TC - 1) / SP_RGB_TC;
   t.tc = (g.W + t.nct - 1) / t.nct;
   t.tr = SP_RGB_TR;
-  while (t.tr > 2 && ((g.H + t.tr - 1) / t.tr) * t.nct < 192) t.tr /= 2;
+  while (t.tr > 2 && ((g.H + t.tr - 1) / t.tr) * t.nct < min_tiles) t.tr /= 2;
   t.nrt = (g.H + t.tr - 1) / t.tr;
   return t;
 }
@@ -334,7 +334,8 @@ void fill_taps(StreamDesc& sd, const sp_params& p) {
 // Fills the geometry/parameter part of a stream description and takes its scratch
 // from `bump`.  Levels below `first_level` get no base storage (level c_min of a
 // recompute stream reads its checkpoint instead).
-void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump, int first_level, bool rgb_parts) {
+void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump, int first_level, bool rgb_parts,
+                   int rgb_min_tiles = 192) {
   std::memset(&sd, 0, sizeof sd);
   sd.H = g.H;
   sd.W = g.W;
@@ -373,7 +374,9 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
   for (int l = 1; l <= g.top; ++l)
     if (g.used & (1u << l)) sd.gab[l] = bump.take<float>((size_t)4 * g.Hl[l] * g.Wl[l]);
   if (rgb_parts) {
-    sd.n_rgb = rgb_tiling(g).count();
+    const RgbTiling t = rgb_tiling(g, rgb_min_tiles);
+    sd.n_rgb = t.count();
+    sd.rgb_tr = t.tr;
     sd.rgb_max_part = bump.take<uint32_t>(sd.n_rgb);
     sd.rgb_d2_part = bump.take<unsigned long long>(sd.n_rgb);
   }
@@ -386,7 +389,9 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
 }
 
 void rgb_jobs(std::vector<Job>& v, int s, const StreamDesc& sd, const Geo& g) {
-  const RgbTiling t = rgb_tiling(g);
+  RgbTiling t = rgb_tiling(g);
+  t.tr = sd.rgb_tr;   // the tiling chosen when the partials were laid out
+  t.nrt = (g.H + t.tr - 1) / t.tr;
   if (t.count() != sd.n_rgb) throw std::logic_error("colour tiling and partial buffer disagree");
   for (int i = 0; i < t.nrt; ++i)
     for (int j = 0; j < t.nct; ++j) {
@@ -1403,6 +1408,26 @@ int batch_enqueue(sp_batch* b, hipStream_t st) {
   return SP_OK;
 }
 
+// Captures the whole step once on the private stream (graph kept until the tables change).
+int batch_capture(sp_batch* b) {
+  HIPCHK(hipStreamSynchronize(b->stream));
+  HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  const bool was = b->prof.on;
+  b->prof.on = false;
+  int rc = batch_enqueue(b, b->cap_stream);
+  b->prof.on = was;
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
+  if (rc) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(SP_EHIP, "graph capture: %s", hipGetErrorString(e));
+  b->graph = gr;
+  HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return SP_OK;
+}
+
 void batch_free(sp_batch* b) {
   if (!b) return;
   if (b->stream || b->arena) (void)hipStreamSynchronize(b->stream);
@@ -1524,22 +1549,8 @@ int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* pri
     return SP_OK;
   }
   if (!b->exec) {
-    // capture the whole step once on the private stream
-    HIPCHK(hipStreamSynchronize(b->stream));
-    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    const bool was = b->prof.on;
-    b->prof.on = false;
-    int rc = batch_enqueue(b, b->cap_stream);
-    b->prof.on = was;
-    hipGraph_t gr = nullptr;
-    hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
-    if (rc) {
-      if (gr) (void)hipGraphDestroy(gr);
-      return rc;
-    }
-    if (e != hipSuccess) return fail(SP_EHIP, "graph capture: %s", hipGetErrorString(e));
-    b->graph = gr;
-    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    const int rc = batch_capture(b);
+    if (rc) return rc;
   }
   HIPCHK(hipMemcpyAsync(b->d_in, rgb_ptrs, sizeof(void*) * b->n, hipMemcpyDeviceToDevice, b->stream));
   HIPCHK(hipGraphLaunch(b->exec, b->stream));
@@ -1606,14 +1617,14 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
   b->prof.on = false;
   std::string rep;
   int rc = SP_OK;
-  auto time_it = [&](double* ms) -> int {
+  auto time_it = [&](double* ms) -> int {   // replays of the captured step, as deployed
     int r = batch_build_tables(b);
     if (r) return r;
-    r = batch_enqueue(b, b->stream);   // warm-up
+    r = batch_capture(b);
     if (r) return r;
+    HIPCHK(hipGraphLaunch(b->exec, b->stream));   // warm-up
     HIPCHK(hipEventRecord(e0, b->stream));
-    for (int i = 0; i < steps && !r; ++i) r = batch_enqueue(b, b->stream);
-    if (r) return r;
+    for (int i = 0; i < steps; ++i) HIPCHK(hipGraphLaunch(b->exec, b->stream));
     HIPCHK(hipEventRecord(e1, b->stream));
     HIPCHK(hipEventSynchronize(e1));
     float f = 0.f;

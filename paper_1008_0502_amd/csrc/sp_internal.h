@@ -69,6 +69,7 @@ struct StreamDesc {
   int32_t cs_off[SP_MAXP];       // offset (in partial triples) of pair p: [8][cs_nt[p]]
   int32_t cs_nt[SP_MAXP];        // partial triples per map of pair p
   int32_t gpath;                 // 1: every pair has c_max - c <= 1 (reduced-map path)
+  int32_t rgb_tr;                // rows of a colour-statistics tile
   int32_t n_cmax_tiles;          // tiles of the c_max grid (fbar / consp / smax partials)
   int32_t gr;                    // Gabor radius
   uint32_t used;                 // bit l: level l is a centre or a surround level
