@@ -180,7 +180,8 @@ __host__ __device__ inline CaLayout csapply_layout(const int32_t* pc, const int3
 
 // LDS of the reduced-map job, per channel: the centre region of the level below c_max
 // (x1), its centre-surround map for one pair at a time (fq), the row pass of the
-// reduction (tm), the c_max tile (x0) and one surround footprint per pair.
+// reduction (tm), the c_max tile (x0) and one surround footprint per pair.  x1 and x0
+// hold whole 16-byte quads per row (x0's tiles start at multiples of 16 columns).
 struct CgLayout {
   int x1, fq, tm, x0, foot0, total;
 };
@@ -192,18 +193,20 @@ __host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t*
     has1 |= (c_max - pc[p]) == 1;
   }
   const int n1 = 2 * SP_CA_T + 3;
+  const int pw1 = (n1 + 6) & ~3;   // widest row of whole 16-byte quads covering n1 columns
   CgLayout L;
   int o = 0;
   L.x1 = o;
-  if (has1) o += n1 * n1;
+  if (has1) o += n1 * pw1;
   L.fq = o;
   if (has1) o += n1 * n1;
   L.tm = o;
   if (has1) o += n1 * SP_CA_T;
+  o = (o + 3) & ~3;
   L.x0 = o;
   if (has0) o += SP_CA_T * SP_CA_T;
   L.foot0 = o;
   for (int p = 0; p < n_pairs; ++p) o += csapply_foot_cap(c_max - pc[p], ps[p] - pc[p]);
-  L.total = o;
+  L.total = (o + 3) & ~3;   // keeps every channel's block 16-byte aligned
   return L;
 }

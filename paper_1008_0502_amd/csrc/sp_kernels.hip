@@ -142,6 +142,12 @@ typedef __attribute__((address_space(3))) void lds_void;
 __device__ __forceinline__ void lds_load(float* dst_of_lane, const float* src) {
   __builtin_amdgcn_global_load_lds(src, (lds_void*)(dst_of_lane - lane_id()), 4, 0, 0);
 }
+// The 16-byte form (global_load_lds_dwordx4): lane l writes four floats at the
+// wavefront's base + 16 * l, so a loop over quads q = threadIdx.x + k * SP_BLOCK passes
+// region + 4 * q.  Source and destination must be 16-byte aligned.
+__device__ __forceinline__ void lds_load4(float* dst_of_lane, const float* src) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void*)(dst_of_lane - 4 * lane_id()), 16, 0, 0);
+}
 __device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 // Global-memory views of device pointers.  Pointers read from the stream and step
@@ -300,10 +306,11 @@ __device__ void smax_from_parts(const float* parts, int n, float* m_out, int* id
   *idx_out = min(min(shi4[0], shi4[1]), min(shi4[2], shi4[3]));
 }
 
-// Observation before clamping: bilinear up-sample of S / m at level-0 pixel (y, x).
+// Observation before clamping: bilinear up-sample of S times 1 / m at level-0 pixel
+// (y, x), rounded as the prior update rounds it.
 __device__ __forceinline__ float observe_u(const float* S, int Hc, int Wc, int c, float m, int y, int x) {
   const Tap ty = bilinear_tap(y, c, Hc), tx = bilinear_tap(x, c, Wc);
-  return bilinear(S, Wc, ty, tx) / m;
+  return bilinear(S, Wc, ty, tx) * (1.f / m);
 }
 
 __device__ __forceinline__ bool on_border(int y, int x, int H, int W, int b) {
@@ -313,11 +320,13 @@ __device__ __forceinline__ bool on_border(int y, int x, int H, int W, int b) {
 #define IOF(field) (ios ? ios[J.stream].field : io0.field)
 
 // ---------------------------------------------------------------- colour statistics
+// Colours packed as R | G << 8 | B << 16 are byte vectors with a zero fourth byte, so
+// the byte dot product (v_dot4_u32_u8) gives sums and squared distances exactly in
+// 32-bit integers: R + G + B = a . (1,1,1,0) and |a - b|^2 = a.a + b.b - 2 a.b.
+__device__ __forceinline__ uint32_t rgb_sum(uint32_t a) { return __builtin_amdgcn_udot4(a, 0x010101u, 0u, false); }
 __device__ __forceinline__ uint32_t rgb_d2i(uint32_t a, uint32_t b) {
-  const int dr = (int)(a & 0xff) - (int)(b & 0xff);
-  const int dg = (int)((a >> 8) & 0xff) - (int)((b >> 8) & 0xff);
-  const int db = (int)(a >> 16) - (int)(b >> 16);
-  return (uint32_t)(dr * dr + dg * dg + db * db);
+  return __builtin_amdgcn_udot4(a, a, 0u, false) + __builtin_amdgcn_udot4(b, b, 0u, false) -
+         2u * __builtin_amdgcn_udot4(a, b, 0u, false);
 }
 
 // Largest R+G+B over a tile of th x tw pixels; with want_d2 also the sum of squared
@@ -392,7 +401,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
     const int r = wk2.r, x = x0 + wk2.c, y = y0 + r;
     const int k0 = x - xs + (int)(((long long)y * W + xs) & 3);
     const uint32_t a = Pk[r][k0];
-    mx = max(mx, (a & 0xffu) + ((a >> 8) & 0xffu) + (a >> 16));
+    mx = max(mx, rgb_sum(a));
     if (want_d2) {
       if (x + 1 < W) d2 += rgb_d2i(a, Pk[r][k0 + 1]);
       if (y + 1 < H) {
@@ -436,15 +445,28 @@ __device__ __forceinline__ float beta_from_parts(const StreamDesc& sd, unsigned 
 }
 
 // One contrast-sensitive capacity: Potts constant plus the colour term over the
-// neighbour's distance (1 or sqrt 2).  Shared by every kernel that writes capacities so
-// the fused and the separate MRF calls agree bit for bit.
-__device__ __forceinline__ float pair_cap(float potts, float lam, float beta, float d2, bool diag) {
-  const float w = lam * expf(-beta * d2);
+// neighbour's distance (1 or sqrt 2).  nb2 = -beta * log2(e) (from neg_beta_log2e), so
+// exp(-beta d2) is the hardware base-2 exponential of nb2 * d2.  Shared by every kernel
+// that writes capacities so the fused and the separate MRF calls agree bit for bit.
+__device__ __forceinline__ float neg_beta_log2e(float beta) { return -beta * 1.44269504088896341f; }
+__device__ __forceinline__ float pair_cap(float potts, float lam, float nb2, float d2, bool diag) {
+  const float w = lam * __builtin_amdgcn_exp2f(nb2 * d2);
   return potts + (diag ? w * 0.70710678118654752f : w);
 }
 
+// Unary capacities of a prior value pi (eps <= pi <= 1 - eps after the clamps):
+// U0 = -ln(1 - pi) and U1 = -ln(pi), from the hardware base-2 logarithm.  For U0,
+// u = 1 - pi is rounded; ln(u) * pi / (1 - u) corrects that rounding (Goldberg's
+// log1p method), and U0 = pi exactly when u rounds to 1.
+__device__ __forceinline__ float unary0(float pi) {
+  const float u = 1.f - pi;
+  if (u == 1.f) return pi;
+  return -__builtin_amdgcn_logf(u) * 0.693147180559945309f * (pi * __builtin_amdgcn_rcpf(1.f - u));
+}
+__device__ __forceinline__ float unary1(float pi) { return -__builtin_amdgcn_logf(pi) * 0.693147180559945309f; }
+
 // Contrast-sensitive capacities of pixel (y, x) towards its E, S, SE, SW neighbours.
-__device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, int y, int x, float beta, float lam,
+__device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, int y, int x, float nb2, float lam,
                                             float potts, float* pairw, size_t plane) {
   const size_t o = (size_t)y * W + x;
   const uint8_t* p = rgb + o * 3;
@@ -458,19 +480,14 @@ __device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, in
       const uint8_t* q = rgb + ((size_t)y2 * W + x2) * 3;
       const int dr = r - q[0], dg = g - q[1], db = b - q[2];
       const float d2 = (float)(dr * dr + dg * dg + db * db);
-      wv = pair_cap(potts, lam, beta, d2, dd >= 2);
+      wv = pair_cap(potts, lam, nb2, d2, dd >= 2);
     }
     pairw[dd * plane + o] = wv;
   }
 }
 
-// Squared colour distance of two pixels packed as R | G << 8 | B << 16.
-__device__ __forceinline__ float rgb_d2(uint32_t a, uint32_t b) {
-  const int dr = (int)(a & 0xff) - (int)(b & 0xff);
-  const int dg = (int)((a >> 8) & 0xff) - (int)((b >> 8) & 0xff);
-  const int db = (int)(a >> 16) - (int)(b >> 16);
-  return (float)(dr * dr + dg * dg + db * db);
-}
+// Squared colour distance of two packed pixels as a float.
+__device__ __forceinline__ float rgb_d2(uint32_t a, uint32_t b) { return (float)rgb_d2i(a, b); }
 
 // Level-0 features of the region a level-1 tile needs, then one blur + decimation.
 // With io.pairwise set it also writes the pairwise capacities of the tile's level-0
@@ -530,11 +547,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
 #pragma unroll
   for (int u = 0; u < NP; ++u) {
     const int R8 = (int)(cv[u] & 0xff), G8 = (int)((cv[u] >> 8) & 0xff), B8 = (int)(cv[u] >> 16);
-    const int S8 = R8 + G8 + B8;
-    const float I = (float)S8 / 765.f;
+    const int S8 = (int)rgb_sum(cv[u]);
+    const float I = (float)S8 * (1.f / 765.f);
     float rg = 0.f, by = 0.f;
     if ((uint32_t)(10 * S8) > smax) {
-      const float inv = 3.f / (float)S8;
+      const float inv = 3.f * __builtin_amdgcn_rcpf((float)S8);
       const float rp = (float)R8 * inv, gp = (float)G8 * inv, bp = (float)B8 * inv;
       const float Rc = fmaxf(0.f, rp - (gp + bp) * 0.5f);
       const float Gc = fmaxf(0.f, gp - (rp + bp) * 0.5f);
@@ -546,7 +563,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
     fI[u] = I;
     fRG[u] = rg;
     fBY[u] = by;
-    fM[u] = prev ? fabsf(I - (float)pv[u] / 765.f) : 0.f;
+    fM[u] = prev ? fabsf(I - (float)pv[u] * (1.f / 765.f)) : 0.f;
   }
   float beta = 0.f;
   const int H1 = sd.Hl[1], W1 = sd.Wl[1];
@@ -578,7 +595,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
       const int xlo = 2 * J.x0, xhi = min(W, 2 * (J.x0 + J.tw));
       const int cw = xhi - xlo, n = max(0, yhi - ylo) * cw;
       const size_t plane = (size_t)H * W;
-      const float lam = sd.lam, potts = sd.potts;
+      const float lam = sd.lam, potts = sd.potts, nb2 = neg_beta_log2e(beta);
       Walk2 wk(threadIdx.x, cw);
       for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
         const int y = ylo + wk.r, x = xlo + wk.c;
@@ -586,10 +603,10 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
         const uint32_t c0 = Pk[r];
         const size_t o = (size_t)y * W + x;
         const bool e = x + 1 < W, s = y + 1 < H;
-        pairw[o] = e ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + 1]), false) : 0.f;
-        pairw[plane + o] = s ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW]), false) : 0.f;
-        pairw[2 * plane + o] = (s && e) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW + 1]), true) : 0.f;
-        pairw[3 * plane + o] = (s && x > 0) ? pair_cap(potts, lam, beta, rgb_d2(c0, Pk[r + RW - 1]), true) : 0.f;
+        pairw[o] = e ? pair_cap(potts, lam, nb2, rgb_d2(c0, Pk[r + 1]), false) : 0.f;
+        pairw[plane + o] = s ? pair_cap(potts, lam, nb2, rgb_d2(c0, Pk[r + RW]), false) : 0.f;
+        pairw[2 * plane + o] = (s && e) ? pair_cap(potts, lam, nb2, rgb_d2(c0, Pk[r + RW + 1]), true) : 0.f;
+        pairw[3 * plane + o] = (s && x > 0) ? pair_cap(potts, lam, nb2, rgb_d2(c0, Pk[r + RW - 1]), true) : 0.f;
       }
       if (h == 0 && J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) G(IOF(beta_out))[0] = beta;
     }
@@ -1306,7 +1323,7 @@ template <int NC>
 __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
                                                   const StepIO* __restrict__ ios, StepIO io0) {
-  extern __shared__ float dyn[];
+  extern __shared__ __align__(16) float dyn[];   // 16-byte transfers land in it
   __shared__ float wred[4][NC][3];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
@@ -1330,20 +1347,32 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   const size_t plane = (size_t)Hm * Wm;
   // ---- one round trip: the c_max tile, the region of the level below and every pair's
   // footprint, for each channel of the group
-  auto stage = [&](Range rr, Range cc, int c, int xoff) {
+  // The tile and the region are staged whole rows of 16-byte quads: row stride pw in LDS,
+  // first staged column xa = (first column) & ~3, so column x sits at x - xa.  Rows are
+  // 16-byte aligned in memory when the level width is a multiple of 4 and the plane is
+  // 16-byte aligned; otherwise 4-byte transfers fill the same layout.
+  const int xa0 = cg0.lo & ~3, pw0 = ((cg0.lo + cg0.n + 3) & ~3) - xa0;
+  const int xa1 = cg1.lo & ~3, pw1 = ((cg1.lo + cg1.n + 3) & ~3) - xa1;
+  auto stage = [&](Range rr, int xa, int pw, int c, int xoff) {
     const int Wc = sd.Wl[c];
-    const int n = rr.n * cc.n;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
       const float* Xc = chan_ptr(sd, ckpt, k0 + j, c);
       float* X = dyn + j * CS + xoff;
-      Walk2 wk(threadIdx.x, cc.n);
-      for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next())
-        lds_load(X + i, Xc + (size_t)(rr.lo + wk.r) * Wc + cc.lo + wk.c);
+      if ((Wc & 3) == 0 && (reinterpret_cast<uintptr_t>(Xc) & 15) == 0) {
+        const int nq = pw >> 2;
+        Walk2 wk(threadIdx.x, nq);
+        for (int q = threadIdx.x; q < rr.n * nq; q += SP_BLOCK, wk.next())
+          lds_load4(X + 4 * q, Xc + (size_t)(rr.lo + wk.r) * Wc + xa + 4 * wk.c);
+      } else {
+        Walk2 wk(threadIdx.x, pw);
+        for (int i = threadIdx.x; i < rr.n * pw; i += SP_BLOCK, wk.next())
+          lds_load(X + i, Xc + (size_t)(rr.lo + wk.r) * Wc + min(xa + wk.c, Wc - 1));
+      }
     }
   };
-  if (has0) stage(rg0, cg0, cm, L.x0);
-  if (has1) stage(rg1, cg1, cm - 1, L.x1);
+  if (has0) stage(rg0, xa0, pw0, cm, L.x0);
+  if (has1) stage(rg1, xa1, pw1, cm - 1, L.x1);
   {
     int off = L.foot0;
     for (int p = 0; p < sd.n_pairs; ++p) {
@@ -1397,7 +1426,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
               const float up = bilinear_lds(B + off, f.w, ty[u], tx[v], f.y0, f.x0);
-              const float F = fabsf(B[L.x0 + yl[u] * J.tw + xl[v]] - up);
+              const float F = fabsf(B[L.x0 + yl[u] * pw0 + cg0.lo - xa0 + xl[v]] - up);
               mn = fminf(mn, F);
               mx = fmaxf(mx, F);
               if (qy + u < J.th && qx + v < J.tw)
@@ -1463,7 +1492,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
             float* B = dyn + j * CS;
             const float top = fmaf(tx.w, B[o0 + tx.i1], (1.f - tx.w) * B[o0 + tx.i0]);
             const float bot = fmaf(tx.w, B[o1 + tx.i1], (1.f - tx.w) * B[o1 + tx.i0]);
-            B[L.fq + i] = fabsf(B[L.x1 + i] - fmaf(ty.w, bot, (1.f - ty.w) * top));
+            B[L.fq + i] = fabsf(B[L.x1 + wk.r * pw1 + cg1.lo - xa1 + wk.c] - fmaf(ty.w, bot, (1.f - ty.w) * top));
           }
         }
         __syncthreads();
@@ -1752,23 +1781,28 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
     __syncthreads();
   }
   // consecutive lanes take consecutive pixels of a row, so every store of a wavefront
-  // covers a contiguous run
-  const float eps = sd.eps;
-  Walk2 wk2(threadIdx.x, tw);
-  for (int i = threadIdx.x; i < J.th * tw; i += SP_BLOCK, wk2.next()) {
-    const int yy = wk2.r, xx = wk2.c;
-    const int y = J.y0 + yy, x = J.x0 + xx;
-    if (y >= H || x >= W) continue;
-    const bool ring = y < sd.border || y >= H - sd.border || x < sd.border || x >= W - sd.border;
+  // covers a contiguous run.  Threads map to columns modulo cw, the power of two >= tw
+  // (it divides the block), so each thread keeps one column (its horizontal tap and
+  // border test) and steps down the rows.
+  const float eps = sd.eps, rm = flat ? 0.f : 1.f / m;
+  const int cw = tw <= 1 ? 1 : 1 << (32 - __clz(tw - 1));
+  const int xx = threadIdx.x & (cw - 1), x = J.x0 + xx;
+  const bool xring = x < sd.border || x >= W - sd.border;
+  const Tap tx = bilinear_tap(x, cm, Wm);
+  const gp<float> unary1p = unary + (size_t)H * W;
+  for (int yy = threadIdx.x / cw; yy < J.th; yy += SP_BLOCK / cw) {
+    const int y = J.y0 + yy;
+    if (y >= H || xx >= tw || x >= W) continue;
+    const bool ring = xring || y < sd.border || y >= H - sd.border;
     float q = 0.5f;
     if (!flat) {
-      const Tap ty = bilinear_tap(y, cm, Hm), tx = bilinear_tap(x, cm, Wm);
-      const float u = bilinear_lds(Sl, sf.w, ty, tx, sf.y0, sf.x0) / m;
+      const Tap ty = bilinear_tap(y, cm, Hm);
+      const float u = bilinear_lds(Sl, sf.w, ty, tx, sf.y0, sf.x0) * rm;
       q = fminf(fmaxf(u, eps), 1.f - eps);
     }
     if (ring) q = eps;
     float pi = q;
-    const size_t o = (size_t)y * W + x;
+    const uint32_t o = (uint32_t)y * (uint32_t)W + (uint32_t)x;
     if (t > 0) {
       const float f = kB0 * hb[yy][xx] + kB1 * hb[yy + 1][xx] + kB2 * hb[yy + 2][xx] + kB1 * hb[yy + 3][xx] +
                       kB0 * hb[yy + 4][xx];
@@ -1779,8 +1813,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
     pnext[o] = pi;
     if (pout) pout[o] = pi;
     if (unary) {
-      unary[o] = -log1pf(-fminf(pi, 1.f - eps));
-      unary[(size_t)H * W + o] = -logf(fmaxf(pi, eps));
+      unary[o] = unary0(fminf(pi, 1.f - eps));
+      unary1p[o] = unary1(fmaxf(pi, eps));
     }
   }
   if (mstape && J.tid == 0 && threadIdx.x == 0) {
@@ -1808,9 +1842,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_mrf(const Job* __restrict__ jobs,
   if (yy < J.th && xx < J.tw && y < H && x < W) {
     const size_t o = (size_t)y * W + x, plane = (size_t)H * W;
     const float pi = prior[o];
-    unary[o] = -log1pf(-fminf(pi, 1.f - sd.eps));
-    unary[plane + o] = -logf(fmaxf(pi, sd.eps));
-    pairwise_at(rgb, H, W, y, x, beta, sd.lam, sd.potts, pairw, plane);
+    unary[o] = unary0(fminf(pi, 1.f - sd.eps));
+    unary[plane + o] = unary1(fmaxf(pi, sd.eps));
+    pairwise_at(rgb, H, W, y, x, neg_beta_log2e(beta), sd.lam, sd.potts, pairw, plane);
   }
   if (beta_out && J.tid == 0 && threadIdx.x == 0) beta_out[0] = beta;
 }
