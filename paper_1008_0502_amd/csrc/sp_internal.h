@@ -178,12 +178,17 @@ __host__ __device__ inline CaLayout csapply_layout(const int32_t* pc, const int3
   return L;
 }
 
-// LDS of the reduced-map job, per channel: the centre region of the level below c_max
-// (x1), its centre-surround map for one pair at a time (fq), the row pass of the
-// reduction (tm), the c_max tile (x0) and one surround footprint per pair.  x1 and x0
-// hold whole 16-byte quads per row (x0's tiles start at multiples of 16 columns).
+// LDS of the reduced-map job.  One staging block of `chan` floats per channel
+// (16-byte aligned): the centre region of the level below c_max (x1) and the c_max tile
+// (x0), both in whole 16-byte quads per row (x0's tiles start at multiples of 16
+// columns), then one surround footprint per pair.  After the NC blocks, shared by the
+// channels and interleaved (element e of channel j at e * NC + j): one pair's
+// centre-surround map on the region (fqn floats per channel) and a table (ttn floats
+// per channel) holding first that pair's footprint rows interpolated at the region's
+// columns, then the row pass of the reduction.  total = chan + fqn + ttn floats per
+// channel of the group.
 struct CgLayout {
-  int x1, fq, tm, x0, foot0, total;
+  int x1, x0, foot0, chan, fqn, ttn, total;
 };
 
 __host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t* ps, int n_pairs, int c_max) {
@@ -198,15 +203,18 @@ __host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t*
   int o = 0;
   L.x1 = o;
   if (has1) o += n1 * pw1;
-  L.fq = o;
-  if (has1) o += n1 * n1;
-  L.tm = o;
-  if (has1) o += n1 * SP_CA_T;
-  o = (o + 3) & ~3;
   L.x0 = o;
   if (has0) o += SP_CA_T * SP_CA_T;
   L.foot0 = o;
-  for (int p = 0; p < n_pairs; ++p) o += csapply_foot_cap(c_max - pc[p], ps[p] - pc[p]);
-  L.total = (o + 3) & ~3;   // keeps every channel's block 16-byte aligned
+  int tt = has1 ? n1 * SP_CA_T : 0;
+  for (int p = 0; p < n_pairs; ++p) {
+    const int r = c_max - pc[p], d = ps[p] - pc[p];
+    o += csapply_foot_cap(r, d);
+    if (r == 1) tt = tt > (((n1 - 1) >> d) + 3) * n1 ? tt : (((n1 - 1) >> d) + 3) * n1;
+  }
+  L.chan = (o + 3) & ~3;
+  L.fqn = has1 ? (n1 * n1 + 3) & ~3 : 0;
+  L.ttn = (tt + 3) & ~3;
+  L.total = L.chan + L.fqn + L.ttn;
   return L;
 }

@@ -1317,21 +1317,59 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
 // reduction to c_max (REDUCE once for c = c_max - 1, the map itself for c = c_max) is
 // stored.  k_csmix then forms F-bar at c_max as the sum of N(reduced map) over pairs.
 //
-// One workgroup per c_max tile and group of NC channels (from job a).  Each channel
-// owns a block of CgLayout.total floats of dynamic LDS.
+// One workgroup per c_max tile and group of NC channels (from job a).  Its dynamic LDS
+// holds one staging block per channel and, after them, the channel-interleaved map and
+// table of CgLayout: the compute loops read every channel of an element with one
+// vector access.
+
+// NC consecutive floats of LDS (one element of an interleaved buffer) in one access.
+template <int NC>
+__device__ __forceinline__ void lds_getv(const float* p, float (&v)[NC]) {
+  if constexpr (NC == 1) {
+    v[0] = p[0];
+  } else if constexpr (NC == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < NC; k += 4) {
+      const float4 t = *reinterpret_cast<const float4*>(p + k);
+      v[k] = t.x;
+      v[k + 1] = t.y;
+      v[k + 2] = t.z;
+      v[k + 3] = t.w;
+    }
+  }
+}
+template <int NC>
+__device__ __forceinline__ void lds_putv(float* p, const float (&v)[NC]) {
+  if constexpr (NC == 1) {
+    p[0] = v[0];
+  } else if constexpr (NC == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NC; k += 4) *reinterpret_cast<float4*>(p + k) = make_float4(v[k], v[k + 1], v[k + 2], v[k + 3]);
+  }
+}
+
 template <int NC>
 __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
                                                   const StepIO* __restrict__ ios, StepIO io0) {
-  extern __shared__ __align__(16) float dyn[];   // 16-byte transfers land in it
+  extern __shared__ __align__(16) float dyn[];   // 16-byte transfers and vector reads land in it
   __shared__ float wred[4][NC][3];
+  __shared__ float4 rtap[2 * SP_CA_T + 3];       // per region row: two table offsets and a weight
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const float* ckpt = IOF(ckpt);
   const int k0 = J.a, cm = sd.c_max;
   const int Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const CgLayout L = csg_layout(sd.pc, sd.ps, sd.n_pairs, cm);
-  const int CS = L.total;
+  const int CH = L.chan;
+  float* const FQ = dyn + NC * CH;          // [region pixel][NC]
+  float* const TT = FQ + NC * L.fqn;        // [footprint row][region column][NC], then [region row][tile column][NC]
   bool has0 = false, has1 = false;
   for (int p = 0; p < sd.n_pairs; ++p) {
     has0 |= (cm - sd.pc[p]) == 0;
@@ -1346,11 +1384,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   const gp<float> gmap = G(sd.gmap);
   const size_t plane = (size_t)Hm * Wm;
   // ---- one round trip: the c_max tile, the region of the level below and every pair's
-  // footprint, for each channel of the group
-  // The tile and the region are staged whole rows of 16-byte quads: row stride pw in LDS,
-  // first staged column xa = (first column) & ~3, so column x sits at x - xa.  Rows are
-  // 16-byte aligned in memory when the level width is a multiple of 4 and the plane is
-  // 16-byte aligned; otherwise 4-byte transfers fill the same layout.
+  // footprint, for each channel of the group.  The tile and the region are staged in
+  // whole rows of 16-byte quads: row stride pw in LDS, first staged column
+  // xa = (first column) & ~3, so column x sits at x - xa.  Rows are 16-byte aligned in
+  // memory when the level width is a multiple of 4 and the plane is 16-byte aligned;
+  // otherwise 4-byte transfers fill the same layout.
   const int xa0 = cg0.lo & ~3, pw0 = ((cg0.lo + cg0.n + 3) & ~3) - xa0;
   const int xa1 = cg1.lo & ~3, pw1 = ((cg1.lo + cg1.n + 3) & ~3) - xa1;
   auto stage = [&](Range rr, int xa, int pw, int c, int xoff) {
@@ -1358,7 +1396,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
       const float* Xc = chan_ptr(sd, ckpt, k0 + j, c);
-      float* X = dyn + j * CS + xoff;
+      float* X = dyn + j * CH + xoff;
       if ((Wc & 3) == 0 && (reinterpret_cast<uintptr_t>(Xc) & 15) == 0) {
         const int nq = pw >> 2;
         Walk2 wk(threadIdx.x, nq);
@@ -1382,7 +1420,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const float* Xs = chan_ptr(sd, ckpt, k0 + j, s);
-        float* dst = dyn + j * CS + off;
+        float* dst = dyn + j * CH + off;
         Walk2 wk(threadIdx.x, f.w);
         for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK, wk.next())
           lds_load(dst + i, Xs + (size_t)(f.y0 + wk.r) * Ws + f.x0 + wk.c);
@@ -1419,7 +1457,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
 #pragma unroll
         for (int j = 0; j < NC; ++j, ++m) {
           if ((m & 3) != w) continue;   // wave-uniform
-          const float* B = dyn + j * CS;
+          const float* B = dyn + j * CH;
           float mn = INFINITY, mx = -INFINITY;
 #pragma unroll
           for (int u = 0; u < 2; ++u)
@@ -1458,11 +1496,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
       off += csapply_foot_cap(r, d);
     }
   }
-  // ---- pairs with c = c_max - 1, one at a time: the map on the whole region, its
-  // statistics on the 2*th x 2*tw pixels the tile owns (wavefront w: block row w, a 2x2
-  // quad per lane), then REDUCE to the tile
+  // ---- pairs with c = c_max - 1, one at a time: the footprint's rows interpolated at the
+  // region's columns (the separable first half of the bilinear up-sample), the map on
+  // the whole region, its statistics on the 2*th x 2*tw pixels the tile owns (wavefront
+  // w: block row w, a 2x2 quad per lane), then REDUCE to the tile
   if (has1) {
     const int c1 = cm - 1, H1 = sd.Hl[c1], W1 = sd.Wl[c1];
+    const int n1r = rg1.n, n1c = cg1.n, n = n1r * n1c;
     const int oh = min(2 * J.th, H1 - 2 * J.y0), ow = min(2 * J.tw, W1 - 2 * J.x0);
     const int oy0 = 2 * J.y0 - rg1.lo, ox0 = 2 * J.x0 - cg1.lo;   // region offset of the owned pixels
     const int bx = lane >> 4, qy = 8 * w + 2 * sy, qx = 8 * bx + 2 * sx;
@@ -1476,95 +1516,119 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
     bool bval[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) bval[i] = rowval && 8 * i < ow;
-    const int n = rg1.n * cg1.n;
+    // reduction taps: a row-pass thread keeps one tile column (the tile width divides the
+    // block), a column-pass thread one output
+    const int rc = threadIdx.x % SP_CA_T, rr0 = threadIdx.x / SP_CA_T;
+    int ix[5], iy[5];
+#pragma unroll
+    for (int t = -2; t <= 2; ++t) {
+      ix[t + 2] = clampi(2 * (cg0.lo + rc) + t, 0, W1 - 1) - cg1.lo;
+      iy[t + 2] = clampi(2 * (rg0.lo + rr0) + t, 0, H1 - 1) - rg1.lo;
+    }
+    const int xoff1 = L.x1 + cg1.lo - xa1;   // region column c of row r at xoff1 + r * pw1 + c
     int off = L.foot0;
     for (int p = 0; p < sd.n_pairs; ++p) {
       const int c = sd.pc[p], r = cm - c, s = sd.ps[p], d = s - c;
       if (r == 1) {
-        const Foot f = footprint(rg1.lo, rg1.n, cg1.lo, cg1.n, d, sd.Hl[s], sd.Wl[s]);
-        // the map on the region
-        Walk2 wk(threadIdx.x, cg1.n);
-        for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
-          const Tap ty = bilinear_tap(rg1.lo + wk.r, d, sd.Hl[s]), tx = bilinear_tap(cg1.lo + wk.c, d, sd.Wl[s]);
-          const int o0 = off + (ty.i0 - f.y0) * f.w - f.x0, o1 = off + (ty.i1 - f.y0) * f.w - f.x0;
+        const int Hs = sd.Hl[s], Ws = sd.Wl[s];
+        const Foot f = footprint(rg1.lo, n1r, cg1.lo, n1c, d, Hs, Ws);
+        {
+          Walk2 wk(threadIdx.x, n1c);
+          for (int i = threadIdx.x; i < f.h * n1c; i += SP_BLOCK, wk.next()) {
+            const Tap tx = bilinear_tap(cg1.lo + wk.c, d, Ws);
+            const int a0 = off + wk.r * f.w + tx.i0 - f.x0, a1 = off + wk.r * f.w + tx.i1 - f.x0;
+            float v[NC];
 #pragma unroll
-          for (int j = 0; j < NC; ++j) {
-            float* B = dyn + j * CS;
-            const float top = fmaf(tx.w, B[o0 + tx.i1], (1.f - tx.w) * B[o0 + tx.i0]);
-            const float bot = fmaf(tx.w, B[o1 + tx.i1], (1.f - tx.w) * B[o1 + tx.i0]);
-            B[L.fq + i] = fabsf(B[L.x1 + wk.r * pw1 + cg1.lo - xa1 + wk.c] - fmaf(ty.w, bot, (1.f - ty.w) * top));
+            for (int j = 0; j < NC; ++j) v[j] = fmaf(tx.w, dyn[j * CH + a1], (1.f - tx.w) * dyn[j * CH + a0]);
+            lds_putv<NC>(TT + i * NC, v);
+          }
+          if ((int)threadIdx.x < n1r) {
+            const Tap ty = bilinear_tap(rg1.lo + threadIdx.x, d, Hs);
+            rtap[threadIdx.x] = make_float4(__int_as_float((ty.i0 - f.y0) * n1c * NC),
+                                            __int_as_float((ty.i1 - f.y0) * n1c * NC), ty.w, 1.f - ty.w);
+          }
+        }
+        __syncthreads();
+        // the map on the region
+        {
+          Walk2 wk(threadIdx.x, n1c);
+          for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
+            const float4 rt = rtap[wk.r];
+            float t0[NC], t1[NC], F[NC];
+            lds_getv<NC>(TT + __float_as_int(rt.x) + wk.c * NC, t0);
+            lds_getv<NC>(TT + __float_as_int(rt.y) + wk.c * NC, t1);
+            const int xo = xoff1 + wk.r * pw1 + wk.c;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) F[j] = fabsf(dyn[j * CH + xo] - fmaf(rt.z, t1[j], rt.w * t0[j]));
+            lds_putv<NC>(FQ + i * NC, F);
           }
         }
         __syncthreads();
         // statistics of the owned pixels
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          const float* FQ = dyn + j * CS + L.fq;
-          float mn = INFINITY, mx = -INFINITY;
+        {
+          float q[4][NC];
 #pragma unroll
           for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int v = 0; v < 2; ++v) {
-              const float F = FQ[ro[u] * cg1.n + co[v]];
-              mn = fminf(mn, F);
-              mx = fmaxf(mx, F);
-            }
-          mn = fminf(mn, dpp_f<0xB1>(mn));
-          mx = fmaxf(mx, dpp_f<0xB1>(mx));
-          mn = fminf(mn, dpp_f<0x4E>(mn));
-          mx = fmaxf(mx, dpp_f<0x4E>(mx));
-          mn = fminf(mn, dpp_f<0x141>(mn));
-          mx = fmaxf(mx, dpp_f<0x141>(mx));
-          mn = fminf(mn, dpp_f<0x140>(mn));
-          mx = fmaxf(mx, dpp_f<0x140>(mx));
-          float bmn[4], bmx[4];
+            for (int v = 0; v < 2; ++v) lds_getv<NC>(FQ + (ro[u] * n1c + co[v]) * NC, q[2 * u + v]);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            bmn[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i)) : INFINITY;
-            bmx[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i)) : -INFINITY;
-          }
-          if (lane == 0) {
-            wred[w][j][0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
-            wred[w][j][1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
-            wred[w][j][2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) +
-                            ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
+          for (int j = 0; j < NC; ++j) {
+            float mn = fminf(fminf(q[0][j], q[1][j]), fminf(q[2][j], q[3][j]));
+            float mx = fmaxf(fmaxf(q[0][j], q[1][j]), fmaxf(q[2][j], q[3][j]));
+            mn = fminf(mn, dpp_f<0xB1>(mn));
+            mx = fmaxf(mx, dpp_f<0xB1>(mx));
+            mn = fminf(mn, dpp_f<0x4E>(mn));
+            mx = fmaxf(mx, dpp_f<0x4E>(mx));
+            mn = fminf(mn, dpp_f<0x141>(mn));
+            mx = fmaxf(mx, dpp_f<0x141>(mx));
+            mn = fminf(mn, dpp_f<0x140>(mn));
+            mx = fmaxf(mx, dpp_f<0x140>(mx));
+            float bmn[4], bmx[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              bmn[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i)) : INFINITY;
+              bmx[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i)) : -INFINITY;
+            }
+            if (lane == 0) {
+              wred[w][j][0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
+              wred[w][j][1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
+              wred[w][j][2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) +
+                              ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
+            }
           }
         }
-        // REDUCE to the tile: row pass (region rows x tile columns), then column pass
-        {
-          Walk2 wr(threadIdx.x, cg0.n);
-          for (int i = threadIdx.x; i < rg1.n * cg0.n; i += SP_BLOCK, wr.next()) {
-            const int X = cg0.lo + wr.c;
-            int ix[5];
+        // REDUCE to the tile: row pass (region rows x tile columns) into the table, then
+        // column pass
+        if (rc < cg0.n) {
+          for (int rr = rr0; rr < n1r; rr += SP_BLOCK / SP_CA_T) {
+            float acc[NC];
 #pragma unroll
-            for (int t = -2; t <= 2; ++t) ix[t + 2] = wr.r * cg1.n + clampi(2 * X + t, 0, W1 - 1) - cg1.lo;
+            for (int j = 0; j < NC; ++j) acc[j] = 0.f;
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-              const float* FQ = dyn + j * CS + L.fq;
-              float acc = 0.f;
+            for (int t = 0; t < 5; ++t) {
+              float v[NC];
+              lds_getv<NC>(FQ + (rr * n1c + ix[t]) * NC, v);
 #pragma unroll
-              for (int t = -2; t <= 2; ++t) acc = fmaf(binom(t), FQ[ix[t + 2]], acc);
-              dyn[j * CS + L.tm + wr.r * cg0.n + wr.c] = acc;
+              for (int j = 0; j < NC; ++j) acc[j] = fmaf(binom(t - 2), v[j], acc[j]);
             }
+            lds_putv<NC>(TT + (rr * SP_CA_T + rc) * NC, acc);
           }
         }
         __syncthreads();
-        {
-          Walk2 wc(threadIdx.x, cg0.n);
-          for (int i = threadIdx.x; i < rg0.n * cg0.n; i += SP_BLOCK, wc.next()) {
-            const int Y = rg0.lo + wc.r;
-            int iy[5];
+        if (rr0 < rg0.n && rc < cg0.n) {
+          float acc[NC];
 #pragma unroll
-            for (int t = -2; t <= 2; ++t) iy[t + 2] = (clampi(2 * Y + t, 0, H1 - 1) - rg1.lo) * cg0.n + wc.c;
+          for (int j = 0; j < NC; ++j) acc[j] = 0.f;
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-              const float* TM = dyn + j * CS + L.tm;
-              float acc = 0.f;
+          for (int t = 0; t < 5; ++t) {
+            float v[NC];
+            lds_getv<NC>(TT + (iy[t] * SP_CA_T + rc) * NC, v);
 #pragma unroll
-              for (int t = -2; t <= 2; ++t) acc = fmaf(binom(t), TM[iy[t + 2]], acc);
-              gmap[((size_t)p * SP_NCH + k0 + j) * plane + (size_t)Y * Wm + cg0.lo + wc.c] = acc;
-            }
+            for (int j = 0; j < NC; ++j) acc[j] = fmaf(binom(t - 2), v[j], acc[j]);
           }
+          const size_t o = (size_t)(rg0.lo + rr0) * Wm + cg0.lo + rc;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) gmap[((size_t)p * SP_NCH + k0 + j) * plane + o] = acc[j];
         }
         if ((int)threadIdx.x < NC) {
           const int j = threadIdx.x;
@@ -1573,7 +1637,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
           out[1] = fmaxf(fmaxf(wred[0][j][1], wred[1][j][1]), fmaxf(wred[2][j][1], wred[3][j][1]));
           out[2] = (wred[0][j][2] + wred[1][j][2]) + (wred[2][j][2] + wred[3][j][2]);
         }
-        __syncthreads();   // fq, tm and wred are reused by the next pair
+        __syncthreads();   // the map, the table, the row taps and wred are reused by the next pair
       }
       off += csapply_foot_cap(r, d);
     }
