@@ -190,10 +190,14 @@ __device__ __forceinline__ const float* base_ptr(const StreamDesc& sd, const flo
 
 // Channel k (I, RG, BY, O0, O45, O90, O135, M) of level l.
 __device__ __forceinline__ const float* chan_ptr(const StreamDesc& sd, const float* ckpt, int k, int l) {
+  // selects rather than branches: every operand is a uniform scalar load
   const size_t plane = (size_t)sd.Hl[l] * sd.Wl[l];
-  if (k < 3) return base_ptr(sd, ckpt, l) + k * plane;
-  if (k == 7) return base_ptr(sd, ckpt, l) + 3 * plane;
-  return sd.gab[l] + (k - 3) * plane;
+  const float* b = sd.base[l];
+  const float* g = sd.gab[l];
+  b = (l == sd.c_min && ckpt) ? ckpt : b;
+  const bool gabor = (unsigned)(k - 3) < 4u;
+  const int idx = k < 3 ? k : (k == 7 ? 3 : k - 3);
+  return (gabor ? g : b) + idx * plane;
 }
 
 // Sample-aligned bilinear tap set for target index y of a map whose source level is
@@ -1029,8 +1033,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
       float bmn[4], bmx[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        bmn[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i)) : INFINITY;
-        bmx[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i)) : -INFINITY;
+        // read unconditionally, then select: a readlane under the condition becomes a branch
+        const float rmn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i));
+        const float rmx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i));
+        bmn[i] = bval[i] ? rmn : INFINITY;
+        bmx[i] = bval[i] ? rmx : -INFINITY;
       }
       if (lane == 0) {
         const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)k * sd.ntiles_lvl[c] + J.tid);
@@ -1481,8 +1488,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
           float bmn[4], bmx[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            bmn[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i)) : INFINITY;
-            bmx[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i)) : -INFINITY;
+            // read unconditionally, then select: a readlane under the condition becomes a branch
+            const float rmn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i));
+            const float rmx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i));
+            bmn[i] = bval[i] ? rmn : INFINITY;
+            bmx[i] = bval[i] ? rmx : -INFINITY;
           }
           if (lane == 0) {
             const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)(k0 + j) * sd.cs_nt[p] + J.tid);
@@ -1586,8 +1596,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
             float bmn[4], bmx[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              bmn[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i)) : INFINITY;
-              bmx[i] = bval[i] ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i)) : -INFINITY;
+              // read unconditionally, then select: a readlane under the condition becomes a branch
+              const float rmn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i));
+              const float rmx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i));
+              bmn[i] = bval[i] ? rmn : INFINITY;
+              bmx[i] = bval[i] ? rmx : -INFINITY;
             }
             if (lane == 0) {
               wred[w][j][0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
