@@ -162,6 +162,15 @@ __device__ __forceinline__ gp<T> G(T* p) {
   return (gp<T>)p;
 }
 
+// base + a 32-bit byte offset, which the compiler addresses as a scalar base plus one
+// vector register (no 64-bit vector add per access).  Frames hold at most 2^28 pixels,
+// so byte offsets into a plane stay below 2^30.
+template <class T>
+__device__ __forceinline__ gp<T> at_bytes(gp<T> base, uint32_t byte_off) {
+  typedef __attribute__((address_space(1))) char gchar;
+  return (gp<T>)((gchar*)base + byte_off);
+}
+
 // Row and column of the flat index i = threadIdx.x + k * SP_BLOCK over rows of length
 // w, advanced by SP_BLOCK per step: the quotient and remainder of the start and of the
 // stride are taken once, so a staging loop does no integer division per element.
@@ -427,13 +436,18 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
 }
 
 // ---------------------------------------------------------------- pyramid
-// Separable blur + decimation of a (2*TH+3) x (2*TW+3) LDS region into TH x TW.
-template <int TH, int TW, int RH, int RW>
-__device__ __forceinline__ void down_region(float (*F)[RH][RW], float (*Hb)[RH][TW], int nch) {
-  for (int i = threadIdx.x; i < nch * RH * TW; i += SP_BLOCK) {
-    const int c = i / (RH * TW), rem = i - c * RH * TW, r = rem / TW, j = rem - r * TW;
-    const float* row = &F[c][r][2 * j];
-    Hb[c][r][j] = kB0 * row[0] + kB1 * row[1] + kB2 * row[2] + kB1 * row[3] + kB0 * row[4];
+// Row pass of the blur + decimation of NCH channels of a RH x (2*TW+3) LDS region:
+// Hb[c][r][j] = 5-tap binomial of F[c][r][2j-2+2 .. 2j+2+2].  A thread keeps one (r, j)
+// and runs over the channels, whose offsets are compile-time constants.
+template <int TW, int RH, int RW, int NCH>
+__device__ __forceinline__ void down_rows(float (*F)[RH][RW], float (*Hb)[RH][TW]) {
+  for (int i = threadIdx.x; i < RH * TW; i += SP_BLOCK) {
+    const int r = i / TW, j = i - r * TW;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const float* row = &F[c][r][2 * j];
+      Hb[c][r][j] = kB0 * row[0] + kB1 * row[1] + kB2 * row[2] + kB1 * row[3] + kB0 * row[4];
+    }
   }
 }
 
@@ -449,13 +463,19 @@ __device__ __forceinline__ float beta_from_parts(const StreamDesc& sd, unsigned 
 }
 
 // One contrast-sensitive capacity: Potts constant plus the colour term over the
-// neighbour's distance (1 or sqrt 2).  nb2 = -beta * log2(e) (from neg_beta_log2e), so
-// exp(-beta d2) is the hardware base-2 exponential of nb2 * d2.  Shared by every kernel
-// that writes capacities so the fused and the separate MRF calls agree bit for bit.
-__device__ __forceinline__ float neg_beta_log2e(float beta) { return -beta * 1.44269504088896341f; }
-__device__ __forceinline__ float pair_cap(float potts, float lam, float nb2, float d2, bool diag) {
-  const float w = lam * __builtin_amdgcn_exp2f(nb2 * d2);
-  return potts + (diag ? w * 0.70710678118654752f : w);
+// neighbour's distance (1 or sqrt 2).  lambda * exp(-beta d2) is the hardware base-2
+// exponential of nb2 * d2 + log2(lambda), nb2 = -beta * log2(e) (lambda = 0 gives
+// log2 = -inf and a zero term).  Shared by every kernel that writes capacities so the
+// fused and the separate MRF calls agree bit for bit.
+struct CapK {
+  float nb2, l2lam, potts;
+};
+__device__ __forceinline__ CapK cap_consts(float beta, float lam, float potts) {
+  return CapK{-beta * 1.44269504088896341f, __builtin_amdgcn_logf(lam), potts};
+}
+__device__ __forceinline__ float pair_cap(const CapK& k, float d2, bool diag) {
+  const float w = __builtin_amdgcn_exp2f(fmaf(k.nb2, d2, k.l2lam));
+  return diag ? fmaf(w, 0.70710678118654752f, k.potts) : k.potts + w;
 }
 
 // Unary capacities of a prior value pi (eps <= pi <= 1 - eps after the clamps):
@@ -470,8 +490,8 @@ __device__ __forceinline__ float unary0(float pi) {
 __device__ __forceinline__ float unary1(float pi) { return -__builtin_amdgcn_logf(pi) * 0.693147180559945309f; }
 
 // Contrast-sensitive capacities of pixel (y, x) towards its E, S, SE, SW neighbours.
-__device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, int y, int x, float nb2, float lam,
-                                            float potts, float* pairw, size_t plane) {
+__device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, int y, int x, const CapK& ck,
+                                            float* pairw, size_t plane) {
   const size_t o = (size_t)y * W + x;
   const uint8_t* p = rgb + o * 3;
   const int r = p[0], g = p[1], b = p[2];
@@ -484,7 +504,7 @@ __device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, in
       const uint8_t* q = rgb + ((size_t)y2 * W + x2) * 3;
       const int dr = r - q[0], dg = g - q[1], db = b - q[2];
       const float d2 = (float)(dr * dr + dg * dg + db * db);
-      wv = pair_cap(potts, lam, nb2, d2, dd >= 2);
+      wv = pair_cap(ck, d2, dd >= 2);
     }
     pairw[dd * plane + o] = wv;
   }
@@ -599,23 +619,30 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
       const int xlo = 2 * J.x0, xhi = min(W, 2 * (J.x0 + J.tw));
       const int cw = xhi - xlo, n = max(0, yhi - ylo) * cw;
       const size_t plane = (size_t)H * W;
-      const float lam = sd.lam, potts = sd.potts, nb2 = neg_beta_log2e(beta);
+      const gp<float> pw0 = pairw, pw1 = pairw + plane, pw2 = pairw + 2 * plane, pw3 = pairw + 3 * plane;
+      const CapK ck = cap_consts(beta, sd.lam, sd.potts);
       Walk2 wk(threadIdx.x, cw);
       for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
         const int y = ylo + wk.r, x = xlo + wk.c;
         const int r = (y - Y0 - r0) * RW + (x - X0);
         const uint32_t c0 = Pk[r];
-        const size_t o = (size_t)y * W + x;
+        const uint32_t ob = ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 4u;
         const bool e = x + 1 < W, s = y + 1 < H;
-        pairw[o] = e ? pair_cap(potts, lam, nb2, rgb_d2(c0, Pk[r + 1]), false) : 0.f;
-        pairw[plane + o] = s ? pair_cap(potts, lam, nb2, rgb_d2(c0, Pk[r + RW]), false) : 0.f;
-        pairw[2 * plane + o] = (s && e) ? pair_cap(potts, lam, nb2, rgb_d2(c0, Pk[r + RW + 1]), true) : 0.f;
-        pairw[3 * plane + o] = (s && x > 0) ? pair_cap(potts, lam, nb2, rgb_d2(c0, Pk[r + RW - 1]), true) : 0.f;
+        // the staged region holds every neighbour (clamped at the frame edge), so all
+        // four capacities are computed and the ones that leave the frame are zeroed
+        const float cE = pair_cap(ck, rgb_d2(c0, Pk[r + 1]), false);
+        const float cS = pair_cap(ck, rgb_d2(c0, Pk[r + RW]), false);
+        const float cSE = pair_cap(ck, rgb_d2(c0, Pk[r + RW + 1]), true);
+        const float cSW = pair_cap(ck, rgb_d2(c0, Pk[r + RW - 1]), true);
+        *at_bytes(pw0, ob) = e ? cE : 0.f;
+        *at_bytes(pw1, ob) = s ? cS : 0.f;
+        *at_bytes(pw2, ob) = (s && e) ? cSE : 0.f;
+        *at_bytes(pw3, ob) = (s && x > 0) ? cSW : 0.f;
       }
       if (h == 0 && J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) G(IOF(beta_out))[0] = beta;
     }
     __syncthreads();
-    down_region<TH / 2, TW, HR, RW>(F, Hb, 4);
+    down_rows<TW, HR, RW, 4>(F, Hb);
     __syncthreads();
     for (int i = threadIdx.x; i < (TH / 2) * TW; i += SP_BLOCK) {
       const int yr = i / TW, xx = i - yr * TW;
@@ -1879,19 +1906,19 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
     }
     if (ring) q = eps;
     float pi = q;
-    const uint32_t o = (uint32_t)y * (uint32_t)W + (uint32_t)x;
+    const uint32_t ob = ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 4u;
     if (t > 0) {
       const float f = kB0 * hb[yy][xx] + kB1 * hb[yy + 1][xx] + kB2 * hb[yy + 2][xx] + kB1 * hb[yy + 3][xx] +
                       kB0 * hb[yy + 4][xx];
       pi = f + K * (q - f);
-      if (ftape) ftape[o] = f;
+      if (ftape) *at_bytes(ftape, ob) = f;
     }
     if (ring) pi = eps;
-    pnext[o] = pi;
-    if (pout) pout[o] = pi;
+    *at_bytes(pnext, ob) = pi;
+    if (pout) *at_bytes(pout, ob) = pi;
     if (unary) {
-      unary[o] = unary0(fminf(pi, 1.f - eps));
-      unary1p[o] = unary1(fmaxf(pi, eps));
+      *at_bytes(unary, ob) = unary0(fminf(pi, 1.f - eps));
+      *at_bytes(unary1p, ob) = unary1(fmaxf(pi, eps));
     }
   }
   if (mstape && J.tid == 0 && threadIdx.x == 0) {
@@ -1921,7 +1948,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_mrf(const Job* __restrict__ jobs,
     const float pi = prior[o];
     unary[o] = unary0(fminf(pi, 1.f - sd.eps));
     unary[plane + o] = unary1(fmaxf(pi, sd.eps));
-    pairwise_at(rgb, H, W, y, x, neg_beta_log2e(beta), sd.lam, sd.potts, pairw, plane);
+    pairwise_at(rgb, H, W, y, x, cap_consts(beta, sd.lam, sd.potts), pairw, plane);
   }
   if (beta_out && J.tid == 0 && threadIdx.x == 0) beta_out[0] = beta;
 }
