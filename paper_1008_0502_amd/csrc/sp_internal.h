@@ -178,17 +178,21 @@ __host__ __device__ inline CaLayout csapply_layout(const int32_t* pc, const int3
   return L;
 }
 
-// LDS of the reduced-map job.  One staging block of `chan` floats per channel
-// (16-byte aligned): the centre region of the level below c_max (x1) and the c_max tile
-// (x0), both in whole 16-byte quads per row (x0's tiles start at multiples of 16
-// columns), then one surround footprint per pair.  After the NC blocks, shared by the
-// channels and interleaved (element e of channel j at e * NC + j): one pair's
-// centre-surround map on the region (fqn floats per channel) and a table (ttn floats
-// per channel) holding first that pair's footprint rows interpolated at the region's
-// columns, then the row pass of the reduction.  total = chan + fqn + ttn floats per
-// channel of the group.
+// LDS of the reduced-map job for a group of NC channels, in floats per channel:
+// x1n, the centre region of the level below c_max in whole 16-byte quads per row
+// (CG_X1N each, at a compile-time stride so per-channel offsets fold into the LDS
+// instructions); x0n, the c_max tile (its tiles start at multiples of 16 columns, so
+// SP_CA_T quads per row); footn, one surround footprint per pair (pair p's block holds
+// the NC channels at a stride of its cap); then, channel-interleaved (element e of
+// channel j at e * NC + j), fqn for one pair's centre-surround map on the region and
+// ttn for a table holding first that pair's footprint rows interpolated at the
+// region's columns, then the row pass of the reduction.  The blocks follow each other
+// in this order, each NC * size floats long.
+#define CG_N1 (2 * SP_CA_T + 3)
+#define CG_PW1 ((CG_N1 + 6) & ~3)   // widest row of whole 16-byte quads covering CG_N1 columns
+#define CG_X1N (CG_N1 * CG_PW1)
 struct CgLayout {
-  int x1, x0, foot0, chan, fqn, ttn, total;
+  int x1n, x0n, footn, fqn, ttn, total;
 };
 
 __host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t* ps, int n_pairs, int c_max) {
@@ -197,24 +201,19 @@ __host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t*
     has0 |= (c_max - pc[p]) == 0;
     has1 |= (c_max - pc[p]) == 1;
   }
-  const int n1 = 2 * SP_CA_T + 3;
-  const int pw1 = (n1 + 6) & ~3;   // widest row of whole 16-byte quads covering n1 columns
+  const int n1 = CG_N1;
   CgLayout L;
-  int o = 0;
-  L.x1 = o;
-  if (has1) o += n1 * pw1;
-  L.x0 = o;
-  if (has0) o += SP_CA_T * SP_CA_T;
-  L.foot0 = o;
-  int tt = has1 ? n1 * SP_CA_T : 0;
+  L.x1n = has1 ? CG_X1N : 0;
+  L.x0n = has0 ? SP_CA_T * SP_CA_T : 0;
+  int f = 0, tt = has1 ? n1 * SP_CA_T : 0;
   for (int p = 0; p < n_pairs; ++p) {
     const int r = c_max - pc[p], d = ps[p] - pc[p];
-    o += csapply_foot_cap(r, d);
+    f += csapply_foot_cap(r, d);
     if (r == 1) tt = tt > (((n1 - 1) >> d) + 3) * n1 ? tt : (((n1 - 1) >> d) + 3) * n1;
   }
-  L.chan = (o + 3) & ~3;
+  L.footn = (f + 3) & ~3;
   L.fqn = has1 ? (n1 * n1 + 3) & ~3 : 0;
   L.ttn = (tt + 3) & ~3;
-  L.total = L.chan + L.fqn + L.ttn;
+  L.total = L.x1n + L.x0n + L.footn + L.fqn + L.ttn;
   return L;
 }

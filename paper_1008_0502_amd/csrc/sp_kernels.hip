@@ -1401,8 +1401,10 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   const int k0 = J.a, cm = sd.c_max;
   const int Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const CgLayout L = csg_layout(sd.pc, sd.ps, sd.n_pairs, cm);
-  const int CH = L.chan;
-  float* const FQ = dyn + NC * CH;          // [region pixel][NC]
+  float* const X1 = dyn;                    // [NC][CG_X1N]
+  float* const X0 = X1 + NC * L.x1n;        // [NC][SP_CA_T * SP_CA_T]
+  float* const FT = X0 + NC * L.x0n;        // per pair: [NC][cap]
+  float* const FQ = FT + NC * L.footn;      // [region pixel][NC]
   float* const TT = FQ + NC * L.fqn;        // [footprint row][region column][NC], then [region row][tile column][NC]
   bool has0 = false, has1 = false;
   for (int p = 0; p < sd.n_pairs; ++p) {
@@ -1425,12 +1427,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   // otherwise 4-byte transfers fill the same layout.
   const int xa0 = cg0.lo & ~3, pw0 = ((cg0.lo + cg0.n + 3) & ~3) - xa0;
   const int xa1 = cg1.lo & ~3, pw1 = ((cg1.lo + cg1.n + 3) & ~3) - xa1;
-  auto stage = [&](Range rr, int xa, int pw, int c, int xoff) {
+  auto stage = [&](Range rr, int xa, int pw, int c, float* xbase, int xstride) {
     const int Wc = sd.Wl[c];
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
       const float* Xc = chan_ptr(sd, ckpt, k0 + j, c);
-      float* X = dyn + j * CH + xoff;
+      float* X = xbase + j * xstride;
       if ((Wc & 3) == 0 && (reinterpret_cast<uintptr_t>(Xc) & 15) == 0) {
         const int nq = pw >> 2;
         Walk2 wk(threadIdx.x, nq);
@@ -1443,23 +1445,24 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
       }
     }
   };
-  if (has0) stage(rg0, xa0, pw0, cm, L.x0);
-  if (has1) stage(rg1, xa1, pw1, cm - 1, L.x1);
+  if (has0) stage(rg0, xa0, pw0, cm, X0, SP_CA_T * SP_CA_T);
+  if (has1) stage(rg1, xa1, pw1, cm - 1, X1, CG_X1N);
   {
-    int off = L.foot0;
+    float* fb = FT;
     for (int p = 0; p < sd.n_pairs; ++p) {
       const int c = sd.pc[p], r = cm - c, s = sd.ps[p], Ws = sd.Wl[s];
       const Range rr = (r == 0) ? rg0 : rg1, cc = (r == 0) ? cg0 : cg1;
       const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], Ws);
+      const int cap = csapply_foot_cap(r, s - c);
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const float* Xs = chan_ptr(sd, ckpt, k0 + j, s);
-        float* dst = dyn + j * CH + off;
+        float* dst = fb + j * cap;
         Walk2 wk(threadIdx.x, f.w);
         for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK, wk.next())
           lds_load(dst + i, Xs + (size_t)(f.y0 + wk.r) * Ws + f.x0 + wk.c);
       }
-      off += csapply_foot_cap(r, s - c);
+      fb += NC * cap;
     }
   }
   lds_wait();
@@ -1474,9 +1477,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
     bool bval[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) bval[i] = 8 * (i >> 1) < J.th && 8 * (i & 1) < J.tw;
-    int m = 0, off = L.foot0;
+    int m = 0;
+    const float* fb = FT;
     for (int p = 0; p < sd.n_pairs; ++p) {
       const int c = sd.pc[p], r = cm - c, s = sd.ps[p], d = s - c;
+      const int cap = csapply_foot_cap(r, d);
       if (r == 0) {
         const Foot f = footprint(J.y0, J.th, J.x0, J.tw, d, sd.Hl[s], sd.Wl[s]);
         int yl[2], xl[2];
@@ -1491,14 +1496,14 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
 #pragma unroll
         for (int j = 0; j < NC; ++j, ++m) {
           if ((m & 3) != w) continue;   // wave-uniform
-          const float* B = dyn + j * CH;
+          const float* B = X0 + j * (SP_CA_T * SP_CA_T) + cg0.lo - xa0;
           float mn = INFINITY, mx = -INFINITY;
 #pragma unroll
           for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
-              const float up = bilinear_lds(B + off, f.w, ty[u], tx[v], f.y0, f.x0);
-              const float F = fabsf(B[L.x0 + yl[u] * pw0 + cg0.lo - xa0 + xl[v]] - up);
+              const float up = bilinear_lds(fb + j * cap, f.w, ty[u], tx[v], f.y0, f.x0);
+              const float F = fabsf(B[yl[u] * pw0 + xl[v]] - up);
               mn = fminf(mn, F);
               mx = fmaxf(mx, F);
               if (qy + u < J.th && qx + v < J.tw)
@@ -1530,7 +1535,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
           }
         }
       }
-      off += csapply_foot_cap(r, d);
+      fb += NC * cap;
     }
   }
   // ---- pairs with c = c_max - 1, one at a time: the footprint's rows interpolated at the
@@ -1539,7 +1544,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   // w: block row w, a 2x2 quad per lane), then REDUCE to the tile
   if (has1) {
     const int c1 = cm - 1, H1 = sd.Hl[c1], W1 = sd.Wl[c1];
-    const int n1r = rg1.n, n1c = cg1.n, n = n1r * n1c;
+    const int n1r = rg1.n, n1c = cg1.n;
     const int oh = min(2 * J.th, H1 - 2 * J.y0), ow = min(2 * J.tw, W1 - 2 * J.x0);
     const int oy0 = 2 * J.y0 - rg1.lo, ox0 = 2 * J.x0 - cg1.lo;   // region offset of the owned pixels
     const int bx = lane >> 4, qy = 8 * w + 2 * sy, qx = 8 * bx + 2 * sx;
@@ -1562,23 +1567,30 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
       ix[t + 2] = clampi(2 * (cg0.lo + rc) + t, 0, W1 - 1) - cg1.lo;
       iy[t + 2] = clampi(2 * (rg0.lo + rr0) + t, 0, H1 - 1) - rg1.lo;
     }
-    const int xoff1 = L.x1 + cg1.lo - xa1;   // region column c of row r at xoff1 + r * pw1 + c
-    int off = L.foot0;
+    // the table and map passes: a thread keeps region column rcol and steps over the rows
+    // (G1 rows at a time; threads beyond G1 * n1c sit these passes out)
+    const int G1 = SP_BLOCK / n1c, g1 = threadIdx.x / n1c, rcol = threadIdx.x - g1 * n1c;
+    const float* const x1c = X1 + (cg1.lo - xa1) + rcol;   // row r of channel j at x1c + j * CG_X1N + r * pw1
+    const float* fb = FT;
     for (int p = 0; p < sd.n_pairs; ++p) {
       const int c = sd.pc[p], r = cm - c, s = sd.ps[p], d = s - c;
+      const int cap = csapply_foot_cap(r, d);
       if (r == 1) {
         const int Hs = sd.Hl[s], Ws = sd.Wl[s];
         const Foot f = footprint(rg1.lo, n1r, cg1.lo, n1c, d, Hs, Ws);
-        {
-          Walk2 wk(threadIdx.x, n1c);
-          for (int i = threadIdx.x; i < f.h * n1c; i += SP_BLOCK, wk.next()) {
-            const Tap tx = bilinear_tap(cg1.lo + wk.c, d, Ws);
-            const int a0 = off + wk.r * f.w + tx.i0 - f.x0, a1 = off + wk.r * f.w + tx.i1 - f.x0;
+        if (g1 < G1) {
+          const Tap tx = bilinear_tap(cg1.lo + rcol, d, Ws);
+          const float* f0 = fb + tx.i0 - f.x0;
+          const float* f1 = fb + tx.i1 - f.x0;
+          for (int rr = g1; rr < f.h; rr += G1) {
             float v[NC];
 #pragma unroll
-            for (int j = 0; j < NC; ++j) v[j] = fmaf(tx.w, dyn[j * CH + a1], (1.f - tx.w) * dyn[j * CH + a0]);
-            lds_putv<NC>(TT + i * NC, v);
+            for (int j = 0; j < NC; ++j)
+              v[j] = fmaf(tx.w, f1[j * cap + rr * f.w], (1.f - tx.w) * f0[j * cap + rr * f.w]);
+            lds_putv<NC>(TT + (rr * n1c + rcol) * NC, v);
           }
+        }
+        {
           if ((int)threadIdx.x < n1r) {
             const Tap ty = bilinear_tap(rg1.lo + threadIdx.x, d, Hs);
             rtap[threadIdx.x] = make_float4(__int_as_float((ty.i0 - f.y0) * n1c * NC),
@@ -1587,17 +1599,16 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
         }
         __syncthreads();
         // the map on the region
-        {
-          Walk2 wk(threadIdx.x, n1c);
-          for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
-            const float4 rt = rtap[wk.r];
+        if (g1 < G1) {
+          for (int rr = g1; rr < n1r; rr += G1) {
+            const float4 rt = rtap[rr];
             float t0[NC], t1[NC], F[NC];
-            lds_getv<NC>(TT + __float_as_int(rt.x) + wk.c * NC, t0);
-            lds_getv<NC>(TT + __float_as_int(rt.y) + wk.c * NC, t1);
-            const int xo = xoff1 + wk.r * pw1 + wk.c;
+            lds_getv<NC>(TT + __float_as_int(rt.x) + rcol * NC, t0);
+            lds_getv<NC>(TT + __float_as_int(rt.y) + rcol * NC, t1);
+            const float* xr = x1c + rr * pw1;
 #pragma unroll
-            for (int j = 0; j < NC; ++j) F[j] = fabsf(dyn[j * CH + xo] - fmaf(rt.z, t1[j], rt.w * t0[j]));
-            lds_putv<NC>(FQ + i * NC, F);
+            for (int j = 0; j < NC; ++j) F[j] = fabsf(xr[j * CG_X1N] - fmaf(rt.z, t1[j], rt.w * t0[j]));
+            lds_putv<NC>(FQ + (rr * n1c + rcol) * NC, F);
           }
         }
         __syncthreads();
@@ -1679,7 +1690,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
         }
         __syncthreads();   // the map, the table, the row taps and wred are reused by the next pair
       }
-      off += csapply_foot_cap(r, d);
+      fb += NC * cap;
     }
   }
 }
