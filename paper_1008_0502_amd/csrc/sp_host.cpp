@@ -61,6 +61,16 @@ bool gpath_ok(const Geo& g) {
   return true;
 }
 
+// Pair set the reduced-map kernel is compiled for (see cg_set1_r/d): 1 when the
+// geometry's pairs are, in order, (c_max - c, s - c) = (1,2), (1,3), (0,2), (0,3); 0 reads
+// the pairs at run time.
+int csg_set(const Geo& g) {
+  if (!gpath_ok(g) || g.n_pairs != CG_SET1_N) return 0;
+  for (int p = 0; p < g.n_pairs; ++p)
+    if (g.c_max - g.pc[p] != cg_set1_r(p) || g.ps[p] - g.pc[p] != cg_set1_d(p)) return 0;
+  return 1;
+}
+
 size_t csg_lds_bytes(const Geo& g) {
   return sizeof(float) * (size_t)csg_layout(g.pc, g.ps, g.n_pairs, g.c_max).total;
 }
@@ -813,7 +823,8 @@ int ctx_build_tables(sp_ctx* c) {
     for (size_t i = 0; i < parts.size(); ++i) {
       const bool grp = kinds[i] == JOB_CSAPPLY || kinds[i] == JOB_CSG;
       const bool pyr = kinds[i] == JOB_DOWN || kinds[i] == JOB_TAIL;   // flag: Gabor radius
-      c->fwd.push_back(c->jobs.add(kinds[i], grp ? nc : (pyr ? c->p.gabor_radius : 0), order(parts[i]), 1));
+      const int gflag = nc | (kinds[i] == JOB_CSG ? csg_set(g) << 8 : 0);
+      c->fwd.push_back(c->jobs.add(kinds[i], grp ? gflag : (pyr ? c->p.gabor_radius : 0), order(parts[i]), 1));
       if (grp) c->fwd.back().lds = ca_lds;
     }
     std::vector<Job> v;
@@ -850,7 +861,8 @@ int ctx_build_tables(sp_ctx* c) {
       for (size_t i = 0; i < all.size(); ++i) {
         const bool grp = kk[i] == JOB_CSAPPLY || kk[i] == JOB_CSG;
         const bool pyr = kk[i] == JOB_DOWN || kk[i] == JOB_TAIL;
-        c->rec.push_back(c->jobs.add(kk[i], grp ? nc : (pyr ? c->p.gabor_radius : 0), all[i], c->CH));
+        const int gflag = nc | (kk[i] == JOB_CSG ? csg_set(g) << 8 : 0);
+        c->rec.push_back(c->jobs.add(kk[i], grp ? gflag : (pyr ? c->p.gabor_radius : 0), all[i], c->CH));
         if (grp) c->rec.back().lds = ca_lds;
       }
     }
@@ -1382,7 +1394,10 @@ int batch_build_tables(sp_batch* b) {
     return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", nc * std::max(lds_a, lds_g));
   if (!css.empty()) b->phases.push_back(b->jobs.add(JOB_CSSTATS, 0, order(css), n));
   if (!csg.empty()) {
-    b->phases.push_back(b->jobs.add(JOB_CSG, nc, order(csg), n));
+    int set = 1;
+    for (const Geo& g : b->geo)
+      if (gpath_ok(g)) set = std::min(set, csg_set(g));
+    b->phases.push_back(b->jobs.add(JOB_CSG, nc | (set << 8), order(csg), n));
     b->phases.back().lds = nc * lds_g;
   }
   b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, n));

@@ -195,11 +195,12 @@ struct CgLayout {
   int x1n, x0n, footn, fqn, ttn, total;
 };
 
-__host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t* ps, int n_pairs, int c_max) {
+// From each pair's level offsets r = c_max - c and d = s - c.
+__host__ __device__ inline CgLayout csg_layout_rd(const int* rs, const int* ds, int n_pairs) {
   bool has0 = false, has1 = false;
   for (int p = 0; p < n_pairs; ++p) {
-    has0 |= (c_max - pc[p]) == 0;
-    has1 |= (c_max - pc[p]) == 1;
+    has0 |= rs[p] == 0;
+    has1 |= rs[p] == 1;
   }
   const int n1 = CG_N1;
   CgLayout L;
@@ -207,7 +208,7 @@ __host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t*
   L.x0n = has0 ? SP_CA_T * SP_CA_T : 0;
   int f = 0, tt = has1 ? n1 * SP_CA_T : 0;
   for (int p = 0; p < n_pairs; ++p) {
-    const int r = c_max - pc[p], d = ps[p] - pc[p];
+    const int r = rs[p], d = ds[p];
     f += csapply_foot_cap(r, d);
     if (r == 1) tt = tt > (((n1 - 1) >> d) + 3) * n1 ? tt : (((n1 - 1) >> d) + 3) * n1;
   }
@@ -217,3 +218,20 @@ __host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t*
   L.total = L.x1n + L.x0n + L.footn + L.fqn + L.ttn;
   return L;
 }
+
+__host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t* ps, int n_pairs, int c_max) {
+  int rs[SP_MAXP], ds[SP_MAXP];
+  for (int p = 0; p < n_pairs; ++p) {
+    rs[p] = c_max - pc[p];
+    ds[p] = ps[p] - pc[p];
+  }
+  return csg_layout_rd(rs, ds, n_pairs);
+}
+
+// Pair sets the reduced-map kernel is compiled for, as (r, d) = (c_max - c, s - c) per
+// pair in the stream's pair order; set 0 reads the pairs from the stream description.
+// Set 1: centres c_max - 1 and c_max, each with surround offsets 2 and 3 (the default
+// parameters' centres 1, 2 and deltas 2, 3).
+#define CG_SET1_N 4
+__host__ __device__ constexpr int cg_set1_r(int p) { return p < 2 ? 1 : 0; }
+__host__ __device__ constexpr int cg_set1_d(int p) { return 2 + (p & 1); }

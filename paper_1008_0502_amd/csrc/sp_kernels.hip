@@ -1388,7 +1388,10 @@ __device__ __forceinline__ void lds_putv(float* p, const float (&v)[NC]) {
   }
 }
 
-template <int NC>
+// The pair loops carry an unroll request that only the compile-time pair set can meet.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wpass-failed"
+template <int NC, int SET>
 __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
                                                   const StepIO* __restrict__ ios, StepIO io0) {
@@ -1400,16 +1403,29 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   const float* ckpt = IOF(ckpt);
   const int k0 = J.a, cm = sd.c_max;
   const int Hm = sd.Hl[cm], Wm = sd.Wl[cm];
-  const CgLayout L = csg_layout(sd.pc, sd.ps, sd.n_pairs, cm);
+  // the pairs as (r, d) = (c_max - c, s - c): compile-time constants for a known set
+  // (its pair loops unroll), else read from the stream description
+  const int np = SET ? CG_SET1_N : sd.n_pairs;
+  auto pr = [&](int p) { return SET ? cg_set1_r(p) : cm - sd.pc[p]; };
+  auto pd = [&](int p) { return SET ? cg_set1_d(p) : sd.ps[p] - sd.pc[p]; };
+  CgLayout L;
+  if constexpr (SET != 0) {
+    constexpr int R[CG_SET1_N] = {cg_set1_r(0), cg_set1_r(1), cg_set1_r(2), cg_set1_r(3)};
+    constexpr int D[CG_SET1_N] = {cg_set1_d(0), cg_set1_d(1), cg_set1_d(2), cg_set1_d(3)};
+    L = csg_layout_rd(R, D, CG_SET1_N);
+  } else {
+    L = csg_layout(sd.pc, sd.ps, sd.n_pairs, cm);
+  }
   float* const X1 = dyn;                    // [NC][CG_X1N]
   float* const X0 = X1 + NC * L.x1n;        // [NC][SP_CA_T * SP_CA_T]
   float* const FT = X0 + NC * L.x0n;        // per pair: [NC][cap]
   float* const FQ = FT + NC * L.footn;      // [region pixel][NC]
   float* const TT = FQ + NC * L.fqn;        // [footprint row][region column][NC], then [region row][tile column][NC]
   bool has0 = false, has1 = false;
-  for (int p = 0; p < sd.n_pairs; ++p) {
-    has0 |= (cm - sd.pc[p]) == 0;
-    has1 |= (cm - sd.pc[p]) == 1;
+#pragma unroll
+  for (int p = 0; p < np; ++p) {
+    has0 |= pr(p) == 0;
+    has1 |= pr(p) == 1;
   }
   const Range rg0{J.y0, J.th}, cg0{J.x0, J.tw};
   Range rg1 = rg0, cg1 = cg0;
@@ -1449,11 +1465,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   if (has1) stage(rg1, xa1, pw1, cm - 1, X1, CG_X1N);
   {
     float* fb = FT;
-    for (int p = 0; p < sd.n_pairs; ++p) {
-      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], Ws = sd.Wl[s];
+#pragma unroll
+    for (int p = 0; p < np; ++p) {
+      const int r = pr(p), d = pd(p), s = cm - r + d, Ws = sd.Wl[s];
       const Range rr = (r == 0) ? rg0 : rg1, cc = (r == 0) ? cg0 : cg1;
-      const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, s - c, sd.Hl[s], Ws);
-      const int cap = csapply_foot_cap(r, s - c);
+      const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, d, sd.Hl[s], Ws);
+      const int cap = csapply_foot_cap(r, d);
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const float* Xs = chan_ptr(sd, ckpt, k0 + j, s);
@@ -1479,8 +1496,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
     for (int i = 0; i < 4; ++i) bval[i] = 8 * (i >> 1) < J.th && 8 * (i & 1) < J.tw;
     int m = 0;
     const float* fb = FT;
-    for (int p = 0; p < sd.n_pairs; ++p) {
-      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], d = s - c;
+#pragma unroll
+    for (int p = 0; p < np; ++p) {
+      const int r = pr(p), d = pd(p), s = cm - r + d;
       const int cap = csapply_foot_cap(r, d);
       if (r == 0) {
         const Foot f = footprint(J.y0, J.th, J.x0, J.tw, d, sd.Hl[s], sd.Wl[s]);
@@ -1572,8 +1590,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
     const int G1 = SP_BLOCK / n1c, g1 = threadIdx.x / n1c, rcol = threadIdx.x - g1 * n1c;
     const float* const x1c = X1 + (cg1.lo - xa1) + rcol;   // row r of channel j at x1c + j * CG_X1N + r * pw1
     const float* fb = FT;
-    for (int p = 0; p < sd.n_pairs; ++p) {
-      const int c = sd.pc[p], r = cm - c, s = sd.ps[p], d = s - c;
+#pragma unroll
+    for (int p = 0; p < np; ++p) {
+      const int r = pr(p), d = pd(p), s = cm - r + d;
       const int cap = csapply_foot_cap(r, d);
       if (r == 1) {
         const int Hs = sd.Hl[s], Ws = sd.Wl[s];
@@ -1694,6 +1713,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
     }
   }
 }
+#pragma clang diagnostic pop
 
 // F-bar_k on a 16x16 c_max tile = sum over pairs of N(reduced map), all 8 channels; then
 // its partial statistics (one 8x8 block per wavefront).
@@ -2273,16 +2293,29 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
       break;
     case JOB_CSSTATS: hipLaunchKernelGGL(k_csstats, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSFINAL: hipLaunchKernelGGL(k_csfinal, g, b, 0, st, jobs, sds, ios, io); break;
-    case JOB_CSG:   // flag: channels per workgroup
-      if (flag == 8)
-        hipLaunchKernelGGL(k_csg<8>, g, b, lds, st, jobs, sds, ios, io);
-      else if (flag == 4)
-        hipLaunchKernelGGL(k_csg<4>, g, b, lds, st, jobs, sds, ios, io);
-      else if (flag == 2)
-        hipLaunchKernelGGL(k_csg<2>, g, b, lds, st, jobs, sds, ios, io);
-      else
-        hipLaunchKernelGGL(k_csg<1>, g, b, lds, st, jobs, sds, ios, io);
+    case JOB_CSG: {   // flag: channels per workgroup | pair set << 8
+      const int nc = flag & 0xff, set = flag >> 8;
+      if (set == 1) {
+        if (nc == 8)
+          hipLaunchKernelGGL((k_csg<8, 1>), g, b, lds, st, jobs, sds, ios, io);
+        else if (nc == 4)
+          hipLaunchKernelGGL((k_csg<4, 1>), g, b, lds, st, jobs, sds, ios, io);
+        else if (nc == 2)
+          hipLaunchKernelGGL((k_csg<2, 1>), g, b, lds, st, jobs, sds, ios, io);
+        else
+          hipLaunchKernelGGL((k_csg<1, 1>), g, b, lds, st, jobs, sds, ios, io);
+      } else {
+        if (nc == 8)
+          hipLaunchKernelGGL((k_csg<8, 0>), g, b, lds, st, jobs, sds, ios, io);
+        else if (nc == 4)
+          hipLaunchKernelGGL((k_csg<4, 0>), g, b, lds, st, jobs, sds, ios, io);
+        else if (nc == 2)
+          hipLaunchKernelGGL((k_csg<2, 0>), g, b, lds, st, jobs, sds, ios, io);
+        else
+          hipLaunchKernelGGL((k_csg<1, 0>), g, b, lds, st, jobs, sds, ios, io);
+      }
       break;
+    }
     case JOB_CSMIX: hipLaunchKernelGGL(k_csmix, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_CSAPPLY:   // flag: channels per workgroup
       if (flag == 8)
@@ -2364,10 +2397,12 @@ hipError_t sp_launch_batch_copy_out(int n, const BatchState* st, const StreamDes
 
 hipError_t sp_csapply_reserve_lds(size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
-  const void* fns[8] = {reinterpret_cast<const void*>(&k_csapply<1>), reinterpret_cast<const void*>(&k_csapply<2>),
-                        reinterpret_cast<const void*>(&k_csapply<4>), reinterpret_cast<const void*>(&k_csapply<8>),
-                        reinterpret_cast<const void*>(&k_csg<1>),     reinterpret_cast<const void*>(&k_csg<2>),
-                        reinterpret_cast<const void*>(&k_csg<4>),     reinterpret_cast<const void*>(&k_csg<8>)};
+  const void* fns[12] = {reinterpret_cast<const void*>(&k_csapply<1>), reinterpret_cast<const void*>(&k_csapply<2>),
+                         reinterpret_cast<const void*>(&k_csapply<4>), reinterpret_cast<const void*>(&k_csapply<8>),
+                         reinterpret_cast<const void*>(&k_csg<1, 0>),  reinterpret_cast<const void*>(&k_csg<2, 0>),
+                         reinterpret_cast<const void*>(&k_csg<4, 0>),  reinterpret_cast<const void*>(&k_csg<8, 0>),
+                         reinterpret_cast<const void*>(&k_csg<1, 1>),  reinterpret_cast<const void*>(&k_csg<2, 1>),
+                         reinterpret_cast<const void*>(&k_csg<4, 1>),  reinterpret_cast<const void*>(&k_csg<8, 1>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
