@@ -295,7 +295,6 @@ struct Bump {
   }
 };
 
-// Pixels per colour-statistics workgroup: 1024 * G with at most 256 workgroups.
 // Colour-statistics tiles: rows x columns, at most SP_RGB_TR x SP_RGB_TC, with the
 // row count lowered (down to 2) while a frame would give fewer than min_tiles workgroups.
 struct RgbTiling {
@@ -306,7 +305,8 @@ struct RgbTiling {
 RgbTiling rgb_tiling(const Geo& g, int min_tiles = 192) {
   RgbTiling t;
   t.nct = (g.W + SP_RGB_TC - 1) / SP_RGB_TC;
-  t.tc = (g.W + t.nct - 1) / t.nct;
+  t.tc = (((g.W + t.nct - 1) / t.nct) + 3) & ~3;   // tiles start at multiples of 4 columns
+  t.nct = (g.W + t.tc - 1) / t.tc;
   t.tr = SP_RGB_TR;
   while (t.tr > 2 && ((g.H + t.tr - 1) / t.tr) * t.nct < min_tiles) t.tr /= 2;
   t.nrt = (g.H + t.tr - 1) / t.tr;
@@ -1491,7 +1491,8 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
     Bump bm;
     bm.base = b->arena;
     for (int i = 0; i < n; ++i) {
-      layout_stream(b->h_sd[i], b->geo[i], *p, bm, 1, true);
+      // the colour-statistics launch holds every stream's tiles: aim at ~192 in total
+      layout_stream(b->h_sd[i], b->geo[i], *p, bm, 1, true, std::max(1, 192 / n));
       const Geo& g = b->geo[i];
       BatchState& s = b->h_st[i];
       std::memset(&s, 0, sizeof s);

@@ -344,84 +344,108 @@ __device__ __forceinline__ uint32_t rgb_d2i(uint32_t a, uint32_t b) {
 
 // Largest R+G+B over a tile of th x tw pixels; with want_d2 also the sum of squared
 // colour differences over the 8-neighbour pairs (E, S, SE, SW) whose first pixel is in
-// the tile, so that every unordered pair of the frame is counted once.  The tile and,
-// for the differences, its left/right neighbour columns and the row below are staged
-// in LDS as packed colours (R | G << 8 | B << 16), read from global memory in groups of
-// four pixels (three aligned dwords) where the frame allows it.
+// the tile, so that every unordered pair of the frame is counted once.
+//
+// Tiles are at most 256 columns wide (starting at multiples of 4) and are split into
+// four bands of rows, one per wavefront.  Lane l owns the four pixels x .. x+3,
+// x = x0 + 4 l, and walks down its band keeping the row below in registers.  When rows
+// start on 4-byte boundaries (width a multiple of 4, aligned frame), five aligned
+// dwords of a row hold pixels x-1 .. x+4, so each row is read once with no LDS; other
+// frames take a per-pixel byte path.
+__device__ __forceinline__ void rgb_row6(gp<const uint32_t> w, bool left, bool right, uint32_t (&p)[6]) {
+  // w: the dword holding the first byte of pixel x; p[k] = pixel x - 1 + k, zero outside
+  const uint32_t d0 = left ? w[-1] : 0u;
+  const uint32_t d1 = w[0], d2 = w[1], d3 = w[2];
+  const uint32_t d4 = right ? w[3] : 0u;
+  p[0] = d0 >> 8;
+  p[1] = d1 & 0xffffffu;
+  p[2] = __builtin_amdgcn_alignbyte(d2, d1, 3) & 0xffffffu;
+  p[3] = __builtin_amdgcn_alignbyte(d3, d2, 2) & 0xffffffu;
+  p[4] = d3 >> 8;
+  p[5] = d4 & 0xffffffu;
+}
+
+__device__ __forceinline__ uint32_t rgb_at(gp<const uint8_t> rgb, size_t o) {
+  return (uint32_t)rgb[3 * o] | ((uint32_t)rgb[3 * o + 1] << 8) | ((uint32_t)rgb[3 * o + 2] << 16);
+}
+
 __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
                                                   const StepIO* __restrict__ ios, StepIO io0, int want_d2) {
-  constexpr int LW = SP_RGB_TC + 8;
-  __shared__ uint32_t Pk[SP_RGB_TR + 1][LW];
   __shared__ unsigned long long sh[4];
   __shared__ uint32_t shm[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const gp<const uint8_t> rgb = G(IOF(rgb));
   const int W = sd.W, H = sd.H;
-  const int y0 = J.y0, x0 = J.x0, th = J.th, tw = J.tw;
-  const long long HW = (long long)H * W;
-  const bool al = (reinterpret_cast<uintptr_t>(IOF(rgb)) & 3) == 0;
-  const int nr = th + ((want_d2 && y0 + th < H) ? 1 : 0);
-  const int xs = want_d2 ? max(x0 - 1, 0) : x0;              // first staged column
-  const int xe = want_d2 ? min(x0 + tw, W - 1) : x0 + tw - 1;  // last staged column
-  // a staged row starts at the 4-pixel group holding (y, xs): at most 3 leading pixels.
-  // Up to RU groups per thread are loaded before any is stored, so their global loads
-  // are in flight together.
-  const int NG = (xe - xs + 3) / 4 + 1;
-  constexpr int RU = 4;
-  Walk2 wk(threadIdx.x, NG);
-  for (int i0 = threadIdx.x; i0 < nr * NG; i0 += RU * SP_BLOCK) {
-    uint32_t c[RU][4];
-    int slot[RU];
+  const int lane = lane_id(), w = wave_id();
+  const int rows = (J.th + 3) >> 2;   // rows of each wavefront's band
+  const int ya = J.y0 + w * rows, yb = min(ya + rows, J.y0 + J.th);
+  uint32_t mx = 0, d2 = 0;
+  const bool fast = (W & 3) == 0 && (reinterpret_cast<uintptr_t>(IOF(rgb)) & 3) == 0;
+  if (fast) {
+    const int x = J.x0 + 4 * lane;
+    if (x < J.x0 + J.tw && ya < yb) {
+      const bool left = x > 0, right = x + 4 < W;
+      const gp<const uint32_t> fw = (gp<const uint32_t>)(rgb);
+      const int wrow = 3 * W / 4;   // dwords per row
+      uint32_t a[6], b[6];
+      rgb_row6(fw + (size_t)ya * wrow + 3 * (x >> 2), left, right, a);
+      for (int y = ya; y < yb; ++y) {
+        const bool s = want_d2 && y + 1 < H;   // uniform over the wavefront
+        if (s) {
+          rgb_row6(fw + (size_t)(y + 1) * wrow + 3 * (x >> 2), left, right, b);
+        } else {
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int r = wk.r, gi = wk.c;
-      wk.next();
-      slot[u] = -1;
-      c[u][0] = c[u][1] = c[u][2] = c[u][3] = 0u;
-      if (i0 + u * SP_BLOCK >= nr * NG) continue;
-      const long long rowp = (long long)(y0 + r) * W;
-      const long long q = ((rowp + xs) & ~3LL) + 4 * gi;
-      if (q > rowp + xe) continue;
-      slot[u] = r * LW + 4 * gi;
-      if (al && q + 3 < HW) {
-        const gp<const uint32_t> w = (gp<const uint32_t>)(rgb + 3 * q);
-        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-        c[u][0] = w0 & 0xffffffu;
-        c[u][1] = (w0 >> 24) | ((w1 & 0xffffu) << 8);
-        c[u][2] = (w1 >> 16) | ((w2 & 0xffu) << 16);
-        c[u][3] = w2 >> 8;
-      } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const long long o = 3 * (q + j);
-          c[u][j] = (q + j < HW) ? ((uint32_t)rgb[o] | ((uint32_t)rgb[o + 1] << 8) | ((uint32_t)rgb[o + 2] << 16)) : 0u;
+          for (int k = 0; k < 6; ++k) b[k] = 0u;
         }
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) mx = max(mx, rgb_sum(a[k]));
+        if (want_d2) {
+          // squared distances of the owned pairs: E (a_k, a_k+1), S (a_k, b_k),
+          // SE (a_k, b_k+1), SW (a_k, b_k-1) for k = 1..4; pairs leaving the frame are
+          // dropped (their partner is a zero vector and masked out of the norm sum)
+          uint32_t na[6], nb[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            na[k] = __builtin_amdgcn_udot4(a[k], a[k], 0u, false);
+            nb[k] = __builtin_amdgcn_udot4(b[k], b[k], 0u, false);
+          }
+          uint32_t cross = 0u, nsum = 0u;
+#pragma unroll
+          for (int k = 1; k <= 4; ++k) {
+            const bool e = k < 4 || right, sw = k > 1 || left;
+            cross = __builtin_amdgcn_udot4(a[k], a[k + 1], cross, false);
+            nsum += e ? na[k] + na[k + 1] : 0u;
+            if (s) {
+              cross = __builtin_amdgcn_udot4(a[k], b[k], cross, false);
+              cross = __builtin_amdgcn_udot4(a[k], b[k + 1], cross, false);
+              cross = __builtin_amdgcn_udot4(a[k], b[k - 1], cross, false);
+              nsum += na[k] + nb[k];
+              nsum += e ? na[k] + nb[k + 1] : 0u;
+              nsum += sw ? na[k] + nb[k - 1] : 0u;
+            }
+          }
+          d2 += nsum - 2u * cross;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a[k] = b[k];
       }
     }
-#pragma unroll
-    for (int u = 0; u < RU; ++u)
-      if (slot[u] >= 0) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) (&Pk[0][0])[slot[u] + j] = c[u][j];
-      }
-  }
-  __syncthreads();
-  uint32_t mx = 0, d2 = 0;
-  Walk2 wk2(threadIdx.x, tw);
-  for (int i = threadIdx.x; i < th * tw; i += SP_BLOCK, wk2.next()) {
-    const int r = wk2.r, x = x0 + wk2.c, y = y0 + r;
-    const int k0 = x - xs + (int)(((long long)y * W + xs) & 3);
-    const uint32_t a = Pk[r][k0];
-    mx = max(mx, rgb_sum(a));
-    if (want_d2) {
-      if (x + 1 < W) d2 += rgb_d2i(a, Pk[r][k0 + 1]);
-      if (y + 1 < H) {
-        const int k1 = x - xs + (int)(((long long)(y + 1) * W + xs) & 3);
-        d2 += rgb_d2i(a, Pk[r + 1][k1]);
-        if (x + 1 < W) d2 += rgb_d2i(a, Pk[r + 1][k1 + 1]);
-        if (x > 0) d2 += rgb_d2i(a, Pk[r + 1][k1 - 1]);
+  } else {
+    Walk2 wk(threadIdx.x, J.tw);
+    for (int i = threadIdx.x; i < J.th * J.tw; i += SP_BLOCK, wk.next()) {
+      const int y = J.y0 + wk.r, x = J.x0 + wk.c;
+      const size_t o = (size_t)y * W + x;
+      const uint32_t a = rgb_at(rgb, o);
+      mx = max(mx, rgb_sum(a));
+      if (want_d2) {
+        if (x + 1 < W) d2 += rgb_d2i(a, rgb_at(rgb, o + 1));
+        if (y + 1 < H) {
+          d2 += rgb_d2i(a, rgb_at(rgb, o + W));
+          if (x + 1 < W) d2 += rgb_d2i(a, rgb_at(rgb, o + W + 1));
+          if (x > 0) d2 += rgb_d2i(a, rgb_at(rgb, o + W - 1));
+        }
       }
     }
   }
