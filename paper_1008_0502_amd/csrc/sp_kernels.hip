@@ -508,8 +508,8 @@ __device__ __forceinline__ float pair_cap(const CapK& k, float d2, bool diag) {
 // log1p method), and U0 = pi exactly when u rounds to 1.
 __device__ __forceinline__ float unary0(float pi) {
   const float u = 1.f - pi;
-  if (u == 1.f) return pi;
-  return -__builtin_amdgcn_logf(u) * 0.693147180559945309f * (pi * __builtin_amdgcn_rcpf(1.f - u));
+  const float v = -__builtin_amdgcn_logf(u) * 0.693147180559945309f * (pi * __builtin_amdgcn_rcpf(1.f - u));
+  return u == 1.f ? pi : v;   // a select: v is NaN there and discarded
 }
 __device__ __forceinline__ float unary1(float pi) { return -__builtin_amdgcn_logf(pi) * 0.693147180559945309f; }
 
@@ -1882,9 +1882,10 @@ constexpr int KTW_MAX = 64;   // widest tile (the width is chosen per stream by 
 __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ jobs,
                                                      const StreamDesc* __restrict__ sds,
                                                      const StepIO* __restrict__ ios, StepIO io0) {
-  __shared__ float reg[(KT + 4) * (KTW_MAX + 4)];   // flat, row stride tw + 4
+  __shared__ __align__(16) float reg[(KT + 4) * (KTW_MAX + 8)];   // flat, row stride rs
   __shared__ float Sl[(KT + 1) * (KTW_MAX + 1)];    // footprint of the tile on level c_max
   __shared__ float hb[KT + 4][KTW_MAX];
+  __shared__ int4 rtab[KT];   // per tile row: offsets in Sl of its two footprint rows, weight bits
   __shared__ float sh4[4];
   __shared__ int shi4[4];
   const Job J = jobs[blockIdx.x];
@@ -1899,17 +1900,28 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   const float K = IOF(K);
   const int t = IOF(t);
   const int H = sd.H, W = sd.W, cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
-  const int tw = J.tw, rw = tw + 4;
+  // the prior region: rows y0-2 .. y0+KT+1, columns from x0-4 in whole 16-byte quads
+  // (row stride rs; column x at x - x0 + 4), clamped to the frame.  Interior tiles of a
+  // float prior whose rows are 16-byte aligned are staged by 16-byte transfers.
+  const int tw = J.tw, rs = (tw + 11) & ~3;
   if (t > 0) {
-    Walk2 wk(threadIdx.x, rw);
-    for (int i = threadIdx.x; i < (KT + 4) * rw; i += SP_BLOCK, wk.next()) {
-      const int ry = wk.r, rx = wk.c;
-      const int y = clampi(J.y0 - 2 + ry, 0, H - 1), x = clampi(J.x0 - 2 + rx, 0, W - 1);
-      const size_t o = (size_t)y * W + x;
-      if (seg)
-        reg[i] = (float)seg[o];
-      else
-        lds_load(reg + i, pprev + o);
+    const bool quads = !seg && (W & 3) == 0 && (tw & 3) == 0 && J.x0 >= 4 && J.x0 + tw + 4 <= W &&
+                       (reinterpret_cast<uintptr_t>(pprev) & 15) == 0;
+    if (quads) {
+      const int nq = rs >> 2;
+      Walk2 wk(threadIdx.x, nq);
+      for (int q = threadIdx.x; q < (KT + 4) * nq; q += SP_BLOCK, wk.next())
+        lds_load4(reg + 4 * q, pprev + (size_t)clampi(J.y0 - 2 + wk.r, 0, H - 1) * W + J.x0 - 4 + 4 * wk.c);
+    } else {
+      Walk2 wk(threadIdx.x, rs);
+      for (int i = threadIdx.x; i < (KT + 4) * rs; i += SP_BLOCK, wk.next()) {
+        const int y = clampi(J.y0 - 2 + wk.r, 0, H - 1), x = clampi(J.x0 - 4 + wk.c, 0, W - 1);
+        const size_t o = (size_t)y * W + x;
+        if (seg)
+          reg[i] = (float)seg[o];
+        else
+          lds_load(reg + i, pprev + o);
+      }
     }
   }
   // the saliency samples of the tile: its footprint on level c_max, flat with row
@@ -1922,6 +1934,10 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
       const int fy = wk.r, fx = wk.c;
       lds_load(Sl + i, Sg + (size_t)(sf.y0 + fy) * Wm + sf.x0 + fx);
     }
+    if ((int)threadIdx.x < J.th) {
+      const Tap ty = bilinear_tap(J.y0 + threadIdx.x, cm, Hm);
+      rtab[threadIdx.x] = make_int4((ty.i0 - sf.y0) * sf.w - sf.x0, (ty.i1 - sf.y0) * sf.w - sf.x0, __float_as_int(ty.w), 0);
+    }
   }
   // the partial maxima are read while the staging loads are still in flight
   float m;
@@ -1930,22 +1946,24 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   lds_wait();
   __syncthreads();
   const bool flat = !(m > sd.flat_tol);
+  // threads map to columns modulo cw, the power of two >= tw (it divides the block): each
+  // keeps one column in the row pass below and in the update loop
+  const int cw = tw <= 1 ? 1 : 1 << (32 - __clz(tw - 1));
+  const int xx = threadIdx.x & (cw - 1);
   if (t > 0) {
-    Walk2 wk(threadIdx.x, tw);
-    for (int i = threadIdx.x; i < (KT + 4) * tw; i += SP_BLOCK, wk.next()) {
-      const int r = wk.r, j = wk.c;
-      const float* g = reg + r * rw + j;
-      hb[r][j] = kB0 * g[0] + kB1 * g[1] + kB2 * g[2] + kB1 * g[3] + kB0 * g[4];
+    if (xx < tw) {
+      for (int r = threadIdx.x / cw; r < KT + 4; r += SP_BLOCK / cw) {
+        const float* g = reg + r * rs + xx + 2;
+        hb[r][xx] = kB0 * g[0] + kB1 * g[1] + kB2 * g[2] + kB1 * g[3] + kB0 * g[4];
+      }
     }
     __syncthreads();
   }
   // consecutive lanes take consecutive pixels of a row, so every store of a wavefront
-  // covers a contiguous run.  Threads map to columns modulo cw, the power of two >= tw
-  // (it divides the block), so each thread keeps one column (its horizontal tap and
-  // border test) and steps down the rows.
+  // covers a contiguous run.  Each thread keeps its column (horizontal tap and border
+  // test) and steps down the rows.
   const float eps = sd.eps, rm = flat ? 0.f : 1.f / m;
-  const int cw = tw <= 1 ? 1 : 1 << (32 - __clz(tw - 1));
-  const int xx = threadIdx.x & (cw - 1), x = J.x0 + xx;
+  const int x = J.x0 + xx;
   const bool xring = x < sd.border || x >= W - sd.border;
   const Tap tx = bilinear_tap(x, cm, Wm);
   const gp<float> unary1p = unary + (size_t)H * W;
@@ -1955,8 +1973,14 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
     const bool ring = xring || y < sd.border || y >= H - sd.border;
     float q = 0.5f;
     if (!flat) {
-      const Tap ty = bilinear_tap(y, cm, Hm);
-      const float u = bilinear_lds(Sl, sf.w, ty, tx, sf.y0, sf.x0) * rm;
+      // the bilinear up-sample of bilinear_lds, with the row offsets from the table
+      const int4 rt = rtab[yy];
+      const float wy = __int_as_float(rt.z);
+      const float* r0 = Sl + rt.x;
+      const float* r1 = Sl + rt.y;
+      const float top = (1.f - tx.w) * r0[tx.i0] + tx.w * r0[tx.i1];
+      const float bot = (1.f - tx.w) * r1[tx.i0] + tx.w * r1[tx.i1];
+      const float u = ((1.f - wy) * top + wy * bot) * rm;
       q = fminf(fmaxf(u, eps), 1.f - eps);
     }
     if (ring) q = eps;
