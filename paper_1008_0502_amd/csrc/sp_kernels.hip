@@ -1467,21 +1467,31 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   // otherwise 4-byte transfers fill the same layout.
   const int xa0 = cg0.lo & ~3, pw0 = ((cg0.lo + cg0.n + 3) & ~3) - xa0;
   const int xa1 = cg1.lo & ~3, pw1 = ((cg1.lo + cg1.n + 3) & ~3) - xa1;
+  // One index walk per region drives the transfers of every channel of the group (the
+  // channels differ only in their plane and LDS block).
   auto stage = [&](Range rr, int xa, int pw, int c, float* xbase, int xstride) {
     const int Wc = sd.Wl[c];
+    const float* Xc[NC];
+    bool vec = (Wc & 3) == 0;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      const float* Xc = chan_ptr(sd, ckpt, k0 + j, c);
-      float* X = xbase + j * xstride;
-      if ((Wc & 3) == 0 && (reinterpret_cast<uintptr_t>(Xc) & 15) == 0) {
-        const int nq = pw >> 2;
-        Walk2 wk(threadIdx.x, nq);
-        for (int q = threadIdx.x; q < rr.n * nq; q += SP_BLOCK, wk.next())
-          lds_load4(X + 4 * q, Xc + (size_t)(rr.lo + wk.r) * Wc + xa + 4 * wk.c);
-      } else {
-        Walk2 wk(threadIdx.x, pw);
-        for (int i = threadIdx.x; i < rr.n * pw; i += SP_BLOCK, wk.next())
-          lds_load(X + i, Xc + (size_t)(rr.lo + wk.r) * Wc + min(xa + wk.c, Wc - 1));
+      Xc[j] = chan_ptr(sd, ckpt, k0 + j, c);
+      vec = vec && (reinterpret_cast<uintptr_t>(Xc[j]) & 15) == 0;
+    }
+    if (vec) {
+      const int nq = pw >> 2;
+      Walk2 wk(threadIdx.x, nq);
+      for (int q = threadIdx.x; q < rr.n * nq; q += SP_BLOCK, wk.next()) {
+        const size_t o = (size_t)(rr.lo + wk.r) * Wc + xa + 4 * wk.c;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) lds_load4(xbase + j * xstride + 4 * q, Xc[j] + o);
+      }
+    } else {
+      Walk2 wk(threadIdx.x, pw);
+      for (int i = threadIdx.x; i < rr.n * pw; i += SP_BLOCK, wk.next()) {
+        const size_t o = (size_t)(rr.lo + wk.r) * Wc + min(xa + wk.c, Wc - 1);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) lds_load(xbase + j * xstride + i, Xc[j] + o);
       }
     }
   };
@@ -1495,13 +1505,14 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
       const Range rr = (r == 0) ? rg0 : rg1, cc = (r == 0) ? cg0 : cg1;
       const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, d, sd.Hl[s], Ws);
       const int cap = csapply_foot_cap(r, d);
+      const float* Xs[NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const float* Xs = chan_ptr(sd, ckpt, k0 + j, s);
-        float* dst = fb + j * cap;
-        Walk2 wk(threadIdx.x, f.w);
-        for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK, wk.next())
-          lds_load(dst + i, Xs + (size_t)(f.y0 + wk.r) * Ws + f.x0 + wk.c);
+      for (int j = 0; j < NC; ++j) Xs[j] = chan_ptr(sd, ckpt, k0 + j, s);
+      Walk2 wk(threadIdx.x, f.w);
+      for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK, wk.next()) {
+        const size_t o = (size_t)(f.y0 + wk.r) * Ws + f.x0 + wk.c;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) lds_load(fb + j * cap + i, Xs[j] + o);
       }
       fb += NC * cap;
     }
