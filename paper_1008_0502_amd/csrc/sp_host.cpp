@@ -1308,7 +1308,9 @@ struct sp_batch {
   StepIO* d_io = nullptr;
   BatchState* d_st = nullptr;
   std::vector<BatchState> h_st;
-  const uint8_t** d_in = nullptr;   // [n] frame pointers of the current step
+  const uint8_t* const* in_node = nullptr;   // frame table the captured graph reads
+  hipGraphNode_t rgb_node = nullptr;         // its first node: colour statistics + step start
+  RgbNodeArgs rgb_args{};
   JobStore jobs;
   std::vector<Phase> phases;
   hipGraph_t graph = nullptr;
@@ -1336,6 +1338,8 @@ int batch_build_tables(sp_batch* b) {
     (void)hipGraphDestroy(b->graph);
     b->graph = nullptr;
   }
+  b->rgb_node = nullptr;
+  b->in_node = nullptr;
   b->jobs.host.clear();
   b->phases.clear();
   std::vector<Job> rgb, feat, fin, css, csf, csa, csg, csm, cons, kal;
@@ -1411,25 +1415,66 @@ int batch_build_tables(sp_batch* b) {
   return upload_jobs(b->jobs, b->stream);
 }
 
-int batch_enqueue(sp_batch* b, hipStream_t st) {
-  hipError_t e = sp_launch_batch_begin(b->n, b->d_st, b->d_in, b->d_io, b->p.q, b->p.r, st);
-  if (e != hipSuccess) return fail(SP_EHIP, "batch begin launch: %s", hipGetErrorString(e));
+// One step's launches.  The first phase (colour statistics) also starts the step and
+// reads the frames from in_ptrs; with node set (under capture) its graph node is kept so
+// later steps can point it at their own frame tables.
+int batch_enqueue(sp_batch* b, hipStream_t st, const uint8_t* const* in_ptrs, hipGraphNode_t* node = nullptr) {
+  bool first = true;
   for (const Phase& ph : b->phases) {
-    e = b->prof.timed(st, ph.kind, [&] {
-      return sp_launch(ph.kind, b->jobs.dev + ph.off, ph.n, b->d_sd, b->d_io, nullptr, ph.flag, nullptr, st, ph.lds);
-    });
+    hipError_t e;
+    if (first) {
+      if (ph.kind != JOB_RGB) return fail(SP_ESTATE, "batched step must start with the colour statistics");
+      const BatchBegin bb{in_ptrs, b->d_st, b->d_io, b->n, 0, b->p.q, b->p.r};
+      e = b->prof.timed(st, ph.kind, [&] {
+        return sp_launch_batch_rgb(b->jobs.dev + ph.off, ph.n, b->d_sd, b->d_io, ph.flag, bb, st);
+      });
+      if (e == hipSuccess && node) {
+        hipStreamCaptureStatus cs;
+        const hipGraphNode_t* deps = nullptr;
+        size_t nd = 0;
+        e = hipStreamGetCaptureInfo_v2(st, &cs, nullptr, nullptr, &deps, &nd);
+        if (e == hipSuccess && (cs != hipStreamCaptureStatusActive || nd != 1))
+          return fail(SP_EHIP, "graph capture: cannot find the first node");
+        if (e == hipSuccess) *node = deps[0];
+      }
+      first = false;
+    } else {
+      e = b->prof.timed(st, ph.kind, [&] {
+        return sp_launch(ph.kind, b->jobs.dev + ph.off, ph.n, b->d_sd, b->d_io, nullptr, ph.flag, nullptr, st, ph.lds);
+      });
+    }
     if (e != hipSuccess) return fail(SP_EHIP, "batch phase launch (kind %d): %s", ph.kind, hipGetErrorString(e));
   }
   return SP_OK;
 }
 
-// Captures the whole step once on the private stream (graph kept until the tables change).
-int batch_capture(sp_batch* b) {
+// Points the captured graph's first node at this step's frame table.
+int batch_point_graph(sp_batch* b, const uint8_t* const* in_ptrs) {
+  if (in_ptrs == b->in_node) return SP_OK;
+  const Phase& ph = b->phases.front();
+  RgbNodeArgs& a = b->rgb_args;
+  a.jobs = b->jobs.dev + ph.off;
+  a.sds = b->d_sd;
+  a.ios = b->d_io;
+  a.io0 = StepIO{};
+  a.want_d2 = ph.flag;
+  a.bb = BatchBegin{in_ptrs, b->d_st, b->d_io, b->n, 0, b->p.q, b->p.r};
+  hipKernelNodeParams kp;
+  sp_batch_rgb_node_params(&a, ph.n, &kp);
+  HIPCHK(hipGraphExecKernelNodeSetParams(b->exec, b->rgb_node, &kp));
+  b->in_node = in_ptrs;
+  return SP_OK;
+}
+
+// Captures the whole step once on the private stream (graph kept until the tables change),
+// reading the frames from in_ptrs until batch_point_graph points it elsewhere.
+int batch_capture(sp_batch* b, const uint8_t* const* in_ptrs) {
   HIPCHK(hipStreamSynchronize(b->stream));
   HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   const bool was = b->prof.on;
   b->prof.on = false;
-  int rc = batch_enqueue(b, b->cap_stream);
+  hipGraphNode_t node = nullptr;
+  int rc = batch_enqueue(b, b->cap_stream, in_ptrs, &node);
   b->prof.on = was;
   hipGraph_t gr = nullptr;
   hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
@@ -1440,6 +1485,8 @@ int batch_capture(sp_batch* b) {
   if (e != hipSuccess) return fail(SP_EHIP, "graph capture: %s", hipGetErrorString(e));
   b->graph = gr;
   HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->rgb_node = node;
+  b->in_node = in_ptrs;
   return SP_OK;
 }
 
@@ -1508,7 +1555,6 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
     b->d_sd = bm.take<StreamDesc>(n);
     b->d_io = bm.take<StepIO>(n);
     b->d_st = bm.take<BatchState>(n);
-    b->d_in = bm.take<const uint8_t*>(n);
     if (pass == 0) {
       bytes = bm.off + 256;
       if (hipMalloc(&b->arena, bytes) != hipSuccess) {
@@ -1554,8 +1600,7 @@ int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* pri
   if (!b || !rgb_ptrs) return fail(SP_EINVAL, "batch and rgb_ptrs must not be NULL");
   if (b->prof.on) {
     // measurement: the same phases, launched one by one with events around each
-    HIPCHK(hipMemcpyAsync(b->d_in, rgb_ptrs, sizeof(void*) * b->n, hipMemcpyDeviceToDevice, b->stream));
-    int rc = batch_enqueue(b, b->stream);
+    int rc = batch_enqueue(b, b->stream, rgb_ptrs);
     if (rc) return rc;
     b->steps += 1;
     if (prior_ptrs) {
@@ -1565,10 +1610,12 @@ int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* pri
     return SP_OK;
   }
   if (!b->exec) {
-    const int rc = batch_capture(b);
+    const int rc = batch_capture(b, rgb_ptrs);
+    if (rc) return rc;
+  } else {
+    const int rc = batch_point_graph(b, rgb_ptrs);
     if (rc) return rc;
   }
-  HIPCHK(hipMemcpyAsync(b->d_in, rgb_ptrs, sizeof(void*) * b->n, hipMemcpyDeviceToDevice, b->stream));
   HIPCHK(hipGraphLaunch(b->exec, b->stream));
   b->steps += 1;
   if (prior_ptrs) {
@@ -1625,7 +1672,6 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
   if (!b || !rgb_ptrs) return fail(SP_EINVAL, "batch and rgb_ptrs must not be NULL");
   if (steps < 1 || steps > 1000) return fail(SP_EINVAL, "steps must be 1..1000");
   HIPCHK(hipStreamSynchronize(b->stream));
-  HIPCHK(hipMemcpyAsync(b->d_in, rgb_ptrs, sizeof(void*) * b->n, hipMemcpyDeviceToDevice, b->stream));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1636,7 +1682,7 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
   auto time_it = [&](double* ms) -> int {   // replays of the captured step, as deployed
     int r = batch_build_tables(b);
     if (r) return r;
-    r = batch_capture(b);
+    r = batch_capture(b, rgb_ptrs);
     if (r) return r;
     HIPCHK(hipGraphLaunch(b->exec, b->stream));   // warm-up
     HIPCHK(hipEventRecord(e0, b->stream));

@@ -141,6 +141,17 @@ struct BatchState {
   int32_t cur, pad;
 };
 
+// Arguments that make the colour-statistics launch also start a batched step: its
+// workgroup 0 does every stream's step bookkeeping, and every workgroup reads its frame
+// from in_ptrs (in_ptrs null: an ordinary launch).
+struct BatchBegin {
+  const uint8_t* const* in_ptrs;   // [n] device pointers to this step's frames
+  BatchState* st;
+  StepIO* ios;
+  int32_t n, pad;
+  double Q, R;
+};
+
 // LDS layout (in floats) of the across-scale-sum job: centre values of the c_max tile
 // and of the regions one and two levels finer, the reduction temporary, and one
 // surround footprint per pair.  Shared by the kernel and the host (which sizes the

@@ -369,20 +369,29 @@ __device__ __forceinline__ uint32_t rgb_at(gp<const uint8_t> rgb, size_t o) {
   return (uint32_t)rgb[3 * o] | ((uint32_t)rgb[3 * o + 1] << 8) | ((uint32_t)rgb[3 * o + 2] << 16);
 }
 
+__device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const uint8_t* const* __restrict__ in_ptrs,
+                                   StepIO* __restrict__ ios, double Q, double R);
+
 __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
-                                                  const StepIO* __restrict__ ios, StepIO io0, int want_d2) {
+                                                  const StepIO* __restrict__ ios, StepIO io0, int want_d2,
+                                                  BatchBegin bb) {
   __shared__ unsigned long long sh[4];
   __shared__ uint32_t shm[4];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
-  const gp<const uint8_t> rgb = G(IOF(rgb));
+  // a batched step: this launch also starts the step (the other launches read the step's
+  // inputs after it completes); its own frames come from the caller's table
+  if (bb.in_ptrs && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < bb.n; i += SP_BLOCK) batch_begin_stream(i, bb.st, bb.in_ptrs, bb.ios, bb.Q, bb.R);
+  const uint8_t* frame = bb.in_ptrs ? bb.in_ptrs[J.stream] : IOF(rgb);
+  const gp<const uint8_t> rgb = G(frame);
   const int W = sd.W, H = sd.H;
   const int lane = lane_id(), w = wave_id();
   const int rows = (J.th + 3) >> 2;   // rows of each wavefront's band
   const int ya = J.y0 + w * rows, yb = min(ya + rows, J.y0 + J.th);
   uint32_t mx = 0, d2 = 0;
-  const bool fast = (W & 3) == 0 && (reinterpret_cast<uintptr_t>(IOF(rgb)) & 3) == 0;
+  const bool fast = (W & 3) == 0 && (reinterpret_cast<uintptr_t>(frame) & 3) == 0;
   if (fast) {
     const int x = J.x0 + 4 * lane;
     if (x < J.x0 + J.tw && ya < yb) {
@@ -2261,11 +2270,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_loss_final(const float* __restrict
 }
 
 // ---------------------------------------------------------------- batched step bookkeeping
-// Start of a step: every stream's inputs, Kalman gain (FP64) and prior buffers.
-__global__ void k_batch_begin(int n, BatchState* __restrict__ st, const uint8_t* const* __restrict__ in_ptrs,
-                              StepIO* __restrict__ ios, double Q, double R) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Start of a step for stream i: its inputs, Kalman gain (FP64) and prior buffers.
+__device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const uint8_t* const* __restrict__ in_ptrs,
+                                   StepIO* __restrict__ ios, double Q, double R) {
   BatchState s = st[i];
   double K, P;
   if (s.t == 0) {
@@ -2335,7 +2342,7 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
   StepIO z{};
   const StepIO& io = io0 ? *io0 : z;
   switch (kind) {
-    case JOB_RGB: hipLaunchKernelGGL(k_rgb, g, b, 0, st, jobs, sds, ios, io, flag); break;
+    case JOB_RGB: hipLaunchKernelGGL(k_rgb, g, b, 0, st, jobs, sds, ios, io, flag, BatchBegin{}); break;
     case JOB_FEAT: hipLaunchKernelGGL((k_feat<16, 16>), g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_DOWN:   // pyramid launch without tail jobs (DOWN and GABOR jobs)
     case JOB_GABOR:   // flag: the Gabor radius of the launch
@@ -2437,10 +2444,26 @@ hipError_t sp_launch_loss(const float* prior, const uint8_t* mask, size_t n, flo
   return chk();
 }
 
-hipError_t sp_launch_batch_begin(int n, BatchState* st, const uint8_t* const* in_ptrs, StepIO* ios, double Q,
-                                 double R, hipStream_t stream) {
-  hipLaunchKernelGGL(k_batch_begin, dim3((n + 63) / 64), dim3(64), 0, stream, n, st, in_ptrs, ios, Q, R);
+hipError_t sp_launch_batch_rgb(const Job* jobs, int n_jobs, const StreamDesc* sds, StepIO* ios, int want_d2,
+                               const BatchBegin& bb, hipStream_t stream) {
+  hipLaunchKernelGGL(k_rgb, dim3(n_jobs), dim3(SP_BLOCK), 0, stream, jobs, sds, ios, StepIO{}, want_d2, bb);
   return chk();
+}
+
+void sp_batch_rgb_node_params(RgbNodeArgs* a, int n_jobs, hipKernelNodeParams* p) {
+  a->argv[0] = &a->jobs;
+  a->argv[1] = &a->sds;
+  a->argv[2] = &a->ios;
+  a->argv[3] = &a->io0;
+  a->argv[4] = &a->want_d2;
+  a->argv[5] = &a->bb;
+  *p = hipKernelNodeParams{};
+  p->func = reinterpret_cast<void*>(&k_rgb);
+  p->gridDim = dim3(n_jobs);
+  p->blockDim = dim3(SP_BLOCK);
+  p->sharedMemBytes = 0;
+  p->kernelParams = a->argv;
+  p->extra = nullptr;
 }
 
 hipError_t sp_launch_batch_reset(int n, BatchState* st, hipStream_t stream) {
