@@ -182,10 +182,11 @@ int sp_set_state(sp_ctx* ctx, const void* dev_buf, size_t bytes);
 int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32_t* W, int32_t flags,
                     void* hip_stream, sp_batch** out);
 
-/* One step.  rgb_ptrs: DEVICE array of n device pointers to this step's frames (read
- * when the step runs; the frames must stay valid until the next step has run, which
- * reads them as the previous frames).  prior_ptrs: DEVICE array of n device pointers
- * receiving the priors, or NULL (then read them with sp_batch_prior). */
+/* One step.  rgb_ptrs: DEVICE array of n device pointers to this step's frames, read by
+ * the step's first launch when it runs (the array must stay valid until then; the frames
+ * until the next step has run, which reads them as the previous frames).  prior_ptrs:
+ * DEVICE array of n device pointers receiving the priors, or NULL (then read them with
+ * sp_batch_prior). */
 int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* prior_ptrs);
 
 /* Device pointer to stream i's current prior (valid until the next step). */
