@@ -29,6 +29,36 @@ __device__ __forceinline__ int dpp_i(int v) {
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
 
+// Minimum and maximum of non-negative floats on their bit patterns: for values >= 0 the
+// unsigned order of the bits is the float order, so no NaN canonicalisation is needed
+// and each DPP step folds into one DPP min/max instruction (the DPP source's old value
+// is left undefined: every lane is active and no pattern below leaves its row).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float fmin_nn(float a, float b) {
+  return __uint_as_float(min(__float_as_uint(a), __float_as_uint(b)));
+}
+__device__ __forceinline__ float fmax_nn(float a, float b) {
+  return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+// Per 16-lane row (an 8x8 block of 2x2 quads): every lane ends with its row's minimum and
+// maximum.
+__device__ __forceinline__ void row16_minmax_nn(float& mn, float& mx) {
+  uint32_t a = __float_as_uint(mn), b = __float_as_uint(mx);
+  a = min(a, dpp_u<0xB1>(a));    // quad_perm [1,0,3,2]
+  b = max(b, dpp_u<0xB1>(b));
+  a = min(a, dpp_u<0x4E>(a));    // quad_perm [2,3,0,1]
+  b = max(b, dpp_u<0x4E>(b));
+  a = min(a, dpp_u<0x141>(a));   // row_half_mirror
+  b = max(b, dpp_u<0x141>(b));
+  a = min(a, dpp_u<0x140>(a));   // row_mirror
+  b = max(b, dpp_u<0x140>(b));
+  mn = __uint_as_float(a);
+  mx = __uint_as_float(b);
+}
+
 struct OpMax { __device__ static float f(float a, float b) { return fmaxf(a, b); } };
 struct OpMin { __device__ static float f(float a, float b) { return fminf(a, b); } };
 struct OpSum { __device__ static float f(float a, float b) { return a + b; } };
@@ -1071,25 +1101,18 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jo
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
       const int k = 2 * w + kk;
-      float mn = INFINITY, mx = -INFINITY;
+      float mn = INFINITY, mx = 0.f;   // F >= 0
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           const float up = bilinear_lds(sur[q][k], CS_F, ty[u], tx[v], f.y0, f.x0);
           const float F = fabsf(cen[k][(yc[u] - J.y0) * CS_T + (xc[v] - J.x0)] - up);
-          mn = fminf(mn, F);
-          mx = fmaxf(mx, F);
+          mn = fmin_nn(mn, F);
+          mx = fmax_nn(mx, F);
         }
       // 8x8 block minimum and maximum: DPP within each 16-lane row
-      mn = fminf(mn, dpp_f<0xB1>(mn));
-      mx = fmaxf(mx, dpp_f<0xB1>(mx));
-      mn = fminf(mn, dpp_f<0x4E>(mn));
-      mx = fmaxf(mx, dpp_f<0x4E>(mx));
-      mn = fminf(mn, dpp_f<0x141>(mn));
-      mx = fmaxf(mx, dpp_f<0x141>(mx));
-      mn = fminf(mn, dpp_f<0x140>(mn));
-      mx = fmaxf(mx, dpp_f<0x140>(mx));
+      row16_minmax_nn(mn, mx);
       float bmn[4], bmx[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -1559,26 +1582,19 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
         for (int j = 0; j < NC; ++j, ++m) {
           if ((m & 3) != w) continue;   // wave-uniform
           const float* B = X0 + j * (SP_CA_T * SP_CA_T) + cg0.lo - xa0;
-          float mn = INFINITY, mx = -INFINITY;
+          float mn = INFINITY, mx = 0.f;   // F >= 0
 #pragma unroll
           for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
               const float up = bilinear_lds(fb + j * cap, f.w, ty[u], tx[v], f.y0, f.x0);
               const float F = fabsf(B[yl[u] * pw0 + xl[v]] - up);
-              mn = fminf(mn, F);
-              mx = fmaxf(mx, F);
+              mn = fmin_nn(mn, F);
+              mx = fmax_nn(mx, F);
               if (qy + u < J.th && qx + v < J.tw)
                 gmap[((size_t)p * SP_NCH + k0 + j) * plane + (size_t)(J.y0 + qy + u) * Wm + J.x0 + qx + v] = F;
             }
-          mn = fminf(mn, dpp_f<0xB1>(mn));
-          mx = fmaxf(mx, dpp_f<0xB1>(mx));
-          mn = fminf(mn, dpp_f<0x4E>(mn));
-          mx = fmaxf(mx, dpp_f<0x4E>(mx));
-          mn = fminf(mn, dpp_f<0x141>(mn));
-          mx = fmaxf(mx, dpp_f<0x141>(mx));
-          mn = fminf(mn, dpp_f<0x140>(mn));
-          mx = fmaxf(mx, dpp_f<0x140>(mx));
+          row16_minmax_nn(mn, mx);
           float bmn[4], bmx[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -1684,16 +1700,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
             for (int v = 0; v < 2; ++v) lds_getv<NC>(FQ + (ro[u] * n1c + co[v]) * NC, q[2 * u + v]);
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
-            float mn = fminf(fminf(q[0][j], q[1][j]), fminf(q[2][j], q[3][j]));
-            float mx = fmaxf(fmaxf(q[0][j], q[1][j]), fmaxf(q[2][j], q[3][j]));
-            mn = fminf(mn, dpp_f<0xB1>(mn));
-            mx = fmaxf(mx, dpp_f<0xB1>(mx));
-            mn = fminf(mn, dpp_f<0x4E>(mn));
-            mx = fmaxf(mx, dpp_f<0x4E>(mx));
-            mn = fminf(mn, dpp_f<0x141>(mn));
-            mx = fmaxf(mx, dpp_f<0x141>(mx));
-            mn = fminf(mn, dpp_f<0x140>(mn));
-            mx = fmaxf(mx, dpp_f<0x140>(mx));
+            float mn = fmin_nn(fmin_nn(q[0][j], q[1][j]), fmin_nn(q[2][j], q[3][j]));   // F >= 0
+            float mx = fmax_nn(fmax_nn(q[0][j], q[1][j]), fmax_nn(q[2][j], q[3][j]));
+            row16_minmax_nn(mn, mx);
             float bmn[4], bmx[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
