@@ -245,9 +245,10 @@ int tail_source(const Geo& g, int lo) {
   for (int L0 = lo; L0 < g.top; ++L0) {
     bool ok = sz(L0) <= SP_TAIL_SRC;
     for (int l = L0 + 1; ok && l <= g.top; ++l) {
-      ok &= sz(l) <= (((l - L0) & 1) ? SP_TAIL_ALT : SP_TAIL_SRC);
+      const bool odd = (l - L0) & 1;   // level l in the second buffer, level l-1 in the first
+      ok &= sz(l) <= (odd ? SP_TAIL_ALT : SP_TAIL_SRC);
       ok &= (long long)g.Hl[l - 1] * g.Wl[l] <= SP_TAIL_HB;
-      if (g.used & (1u << l)) ok &= 4 * sz(l) <= SP_TAIL_V;
+      if (g.used & (1u << l)) ok &= 4 * sz(l) <= (odd ? SP_TAIL_SRC : SP_TAIL_ALT);
     }
     if (ok) return L0;
   }

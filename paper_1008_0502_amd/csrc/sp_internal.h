@@ -45,11 +45,12 @@ enum JobKind : int32_t {
   JOB_NKINDS
 };
 
-// Capacities of the LDS buffers of the tail job (floats).
-#define SP_TAIL_SRC 8192   // source level
-#define SP_TAIL_ALT 4096   // every other level above it
+// Capacities of the LDS buffers of the tail job (floats).  The levels alternate between
+// the first two buffers; the four vertical Gabor passes of a level take the buffer of the
+// level below it, no longer needed once the level is built.
+#define SP_TAIL_SRC 8192   // source level and every second level above it
+#define SP_TAIL_ALT 4096   // the other levels above it
 #define SP_TAIL_HB 4096    // horizontal intermediate
-#define SP_TAIL_V 8192     // 4 vertical Gabor passes of one level
 
 struct Job {
   int32_t stream;   // index into the stream table

@@ -730,7 +730,7 @@ constexpr int DOWN_LDS = 4 * DR * DR;                           // floats (the r
 constexpr int GT = 16, GW = 32;                                 // Gabor tile: rows x columns
 constexpr int GRM = GT + 2 * SP_MAXR, GCM = GW + 2 * SP_MAXR;    // its largest region
 constexpr int GAB_LDS = GRM * GCM + 4 * GT * (GCM + 1) + 4 * (2 * SP_MAXR + 1);
-constexpr int TAIL_LDS = SP_TAIL_SRC + SP_TAIL_ALT + SP_TAIL_HB + SP_TAIL_V + 4 * (2 * SP_MAXR + 1);
+constexpr int TAIL_LDS = SP_TAIL_SRC + SP_TAIL_ALT + SP_TAIL_HB + 4 * (2 * SP_MAXR + 1);
 static_assert(DOWN_LDS >= GAB_LDS, "LDS of the small pyramid kernel");
 
 __device__ __forceinline__ gp<float> level_dst(const StreamDesc& sd, float* ckpt, int l) {
@@ -940,8 +940,7 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   float* SA = smem;
   float* SB = SA + SP_TAIL_SRC;
   float* HB = SB + SP_TAIL_ALT;
-  float* V = HB + SP_TAIL_HB;
-  float* taps = V + SP_TAIL_V;
+  float* taps = HB + SP_TAIL_HB;
   const bool gab = J.kind == JOB_TAILGAB;
   const int ch = gab ? 0 : J.tid, L0 = J.a, R = sd.gr, nt = 2 * R + 1;
   const int last = gab ? J.tid : sd.top;
@@ -978,8 +977,8 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
       if (dst) dst[i] = acc;
     }
     __syncthreads();
-    if (gab && l + 1 == last)
-      gabor_lds<(RC > 0 ? 2 * RC + 1 : 2 * SP_MAXR + 1)>(nxt, nH, nW, J.y0, J.th, V, taps, R, sd.c45,
+    if (gab && l + 1 == last)   // its vertical passes go to the buffer of level l, now free
+      gabor_lds<(RC > 0 ? 2 * RC + 1 : 2 * SP_MAXR + 1)>(nxt, nH, nW, J.y0, J.th, cur, taps, R, sd.c45,
                                                      G(sd.gab[l + 1]));
     float* tmp = cur;
     cur = nxt;
