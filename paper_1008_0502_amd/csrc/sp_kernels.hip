@@ -30,13 +30,7 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
 
 // Minimum and maximum of non-negative floats on their bit patterns: for values >= 0 the
-// unsigned order of the bits is the float order, so no NaN canonicalisation is needed
-// and each DPP step folds into one DPP min/max instruction (the DPP source's old value
-// is left undefined: every lane is active and no pattern below leaves its row).
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
-}
+// unsigned order of the bits is the float order, so no NaN canonicalisation is needed.
 __device__ __forceinline__ float fmin_nn(float a, float b) {
   return __uint_as_float(min(__float_as_uint(a), __float_as_uint(b)));
 }
@@ -44,17 +38,25 @@ __device__ __forceinline__ float fmax_nn(float a, float b) {
   return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
 }
 // Per 16-lane row (an 8x8 block of 2x2 quads): every lane ends with its row's minimum and
-// maximum.
+// maximum.  Written as DPP-combined v_min_u32/v_max_u32 (the compiler keeps a separate
+// DPP move per step); every lane must be active.  The s_nop 1 before each step gives
+// the two wait states a DPP read of a VGPR needs after a VALU write to it.
 __device__ __forceinline__ void row16_minmax_nn(float& mn, float& mx) {
   uint32_t a = __float_as_uint(mn), b = __float_as_uint(mx);
-  a = min(a, dpp_u<0xB1>(a));    // quad_perm [1,0,3,2]
-  b = max(b, dpp_u<0xB1>(b));
-  a = min(a, dpp_u<0x4E>(a));    // quad_perm [2,3,0,1]
-  b = max(b, dpp_u<0x4E>(b));
-  a = min(a, dpp_u<0x141>(a));   // row_half_mirror
-  b = max(b, dpp_u<0x141>(b));
-  a = min(a, dpp_u<0x140>(a));   // row_mirror
-  b = max(b, dpp_u<0x140>(b));
+  asm volatile(
+      "s_nop 1\n"
+      "v_min_u32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n"
+      "v_max_u32_dpp %1, %1, %1 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n"
+      "s_nop 1\n"
+      "v_min_u32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n"
+      "v_max_u32_dpp %1, %1, %1 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n"
+      "s_nop 1\n"
+      "v_min_u32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n"
+      "v_max_u32_dpp %1, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xf\n"
+      "s_nop 1\n"
+      "v_min_u32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf\n"
+      "v_max_u32_dpp %1, %1, %1 row_mirror row_mask:0xf bank_mask:0xf\n"
+      : "+v"(a), "+v"(b));
   mn = __uint_as_float(a);
   mx = __uint_as_float(b);
 }
