@@ -832,7 +832,7 @@ int ctx_build_tables(sp_ctx* c) {
     add_tiles(v, 0, 0, Hc, Wc);
     c->prior.push_back(c->jobs.add(JOB_SMAX, 0, v, 1));
     v.clear();
-    add_tiles_wh(v, 0, 0, H, W, 16, c->tune.kalman_tw, JOB_KALMAN);
+    add_tiles_wh(v, 0, 0, H, W, SP_KAL_ROWS, c->tune.kalman_tw, JOB_KALMAN);
     c->prior.push_back(c->jobs.add(JOB_KALMAN, 0, order(v), 1));
     v.clear();
     rgb_jobs(v, 0, c->h_sd, g);
@@ -1092,7 +1092,7 @@ int sp_autotune(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, int32_
       c->tune.kalman_tw = tw;
       rc = time_it(&t);
       if (rc) break;
-      snprintf(line, sizeof line, "%dx%d xcd_order=%d kalman tile 16x%d: %.4f ms/frame\n", g.H, g.W, x, tw, t);
+      snprintf(line, sizeof line, "%dx%d xcd_order=%d kalman tile %dx%d: %.4f ms/frame\n", g.H, g.W, x, SP_KAL_ROWS, tw, t);
       rep += line;
       if (t < best) {
         best = t;
@@ -1373,7 +1373,7 @@ int batch_build_tables(sp_batch* b) {
       for (int k = 0; k < SP_NCH; k += nc) add_tiles(csa, i, k, g.Hl[g.c_max], g.Wl[g.c_max]);
     }
     add_tiles(cons, i, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
-    add_tiles_wh(kal, i, 0, g.H, g.W, 16, b->tune[i].kalman_tw, JOB_KALMAN);
+    add_tiles_wh(kal, i, 0, g.H, g.W, SP_KAL_ROWS, b->tune[i].kalman_tw, JOB_KALMAN);
   }
   // tail jobs first in the final pyramid launch: they are the longest workgroups
   std::stable_sort(fin.begin(), fin.end(), [](const Job& a, const Job& c) {
@@ -1719,7 +1719,7 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
       for (int i : kv.second) b->tune[i].kalman_tw = tw;
       rc = time_it(&t);
       if (rc) break;
-      snprintf(line, sizeof line, "%dx%d kalman tile 16x%d: %.4f ms/step\n", kv.first.first, kv.first.second, tw, t);
+      snprintf(line, sizeof line, "%dx%d kalman tile %dx%d: %.4f ms/step\n", kv.first.first, kv.first.second, SP_KAL_ROWS, tw, t);
       rep += line;
       if (t < bt) {
         bt = t;

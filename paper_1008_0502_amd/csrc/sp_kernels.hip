@@ -1907,15 +1907,16 @@ __global__ __launch_bounds__(SP_BLOCK) void k_smax(const Job* __restrict__ jobs,
 // q = clamp(up(S / max S), eps, 1 - eps) (0.5 if S is flat), eps on the border ring;
 // f = G * pi_{t-1} (or G * seg_{t-1}); pi_t = f + K_t (q - f); eps on the border ring.
 // With io.unary set it also writes the unary capacities of pi_t.
-constexpr int KT = 16;        // tile rows of the level-0 update
+constexpr int KT = 16;        // tile edge of the level-0 adjoint sweep
+constexpr int KTR = SP_KAL_ROWS;   // tile rows of the level-0 update
 constexpr int KTW_MAX = 64;   // widest tile (the width is chosen per stream by the host)
 __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ jobs,
                                                      const StreamDesc* __restrict__ sds,
                                                      const StepIO* __restrict__ ios, StepIO io0) {
-  __shared__ __align__(16) float reg[(KT + 4) * (KTW_MAX + 8)];   // flat, row stride rs
-  __shared__ float Sl[(KT + 1) * (KTW_MAX + 1)];    // footprint of the tile on level c_max
-  __shared__ float hb[KT + 4][KTW_MAX];
-  __shared__ int4 rtab[KT];   // per tile row: offsets in Sl of its two footprint rows, weight bits
+  __shared__ __align__(16) float reg[(KTR + 4) * (KTW_MAX + 8)];   // flat, row stride rs
+  __shared__ float Sl[(KTR / 2 + 2) * (KTW_MAX / 2 + 2)];   // footprint of the tile on level c_max >= 1
+  __shared__ float hb[KTR + 4][KTW_MAX];
+  __shared__ int4 rtab[KTR];   // per tile row: offsets in Sl of its two footprint rows, weight bits
   __shared__ float sh4[4];
   __shared__ int shi4[4];
   const Job J = jobs[blockIdx.x];
@@ -1930,7 +1931,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   const float K = IOF(K);
   const int t = IOF(t);
   const int H = sd.H, W = sd.W, cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
-  // the prior region: rows y0-2 .. y0+KT+1, columns from x0-4 in whole 16-byte quads
+  // the prior region: rows y0-2 .. y0+KTR+1, columns from x0-4 in whole 16-byte quads
   // (row stride rs; column x at x - x0 + 4), clamped to the frame.  Interior tiles of a
   // float prior whose rows are 16-byte aligned are staged by 16-byte transfers.
   const int tw = J.tw, rs = (tw + 11) & ~3;
@@ -1940,11 +1941,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
     if (quads) {
       const int nq = rs >> 2;
       Walk2 wk(threadIdx.x, nq);
-      for (int q = threadIdx.x; q < (KT + 4) * nq; q += SP_BLOCK, wk.next())
+      for (int q = threadIdx.x; q < (KTR + 4) * nq; q += SP_BLOCK, wk.next())
         lds_load4(reg + 4 * q, pprev + (size_t)clampi(J.y0 - 2 + wk.r, 0, H - 1) * W + J.x0 - 4 + 4 * wk.c);
     } else {
       Walk2 wk(threadIdx.x, rs);
-      for (int i = threadIdx.x; i < (KT + 4) * rs; i += SP_BLOCK, wk.next()) {
+      for (int i = threadIdx.x; i < (KTR + 4) * rs; i += SP_BLOCK, wk.next()) {
         const int y = clampi(J.y0 - 2 + wk.r, 0, H - 1), x = clampi(J.x0 - 4 + wk.c, 0, W - 1);
         const size_t o = (size_t)y * W + x;
         if (seg)
@@ -1982,7 +1983,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   const int xx = threadIdx.x & (cw - 1);
   if (t > 0) {
     if (xx < tw) {
-      for (int r = threadIdx.x / cw; r < KT + 4; r += SP_BLOCK / cw) {
+      for (int r = threadIdx.x / cw; r < KTR + 4; r += SP_BLOCK / cw) {
         const float* g = reg + r * rs + xx + 2;
         hb[r][xx] = kB0 * g[0] + kB1 * g[1] + kB2 * g[2] + kB1 * g[3] + kB0 * g[4];
       }
