@@ -202,6 +202,9 @@ __device__ __forceinline__ gp<T> at_bytes(gp<T> base, uint32_t byte_off) {
   typedef __attribute__((address_space(1))) char gchar;
   return (gp<T>)((gchar*)base + byte_off);
 }
+// Streaming store (nt: not kept in the caches) for per-pixel outputs written once and not
+// read again within the step.
+__device__ __forceinline__ void st_stream(gp<float> p, float v) { __builtin_nontemporal_store(v, p); }
 
 // Row and column of the flat index i = threadIdx.x + k * SP_BLOCK over rows of length
 // w, advanced by SP_BLOCK per step: the quotient and remainder of the start and of the
@@ -699,10 +702,10 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
         const float cS = pair_cap(ck, rgb_d2(c0, Pk[r + RW]), false);
         const float cSE = pair_cap(ck, rgb_d2(c0, Pk[r + RW + 1]), true);
         const float cSW = pair_cap(ck, rgb_d2(c0, Pk[r + RW - 1]), true);
-        *at_bytes(pw0, ob) = e ? cE : 0.f;
-        *at_bytes(pw1, ob) = s ? cS : 0.f;
-        *at_bytes(pw2, ob) = (s && e) ? cSE : 0.f;
-        *at_bytes(pw3, ob) = (s && x > 0) ? cSW : 0.f;
+        st_stream(at_bytes(pw0, ob), e ? cE : 0.f);
+        st_stream(at_bytes(pw1, ob), s ? cS : 0.f);
+        st_stream(at_bytes(pw2, ob), (s && e) ? cSE : 0.f);
+        st_stream(at_bytes(pw3, ob), (s && x > 0) ? cSW : 0.f);
       }
       if (h == 0 && J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) G(IOF(beta_out))[0] = beta;
     }
@@ -2024,11 +2027,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
       if (ftape) *at_bytes(ftape, ob) = f;
     }
     if (ring) pi = eps;
-    *at_bytes(pnext, ob) = pi;
+    st_stream(at_bytes(pnext, ob), pi);
     if (pout) *at_bytes(pout, ob) = pi;
     if (unary) {
-      *at_bytes(unary, ob) = unary0(fminf(pi, 1.f - eps));
-      *at_bytes(unary1p, ob) = unary1(fmaxf(pi, eps));
+      st_stream(at_bytes(unary, ob), unary0(fminf(pi, 1.f - eps)));
+      st_stream(at_bytes(unary1p, ob), unary1(fmaxf(pi, eps)));
     }
   }
   if (mstape && J.tid == 0 && threadIdx.x == 0) {
