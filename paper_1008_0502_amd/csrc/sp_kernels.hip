@@ -202,6 +202,20 @@ __device__ __forceinline__ gp<T> at_bytes(gp<T> base, uint32_t byte_off) {
   typedef __attribute__((address_space(1))) char gchar;
   return (gp<T>)((gchar*)base + byte_off);
 }
+
+// Wave-uniform forms of the direct loads: wave_dst is the LDS address of the wavefront's
+// lane 0 (one value for the whole wavefront, so M0 is set from scalar registers with no
+// read-back from a vector register), and the source is a uniform base plus the lane's
+// 32-bit byte offset (the scalar-base form of the instruction).  A loop over k with
+// element i = k * SP_BLOCK + threadIdx.x passes region + k * SP_BLOCK + wave_first()
+// (times 4 for the 16-byte form).
+__device__ __forceinline__ int wave_first() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63); }
+__device__ __forceinline__ void lds_load_u(float* wave_dst, gp<const float> base, uint32_t byte_off) {
+  __builtin_amdgcn_global_load_lds(at_bytes(base, byte_off), (lds_void*)wave_dst, 4, 0, 0);
+}
+__device__ __forceinline__ void lds_load4_u(float* wave_dst, gp<const float> base, uint32_t byte_off) {
+  __builtin_amdgcn_global_load_lds(at_bytes(base, byte_off), (lds_void*)wave_dst, 16, 0, 0);
+}
 // Streaming store (nt: not kept in the caches) for per-pixel outputs written once and not
 // read again within the step.
 __device__ __forceinline__ void st_stream(gp<float> p, float v) { __builtin_nontemporal_store(v, p); }
@@ -761,11 +775,12 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   const float* src = base_ptr(sd, ckpt, l);
   const size_t splane = (size_t)Hs * Ws;
   const int Y0 = 2 * J.y0 - 2, X0 = 2 * J.x0 - 2;
-  for (int i = threadIdx.x; i < DR * DR; i += SP_BLOCK) {
-    const int ry = i / DR, rx = i - ry * DR;
-    const size_t o = (size_t)clampi(Y0 + ry, 0, Hs - 1) * Ws + clampi(X0 + rx, 0, Ws - 1);
+  const int wf = wave_first();
+  for (int i0 = 0; i0 + (int)threadIdx.x < DR * DR; i0 += SP_BLOCK) {
+    const int i = i0 + threadIdx.x, ry = i / DR, rx = i - ry * DR;
+    const uint32_t ob = ((uint32_t)clampi(Y0 + ry, 0, Hs - 1) * (uint32_t)Ws + (uint32_t)clampi(X0 + rx, 0, Ws - 1)) * 4u;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) lds_load(F + c * DR * DR + i, src + c * splane + o);
+    for (int c = 0; c < 4; ++c) lds_load_u(F + c * DR * DR + i0 + wf, G(src + c * splane), ob);
   }
   lds_wait();
   __syncthreads();
@@ -820,10 +835,12 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
   const int Hs = sd.Hl[l], Ws = sd.Wl[l];
   const float* I = base_ptr(sd, ckpt, l);
   load_taps(sd, n, taps);
+  const gp<const float> gI = G(I);
+  const int wf = wave_first();
   Walk2 wk(threadIdx.x, RRc);
-  for (int i = threadIdx.x; i < RRr * RRc; i += SP_BLOCK, wk.next()) {
+  for (int i0 = 0; i0 + (int)threadIdx.x < RRr * RRc; i0 += SP_BLOCK, wk.next()) {
     const int y = clampi(J.y0 - R + wk.r, 0, Hs - 1), x = clampi(J.x0 - R + wk.c, 0, Ws - 1);
-    lds_load(Ir + i, I + (size_t)y * Ws + x);
+    lds_load_u(Ir + i0 + wf, gI, ((uint32_t)y * (uint32_t)Ws + (uint32_t)x) * 4u);
   }
   lds_wait();
   __syncthreads();
@@ -953,7 +970,9 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   int cH = sd.Hl[L0], cW = sd.Wl[L0];
   {
     const float* src = base_ptr(sd, ckpt, L0) + (size_t)ch * cH * cW;
-    for (int i = threadIdx.x; i < cH * cW; i += SP_BLOCK) lds_load(SA + i, src + i);
+    const int wf = wave_first();
+    for (int i0 = 0; i0 + (int)threadIdx.x < cH * cW; i0 += SP_BLOCK)
+      lds_load_u(SA + i0 + wf, G(src), (uint32_t)(i0 + threadIdx.x) * 4u);
     lds_wait();
   }
   float* cur = SA;
@@ -1505,29 +1524,31 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
   const int xa1 = cg1.lo & ~3, pw1 = ((cg1.lo + cg1.n + 3) & ~3) - xa1;
   // One index walk per region drives the transfers of every channel of the group (the
   // channels differ only in their plane and LDS block).
+  const int wf = wave_first();
   auto stage = [&](Range rr, int xa, int pw, int c, float* xbase, int xstride) {
-    const int Wc = sd.Wl[c];
-    const float* Xc[NC];
+    const uint32_t Wc = sd.Wl[c];
+    gp<const float> Xc[NC];
     bool vec = (Wc & 3) == 0;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      Xc[j] = chan_ptr(sd, ckpt, k0 + j, c);
+      Xc[j] = G(chan_ptr(sd, ckpt, k0 + j, c));
       vec = vec && (reinterpret_cast<uintptr_t>(Xc[j]) & 15) == 0;
     }
     if (vec) {
-      const int nq = pw >> 2;
+      const int nq = pw >> 2, n = rr.n * nq;
       Walk2 wk(threadIdx.x, nq);
-      for (int q = threadIdx.x; q < rr.n * nq; q += SP_BLOCK, wk.next()) {
-        const size_t o = (size_t)(rr.lo + wk.r) * Wc + xa + 4 * wk.c;
+      for (int q0 = 0; q0 + (int)threadIdx.x < n; q0 += SP_BLOCK, wk.next()) {
+        const uint32_t ob = ((uint32_t)(rr.lo + wk.r) * Wc + (uint32_t)(xa + 4 * wk.c)) * 4u;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) lds_load4(xbase + j * xstride + 4 * q, Xc[j] + o);
+        for (int j = 0; j < NC; ++j) lds_load4_u(xbase + j * xstride + 4 * (q0 + wf), Xc[j], ob);
       }
     } else {
+      const int n = rr.n * pw;
       Walk2 wk(threadIdx.x, pw);
-      for (int i = threadIdx.x; i < rr.n * pw; i += SP_BLOCK, wk.next()) {
-        const size_t o = (size_t)(rr.lo + wk.r) * Wc + min(xa + wk.c, Wc - 1);
+      for (int i0 = 0; i0 + (int)threadIdx.x < n; i0 += SP_BLOCK, wk.next()) {
+        const uint32_t ob = ((uint32_t)(rr.lo + wk.r) * Wc + (uint32_t)min(xa + wk.c, (int)Wc - 1)) * 4u;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) lds_load(xbase + j * xstride + i, Xc[j] + o);
+        for (int j = 0; j < NC; ++j) lds_load_u(xbase + j * xstride + i0 + wf, Xc[j], ob);
       }
     }
   };
@@ -1541,14 +1562,14 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
       const Range rr = (r == 0) ? rg0 : rg1, cc = (r == 0) ? cg0 : cg1;
       const Foot f = footprint(rr.lo, rr.n, cc.lo, cc.n, d, sd.Hl[s], Ws);
       const int cap = csapply_foot_cap(r, d);
-      const float* Xs[NC];
+      gp<const float> Xs[NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) Xs[j] = chan_ptr(sd, ckpt, k0 + j, s);
+      for (int j = 0; j < NC; ++j) Xs[j] = G(chan_ptr(sd, ckpt, k0 + j, s));
       Walk2 wk(threadIdx.x, f.w);
-      for (int i = threadIdx.x; i < f.h * f.w; i += SP_BLOCK, wk.next()) {
-        const size_t o = (size_t)(f.y0 + wk.r) * Ws + f.x0 + wk.c;
+      for (int i0 = 0; i0 + (int)threadIdx.x < f.h * f.w; i0 += SP_BLOCK, wk.next()) {
+        const uint32_t ob = ((uint32_t)(f.y0 + wk.r) * (uint32_t)Ws + (uint32_t)(f.x0 + wk.c)) * 4u;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) lds_load(fb + j * cap + i, Xs[j] + o);
+        for (int j = 0; j < NC; ++j) lds_load_u(fb + j * cap + i0 + wf, Xs[j], ob);
       }
       fb += NC * cap;
     }
@@ -1941,20 +1962,23 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   if (t > 0) {
     const bool quads = !seg && (W & 3) == 0 && (tw & 3) == 0 && J.x0 >= 4 && J.x0 + tw + 4 <= W &&
                        (reinterpret_cast<uintptr_t>(pprev) & 15) == 0;
+    const gp<const float> gprev = G(pprev);
+    const int wf = wave_first();
     if (quads) {
       const int nq = rs >> 2;
       Walk2 wk(threadIdx.x, nq);
-      for (int q = threadIdx.x; q < (KTR + 4) * nq; q += SP_BLOCK, wk.next())
-        lds_load4(reg + 4 * q, pprev + (size_t)clampi(J.y0 - 2 + wk.r, 0, H - 1) * W + J.x0 - 4 + 4 * wk.c);
+      for (int q0 = 0; q0 + (int)threadIdx.x < (KTR + 4) * nq; q0 += SP_BLOCK, wk.next())
+        lds_load4_u(reg + 4 * (q0 + wf), gprev,
+                    ((uint32_t)clampi(J.y0 - 2 + wk.r, 0, H - 1) * (uint32_t)W + (uint32_t)(J.x0 - 4 + 4 * wk.c)) * 4u);
     } else {
       Walk2 wk(threadIdx.x, rs);
-      for (int i = threadIdx.x; i < (KTR + 4) * rs; i += SP_BLOCK, wk.next()) {
+      for (int i0 = 0; i0 + (int)threadIdx.x < (KTR + 4) * rs; i0 += SP_BLOCK, wk.next()) {
         const int y = clampi(J.y0 - 2 + wk.r, 0, H - 1), x = clampi(J.x0 - 4 + wk.c, 0, W - 1);
-        const size_t o = (size_t)y * W + x;
+        const uint32_t o = (uint32_t)y * (uint32_t)W + (uint32_t)x;
         if (seg)
-          reg[i] = (float)seg[o];
+          reg[i0 + threadIdx.x] = (float)seg[o];
         else
-          lds_load(reg + i, pprev + o);
+          lds_load_u(reg + i0 + wf, gprev, o * 4u);
       }
     }
   }
@@ -1962,12 +1986,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   // stride f.w
   const Foot sf = footprint(J.y0, J.th, J.x0, tw, cm, Hm, Wm);
   {
-    const float* Sg = IOF(S_in);
+    const gp<const float> Sg = G(IOF(S_in));
+    const int wf = wave_first();
     Walk2 wk(threadIdx.x, sf.w);
-    for (int i = threadIdx.x; i < sf.h * sf.w; i += SP_BLOCK, wk.next()) {
-      const int fy = wk.r, fx = wk.c;
-      lds_load(Sl + i, Sg + (size_t)(sf.y0 + fy) * Wm + sf.x0 + fx);
-    }
+    for (int i0 = 0; i0 + (int)threadIdx.x < sf.h * sf.w; i0 += SP_BLOCK, wk.next())
+      lds_load_u(Sl + i0 + wf, Sg, ((uint32_t)(sf.y0 + wk.r) * (uint32_t)Wm + (uint32_t)(sf.x0 + wk.c)) * 4u);
     if ((int)threadIdx.x < J.th) {
       const Tap ty = bilinear_tap(J.y0 + threadIdx.x, cm, Hm);
       rtab[threadIdx.x] = make_int4((ty.i0 - sf.y0) * sf.w - sf.x0, (ty.i1 - sf.y0) * sf.w - sf.x0, __float_as_int(ty.w), 0);
