@@ -397,21 +397,23 @@ __device__ __forceinline__ uint32_t rgb_d2i(uint32_t a, uint32_t b) {
 //
 // Tiles are at most 256 columns wide (starting at multiples of 4) and are split into
 // four bands of rows, one per wavefront.  Lane l owns the four pixels x .. x+3,
-// x = x0 + 4 l, and walks down its band keeping the row below in registers.  When rows
+// x = x0 + 4 l, and holds its band's rows and the row below in registers.  When rows
 // start on 4-byte boundaries (width a multiple of 4, aligned frame), five aligned
 // dwords of a row hold pixels x-1 .. x+4, so each row is read once with no LDS; other
 // frames take a per-pixel byte path.
-__device__ __forceinline__ void rgb_row6(gp<const uint32_t> w, bool left, bool right, uint32_t (&p)[6]) {
-  // w: the dword holding the first byte of pixel x; p[k] = pixel x - 1 + k, zero outside
-  const uint32_t d0 = left ? w[-1] : 0u;
-  const uint32_t d1 = w[0], d2 = w[1], d3 = w[2];
-  const uint32_t d4 = right ? w[3] : 0u;
-  p[0] = d0 >> 8;
-  p[1] = d1 & 0xffffffu;
-  p[2] = __builtin_amdgcn_alignbyte(d2, d1, 3) & 0xffffffu;
-  p[3] = __builtin_amdgcn_alignbyte(d3, d2, 2) & 0xffffffu;
-  p[4] = d3 >> 8;
-  p[5] = d4 & 0xffffffu;
+
+// Pixels x-1 .. x+4 of a row from five aligned dwords: d[1..3] hold the owned pixels
+// x .. x+3 (pixel x starts dword d[1]), d[0] the dword before (pixel x-1 in its top three
+// bytes), d[4] the dword after (pixel x+4 in its low three bytes).  Pixels are zeroed
+// where the flags say they are outside the frame or the rows in use.
+__device__ __forceinline__ void rgb_unpack6(const uint32_t (&d)[5], bool left, bool row, bool right,
+                                            uint32_t (&p)[6]) {
+  p[0] = left ? d[0] >> 8 : 0u;
+  p[1] = row ? d[1] & 0xffffffu : 0u;
+  p[2] = row ? __builtin_amdgcn_alignbyte(d[2], d[1], 3) & 0xffffffu : 0u;
+  p[3] = row ? __builtin_amdgcn_alignbyte(d[3], d[2], 2) & 0xffffffu : 0u;
+  p[4] = row ? d[3] >> 8 : 0u;
+  p[5] = right ? d[4] & 0xffffffu : 0u;
 }
 
 __device__ __forceinline__ uint32_t rgb_at(gp<const uint8_t> rgb, size_t o) {
@@ -446,17 +448,40 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
     if (x < J.x0 + J.tw && ya < yb) {
       const bool left = x > 0, right = x + 4 < W;
       const gp<const uint32_t> fw = (gp<const uint32_t>)(rgb);
-      const int wrow = 3 * W / 4;   // dwords per row
-      uint32_t a[6], b[6];
-      rgb_row6(fw + (size_t)ya * wrow + 3 * (x >> 2), left, right, a);
-      for (int y = ya; y < yb; ++y) {
-        const bool s = want_d2 && y + 1 < H;   // uniform over the wavefront
-        if (s) {
-          rgb_row6(fw + (size_t)(y + 1) * wrow + 3 * (x >> 2), left, right, b);
-        } else {
+      const uint32_t wrow = 3u * (uint32_t)W / 4u;   // dwords per row
+      // the band (at most SP_RGB_TR / 4 rows) and, for the pairs, the row below it: all
+      // rows are loaded before any is used, so the band costs one memory round trip
+      constexpr int RB = SP_RGB_TR / 4;
+      const int nrow = yb - ya + ((want_d2 && yb < H) ? 1 : 0);
+      uint32_t p[RB + 1][6];
+      {
+        // unconditional loads at clamped addresses (rows past the last one used read the
+        // frame's last row, edge dwords read an owned dword), zeroed afterwards
+        uint32_t d[RB + 1][5];
 #pragma unroll
-          for (int k = 0; k < 6; ++k) b[k] = 0u;
+        for (int r = 0; r <= RB; ++r) {
+          const uint32_t o = ((uint32_t)min(ya + r, H - 1) * wrow + 3u * (uint32_t)(x >> 2)) * 4u;
+          const gp<const uint32_t> wr = at_bytes(fw, o);
+          d[r][0] = *at_bytes(fw, left ? o - 4u : o);
+          d[r][1] = wr[0];
+          d[r][2] = wr[1];
+          d[r][3] = wr[2];
+          d[r][4] = *at_bytes(fw, right ? o + 12u : o + 8u);
         }
+        // every loaded dword is used here, so no load is sunk into a later branch
+#pragma unroll
+        for (int r = 0; r <= RB; ++r)
+#pragma unroll
+          for (int k = 0; k < 5; ++k) asm volatile("" : "+v"(d[r][k]));
+#pragma unroll
+        for (int r = 0; r <= RB; ++r) rgb_unpack6(d[r], left && r < nrow, r < nrow, right && r < nrow, p[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (ya + r >= yb) break;   // uniform over the wavefront
+        const uint32_t* a = p[r];
+        const uint32_t* b = p[r + 1];   // zero when row ya + r + 1 is not used
+        const bool s = want_d2 && ya + r + 1 < H;
 #pragma unroll
         for (int k = 1; k <= 4; ++k) mx = max(mx, rgb_sum(a[k]));
         if (want_d2) {
@@ -486,8 +511,6 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
           }
           d2 += nsum - 2u * cross;
         }
-#pragma unroll
-        for (int k = 0; k < 6; ++k) a[k] = b[k];
       }
     }
   } else {
