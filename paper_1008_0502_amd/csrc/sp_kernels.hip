@@ -867,6 +867,15 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
   }
   lds_wait();
   __syncthreads();
+  // tap v of factor f: for a compile-time radius a uniform value of the stream description
+  // (scalar loads, hoisted out of the loops, used directly as multiply-add operands);
+  // otherwise the zero-padded LDS table
+  auto tap = [&](int f, int v) -> float {
+    if constexpr (RC > 0)
+      return sd.gf[f][v];
+    else
+      return taps[f * (2 * SP_MAXR + 1) + v];
+  };
   // vertical pass: the four factors of one (row, column) from one read of its column
   Walk2 wk2(threadIdx.x, RRc);
 #pragma unroll 1
@@ -876,10 +885,10 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
 #pragma unroll
     for (int v = 0; v < NT; ++v) {
       const float iv = Ir[(yy + (RC > 0 ? v : min(v, n - 1))) * RRc + xr];
-      a0 += taps[v] * iv;
-      a1 += taps[(2 * SP_MAXR + 1) + v] * iv;
-      a2 += taps[2 * (2 * SP_MAXR + 1) + v] * iv;
-      a3 += taps[3 * (2 * SP_MAXR + 1) + v] * iv;
+      a0 += tap(0, v) * iv;
+      a1 += tap(1, v) * iv;
+      a2 += tap(2, v) * iv;
+      a3 += tap(3, v) * iv;
     }
     V[(0 * GT + yy) * (GCM + 1) + xr] = a0;
     V[(1 * GT + yy) * (GCM + 1) + xr] = a1;
@@ -887,10 +896,6 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
     V[(3 * GT + yy) * (GCM + 1) + xr] = a3;
   }
   __syncthreads();
-  const float* t0 = taps;
-  const float* t1 = taps + (2 * SP_MAXR + 1);
-  const float* t2 = taps + 2 * (2 * SP_MAXR + 1);
-  const float* t3 = taps + 3 * (2 * SP_MAXR + 1);
   const size_t plane = (size_t)Hs * Ws;
   const gp<float> Go = G(sd.gab[l]);
 #pragma unroll 1
@@ -906,11 +911,11 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
     for (int u = 0; u < NT; ++u) {
       const int uc = RC > 0 ? u : min(u, n - 1);
       const float vg = V0[uc];
-      A += t1[u] * vg;
-      B += t0[u] * vg;
-      C += t0[u] * V1[uc];
-      D += t2[u] * V2[uc];
-      E += t3[u] * V3[uc];
+      A += tap(1, u) * vg;
+      B += tap(0, u) * vg;
+      C += tap(0, u) * V1[uc];
+      D += tap(2, u) * V2[uc];
+      E += tap(3, u) * V3[uc];
     }
     if (yy < J.th && xx < J.tw && y < Hs && x < Ws) {
       const size_t o = (size_t)y * Ws + x;
