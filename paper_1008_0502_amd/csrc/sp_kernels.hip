@@ -930,9 +930,17 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
 // Gabor maps of a whole (small) level held in LDS.
 // Rows [y0, y0 + nr) only: the vertical pass of an output row reads the whole level (in
 // LDS), so a band needs no halo of its own.
-template <int NT>
-__device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V, const float* taps, int R, float c45,
-                          gp<float> out) {
+// SC: the taps are the NT = 2R + 1 leading values of the stream's factor table gf, read as
+// uniform scalars; otherwise the zero-padded LDS table taps.
+template <int NT, bool SC>
+__device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V, const float* taps,
+                          const float (*gf)[2 * SP_MAXR + 1], int R, float c45, gp<float> out) {
+  auto tap = [&](int f, int v) -> float {
+    if constexpr (SC)
+      return gf[f][v];
+    else
+      return taps[f * (2 * SP_MAXR + 1) + v];
+  };
   const int n = nr * w, plane = h * w;
   {
     Walk2 wk(threadIdx.x, w);
@@ -942,10 +950,10 @@ __device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V
 #pragma unroll
       for (int v = 0; v < NT; ++v) {
         const float iv = I[clampi(y + v - R, 0, h - 1) * w + x];
-        a0 += taps[v] * iv;
-        a1 += taps[(2 * SP_MAXR + 1) + v] * iv;
-        a2 += taps[2 * (2 * SP_MAXR + 1) + v] * iv;
-        a3 += taps[3 * (2 * SP_MAXR + 1) + v] * iv;
+        a0 += tap(0, v) * iv;
+        a1 += tap(1, v) * iv;
+        a2 += tap(2, v) * iv;
+        a3 += tap(3, v) * iv;
       }
       V[pix] = a0;
       V[n + pix] = a1;
@@ -954,10 +962,6 @@ __device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V
     }
   }
   __syncthreads();
-  const float* t0 = taps;
-  const float* t1 = taps + (2 * SP_MAXR + 1);
-  const float* t2 = taps + 2 * (2 * SP_MAXR + 1);
-  const float* t3 = taps + 3 * (2 * SP_MAXR + 1);
   Walk2 wk(threadIdx.x, w);
   for (int pix = threadIdx.x; pix < n; pix += SP_BLOCK, wk.next()) {
     const int y = wk.r, x = wk.c;   // y relative to the band
@@ -966,11 +970,11 @@ __device__ void gabor_lds(const float* I, int h, int w, int y0, int nr, float* V
     for (int u = 0; u < NT; ++u) {
       const int o = y * w + clampi(x + u - R, 0, w - 1);
       const float vg = V[o];
-      A += t1[u] * vg;
-      B += t0[u] * vg;
-      C += t0[u] * V[n + o];
-      D += t2[u] * V[2 * n + o];
-      E += t3[u] * V[3 * n + o];
+      A += tap(1, u) * vg;
+      B += tap(0, u) * vg;
+      C += tap(0, u) * V[n + o];
+      D += tap(2, u) * V[2 * n + o];
+      E += tap(3, u) * V[3 * n + o];
     }
     const int go = y0 * w + pix;
     out[go] = A;
@@ -1030,8 +1034,8 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
     }
     __syncthreads();
     if (gab && l + 1 == last)   // its vertical passes go to the buffer of level l, now free
-      gabor_lds<(RC > 0 ? 2 * RC + 1 : 2 * SP_MAXR + 1)>(nxt, nH, nW, J.y0, J.th, cur, taps, R, sd.c45,
-                                                     G(sd.gab[l + 1]));
+      gabor_lds<(RC > 0 ? 2 * RC + 1 : 2 * SP_MAXR + 1), (RC > 0)>(nxt, nH, nW, J.y0, J.th, cur, taps, sd.gf, R,
+                                                               sd.c45, G(sd.gab[l + 1]));
     float* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -1043,7 +1047,7 @@ __device__ void tail_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
 // RC: the Gabor radius the launch is built for (every stream of a launch shares it), or
 // 0 for any radius.  The default radius keeps 8 workgroups per CU.
 template <bool BIG, int RC>
-__global__ __launch_bounds__(SP_BLOCK) __attribute__((amdgpu_waves_per_eu((!BIG && RC > 0) ? 6 : 1))) void k_pyr(
+__global__ __launch_bounds__(SP_BLOCK) void k_pyr(
     const Job* __restrict__ jobs, const StreamDesc* __restrict__ sds, const StepIO* __restrict__ ios, StepIO io0) {
   __shared__ float smem[BIG ? TAIL_LDS : DOWN_LDS];
   const Job J = jobs[blockIdx.x];
