@@ -301,33 +301,50 @@ __device__ NParams make_nparams(float mn, float mx, double sb, int nb, float fla
   return p;
 }
 
-// One wavefront reduces the partials of one map (no workgroup barrier).
-__device__ NParams nparams_wave(const float* parts, int n, int nb, float flat_tol) {
-  float mn = INFINITY, mx = -INFINITY;
-  double sb = 0.0;
+// One wavefront reduces the partials of two maps with the same partial count (no
+// workgroup barrier); both maps' loads are in flight together.  Each lane visits its
+// partials in increasing order and the wavefront reductions are fixed, so every result
+// is reproducible bit for bit.
+__device__ void nparams_wave2(const float* pa, const float* pb, int n, int nb, float flat_tol, NParams* qa,
+                              NParams* qb) {
+  float mna = INFINITY, mxa = -INFINITY, mnb = INFINITY, mxb = -INFINITY;
+  double sa = 0.0, sb = 0.0;
   int i = lane_id();
-  for (; i + 192 < n; i += 256) {   // four partials per lane in flight
-    float a[4][3];
+  for (; i + 64 < n; i += 128) {   // two partials per lane and map in flight
+    float a[2][3], b[2][3];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int f = 0; f < 3; ++f) a[u][f] = parts[3 * (i + 64 * u) + f];
+      for (int f = 0; f < 3; ++f) {
+        a[u][f] = pa[3 * (i + 64 * u) + f];
+        b[u][f] = pb[3 * (i + 64 * u) + f];
+      }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      mn = fminf(mn, a[u][0]);
-      mx = fmaxf(mx, a[u][1]);
-      sb += (double)a[u][2];
+    for (int u = 0; u < 2; ++u) {
+      mna = fminf(mna, a[u][0]);
+      mxa = fmaxf(mxa, a[u][1]);
+      sa += (double)a[u][2];
+      mnb = fminf(mnb, b[u][0]);
+      mxb = fmaxf(mxb, b[u][1]);
+      sb += (double)b[u][2];
     }
   }
-  for (; i < n; i += 64) {
-    mn = fminf(mn, parts[3 * i]);
-    mx = fmaxf(mx, parts[3 * i + 1]);
-    sb += (double)parts[3 * i + 2];
+  if (i < n) {
+    mna = fminf(mna, pa[3 * i]);
+    mxa = fmaxf(mxa, pa[3 * i + 1]);
+    sa += (double)pa[3 * i + 2];
+    mnb = fminf(mnb, pb[3 * i]);
+    mxb = fmaxf(mxb, pb[3 * i + 1]);
+    sb += (double)pb[3 * i + 2];
   }
-  mn = wave_reduce<OpMin>(mn);
-  mx = wave_reduce<OpMax>(mx);
+  mna = wave_reduce<OpMin>(mna);
+  mnb = wave_reduce<OpMin>(mnb);
+  mxa = wave_reduce<OpMax>(mxa);
+  mxb = wave_reduce<OpMax>(mxb);
+  sa = wave_sum_d(sa);
   sb = wave_sum_d(sb);
-  return make_nparams(mn, mx, sb, nb, flat_tol);
+  *qa = make_nparams(mna, mxa, sa, nb, flat_tol);
+  *qb = make_nparams(mnb, mxb, sb, nb, flat_tol);
 }
 
 __device__ __forceinline__ void store_np(float* dst, const NParams& p) {
@@ -1194,9 +1211,14 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csfinal(const Job* __restrict__ jo
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const int p = J.a, c = sd.pc[p], nt = sd.cs_nt[p], nb = nblocks8(sd.Hl[c], sd.Wl[c]);
-  for (int k = wave_id(); k < SP_NCH; k += 4) {
-    const NParams q = nparams_wave(sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)k * nt), nt, nb, sd.flat_tol);
-    if (lane_id() == 0) store_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k), q);
+  static_assert(SP_NCH == 8, "two maps per wavefront");
+  const int k = wave_id();
+  NParams qa, qb;
+  nparams_wave2(sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)k * nt),
+                sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)(k + 4) * nt), nt, nb, sd.flat_tol, &qa, &qb);
+  if (lane_id() == 0) {
+    store_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k), qa);
+    store_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k + 4), qb);
   }
 }
 
@@ -1887,10 +1909,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csmix(const Job* __restrict__ jobs
 __device__ void consp_nparams(const StreamDesc& sd, NParams* np) {
   const int cm = sd.c_max;
   const int nb = nblocks8(sd.Hl[cm], sd.Wl[cm]);
-  for (int k = wave_id(); k < SP_NCH; k += 4) {
-    const NParams q = nparams_wave(sd.fbar_part + 3 * (size_t)k * sd.n_cmax_tiles, sd.n_cmax_tiles, nb,
-                                   sd.flat_tol);
-    if (lane_id() == 0) np[k] = q;
+  const int k = wave_id(), nt = sd.n_cmax_tiles;
+  NParams qa, qb;
+  nparams_wave2(sd.fbar_part + 3 * (size_t)k * nt, sd.fbar_part + 3 * (size_t)(k + 4) * nt, nt, nb, sd.flat_tol,
+                &qa, &qb);
+  if (lane_id() == 0) {
+    np[k] = qa;
+    np[k + 4] = qb;
   }
   __syncthreads();
 }
