@@ -305,8 +305,9 @@ __device__ NParams make_nparams(float mn, float mx, double sb, int nb, float fla
 // workgroup barrier); both maps' loads are in flight together.  Each lane visits its
 // partials in increasing order and the wavefront reductions are fixed, so every result
 // is reproducible bit for bit.
-__device__ void nparams_wave2(const float* pa, const float* pb, int n, int nb, float flat_tol, NParams* qa,
+__device__ void nparams_wave2(const float* pa_, const float* pb_, int n, int nb, float flat_tol, NParams* qa,
                               NParams* qb) {
+  const gp<const float> pa = G(pa_), pb = G(pb_);
   float mna = INFINITY, mxa = -INFINITY, mnb = INFINITY, mxb = -INFINITY;
   double sa = 0.0, sb = 0.0;
   int i = lane_id();
@@ -347,14 +348,14 @@ __device__ void nparams_wave2(const float* pa, const float* pb, int n, int nb, f
   *qb = make_nparams(mnb, mxb, sb, nb, flat_tol);
 }
 
-__device__ __forceinline__ void store_np(float* dst, const NParams& p) {
+__device__ __forceinline__ void store_np(gp<float> dst, const NParams& p) {
   dst[0] = p.mn;
   dst[1] = p.inv;
   dst[2] = p.scale;
   dst[3] = p.flat ? 1.f : 0.f;
 }
 
-__device__ __forceinline__ NParams load_np(const float* src) {
+__device__ __forceinline__ NParams load_np(gp<const float> src) {
   NParams p;
   p.mn = src[0];
   p.inv = src[1];
@@ -370,14 +371,25 @@ __device__ __forceinline__ float napply(const NParams& p, float v) {
 __device__ __forceinline__ int nblocks8(int h, int w) { return ((h + 7) >> 3) * ((w + 7) >> 3); }
 
 // Max of S with its first row-major index, from (max, index) partials.
-__device__ void smax_from_parts(const float* parts, int n, float* m_out, int* idx_out, float* sh4, int* shi4) {
-  float m = -INFINITY;
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK) m = fmaxf(m, parts[2 * i]);
-  m = block_reduce<OpMax>(m, sh4);
-  int idx = 0x7fffffff;
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK)
-    if (parts[2 * i] == m) idx = min(idx, __float_as_int(parts[2 * i + 1]));
-  idx = wave_min_i(idx);
+__device__ void smax_from_parts(const float* parts_, int n, float* m_out, int* idx_out, float* sh4, int* shi4) {
+  // one pass over the partials: each thread keeps its largest value and the smallest
+  // index among its partials holding that value; the block's first argmax is then the
+  // smallest index among the threads whose largest value is the block maximum
+  const gp<const float> parts = G(parts_);
+  float ml = -INFINITY;
+  int il = 0x7fffffff;
+  for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
+    const float v = parts[2 * i];
+    const int id = __float_as_int(parts[2 * i + 1]);
+    if (v > ml) {
+      ml = v;
+      il = id;
+    } else if (v == ml) {
+      il = min(il, id);
+    }
+  }
+  const float m = block_reduce<OpMax>(ml, sh4);
+  int idx = wave_min_i(ml == m ? il : 0x7fffffff);
   __syncthreads();
   if (lane_id() == 0) shi4[wave_id()] = idx;
   __syncthreads();
@@ -575,7 +587,7 @@ __device__ __forceinline__ void down_rows(float (*F)[RH][RW], float (*Hb)[RH][TW
 
 __device__ __forceinline__ float beta_from_parts(const StreamDesc& sd, unsigned long long* sh) {
   unsigned long long s = 0;
-  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) s += sd.rgb_d2_part[i];
+  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) s += G((const unsigned long long*)sd.rgb_d2_part)[i];
   s = block_sum_u64(s, sh);
   const int H = sd.H, W = sd.W;
   const unsigned long long cnt = (unsigned long long)H * (W - 1) + (unsigned long long)(H - 1) * W +
@@ -684,7 +696,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
   }
   // largest R+G+B of the frame, from the colour-statistics partials
   uint32_t smax = 0;
-  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) smax = max(smax, sd.rgb_max_part[i]);
+  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) smax = max(smax, G((const uint32_t*)sd.rgb_max_part)[i]);
   smax = wave_max_u(smax);
   if (lane_id() == 0) shm[wave_id()] = smax;
   __syncthreads();
@@ -1217,8 +1229,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csfinal(const Job* __restrict__ jo
   nparams_wave2(sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)k * nt),
                 sd.cs_part + 3 * ((size_t)sd.cs_off[p] + (size_t)(k + 4) * nt), nt, nb, sd.flat_tol, &qa, &qb);
   if (lane_id() == 0) {
-    store_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k), qa);
-    store_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k + 4), qb);
+    store_np(G(sd.cs_np) + 4 * ((size_t)p * SP_NCH + k), qa);
+    store_np(G(sd.cs_np) + 4 * ((size_t)p * SP_NCH + k + 4), qb);
   }
 }
 
@@ -1344,7 +1356,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csapply(const Job* __restrict__ jo
       P.Ws = sd.Wl[s];
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        const NParams np = load_np(sd.cs_np + 4 * ((size_t)p * SP_NCH + k0 + j));
+        const NParams np = load_np(G((const float*)sd.cs_np) + 4 * ((size_t)p * SP_NCH + k0 + j));
         cnp[r][q][j][0] = np.mn;
         cnp[r][q][j][1] = np.flat ? 0.f : np.inv;
         cnp[r][q][j][2] = np.flat ? 0.f : np.scale;
@@ -1858,30 +1870,48 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csmix(const Job* __restrict__ jobs
   const StreamDesc& sd = sds[J.stream];
   const int cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const size_t plane = (size_t)Hm * Wm;
-  for (int i = threadIdx.x; i < sd.n_pairs * SP_NCH; i += SP_BLOCK) {
-    const NParams q = load_np(sd.cs_np + 4 * (size_t)i);
-    (&nps[0][0][0])[3 * i] = q.mn;
-    (&nps[0][0][0])[3 * i + 1] = q.flat ? 0.f : q.inv;
-    (&nps[0][0][0])[3 * i + 2] = q.flat ? 0.f : q.scale;
-  }
   const int lane = lane_id(), w = wave_id();
   const int by = w >> 1, bx = w & 1;
   const int yy = 8 * by + (lane >> 3), xx = 8 * bx + (lane & 7);
   const bool bvalid = 8 * by < J.th && 8 * bx < J.tw;
   const bool valid = yy < J.th && xx < J.tw;
-  const size_t o = (size_t)(J.y0 + min(yy, J.th - 1)) * Wm + J.x0 + min(xx, J.tw - 1);
-  const gp<const float> gmap = G((const float*)sd.gmap);
+  const uint32_t ob = ((uint32_t)(J.y0 + min(yy, J.th - 1)) * (uint32_t)Wm + (uint32_t)(J.x0 + min(xx, J.tw - 1))) * 4u;
+  const size_t o = ob / 4u;
+  // the maps of PG pairs are loaded together, the first group before the N parameters
+  // are staged; pairs are added in increasing order
+  constexpr int PG = 4;
+  const int np = sd.n_pairs;
+  float g[PG][SP_NCH];
+  auto load_group = [&](int p0) {
+#pragma unroll
+    for (int u = 0; u < PG; ++u) {
+      const int p = max(min(p0 + u, np - 1), 0);   // past the last pair: loaded again, not added
+#pragma unroll
+      for (int k = 0; k < SP_NCH; ++k) g[u][k] = *at_bytes(G(sd.gmap + ((size_t)p * SP_NCH + k) * plane), ob);
+    }
+  };
+  load_group(0);
+  for (int i = threadIdx.x; i < np * SP_NCH; i += SP_BLOCK) {
+    const NParams q = load_np(G((const float*)sd.cs_np) + 4 * (size_t)i);
+    (&nps[0][0][0])[3 * i] = q.mn;
+    (&nps[0][0][0])[3 * i + 1] = q.flat ? 0.f : q.inv;
+    (&nps[0][0][0])[3 * i + 2] = q.flat ? 0.f : q.scale;
+  }
   __syncthreads();
   float acc[SP_NCH];
 #pragma unroll
   for (int k = 0; k < SP_NCH; ++k) acc[k] = 0.f;
-  for (int p = 0; p < sd.n_pairs; ++p) {
-    float g[SP_NCH];
+  for (int p0 = 0; p0 < np; p0 += PG) {
+    if (p0 > 0) load_group(p0);
 #pragma unroll
-    for (int k = 0; k < SP_NCH; ++k) g[k] = gmap[((size_t)p * SP_NCH + k) * plane + o];
+    for (int u = 0; u < PG; ++u) {
+      const int p = p0 + u;
+      if (p < np) {
 #pragma unroll
-    for (int k = 0; k < SP_NCH; ++k)
-      acc[k] = fmaf((g[k] - nps[p][k][0]) * nps[p][k][1], nps[p][k][2], acc[k]);
+        for (int k = 0; k < SP_NCH; ++k)
+          acc[k] = fmaf((g[u][k] - nps[p][k][0]) * nps[p][k][1], nps[p][k][2], acc[k]);
+      }
+    }
   }
   const gp<float> fbar = G(sd.fbar);
 #pragma unroll
@@ -1921,7 +1951,7 @@ __device__ void consp_nparams(const StreamDesc& sd, NParams* np) {
 }
 
 // Block max of S over the tile with the first row-major argmax -> partial slot.
-__device__ void smax_partial(float v, int idx, bool valid, float* out, float* sh4, int* shi4) {
+__device__ void smax_partial(float v, int idx, bool valid, gp<float> out, float* sh4, int* shi4) {
   const float m = block_reduce<OpMax>(valid ? v : -INFINITY, sh4);
   int cand = (valid && v == m) ? idx : 0x7fffffff;
   cand = wave_min_i(cand);
@@ -1965,7 +1995,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_consp(const Job* __restrict__ jobs
     S_out[o] = S;
     if (S_tape) S_tape[o] = S;
   }
-  smax_partial(S, (int)o, valid, sd.s_part + 2 * (size_t)J.tid, sh4, shi4);
+  smax_partial(S, (int)o, valid, G(sd.s_part) + 2 * (size_t)J.tid, sh4, shi4);
 }
 
 __global__ __launch_bounds__(SP_BLOCK) void k_smax(const Job* __restrict__ jobs,
@@ -1981,7 +2011,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_smax(const Job* __restrict__ jobs,
   const int y = J.y0 + yy, x = J.x0 + xx;
   const bool valid = yy < J.th && xx < J.tw;
   const size_t o = (size_t)min(y, Hm - 1) * Wm + min(x, Wm - 1);
-  smax_partial(S_in[o], (int)o, valid, sd.s_part + 2 * (size_t)J.tid, sh4, shi4);
+  smax_partial(S_in[o], (int)o, valid, G(sd.s_part) + 2 * (size_t)J.tid, sh4, shi4);
 }
 
 // ---------------------------------------------------------------- Kalman prior update
