@@ -585,15 +585,24 @@ __device__ __forceinline__ void down_rows(float (*F)[RH][RW], float (*Hb)[RH][TW
   }
 }
 
-__device__ __forceinline__ float beta_from_parts(const StreamDesc& sd, unsigned long long* sh) {
-  unsigned long long s = 0;
-  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) s += G((const unsigned long long*)sd.rgb_d2_part)[i];
-  s = block_sum_u64(s, sh);
+// beta from this thread's share of the squared-distance partials (the block sums them;
+// integers, so the result does not depend on the order)
+__device__ __forceinline__ float beta_from_share(const StreamDesc& sd, unsigned long long share,
+                                                 unsigned long long* sh) {
+  const unsigned long long s = block_sum_u64(share, sh);
   const int H = sd.H, W = sd.W;
   const unsigned long long cnt = (unsigned long long)H * (W - 1) + (unsigned long long)(H - 1) * W +
                                  2ull * (unsigned long long)(H - 1) * (W - 1);
   const double mean = cnt ? (double)s / (double)cnt : 0.0;
   return (mean > 0.0) ? (float)(1.0 / (2.0 * mean)) : 0.f;
+}
+__device__ __forceinline__ unsigned long long d2_share(const StreamDesc& sd) {
+  unsigned long long s = 0;
+  for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) s += G((const unsigned long long*)sd.rgb_d2_part)[i];
+  return s;
+}
+__device__ __forceinline__ float beta_from_parts(const StreamDesc& sd, unsigned long long* sh) {
+  return beta_from_share(sd, d2_share(sd), sh);
 }
 
 // One contrast-sensitive capacity: Potts constant plus the colour term over the
@@ -694,9 +703,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
       for (int u = 0; u < NP; ++u) pv[u] = (uint32_t)gprev[o[u]] + (uint32_t)gprev[o[u] + 1] + (uint32_t)gprev[o[u] + 2];
     }
   }
-  // largest R+G+B of the frame, from the colour-statistics partials
+  // largest R+G+B of the frame, from the colour-statistics partials; the squared-distance
+  // partials for beta are read in the same round trip
   uint32_t smax = 0;
   for (int i = threadIdx.x; i < sd.n_rgb; i += SP_BLOCK) smax = max(smax, G((const uint32_t*)sd.rgb_max_part)[i]);
+  const unsigned long long d2s = pairw ? d2_share(sd) : 0ull;
   smax = wave_max_u(smax);
   if (lane_id() == 0) shm[wave_id()] = smax;
   __syncthreads();
@@ -708,7 +719,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
     const int S8 = (int)rgb_sum(cv[u]);
     const float I = (float)S8 * (1.f / 765.f);
     float rg = 0.f, by = 0.f;
-    if ((uint32_t)(10 * S8) > smax) {
+    if (__umul24((uint32_t)S8, 10u) > smax) {   // S8 <= 765: a 24-bit multiply is exact
       const float inv = 3.f * __builtin_amdgcn_rcpf((float)S8);
       const float rp = (float)R8 * inv, gp = (float)G8 * inv, bp = (float)B8 * inv;
       const float Rc = fmaxf(0.f, rp - (gp + bp) * 0.5f);
@@ -745,7 +756,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
     }
     if (pairw) {
       if (h == 0)
-        beta = beta_from_parts(sd, sh);   // synchronises the block before and after its reduction
+        beta = beta_from_share(sd, d2s, sh);   // synchronises the block before and after its reduction
       else
         __syncthreads();
       // level-0 rows of this half: 2*y0 + r0 .. +TH-1 (region rows r0+2 .. r0+TH+1)
@@ -755,12 +766,17 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
       const size_t plane = (size_t)H * W;
       const gp<float> pw0 = pairw, pw1 = pairw + plane, pw2 = pairw + 2 * plane, pw3 = pairw + 3 * plane;
       const CapK ck = cap_consts(beta, sd.lam, sd.potts);
+      // the walk also advances the row's byte offset in the output planes and its index in
+      // the staged region, so a pixel costs no multiply
       Walk2 wk(threadIdx.x, cw);
-      for (int i = threadIdx.x; i < n; i += SP_BLOCK, wk.next()) {
+      uint32_t orow = (uint32_t)(ylo + wk.r) * (uint32_t)W * 4u;
+      int rrow = (ylo + wk.r - Y0 - r0) * RW;
+      const uint32_t ostep = (uint32_t)wk.dr * (uint32_t)W * 4u;
+      for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
         const int y = ylo + wk.r, x = xlo + wk.c;
-        const int r = (y - Y0 - r0) * RW + (x - X0);
+        const int r = rrow + (x - X0);
         const uint32_t c0 = Pk[r];
-        const uint32_t ob = ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 4u;
+        const uint32_t ob = orow + (uint32_t)x * 4u;
         const bool e = x + 1 < W, s = y + 1 < H;
         // the staged region holds every neighbour (clamped at the frame edge), so all
         // four capacities are computed and the ones that leave the frame are zeroed
@@ -772,6 +788,16 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
         st_stream(at_bytes(pw1, ob), s ? cS : 0.f);
         st_stream(at_bytes(pw2, ob), (s && e) ? cSE : 0.f);
         st_stream(at_bytes(pw3, ob), (s && x > 0) ? cSW : 0.f);
+        wk.r += wk.dr;
+        wk.c += wk.dc;
+        orow += ostep;
+        rrow += wk.dr * RW;
+        if (wk.c >= wk.w) {
+          wk.c -= wk.w;
+          ++wk.r;
+          orow += (uint32_t)W * 4u;
+          rrow += RW;
+        }
       }
       if (h == 0 && J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) G(IOF(beta_out))[0] = beta;
     }
