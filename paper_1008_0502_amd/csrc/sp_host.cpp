@@ -264,9 +264,9 @@ void pyramid_stages(const Geo& g, int s, int lo, std::vector<std::vector<Job>>& 
   mid.clear();
   fin.clear();
   for (int j = lo; j < L0; ++j) {
-    std::vector<Job> v;
-    add_tiles(v, s, j, g.Hl[j + 1], g.Wl[j + 1], JOB_DOWN);
+    std::vector<Job> v;   // Gabor tiles (the longer jobs) first, then the next level's tiles
     if (g.used & (1u << j)) add_tiles_wh(v, s, j, g.Hl[j], g.Wl[j], 16, 32, JOB_GABOR);
+    add_tiles(v, s, j, g.Hl[j + 1], g.Wl[j + 1], JOB_DOWN);
     mid.push_back(std::move(v));
   }
   *big = L0 < g.top;
@@ -1385,8 +1385,16 @@ int batch_build_tables(sp_batch* b) {
   };
   b->phases.push_back(b->jobs.add(JOB_RGB, b->mrf ? 1 : 0, order(rgb), n));
   b->phases.push_back(b->jobs.add(JOB_FEAT, 0, order(feat), n));
-  for (auto& d : mids)
-    if (!d.empty()) b->phases.push_back(b->jobs.add(JOB_DOWN, b->p.gabor_radius, order(d), n));
+  for (auto& d : mids) {
+    if (d.empty()) continue;
+    // every stream's Gabor tiles (the longer jobs) before the next level's tiles, each
+    // group in its own XCD order
+    std::vector<Job> gab, down;
+    for (const Job& jb : d) (jb.kind == JOB_GABOR ? gab : down).push_back(jb);
+    std::vector<Job> all = order(gab), rest = order(down);
+    all.insert(all.end(), rest.begin(), rest.end());
+    b->phases.push_back(b->jobs.add(JOB_DOWN, b->p.gabor_radius, all, n));
+  }
   if (!fin.empty()) b->phases.push_back(b->jobs.add(any_big ? JOB_TAIL : JOB_DOWN, b->p.gabor_radius, fin, n));
   size_t lds_a = 0, lds_g = 0;
   for (const Geo& g : b->geo) {
