@@ -689,18 +689,22 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
   const gbytes gprev = (gbytes)prev;
   uint32_t cv[NP], pv[NP];
   {
-    size_t o[NP];
+    uint32_t o[NP];   // byte offsets: frames hold at most 2^28 pixels
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
       const int i = min((int)threadIdx.x + u * SP_BLOCK, RH * RW - 1);
       const int ry = i / RW, rx = i - ry * RW;
       const int y = clampi(Y0 + ry, 0, H - 1), x = clampi(X0 + rx, 0, W - 1);
-      o[u] = ((size_t)y * W + x) * 3;
-      cv[u] = (uint32_t)grgb[o[u]] | ((uint32_t)grgb[o[u] + 1] << 8) | ((uint32_t)grgb[o[u] + 2] << 16);
+      o[u] = ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 3u;
+      const gbytes c = at_bytes(grgb, o[u]);
+      cv[u] = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
     }
     if (prev) {
 #pragma unroll
-      for (int u = 0; u < NP; ++u) pv[u] = (uint32_t)gprev[o[u]] + (uint32_t)gprev[o[u] + 1] + (uint32_t)gprev[o[u] + 2];
+      for (int u = 0; u < NP; ++u) {
+        const gbytes c = at_bytes(gprev, o[u]);
+        pv[u] = (uint32_t)c[0] + (uint32_t)c[1] + (uint32_t)c[2];
+      }
     }
   }
   // largest R+G+B of the frame, from the colour-statistics partials; the squared-distance
