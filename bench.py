@@ -182,8 +182,9 @@ def pmc_summarize(fetch_db: str, write_db: str) -> None:
     print(json.dumps(out, indent=1))
 
 
-def roofline_of(prof, bytes_per_step, n_steps):
-    """Roofline record of the kernel with the largest device time per step."""
+def roofline_of(prof, bytes_per_step, n_steps, counters=True):
+    """Roofline record of the kernel with the largest device time per step.  The counter
+    traffic (taken on the batched workload) is attached only when counters is set."""
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
     ms, cnt = prof[dom]
     avg_s = ms / cnt * 1e-3
@@ -191,7 +192,7 @@ def roofline_of(prof, bytes_per_step, n_steps):
     achieved = per_launch / avg_s / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic_batched16_640x480.json")
-    if os.path.exists(tfile):
+    if counters and os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
             if tj.get("source_hash") == source_hash() and dom in tj.get("kernels", {}):
@@ -289,7 +290,8 @@ def main():
             for name, (ms, cnt) in prof.items():
                 kernels[name] = {"avg_us": round(ms / cnt * 1e3, 3), "launches_per_step": cnt / nprof,
                                  "us_per_step": round(ms / nprof * 1e3, 3),
-                                 "alg_GBps": round(bytes_step.get(name, float("nan")) / (ms / nprof * 1e-3) / 1e9, 2)}
+                                 "alg_GBps": (round(bytes_step[name] / (ms / nprof * 1e-3) / 1e9, 2)
+                                              if name in bytes_step else None)}
             roof = roofline_of(prof, bytes_step, nprof)
         bt.close()
 
@@ -342,7 +344,7 @@ def main():
             profile_enable(ctx, False)
             plain["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 3) for k, v in pr.items()}
             pb = alg_bytes_per_stream(g, mrf=True, prior_copy=True)
-            plain["roofline"] = roofline_of(pr, pb, 100)
+            plain["roofline"] = roofline_of(pr, pb, 100, counters=False)
         ctx.close()
         log(f"plain: {plain['frames_per_s']} frames/s")
 
