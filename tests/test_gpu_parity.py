@@ -100,6 +100,19 @@ def test_three_ellipse_clip_320x240_with_mrf():
     check_mrf(gpu, frames, pp, label="320x240")
 
 
+def test_eight_pairs_reduced_map_path():
+    # every centre within one level of c_max, so the reduced-map kernels run with a pair set
+    # read at run time, and the across-scale mix loads its maps in two groups of four
+    banner("320x240, centres {1,2}, surround +{1,2,3,4}: eight pairs; 3 frames")
+    clip = synth.Clip(synth.three_ellipse_spec(T=3, seed=5))
+    frames, _ = clip.stack()
+    pp = params(depth=6, centers=(1, 2), deltas=(1, 2, 3, 4))
+    assert len(O.geometry(240, 320, oracle_params(pp)).pairs) == 8
+    gpu, ref = run_both(frames, pp, with_mrf=True)
+    check_clip(gpu, ref, frames, pp, label="8 pairs")
+    check_mrf(gpu, frames, pp, label="8 pairs")
+
+
 def test_640x480_sampled_frames():
     banner("640x480, first 3 frames (bench frame size)")
     clip = synth.Clip(synth.single_ellipse_spec(H=480, W=640, T=3, seed=2))
