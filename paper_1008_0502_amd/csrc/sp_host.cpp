@@ -1375,14 +1375,19 @@ int batch_build_tables(sp_batch* b) {
     add_tiles(cons, i, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
     add_tiles_wh(kal, i, 0, g.H, g.W, SP_KAL_ROWS, b->tune[i].kalman_tw, JOB_KALMAN);
   }
-  // tail jobs first in the final pyramid launch: they are the longest workgroups
-  std::stable_sort(fin.begin(), fin.end(), [](const Job& a, const Job& c) {
-    return (a.kind == JOB_TAIL || a.kind == JOB_TAILGAB) > (c.kind == JOB_TAIL || c.kind == JOB_TAILGAB);
-  });
   auto order = [&](std::vector<Job> v) {
     if (b->xcd) xcd_order(v);
     return v;
   };
+  // tail jobs first in the final pyramid launch (they are the longest workgroups), each
+  // group in its own XCD order so a stream's jobs stay on the XCD that produced its levels
+  {
+    std::vector<Job> tails, rest;
+    for (const Job& jb : fin) (jb.kind == JOB_TAIL || jb.kind == JOB_TAILGAB ? tails : rest).push_back(jb);
+    fin = order(tails);
+    rest = order(rest);
+    fin.insert(fin.end(), rest.begin(), rest.end());
+  }
   b->phases.push_back(b->jobs.add(JOB_RGB, b->mrf ? 1 : 0, order(rgb), n));
   b->phases.push_back(b->jobs.add(JOB_FEAT, 0, order(feat), n));
   for (auto& d : mids) {
@@ -1413,7 +1418,7 @@ int batch_build_tables(sp_batch* b) {
     b->phases.push_back(b->jobs.add(JOB_CSG, nc | (set << 8), order(csg), n));
     b->phases.back().lds = nc * lds_g;
   }
-  b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, n));
+  b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, order(csf), n));
   if (!csa.empty()) {
     b->phases.push_back(b->jobs.add(JOB_CSAPPLY, nc, order(csa), n));
     b->phases.back().lds = nc * lds_a;
