@@ -866,25 +866,27 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
   }
   lds_wait();
   __syncthreads();
-  // row pass of each channel into registers, then into the start of that channel's own
-  // staged region (no longer read): the launch keeps 8 workgroups per CU
+  // row pass of every channel into registers, then (after one barrier) into the start of
+  // that channel's own staged region, no longer read: the launch keeps 8 workgroups per CU
   constexpr int NH = (DR * DT + SP_BLOCK - 1) / SP_BLOCK;
-  for (int c = 0; c < 4; ++c) {
-    float hv[NH];
+  float hv[4][NH];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int k = 0; k < NH; ++k) {
       const int i = threadIdx.x + k * SP_BLOCK;
       const int r = min(i / DT, DR - 1), j = i % DT;
       const float* row = F + (c * DR + r) * DR + 2 * j;
-      hv[k] = kB0 * row[0] + kB1 * row[1] + kB2 * row[2] + kB1 * row[3] + kB0 * row[4];
+      hv[c][k] = kB0 * row[0] + kB1 * row[1] + kB2 * row[2] + kB1 * row[3] + kB0 * row[4];
     }
-    __syncthreads();
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int k = 0; k < NH; ++k) {
       const int i = threadIdx.x + k * SP_BLOCK;
-      if (i < DR * DT) F[c * DR * DR + i] = hv[k];
+      if (i < DR * DT) F[c * DR * DR + i] = hv[c][k];
     }
-  }
   __syncthreads();
   const float* Hb = F;   // channel c's row pass at c * DR * DR, [DR][DT]
   const int Hd = sd.Hl[l + 1], Wd = sd.Wl[l + 1];
