@@ -899,7 +899,7 @@ __device__ void down_job(const Job& J, const StreamDesc& sd, float* ckpt, float*
     for (int c = 0; c < 4; ++c) {
       const float* col = Hb + c * DR * DR + 2 * yy * DT + xx;
       const float v = kB0 * col[0] + kB1 * col[DT] + kB2 * col[2 * DT] + kB1 * col[3 * DT] + kB0 * col[4 * DT];
-      dst[c * plane + (size_t)y * Wd + x] = v;
+      *at_bytes(dst + c * plane, ((uint32_t)y * (uint32_t)Wd + (uint32_t)x) * 4u) = v;
     }
   }
 }
@@ -979,11 +979,11 @@ __device__ void gabor_job(const Job& J, const StreamDesc& sd, const float* ckpt,
       E += tap(3, u) * V3[uc];
     }
     if (yy < J.th && xx < J.tw && y < Hs && x < Ws) {
-      const size_t o = (size_t)y * Ws + x;
-      Go[o] = A;
-      Go[plane + o] = D - E - sd.c45 * B;
-      Go[2 * plane + o] = C;
-      Go[3 * plane + o] = D + E - sd.c45 * B;
+      const uint32_t ob = ((uint32_t)y * (uint32_t)Ws + (uint32_t)x) * 4u;
+      *at_bytes(Go, ob) = A;
+      *at_bytes(Go + plane, ob) = D - E - sd.c45 * B;
+      *at_bytes(Go + 2 * plane, ob) = C;
+      *at_bytes(Go + 3 * plane, ob) = D + E - sd.c45 * B;
     }
   }
 }
@@ -2012,15 +2012,16 @@ __global__ __launch_bounds__(SP_BLOCK) void k_consp(const Job* __restrict__ jobs
   const int y = J.y0 + yy, x = J.x0 + xx;
   const bool valid = yy < J.th && xx < J.tw;
   const size_t o = (size_t)min(y, Hm - 1) * Wm + min(x, Wm - 1);
+  const uint32_t ob = (uint32_t)o * 4u;
   float fv[SP_NCH];
 #pragma unroll
-  for (int k = 0; k < SP_NCH; ++k) fv[k] = G(sd.fbar)[k * plane + o];
+  for (int k = 0; k < SP_NCH; ++k) fv[k] = *at_bytes(G((const float*)sd.fbar) + k * plane, ob);
   consp_nparams(sd, np);
   float S = 0.f;
 #pragma unroll
   for (int k = 0; k < SP_NCH; ++k) {
     const float Ck = napply(np[k], fv[k]);
-    if (valid && C_out) C_out[k * plane + o] = Ck;
+    if (valid && C_out) *at_bytes(C_out + k * plane, ob) = Ck;
     S += sd.w[k] * Ck;
   }
   if (valid) {
