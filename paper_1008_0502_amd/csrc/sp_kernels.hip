@@ -2059,7 +2059,6 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
                                                      const StepIO* __restrict__ ios, StepIO io0) {
   __shared__ __align__(16) float reg[(KTR + 4) * (KTW_MAX + 8)];   // flat, row stride rs
   __shared__ float Sl[(KTR / 2 + 2) * (KTW_MAX / 2 + 2)];   // footprint of the tile on level c_max >= 1
-  __shared__ float hb[KTR + 4][KTW_MAX];
   __shared__ int4 rtab[KTR];   // per tile row: offsets in Sl of its two footprint rows, weight bits
   __shared__ float sh4[4];
   __shared__ int shi4[4];
@@ -2123,30 +2122,36 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   lds_wait();
   __syncthreads();
   const bool flat = !(m > sd.flat_tol);
-  // threads map to columns modulo cw, the power of two >= tw (it divides the block): each
-  // keeps one column in the row pass below and in the update loop
+  // threads map to columns modulo cw, the power of two >= tw (it divides the block), and
+  // take nr consecutive tile rows from ya: the horizontal pass of the blur for those rows
+  // and the four below stays in registers, so the vertical pass needs no LDS round trip
   const int cw = tw <= 1 ? 1 : 1 << (32 - __clz(tw - 1));
   const int xx = threadIdx.x & (cw - 1);
-  if (t > 0) {
-    if (xx < tw) {
-      for (int r = threadIdx.x / cw; r < KTR + 4; r += SP_BLOCK / cw) {
-        const float* g = reg + r * rs + xx + 2;
-        hb[r][xx] = kB0 * g[0] + kB1 * g[1] + kB2 * g[2] + kB1 * g[3] + kB0 * g[4];
+  constexpr int RPMAX = KTR / (SP_BLOCK / KTW_MAX);   // rows per thread at the widest tile
+  const int ng = SP_BLOCK / cw, rp = (J.th + ng - 1) / ng;   // rp <= RPMAX: cw <= KTW_MAX
+  const int ya = (int)(threadIdx.x / cw) * rp, nr = min(rp, J.th - ya);
+  float hv[RPMAX + 4];
+  if (t > 0 && xx < tw) {
+#pragma unroll
+    for (int k = 0; k < RPMAX + 4; ++k)
+      if (k < nr + 4) {   // region rows ya .. ya + nr + 3 <= th + 3, all staged
+        const float* g = reg + (ya + k) * rs + xx + 2;
+        hv[k] = kB0 * g[0] + kB1 * g[1] + kB2 * g[2] + kB1 * g[3] + kB0 * g[4];
       }
-    }
-    __syncthreads();
   }
   // consecutive lanes take consecutive pixels of a row, so every store of a wavefront
   // covers a contiguous run.  Each thread keeps its column (horizontal tap and border
-  // test) and steps down the rows.
+  // test) and steps down its rows.
   const float eps = sd.eps, rm = flat ? 0.f : 1.f / m;
   const int x = J.x0 + xx;
   const bool xring = x < sd.border || x >= W - sd.border;
   const Tap tx = bilinear_tap(x, cm, Wm);
   const gp<float> unary1p = unary + (size_t)H * W;
-  for (int yy = threadIdx.x / cw; yy < J.th; yy += SP_BLOCK / cw) {
+#pragma unroll
+  for (int k = 0; k < RPMAX; ++k) {
+    const int yy = ya + k;
     const int y = J.y0 + yy;
-    if (y >= H || xx >= tw || x >= W) continue;
+    if (k >= nr || y >= H || xx >= tw || x >= W) continue;
     const bool ring = xring || y < sd.border || y >= H - sd.border;
     float q = 0.5f;
     if (!flat) {
@@ -2164,8 +2169,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
     float pi = q;
     const uint32_t ob = ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 4u;
     if (t > 0) {
-      const float f = kB0 * hb[yy][xx] + kB1 * hb[yy + 1][xx] + kB2 * hb[yy + 2][xx] + kB1 * hb[yy + 3][xx] +
-                      kB0 * hb[yy + 4][xx];
+      const float f = kB0 * hv[k] + kB1 * hv[k + 1] + kB2 * hv[k + 2] + kB1 * hv[k + 3] + kB0 * hv[k + 4];
       pi = f + K * (q - f);
       if (ftape) *at_bytes(ftape, ob) = f;
     }
