@@ -169,16 +169,12 @@ __device__ unsigned long long block_sum_u64(unsigned long long v, unsigned long 
 // without a wait per element, so a staging loop keeps all its loads in flight.  A loop
 // over a flat index i = threadIdx.x + k * SP_BLOCK passes the lane's own destination
 // (region + i); since i - lane is the same for the whole wavefront, the base is
-// region + i - lane.  The copy is complete after lds_wait() and a barrier.
+// region + i - lane.  The copy is complete after lds_wait() and a barrier.  The 16-byte
+// form (global_load_lds_dwordx4, lane l writing four floats at the base + 16 * l) is used
+// through the wave-uniform helpers below; its source and destination are 16-byte aligned.
 typedef __attribute__((address_space(3))) void lds_void;
 __device__ __forceinline__ void lds_load(float* dst_of_lane, const float* src) {
   __builtin_amdgcn_global_load_lds(src, (lds_void*)(dst_of_lane - lane_id()), 4, 0, 0);
-}
-// The 16-byte form (global_load_lds_dwordx4): lane l writes four floats at the
-// wavefront's base + 16 * l, so a loop over quads q = threadIdx.x + k * SP_BLOCK passes
-// region + 4 * q.  Source and destination must be 16-byte aligned.
-__device__ __forceinline__ void lds_load4(float* dst_of_lane, const float* src) {
-  __builtin_amdgcn_global_load_lds(src, (lds_void*)(dst_of_lane - 4 * lane_id()), 16, 0, 0);
 }
 __device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
