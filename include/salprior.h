@@ -100,7 +100,8 @@ int sp_get_geometry(const sp_ctx* ctx, sp_geometry* out);
 
 /* Replaces the channel weights and the Kalman variances (finite, q >= 0, r >= 0,
  * q + r > 0).  Takes effect from the next call; the gain sequence restarts only on
- * sp_reset. */
+ * sp_reset.  After recorded steps it invalidates the tape (saliency_backward then
+ * fails with SP_ESTATE until sp_reset). */
 int sp_set_weights(sp_ctx* ctx, const float* weights8, double q, double r);
 
 /* Starts a new clip: the next prior_update is step t = 0 (prior = observation) and the
@@ -109,6 +110,13 @@ int sp_reset(sp_ctx* ctx);
 
 /* Step index the next prior_update will run (frames updated since sp_reset). */
 int64_t sp_step_index(const sp_ctx* ctx);
+
+/* Generation of the recorded clip: a counter that sp_reset, sp_set_weights and
+ * sp_set_state each advance (-1 for a NULL context).  A caller that runs the forward
+ * clip, then later the adjoint, compares the value taken after the forward with the
+ * value before the backward: a change means the tape was restarted or no longer
+ * matches the weights and variances it was recorded with. */
+int64_t sp_tape_generation(const sp_ctx* ctx);
 
 /* Saliency map of one frame (Section 3; Section 7.2).
  *   rgb_t    [H][W][3] uint8, frame t.
@@ -177,8 +185,11 @@ int sp_set_state(sp_ctx* ctx, const void* dev_buf, size_t bytes);
  * in a HIP graph and replayed.  Each stream keeps its Kalman state on the device.
  *   H[n], W[n]: host arrays.  p: shared parameters (record_tape must be 0).
  *   flags: SP_BATCH_MRF also computes every stream's MRF capacities each step into
- *   buffers the batch owns (read them with sp_batch_outputs). */
+ *   buffers the batch owns (read them with sp_batch_outputs); see also SP_BATCH_CONSP. */
 #define SP_BATCH_MRF 1
+/* SP_BATCH_CONSP also keeps every stream's 8 conspicuity maps of the last step (read
+ * them with sp_batch_consp). */
+#define SP_BATCH_CONSP 2
 int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32_t* W, int32_t flags,
                     void* hip_stream, sp_batch** out);
 
@@ -196,6 +207,9 @@ int sp_batch_prior(sp_batch* b, int32_t i, const float** prior);
  * output pointer may be NULL; the MRF ones are NULL without SP_BATCH_MRF). */
 int sp_batch_outputs(sp_batch* b, int32_t i, const float** S, const float** unary, const float** pairwise,
                      const float** beta);
+/* Device pointer to stream i's conspicuity maps [8][Hc][Wc] of the last step (NULL
+ * without SP_BATCH_CONSP). */
+int sp_batch_consp(sp_batch* b, int32_t i, const float** C);
 int sp_batch_reset(sp_batch* b);
 int sp_batch_destroy(sp_batch* b);
 
@@ -226,6 +240,18 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
  * resets the context. */
 int sp_autotune(sp_ctx* ctx, const uint8_t* rgb_t, const uint8_t* rgb_prev, int32_t steps, char* report,
                 size_t report_len);
+
+/* Forces the launch shapes the autotuner would otherwise choose: the width (16, 32 or
+ * 64) of the level-0 update tiles, the XCD-aware job order (0/1) and the channels per
+ * across-scale workgroup (1, 2, 4 or 8; rejected when the LDS of that many channels
+ * exceeds the limit for the geometry).  Every choice computes identical results.  The
+ * context form synchronises its stream; the batch form drops the captured graph, which
+ * is captured again at the next step. */
+int sp_set_tune(sp_ctx* ctx, int32_t kalman_tw, int32_t xcd_order, int32_t channels);
+int sp_batch_set_tune(sp_batch* b, int32_t kalman_tw, int32_t xcd_order, int32_t channels);
+/* Forgets every autotuner choice recorded in this process (contexts and batches created
+ * later start from the defaults: tile width 32, no XCD order, 2 channels). */
+int sp_tune_cache_clear(void);
 
 /* Description of the last error on this host thread ("" if none). */
 const char* sp_last_error(void);

@@ -66,6 +66,7 @@ SIGNATURES = [
     ("sp_set_weights", c_int32, [c_void_p, ctypes.POINTER(c_float), c_double, c_double]),
     ("sp_reset", c_int32, [c_void_p]),
     ("sp_step_index", ctypes.c_int64, [c_void_p]),
+    ("sp_tape_generation", ctypes.c_int64, [c_void_p]),
     ("saliency_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("prior_update", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("mrf_weights", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -82,6 +83,7 @@ SIGNATURES = [
     ("sp_batch_prior", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
     ("sp_batch_outputs", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                                    ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    ("sp_batch_consp", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
     ("sp_batch_reset", c_int32, [c_void_p]),
     ("sp_batch_destroy", c_int32, [c_void_p]),
     ("sp_profile_enable", c_int32, [c_void_p, c_int32]),
@@ -90,6 +92,9 @@ SIGNATURES = [
     ("sp_autotune", c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_char_p, c_size_t]),
     ("sp_batch_profile_enable", c_int32, [c_void_p, c_int32]),
     ("sp_batch_profile_read", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_float), ctypes.POINTER(c_int32)]),
+    ("sp_set_tune", c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    ("sp_batch_set_tune", c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    ("sp_tune_cache_clear", c_int32, []),
     ("sp_kernel_name", ctypes.c_char_p, [c_int32]),
     ("sp_last_error", ctypes.c_char_p, []),
 ]

@@ -147,6 +147,10 @@ class Context:
     def step_index(self) -> int:
         return int(self.lib.sp_step_index(self._handle))
 
+    @property
+    def tape_generation(self) -> int:
+        return int(self.lib.sp_tape_generation(self._handle))
+
     def set_weights(self, weights: Sequence[float], q: float, r: float) -> None:
         w = (ctypes.c_float * 8)(*[float(x) for x in weights])
         self._bind_stream()
@@ -244,6 +248,12 @@ class Context:
               "sp_autotune")
         return buf.value.decode()
 
+    def set_tune(self, kalman_tw: int, xcd_order: bool, channels: int) -> None:
+        """Force the launch shapes (results are identical for every choice)."""
+        self._bind_stream()
+        check(self.lib.sp_set_tune(self._handle, int(kalman_tw), 1 if xcd_order else 0, int(channels)),
+              "sp_set_tune")
+
     def saliency_backward(self, grad_prior: torch.Tensor):
         g = self.geometry
         T = grad_prior.shape[0]
@@ -317,15 +327,25 @@ class SaliencyPrior(torch.autograd.Function):
         sp.set_weights(w.detach().float().cpu().tolist(), float(q), float(r))
         out = sp.run_clip(frames)
         ctx.sp = sp
+        ctx.gen = sp.tape_generation
         ctx.meta = [(x.device, x.dtype, x.shape) for x in (w, q, r)]
         return out["pi"]
 
     @staticmethod
     def backward(ctx, grad_pi: torch.Tensor):
         sp: Context = ctx.sp
+        if sp.tape_generation != ctx.gen:
+            raise RuntimeError("SaliencyPrior.backward: the context ran another clip, or its weights or "
+                               "state changed, after this forward; its tape no longer holds this graph")
         gw, gq, gr = sp.saliency_backward(grad_pi.contiguous().float())
         grads = [g.to(device=d, dtype=t).reshape(s) for g, (d, t, s) in zip((gw, gq, gr), ctx.meta)]
         return None, None, grads[0], grads[1], grads[2]
+
+
+def tune_cache_clear() -> None:
+    """Forget the autotuner's per-process choices (later contexts start from defaults)."""
+    lib = _lib.load()
+    check(lib.sp_tune_cache_clear(), "sp_tune_cache_clear")
 
 
 def profile_enable(ctx, on: bool = True) -> None:
@@ -355,7 +375,8 @@ class Batch:
     """Many streams of possibly different sizes advanced together, one frame each per
     step; the step is one replay of a captured HIP graph."""
 
-    def __init__(self, sizes: Sequence[Tuple[int, int]], params: Optional[Params] = None, mrf: bool = False):
+    def __init__(self, sizes: Sequence[Tuple[int, int]], params: Optional[Params] = None, mrf: bool = False,
+                 consp: bool = False):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("salprior needs a ROCm GPU; torch.cuda.is_available() is False")
@@ -366,7 +387,8 @@ class Batch:
         Ws = (ctypes.c_int32 * n)(*[w for _, w in self.sizes])
         self._handle = ctypes.c_void_p()
         cp = self.params.to_c()
-        check(self.lib.sp_batch_create(ctypes.byref(cp), n, Hs, Ws, 1 if mrf else 0, _stream(),
+        flags = (1 if mrf else 0) | (2 if consp else 0)
+        check(self.lib.sp_batch_create(ctypes.byref(cp), n, Hs, Ws, flags, _stream(),
                                        ctypes.byref(self._handle)), "sp_batch_create")
         self.mrf = mrf
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -408,9 +430,20 @@ class Batch:
               "sp_batch_autotune")
         return buf.value.decode()
 
+    def set_tune(self, kalman_tw: int, xcd_order: bool, channels: int) -> None:
+        """Force the launch shapes of every stream (results are identical for every choice)."""
+        check(self.lib.sp_batch_set_tune(self._handle, int(kalman_tw), 1 if xcd_order else 0, int(channels)),
+              "sp_batch_set_tune")
+
     def output_pointers(self, i: int):
         """Device pointers (ints) of stream i's S, unary, pairwise and beta buffers."""
         ptrs = [ctypes.c_void_p() for _ in range(4)]
         check(self.lib.sp_batch_outputs(self._handle, int(i), *[ctypes.byref(p) for p in ptrs]),
               "sp_batch_outputs")
         return [p.value for p in ptrs]
+
+    def consp_pointer(self, i: int):
+        """Device pointer (int) of stream i's conspicuity maps [8][Hc][Wc] (needs consp=True)."""
+        ptr = ctypes.c_void_p()
+        check(self.lib.sp_batch_consp(self._handle, int(i), ctypes.byref(ptr)), "sp_batch_consp")
+        return ptr.value

@@ -551,6 +551,7 @@ struct sp_ctx {
   int cap = 0;
   int64_t tape_valid_from = 0;   // tape covers steps since the last reset only
   bool tape_ok = true;
+  int64_t tape_gen = 0;           // bumped whenever the recorded clip stops being the current one
   float* ckpt = nullptr;          // [cap][4][Hcmin][Wcmin]
   float* S_tape = nullptr;        // [cap][Hc][Wc]
   float* f_tape = nullptr;        // [cap][H][W]
@@ -920,6 +921,10 @@ int sp_set_weights(sp_ctx* c, const float* w, double q, double r) {
   }
   c->p.q = q;
   c->p.r = r;
+  // steps already recorded used the old weights and variances: their tape no longer
+  // matches what the adjoint would rebuild
+  if (c->t > 0) c->tape_ok = false;
+  c->tape_gen += 1;
   HIPCHK(hipMemcpyAsync(c->d_sd, &c->h_sd, sizeof(StreamDesc), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return SP_OK;
@@ -932,12 +937,15 @@ int sp_reset(sp_ctx* c) {
   c->P = 0.0;
   c->cur = 0;
   c->tape_ok = true;
+  c->tape_gen += 1;
   c->Kf.clear();
   c->uses_pi.clear();
   return SP_OK;
 }
 
 int64_t sp_step_index(const sp_ctx* c) { return c ? c->t : -1; }
+
+int64_t sp_tape_generation(const sp_ctx* c) { return c ? c->tape_gen : -1; }
 
 int saliency_forward(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, float* S_out, float* C_out) {
   g_err.clear();
@@ -1131,6 +1139,29 @@ int sp_autotune(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, int32_
   return sp_reset(c);
 }
 
+int sp_set_tune(sp_ctx* c, int32_t kalman_tw, int32_t xcd_order, int32_t channels) {
+  g_err.clear();
+  if (!c) return fail(SP_EINVAL, "ctx is NULL");
+  if (kalman_tw != 16 && kalman_tw != 32 && kalman_tw != 64) return fail(SP_EINVAL, "kalman_tw must be 16, 32 or 64");
+  if (channels != 1 && channels != 2 && channels != 4 && channels != 8) return fail(SP_EINVAL, "channels must be 1, 2, 4 or 8");
+  if (csapply_nc(c->g, channels) != channels)
+    return fail(SP_EINVAL, "%d channels per across-scale workgroup exceed the LDS limit for this geometry", channels);
+  c->tune.kalman_tw = kalman_tw;
+  c->tune.xcd = xcd_order != 0;
+  c->tune.ca_nc = channels;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return ctx_build_tables(c);
+}
+
+int sp_tune_cache_clear(void) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  tune_cache_tw().clear();
+  tune_cache_xcd() = false;
+  tune_cache_nc() = 2;
+  return SP_OK;
+}
+
 int mrf_weights(sp_ctx* c, const uint8_t* rgb_t, const float* prior, float* unary_out, float* pairwise_out,
                 float* beta_out) {
   g_err.clear();
@@ -1153,7 +1184,8 @@ int saliency_backward(sp_ctx* c, const float* grad_prior, int32_t T, float* grad
   g_err.clear();
   if (!c || !grad_prior || !grad_w || !grad_q || !grad_r) return fail(SP_EINVAL, "NULL argument");
   if (c->cap <= 0) return fail(SP_ESTATE, "context was created without a tape (record_tape = 0)");
-  if (!c->tape_ok) return fail(SP_ESTATE, "tape invalidated by sp_set_state; call sp_reset");
+  if (!c->tape_ok)
+    return fail(SP_ESTATE, "tape invalidated by sp_set_state or sp_set_weights after recorded steps; call sp_reset");
   if (T < 1 || T != c->t || (size_t)T != c->Kf.size())
     return fail(SP_ESTATE, "backward of %d steps, but %lld prior updates were recorded since the reset", T,
                 (long long)c->t);
@@ -1267,6 +1299,7 @@ int sp_set_state(sp_ctx* c, const void* buf, size_t bytes) {
   c->t = (int64_t)sc[0];
   c->P = sc[1];
   c->tape_ok = false;
+  c->tape_gen += 1;
   return SP_OK;
 }
 
@@ -1530,8 +1563,9 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
   int rc = validate_params(p);
   if (rc) return rc;
   if (p->record_tape != 0) return fail(SP_EINVAL, "the batched step keeps no tape (record_tape must be 0)");
-  if (flags & ~SP_BATCH_MRF) return fail(SP_EINVAL, "unknown batch flags 0x%x", flags);
+  if (flags & ~(SP_BATCH_MRF | SP_BATCH_CONSP)) return fail(SP_EINVAL, "unknown batch flags 0x%x", flags);
   const bool mrf = (flags & SP_BATCH_MRF) != 0;
+  const bool consp = (flags & SP_BATCH_CONSP) != 0;
   sp_batch* b = new (std::nothrow) sp_batch();
   if (!b) return fail(SP_ENOMEM, "host allocation failed");
   b->p = *p;
@@ -1565,6 +1599,7 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
         s.pairwise = bm.take<float>((size_t)4 * g.H * g.W);
         s.beta = bm.take<float>(1);
       }
+      if (consp) s.C = bm.take<float>((size_t)SP_NCH * g.Hl[g.c_max] * g.Wl[g.c_max]);
     }
     b->d_sd = bm.take<StreamDesc>(n);
     b->d_io = bm.take<StepIO>(n);
@@ -1657,6 +1692,14 @@ int sp_batch_outputs(sp_batch* b, int32_t i, const float** S, const float** unar
   if (unary) *unary = b->h_st[i].unary;
   if (pairwise) *pairwise = b->h_st[i].pairwise;
   if (beta) *beta = b->h_st[i].beta;
+  return SP_OK;
+}
+
+int sp_batch_consp(sp_batch* b, int32_t i, const float** C) {
+  g_err.clear();
+  if (!b || !C) return fail(SP_EINVAL, "NULL argument");
+  if (i < 0 || i >= b->n) return fail(SP_EINVAL, "stream index %d out of range", i);
+  *C = b->h_st[i].C;
   return SP_OK;
 }
 
@@ -1784,6 +1827,20 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
   b->steps = 0;
   HIPCHK(hipStreamSynchronize(b->stream));
   return SP_OK;
+}
+
+int sp_batch_set_tune(sp_batch* b, int32_t kalman_tw, int32_t xcd_order, int32_t channels) {
+  g_err.clear();
+  if (!b) return fail(SP_EINVAL, "batch is NULL");
+  if (kalman_tw != 16 && kalman_tw != 32 && kalman_tw != 64) return fail(SP_EINVAL, "kalman_tw must be 16, 32 or 64");
+  if (channels != 1 && channels != 2 && channels != 4 && channels != 8) return fail(SP_EINVAL, "channels must be 1, 2, 4 or 8");
+  for (const Geo& g : b->geo)
+    if (csapply_nc(g, channels) != channels)
+      return fail(SP_EINVAL, "%d channels per across-scale workgroup exceed the LDS limit of a stream", channels);
+  for (Tune& t : b->tune) t.kalman_tw = kalman_tw;
+  b->xcd = xcd_order != 0;
+  b->ca_nc = channels;
+  return batch_build_tables(b);
 }
 
 int sp_batch_destroy(sp_batch* b) {

@@ -139,6 +139,7 @@ struct BatchState {
   float* unary;              // [2][H][W] or null
   float* pairwise;           // [4][H][W] or null
   float* beta;               // [1] or null
+  float* C;                  // [8][Hc][Wc] conspicuity maps or null
   const uint8_t* last_rgb;   // frame of the last step (next step's previous frame)
   int32_t cur, pad;
 };

@@ -2445,7 +2445,7 @@ __device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const uin
   io->rgb = cur;
   io->rgb_prev = (s.t == 0) ? nullptr : s.last_rgb;
   io->S_out = s.S;
-  io->C_out = nullptr;
+  io->C_out = s.C;
   io->ckpt = nullptr;
   io->S_tape = nullptr;
   io->S_in = s.S;

@@ -1,0 +1,46 @@
+"""Oracle runs in worker processes (spawned, CPU only) so GPU tests at full frame sizes
+can check every stream against the FP64 oracle within their time limit.  Workers
+regenerate the seeded clips themselves; nothing here touches the GPU."""
+import multiprocessing as mp
+
+import numpy as np
+
+
+def _spec(kind, H, W, T, seed):
+    from paper_1008_0502_amd import synth
+    fn = {"single": synth.single_ellipse_spec, "three": synth.three_ellipse_spec,
+          "five": synth.five_ellipse_spec}[kind]
+    return fn(H=H, W=W, T=T, seed=seed)
+
+
+def clip_job(args):
+    """(kind, H, W, T, seed, oracle param dict) -> oracle outputs of the whole clip."""
+    import oracle as O
+    from paper_1008_0502_amd import synth
+    kind, H, W, T, seed, pkw = args
+    frames, _ = synth.Clip(_spec(kind, H, W, T, seed)).stack()
+    out = O.run_clip(frames, O.OracleParams(**pkw))
+    return {"S": out["S"], "C": out["C"], "pi": out["pi"]}
+
+
+def mrf_job(args):
+    """(kind, H, W, T, seed, param dict, priors [T][H][W]) -> oracle capacities of the
+    given priors (stage-isolated check of the MRF weights)."""
+    import oracle as O
+    from paper_1008_0502_amd import synth
+    kind, H, W, T, seed, pkw, priors = args
+    frames, _ = synth.Clip(_spec(kind, H, W, T, seed)).stack()
+    p = O.OracleParams(**pkw)
+    us, pws, bs = [], [], []
+    for t in range(T):
+        u, pw, b = O.mrf_weights(frames[t], priors[t].astype(np.float64), p)
+        us.append(u)
+        pws.append(pw)
+        bs.append(b)
+    return {"unary": np.stack(us), "pairwise": np.stack(pws), "beta": np.array(bs)}
+
+
+def run(fn, jobs, workers=8):
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(min(workers, len(jobs))) as pool:
+        return pool.map(fn, jobs)

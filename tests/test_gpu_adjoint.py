@@ -187,3 +187,30 @@ def test_autograd_function_fits_weights():
             w.clamp_(min=0.0)
     assert float(l) < l0
     ctx.close()
+
+
+def test_autograd_backward_after_another_forward_raises():
+    banner("autograd wrapper: a second forward on the same context invalidates the first graph's tape")
+    torch = _torch()
+    from paper_1008_0502_amd.api import Context, SaliencyPrior
+    frames, masks = small_clip(T=4, seed=13)
+    T, H, W = frames.shape[:3]
+    ctx = Context(H, W, params(record_tape=T))
+    fr = torch.from_numpy(frames).cuda()
+    mk = torch.from_numpy(masks).cuda().float()
+    w = torch.tensor(W8, dtype=torch.float32, device="cuda", requires_grad=True)
+    q = torch.tensor(1e-3, dtype=torch.float64)
+    r = torch.tensor(1e-1, dtype=torch.float64)
+    pi1 = SaliencyPrior.apply(ctx, fr, w, q, r)
+    pi2 = SaliencyPrior.apply(ctx, fr, w * 1.5, q, r)
+    with pytest.raises(RuntimeError, match="tape"):
+        ((pi1 - mk) ** 2).mean().backward()
+    ((pi2 - mk) ** 2).mean().backward()          # the latest graph still differentiates
+    assert w.grad is not None and torch.isfinite(w.grad).all()
+    # set_weights after recorded steps: the C-ABI refuses the stale tape
+    from paper_1008_0502_amd import SalpriorError
+    ctx.run_clip(fr)
+    ctx.set_weights(W8, 1e-3, 1e-1)
+    with pytest.raises(SalpriorError):
+        ctx.saliency_backward(torch.zeros((T, H, W), device="cuda"))
+    ctx.close()

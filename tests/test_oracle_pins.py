@@ -545,3 +545,157 @@ def test_planted_mistake_is_caught_by_fd():
     gw, gQ, gR = O.prior_chain_backward(tape, out["C"], g, p)
     fw, fQ, fR = O.finite_difference_grad(out["C"], masks, w, p.q, p.r, p, H, W, geo.c_max, h=1e-4)
     assert abs(gQ - fQ) > 1e-3 * abs(fQ) or np.max(np.abs(gw - fw)) > 1e-3 * np.abs(fw).max()
+
+
+# ---------------------------------------------------------------- observation q_t and the border ring
+# Hand-built saliency maps at level c_max whose values are dyadic, so the bilinear
+# up-sample at and between the sample points is exact in FP64 and the expected
+# observation can be written down without calling the oracle's own up-sample.
+def _dyadic_saliency():
+    # 6 x 7 map at c_max = 2 for a 24 x 28 frame (24 -> 12 -> 6, 28 -> 14 -> 7)
+    S = np.array([
+        [0.0, 0.5, 0.25, 0.0, 1.0, 0.5, 0.0],
+        [0.25, 2.0, 0.5, 0.0, 0.0, 0.75, 0.25],   # the maximum 2.0 at (1, 1)
+        [0.0, 0.5, 1.0, 0.5, 0.25, 0.0, 0.0],
+        [0.0, 0.0, 0.0, 0.0, 1.5, 1.0, 0.5],
+        [0.5, 0.25, 0.0, 1.25, 0.0, 0.0, 0.25],
+        [1.0, 0.0, 0.5, 0.0, 0.0, 0.25, 0.75],
+    ])
+    return S, 24, 28, 2
+
+
+def _check_observation(obs_fn, border):
+    """Hand values of q = clamp(up_{c_max -> 0}(S / max S), eps, 1 - eps), eps on the
+    border ring (Section 5: the prior at the frame edge is close to 0)."""
+    S, H, W, cm = _dyadic_saliency()
+    p = O.OracleParams(border=border)
+    q, info = obs_fn(S, p, H, W, cm)
+    m = 2.0
+    assert info["m"] == m and info["xstar"] == 1 * 7 + 1
+    sc = 2 ** cm
+
+    def ring(y, x):
+        return y < border or y >= H - border or x < border or x >= W - border
+
+    def want(v):
+        return min(max(v, p.eps), 1.0 - p.eps)
+
+    for k in range(S.shape[0]):
+        for j in range(S.shape[1]):
+            y, x = k * sc, j * sc
+            assert q[y, x] == (p.eps if ring(y, x) else want(S[k, j] / m)), (k, j)
+            # half-way between two samples along a row and along a column
+            if k + 1 < S.shape[0] and not ring(y + sc // 2, x):
+                assert q[y + sc // 2, x] == want((S[k, j] + S[k + 1, j]) / 2 / m), (k, j, "row mid")
+            if j + 1 < S.shape[1] and not ring(y, x + sc // 2):
+                assert q[y, x + sc // 2] == want((S[k, j] + S[k, j + 1]) / 2 / m), (k, j, "col mid")
+    # the maximum sits where the clamp is active from above, zeros from below
+    assert q[sc, sc] == 1.0 - p.eps
+    # a quarter of the way from S[2][3] = 0.5 to S[2][4] = 0.25 along the row
+    assert q[2 * sc, 3 * sc + 1] == want((0.75 * 0.5 + 0.25 * 0.25) / m)
+    assert np.count_nonzero(q[~O.border_mask(H, W, border)] == p.eps) > 0
+    # past the last sample the coordinate is clamped to the last row / column
+    assert q[H - 1 - border, W - 1 - border] == want(S[-1, -1] / m) or ring(H - 1 - border, W - 1 - border)
+    for y in range(H):
+        for x in range(W):
+            if ring(y, x):
+                assert q[y, x] == p.eps, (y, x)
+    return q
+
+
+def _obs_no_clamp(S, p, H, W, c_max):
+    # planted mistake: the [eps, 1 - eps] clamp of q dropped
+    m = float(S.max())
+    u = O.upsample(S / m, c_max, H, W)
+    q = u.copy()
+    q[O.border_mask(H, W, p.border)] = p.eps
+    return q, {"m": m, "xstar": int(np.argmax(S))}
+
+
+def _obs_no_ring(S, p, H, W, c_max):
+    # planted mistake: q keeps its value on the border ring
+    m = float(S.max())
+    q = np.clip(O.upsample(S / m, c_max, H, W), p.eps, 1 - p.eps)
+    return q, {"m": m, "xstar": int(np.argmax(S))}
+
+
+def _obs_wrong_level(S, p, H, W, c_max):
+    # planted mistake: up-sampled as if S were one level finer than c_max
+    m = float(S.max())
+    q = np.clip(O.upsample(S / m, c_max - 1, H, W), p.eps, 1 - p.eps)
+    q[O.border_mask(H, W, p.border)] = p.eps
+    return q, {"m": m, "xstar": int(np.argmax(S))}
+
+
+@pytest.mark.parametrize("border", [1, 2])
+def test_observation_hand_values(border):
+    _check_observation(O.observation, border)
+
+
+@pytest.mark.parametrize("mutant", [_obs_no_clamp, _obs_no_ring, _obs_wrong_level])
+def test_observation_pin_catches_planted_mistakes(mutant):
+    with pytest.raises(AssertionError):
+        _check_observation(mutant, 1)
+
+
+def test_observation_matches_brute_force_bilinear():
+    # every level-0 pixel of a non-dyadic map, against the loop bilinear helper
+    rng = np.random.default_rng(17)
+    for cm, (H, W) in [(1, (13, 17)), (2, (21, 26)), (3, (40, 33))]:
+        Hc, Wc = H, W
+        for _ in range(cm):
+            Hc, Wc = (Hc + 1) // 2, (Wc + 1) // 2
+        S = rng.uniform(0, 3, (Hc, Wc))
+        S[rng.uniform(0, 1, (Hc, Wc)) < 0.3] = 0.0
+        p = O.OracleParams(border=1)
+        q, _ = O.observation(S, p, H, W, cm)
+        up = np.asarray(bf_bilinear((S / S.max()).tolist(), cm, H, W))
+        want = np.clip(up, p.eps, 1 - p.eps)
+        want[O.border_mask(H, W, 1)] = p.eps
+        close(q, want, 1e-15)
+
+
+def _check_prior_ring(prior_fn, border):
+    """pi_t = eps on the border ring at every step, whatever q and G * pi_{t-1} hold there
+    (Section 5's near-zero edge prior carried through the Section 6 update)."""
+    H, W, T = 14, 17, 4
+    p = O.OracleParams(border=border, q=1e-3, r=1e-1)
+    rng = np.random.default_rng(border)
+    qs = [rng.uniform(0.2, 0.9, (H, W)) for _ in range(T)]      # no ring in q on purpose
+    pis, fs, K = prior_fn(qs, p)
+    ring = O.border_mask(H, W, border)
+    assert ring.sum() == 2 * border * (H + W) - 4 * border * border
+    for t in range(T):
+        assert np.all(pis[t][ring] == p.eps), t
+        if t > 0:
+            assert K[t] < 1.0
+    # interior of step 1 by hand: f = blur(pi_0) with pi_0 = q_0 off the ring and eps on it
+    pi0 = np.where(ring, p.eps, qs[0])
+    f1 = np.asarray(bf_blur(pi0.tolist()))
+    a = p.r + p.q
+    K1 = a / (a + p.r)
+    close(pis[1][~ring], (f1 + K1 * (qs[1] - f1))[~ring], 1e-15)
+
+
+def _prior_no_ring(qs, p, segs=None):
+    # planted mistake: the update without the eps ring on pi_t
+    K, _ = O.kalman_gains(len(qs), p.q, p.r)
+    pis, fs = [], [None]
+    for t, q in enumerate(qs):
+        if t == 0:
+            pis.append(q.copy())
+        else:
+            f = O.blur(pis[-1])
+            fs.append(f)
+            pis.append(f + K[t] * (q - f))
+    return pis, fs, K
+
+
+@pytest.mark.parametrize("border", [1, 2])
+def test_prior_border_ring_is_eps(border):
+    _check_prior_ring(O.prior_clip, border)
+
+
+def test_prior_ring_pin_catches_planted_mistake():
+    with pytest.raises(AssertionError):
+        _check_prior_ring(_prior_no_ring, 1)
