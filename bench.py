@@ -9,9 +9,14 @@ the same GPU:
   * plain: one 640x480 stream, one frame per sp_step call (and through the three
     separate calls, and saliency + prior only),
   * fwd+bwd: a 120-frame 640x480 clip forward with tape, masked-MSE loss and adjoint,
+    on one stream and batched over 16 streams (the batched fwd+bwd workload),
   * the mixed batch of 64 streams (16 each of 160x120, 320x240, 640x480, 1280x720),
   * the roofline of the step's dominant kernel, timed live with HIP events,
-  * the FP64 CPU oracle on a bounded sample (cpu_baseline).
+  * the named single-stream workloads: the single ellipse at 160x120, the three
+    ellipses at 320x240 with MRF capacities, the five ellipses at 1920x1080, and the
+    single ellipse at 352x288, 480x384 and 640x512,
+  * the FP64 CPU oracle on a bounded sample (cpu_baseline), single-threaded and with one
+    process per stream.
 """
 from __future__ import annotations
 
@@ -93,6 +98,98 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def cpu_info():
+    """CPU model and the number of host threads this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
+def _gen_clip(args):
+    from paper_1008_0502_amd import synth
+    kind, H, W, T, seed = args
+    fn = {"single": synth.single_ellipse_spec, "three": synth.three_ellipse_spec,
+          "five": synth.five_ellipse_spec}[kind]
+    return synth.Clip(fn(H=H, W=W, T=T, seed=seed)).stack()
+
+
+def gen_clips(jobs, workers=8):
+    """Seeded clips drawn in worker processes (the generator holds no method arithmetic)."""
+    import multiprocessing as mp
+    if len(jobs) == 1:
+        return [_gen_clip(jobs[0])]
+    with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
+        return pool.map(_gen_clip, jobs)
+
+
+def _oracle_stream(args):
+    """One stream of the oracle for the parallel baseline: frames of the clip until the
+    deadline (saliency, observation, Kalman update), single-threaded; frames are drawn
+    one at a time (a small share of the oracle's time per frame)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except Exception:
+        pass
+    import oracle as O
+    from paper_1008_0502_amd import synth
+    H, W, T, seed, deadline = args
+    clip = synth.Clip(synth.single_ellipse_spec(H=H, W=W, T=T, seed=seed))
+    p = O.OracleParams()
+    geo = O.geometry(H, W, p)
+    K, _ = O.kalman_gains(T, p.q, p.r)
+    ring = O.border_mask(H, W, p.border)
+    n, prev, prev_rgb = 0, None, None
+    while n < T and time.time() < deadline:
+        rgb, _ = clip.frame(n)
+        S, _ = O.saliency(rgb, prev_rgb, p)
+        q, _ = O.observation(S, p, H, W, geo.c_max)
+        if n == 0:
+            pi = q.copy()
+        else:
+            f = O.blur(prev)
+            pi = f + K[n] * (q - f)
+        pi[ring] = p.eps
+        prev, prev_rgb = pi, rgb
+        n += 1
+    return n
+
+
+def _warm_oracle(_):
+    import oracle  # noqa: F401
+    from paper_1008_0502_amd import synth  # noqa: F401
+    return os.getpid()
+
+
+def cpu_baseline_parallel(streams: int, budget_s: float):
+    """The oracle with one process per stream (16 streams of 640x480, seeds 6000+i) over
+    min(streams, host threads) processes; frames finished by all processes in the budget."""
+    import multiprocessing as mp
+    _, nthreads = cpu_info()
+    procs = max(1, min(streams, nthreads))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        pool.map(_warm_oracle, range(procs))   # interpreter start and imports before the window
+        t0 = time.time()
+        jobs = [(H, W, T_CLIP, 6000 + i, t0 + budget_s) for i in range(streams)]
+        counts = pool.map(_oracle_stream, jobs, chunksize=1)
+        dt = time.time() - t0
+    return {"value": sum(counts) / dt, "unit": "frames/s", "cores": procs, "kind": "oracle",
+            "sample": f"{sum(counts)} frames over {streams} streams of 640x480 (single-ellipse generator, seeds "
+                      f"6000+i): saliency, observation and Kalman update in FP64 NumPy, one single-threaded "
+                      f"process per stream on {procs} processes, {dt:.1f} s"}
+
+
 def cpu_baseline(frames_np, budget_s: float):
     """The FP64 oracle, as it stands, on the first frames of the same clip."""
     import numpy as np
@@ -127,55 +224,89 @@ def cpu_baseline(frames_np, budget_s: float):
     dt = time.perf_counter() - t0
     if limiter is not None:
         limiter.unregister() if hasattr(limiter, "unregister") else None
+    model, nthreads = cpu_info()
     return {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} frames of the 640x480 clip (single-ellipse generator, seed 2): saliency, observation, "
-                      f"Kalman update and MRF capacities in FP64 NumPy, one thread, {dt:.1f} s"}
+                      f"Kalman update and MRF capacities in FP64 NumPy, one thread, {dt:.1f} s",
+            "cpu_model": model, "host_threads": nthreads}
 
 
-def pmc_summarize(fetch_db: str, write_db: str) -> None:
-    """HBM traffic per launch of each kernel of the batched step from two rocprofv3 --pmc
-    runs of --pmc-workload (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by
-    what the counter reads for the 256 MiB calibration copy."""
+CALIB = ((0, 512 << 20), (1, 96 << 20), (2, 16 << 20))   # (access form, bytes) of the calibration copies
+VALU_ISSUE_PER_S = 256 * 2.4e9   # wave64 VALU instructions per second: one per CU per clock (no packed FP32)
+KERNEL_KEYS = {"k_rgb": "k_rgb", "k_feat": "k_feat", "k_csstats": "k_csstats", "k_csfinal": "k_csfinal",
+               "k_csapply": "k_csapply", "k_consp": "k_consp", "k_kalman": "k_kalman", "k_csg": "k_csg",
+               "k_csmix": "k_csmix", "k_calib": "k_calib"}
+
+
+def _short_kernel(raw: str):
     import re
+    short = re.sub(r"\(anonymous namespace\)::", "", raw)
+    short = re.sub(r"\(.*\)$", "", short).replace("void ", "").replace(" ", "")
+    if short.startswith("k_pyr<"):
+        return "k_pyr_tail" if short.startswith("k_pyr<true") else "k_pyr"
+    return KERNEL_KEYS.get(re.sub(r"<.*>$", "", short))
+
+
+def _per_kernel(db: str, counter: str):
+    """{kernel: [value per dispatch, in dispatch order]} of one counter of a rocprofv3 database."""
     import sqlite3
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(counters_collection)").fetchall()]
+    order = " order by dispatch_id" if "dispatch_id" in cols else ""
+    rows = cur.execute(f"select kernel_name, value from counters_collection where counter_name = ?{order}",
+                       (counter,)).fetchall()
+    out = {}
+    for name, val in rows:
+        key = _short_kernel(name)
+        if key is not None:
+            out.setdefault(key, []).append(float(val))
+    return out
 
-    def per_kernel(db, counter):
-        con = sqlite3.connect(db)
-        cur = con.cursor()
-        rows = cur.execute("select kernel_name, value from counters_collection where counter_name = ?",
-                           (counter,)).fetchall()
-        out = {}
-        for name, val in rows:
-            out.setdefault(name, []).append(float(val))
-        return out
 
-    fetch = per_kernel(fetch_db, "FETCH_SIZE")
-    write = per_kernel(write_db, "WRITE_SIZE")
-    copy_bytes = 64 * 1024 * 1024 * 4
-    cal_f = [v for n, vs in fetch.items() if "copybuffer" in n.lower() for v in vs]
-    cal_w = [v for n, vs in write.items() if "copybuffer" in n.lower() for v in vs]
-    kf = copy_bytes / (max(cal_f) * 1024.0)
-    kw = copy_bytes / (max(cal_w) * 1024.0)
+def _calib_factors(vals):
+    """Scale factor (true bytes / counted bytes) of each calibration access form: the k_calib
+    dispatches are told apart by their byte counts (disjoint ranges for factors 0.5..2)."""
+    out = {}
+    for mode, nbytes in CALIB:
+        cands = [v for v in vals if 0.4 * nbytes <= v * 1024.0 <= 2.5 * nbytes]
+        if cands:
+            out[mode] = nbytes / (max(cands) * 1024.0)
+    return out
+
+
+def pmc_summarize(fetch_db: str, write_db: str, valu_db=None) -> None:
+    """HBM traffic (and VALU instructions) per launch of each kernel of the batched step from
+    rocprofv3 --pmc runs of --pmc-workload: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what the counter reads for the library's own calibration copies of a
+    known byte count; SQ_INSTS_VALU (wave instructions per dispatch) when given."""
+    fetch = _per_kernel(fetch_db, "FETCH_SIZE")
+    write = _per_kernel(write_db, "WRITE_SIZE")
+    valu = _per_kernel(valu_db, "SQ_INSTS_VALU") if valu_db else {}
+    kf = _calib_factors(fetch.get("k_calib", []))
+    kw = _calib_factors(write.get("k_calib", []))
+    forms = {0: "dword", 1: "dwordx4", 2: "global_load_lds dword"}
+    fs, ws = kf.get(0, 1.0), kw.get(0, 1.0)
     kernels = {}
-    names = {"k_rgb": "k_rgb", "k_feat<16,16>": "k_feat", "k_pyr<false>": "k_pyr", "k_pyr<true>": "k_pyr_tail",
-             "k_csstats": "k_csstats", "k_csfinal": "k_csfinal", "k_csapply": "k_csapply", "k_consp": "k_consp",
-             "k_kalman": "k_kalman", "k_csg": "k_csg", "k_csmix": "k_csmix"}
-    for raw in set(fetch) | set(write):
-        short = re.sub(r"\(anonymous namespace\)::", "", raw)
-        short = re.sub(r"\(.*\)$", "", short).replace("void ", "").replace(" ", "")
-        key = names.get(short) or names.get(re.sub(r"<.*>$", "", short))
-        if short.startswith("k_pyr<"):
-            key = "k_pyr_tail" if short.startswith("k_pyr<true") else "k_pyr"
-        if key is None:
+    for key in sorted(set(fetch) | set(write)):
+        if key == "k_calib":
             continue
-        f = fetch.get(raw, [0.0])
-        w = write.get(raw, [0.0])
-        fb = sum(f) / len(f) * 1024.0 * kf
-        wb = sum(w) / len(w) * 1024.0 * kw
-        kernels[key] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb}
+        f = fetch.get(key, [0.0])
+        w = write.get(key, [0.0])
+        fr = sum(f) / len(f) * 1024.0
+        wr = sum(w) / len(w) * 1024.0
+        rec = {"fetch_bytes_raw": fr, "write_bytes_raw": wr, "fetch_bytes_per_launch": fr * fs,
+               "write_bytes_per_launch": wr * ws, "hbm_bytes_per_launch": fr * fs + wr * ws}
+        if key in valu:
+            v = valu[key]
+            rec["valu_insts_per_launch"] = sum(v) / len(v)
+        kernels[key] = rec
     out = {"source_hash": source_hash(), "workload": "batched step, 16 streams of 640x480, MRF on",
-           "calibration": {"copy_bytes": copy_bytes, "fetch_scale": kf, "write_scale": kw},
-           "kernels": kernels}
+           "calibration": {"copies": {forms[m]: n for m, n in CALIB},
+                           "fetch_scale": {forms[m]: v for m, v in kf.items()},
+                           "write_scale": {forms[m]: v for m, v in kw.items()},
+                           "applied": "dword"},
+           "valu_issue_per_s": VALU_ISSUE_PER_S, "kernels": kernels}
     path = os.environ.get("SALPRIOR_TRAFFIC_OUT", os.path.join(ROOT, "profiles", "traffic_batched16_640x480.json"))
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
@@ -190,17 +321,22 @@ def roofline_of(prof, bytes_per_step, n_steps, counters=True):
     avg_s = ms / cnt * 1e-3
     per_launch = bytes_per_step[dom] / (cnt / n_steps)
     achieved = per_launch / avg_s / 1e9
-    traffic = None
+    traffic, valu = None, None
     tfile = os.path.join(ROOT, "profiles", "traffic_batched16_640x480.json")
     if counters and os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
             if tj.get("source_hash") == source_hash() and dom in tj.get("kernels", {}):
-                traffic = tj["kernels"][dom]["hbm_bytes_per_launch"]
+                rec = tj["kernels"][dom]
+                traffic = rec["hbm_bytes_per_launch"]
+                if "valu_insts_per_launch" in rec:
+                    need = rec["valu_insts_per_launch"] / VALU_ISSUE_PER_S
+                    valu = {"insts_per_launch": rec["valu_insts_per_launch"], "issue_s_at_peak": need,
+                            "frac": round(need / avg_s, 4)}
         except Exception:
-            traffic = None
+            traffic, valu = None, None
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dom,
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "valu": valu, "kernel": dom,
             "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 3)}
 
 
@@ -210,11 +346,13 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--skip", default="", help="comma list of legs to skip: batched,plain,bwd,mixed,cpu,profile")
+    ap.add_argument("--skip", default="",
+                    help="comma list of legs to skip: batched,plain,bwd,bwd_batched,mixed,configs,cpu,cpu_par,profile")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="short run for rocprofv3 --pmc: a 256 MiB copy (calibration) then 5 batched steps")
-    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
-                    help="write profiles/traffic_batched16_640x480.json from two rocprofv3 --pmc databases")
+    ap.add_argument("--pmc-summarize", nargs="+", metavar="DB",
+                    help="write profiles/traffic_batched16_640x480.json from the rocprofv3 --pmc databases of "
+                         "FETCH_SIZE, WRITE_SIZE and (optional) SQ_INSTS_VALU")
     args = ap.parse_args()
     if args.pmc_summarize:
         pmc_summarize(*args.pmc_summarize)
@@ -243,11 +381,15 @@ def main():
         return time.perf_counter() - t0
 
     if args.pmc_workload:
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        from paper_1008_0502_amd import _lib
+        lib = _lib.load()
+        src = torch.ones(CALIB[0][1] // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+        for mode, nbytes in CALIB:
+            _lib.check(lib.sp_calibration_copy(src.data_ptr(), dst.data_ptr(), nbytes, mode,
+                                               torch.cuda.current_stream().cuda_stream), "sp_calibration_copy")
         torch.cuda.synchronize()
+        del src, dst
         bf = [torch.from_numpy(synth.Clip(synth.single_ellipse_spec(H=H, W=W, T=2, seed=6000 + i)).stack()[0]).to(dev)
               for i in range(16)]
         tabs = [Batch.pointer_table([f[t] for f in bf]) for t in range(2)]
@@ -380,6 +522,62 @@ def main():
         tctx.close()
         log(f"fwd+bwd: {fb['frames_per_s']} frames/s")
 
+    # ------------------------------------------------------------ batched fwd + bwd, 16 x 640x480 x 120
+    fbb = None
+    if "bwd_batched" not in skip:
+        NB = 16
+        log(f"generating {NB} clips of 640x480 x {T_CLIP} frames (seeds 6000+i)")
+        clips = gen_clips([("single", H, W, T_CLIP, 6000 + i) for i in range(NB)])
+        bfr = [torch.from_numpy(f).to(dev) for f, _ in clips]
+        bmk = [torch.from_numpy(m).to(dev) for _, m in clips]
+        del clips
+        btabs = [Batch.pointer_table([f[t] for f in bfr]) for t in range(T_CLIP)]
+        bb = Batch([(H, W)] * NB, Params(record_tape=T_CLIP))
+        bb.autotune(btabs[0], steps=3)
+        lib, bh = bb.lib, bb._handle
+        from ctypes import c_void_p
+        mptr = (c_void_p * NB)(*[m.data_ptr() for m in bmk])
+        bgrad = [torch.empty((T_CLIP, H, W), dtype=torch.float32, device=dev) for _ in range(NB)]
+        gptr = (c_void_p * NB)(*[x.data_ptr() for x in bgrad])
+        bloss = torch.empty(NB, dtype=torch.float32, device=dev)
+        bgw = torch.empty((NB, 8), dtype=torch.float32, device=dev)
+        bgq = torch.empty(NB, dtype=torch.float32, device=dev)
+        bgr = torch.empty(NB, dtype=torch.float32, device=dev)
+        tp = [t.data_ptr() for t in btabs]
+
+        def batch_fwd(_):
+            if lib.sp_batch_reset(bh):
+                raise RuntimeError(lib.sp_last_error().decode())
+            for t in range(T_CLIP):
+                if lib.sp_batch_step(bh, tp[t], None):
+                    raise RuntimeError(lib.sp_last_error().decode())
+
+        def batch_fb(_):
+            batch_fwd(0)
+            rc = lib.sp_batch_mse_mask_loss(bh, mptr, T_CLIP, bloss.data_ptr(), gptr)
+            rc |= lib.sp_batch_backward(bh, gptr, T_CLIP, bgw.data_ptr(), bgq.data_ptr(), bgr.data_ptr())
+            if rc:
+                raise RuntimeError(lib.sp_last_error().decode())
+
+        timed(batch_fb, 1)
+        reps = 3
+        dfb = timed(batch_fb, reps)
+        dfw = timed(batch_fwd, reps)
+        fbb = {"frames_per_s": round(reps * NB * T_CLIP / dfb, 2), "ms_per_clip_batch": round(dfb / reps * 1e3, 3),
+               "forward_with_tape_frames_per_s": round(reps * NB * T_CLIP / dfw, 2),
+               "streams": NB, "clip_frames": T_CLIP, "loss_mean": float(bloss.mean().item())}
+        if "profile" not in skip:
+            profile_enable(bb, True)
+            timed(batch_fb, 1)
+            pr = profile_read(bb)
+            profile_enable(bb, False)
+            fbb["kernels_ms_per_clip"] = {k: round(v[0], 3) for k, v in sorted(pr.items(), key=lambda kv: -kv[1][0])}
+            fbb["launches_per_clip"] = {k: v[1] for k, v in pr.items()}
+        bb.close()
+        del bfr, bmk, bgrad, btabs
+        torch.cuda.empty_cache()
+        log(f"batched fwd+bwd: {fbb['frames_per_s']} frames/s")
+
     # ------------------------------------------------------------ mixed batch of 64 streams of four sizes
     mixed = None
     if "mixed" not in skip:
@@ -398,10 +596,61 @@ def main():
                  "mpx_per_s": round(sum(hh * ww for hh, ww in sizes) * steps / dtm / 1e6, 1), "streams": 64}
         log(f"mixed: {mixed['frames_per_s']} frames/s")
 
+    # ------------------------------------------------------------ the named single-stream workloads
+    configs = None
+    if "configs" not in skip:
+        configs = {}
+        named = [
+            ("single_ellipse_160x120_x30", "single", 120, 160, 30, 0, Params(), False, 300),
+            ("three_ellipse_320x240_x300_mrf", "three", 240, 320, 300, 1,
+             Params(depth=6, centers=(2, 3), deltas=(3, 4)), True, 300),
+            ("five_ellipse_1920x1080", "five", 1080, 1920, 40, 5,
+             Params(depth=9, centers=(2, 3, 4), deltas=(3, 4)), False, 1000),
+            ("single_ellipse_352x288", "single", 288, 352, 30, 7, Params(), False, 300),
+            ("single_ellipse_480x384", "single", 384, 480, 30, 7, Params(), False, 300),
+            ("single_ellipse_640x512", "single", 512, 640, 30, 7, Params(), False, 300),
+        ]
+        log("generating the named clips")
+        drawn = gen_clips([(k, hh, ww, tt, sd) for _, k, hh, ww, tt, sd, _, _, _ in named])
+        for (name, kind, hh, ww, tt, sd, pp, mrf, nsteps), (fnp, _) in zip(named, drawn):
+            fr = torch.from_numpy(fnp).to(dev)
+            cx = Context(hh, ww, pp)
+            gg = cx.geometry
+            lib, ch = cx.lib, cx._handle
+            lib.sp_set_stream(ch, stream)
+            So = torch.empty((gg.Hc, gg.Wc), dtype=torch.float32, device=dev)
+            Po = torch.empty((hh, ww), dtype=torch.float32, device=dev)
+            Uo = torch.empty((2, hh, ww), dtype=torch.float32, device=dev) if mrf else None
+            PWo = torch.empty((4, hh, ww), dtype=torch.float32, device=dev) if mrf else None
+            Bo = torch.empty((1,), dtype=torch.float32, device=dev) if mrf else None
+            fpp = [fr[t].data_ptr() for t in range(tt)]
+
+            def cstep(i):
+                t = i % tt
+                if t == 0:
+                    lib.sp_reset(ch)
+                rc = lib.sp_step(ch, fpp[t], fpp[t - 1] if t else None, None, So.data_ptr(), None, Po.data_ptr(),
+                                 Uo.data_ptr() if mrf else None, PWo.data_ptr() if mrf else None,
+                                 Bo.data_ptr() if mrf else None)
+                if rc:
+                    raise RuntimeError(lib.sp_last_error().decode())
+
+            timed(cstep, 20)
+            dc = timed(cstep, nsteps)
+            configs[name] = {"frames_per_s": round(nsteps / dc, 2), "ms_per_frame": round(dc / nsteps * 1e3, 5),
+                             "H": hh, "W": ww, "depth": gg.depth, "pairs": gg.pairs, "mrf": mrf,
+                             "distinct_frames": tt, "steps_timed": nsteps}
+            cx.close()
+            del fr
+        log("configs: " + ", ".join(f"{k} {v['frames_per_s']}" for k, v in configs.items()))
+
     cpu = None
     if "cpu" not in skip:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(frames_np, args.cpu_seconds)
+        if "cpu_par" not in skip:
+            log("cpu baseline (oracle), one process per stream")
+            cpu["parallel"] = cpu_baseline_parallel(16, args.cpu_seconds)
 
     out = {
         "metric": "frames/s saliency+Kalman prior at 640x480 (fwd, fwd+bwd, batched); HBM GB/s",
@@ -426,6 +675,8 @@ def main():
         "autotune": tune_report.strip().splitlines(),
         "plain_640x480": plain,
         "fwd_bwd_640x480": fb,
+        "fwd_bwd_batched16_640x480": fbb,
+        "configs": configs,
         "batched_mixed64": mixed,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),

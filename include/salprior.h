@@ -183,7 +183,9 @@ int sp_set_state(sp_ctx* ctx, const void* dev_buf, size_t bytes);
 /* Batched form: n independent streams of possibly different sizes, one frame each per
  * step, every phase of the step in one launch over all streams, the step captured once
  * in a HIP graph and replayed.  Each stream keeps its Kalman state on the device.
- *   H[n], W[n]: host arrays.  p: shared parameters (record_tape must be 0).
+ *   H[n], W[n]: host arrays.  p: shared parameters.  With p->record_tape = T > 0 every
+ *   stream records an adjoint tape of up to T steps (sp_batch_backward); a step beyond
+ *   the tape fails with SP_ESTATE until sp_batch_reset.
  *   flags: SP_BATCH_MRF also computes every stream's MRF capacities each step into
  *   buffers the batch owns (read them with sp_batch_outputs); see also SP_BATCH_CONSP. */
 #define SP_BATCH_MRF 1
@@ -213,6 +215,40 @@ int sp_batch_consp(sp_batch* b, int32_t i, const float** C);
 int sp_batch_reset(sp_batch* b);
 int sp_batch_destroy(sp_batch* b);
 
+/* Channel weights w[8] and Kalman variances q, r (host values) shared by every stream
+ * of the batch.  Steps already recorded used the old values, so a tape holding any
+ * steps becomes invalid for sp_batch_backward until sp_batch_reset.  Synchronises. */
+int sp_batch_set_weights(sp_batch* b, const float* w, double q, double r);
+/* Steps run since the last reset (-1 for NULL), and a counter bumped by every reset,
+ * autotune and weight change (a caller holding a recorded clip can tell whether the
+ * tape still holds it). */
+int64_t sp_batch_step_index(const sp_batch* b);
+int64_t sp_batch_tape_generation(const sp_batch* b);
+
+/* Batched form of the adjoint (record_tape > 0).  The clip of every stream is the steps
+ * since the last sp_batch_reset; the recursion and its adjoint follow Section 6 as in
+ * saliency_backward, for each stream on its own.
+ *   sp_batch_tape_prior: device pointer to stream i's recorded priors [cap][H][W] (row t
+ *     holds the prior of step t).
+ *   sp_batch_mse_mask_loss: for every stream i, loss[i] = mean over [T][H][W] of
+ *     (prior - mask_i)^2 on its first T recorded priors (T <= steps recorded).
+ *     masks: HOST array of n device pointers, mask_i [T][H][W] uint8 in {0,1}.
+ *     loss: device [n] float.  grad_prior: HOST array of n device pointers receiving
+ *     dL_i/dprior [T][H][W] float, or NULL.
+ *   sp_batch_backward: gradients of every stream's loss L_i, given grad_prior (HOST array
+ *     of n device pointers, [T][H][W] float each, dL_i/dprior_t), for exactly T = the
+ *     steps recorded since the reset.  grad_w: device [n][8], grad_q, grad_r: device [n].
+ *     The conspicuity maps are recomputed from every stream's checkpointed level c_min,
+ *     a few frames of every stream per launch.
+ * The host arrays are read during the call; the device buffers must stay valid until
+ * the stream reaches the call's launches.  The tables the calls upload are staged in
+ * pinned host memory; refilling a stage waits for its previous upload. */
+int sp_batch_tape_prior(sp_batch* b, int32_t i, const float** prior);
+int sp_batch_mse_mask_loss(sp_batch* b, const uint8_t* const* masks, int32_t T, float* loss,
+                           float* const* grad_prior);
+int sp_batch_backward(sp_batch* b, const float* const* grad_prior, int32_t T, float* grad_w, float* grad_q,
+                      float* grad_r);
+
 /* Measurement hook: while enabled, every kernel launch of the context is bracketed by
  * a pair of HIP events recorded on the context's stream (one pair per launch, up to
  * 65536 pairs).  sp_profile_read synchronises the stream and returns, per kernel kind
@@ -225,6 +261,13 @@ int sp_profile_read(sp_ctx* ctx, int32_t n, float* total_ms, int32_t* launches);
  * step's phases one by one (the same kernels as the graph) bracketed by events. */
 int sp_batch_profile_enable(sp_batch* b, int32_t enable);
 int sp_batch_profile_read(sp_batch* b, int32_t n, float* total_ms, int32_t* launches);
+/* Measurement hook for HBM byte counters: copies `bytes` (a positive multiple of 16, at
+ * most 2 GiB) from device buffer src to device buffer dst on the given stream, with one
+ * of the access forms the kernels use: mode 0 = a 4-byte load and store per lane, 1 = a
+ * 16-byte load and store per lane, 2 = 4-byte direct global-to-LDS loads, then 4-byte
+ * stores from LDS.  A counter run over it reads against a known byte count. */
+int sp_calibration_copy(const void* src, void* dst, size_t bytes, int32_t mode, void* hip_stream);
+
 /* Name of the kernel behind kind k (static string; "" if out of range). */
 const char* sp_kernel_name(int32_t k);
 

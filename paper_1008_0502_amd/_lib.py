@@ -86,6 +86,13 @@ SIGNATURES = [
     ("sp_batch_consp", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
     ("sp_batch_reset", c_int32, [c_void_p]),
     ("sp_batch_destroy", c_int32, [c_void_p]),
+    ("sp_batch_set_weights", c_int32, [c_void_p, ctypes.POINTER(c_float), c_double, c_double]),
+    ("sp_batch_step_index", ctypes.c_int64, [c_void_p]),
+    ("sp_batch_tape_generation", ctypes.c_int64, [c_void_p]),
+    ("sp_batch_tape_prior", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
+    ("sp_batch_mse_mask_loss", c_int32, [c_void_p, ctypes.POINTER(c_void_p), c_int32, c_void_p,
+                                         ctypes.POINTER(c_void_p)]),
+    ("sp_batch_backward", c_int32, [c_void_p, ctypes.POINTER(c_void_p), c_int32, c_void_p, c_void_p, c_void_p]),
     ("sp_profile_enable", c_int32, [c_void_p, c_int32]),
     ("sp_profile_read", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_float), ctypes.POINTER(c_int32)]),
     ("sp_batch_autotune", c_int32, [c_void_p, c_void_p, c_int32, ctypes.c_char_p, c_size_t]),
@@ -95,6 +102,7 @@ SIGNATURES = [
     ("sp_set_tune", c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     ("sp_batch_set_tune", c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     ("sp_tune_cache_clear", c_int32, []),
+    ("sp_calibration_copy", c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_void_p]),
     ("sp_kernel_name", ctypes.c_char_p, [c_int32]),
     ("sp_last_error", ctypes.c_char_p, []),
 ]
@@ -133,3 +141,21 @@ def check(rc: int, where: str) -> None:
     if rc != SP_OK:
         msg = _LIB.sp_last_error().decode(errors="replace") if _LIB is not None else ""
         raise SalpriorError(rc, where, msg)
+
+
+_HIP = None
+
+
+def hip_copy_d2d(dst: int, src: int, nbytes: int, stream: int) -> None:
+    """Device-to-device copy enqueued on `stream` through the HIP runtime torch already
+    loaded (moves a library-owned buffer into a caller's tensor; no arithmetic)."""
+    global _HIP
+    if _HIP is None:
+        hip = ctypes.CDLL("libamdhip64.so.7")
+        hip.hipMemcpyAsync.restype = ctypes.c_int
+        hip.hipMemcpyAsync.argtypes = [c_void_p, c_void_p, c_size_t, ctypes.c_int, c_void_p]
+        _HIP = hip
+    rc = _HIP.hipMemcpyAsync(dst, src, nbytes, 3, stream)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+from ctypes import c_void_p
 from typing import List, Optional, Sequence, Tuple
 
 import torch
@@ -447,3 +448,101 @@ class Batch:
         ptr = ctypes.c_void_p()
         check(self.lib.sp_batch_consp(self._handle, int(i), ctypes.byref(ptr)), "sp_batch_consp")
         return ptr.value
+
+    # -- adjoint (params.record_tape > 0) -------------------------------------
+    @property
+    def step_index(self) -> int:
+        return int(self.lib.sp_batch_step_index(self._handle))
+
+    @property
+    def tape_generation(self) -> int:
+        return int(self.lib.sp_batch_tape_generation(self._handle))
+
+    def set_weights(self, weights: Sequence[float], q: float, r: float) -> None:
+        w = (ctypes.c_float * 8)(*[float(x) for x in weights])
+        check(self.lib.sp_batch_set_weights(self._handle, w, float(q), float(r)), "sp_batch_set_weights")
+        self.params = dataclasses.replace(self.params, weights=tuple(float(x) for x in weights), q=q, r=r)
+
+    def tape_prior_pointer(self, i: int) -> int:
+        """Device pointer (int) of stream i's recorded priors [record_tape][H][W]."""
+        ptr = ctypes.c_void_p()
+        check(self.lib.sp_batch_tape_prior(self._handle, int(i), ctypes.byref(ptr)), "sp_batch_tape_prior")
+        return ptr.value
+
+    def tape_priors(self, i: int, T: int) -> torch.Tensor:
+        """Copy of stream i's first T recorded priors as a [T][H][W] tensor."""
+        H, W = self.sizes[i]
+        out = torch.empty((T, H, W), dtype=torch.float32, device=self.device)
+        _lib.hip_copy_d2d(out.data_ptr(), self.tape_prior_pointer(i), out.numel() * 4, _stream())
+        return out
+
+    def mse_mask_loss(self, masks: Sequence[torch.Tensor], T: int, want_grad: bool = True):
+        """Per-stream masked MSE of the first T recorded priors; masks[i]: uint8 [T][H][W].
+        Returns (loss [n], list of dL_i/dprior [T][H][W] or None)."""
+        n = len(self.sizes)
+        if len(masks) != n:
+            raise ValueError(f"{n} masks are required")
+        for i, (H, W) in enumerate(self.sizes):
+            _need(masks[i], f"masks[{i}]", torch.uint8, (T, H, W), self.device)
+        loss = torch.empty(n, dtype=torch.float32, device=self.device)
+        grads = [torch.empty((T, H, W), dtype=torch.float32, device=self.device) for H, W in self.sizes] \
+            if want_grad else None
+        mp = (c_void_p * n)(*[m.data_ptr() for m in masks])
+        gp = (c_void_p * n)(*[g.data_ptr() for g in grads]) if grads is not None else None
+        check(self.lib.sp_batch_mse_mask_loss(self._handle, mp, int(T), _ptr(loss), gp), "sp_batch_mse_mask_loss")
+        return loss, grads
+
+    def backward(self, grad_priors: Sequence[torch.Tensor]):
+        """Adjoint of every stream's recorded clip; grad_priors[i]: [T][H][W] float.
+        Returns per-stream gradients (grad_w [n][8], grad_q [n], grad_r [n])."""
+        n = len(self.sizes)
+        if len(grad_priors) != n:
+            raise ValueError(f"{n} gradient tensors are required")
+        T = grad_priors[0].shape[0]
+        for i, (H, W) in enumerate(self.sizes):
+            _need(grad_priors[i], f"grad_priors[{i}]", torch.float32, (T, H, W), self.device)
+        gw = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        gq = torch.empty(n, dtype=torch.float32, device=self.device)
+        gr = torch.empty(n, dtype=torch.float32, device=self.device)
+        gp = (c_void_p * n)(*[g.data_ptr() for g in grad_priors])
+        check(self.lib.sp_batch_backward(self._handle, gp, int(T), _ptr(gw), _ptr(gq), _ptr(gr)),
+              "sp_batch_backward")
+        return gw, gq, gr
+
+
+class BatchSaliencyPrior(torch.autograd.Function):
+    """(prior_0, ..., prior_{n-1}) = path of every stream of a Batch over T steps, each
+    prior_i [T][H_i][W_i], differentiable in the weights w (8) and variances q, r that
+    every stream shares.
+
+    forward(ctx_obj, batch, tables, w, q, r): batch created with record_tape >= T;
+    tables: T device pointer tables (Batch.pointer_table), one per step.  The backward
+    runs the batched hand-written adjoint and adds up the streams' gradients of the
+    shared parameters."""
+
+    @staticmethod
+    def forward(ctx, b: "Batch", tables, w: torch.Tensor, q: torch.Tensor, r: torch.Tensor):
+        b.set_weights(w.detach().float().cpu().tolist(), float(q), float(r))
+        b.reset()
+        for tab in tables:
+            b.step(tab)
+        T = len(tables)
+        outs = tuple(b.tape_priors(i, T) for i in range(len(b.sizes)))
+        ctx.b = b
+        ctx.T = T
+        ctx.gen = b.tape_generation
+        ctx.meta = [(x.device, x.dtype, x.shape) for x in (w, q, r)]
+        return outs
+
+    @staticmethod
+    def backward(ctx, *grads):
+        b: Batch = ctx.b
+        if b.tape_generation != ctx.gen:
+            raise RuntimeError("BatchSaliencyPrior.backward: the batch was reset, stepped again or re-weighted "
+                               "after this forward; its tape no longer holds this graph")
+        gp = [torch.zeros((ctx.T, H, W), dtype=torch.float32, device=b.device) if g is None
+              else g.contiguous().float() for g, (H, W) in zip(grads, b.sizes)]
+        gw, gq, gr = b.backward(gp)
+        tot = (gw.sum(0), gq.sum(), gr.sum())
+        out = [g.to(device=d, dtype=t).reshape(s) for g, (d, t, s) in zip(tot, ctx.meta)]
+        return None, None, out[0], out[1], out[2]

@@ -571,8 +571,7 @@ struct sp_ctx {
   int n_lvl0_tiles = 0;
   int CH = 0;                     // frames per recompute chunk
   StreamDesc* d_rsd = nullptr;    // [CH] recompute streams
-  StepIO* d_rio = nullptr;        // [cap] io of every tape frame (ckpt pointers)
-  int* d_frame_ids = nullptr;     // [cap] = 0..cap-1
+  StepIO* d_rio = nullptr;        // [cap] io of every tape frame (checkpoint and adjoint buffers)
   std::vector<Phase> rec;         // recompute phases (stream-major, CH streams)
   float* S_scratch = nullptr;     // [Hc][Wc] saliency map of the autotuner's steps
   // loss helper
@@ -744,7 +743,6 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
       c->gK_scratch = b.take<double>(c->cap);
       c->d_rsd = b.take<StreamDesc>(c->CH);
       c->d_rio = b.take<StepIO>(c->cap);
-      c->d_frame_ids = b.take<int>(c->cap);
       for (int i = 0; i < c->CH; ++i) layout_stream(rsd[i], g, *p, b, g.c_min + 1, false);
     }
     if (pass == 0) {
@@ -760,17 +758,18 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
       if (e == hipSuccess && c->cap > 0) {
         e = hipMemcpyAsync(c->d_rsd, rsd.data(), sizeof(StreamDesc) * c->CH, hipMemcpyHostToDevice, c->stream);
         std::vector<StepIO> rio(c->cap);
-        std::vector<int> ids(c->cap);
         const size_t cstride = (size_t)4 * g.Hl[g.c_min] * g.Wl[g.c_min];
+        const size_t plane = (size_t)Hc * Wc;
         for (int t = 0; t < c->cap; ++t) {
           std::memset(&rio[t], 0, sizeof(StepIO));
           rio[t].ckpt = c->ckpt + (size_t)t * cstride;
-          ids[t] = t;
+          rio[t].gs = c->gs_all + (size_t)t * plane;
+          rio[t].ms_tape = c->ms_tape + 2 * (size_t)t;
+          rio[t].dot = c->dot_part + (size_t)t * c->h_sd.n_cmax_tiles * SP_NCH;
+          rio[t].cx = c->cx + (size_t)t * SP_NCH;
         }
         if (e == hipSuccess)
           e = hipMemcpyAsync(c->d_rio, rio.data(), sizeof(StepIO) * c->cap, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-          e = hipMemcpyAsync(c->d_frame_ids, ids.data(), sizeof(int) * c->cap, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       }
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1228,23 +1227,20 @@ int saliency_backward(sp_ctx* c, const float* grad_prior, int32_t T, float* grad
   for (int t0 = 0; t0 < T; t0 += c->CH) {
     const int n = std::min(c->CH, T - t0);
     const StepIO* ios = c->d_rio + t0;
-    const int* fid = c->d_frame_ids + t0;
     for (const Phase& ph : c->rec) {
       const int nj = ph.upto[n];
       hipError_t e = timed(c, ph.kind, [&] {
-        if (ph.kind == JOB_CONSP_DOT)
-          return sp_launch_consp_dot(c->jobs.dev + ph.off, nj, c->d_rsd, ios, c->gs_all, c->ms_tape, fid,
-                                     c->dot_part, c->cx, c->stream);
+        if (ph.kind == JOB_CONSP_DOT) return sp_launch_consp_dot(c->jobs.dev + ph.off, nj, c->d_rsd, ios, c->stream);
         return sp_launch(ph.kind, c->jobs.dev + ph.off, nj, c->d_rsd, ios, nullptr, ph.flag, nullptr, c->stream, ph.lds);
       });
       if (e != hipSuccess) return fail(SP_EHIP, "recompute launch: %s", hipGetErrorString(e));
     }
   }
   const float* wdev = reinterpret_cast<const float*>(reinterpret_cast<const char*>(c->d_sd) + offsetof(StreamDesc, w));
+  BwdFin fin{c->gk_part, c->dot_part, c->cx, c->ms_tape, wdev, c->gK_scratch, grad_w, grad_q, grad_r,
+             c->n_lvl0_tiles, c->h_sd.n_cmax_tiles};
   hipError_t e = timed(c, JOB_BWD_FINAL, [&] {
-    return sp_launch_bwd_final(T, c->n_lvl0_tiles, c->h_sd.n_cmax_tiles, c->gk_part, c->dot_part, c->cx,
-                               c->ms_tape, c->K_tape, c->P_tape, c->p.q, c->p.r, wdev, c->p.flat_tol,
-                               c->gK_scratch, grad_w, grad_q, grad_r, c->stream);
+    return sp_launch_bwd_final(nullptr, &fin, 1, T, c->K_tape, c->P_tape, c->p.q, c->p.r, c->p.flat_tol, c->stream);
   });
   if (e != hipSuccess) return fail(SP_EHIP, "adjoint reduction launch: %s", hipGetErrorString(e));
   return SP_OK;
@@ -1256,9 +1252,8 @@ int sp_mse_mask_loss(sp_ctx* c, const float* prior, const uint8_t* mask, int32_t
   if (T < 1) return fail(SP_EINVAL, "T must be >= 1");
   const size_t n = (size_t)T * c->g.H * c->g.W;
   const int nblk = (int)std::min<size_t>(c->loss_nblk, (n + SP_BLOCK - 1) / SP_BLOCK);
-  hipError_t e = timed(c, JOB_LOSS, [&] {
-    return sp_launch_loss(prior, mask, n, grad_prior, c->loss_part, nblk, loss, c->stream);
-  });
+  const LossIO L{prior, mask, grad_prior, c->loss_part, loss, (unsigned long long)n};
+  hipError_t e = timed(c, JOB_LOSS, [&] { return sp_launch_loss(nullptr, &L, 1, nblk, c->stream); });
   if (e != hipSuccess) return fail(SP_EHIP, "loss launch: %s", hipGetErrorString(e));
   return SP_OK;
 }
@@ -1317,6 +1312,18 @@ int sp_profile_read(sp_ctx* c, int32_t n, float* total_ms, int32_t* launches) {
   return c->prof.read(c->stream, n, total_ms, launches);
 }
 
+int sp_calibration_copy(const void* src, void* dst, size_t bytes, int32_t mode, void* hip_stream) {
+  g_err.clear();
+  if (!src || !dst) return fail(SP_EINVAL, "src and dst must not be NULL");
+  if (bytes == 0 || bytes % 16 != 0 || bytes > (size_t(1) << 31))
+    return fail(SP_EINVAL, "bytes must be a positive multiple of 16, at most 2 GiB");
+  if (mode < 0 || mode > 2) return fail(SP_EINVAL, "mode must be 0, 1 or 2");
+  hipError_t e = sp_launch_calib(static_cast<const float*>(src), static_cast<float*>(dst), bytes / 16, mode,
+                                 (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(SP_EHIP, "calibration launch: %s", hipGetErrorString(e));
+  return SP_OK;
+}
+
 const char* sp_kernel_name(int32_t k) {
   // launch kinds: a pyramid launch is timed under the kind of its phase (k_pyr small
   // for DOWN/GABOR stages, k_pyr tail for the final stage with tail jobs)
@@ -1330,6 +1337,55 @@ const char* sp_kernel_name(int32_t k) {
 }  // extern "C"
 
 // ---------------------------------------------------------------- batched step
+// Adjoint buffers of one stream of a batch with a tape.
+struct BatchAdj {
+  float* nu[2];        // [H][W] masked adjoint ping-pong
+  float* gu;           // [H][W] adjoint of the unclamped observation
+  float* gs_all;       // [cap][Hc][Wc]
+  float* gk_part;      // [cap][n_lvl0_tiles]
+  float* dot_part;     // [cap][n_cmax_tiles][8]
+  float* cx;           // [cap][8]
+  double* gK;          // [cap]
+  float* loss_part;    // [loss_nblk]
+  int n_lvl0_tiles;
+};
+
+// Pinned host buffer for a table uploaded asynchronously.  Refilling waits for the event
+// recorded after the last upload, so the copy engine has consumed it first.
+struct HostStage {
+  char* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  int init(size_t n) {
+    if (hipHostMalloc((void**)&host, std::max<size_t>(n, 256), 0) != hipSuccess) {
+      (void)hipGetLastError();
+      host = nullptr;
+      return fail(SP_ENOMEM, "hipHostMalloc of %zu bytes failed", n);
+    }
+    bytes = n;
+    HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    return SP_OK;
+  }
+  int acquire() {
+    if (pending) HIPCHK(hipEventSynchronize(done));
+    pending = false;
+    return SP_OK;
+  }
+  int upload(void* dev, size_t n, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(dev, host, n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(done, st));
+    pending = true;
+    return SP_OK;
+  }
+  void destroy() {
+    if (done) (void)hipEventDestroy(done);
+    if (host) (void)hipHostFree(host);
+    done = nullptr;
+    host = nullptr;
+  }
+};
+
 struct sp_batch {
   sp_params p{};
   int n = 0;
@@ -1355,9 +1411,91 @@ struct sp_batch {
   std::vector<Tune> tune;   // per stream
   bool xcd = false;
   int ca_nc = 2;            // preferred channels per across-scale workgroup (one value per launch)
+  // tape and adjoint (record_tape > 0): every stream records the same steps
+  int cap = 0;              // frames each stream's tape holds
+  int CH = 0;               // frames of every stream per recompute chunk
+  bool tape_ok = true;      // false once the weights changed after recorded steps
+  long long tape_gen = 0;   // bumped whenever the recorded clip stops being the current one
+  std::vector<BatchAdj> adj;                  // per stream: adjoint buffers
+  std::vector<StreamDesc> h_rsd;              // [CH * n] recompute streams (v = j * n + i)
+  StreamDesc* d_rsd = nullptr;
+  StepIO* d_rio = nullptr;                    // [cap][n] checkpoint and adjoint buffers of each frame
+  char* d_bstage = nullptr;                   // gains, variances, [cap][n] BwdIO, [n] BwdFin
+  char* d_lstage = nullptr;                   // [n] LossIO
+  HostStage bstage, lstage;                   // pinned host copies of the two tables
+  std::vector<Phase> bwd, rec;                // adjoint sweep (2 launches per step), recompute program
+  int loss_nblk = 1024;
 };
 
 namespace {
+
+// Job tables of the batched adjoint: the level-0 sweep and the up-sample transpose over
+// every stream (one launch each per reverse step), and the recompute program over the
+// CH * n recompute streams of a chunk (recompute stream v = j * n + i takes frame t0 + j of
+// stream i).  Each phase lists its jobs in recompute-stream order, so a chunk of rem < CH
+// frames launches the prefix of rem * n streams.  Streams of different sizes may have
+// different numbers of pyramid stages: middle stages are merged by index and every final
+// stage goes to one last pyramid launch (its kernel handles every pyramid job kind).
+void batch_adjoint_tables(sp_batch* b, int nc, size_t lds_a, size_t lds_g) {
+  const int n = b->n, nv = b->CH * n;
+  std::vector<Job> nu, gs;
+  for (int i = 0; i < n; ++i) {
+    const Geo& g = b->geo[i];
+    add_tiles(nu, i, 0, g.H, g.W);
+    add_tiles(gs, i, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
+  }
+  b->bwd.clear();
+  b->bwd.push_back(b->jobs.add(JOB_BWD_NU, 0, nu, n));
+  b->bwd.push_back(b->jobs.add(JOB_BWD_GS, 0, gs, n));
+  std::vector<std::vector<Job>> mids;
+  std::vector<Job> fin, css, csg, csf, csa, csm, dot;
+  bool any_tail = false;
+  int set = 1;
+  for (int v = 0; v < nv; ++v) {
+    const int i = v % n;
+    const Geo& g = b->geo[i];
+    std::vector<std::vector<Job>> parts;
+    std::vector<int> kinds;
+    build_forward_jobs(parts, kinds, b->h_rsd[v], g, v, PROG_RECOMPUTE, nc);
+    size_t np = 0;   // leading pyramid stages; the last of them is the final one
+    while (np < parts.size() && (kinds[np] == JOB_DOWN || kinds[np] == JOB_TAIL)) ++np;
+    for (size_t k = 0; k + 1 < np; ++k) {
+      if (mids.size() <= k) mids.resize(k + 1);
+      mids[k].insert(mids[k].end(), parts[k].begin(), parts[k].end());
+    }
+    if (np > 0) {
+      fin.insert(fin.end(), parts[np - 1].begin(), parts[np - 1].end());
+      any_tail |= kinds[np - 1] == JOB_TAIL;
+    }
+    for (size_t k = np; k < parts.size(); ++k) {
+      std::vector<Job>* dst = nullptr;
+      switch (kinds[k]) {
+        case JOB_CSSTATS: dst = &css; break;
+        case JOB_CSG: dst = &csg; set = std::min(set, csg_set(g)); break;
+        case JOB_CSFINAL: dst = &csf; break;
+        case JOB_CSAPPLY: dst = &csa; break;
+        case JOB_CSMIX: dst = &csm; break;
+        default: dst = &dot; break;
+      }
+      dst->insert(dst->end(), parts[k].begin(), parts[k].end());
+    }
+  }
+  b->rec.clear();
+  for (auto& m : mids) b->rec.push_back(b->jobs.add(JOB_DOWN, b->p.gabor_radius, m, nv));
+  if (!fin.empty()) b->rec.push_back(b->jobs.add(any_tail ? JOB_TAIL : JOB_DOWN, b->p.gabor_radius, fin, nv));
+  if (!css.empty()) b->rec.push_back(b->jobs.add(JOB_CSSTATS, 0, css, nv));
+  if (!csg.empty()) {
+    b->rec.push_back(b->jobs.add(JOB_CSG, nc | (set << 8), csg, nv));
+    b->rec.back().lds = nc * lds_g;
+  }
+  b->rec.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, nv));
+  if (!csa.empty()) {
+    b->rec.push_back(b->jobs.add(JOB_CSAPPLY, nc, csa, nv));
+    b->rec.back().lds = nc * lds_a;
+  }
+  if (!csm.empty()) b->rec.push_back(b->jobs.add(JOB_CSMIX, 0, csm, nv));
+  b->rec.push_back(b->jobs.add(JOB_CONSP_DOT, 0, dot, nv));
+}
 
 // (Re)builds the batch's phase program: one launch per phase over every stream.  Drops
 // the captured graph, which is captured again on the next step.
@@ -1459,6 +1597,7 @@ int batch_build_tables(sp_batch* b) {
   if (!csm.empty()) b->phases.push_back(b->jobs.add(JOB_CSMIX, 0, order(csm), n));
   b->phases.push_back(b->jobs.add(JOB_CONSP, 0, order(cons), n));
   b->phases.push_back(b->jobs.add(JOB_KALMAN, 0, order(kal), n));
+  if (b->cap > 0) batch_adjoint_tables(b, nc, lds_a, lds_g);
   return upload_jobs(b->jobs, b->stream);
 }
 
@@ -1544,6 +1683,8 @@ void batch_free(sp_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   b->prof.destroy();
+  b->bstage.destroy();
+  b->lstage.destroy();
   if (b->arena) (void)hipFree(b->arena);
   if (b->jobs.dev) (void)hipFree(b->jobs.dev);
   delete b;
@@ -1562,7 +1703,6 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
   if (!H || !W) return fail(SP_EINVAL, "H and W must not be NULL");
   int rc = validate_params(p);
   if (rc) return rc;
-  if (p->record_tape != 0) return fail(SP_EINVAL, "the batched step keeps no tape (record_tape must be 0)");
   if (flags & ~(SP_BATCH_MRF | SP_BATCH_CONSP)) return fail(SP_EINVAL, "unknown batch flags 0x%x", flags);
   const bool mrf = (flags & SP_BATCH_MRF) != 0;
   const bool consp = (flags & SP_BATCH_CONSP) != 0;
@@ -1581,6 +1721,14 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
   }
   b->h_sd.resize(n);
   b->h_st.resize(n);
+  b->cap = p->record_tape;
+  // recompute chunks of about 64 recompute streams (at least one frame per stream)
+  b->CH = b->cap > 0 ? std::max(1, std::min({b->cap, 32, (64 + n - 1) / n})) : 0;
+  b->adj.resize(b->cap > 0 ? n : 0);
+  b->h_rsd.resize((size_t)b->CH * n);
+  const size_t bstage_bytes = b->cap > 0 ? 2 * sizeof(double) * b->cap + sizeof(BwdIO) * (size_t)b->cap * n +
+                                               sizeof(BwdFin) * n : 0;
+  const size_t lstage_bytes = b->cap > 0 ? sizeof(LossIO) * n : 0;
   size_t bytes = 0;
   for (int pass = 0; pass < 2; ++pass) {
     Bump bm;
@@ -1600,10 +1748,40 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
         s.beta = bm.take<float>(1);
       }
       if (consp) s.C = bm.take<float>((size_t)SP_NCH * g.Hl[g.c_max] * g.Wl[g.c_max]);
+      if (b->cap > 0) {
+        const size_t cap = (size_t)b->cap, hw = (size_t)g.H * g.W, plane = (size_t)g.Hl[g.c_max] * g.Wl[g.c_max];
+        s.tape_cap = b->cap;
+        s.tape_ckpt = bm.take<float>(cap * 4 * g.Hl[g.c_min] * g.Wl[g.c_min]);
+        s.tape_S = bm.take<float>(cap * plane);
+        s.tape_f = bm.take<float>(cap * hw);
+        s.tape_ms = bm.take<float>(cap * 2);
+        s.tape_pi = bm.take<float>(cap * hw);
+        BatchAdj& a = b->adj[i];
+        a.n_lvl0_tiles = ntiles(g.H, g.W);
+        a.nu[0] = bm.take<float>(hw);
+        a.nu[1] = bm.take<float>(hw);
+        a.gu = bm.take<float>(hw);
+        a.gs_all = bm.take<float>(cap * plane);
+        a.gk_part = bm.take<float>(cap * a.n_lvl0_tiles);
+        a.dot_part = bm.take<float>(cap * b->h_sd[i].n_cmax_tiles * SP_NCH);
+        a.cx = bm.take<float>(cap * SP_NCH);
+        a.gK = bm.take<double>(cap);
+        a.loss_part = bm.take<float>(b->loss_nblk);
+      }
     }
     b->d_sd = bm.take<StreamDesc>(n);
     b->d_io = bm.take<StepIO>(n);
     b->d_st = bm.take<BatchState>(n);
+    if (b->cap > 0) {
+      b->d_rsd = bm.take<StreamDesc>(b->h_rsd.size());
+      b->d_rio = bm.take<StepIO>((size_t)b->cap * n);
+      b->d_bstage = bm.take<char>(bstage_bytes);
+      b->d_lstage = bm.take<char>(lstage_bytes);
+      for (size_t v = 0; v < b->h_rsd.size(); ++v) {
+        const Geo& g = b->geo[v % n];
+        layout_stream(b->h_rsd[v], g, *p, bm, g.c_min + 1, false);
+      }
+    }
     if (pass == 0) {
       bytes = bm.off + 256;
       if (hipMalloc(&b->arena, bytes) != hipSuccess) {
@@ -1635,10 +1813,34 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
   }
   hipError_t e = hipMemcpy(b->d_sd, b->h_sd.data(), sizeof(StreamDesc) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_st, b->h_st.data(), sizeof(BatchState) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess && b->cap > 0) {
+    e = hipMemcpy(b->d_rsd, b->h_rsd.data(), sizeof(StreamDesc) * b->h_rsd.size(), hipMemcpyHostToDevice);
+    std::vector<StepIO> rio((size_t)b->cap * n);
+    for (int t = 0; t < b->cap; ++t)
+      for (int i = 0; i < n; ++i) {
+        const Geo& g = b->geo[i];
+        const BatchState& s = b->h_st[i];
+        const BatchAdj& a = b->adj[i];
+        StepIO& io = rio[(size_t)t * n + i];
+        std::memset(&io, 0, sizeof io);
+        io.ckpt = s.tape_ckpt + (size_t)t * 4 * g.Hl[g.c_min] * g.Wl[g.c_min];
+        io.gs = a.gs_all + (size_t)t * g.Hl[g.c_max] * g.Wl[g.c_max];
+        io.ms_tape = s.tape_ms + 2 * (size_t)t;
+        io.dot = a.dot_part + (size_t)t * b->h_sd[i].n_cmax_tiles * SP_NCH;
+        io.cx = a.cx + (size_t)t * SP_NCH;
+      }
+    if (e == hipSuccess) e = hipMemcpy(b->d_rio, rio.data(), sizeof(StepIO) * rio.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     batch_free(b);
     return fail(SP_EHIP, "batch set-up: %s", hipGetErrorString(e));
+  }
+  if (b->cap > 0 && (b->bstage.init(bstage_bytes) || b->lstage.init(lstage_bytes))) {
+    std::string msg = g_err;
+    batch_free(b);
+    g_err = msg;
+    return SP_ENOMEM;
   }
   *out = b;
   return SP_OK;
@@ -1647,6 +1849,9 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
 int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* prior_ptrs) {
   g_err.clear();
   if (!b || !rgb_ptrs) return fail(SP_EINVAL, "batch and rgb_ptrs must not be NULL");
+  if (b->cap > 0 && b->steps >= b->cap)
+    return fail(SP_ESTATE, "the tape holds %d frames per stream; call sp_batch_reset before step %lld", b->cap,
+                (long long)b->steps);
   if (b->prof.on) {
     // measurement: the same phases, launched one by one with events around each
     int rc = batch_enqueue(b, b->stream, rgb_ptrs);
@@ -1709,6 +1914,8 @@ int sp_batch_reset(sp_batch* b) {
   hipError_t e = sp_launch_batch_reset(b->n, b->d_st, b->stream);
   if (e != hipSuccess) return fail(SP_EHIP, "reset launch: %s", hipGetErrorString(e));
   b->steps = 0;
+  b->tape_ok = true;
+  b->tape_gen += 1;
   return SP_OK;
 }
 
@@ -1825,6 +2032,8 @@ int sp_batch_autotune(sp_batch* b, const uint8_t* const* rgb_ptrs, int32_t steps
   hipError_t e = sp_launch_batch_reset(b->n, b->d_st, b->stream);
   if (e != hipSuccess) return fail(SP_EHIP, "reset launch: %s", hipGetErrorString(e));
   b->steps = 0;
+  b->tape_ok = true;
+  b->tape_gen += 1;
   HIPCHK(hipStreamSynchronize(b->stream));
   return SP_OK;
 }
@@ -1841,6 +2050,160 @@ int sp_batch_set_tune(sp_batch* b, int32_t kalman_tw, int32_t xcd_order, int32_t
   b->xcd = xcd_order != 0;
   b->ca_nc = channels;
   return batch_build_tables(b);
+}
+
+int sp_batch_set_weights(sp_batch* b, const float* w, double q, double r) {
+  g_err.clear();
+  if (!b || !w) return fail(SP_EINVAL, "NULL argument");
+  for (int k = 0; k < SP_NCH; ++k)
+    if (!std::isfinite(w[k])) return fail(SP_EINVAL, "weight %d is not finite", k);
+  if (!is_fin(q) || !is_fin(r) || q < 0 || r < 0 || !(q + r > 0))
+    return fail(SP_EINVAL, "Kalman variances must be finite, >= 0 and not both 0");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (int k = 0; k < SP_NCH; ++k) b->p.weights[k] = w[k];
+  b->p.q = q;
+  b->p.r = r;
+  for (StreamDesc& sd : b->h_sd)
+    for (int k = 0; k < SP_NCH; ++k) sd.w[k] = w[k];
+  for (StreamDesc& sd : b->h_rsd)
+    for (int k = 0; k < SP_NCH; ++k) sd.w[k] = w[k];
+  HIPCHK(hipMemcpy(b->d_sd, b->h_sd.data(), sizeof(StreamDesc) * b->n, hipMemcpyHostToDevice));
+  if (b->d_rsd)
+    HIPCHK(hipMemcpy(b->d_rsd, b->h_rsd.data(), sizeof(StreamDesc) * b->h_rsd.size(), hipMemcpyHostToDevice));
+  b->in_node = nullptr;   // the graph's first node carries Q and R: point it again at the next step
+  if (b->steps > 0) b->tape_ok = false;
+  b->tape_gen += 1;
+  return SP_OK;
+}
+
+int64_t sp_batch_tape_generation(const sp_batch* b) { return b ? b->tape_gen : -1; }
+
+int64_t sp_batch_step_index(const sp_batch* b) { return b ? b->steps : -1; }
+
+int sp_batch_tape_prior(sp_batch* b, int32_t i, const float** prior) {
+  g_err.clear();
+  if (!b || !prior) return fail(SP_EINVAL, "NULL argument");
+  if (i < 0 || i >= b->n) return fail(SP_EINVAL, "stream index %d out of range", i);
+  if (b->cap <= 0) return fail(SP_ESTATE, "the batch was created without a tape (record_tape = 0)");
+  *prior = b->h_st[i].tape_pi;
+  return SP_OK;
+}
+
+int sp_batch_mse_mask_loss(sp_batch* b, const uint8_t* const* masks, int32_t T, float* loss,
+                           float* const* grad_prior) {
+  g_err.clear();
+  if (!b || !masks || !loss) return fail(SP_EINVAL, "NULL argument");
+  if (b->cap <= 0) return fail(SP_ESTATE, "the batch was created without a tape (record_tape = 0)");
+  if (T < 1 || T > b->steps || T > b->cap)
+    return fail(SP_ESTATE, "loss over %d steps, but %lld are recorded since the reset", T, (long long)b->steps);
+  const int n = b->n;
+  size_t most = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!masks[i]) return fail(SP_EINVAL, "mask of stream %d is NULL", i);
+    if (grad_prior && !grad_prior[i]) return fail(SP_EINVAL, "grad_prior of stream %d is NULL", i);
+    most = std::max(most, (size_t)T * b->geo[i].H * b->geo[i].W);
+  }
+  int rc = b->lstage.acquire();
+  if (rc) return rc;
+  LossIO* tab = reinterpret_cast<LossIO*>(b->lstage.host);
+  for (int i = 0; i < n; ++i)
+    tab[i] = LossIO{b->h_st[i].tape_pi, masks[i], grad_prior ? grad_prior[i] : nullptr, b->adj[i].loss_part, loss + i,
+                    (unsigned long long)T * b->geo[i].H * b->geo[i].W};
+  rc = b->lstage.upload(b->d_lstage, sizeof(LossIO) * n, b->stream);
+  if (rc) return rc;
+  const int nblk = (int)std::min<size_t>(b->loss_nblk, (most + SP_BLOCK - 1) / SP_BLOCK);
+  hipError_t e = b->prof.timed(b->stream, JOB_LOSS, [&] {
+    return sp_launch_loss(reinterpret_cast<const LossIO*>(b->d_lstage), nullptr, n, nblk, b->stream);
+  });
+  if (e != hipSuccess) return fail(SP_EHIP, "loss launch: %s", hipGetErrorString(e));
+  return SP_OK;
+}
+
+int sp_batch_backward(sp_batch* b, const float* const* grad_prior, int32_t T, float* grad_w, float* grad_q,
+                      float* grad_r) {
+  g_err.clear();
+  if (!b || !grad_prior || !grad_w || !grad_q || !grad_r) return fail(SP_EINVAL, "NULL argument");
+  if (b->cap <= 0) return fail(SP_ESTATE, "the batch was created without a tape (record_tape = 0)");
+  if (!b->tape_ok) return fail(SP_ESTATE, "tape invalidated by sp_batch_set_weights after recorded steps; reset");
+  if (T < 1 || T != b->steps || T > b->cap)
+    return fail(SP_ESTATE, "backward of %d steps, but %lld steps were recorded since the reset", T,
+                (long long)b->steps);
+  const int n = b->n;
+  for (int i = 0; i < n; ++i)
+    if (!grad_prior[i]) return fail(SP_EINVAL, "grad_prior of stream %d is NULL", i);
+  // tables: the gains and variances (FP64, the device's own recursion), one BwdIO per
+  // stream and step, one BwdFin per stream
+  int rc = b->bstage.acquire();
+  if (rc) return rc;
+  char* h = b->bstage.host;
+  double* Kd = reinterpret_cast<double*>(h);
+  double* Pd = Kd + b->cap;
+  BwdIO* bio = reinterpret_cast<BwdIO*>(Pd + b->cap);
+  BwdFin* fin = reinterpret_cast<BwdFin*>(bio + (size_t)b->cap * n);
+  {
+    double P = 0.0;
+    for (int t = 0; t < T; ++t) Kd[t] = now_gain(t, P, b->p.q, b->p.r, &P), Pd[t] = P;
+  }
+  const float* wdev0 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(b->d_sd) + offsetof(StreamDesc, w));
+  for (int i = 0; i < n; ++i) {
+    const Geo& g = b->geo[i];
+    const BatchState& s = b->h_st[i];
+    const BatchAdj& a = b->adj[i];
+    const size_t hw = (size_t)g.H * g.W, plane = (size_t)g.Hl[g.c_max] * g.Wl[g.c_max];
+    for (int t = 0; t < T; ++t) {
+      BwdIO& o = bio[(size_t)t * n + i];
+      std::memset(&o, 0, sizeof o);
+      o.grad = grad_prior[i] + (size_t)t * hw;
+      o.nu_next = (t + 1 < T) ? a.nu[(t + 1) & 1] : nullptr;
+      o.nu_out = a.nu[t & 1];
+      o.gu = a.gu;
+      o.gs = a.gs_all + (size_t)t * plane;
+      o.gk_part = a.gk_part + (size_t)t * a.n_lvl0_tiles;
+      o.f = (t > 0) ? s.tape_f + (size_t)t * hw : nullptr;
+      o.S = s.tape_S + (size_t)t * plane;
+      o.ms = s.tape_ms + 2 * (size_t)t;
+      o.K = (t > 0) ? (float)Kd[t] : 1.f;
+      o.carry = (t + 1 < T) ? 1.f - (float)Kd[t + 1] : 0.f;   // every later step read the previous prior
+      o.t = t;
+    }
+    const float* wdev = reinterpret_cast<const float*>(reinterpret_cast<const char*>(wdev0) + sizeof(StreamDesc) * i);
+    fin[i] = BwdFin{a.gk_part, a.dot_part, a.cx, s.tape_ms, wdev, a.gK, grad_w + (size_t)SP_NCH * i, grad_q + i,
+                    grad_r + i, a.n_lvl0_tiles, b->h_sd[i].n_cmax_tiles};
+  }
+  rc = b->bstage.upload(b->d_bstage, b->bstage.bytes, b->stream);
+  if (rc) return rc;
+  const double* dKd = reinterpret_cast<const double*>(b->d_bstage);
+  const double* dPd = dKd + b->cap;
+  const BwdIO* dbio = reinterpret_cast<const BwdIO*>(dPd + b->cap);
+  const BwdFin* dfin = reinterpret_cast<const BwdFin*>(dbio + (size_t)b->cap * n);
+  // reverse sweep: per step one launch of the level-0 adjoint and one of the up-sample
+  // transpose, each over every stream
+  for (int t = T - 1; t >= 0; --t)
+    for (const Phase& ph : b->bwd) {
+      hipError_t e = b->prof.timed(b->stream, ph.kind, [&] {
+        return sp_launch_bwd(ph.kind, b->jobs.dev + ph.off, ph.n, b->d_sd, dbio + (size_t)t * n, nullptr, b->stream);
+      });
+      if (e != hipSuccess) return fail(SP_EHIP, "adjoint launch: %s", hipGetErrorString(e));
+    }
+  // conspicuity maps recomputed from the checkpoints, CH frames of every stream at a time
+  for (int t0 = 0; t0 < T; t0 += b->CH) {
+    const int rem = std::min(b->CH, T - t0);
+    const StepIO* ios = b->d_rio + (size_t)t0 * n;
+    for (const Phase& ph : b->rec) {
+      const int nj = ph.upto[(size_t)rem * n];
+      hipError_t e = b->prof.timed(b->stream, ph.kind, [&] {
+        if (ph.kind == JOB_CONSP_DOT) return sp_launch_consp_dot(b->jobs.dev + ph.off, nj, b->d_rsd, ios, b->stream);
+        return sp_launch(ph.kind, b->jobs.dev + ph.off, nj, b->d_rsd, ios, nullptr, ph.flag, nullptr, b->stream,
+                         ph.lds);
+      });
+      if (e != hipSuccess) return fail(SP_EHIP, "recompute launch: %s", hipGetErrorString(e));
+    }
+  }
+  hipError_t e = b->prof.timed(b->stream, JOB_BWD_FINAL, [&] {
+    return sp_launch_bwd_final(dfin, nullptr, n, T, dKd, dPd, b->p.q, b->p.r, b->p.flat_tol, b->stream);
+  });
+  if (e != hipSuccess) return fail(SP_EHIP, "adjoint reduction launch: %s", hipGetErrorString(e));
+  return SP_OK;
 }
 
 int sp_batch_destroy(sp_batch* b) {

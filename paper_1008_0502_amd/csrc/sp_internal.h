@@ -109,9 +109,12 @@ struct StepIO {
   float* unary;              // [2][H][W]
   float* pairwise;           // [4][H][W]
   float* beta_out;           // [1] or null
+  // conspicuity recomputed for the adjoint (one recorded frame per stream of the launch)
+  const float* gs;           // [Hc][Wc] adjoint of S of the frame
+  float* dot;                // [n_cmax_tiles][8] partial sums of gs * C_k
+  float* cx;                 // [8] C_k at the frame's argmax of S (ms_tape: its max and argmax)
   float K;                   // Kalman gain of this step
   int32_t t;                 // step index
-  int32_t pad[2];
 };
 
 // Arguments of the adjoint sweep (one frame at a time).
@@ -141,7 +144,37 @@ struct BatchState {
   float* beta;               // [1] or null
   float* C;                  // [8][Hc][Wc] conspicuity maps or null
   const uint8_t* last_rgb;   // frame of the last step (next step's previous frame)
-  int32_t cur, pad;
+  int32_t cur;
+  int32_t tape_cap;          // frames the tape holds (0: no tape); steps >= tape_cap record nothing
+  float* tape_ckpt;          // [tape_cap][4][H_cmin][W_cmin] base channels of level c_min
+  float* tape_S;             // [tape_cap][Hc][Wc]
+  float* tape_f;             // [tape_cap][H][W] prediction f_t
+  float* tape_ms;            // [tape_cap][2] max S and its first argmax
+  float* tape_pi;            // [tape_cap][H][W] prior of every step
+};
+
+// Adjoint reduction of one stream: per-frame partials -> gradients of (w, Q, R).
+struct BwdFin {
+  const float* gk_part;      // [T][n_lvl0_tiles] partials of sum nu (q - f)
+  const float* dot_part;     // [T][n_cmax_tiles][8] partials of sum gs * C_k
+  const float* cx;           // [T][8] C_k at the argmax
+  const float* ms;           // [T][2] max S and argmax
+  const float* w;            // [8] channel weights
+  double* gK;                // [T] scratch
+  float* grad_w;             // [8]
+  float* grad_q;             // [1]
+  float* grad_r;             // [1]
+  int32_t n_lvl0_tiles, n_cmax_tiles;
+};
+
+// Masked-MSE loss of one stream's clip of priors.
+struct LossIO {
+  const float* prior;        // [T][H][W]
+  const uint8_t* mask;       // [T][H][W] in {0, 1}
+  float* grad;               // [T][H][W] dL/dprior (or null)
+  float* part;               // [nblk] partial sums
+  float* loss;               // [1]
+  unsigned long long n;      // T * H * W
 };
 
 // Arguments that make the colour-statistics launch also start a batched step: its

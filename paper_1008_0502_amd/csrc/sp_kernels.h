@@ -8,15 +8,15 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
 hipError_t sp_csapply_reserve_lds(size_t bytes);
 hipError_t sp_launch_bwd(int kind, const Job* jobs, int n, const StreamDesc* sds, const BwdIO* bios,
                          const BwdIO* b0, hipStream_t st);
-hipError_t sp_launch_consp_dot(const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios,
-                               const float* gs_all, const float* ms_all, const int* frame_of,
-                               float* dot_part, float* cx_out, hipStream_t st);
-hipError_t sp_launch_bwd_final(int T, int n_lvl0_tiles, int n_cmax_tiles, const float* gk_part,
-                               const float* dot_part, const float* cx, const float* ms_all, const double* Kd,
-                               const double* Pd, double Q, double R, const float* w, float flat_tol,
-                               double* gK_scratch, float* grad_w, float* grad_q, float* grad_r, hipStream_t st);
-hipError_t sp_launch_loss(const float* prior, const uint8_t* mask, size_t n, float* grad, float* part, int nblk,
-                          float* loss, hipStream_t st);
+// Conspicuity recomputed from checkpoints, dotted with each frame's saliency adjoint
+// (per-frame buffers named by ios[stream]: gs, dot, cx, ms_tape).
+hipError_t sp_launch_consp_dot(const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios, hipStream_t st);
+// Adjoint reduction: one workgroup per stream of tab (or the single stream *one when tab
+// is null), shared gains Kd and variances Pd of T steps.
+hipError_t sp_launch_bwd_final(const BwdFin* tab, const BwdFin* one, int n_streams, int T, const double* Kd,
+                               const double* Pd, double Q, double R, float flat_tol, hipStream_t st);
+// Masked-MSE loss of n_streams clips (tab) or of the single clip *one, nblk partials each.
+hipError_t sp_launch_loss(const LossIO* tab, const LossIO* one, int n_streams, int nblk, hipStream_t st);
 // The colour-statistics launch of a batched step, which also starts the step (see
 // BatchBegin).  RgbNodeArgs holds the argument values of that launch as a graph kernel
 // node; sp_batch_rgb_node_params points p at them so the node can be re-pointed at the
@@ -36,3 +36,6 @@ void sp_batch_rgb_node_params(RgbNodeArgs* a, int n_jobs, hipKernelNodeParams* p
 hipError_t sp_launch_batch_reset(int n, BatchState* st, hipStream_t stream);
 hipError_t sp_launch_batch_copy_out(int n, const BatchState* st, const StreamDesc* sds, float* const* out,
                                     hipStream_t stream);
+// Counter calibration copy of n16 16-byte units (mode: 0 dword, 1 dwordx4, 2 global->LDS dword).
+hipError_t sp_launch_calib(const float* src, float* dst, size_t n16, int mode, hipStream_t st);
+

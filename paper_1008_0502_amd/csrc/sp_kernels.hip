@@ -445,8 +445,9 @@ __device__ __forceinline__ uint32_t rgb_at(gp<const uint8_t> rgb, size_t o) {
   return (uint32_t)rgb[3 * o] | ((uint32_t)rgb[3 * o + 1] << 8) | ((uint32_t)rgb[3 * o + 2] << 16);
 }
 
-__device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const uint8_t* const* __restrict__ in_ptrs,
-                                   StepIO* __restrict__ ios, double Q, double R);
+__device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const StreamDesc* __restrict__ sds,
+                                   const uint8_t* const* __restrict__ in_ptrs, StepIO* __restrict__ ios, double Q,
+                                   double R);
 
 __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
                                                   const StreamDesc* __restrict__ sds,
@@ -459,7 +460,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_rgb(const Job* __restrict__ jobs,
   // a batched step: this launch also starts the step (the other launches read the step's
   // inputs after it completes); its own frames come from the caller's table
   if (bb.in_ptrs && blockIdx.x == 0)
-    for (int i = threadIdx.x; i < bb.n; i += SP_BLOCK) batch_begin_stream(i, bb.st, bb.in_ptrs, bb.ios, bb.Q, bb.R);
+    for (int i = threadIdx.x; i < bb.n; i += SP_BLOCK) batch_begin_stream(i, bb.st, sds, bb.in_ptrs, bb.ios, bb.Q, bb.R);
   const uint8_t* frame = bb.in_ptrs ? bb.in_ptrs[J.stream] : IOF(rgb);
   const gp<const uint8_t> rgb = G(frame);
   const int W = sd.W, H = sd.H;
@@ -2316,76 +2317,71 @@ __global__ __launch_bounds__(SP_BLOCK) void k_bwd_gs(const Job* __restrict__ job
   B.gs[(size_t)Y * Wm + X] = acc;
 }
 
-// Recomputed conspicuity maps dotted with the adjoint g_s of each frame:
-// partial sums of g_s * C_k per tile, and C_k at the frame's argmax.
+// Recomputed conspicuity maps dotted with the adjoint g_s of each frame (one recorded
+// frame per stream of the launch, its buffers named by the stream's StepIO): partial
+// sums of g_s * C_k per tile, and C_k at the frame's argmax.
 __global__ __launch_bounds__(SP_BLOCK) void k_consp_dot(const Job* __restrict__ jobs,
                                                         const StreamDesc* __restrict__ sds,
-                                                        const StepIO* __restrict__ ios, StepIO io0,
-                                                        const float* __restrict__ gs_all,
-                                                        const float* __restrict__ ms_all,
-                                                        const int* __restrict__ frame_of,
-                                                        float* __restrict__ dot_part, float* __restrict__ cx_out) {
+                                                        const StepIO* __restrict__ ios) {
   __shared__ float sh4[4];
   __shared__ NParams np[SP_NCH];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
+  const StepIO& io = ios[J.stream];
   consp_nparams(sd, np);
-  const int f = frame_of[J.stream];
   const int cm = sd.c_max, Hm = sd.Hl[cm], Wm = sd.Wl[cm];
   const size_t plane = (size_t)Hm * Wm;
   const int yy = threadIdx.x / CA_T, xx = threadIdx.x % CA_T;
   const int y = J.y0 + yy, x = J.x0 + xx;
   const bool valid = yy < J.th && xx < J.tw && y < Hm && x < Wm;
   const size_t o = (size_t)min(y, Hm - 1) * Wm + min(x, Wm - 1);
-  const float g = valid ? gs_all[(size_t)f * plane + o] : 0.f;
-  const int xs = __float_as_int(ms_all[2 * (size_t)f + 1]);
+  const float g = valid ? io.gs[o] : 0.f;
+  const int xs = __float_as_int(io.ms_tape[1]);
   for (int k = 0; k < SP_NCH; ++k) {
     const float Ck = napply(np[k], sd.fbar[k * plane + o]);
     const float tot = block_reduce<OpSum>(valid ? g * Ck : 0.f, sh4);
-    if (threadIdx.x == 0) dot_part[((size_t)f * sd.n_cmax_tiles + J.tid) * SP_NCH + k] = tot;
-    if (valid && (int)o == xs) cx_out[(size_t)f * SP_NCH + k] = Ck;
+    if (threadIdx.x == 0) io.dot[(size_t)J.tid * SP_NCH + k] = tot;
+    if (valid && (int)o == xs) io.cx[k] = Ck;
   }
 }
 
-// Reduction of the per-frame partials and the scalar FP64 sweep over the gains.
-__global__ __launch_bounds__(SP_BLOCK) void k_bwd_final(int T, int n_lvl0_tiles, int n_cmax_tiles,
-                                                        const float* __restrict__ gk_part,
-                                                        const float* __restrict__ dot_part,
-                                                        const float* __restrict__ cx,
-                                                        const float* __restrict__ ms_all,
+// Reduction of the per-frame partials and the scalar FP64 sweep over the gains; one
+// workgroup per stream (tab[blockIdx.x]; tab null: the single stream `one`).  Every
+// stream of a launch ran the same T steps with the same Q and R, so the gains Kd and
+// variances Pd are shared.
+__global__ __launch_bounds__(SP_BLOCK) void k_bwd_final(const BwdFin* __restrict__ tab, BwdFin one, int T,
                                                         const double* __restrict__ Kd,
                                                         const double* __restrict__ Pd, double Q, double R,
-                                                        const float* __restrict__ w, float flat_tol,
-                                                        double* __restrict__ gK_scratch,
-                                                        float* grad_w, float* grad_q, float* grad_r) {
+                                                        float flat_tol) {
   __shared__ double sh256[SP_BLOCK];
   __shared__ double gw[SP_NCH];
+  const BwdFin F = tab ? tab[blockIdx.x] : one;
   if (threadIdx.x < SP_NCH) gw[threadIdx.x] = 0.0;
   __syncthreads();
   for (int t = 0; t < T; ++t) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n_lvl0_tiles; i += SP_BLOCK) s += (double)gk_part[(size_t)t * n_lvl0_tiles + i];
+    for (int i = threadIdx.x; i < F.n_lvl0_tiles; i += SP_BLOCK) s += (double)F.gk_part[(size_t)t * F.n_lvl0_tiles + i];
     s = block_sum_d(s, sh256);
-    if (threadIdx.x == 0) gK_scratch[t] = s;
+    if (threadIdx.x == 0) F.gK[t] = s;
     double A[SP_NCH];
     for (int k = 0; k < SP_NCH; ++k) {
       double a = 0.0;
-      for (int i = threadIdx.x; i < n_cmax_tiles; i += SP_BLOCK)
-        a += (double)dot_part[((size_t)t * n_cmax_tiles + i) * SP_NCH + k];
+      for (int i = threadIdx.x; i < F.n_cmax_tiles; i += SP_BLOCK)
+        a += (double)F.dot_part[((size_t)t * F.n_cmax_tiles + i) * SP_NCH + k];
       A[k] = block_sum_d(a, sh256);
     }
-    const double m = (double)ms_all[2 * t];
+    const double m = (double)F.ms[2 * t];
     if (threadIdx.x == 0 && m > (double)flat_tol) {
       double Bs = 0.0;
-      for (int k = 0; k < SP_NCH; ++k) Bs += (double)w[k] * A[k];
-      for (int k = 0; k < SP_NCH; ++k) gw[k] += A[k] / m - (double)cx[(size_t)t * SP_NCH + k] * Bs / (m * m);
+      for (int k = 0; k < SP_NCH; ++k) Bs += (double)F.w[k] * A[k];
+      for (int k = 0; k < SP_NCH; ++k) gw[k] += A[k] / m - (double)F.cx[(size_t)t * SP_NCH + k] * Bs / (m * m);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     double gQ = 0.0, gR = 0.0, gP = 0.0;
     for (int t = T - 1; t >= 1; --t) {
-      const double g = gK_scratch[t] + R * gP;
+      const double g = F.gK[t] + R * gP;
       gR += Kd[t] * gP;
       const double a = Pd[t - 1] + Q;
       const double den = (a + R) * (a + R);
@@ -2395,41 +2391,45 @@ __global__ __launch_bounds__(SP_BLOCK) void k_bwd_final(int T, int n_lvl0_tiles,
       gP = ga;
     }
     gR += gP;
-    *grad_q = (float)gQ;
-    *grad_r = (float)gR;
-    for (int k = 0; k < SP_NCH; ++k) grad_w[k] = (float)gw[k];
+    *F.grad_q = (float)gQ;
+    *F.grad_r = (float)gR;
+    for (int k = 0; k < SP_NCH; ++k) F.grad_w[k] = (float)gw[k];
   }
 }
 
 // ---------------------------------------------------------------- masked MSE loss helper
-__global__ __launch_bounds__(SP_BLOCK) void k_loss(const float* __restrict__ prior, const uint8_t* __restrict__ mask,
-                                                   size_t n, float inv_n, float* __restrict__ grad,
-                                                   float* __restrict__ part) {
+// L = mean (prior - mask)^2 over one stream's clip, and dL/dprior; blockIdx.y (or
+// blockIdx.x of the final pass) picks the stream's LossIO (tab null: `one`).
+__global__ __launch_bounds__(SP_BLOCK) void k_loss(const LossIO* __restrict__ tab, LossIO one) {
   __shared__ float sh4[4];
+  const LossIO L = tab ? tab[blockIdx.y] : one;
+  const size_t n = (size_t)L.n;
+  const float inv_n = (float)(1.0 / (double)n);
   float acc = 0.f;
   const size_t stride = (size_t)gridDim.x * SP_BLOCK;
   for (size_t i = (size_t)blockIdx.x * SP_BLOCK + threadIdx.x; i < n; i += stride) {
-    const float d = prior[i] - (float)mask[i];
+    const float d = L.prior[i] - (float)L.mask[i];
     acc += d * d;
-    if (grad) grad[i] = 2.f * d * inv_n;
+    if (L.grad) L.grad[i] = 2.f * d * inv_n;
   }
   acc = block_reduce<OpSum>(acc, sh4);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (threadIdx.x == 0) L.part[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(SP_BLOCK) void k_loss_final(const float* __restrict__ part, int n, float inv_n,
-                                                         float* loss) {
+__global__ __launch_bounds__(SP_BLOCK) void k_loss_final(const LossIO* __restrict__ tab, LossIO one, int nblk) {
   __shared__ double sh256[SP_BLOCK];
+  const LossIO L = tab ? tab[blockIdx.x] : one;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK) s += (double)part[i];
+  for (int i = threadIdx.x; i < nblk; i += SP_BLOCK) s += (double)L.part[i];
   s = block_sum_d(s, sh256);
-  if (threadIdx.x == 0) *loss = (float)(s * (double)inv_n);
+  if (threadIdx.x == 0) *L.loss = (float)(s / (double)L.n);
 }
 
 // ---------------------------------------------------------------- batched step bookkeeping
 // Start of a step for stream i: its inputs, Kalman gain (FP64) and prior buffers.
-__device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const uint8_t* const* __restrict__ in_ptrs,
-                                   StepIO* __restrict__ ios, double Q, double R) {
+__device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const StreamDesc* __restrict__ sds,
+                                   const uint8_t* const* __restrict__ in_ptrs, StepIO* __restrict__ ios, double Q,
+                                   double R) {
   BatchState s = st[i];
   double K, P;
   if (s.t == 0) {
@@ -2446,15 +2446,27 @@ __device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const uin
   io->rgb_prev = (s.t == 0) ? nullptr : s.last_rgb;
   io->S_out = s.S;
   io->C_out = s.C;
-  io->ckpt = nullptr;
-  io->S_tape = nullptr;
   io->S_in = s.S;
   io->seg_prev = nullptr;
   io->pi_prev = s.cur ? s.pi[1] : s.pi[0];
   io->pi_next = s.cur ? s.pi[0] : s.pi[1];
-  io->prior_out = nullptr;
-  io->f_tape = nullptr;
-  io->ms_tape = nullptr;
+  if (s.t < s.tape_cap) {
+    // recorded step: level c_min goes straight to its checkpoint slot; S, f, (max S,
+    // argmax) and the prior are kept for the adjoint
+    const StreamDesc& sd = sds[i];
+    const size_t k = (size_t)s.t, hw = (size_t)sd.H * sd.W;
+    io->ckpt = s.tape_ckpt + k * 4 * (size_t)sd.Hl[sd.c_min] * sd.Wl[sd.c_min];
+    io->S_tape = s.tape_S + k * (size_t)sd.Hl[sd.c_max] * sd.Wl[sd.c_max];
+    io->f_tape = s.tape_f + k * hw;
+    io->ms_tape = s.tape_ms + 2 * k;
+    io->prior_out = s.tape_pi + k * hw;
+  } else {
+    io->ckpt = nullptr;
+    io->S_tape = nullptr;
+    io->f_tape = nullptr;
+    io->ms_tape = nullptr;
+    io->prior_out = nullptr;
+  }
   io->unary = s.unary;
   io->pairwise = s.pairwise;
   io->beta_out = s.beta;
@@ -2488,6 +2500,45 @@ __global__ void k_batch_copy_out(const BatchState* __restrict__ st, const Stream
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- counter calibration
+// Copies n16 16-byte units from src to dst in one of the access forms the kernels use, so
+// that the HBM byte counters can be read against a known number of bytes: 0 = a 4-byte
+// load and store per lane, 1 = a 16-byte load and store per lane, 2 = 4-byte direct
+// global->LDS loads of a 1 KB slice per wavefront, then 4-byte stores from LDS.
+__global__ __launch_bounds__(SP_BLOCK) void k_calib(const float* __restrict__ src, float* __restrict__ dst,
+                                                    size_t n16, int mode) {
+  __shared__ float buf[SP_BLOCK * 4];
+  const size_t nf = n16 * 4;
+  const gp<const float> gs = G(src);
+  const gp<float> gd = G(dst);
+  if (mode == 1) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const gp<const v4f> s4 = (gp<const v4f>)gs;
+    const gp<v4f> d4 = (gp<v4f>)gd;
+    for (size_t i = (size_t)blockIdx.x * SP_BLOCK + threadIdx.x; i < n16; i += (size_t)gridDim.x * SP_BLOCK)
+      d4[i] = s4[i];
+  } else if (mode == 0) {
+    for (size_t i = (size_t)blockIdx.x * SP_BLOCK + threadIdx.x; i < nf; i += (size_t)gridDim.x * SP_BLOCK)
+      gd[i] = gs[i];
+  } else {
+    // each wavefront stages 4 x 64 floats (4 loads of 256 bytes) per round
+    const int wf = wave_first(), lane = lane_id();
+    const size_t chunk = (size_t)SP_BLOCK * 4;
+    for (size_t b0 = (size_t)blockIdx.x * chunk; b0 < nf; b0 += (size_t)gridDim.x * chunk) {
+      const size_t w0 = b0 + (size_t)wf * 4;
+      if (w0 + 4 * 64 <= nf) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lds_load_u(buf + wf * 4 + k * 64, gs, (uint32_t)((w0 + k * 64 + lane) * 4u));
+        lds_wait();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gd[w0 + k * 64 + lane] = buf[wf * 4 + k * 64 + lane];
+      } else {
+        for (size_t i = w0 + lane; i < nf && i < w0 + 4 * 64; i += 64) gd[i] = gs[i];
+      }
+    }
+  }
+}
 
 // ---------------------------------------------------------------- launchers
 static inline hipError_t chk() { return hipGetLastError(); }
@@ -2572,32 +2623,29 @@ hipError_t sp_launch_bwd(int kind, const Job* jobs, int n, const StreamDesc* sds
   return chk();
 }
 
-hipError_t sp_launch_consp_dot(const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios,
-                               const float* gs_all, const float* ms_all, const int* frame_of,
-                               float* dot_part, float* cx_out, hipStream_t st) {
+hipError_t sp_launch_consp_dot(const Job* jobs, int n, const StreamDesc* sds, const StepIO* ios, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  StepIO z{};
-  hipLaunchKernelGGL(k_consp_dot, dim3(n), dim3(SP_BLOCK), 0, st, jobs, sds, ios, z, gs_all, ms_all, frame_of,
-                     dot_part, cx_out);
+  hipLaunchKernelGGL(k_consp_dot, dim3(n), dim3(SP_BLOCK), 0, st, jobs, sds, ios);
   return chk();
 }
 
-hipError_t sp_launch_bwd_final(int T, int n_lvl0_tiles, int n_cmax_tiles, const float* gk_part,
-                               const float* dot_part, const float* cx, const float* ms_all, const double* Kd,
-                               const double* Pd, double Q, double R, const float* w, float flat_tol,
-                               double* gK_scratch, float* grad_w, float* grad_q, float* grad_r, hipStream_t st) {
-  hipLaunchKernelGGL(k_bwd_final, dim3(1), dim3(SP_BLOCK), 0, st, T, n_lvl0_tiles, n_cmax_tiles, gk_part, dot_part,
-                     cx, ms_all, Kd, Pd, Q, R, w, flat_tol, gK_scratch, grad_w, grad_q, grad_r);
+hipError_t sp_launch_bwd_final(const BwdFin* tab, const BwdFin* one, int n_streams, int T, const double* Kd,
+                               const double* Pd, double Q, double R, float flat_tol, hipStream_t st) {
+  if (n_streams <= 0) return hipSuccess;
+  BwdFin z{};
+  hipLaunchKernelGGL(k_bwd_final, dim3(n_streams), dim3(SP_BLOCK), 0, st, tab, one ? *one : z, T, Kd, Pd, Q, R,
+                     flat_tol);
   return chk();
 }
 
-hipError_t sp_launch_loss(const float* prior, const uint8_t* mask, size_t n, float* grad, float* part, int nblk,
-                          float* loss, hipStream_t st) {
-  const float inv_n = (float)(1.0 / (double)n);
-  hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(SP_BLOCK), 0, st, prior, mask, n, inv_n, grad, part);
+hipError_t sp_launch_loss(const LossIO* tab, const LossIO* one, int n_streams, int nblk, hipStream_t st) {
+  if (n_streams <= 0) return hipSuccess;
+  LossIO z{};
+  const LossIO& o = one ? *one : z;
+  hipLaunchKernelGGL(k_loss, dim3(nblk, n_streams), dim3(SP_BLOCK), 0, st, tab, o);
   hipError_t e = chk();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(SP_BLOCK), 0, st, part, nblk, inv_n, loss);
+  hipLaunchKernelGGL(k_loss_final, dim3(n_streams), dim3(SP_BLOCK), 0, st, tab, o, nblk);
   return chk();
 }
 
@@ -2648,3 +2696,9 @@ hipError_t sp_csapply_reserve_lds(size_t bytes) {
   }
   return hipSuccess;
 }
+
+hipError_t sp_launch_calib(const float* src, float* dst, size_t n16, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(k_calib, dim3(2048), dim3(SP_BLOCK), 0, st, src, dst, n16, mode);
+  return chk();
+}
+

@@ -186,15 +186,23 @@ class Clip:
     def frame(self, t: int) -> Tuple[np.ndarray, np.ndarray]:
         """(rgb uint8 [H][W][3], mask uint8 [H][W]) of frame t."""
         self._seek(t)
-        img = self.background.astype(np.float64).copy()
-        mask = np.zeros((self.spec.H, self.spec.W), dtype=np.uint8)
+        H, W = self.spec.H, self.spec.W
+        img = self.background.copy()
+        mask = np.zeros((H, W), dtype=np.uint8)
         for o, (cx, cy, _, _) in zip(self.objects, self._positions):
-            inside = ((self._xs - cx) / o.a) ** 2 + ((self._ys - cy) / o.b) ** 2 <= 1.0
-            tex = 0.75 + 0.25 * np.cos(2.0 * math.pi * (self._xs - cx) / 4.0)
-            val = o.colour[None, None, :] * np.broadcast_to(tex, inside.shape)[:, :, None]
-            img = np.where(inside[:, :, None], val, img)
-            mask |= inside.astype(np.uint8)
-        return _round_u8(img), mask
+            # only pixels of the bounding box can be inside; later objects cover earlier ones
+            x0, x1 = max(0, int(math.floor(cx - o.a))), min(W, int(math.ceil(cx + o.a)) + 1)
+            y0, y1 = max(0, int(math.floor(cy - o.b))), min(H, int(math.ceil(cy + o.b)) + 1)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            xs, ys = self._xs[:, x0:x1], self._ys[y0:y1, :]
+            inside = ((xs - cx) / o.a) ** 2 + ((ys - cy) / o.b) ** 2 <= 1.0
+            tex = 0.75 + 0.25 * np.cos(2.0 * math.pi * (xs - cx) / 4.0)
+            val = _round_u8(o.colour[None, None, :] * np.broadcast_to(tex, inside.shape)[:, :, None])
+            win = img[y0:y1, x0:x1]
+            win[inside] = val[inside]
+            mask[y0:y1, x0:x1] |= inside.astype(np.uint8)
+        return img, mask
 
     def frames(self, t0: int = 0, t1: Optional[int] = None) -> Iterator[Tuple[np.ndarray, np.ndarray]]:
         t1 = self.spec.T if t1 is None else t1

@@ -44,3 +44,23 @@ def run(fn, jobs, workers=8):
     ctx = mp.get_context("spawn")
     with ctx.Pool(min(workers, len(jobs))) as pool:
         return pool.map(fn, jobs)
+
+
+def grad_job(args):
+    """(kind, H, W, T, seed, param dict, w, Q, R, fd) -> the oracle's FP64 loss and
+    gradients of the masked MSE of the clip (analytic, and central differences when fd)."""
+    import oracle as O
+    from paper_1008_0502_amd import synth
+    kind, H, W, T, seed, pkw, w, Q, R, fd = args
+    frames, masks = synth.Clip(_spec(kind, H, W, T, seed)).stack()
+    op = O.OracleParams(**pkw)
+    ref = O.run_clip(frames, op)
+    geo = ref["geometry"]
+    tape = O.prior_chain_forward(ref["C"], w, Q, R, op, H, W, geo.c_max)
+    L, g = O.mse_mask_loss(np.stack(tape["pi"]), masks)
+    gw, gQ, gR = O.prior_chain_backward(tape, ref["C"], g, op)
+    out = {"L": L, "gw": np.asarray(gw), "gQ": gQ, "gR": gR}
+    if fd:
+        fw, fQ, fR = O.finite_difference_grad(ref["C"], masks, w, Q, R, op, H, W, geo.c_max, h=1e-3)
+        out.update({"fw": np.asarray(fw), "fQ": fQ, "fR": fR})
+    return out

@@ -134,8 +134,12 @@ def test_create_rejects_bad_shapes_and_nulls(lib):
     lib.sp_default_params(ctypes.byref(p))
     assert lib.sp_batch_create(ctypes.byref(p), 0, Hs, Ws, 0, None, ctypes.byref(hb)) == _lib.SP_EINVAL
     assert lib.sp_batch_create(ctypes.byref(p), 2, Hs, Ws, 8, None, ctypes.byref(hb)) == _lib.SP_EINVAL
-    p.record_tape = 4
+    p.record_tape = -1
     assert lib.sp_batch_create(ctypes.byref(p), 2, Hs, Ws, 0, None, ctypes.byref(hb)) == _lib.SP_EINVAL
+    assert lib.sp_batch_backward(None, None, 1, None, None, None) == _lib.SP_EINVAL
+    assert lib.sp_batch_mse_mask_loss(None, None, 1, None, None) == _lib.SP_EINVAL
+    assert lib.sp_batch_set_weights(None, None, 1e-3, 1e-1) == _lib.SP_EINVAL
+    assert lib.sp_batch_step_index(None) == -1 and lib.sp_batch_tape_generation(None) == -1
 
 
 def test_product_path_has_no_cpu_fallback():
