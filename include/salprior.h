@@ -296,6 +296,24 @@ int sp_batch_set_tune(sp_batch* b, int32_t kalman_tw, int32_t xcd_order, int32_t
  * later start from the defaults: tile width 32, no XCD order, 2 channels). */
 int sp_tune_cache_clear(void);
 
+/* Allocation-free form of saliency_forward, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It needs no context: it validates p against H and W like sp_create, lays
+ * the stream's pyramid, maps, partials and job table out in a device array the library
+ * holds for each GPU from its load until the process ends (SP_NOALLOC_MAX_BYTES), and
+ * computes S_out and C_out (optional) of one frame exactly as saliency_forward of a
+ * context with the same parameters does (same kernels, same launch shapes).  Arguments
+ * as in saliency_forward; hip_stream is a hipStream_t (NULL = the default stream).
+ * It calls no allocation routine.  It copies its job table into the array and waits for
+ * that copy (and so for earlier work on hip_stream) before enqueuing the kernels.  Every
+ * call on one GPU uses that GPU's one array: calls that overlap on a GPU (other host
+ * threads, other streams) race and must be serialised by the caller.  Nothing in the
+ * array needs to start at zero: each call writes what it reads.  A frame whose layout
+ * exceeds the array fails with SP_ESHAPE (the message gives the bytes it needs). */
+#define SP_NOALLOC_MAX_BYTES (64u << 20)
+int sp_saliency_noalloc(const sp_params* p, int32_t H, int32_t W, const uint8_t* rgb_t, const uint8_t* rgb_prev,
+                        float* S_out, float* C_out, void* hip_stream);
+
 /* Description of the last error on this host thread ("" if none). */
 const char* sp_last_error(void);
 

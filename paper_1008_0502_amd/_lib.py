@@ -104,6 +104,8 @@ SIGNATURES = [
     ("sp_tune_cache_clear", c_int32, []),
     ("sp_calibration_copy", c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_void_p]),
     ("sp_kernel_name", ctypes.c_char_p, [c_int32]),
+    ("sp_saliency_noalloc", c_int32, [ctypes.POINTER(sp_params), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p]),
     ("sp_last_error", ctypes.c_char_p, []),
 ]
 

@@ -317,6 +317,30 @@ class Context:
         return {"S": S, "C": C, "pi": P, "unary": U, "pairwise": PW, "beta": B}
 
 
+def saliency_noalloc(H: int, W: int, rgb_t: torch.Tensor, rgb_prev: Optional[torch.Tensor],
+                     S_out: torch.Tensor, C_out: Optional[torch.Tensor] = None,
+                     params: Optional[Params] = None) -> None:
+    """sp_saliency_noalloc: the saliency map of one frame with no context and no device
+    allocation (the library's per-GPU scratch array holds every intermediate).  The caller
+    supplies the outputs: S_out [Hc][Wc] (and C_out [8][Hc][Wc]) float32 on the frame's
+    device; Hc x Wc is the level c_max size of the frame's geometry."""
+    lib = _lib.load()
+    dev = rgb_t.device
+    _need(rgb_t, "rgb_t", torch.uint8, (H, W, 3), dev)
+    if rgb_prev is not None:
+        _need(rgb_prev, "rgb_prev", torch.uint8, (H, W, 3), dev)
+    if not isinstance(S_out, torch.Tensor) or S_out.dtype != torch.float32 or S_out.device != dev \
+            or not S_out.is_contiguous():
+        raise ValueError("S_out must be a contiguous float32 tensor on the frame's device")
+    if C_out is not None and (C_out.dtype != torch.float32 or C_out.device != dev or not C_out.is_contiguous()
+                              or C_out.numel() != 8 * S_out.numel()):
+        raise ValueError("C_out must be a contiguous float32 tensor of 8 maps the size of S_out")
+    cp = (params or Params()).to_c()
+    with torch.cuda.device(dev):
+        check(lib.sp_saliency_noalloc(ctypes.byref(cp), int(H), int(W), _ptr(rgb_t), _ptr(rgb_prev), _ptr(S_out),
+                                      _ptr(C_out), _stream()), "sp_saliency_noalloc")
+
+
 class SaliencyPrior(torch.autograd.Function):
     """prior[T][H][W] = path(frames; w, q, r), differentiable in w (8), q and r.
 

@@ -650,6 +650,30 @@ void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& 
   push(which == PROG_ALL ? JOB_CONSP : JOB_CONSP_DOT, v);
 }
 
+// Phases of one stream's forward saliency map (stream index 0), appended to `js` with
+// their launch flags and LDS sizes; *nc_out receives the channels per across-scale
+// workgroup.  Contexts and the allocation-free entry point build identical tables.
+int forward_phases(const Geo& g, const sp_params& p, const StreamDesc& sd, const Tune& tune, JobStore& js,
+                   std::vector<Phase>& out, int* nc_out) {
+  std::vector<std::vector<Job>> parts;
+  std::vector<int> kinds;
+  const int nc = csapply_nc(g, tune.ca_nc);
+  const size_t ca_lds = nc * (gpath_ok(g) ? csg_lds_bytes(g) : csapply_lds_bytes(g));
+  if (sp_csapply_reserve_lds(ca_lds) != hipSuccess)
+    return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", ca_lds);
+  build_forward_jobs(parts, kinds, sd, g, 0, PROG_ALL, nc);
+  for (size_t i = 0; i < parts.size(); ++i) {
+    const bool grp = kinds[i] == JOB_CSAPPLY || kinds[i] == JOB_CSG;
+    const bool pyr = kinds[i] == JOB_DOWN || kinds[i] == JOB_TAIL;   // flag: Gabor radius
+    const int gflag = nc | (kinds[i] == JOB_CSG ? csg_set(g) << 8 : 0);
+    if (tune.xcd) xcd_order(parts[i]);
+    out.push_back(js.add(kinds[i], grp ? gflag : (pyr ? p.gabor_radius : 0), parts[i], 1));
+    if (grp) out.back().lds = ca_lds;
+  }
+  *nc_out = nc;
+  return SP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -809,25 +833,15 @@ int ctx_build_tables(sp_ctx* c) {
   c->mrf.clear();
   c->bwd.clear();
   c->rec.clear();
-  auto order = [&](std::vector<Job> v) {
-    if (c->tune.xcd) xcd_order(v);
-    return v;
-  };
   {
-    std::vector<std::vector<Job>> parts;
-    std::vector<int> kinds;
-    const int nc = csapply_nc(g, c->tune.ca_nc);
+    int nc = 0;
+    int rc = forward_phases(g, c->p, c->h_sd, c->tune, c->jobs, c->fwd, &nc);
+    if (rc) return rc;
     const size_t ca_lds = nc * (gpath_ok(g) ? csg_lds_bytes(g) : csapply_lds_bytes(g));
-    if (sp_csapply_reserve_lds(ca_lds) != hipSuccess)
-      return fail(SP_EHIP, "cannot reserve %zu bytes of LDS for the across-scale sum", ca_lds);
-    build_forward_jobs(parts, kinds, c->h_sd, g, 0, PROG_ALL, nc);
-    for (size_t i = 0; i < parts.size(); ++i) {
-      const bool grp = kinds[i] == JOB_CSAPPLY || kinds[i] == JOB_CSG;
-      const bool pyr = kinds[i] == JOB_DOWN || kinds[i] == JOB_TAIL;   // flag: Gabor radius
-      const int gflag = nc | (kinds[i] == JOB_CSG ? csg_set(g) << 8 : 0);
-      c->fwd.push_back(c->jobs.add(kinds[i], grp ? gflag : (pyr ? c->p.gabor_radius : 0), order(parts[i]), 1));
-      if (grp) c->fwd.back().lds = ca_lds;
-    }
+    auto order = [&](std::vector<Job> v) {
+      if (c->tune.xcd) xcd_order(v);
+      return v;
+    };
     std::vector<Job> v;
     add_tiles(v, 0, 0, Hc, Wc);
     c->prior.push_back(c->jobs.add(JOB_SMAX, 0, v, 1));
@@ -1057,6 +1071,69 @@ int sp_step(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, const uint
   c->P = Pn;
   c->cur ^= 1;
   c->t += 1;
+  return SP_OK;
+}
+
+int sp_saliency_noalloc(const sp_params* p, int32_t H, int32_t W, const uint8_t* rgb_t, const uint8_t* rgb_prev,
+                        float* S_out, float* C_out, void* hip_stream) {
+  g_err.clear();
+  if (!rgb_t || !S_out) return fail(SP_EINVAL, "rgb_t and S_out must not be NULL");
+  int rc = validate_params(p);
+  if (rc) return rc;
+  Geo g;
+  rc = make_geo(*p, H, W, g);
+  if (rc) return rc;
+  const Tune tune = cached_tune(H, W);
+  const int nc = csapply_nc(g, tune.ca_nc);
+  // sizing pass (no device call): stream description, job table, then the stream's
+  // pyramid, maps and partials, in the order the placing pass takes them
+  StreamDesc sd;
+  size_t n_jobs = 0;
+  size_t need = 0;
+  {
+    Bump b;
+    b.take<StreamDesc>(1);
+    layout_stream(sd, g, *p, b, 1, true);
+    std::vector<std::vector<Job>> parts;
+    std::vector<int> kinds;
+    build_forward_jobs(parts, kinds, sd, g, 0, PROG_ALL, nc);
+    for (const auto& v : parts) n_jobs += v.size();
+    b.take<Job>(n_jobs);
+    need = b.off;
+  }
+  if (need > SP_NOALLOC_BYTES)
+    return fail(SP_ESHAPE, "a %dx%d frame needs %zu bytes of scratch; the allocation-free entry point holds %zu "
+                "(use a context)", H, W, need, (size_t)SP_NOALLOC_BYTES);
+  void* base = nullptr;
+  HIPCHK(sp_noalloc_scratch(&base));
+  Bump b;
+  b.base = static_cast<char*>(base);
+  StreamDesc* d_sd = b.take<StreamDesc>(1);
+  layout_stream(sd, g, *p, b, 1, true);
+  Job* d_jobs = b.take<Job>(n_jobs);
+  if (b.off != need) return fail(SP_EINVAL, "scratch layout changed between its passes");
+  JobStore js;
+  std::vector<Phase> phases;
+  int nc2 = 0;
+  rc = forward_phases(g, *p, sd, tune, js, phases, &nc2);
+  if (rc) return rc;
+  if (js.host.size() != n_jobs || nc2 != nc) return fail(SP_EINVAL, "job table changed between its passes");
+  hipStream_t st = (hipStream_t)hip_stream;
+  // The uploads are ordered after earlier work on this stream (which may still read the
+  // scratch); the wait keeps the host tables alive until they are copied.
+  HIPCHK(hipMemcpyAsync(d_sd, &sd, sizeof(StreamDesc), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_jobs, js.host.data(), sizeof(Job) * n_jobs, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  StepIO io;
+  std::memset(&io, 0, sizeof io);
+  io.rgb = rgb_t;
+  io.rgb_prev = rgb_prev;
+  io.S_out = S_out;
+  io.C_out = C_out;
+  for (const Phase& ph : phases) {
+    const hipError_t e = sp_launch(ph.kind, d_jobs + ph.off, ph.n, d_sd, nullptr, &io, ph.flag, nullptr, st, ph.lds);
+    if (e != hipSuccess) return fail(SP_EHIP, "kernel launch (phase kind %d): %s", ph.kind, hipGetErrorString(e));
+  }
   return SP_OK;
 }
 
@@ -1305,6 +1382,7 @@ int sp_profile_enable(sp_ctx* c, int32_t enable) {
 }
 
 static_assert(JOB_NKINDS == SP_NKINDS, "kernel kinds and the public SP_NKINDS disagree");
+static_assert(SP_NOALLOC_BYTES == SP_NOALLOC_MAX_BYTES, "scratch size and the public SP_NOALLOC_MAX_BYTES disagree");
 
 int sp_profile_read(sp_ctx* c, int32_t n, float* total_ms, int32_t* launches) {
   g_err.clear();

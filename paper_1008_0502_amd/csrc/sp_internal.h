@@ -16,6 +16,8 @@
 #define SP_KAL_ROWS 32      // rows of a prior-update tile (its width is tuned: 16, 32 or 64)
 #define SP_RGB_TR 32        // most rows of a colour-statistics tile (four wavefront bands)
 #define SP_RGB_TC 256       // most columns of a colour-statistics tile (4 pixels per lane)
+#define SP_NOALLOC_BYTES (64u << 20)   // device scratch of the allocation-free saliency entry point
+#define SP_NOALLOC_DEVICES 64          // devices whose scratch address is remembered
 
 // Base channels are stored per level as [4][H_l][W_l] in the order I, RG, BY, M;
 // orientation maps per used level as [4][H_l][W_l] in the order O0, O45, O90, O135.

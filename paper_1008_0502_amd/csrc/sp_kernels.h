@@ -39,3 +39,6 @@ hipError_t sp_launch_batch_copy_out(int n, const BatchState* st, const StreamDes
 // Counter calibration copy of n16 16-byte units (mode: 0 dword, 1 dwordx4, 2 global->LDS dword).
 hipError_t sp_launch_calib(const float* src, float* dst, size_t n16, int mode, hipStream_t st);
 
+// Device address of the allocation-free entry point's scratch array on the current device
+// (SP_NOALLOC_BYTES bytes; looked up once per device, then remembered).
+hipError_t sp_noalloc_scratch(void** ptr);

@@ -9,6 +9,8 @@
 #include <stdint.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "sp_internal.h"
 #include "sp_kernels.h"
 
@@ -2702,3 +2704,29 @@ hipError_t sp_launch_calib(const float* src, float* dst, size_t n16, int mode, h
   return chk();
 }
 
+
+// ---------------------------------------------------------------- allocation-free scratch
+// Device memory of the allocation-free saliency entry point: a file-scope array that every
+// GPU the library runs on holds from the library's load until the process ends.  Its name
+// in host code is only a host-side stand-in, never a device address: host code uses the
+// address hipGetSymbolAddress returns, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[SP_NOALLOC_BYTES];
+
+hipError_t sp_noalloc_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* addr[SP_NOALLOC_DEVICES] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SP_NOALLOC_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!a) return hipErrorInvalidSymbol;
+    addr[dev] = a;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}

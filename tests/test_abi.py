@@ -154,3 +154,15 @@ def test_product_path_has_no_cpu_fallback():
             _lib.load(os.path.join(ROOT, "does_not_exist.so"))
         finally:
             _lib._LIB = saved
+
+
+def test_noalloc_rejects_frames_beyond_its_scratch(lib):
+    # sized before any device call: a 4K frame needs more than the array holds
+    p = _lib.sp_params()
+    lib.sp_default_params(ctypes.byref(p))
+    rc = lib.sp_saliency_noalloc(ctypes.byref(p), 2160, 3840, 1, None, 1, None, None)
+    assert rc == _lib.SP_ESHAPE
+    msg = lib.sp_last_error().decode()
+    assert "needs" in msg and str(64 << 20) in msg
+    assert lib.sp_saliency_noalloc(ctypes.byref(p), 480, 640, None, None, 1, None, None) == _lib.SP_EINVAL
+    assert lib.sp_saliency_noalloc(None, 480, 640, 1, None, 1, None, None) == _lib.SP_EINVAL
