@@ -16,6 +16,9 @@ paper (Sections 3-6) and from the readings taken where the paper is silent:
                   and the MRF capacities (Section 4, Eqs. 1-4).
 * adjoint.py   -- the FP64 adjoint of the prior chain with respect to the channel
                   weights and the Kalman variances, plus central finite differences.
+* variants.py  -- the variants of the prior: f by distance transform (Section 6), the
+                  manual first-frame prior (Section 4, Section 8.1) and the stochastic
+                  saliency map (Section 3).
 
 Parity status: every function is pinned by the CPU tests (constant images, Gabor
 closed form, Kalman steady state, brute-force loops, adjoint dot products, gauge
@@ -28,6 +31,7 @@ from .saliency import (OracleParams, Geometry, geometry, colour_max, features, b
                        saliency)
 from .prior import (observation, kalman_gains, prior_clip, mrf_weights, border_mask,
                     run_clip)
+from . import variants
 from .adjoint import (mse_mask_loss, prior_chain_forward, prior_chain_backward, blur_adjoint,
                       upsample_adjoint, finite_difference_grad)
 
