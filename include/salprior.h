@@ -66,6 +66,16 @@ typedef struct sp_params {
   float gabor_sigma;   /* Gabor envelope sigma (2) */
   int32_t gabor_radius;/* Gabor kernel radius, 1..8 (6: a 13x13 kernel) */
   int32_t record_tape; /* >0: frames the adjoint tape can hold (0: no tape) */
+  /* Variants of the prior.  A context that records a tape must keep the defaults. */
+  int32_t f_mode;      /* prediction f of Section 6 from the previous segmentation (or, without
+                          one, from the previous prior): 0 = 5x5 binomial blur (default);
+                          1 = distance transform, f = exp(-d^2 / (2 dt_sigma^2)) with d the
+                          Euclidean distance to the nearest object pixel (the stand-in object
+                          is prior > 1/2); f = 0 when there is no object pixel */
+  float dt_sigma;      /* f_mode 1: decay length in pixels, 0 < dt_sigma <= 4 (2) */
+  double ssm_q;        /* stochastic saliency map (Section 3): with ssm_r > 0 the observation */
+  double ssm_r;        /* is taken from a per-pixel Kalman filter of S with process variance
+                          ssm_q >= 0 and observation variance ssm_r (0, 0: off) */
 } sp_params;
 
 /* Geometry of a context, as derived by sp_create. */
@@ -138,6 +148,20 @@ int saliency_forward(sp_ctx* ctx, const uint8_t* rgb_t, const uint8_t* rgb_prev,
  * prior = f + K_t (q_t - f), K_t = (P_{t-1} + Q) / (P_{t-1} + Q + R), P_t = R K_t,
  * prior = eps on the border ring.  Advances the step index. */
 int prior_update(sp_ctx* ctx, const float* S, const uint8_t* seg_prev, float* prior_out);
+
+/* Starts a clip from manual labels (Section 4's manual-label prior; the first frame of
+ * the "Manual" comparison of Section 8.1) instead of a saliency observation:
+ *   labels     [H][W] uint8: 1 = object, 0 = background, any other value = no label.
+ *   prior_out  [H][W] float or NULL receives p(A_x = 1): 1, eps and 0.5 respectively.
+ * The prior becomes the Kalman state of step 0 with variance R (no border ring), so the
+ * next prior_update is step 1.  Resets the clip first (like sp_reset). */
+int sp_manual_prior(sp_ctx* ctx, const uint8_t* labels, float* prior_out);
+
+/* The stochastic saliency map of the last prior_update (ssm_r > 0): *mean receives a
+ * device pointer to the per-pixel means [Hc][Wc] (valid until the next update), *var
+ * the variance shared by every pixel.  SP_ESTATE when the map is off or no update has
+ * run since the reset. */
+int sp_stochastic_saliency(const sp_ctx* ctx, const float** mean, double* var);
 
 /* MRF capacities (Section 4, Eqs. 1-4) of one frame and its prior.
  *   rgb_t        [H][W][3] uint8.
@@ -254,7 +278,7 @@ int sp_batch_backward(sp_batch* b, const float* const* grad_prior, int32_t T, fl
  * 65536 pairs).  sp_profile_read synchronises the stream and returns, per kernel kind
  * 0..SP_NKINDS-1, the summed device time in ms and the number of launches since the
  * last read (arrays of length n >= SP_NKINDS), then clears the record. */
-#define SP_NKINDS 20
+#define SP_NKINDS 22
 int sp_profile_enable(sp_ctx* ctx, int32_t enable);
 int sp_profile_read(sp_ctx* ctx, int32_t n, float* total_ms, int32_t* launches);
 /* The same measurement hook for a batch: while enabled, sp_batch_step launches the

@@ -117,8 +117,11 @@ def run_clip_variant(frames: np.ndarray, p: OracleParams, f_mode: int = 0, dt_si
     obs = Ss
     mu, Pm = None, None
     if ssm is not None:
-        mu, Pm = stochastic_saliency(Ss, ssm[0], ssm[1])
-        obs = list(mu)
+        # the stochastic map starts at the first saliency map it filters: frame 1 when the
+        # first frame's prior comes from manual labels
+        first = 0 if manual is None else 1
+        mu, Pm = stochastic_saliency(Ss[first:], ssm[0], ssm[1])
+        obs = list(Ss[:first]) + list(mu)
     qs = [observation(obs[t], p, H, W, geo.c_max)[0] for t in range(T)]
     pi0 = None if manual is None else manual_prior(manual, p.eps)
     pis, fs, K = prior_clip_variant(qs, p, f_mode, dt_sigma, segs, pi0)

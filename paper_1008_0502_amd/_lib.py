@@ -14,7 +14,7 @@ SP_OK, SP_EINVAL, SP_ESHAPE, SP_ENOMEM, SP_EHIP, SP_ESTATE = 0, -1, -2, -3, -4, 
 ERROR_NAMES = {SP_EINVAL: "SP_EINVAL", SP_ESHAPE: "SP_ESHAPE", SP_ENOMEM: "SP_ENOMEM",
                SP_EHIP: "SP_EHIP", SP_ESTATE: "SP_ESTATE"}
 MAX_LEVELS = 12
-NKINDS = 20
+NKINDS = 22
 
 c_int32 = ctypes.c_int32
 c_float = ctypes.c_float
@@ -43,6 +43,10 @@ class sp_params(ctypes.Structure):
         ("gabor_sigma", c_float),
         ("gabor_radius", c_int32),
         ("record_tape", c_int32),
+        ("f_mode", c_int32),
+        ("dt_sigma", c_float),
+        ("ssm_q", c_double),
+        ("ssm_r", c_double),
     ]
 
 
@@ -69,6 +73,8 @@ SIGNATURES = [
     ("sp_tape_generation", ctypes.c_int64, [c_void_p]),
     ("saliency_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("prior_update", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("sp_manual_prior", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("sp_stochastic_saliency", c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_double)]),
     ("mrf_weights", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("sp_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                           c_void_p, c_void_p]),

@@ -38,6 +38,10 @@ class Params:
     gabor_sigma: float = 2.0
     gabor_radius: int = 6
     record_tape: int = 0
+    f_mode: int = 0
+    dt_sigma: float = 2.0
+    ssm_q: float = 0.0
+    ssm_r: float = 0.0
 
     def to_c(self) -> _lib.sp_params:
         p = _lib.sp_params()
@@ -65,6 +69,9 @@ class Params:
         p.gabor_sigma = float(self.gabor_sigma)
         p.gabor_radius = int(self.gabor_radius)
         p.record_tape = int(self.record_tape)
+        p.f_mode = int(self.f_mode)
+        p.dt_sigma = float(self.dt_sigma)
+        p.ssm_q, p.ssm_r = float(self.ssm_q), float(self.ssm_r)
         return p
 
 
@@ -191,6 +198,27 @@ class Context:
         check(self.lib.prior_update(self._handle, _ptr(S), _ptr(seg_prev), _ptr(prior_out)), "prior_update")
         return prior_out
 
+    def manual_prior(self, labels: torch.Tensor, prior_out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Start a clip from manual labels (1 object, 0 background, other: none)."""
+        g = self.geometry
+        _need(labels, "labels", torch.uint8, (g.H, g.W), self.device)
+        if prior_out is None:
+            prior_out = torch.empty((g.H, g.W), dtype=torch.float32, device=self.device)
+        _need(prior_out, "prior_out", torch.float32, (g.H, g.W), self.device)
+        self._bind_stream()
+        check(self.lib.sp_manual_prior(self._handle, _ptr(labels), _ptr(prior_out)), "sp_manual_prior")
+        return prior_out
+
+    def stochastic_saliency(self):
+        """(copy of the stochastic saliency means [Hc][Wc], their variance) of the last update."""
+        g = self.geometry
+        ptr, var = ctypes.c_void_p(), ctypes.c_double()
+        check(self.lib.sp_stochastic_saliency(self._handle, ctypes.byref(ptr), ctypes.byref(var)),
+              "sp_stochastic_saliency")
+        out = torch.empty((g.Hc, g.Wc), dtype=torch.float32, device=self.device)
+        _lib.hip_copy_d2d(out.data_ptr(), ptr.value, out.numel() * 4, _stream())
+        return out, float(var.value)
+
     def mrf_weights(self, rgb_t: torch.Tensor, prior: torch.Tensor, unary_out=None, pairwise_out=None,
                     beta_out=None):
         g = self.geometry
@@ -297,11 +325,15 @@ class Context:
         check(self.lib.sp_set_state(self._handle, _ptr(buf), buf.numel()), "sp_set_state")
 
     # -- convenience: a whole clip -------------------------------------------
-    def run_clip(self, frames: torch.Tensor, with_mrf: bool = False, want_C: bool = False, segs=None):
-        """frames: uint8 [T][H][W][3] on the device.  Resets, then runs every frame."""
+    def run_clip(self, frames: torch.Tensor, with_mrf: bool = False, want_C: bool = False, segs=None,
+                 manual: Optional[torch.Tensor] = None, want_ssm: bool = False):
+        """frames: uint8 [T][H][W][3] on the device.  Resets, then runs every frame.  With
+        manual labels the first frame's prior comes from them (sp_manual_prior); want_ssm
+        collects the stochastic saliency means of every step (key "mu")."""
         T = frames.shape[0]
         g = self.geometry
         self.reset()
+        MU = torch.empty((T, g.Hc, g.Wc), dtype=torch.float32, device=self.device) if want_ssm else None
         S = torch.empty((T, g.Hc, g.Wc), dtype=torch.float32, device=self.device)
         C = torch.empty((T, 8, g.Hc, g.Wc), dtype=torch.float32, device=self.device) if want_C else None
         P = torch.empty((T, g.H, g.W), dtype=torch.float32, device=self.device)
@@ -311,10 +343,16 @@ class Context:
         for t in range(T):
             self.saliency_forward(frames[t], frames[t - 1] if t > 0 else None, S[t], None if C is None else C[t])
             seg = None if segs is None else segs[t]
-            self.prior_update(S[t], seg, P[t])
+            if t == 0 and manual is not None:
+                self.manual_prior(manual, P[0])
+            else:
+                self.prior_update(S[t], seg, P[t])
+                if MU is not None:
+                    mu, _ = self.stochastic_saliency()
+                    MU[t].copy_(mu)
             if with_mrf:
                 self.mrf_weights(frames[t], P[t], U[t], PW[t], B[t])
-        return {"S": S, "C": C, "pi": P, "unary": U, "pairwise": PW, "beta": B}
+        return {"S": S, "C": C, "pi": P, "unary": U, "pairwise": PW, "beta": B, "mu": MU}
 
 
 def saliency_noalloc(H: int, W: int, rgb_t: torch.Tensor, rgb_prev: Optional[torch.Tensor],

@@ -103,6 +103,13 @@ int validate_params(const sp_params* p) {
     return fail(SP_EINVAL, "Gabor wavelength and sigma must be finite and > 0");
   if (p->gabor_radius < 1 || p->gabor_radius > SP_MAXR) return fail(SP_EINVAL, "gabor_radius must be 1..%d", SP_MAXR);
   if (p->record_tape < 0 || p->record_tape > (1 << 20)) return fail(SP_EINVAL, "record_tape must be 0..2^20");
+  if (p->f_mode != 0 && p->f_mode != 1) return fail(SP_EINVAL, "f_mode must be 0 (blur) or 1 (distance transform)");
+  if (!is_fin(p->dt_sigma) || !(p->dt_sigma > 0.f) || p->dt_sigma > 4.f)
+    return fail(SP_EINVAL, "dt_sigma must be in (0, 4]");
+  if (!is_fin(p->ssm_q) || !is_fin(p->ssm_r) || p->ssm_q < 0 || p->ssm_r < 0)
+    return fail(SP_EINVAL, "ssm_q and ssm_r must be finite and >= 0");
+  if (p->record_tape > 0 && (p->f_mode != 0 || p->ssm_r > 0))
+    return fail(SP_EINVAL, "the adjoint covers the default prior only: record_tape needs f_mode 0 and ssm_r 0");
   return SP_OK;
 }
 
@@ -379,6 +386,8 @@ void layout_stream(StreamDesc& sd, const Geo& g, const sp_params& p, Bump& bump,
   sd.flat_tol = p.flat_tol;
   sd.lam = p.lambda;
   sd.potts = p.potts;
+  sd.dt_r = std::min(SP_DT_RMAX, (int)std::ceil(std::sqrt(176.0) * (double)p.dt_sigma));
+  sd.dt_k = (float)(-1.0 / (2.0 * (double)p.dt_sigma * (double)p.dt_sigma * std::log(2.0)));
   fill_taps(sd, p);
   for (int l = std::max(1, first_level); l <= g.top; ++l)
     sd.base[l] = bump.take<float>((size_t)4 * g.Hl[l] * g.Wl[l]);
@@ -574,6 +583,13 @@ struct sp_ctx {
   StepIO* d_rio = nullptr;        // [cap] io of every tape frame (checkpoint and adjoint buffers)
   std::vector<Phase> rec;         // recompute phases (stream-major, CH streams)
   float* S_scratch = nullptr;     // [Hc][Wc] saliency map of the autotuner's steps
+  // variants of the prior
+  float* f_map = nullptr;         // [H][W] distance-transform prediction (f_mode 1)
+  std::vector<Phase> dt;          // its launch
+  float* ssm[2] = {nullptr, nullptr};   // [Hc][Wc] stochastic saliency means (ping-pong)
+  int ssm_cur = 0;
+  int64_t ssm_t = 0;              // maps filtered since the reset
+  double ssm_P = 0.0;             // variance of the stochastic map
   // loss helper
   float* loss_part = nullptr;
   int loss_nblk = 1024;
@@ -703,6 +719,10 @@ void sp_default_params(sp_params* p) {
   p->gabor_sigma = 2.f;
   p->gabor_radius = 6;
   p->record_tape = 0;
+  p->f_mode = 0;
+  p->dt_sigma = 2.f;
+  p->ssm_q = 0.0;
+  p->ssm_r = 0.0;
 }
 
 int sp_destroy(sp_ctx* c) {
@@ -749,6 +769,11 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
     c->pi_state[1] = b.take<float>(HW);
     c->loss_part = b.take<float>(c->loss_nblk);
     c->S_scratch = b.take<float>((size_t)Hc * Wc);
+    if (p->f_mode == 1) c->f_map = b.take<float>(HW);
+    if (p->ssm_r > 0) {
+      c->ssm[0] = b.take<float>((size_t)Hc * Wc);
+      c->ssm[1] = b.take<float>((size_t)Hc * Wc);
+    }
     std::vector<StreamDesc> rsd(c->CH);
     if (c->cap > 0) {
       c->ckpt = b.take<float>((size_t)c->cap * 4 * g.Hl[g.c_min] * g.Wl[g.c_min]);
@@ -833,6 +858,7 @@ int ctx_build_tables(sp_ctx* c) {
   c->mrf.clear();
   c->bwd.clear();
   c->rec.clear();
+  c->dt.clear();
   {
     int nc = 0;
     int rc = forward_phases(g, c->p, c->h_sd, c->tune, c->jobs, c->fwd, &nc);
@@ -854,6 +880,9 @@ int ctx_build_tables(sp_ctx* c) {
     v.clear();
     add_tiles(v, 0, 0, H, W);
     c->mrf.push_back(c->jobs.add(JOB_MRF, 0, v, 1));
+    v.clear();
+    add_tiles_wh(v, 0, 0, H, W, SP_DT_T, SP_DT_T, JOB_DT);
+    c->dt.push_back(c->jobs.add(JOB_DT, 0, order(v), 1));
     v.clear();
     add_tiles(v, 0, 0, H, W);
     c->bwd.push_back(c->jobs.add(JOB_BWD_NU, 0, v, 1));
@@ -949,6 +978,9 @@ int sp_reset(sp_ctx* c) {
   c->t = 0;
   c->P = 0.0;
   c->cur = 0;
+  c->ssm_t = 0;
+  c->ssm_P = 0.0;
+  c->ssm_cur = 0;
   c->tape_ok = true;
   c->tape_gen += 1;
   c->Kf.clear();
@@ -959,6 +991,34 @@ int sp_reset(sp_ctx* c) {
 int64_t sp_step_index(const sp_ctx* c) { return c ? c->t : -1; }
 
 int64_t sp_tape_generation(const sp_ctx* c) { return c ? c->tape_gen : -1; }
+
+int sp_manual_prior(sp_ctx* c, const uint8_t* labels, float* prior_out) {
+  g_err.clear();
+  if (!c || !labels) return fail(SP_EINVAL, "ctx and labels must not be NULL");
+  if (c->cap > 0) return fail(SP_ESTATE, "a context that records a tape starts from the saliency observation");
+  int rc = sp_reset(c);
+  if (rc) return rc;
+  const Geo& g = c->g;
+  float* pnext = c->pi_state[c->cur ^ 1];
+  const hipError_t e = c->prof.timed(c->stream, JOB_MANUAL, [&] {
+    return sp_launch_manual(labels, pnext, prior_out, (size_t)g.H * g.W, c->p.eps, c->stream);
+  });
+  if (e != hipSuccess) return fail(SP_EHIP, "manual prior launch: %s", hipGetErrorString(e));
+  (void)now_gain(0, 0.0, c->p.q, c->p.r, &c->P);   // P_0 = R, as after a first observation
+  c->cur ^= 1;
+  c->t = 1;
+  return SP_OK;
+}
+
+int sp_stochastic_saliency(const sp_ctx* c, const float** mean, double* var) {
+  g_err.clear();
+  if (!c || !mean || !var) return fail(SP_EINVAL, "NULL argument");
+  if (!c->ssm[0]) return fail(SP_ESTATE, "the stochastic saliency map is off (ssm_r = 0)");
+  if (c->ssm_t == 0) return fail(SP_ESTATE, "no prior update since the reset");
+  *mean = c->ssm[c->ssm_cur];
+  *var = c->ssm_P;
+  return SP_OK;
+}
 
 int saliency_forward(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, float* S_out, float* C_out) {
   g_err.clear();
@@ -983,6 +1043,44 @@ int saliency_forward(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, f
   return SP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The variant phases of a prior update, before its Kalman phase: the stochastic saliency
+// map (which then replaces S as the observation, with its max partials) and the
+// distance-transform prediction.  `smax` says whether the max partials of the observation
+// must still be taken (the fused step has them from the conspicuity pass).
+int prior_variants(sp_ctx* c, StepIO& io, bool smax) {
+  double Ps = 0.0;
+  if (c->ssm[0]) {
+    const double Ks = now_gain(c->ssm_t, c->ssm_P, c->p.ssm_q, c->p.ssm_r, &Ps);
+    io.ssm_prev = c->ssm_t == 0 ? nullptr : c->ssm[c->ssm_cur];
+    io.ssm_next = c->ssm[c->ssm_cur ^ 1];
+    io.Ks = (float)Ks;
+  }
+  if (smax || c->ssm[0]) {
+    int rc = run_phase(c, c->prior.front(), c->d_sd, nullptr, &io, c->prior.front().n);   // the max partials
+    if (rc) return rc;
+  }
+  if (c->ssm[0]) {
+    io.S_in = io.ssm_next;
+    c->ssm_P = Ps;
+    c->ssm_cur ^= 1;
+    c->ssm_t += 1;
+  }
+  if (c->f_map && io.t > 0) {
+    io.f_map = c->f_map;
+    int rc = run_phase(c, c->dt.front(), c->d_sd, nullptr, &io, c->dt.front().n);
+    if (rc) return rc;
+  }
+  return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int prior_update(sp_ctx* c, const float* S, const uint8_t* seg_prev, float* prior_out) {
   g_err.clear();
   if (!c || !S) return fail(SP_EINVAL, "ctx and S must not be NULL");
@@ -1004,10 +1102,10 @@ int prior_update(sp_ctx* c, const float* S, const uint8_t* seg_prev, float* prio
     io.f_tape = c->f_tape + (size_t)c->t * g.H * g.W;
     io.ms_tape = c->ms_tape + (size_t)c->t * 2;
   }
-  for (const Phase& ph : c->prior) {
-    int rc = run_phase(c, ph, c->d_sd, nullptr, &io, ph.n);
-    if (rc) return rc;
-  }
+  int rc = prior_variants(c, io, true);
+  if (rc) return rc;
+  rc = run_phase(c, c->prior.back(), c->d_sd, nullptr, &io, c->prior.back().n);   // the Kalman phase
+  if (rc) return rc;
   if (c->cap > 0) {
     // gains and variances of the recorded steps (host -> device, from values that stay
     // alive in the context until the next reset)
@@ -1062,7 +1160,9 @@ int sp_step(sp_ctx* c, const uint8_t* rgb_t, const uint8_t* rgb_prev, const uint
     int rc = run_phase(c, ph, c->d_sd, nullptr, &io, ph.n);
     if (rc) return rc;
   }
-  int rc = run_phase(c, c->prior.back(), c->d_sd, nullptr, &io, c->prior.back().n);   // the Kalman phase
+  int rc = prior_variants(c, io, false);
+  if (rc) return rc;
+  rc = run_phase(c, c->prior.back(), c->d_sd, nullptr, &io, c->prior.back().n);   // the Kalman phase
   if (rc) return rc;
   if (c->cap > 0) {
     c->Kf.push_back((float)K);
@@ -1348,6 +1448,7 @@ int sp_get_state(sp_ctx* c, void* buf, size_t bytes) {
   int rc = sp_state_size(c, &need);
   if (rc) return rc;
   if (!buf || bytes < need) return fail(SP_EINVAL, "state buffer needs %zu bytes", need);
+  if (c->ssm[0]) return fail(SP_ESTATE, "the checkpoint does not hold the stochastic saliency map (ssm_r > 0)");
   const size_t HW = (size_t)c->g.H * c->g.W;
   HIPCHK(hipMemcpyAsync(buf, c->pi_state[c->cur], HW * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   double sc[2] = {(double)c->t, c->P};
@@ -1362,6 +1463,7 @@ int sp_set_state(sp_ctx* c, const void* buf, size_t bytes) {
   int rc = sp_state_size(c, &need);
   if (rc) return rc;
   if (!buf || bytes < need) return fail(SP_EINVAL, "state buffer needs %zu bytes", need);
+  if (c->ssm[0]) return fail(SP_ESTATE, "the checkpoint does not hold the stochastic saliency map (ssm_r > 0)");
   const size_t HW = (size_t)c->g.H * c->g.W;
   double sc[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(sc, (const char*)buf + HW * sizeof(float), sizeof sc, hipMemcpyDeviceToHost, c->stream));
@@ -1408,7 +1510,7 @@ const char* sp_kernel_name(int32_t k) {
   static const char* names[SP_NKINDS] = {"k_rgb", "k_feat", "k_pyr", "k_pyr", "k_csstats", "k_csapply",
                                          "k_consp", "k_smax", "k_kalman", "k_mrf", "k_bwd_nu", "k_bwd_gs",
                                          "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_csfinal", "k_csg", "k_csmix",
-                                         "k_bwd_final"};
+                                         "k_bwd_final", "k_dt", "k_manual"};
   return (k >= 0 && k < SP_NKINDS) ? names[k] : "";
 }
 
@@ -1782,6 +1884,8 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
   int rc = validate_params(p);
   if (rc) return rc;
   if (flags & ~(SP_BATCH_MRF | SP_BATCH_CONSP)) return fail(SP_EINVAL, "unknown batch flags 0x%x", flags);
+  if (p->f_mode != 0 || p->ssm_r > 0)
+    return fail(SP_EINVAL, "the batched step runs the default prior (f_mode 0, no stochastic map)");
   const bool mrf = (flags & SP_BATCH_MRF) != 0;
   const bool consp = (flags & SP_BATCH_CONSP) != 0;
   sp_batch* b = new (std::nothrow) sp_batch();

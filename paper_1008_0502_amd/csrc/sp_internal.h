@@ -18,6 +18,8 @@
 #define SP_RGB_TC 256       // most columns of a colour-statistics tile (4 pixels per lane)
 #define SP_NOALLOC_BYTES (64u << 20)   // device scratch of the allocation-free saliency entry point
 #define SP_NOALLOC_DEVICES 64          // devices whose scratch address is remembered
+#define SP_DT_T 32          // tile edge of the distance-transform prediction
+#define SP_DT_RMAX 54       // its largest search radius (decay length 4 pixels)
 
 // Base channels are stored per level as [4][H_l][W_l] in the order I, RG, BY, M;
 // orientation maps per used level as [4][H_l][W_l] in the order O0, O45, O90, O135.
@@ -45,6 +47,8 @@ enum JobKind : int32_t {
                     // their reduction to c_max (pairs with c_max - c <= 1)
   JOB_CSMIX,        // c_max tile: F-bar as the sum of the normalised reduced maps (+ partials)
   JOB_BWD_FINAL,    // reduction of the adjoint partials (timing id only)
+  JOB_DT,           // level-0 tile: prediction f from the distance to the previous object
+  JOB_MANUAL,       // prior of the first frame from manual labels (timing id only)
   JOB_NKINDS
 };
 
@@ -90,6 +94,8 @@ struct StreamDesc {
   float w[SP_NCH];
   float eps, flat_tol, lam, potts;
   float c45;                     // DC weight of the diagonal Gabor kernels
+  int32_t dt_r;                  // distance-transform prediction: search radius (pixels)
+  float dt_k;                    // its exponent factor, -log2(e) / (2 sigma^2)
   float gf[4][2 * SP_MAXR + 1];  // 1-D Gabor factors: g, g*(cos - c0), g*cos(a u), g*sin(a u)
 };
 
@@ -115,6 +121,11 @@ struct StepIO {
   const float* gs;           // [Hc][Wc] adjoint of S of the frame
   float* dot;                // [n_cmax_tiles][8] partial sums of gs * C_k
   float* cx;                 // [8] C_k at the frame's argmax of S (ms_tape: its max and argmax)
+  // variants of the prior
+  float* f_map;              // [H][W] prediction f from the distance transform (null: blur)
+  const float* ssm_prev;     // [Hc][Wc] stochastic saliency means of step t-1 (null: first step)
+  float* ssm_next;           // [Hc][Wc] means of this step (null: no stochastic map)
+  float Ks;                  // gain of the stochastic map at this step
   float K;                   // Kalman gain of this step
   int32_t t;                 // step index
 };

@@ -42,3 +42,5 @@ hipError_t sp_launch_calib(const float* src, float* dst, size_t n16, int mode, h
 // Device address of the allocation-free entry point's scratch array on the current device
 // (SP_NOALLOC_BYTES bytes; looked up once per device, then remembered).
 hipError_t sp_noalloc_scratch(void** ptr);
+// Prior of the first frame from manual labels (n pixels).
+hipError_t sp_launch_manual(const uint8_t* labels, float* pnext, float* pout, size_t n, float eps, hipStream_t st);

@@ -2043,7 +2043,15 @@ __global__ __launch_bounds__(SP_BLOCK) void k_smax(const Job* __restrict__ jobs,
   const int y = J.y0 + yy, x = J.x0 + xx;
   const bool valid = yy < J.th && xx < J.tw;
   const size_t o = (size_t)min(y, Hm - 1) * Wm + min(x, Wm - 1);
-  smax_partial(S_in[o], (int)o, valid, G(sd.s_part) + 2 * (size_t)J.tid, sh4, shi4);
+  float v = S_in[o];
+  float* sn = IOF(ssm_next);
+  if (sn) {
+    // stochastic saliency map: mu_t = mu_{t-1} + K_s (S_t - mu_{t-1}), mu_0 = S_0
+    const float* sp = IOF(ssm_prev);
+    if (sp) v = fmaf(IOF(Ks), v - sp[o], sp[o]);
+    if (valid) sn[o] = v;
+  }
+  smax_partial(v, (int)o, valid, G(sd.s_part) + 2 * (size_t)J.tid, sh4, shi4);
 }
 
 // ---------------------------------------------------------------- Kalman prior update
@@ -2077,7 +2085,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   // (row stride rs; column x at x - x0 + 4), clamped to the frame.  Interior tiles of a
   // float prior whose rows are 16-byte aligned are staged by 16-byte transfers.
   const int tw = J.tw, rs = (tw + 11) & ~3;
-  if (t > 0) {
+  const gp<const float> fmap = G((const float*)IOF(f_map));
+  if (t > 0 && !fmap) {
     const bool quads = !seg && (W & 3) == 0 && (tw & 3) == 0 && J.x0 >= 4 && J.x0 + tw + 4 <= W &&
                        (reinterpret_cast<uintptr_t>(pprev) & 15) == 0;
     const gp<const float> gprev = G(pprev);
@@ -2130,7 +2139,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   const int ng = SP_BLOCK / cw, rp = (J.th + ng - 1) / ng;   // rp <= RPMAX: cw <= KTW_MAX
   const int ya = (int)(threadIdx.x / cw) * rp, nr = min(rp, J.th - ya);
   float hv[RPMAX + 4];
-  if (t > 0 && xx < tw) {
+  if (t > 0 && !fmap && xx < tw) {
 #pragma unroll
     for (int k = 0; k < RPMAX + 4; ++k)
       if (k < nr + 4) {   // region rows ya .. ya + nr + 3 <= th + 3, all staged
@@ -2168,7 +2177,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
     float pi = q;
     const uint32_t ob = ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 4u;
     if (t > 0) {
-      const float f = kB0 * hv[k] + kB1 * hv[k + 1] + kB2 * hv[k + 2] + kB1 * hv[k + 3] + kB0 * hv[k + 4];
+      const float f = fmap ? *at_bytes(fmap, ob)
+                           : kB0 * hv[k] + kB1 * hv[k + 1] + kB2 * hv[k + 2] + kB1 * hv[k + 3] + kB0 * hv[k + 4];
       pi = f + K * (q - f);
       if (ftape) *at_bytes(ftape, ob) = f;
     }
@@ -2183,6 +2193,83 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
   if (mstape && J.tid == 0 && threadIdx.x == 0) {
     mstape[0] = m;
     mstape[1] = __int_as_float(xs);
+  }
+}
+
+// ---------------------------------------------------------------- distance-transform prediction
+// f(A, x) = exp(-d(x)^2 / (2 sigma^2)), d the Euclidean distance from x to the nearest
+// object pixel of the previous segmentation (or of prior > 1/2 without one).  The search
+// radius R has exp(-R^2 / (2 sigma^2)) below FP32's normal range, so a pixel with no object
+// within R gets 0 and every other pixel its exact squared distance: a column pass gives the
+// distance to the nearest object in the pixel's column within R, a row pass the minimum of
+// v(x')^2 + (x - x')^2 over |x - x'| <= R.
+constexpr int DT_N = SP_DT_T + 2 * SP_DT_RMAX;
+constexpr int DT_INF = 1 << 30;
+__global__ __launch_bounds__(SP_BLOCK) void k_dt(const Job* __restrict__ jobs, const StreamDesc* __restrict__ sds,
+                                                 const StepIO* __restrict__ ios, StepIO io0) {
+  __shared__ uint8_t obj[DT_N * DT_N];
+  __shared__ int vd[SP_DT_T * DT_N];
+  const Job J = jobs[blockIdx.x];
+  const StreamDesc& sd = sds[J.stream];
+  const gp<const uint8_t> seg = G(IOF(seg_prev));
+  const gp<const float> pprev = G(IOF(pi_prev));
+  const gp<float> fout = G(IOF(f_map));
+  const int H = sd.H, W = sd.W, R = sd.dt_r;
+  const int nr = J.th + 2 * R, nc = J.tw + 2 * R;
+  const int ry0 = J.y0 - R, rx0 = J.x0 - R;
+  {
+    Walk2 wk(threadIdx.x, nc);
+    for (int i0 = 0; i0 + (int)threadIdx.x < nr * nc; i0 += SP_BLOCK, wk.next()) {
+      const int y = ry0 + wk.r, x = rx0 + wk.c;
+      uint8_t o = 0;
+      if (y >= 0 && y < H && x >= 0 && x < W) {
+        const uint32_t k = (uint32_t)y * (uint32_t)W + (uint32_t)x;
+        o = seg ? (uint8_t)(seg[k] != 0) : (uint8_t)(pprev[k] > 0.5f);
+      }
+      obj[i0 + threadIdx.x] = o;
+    }
+  }
+  __syncthreads();
+  const int R2 = R * R;
+  for (int c = threadIdx.x; c < nc; c += SP_BLOCK) {
+    int last = -DT_INF;   // region row of the nearest object at or above
+    for (int r = 0; r < R + J.th; ++r) {
+      if (obj[r * nc + c]) last = r;
+      if (r >= R) {
+        const int d = r - last;
+        vd[(r - R) * nc + c] = d <= R ? d * d : DT_INF;
+      }
+    }
+    int next = DT_INF;    // region row of the nearest object at or below
+    for (int r = nr - 1; r >= R; --r) {
+      if (obj[r * nc + c]) next = r;
+      if (r < R + J.th) {
+        const int d = next - r;
+        int& v = vd[(r - R) * nc + c];
+        if (d <= R) v = min(v, d * d);
+      }
+    }
+  }
+  __syncthreads();
+  const float k2 = sd.dt_k;
+  Walk2 wk(threadIdx.x, J.tw);
+  for (int i0 = 0; i0 + (int)threadIdx.x < J.th * J.tw; i0 += SP_BLOCK, wk.next()) {
+    const int* row = vd + wk.r * nc + wk.c + R;
+    int best = row[0];
+    for (int k = 1; k <= R && k * k < best; ++k) best = min(best, min(row[-k], row[k]) + k * k);
+    const float f = best <= R2 ? __builtin_amdgcn_exp2f((float)best * k2) : 0.f;
+    fout[(uint32_t)(J.y0 + wk.r) * (uint32_t)W + (uint32_t)(J.x0 + wk.c)] = f;
+  }
+}
+
+// Prior of the first frame from manual labels: 1 -> 1, 0 -> eps, anything else -> 0.5.
+__global__ __launch_bounds__(SP_BLOCK) void k_manual(const uint8_t* __restrict__ lab, float* __restrict__ pnext,
+                                                     float* __restrict__ pout, uint32_t n, float eps) {
+  for (uint32_t i = blockIdx.x * SP_BLOCK + threadIdx.x; i < n; i += gridDim.x * SP_BLOCK) {
+    const uint8_t l = lab[i];
+    const float v = l == 1 ? 1.f : (l == 0 ? eps : 0.5f);
+    pnext[i] = v;
+    if (pout) pout[i] = v;
   }
 }
 
@@ -2472,6 +2559,10 @@ __device__ void batch_begin_stream(int i, BatchState* __restrict__ st, const Str
   io->unary = s.unary;
   io->pairwise = s.pairwise;
   io->beta_out = s.beta;
+  io->f_map = nullptr;
+  io->ssm_prev = nullptr;
+  io->ssm_next = nullptr;
+  io->Ks = 0.f;
   io->K = (float)K;
   io->t = (int32_t)(s.t < 0x7fffffff ? s.t : 0x7fffffff);
   s.t += 1;
@@ -2607,6 +2698,7 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
     case JOB_SMAX: hipLaunchKernelGGL(k_smax, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_KALMAN: hipLaunchKernelGGL(k_kalman, g, b, 0, st, jobs, sds, ios, io); break;
     case JOB_MRF: hipLaunchKernelGGL(k_mrf, g, b, 0, st, jobs, sds, ios, io, aux); break;
+    case JOB_DT: hipLaunchKernelGGL(k_dt, g, b, 0, st, jobs, sds, ios, io); break;
     default: return hipErrorInvalidValue;
   }
   return chk();
@@ -2697,6 +2789,13 @@ hipError_t sp_csapply_reserve_lds(size_t bytes) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t sp_launch_manual(const uint8_t* labels, float* pnext, float* pout, size_t n, float eps, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<size_t>((n + SP_BLOCK - 1) / SP_BLOCK, 4096);
+  hipLaunchKernelGGL(k_manual, dim3(blocks), dim3(SP_BLOCK), 0, st, labels, pnext, pout, (uint32_t)n, eps);
+  return chk();
 }
 
 hipError_t sp_launch_calib(const float* src, float* dst, size_t n16, int mode, hipStream_t st) {
