@@ -19,6 +19,8 @@ paper (Sections 3-6) and from the readings taken where the paper is silent:
 * variants.py  -- the variants of the prior: f by distance transform (Section 6), the
                   manual first-frame prior (Section 4, Section 8.1) and the stochastic
                   saliency map (Section 3).
+* gmm.py       -- the colour likelihood of the t-links: two RGB Gaussian mixtures fitted
+                  by EM with every pixel weighted by the prior (Sections 4, 5, 8.1).
 
 Parity status: every function is pinned by the CPU tests (constant images, Gabor
 closed form, Kalman steady state, brute-force loops, adjoint dot products, gauge
@@ -31,7 +33,7 @@ from .saliency import (OracleParams, Geometry, geometry, colour_max, features, b
                        saliency)
 from .prior import (observation, kalman_gains, prior_clip, mrf_weights, border_mask,
                     run_clip)
-from . import variants
+from . import gmm, variants
 from .adjoint import (mse_mask_loss, prior_chain_forward, prior_chain_backward, blur_adjoint,
                       upsample_adjoint, finite_difference_grad)
 
