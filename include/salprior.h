@@ -76,6 +76,10 @@ typedef struct sp_params {
   double ssm_q;        /* stochastic saliency map (Section 3): with ssm_r > 0 the observation */
   double ssm_r;        /* is taken from a per-pixel Kalman filter of S with process variance
                           ssm_q >= 0 and observation variance ssm_r (0, 0: off) */
+  /* Colour likelihood of the t-links (sp_colour_likelihood). */
+  int32_t gmm_components; /* Gaussians per label, 0..4 (3; 0: the call is unavailable) */
+  int32_t gmm_iters;   /* EM iterations after the start, 0..100 (10) */
+  float gmm_reg;       /* added to every covariance diagonal, colours in [0, 1] (1e-4) */
 } sp_params;
 
 /* Geometry of a context, as derived by sp_create. */
@@ -174,6 +178,23 @@ int sp_stochastic_saliency(const sp_ctx* ctx, const float** mean, double* var);
  *                pairs (0 for a constant frame). */
 int mrf_weights(sp_ctx* ctx, const uint8_t* rgb_t, const float* prior, float* unary_out, float* pairwise_out,
                 float* beta_out);
+
+/* Colour likelihood of the t-links (Section 4: psi_1(D | A_x) = -log p(C_x | A_x), p a
+ * Gaussian mixture over RGB fitted by EM; Section 5: every pixel is a sample weighted by
+ * the prior; Section 8.1: M = 3).  For each label it fits a mixture of
+ * p->gmm_components Gaussians (full covariances, colours RGB / 255) by weighted EM -- the
+ * object's samples weighted by prior, the background's by 1 - prior -- starting from the
+ * label's weighted mean and covariance with the means spread along the covariance's
+ * leading eigenvector, for p->gmm_iters iterations (covariances + gmm_reg I), then adds
+ * psi_1 of each label to its unary cost.  A label whose weight vanishes adds nothing.
+ *   rgb_t        [H][W][3] uint8.
+ *   prior        [H][W] float p(A_x = 1).
+ *   unary_inout  [2][H][W] float: U0 += psi_1(C | A = 0), U1 += psi_1(C | A = 1) (pass
+ *                zeros to receive psi_1 alone, or mrf_weights' unary_out to get both terms).
+ *   gmm_out      [2][M][10] float or NULL: per label and component the weight, mean (3)
+ *                and covariance (xx, xy, xz, yy, yz, zz); zeros for dropped components.
+ * SP_ESTATE when the context was created with gmm_components = 0. */
+int sp_colour_likelihood(sp_ctx* ctx, const uint8_t* rgb_t, const float* prior, float* unary_inout, float* gmm_out);
 
 /* The whole per-frame path in one call, with fewer kernel launches than the three
  * calls above: saliency_forward, then prior_update on S_out, then (when unary_out and
@@ -278,7 +299,7 @@ int sp_batch_backward(sp_batch* b, const float* const* grad_prior, int32_t T, fl
  * 65536 pairs).  sp_profile_read synchronises the stream and returns, per kernel kind
  * 0..SP_NKINDS-1, the summed device time in ms and the number of launches since the
  * last read (arrays of length n >= SP_NKINDS), then clears the record. */
-#define SP_NKINDS 22
+#define SP_NKINDS 25
 int sp_profile_enable(sp_ctx* ctx, int32_t enable);
 int sp_profile_read(sp_ctx* ctx, int32_t n, float* total_ms, int32_t* launches);
 /* The same measurement hook for a batch: while enabled, sp_batch_step launches the

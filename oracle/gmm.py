@@ -17,9 +17,10 @@ p(A_x = 1); Section 8.1 takes M = 3.  Readings taken here:
   covariance Sigma + reg I, weights 1 / M;
 * a fixed number of EM iterations; the M-step adds reg I to every covariance;
 * a component whose weighted count falls to at most 1e-12 of the label's total weight,
-  or whose covariance is not positive definite, gets weight 0 and keeps its mean and
-  covariance (it no longer takes part); a label whose total weight is at most 1e-12 per
-  pixel has no likelihood (psi_1 = 0 for it);
+  or whose covariance is not positive definite (also at the start), gets weight 0 and
+  keeps its mean and covariance (it no longer takes part); a label whose total weight is
+  at most 1e-12 per pixel, or that has no component left, has no likelihood (psi_1 = 0
+  for it);
 * psi_1 is added to the unary costs: U0 += psi_1(C | A = 0), U1 += psi_1(C | A = 1).
 """
 from __future__ import annotations
@@ -67,8 +68,10 @@ def init_mixture(C: np.ndarray, w: np.ndarray, M: int, reg: float) -> Dict:
     lam, v = principal_axis(S)
     z = np.linspace(-1.0, 1.0, M) if M > 1 else np.zeros(1)
     s = math.sqrt(max(lam, 0.0))
-    return {"alpha": np.full(M, 1.0 / M), "mu": mu[None, :] + z[:, None] * s * v[None, :],
-            "cov": np.repeat((S + reg * np.eye(3))[None], M, axis=0)}
+    cov = S + reg * np.eye(3)
+    alpha = np.full(M, 1.0 / M) if _usable(cov) else np.zeros(M)
+    return {"alpha": alpha, "mu": mu[None, :] + z[:, None] * s * v[None, :],
+            "cov": np.repeat(cov[None], M, axis=0)}
 
 
 def _usable(cov: np.ndarray) -> bool:
@@ -134,6 +137,8 @@ def fit_mixture(C: np.ndarray, w: np.ndarray, M: int, iters: int, reg: float):
     if not float(w.sum()) > 1e-12 * w.size:
         return None, []
     mix = init_mixture(C, w, M, reg)
+    if not np.any(mix["alpha"] > 0.0):
+        return mix, []
     hist = [float((w * log_likelihood(C, mix)).sum())]
     for _ in range(iters):
         mix = em_step(C, w, mix, reg)
@@ -152,6 +157,6 @@ def colour_likelihood(rgb: np.ndarray, prior: np.ndarray, M: int = 3, iters: int
     for lab, w in ((0, 1.0 - pi), (1, pi)):
         mix, _ = fit_mixture(C, w, M, iters, reg)
         mixes.append(mix)
-        if mix is not None:
+        if mix is not None and np.any(mix["alpha"] > 0.0):
             psi[lab] = -log_likelihood(C, mix)
     return psi.reshape(2, H, W), mixes

@@ -42,6 +42,9 @@ class Params:
     dt_sigma: float = 2.0
     ssm_q: float = 0.0
     ssm_r: float = 0.0
+    gmm_components: int = 3
+    gmm_iters: int = 10
+    gmm_reg: float = 1e-4
 
     def to_c(self) -> _lib.sp_params:
         p = _lib.sp_params()
@@ -72,6 +75,9 @@ class Params:
         p.f_mode = int(self.f_mode)
         p.dt_sigma = float(self.dt_sigma)
         p.ssm_q, p.ssm_r = float(self.ssm_q), float(self.ssm_r)
+        p.gmm_components = int(self.gmm_components)
+        p.gmm_iters = int(self.gmm_iters)
+        p.gmm_reg = float(self.gmm_reg)
         return p
 
 
@@ -237,6 +243,23 @@ class Context:
         check(self.lib.mrf_weights(self._handle, _ptr(rgb_t), _ptr(prior), _ptr(unary_out), _ptr(pairwise_out),
                                    _ptr(beta_out)), "mrf_weights")
         return unary_out, pairwise_out, beta_out
+
+    def colour_likelihood(self, rgb_t: torch.Tensor, prior: torch.Tensor, unary_inout=None,
+                          want_params: bool = False):
+        """sp_colour_likelihood: adds psi_1 of both labels to unary_inout [2][H][W] (zeros
+        when None); returns (unary, mixture parameters [2][M][10] or None)."""
+        g = self.geometry
+        _need(rgb_t, "rgb_t", torch.uint8, (g.H, g.W, 3), self.device)
+        _need(prior, "prior", torch.float32, (g.H, g.W), self.device)
+        if unary_inout is None:
+            unary_inout = torch.zeros((2, g.H, g.W), dtype=torch.float32, device=self.device)
+        _need(unary_inout, "unary_inout", torch.float32, (2, g.H, g.W), self.device)
+        M = self.params.gmm_components
+        out = torch.empty((2, max(M, 1), 10), dtype=torch.float32, device=self.device) if want_params else None
+        self._bind_stream()
+        check(self.lib.sp_colour_likelihood(self._handle, _ptr(rgb_t), _ptr(prior), _ptr(unary_inout), _ptr(out)),
+              "sp_colour_likelihood")
+        return unary_inout, out
 
     def step(self, rgb_t: torch.Tensor, rgb_prev: Optional[torch.Tensor] = None,
              seg_prev: Optional[torch.Tensor] = None, S_out: Optional[torch.Tensor] = None,

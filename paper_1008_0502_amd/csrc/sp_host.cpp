@@ -108,6 +108,10 @@ int validate_params(const sp_params* p) {
     return fail(SP_EINVAL, "dt_sigma must be in (0, 4]");
   if (!is_fin(p->ssm_q) || !is_fin(p->ssm_r) || p->ssm_q < 0 || p->ssm_r < 0)
     return fail(SP_EINVAL, "ssm_q and ssm_r must be finite and >= 0");
+  if (p->gmm_components < 0 || p->gmm_components > SP_GMM_MAXM)
+    return fail(SP_EINVAL, "gmm_components must be 0..%d", SP_GMM_MAXM);
+  if (p->gmm_iters < 0 || p->gmm_iters > 100) return fail(SP_EINVAL, "gmm_iters must be 0..100");
+  if (!is_fin(p->gmm_reg) || p->gmm_reg < 0) return fail(SP_EINVAL, "gmm_reg must be finite and >= 0");
   if (p->record_tape > 0 && (p->f_mode != 0 || p->ssm_r > 0))
     return fail(SP_EINVAL, "the adjoint covers the default prior only: record_tape needs f_mode 0 and ssm_r 0");
   return SP_OK;
@@ -590,6 +594,10 @@ struct sp_ctx {
   int ssm_cur = 0;
   int64_t ssm_t = 0;              // maps filtered since the reset
   double ssm_P = 0.0;             // variance of the stochastic map
+  // colour likelihood
+  GmmState* gmm_state = nullptr;
+  double* gmm_part = nullptr;     // [2 M 10][gmm_tiles] FP64 moments per tile
+  int gmm_tiles = 0;
   // loss helper
   float* loss_part = nullptr;
   int loss_nblk = 1024;
@@ -723,6 +731,9 @@ void sp_default_params(sp_params* p) {
   p->dt_sigma = 2.f;
   p->ssm_q = 0.0;
   p->ssm_r = 0.0;
+  p->gmm_components = 3;
+  p->gmm_iters = 10;
+  p->gmm_reg = 1e-4f;
 }
 
 int sp_destroy(sp_ctx* c) {
@@ -770,6 +781,11 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
     c->loss_part = b.take<float>(c->loss_nblk);
     c->S_scratch = b.take<float>((size_t)Hc * Wc);
     if (p->f_mode == 1) c->f_map = b.take<float>(HW);
+    if (p->gmm_components > 0) {
+      c->gmm_tiles = (int)((HW + SP_GMM_TILE - 1) / SP_GMM_TILE);
+      c->gmm_state = b.take<GmmState>(1);
+      c->gmm_part = b.take<double>((size_t)2 * p->gmm_components * 10 * c->gmm_tiles);
+    }
     if (p->ssm_r > 0) {
       c->ssm[0] = b.take<float>((size_t)Hc * Wc);
       c->ssm[1] = b.take<float>((size_t)Hc * Wc);
@@ -1008,6 +1024,37 @@ int sp_manual_prior(sp_ctx* c, const uint8_t* labels, float* prior_out) {
   c->cur ^= 1;
   c->t = 1;
   return SP_OK;
+}
+
+int sp_colour_likelihood(sp_ctx* c, const uint8_t* rgb_t, const float* prior, float* unary_inout, float* gmm_out) {
+  g_err.clear();
+  if (!c || !rgb_t || !prior || !unary_inout) return fail(SP_EINVAL, "ctx, rgb_t, prior and unary_inout must not be NULL");
+  const int M = c->p.gmm_components;
+  if (M < 1 || !c->gmm_state) return fail(SP_ESTATE, "the context was created with gmm_components = 0");
+  GmmIO io{};
+  io.rgb = rgb_t;
+  io.prior = prior;
+  io.st = c->gmm_state;
+  io.part = c->gmm_part;
+  io.unary = unary_inout;
+  io.n = c->g.H * c->g.W;
+  io.ntiles = c->gmm_tiles;
+  io.reg = c->p.gmm_reg;
+  const int iters = c->p.gmm_iters;
+  auto launch = [&](int phase, int kind, float* out) -> int {
+    io.out = out;
+    const hipError_t e = c->prof.timed(c->stream, kind, [&] { return sp_launch_gmm(phase, M, io, c->stream); });
+    if (e != hipSuccess) return fail(SP_EHIP, "colour likelihood launch (phase %d): %s", phase, hipGetErrorString(e));
+    return SP_OK;
+  };
+  int rc = launch(0, JOB_GMM_ACC, nullptr);
+  if (!rc) rc = launch(1, JOB_GMM_FIT, iters == 0 ? gmm_out : nullptr);
+  for (int it = 0; it < iters && !rc; ++it) {
+    rc = launch(2, JOB_GMM_ACC, nullptr);
+    if (!rc) rc = launch(3, JOB_GMM_FIT, it == iters - 1 ? gmm_out : nullptr);
+  }
+  if (!rc) rc = launch(4, JOB_GMM_PSI, nullptr);
+  return rc;
 }
 
 int sp_stochastic_saliency(const sp_ctx* c, const float** mean, double* var) {
@@ -1510,7 +1557,8 @@ const char* sp_kernel_name(int32_t k) {
   static const char* names[SP_NKINDS] = {"k_rgb", "k_feat", "k_pyr", "k_pyr", "k_csstats", "k_csapply",
                                          "k_consp", "k_smax", "k_kalman", "k_mrf", "k_bwd_nu", "k_bwd_gs",
                                          "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_csfinal", "k_csg", "k_csmix",
-                                         "k_bwd_final", "k_dt", "k_manual"};
+                                         "k_bwd_final", "k_dt", "k_manual", "k_gmm_acc", "k_gmm_fit",
+                                         "k_gmm_psi"};
   return (k >= 0 && k < SP_NKINDS) ? names[k] : "";
 }
 

@@ -49,6 +49,9 @@ enum JobKind : int32_t {
   JOB_BWD_FINAL,    // reduction of the adjoint partials (timing id only)
   JOB_DT,           // level-0 tile: prediction f from the distance to the previous object
   JOB_MANUAL,       // prior of the first frame from manual labels (timing id only)
+  JOB_GMM_ACC,      // colour likelihood: prior-weighted moments of a pixel tile (timing id only)
+  JOB_GMM_FIT,      // colour likelihood: mixture parameters from the moments (timing id only)
+  JOB_GMM_PSI,      // colour likelihood: -log p(C | A) added to the unary costs (timing id only)
   JOB_NKINDS
 };
 
@@ -295,3 +298,33 @@ __host__ __device__ inline CgLayout csg_layout(const int32_t* pc, const int32_t*
 #define CG_SET1_N 4
 __host__ __device__ constexpr int cg_set1_r(int p) { return p < 2 ? 1 : 0; }
 __host__ __device__ constexpr int cg_set1_d(int p) { return 2 + (p & 1); }
+
+// Colour likelihood of the t-links: per label (0 background, 1 object) a mixture of up to
+// SP_GMM_MAXM Gaussians over RGB in [0, 1].
+#define SP_GMM_MAXM 4
+#define SP_GMM_TILE 1024   // pixels of an accumulation workgroup (4 per thread)
+struct GmmComp {           // E-step form of one component (FP32)
+  float mu[3];             // mean, also the centre of the moments accumulated for it
+  float P[6];              // precision: xx, xy, xz, yy, yz, zz
+  float lnorm;             // log(alpha) - log det(Sigma) / 2 - 3 log(2 pi) / 2
+  int32_t on;              // weight > 0
+  int32_t pad;
+};
+struct GmmState {
+  double alpha[2][SP_GMM_MAXM];
+  double mu[2][SP_GMM_MAXM][3];
+  double cov[2][SP_GMM_MAXM][6];
+  GmmComp comp[2][SP_GMM_MAXM];
+  int32_t label_on[2];     // the label's total weight is positive
+};
+struct GmmIO {
+  const uint8_t* rgb;      // [n][3]
+  const float* prior;      // [n] p(A = 1): the object's sample weights (1 - p: the background's)
+  GmmState* st;
+  double* part;            // [values][ntiles] FP64 moments per tile
+  float* unary;            // [2][n], psi added in place
+  float* out;              // [2][M][10] alpha, mu, cov (xx, xy, xz, yy, yz, zz) or null
+  int32_t n, ntiles;
+  float reg;               // added to the covariance diagonals
+  int32_t pad;
+};

@@ -44,3 +44,6 @@ hipError_t sp_launch_calib(const float* src, float* dst, size_t n16, int mode, h
 hipError_t sp_noalloc_scratch(void** ptr);
 // Prior of the first frame from manual labels (n pixels).
 hipError_t sp_launch_manual(const uint8_t* labels, float* pnext, float* pout, size_t n, float eps, hipStream_t st);
+// Colour likelihood phases: 0 start moments, 1 start fit, 2 E-step moments, 3 M-step fit,
+// 4 psi added to the unary costs (M = components per label, 1..SP_GMM_MAXM).
+hipError_t sp_launch_gmm(int phase, int M, const GmmIO& io, hipStream_t st);
