@@ -196,6 +196,30 @@ int mrf_weights(sp_ctx* ctx, const uint8_t* rgb_t, const float* prior, float* un
  * SP_ESTATE when the context was created with gmm_components = 0. */
 int sp_colour_likelihood(sp_ctx* ctx, const uint8_t* rgb_t, const float* prior, float* unary_inout, float* gmm_out);
 
+/* Minimum cut of the MRF (Section 4: the MAP labelling is the minimum s-t cut of the graph
+ * of Eqs. 2-4), the segmentation that closes the loop of Section 6 when passed as the next
+ * frame's seg_prev.  An sp_cut holds the residual graph of H x W frames (44 bytes per
+ * pixel, allocated by sp_cut_create, freed by sp_cut_destroy; NULL is a no-op there) and
+ * enqueues on hip_stream (NULL = the default stream).
+ *   unary     [2][H][W] float: U0 (cost of the background), U1 (cost of the object).
+ *   pairwise  [4][H][W] float: the E, S, SE, SW n-link capacities of mrf_weights.
+ *   scale     > 0: capacities become integers q = rint(c * scale) (FP32, half to even),
+ *             clamped to [0, 2^24], so the flow is exact.
+ *   labels    [H][W] uint8 receives 1 (object: source side) or 0 (background).
+ *   flow_out  [1] int64 (device) or NULL receives the maximum flow = the cut's cost in
+ *             the integer capacities.
+ * The source side is the object: a background pixel pays U0, an object pixel U1, and each
+ * 8-neighbour pair with different labels its capacity.  Among all minimum cuts the one
+ * with the largest object is returned (a pixel is background exactly when it can still
+ * reach the sink in the residual graph of a maximum flow), so the labelling is unique.
+ * Push-relabel with exact global relabelling on the GPU; sp_mincut synchronises the stream
+ * between its rounds.  SP_ESTATE if it has not converged after 65536 push rounds. */
+typedef struct sp_cut sp_cut;
+int sp_cut_create(int32_t H, int32_t W, void* hip_stream, sp_cut** out);
+int sp_cut_destroy(sp_cut* cut);
+int sp_mincut(sp_cut* cut, const float* unary, const float* pairwise, float scale, uint8_t* labels,
+              int64_t* flow_out);
+
 /* The whole per-frame path in one call, with fewer kernel launches than the three
  * calls above: saliency_forward, then prior_update on S_out, then (when unary_out and
  * pairwise_out are both given) mrf_weights on the new prior.  The pairwise capacities
@@ -299,7 +323,7 @@ int sp_batch_backward(sp_batch* b, const float* const* grad_prior, int32_t T, fl
  * 65536 pairs).  sp_profile_read synchronises the stream and returns, per kernel kind
  * 0..SP_NKINDS-1, the summed device time in ms and the number of launches since the
  * last read (arrays of length n >= SP_NKINDS), then clears the record. */
-#define SP_NKINDS 25
+#define SP_NKINDS 28
 int sp_profile_enable(sp_ctx* ctx, int32_t enable);
 int sp_profile_read(sp_ctx* ctx, int32_t n, float* total_ms, int32_t* launches);
 /* The same measurement hook for a batch: while enabled, sp_batch_step launches the

@@ -20,7 +20,6 @@ likelihood and prior terms, and a pair of directed n-links of equal weight betwe
 """
 from __future__ import annotations
 
-from collections import deque
 from typing import Tuple
 
 import numpy as np
@@ -87,29 +86,15 @@ def min_cut(cs: np.ndarray, ct: np.ndarray, pw: np.ndarray) -> Tuple[int, np.nda
     G = csr_matrix((caps.astype(np.int32), (rows, cols)), shape=(N + 2, N + 2))
     G.sum_duplicates()
     res = maximum_flow(G, s, t, method="dinic")
-    F = res.flow.tocsr()
-    # residual capacity of u -> v: cap(u, v) - flow(u, v), flow skew-symmetric
-    C = G.tocoo()
-    resid = {}
-    for a, b, c in zip(C.row, C.col, C.data):
-        resid[(int(a), int(b))] = resid.get((int(a), int(b)), 0) + int(c)
-    Fc = F.tocoo()
-    for a, b, f in zip(Fc.row, Fc.col, Fc.data):
-        resid[(int(a), int(b))] = resid.get((int(a), int(b)), 0) - int(f)
-    # vertices that reach t in the residual graph: search backwards from t
-    into = {}
-    for (a, b), r in resid.items():
-        if r > 0:
-            into.setdefault(b, []).append(a)
+    # residual capacity of u -> v: cap(u, v) - flow(u, v), the flow being skew-symmetric;
+    # the vertices that reach t in the residual graph are those t reaches in its transpose
+    from scipy.sparse.csgraph import breadth_first_order
+    R = (G.astype(np.int64) - res.flow.astype(np.int64)).tocsr()
+    R.data = (R.data > 0).astype(np.int8)
+    R.eliminate_zeros()
+    order = breadth_first_order(R.T.tocsr(), t, directed=True, return_predecessors=False)
     reach = np.zeros(N + 2, dtype=bool)
-    reach[t] = True
-    dq = deque([t])
-    while dq:
-        b = dq.popleft()
-        for a in into.get(b, ()):
-            if not reach[a]:
-                reach[a] = True
-                dq.append(a)
+    reach[order] = True
     labels = (~reach[:N]).reshape(H, W).astype(np.uint8)
     return int(res.flow_value), labels
 

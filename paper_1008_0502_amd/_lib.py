@@ -14,7 +14,7 @@ SP_OK, SP_EINVAL, SP_ESHAPE, SP_ENOMEM, SP_EHIP, SP_ESTATE = 0, -1, -2, -3, -4, 
 ERROR_NAMES = {SP_EINVAL: "SP_EINVAL", SP_ESHAPE: "SP_ESHAPE", SP_ENOMEM: "SP_ENOMEM",
                SP_EHIP: "SP_EHIP", SP_ESTATE: "SP_ESTATE"}
 MAX_LEVELS = 12
-NKINDS = 25
+NKINDS = 28
 
 c_int32 = ctypes.c_int32
 c_float = ctypes.c_float
@@ -80,6 +80,9 @@ SIGNATURES = [
     ("sp_stochastic_saliency", c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_double)]),
     ("mrf_weights", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("sp_colour_likelihood", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("sp_cut_create", c_int32, [c_int32, c_int32, c_void_p, ctypes.POINTER(c_void_p)]),
+    ("sp_cut_destroy", c_int32, [c_void_p]),
+    ("sp_mincut", c_int32, [c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p]),
     ("sp_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                           c_void_p, c_void_p]),
     ("saliency_backward", c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),

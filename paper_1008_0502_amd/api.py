@@ -378,6 +378,48 @@ class Context:
         return {"S": S, "C": C, "pi": P, "unary": U, "pairwise": PW, "beta": B, "mu": MU}
 
 
+class MinCut:
+    """sp_cut: the minimum cut of H x W frames' MRF capacities on the current device."""
+
+    def __init__(self, H: int, W: int, device=None):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("salprior needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self.H, self.W = int(H), int(W)
+        self._handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self.lib.sp_cut_create(self.H, self.W, _stream(), ctypes.byref(self._handle)), "sp_cut_create")
+
+    def close(self) -> None:
+        if self._handle:
+            self.lib.sp_cut_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cut(self, unary: torch.Tensor, pairwise: torch.Tensor, scale: float = 256.0, labels=None, flow_out=None):
+        """sp_mincut: the segmentation (uint8 [H][W], 1 = object) and the flow (int64 [1]).
+        Enqueued on torch's current stream (the call synchronises it between rounds)."""
+        H, W = self.H, self.W
+        _need(unary, "unary", torch.float32, (2, H, W), self.device)
+        _need(pairwise, "pairwise", torch.float32, (4, H, W), self.device)
+        if labels is None:
+            labels = torch.empty((H, W), dtype=torch.uint8, device=self.device)
+        _need(labels, "labels", torch.uint8, (H, W), self.device)
+        if flow_out is None:
+            flow_out = torch.empty((1,), dtype=torch.int64, device=self.device)
+        _need(flow_out, "flow_out", torch.int64, (1,), self.device)
+        check(self.lib.sp_mincut(self._handle, _ptr(unary), _ptr(pairwise), float(scale), _ptr(labels),
+                                 _ptr(flow_out)), "sp_mincut")
+        return labels, flow_out
+
+
 def saliency_noalloc(H: int, W: int, rgb_t: torch.Tensor, rgb_prev: Optional[torch.Tensor],
                      S_out: torch.Tensor, C_out: Optional[torch.Tensor] = None,
                      params: Optional[Params] = None) -> None:

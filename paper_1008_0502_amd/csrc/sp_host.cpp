@@ -1558,7 +1558,7 @@ const char* sp_kernel_name(int32_t k) {
                                          "k_consp", "k_smax", "k_kalman", "k_mrf", "k_bwd_nu", "k_bwd_gs",
                                          "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_csfinal", "k_csg", "k_csmix",
                                          "k_bwd_final", "k_dt", "k_manual", "k_gmm_acc", "k_gmm_fit",
-                                         "k_gmm_psi"};
+                                         "k_gmm_psi", "k_cut_init", "k_cut_relabel", "k_cut_push"};
   return (k >= 0 && k < SP_NKINDS) ? names[k] : "";
 }
 
@@ -2440,6 +2440,107 @@ int sp_batch_destroy(sp_batch* b) {
   g_err.clear();
   batch_free(b);
   return SP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- minimum cut
+struct sp_cut {
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  CutIO io{};   // buffers and the frame size
+  Profiler prof;
+};
+
+extern "C" {
+
+int sp_cut_create(int32_t H, int32_t W, void* hip_stream, sp_cut** out) {
+  g_err.clear();
+  if (!out) return fail(SP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (H < 1 || W < 1 || (long long)H * W > (1LL << 28)) return fail(SP_ESHAPE, "frame %dx%d out of range", H, W);
+  sp_cut* c = new (std::nothrow) sp_cut();
+  if (!c) return fail(SP_ENOMEM, "host allocation failed");
+  c->stream = (hipStream_t)hip_stream;
+  const size_t n = (size_t)H * W;
+  size_t bytes = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    Bump b;
+    b.base = c->arena;
+    c->io.r = b.take<int32_t>(8 * n);
+    c->io.e = b.take<int32_t>(n);
+    c->io.h = b.take<int32_t>(n);
+    c->io.rt = b.take<int32_t>(n);
+    c->io.flow = b.take<unsigned long long>(2);
+    c->io.flags = b.take<int32_t>(2);
+    if (pass == 0) {
+      bytes = b.off + 256;
+      if (hipMalloc(&c->arena, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(SP_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+      }
+    }
+  }
+  c->io.H = H;
+  c->io.W = W;
+  *out = c;
+  return SP_OK;
+}
+
+int sp_cut_destroy(sp_cut* c) {
+  g_err.clear();
+  if (!c) return SP_OK;
+  (void)hipStreamSynchronize(c->stream);
+  c->prof.destroy();
+  if (c->arena) (void)hipFree(c->arena);
+  delete c;
+  return SP_OK;
+}
+
+int sp_mincut(sp_cut* c, const float* unary, const float* pairwise, float scale, uint8_t* labels, int64_t* flow_out) {
+  g_err.clear();
+  if (!c || !unary || !pairwise || !labels) return fail(SP_EINVAL, "cut, unary, pairwise and labels must not be NULL");
+  if (!std::isfinite(scale) || !(scale > 0.f)) return fail(SP_EINVAL, "scale must be finite and > 0");
+  CutIO io = c->io;
+  io.unary = unary;
+  io.pairwise = pairwise;
+  io.labels = labels;
+  io.flow_out = flow_out;
+  io.scale = scale;
+  io.cycles = 64;
+  const long long tiles = (long long)((io.H + SP_CUT_T - 1) / SP_CUT_T) * ((io.W + SP_CUT_T - 1) / SP_CUT_T);
+  const long long max_pass = std::max(64LL, 4 * tiles + (long long)io.H + io.W);
+  auto launch = [&](int phase, int kind) -> int {
+    const hipError_t e = c->prof.timed(c->stream, kind, [&] { return sp_launch_cut(phase, io, c->stream); });
+    if (e != hipSuccess) return fail(SP_EHIP, "minimum cut launch (phase %d): %s", phase, hipGetErrorString(e));
+    return SP_OK;
+  };
+  int rc = launch(0, JOB_CUT_INIT);
+  if (rc) return rc;
+  bool done = false;
+  for (int round = 0; round < 65536 && !done; ++round) {
+    // global relabel: exact distances to the sink, then the pixels with excess that reach it
+    io.reset = 1;
+    if ((rc = launch(1, JOB_CUT_RELABEL))) return rc;
+    io.reset = 0;
+    int32_t fl[2] = {1, 0};
+    long long pass = 0;
+    while (fl[0] != 0) {
+      if (++pass > max_pass) return fail(SP_ESTATE, "minimum cut: relabelling did not settle");
+      if ((rc = launch(1, JOB_CUT_RELABEL))) return rc;
+      HIPCHK(hipMemcpyAsync(fl, io.flags, sizeof fl, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    if (fl[1] == 0) {
+      done = true;
+      break;
+    }
+    for (int k = 0; k < 4; ++k)
+      if ((rc = launch(2, JOB_CUT_PUSH))) return rc;
+  }
+  if (!done) return fail(SP_ESTATE, "minimum cut did not converge in 65536 rounds");
+  return launch(3, JOB_CUT_INIT);
 }
 
 }  // extern "C"

@@ -52,6 +52,9 @@ enum JobKind : int32_t {
   JOB_GMM_ACC,      // colour likelihood: prior-weighted moments of a pixel tile (timing id only)
   JOB_GMM_FIT,      // colour likelihood: mixture parameters from the moments (timing id only)
   JOB_GMM_PSI,      // colour likelihood: -log p(C | A) added to the unary costs (timing id only)
+  JOB_CUT_INIT,     // minimum cut: integer capacities and the saturated t-link flow (timing id only)
+  JOB_CUT_RELABEL,  // minimum cut: distances to the sink in the residual graph (timing id only)
+  JOB_CUT_PUSH,     // minimum cut: push / relabel cycles (timing id only)
   JOB_NKINDS
 };
 
@@ -326,5 +329,30 @@ struct GmmIO {
   float* out;              // [2][M][10] alpha, mu, cov (xx, xy, xz, yy, yz, zz) or null
   int32_t n, ntiles;
   float reg;               // added to the covariance diagonals
+  int32_t pad;
+};
+
+// Minimum cut of the MRF on the pixel grid: integer residual capacities of the 8 n-links
+// of every pixel, in the direction order E, W, S, N, SE, NW, SW, NE (d ^ 1 is the reverse
+// of d), the excess, the height (distance to the sink in the residual graph; SP_CUT_INF:
+// the sink cannot be reached) and the residual capacity to the sink.
+#define SP_CUT_INF (1 << 30)
+#define SP_CUT_T 32        // tile edge of the relabel pass
+#define SP_CUT_CAPMAX (1 << 24)
+struct CutIO {
+  const float* unary;      // [2][n] U0 (cost of the background), U1 (cost of the object)
+  const float* pairwise;   // [4][n] E, S, SE, SW
+  int32_t* r;              // [8][n]
+  int32_t* e;              // [n]
+  int32_t* h;              // [n]
+  int32_t* rt;             // [n]
+  uint8_t* labels;         // [n] 1 = object (source side)
+  unsigned long long* flow;   // [2] flow through the t-links at the start, flow pushed into the sink
+  int32_t* flags;          // [2] heights lowered by a relabel pass, pixels with excess that reach the sink
+  int64_t* flow_out;       // caller's, or null
+  int32_t H, W;
+  float scale;
+  int32_t cycles;          // push / relabel cycles per thread and launch
+  int32_t reset;           // relabel pass: start from the sink's neighbours (1) or from the heights (0)
   int32_t pad;
 };

@@ -47,3 +47,6 @@ hipError_t sp_launch_manual(const uint8_t* labels, float* pnext, float* pout, si
 // Colour likelihood phases: 0 start moments, 1 start fit, 2 E-step moments, 3 M-step fit,
 // 4 psi added to the unary costs (M = components per label, 1..SP_GMM_MAXM).
 hipError_t sp_launch_gmm(int phase, int M, const GmmIO& io, hipStream_t st);
+// Minimum cut phases: 0 counters + capacities, 1 relabel pass (flags cleared first),
+// 2 push / relabel cycles, 3 labels and the flow value.
+hipError_t sp_launch_cut(int phase, const CutIO& io, hipStream_t st);
