@@ -92,7 +92,8 @@ def alg_bytes_per_stream(g, mrf: bool, prior_copy: bool):
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sp_kernels.hip", "sp_internal.h", "sp_kernels.h", "sp_host.cpp"):
+    for f in ("sp_kernels.hip", "sp_gmm.hip", "sp_mincut.hip", "sp_device.h", "sp_internal.h", "sp_kernels.h",
+              "sp_host.cpp"):
         with open(os.path.join(ROOT, "paper_1008_0502_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -347,7 +348,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip", default="",
-                    help="comma list of legs to skip: batched,plain,bwd,bwd_batched,mixed,configs,cpu,cpu_par,profile")
+                    help="comma list of legs to skip: batched,plain,bwd,bwd_batched,mixed,configs,extras,cpu,cpu_par,"
+                         "profile")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="short run for rocprofv3 --pmc: a 256 MiB copy (calibration) then 5 batched steps")
     ap.add_argument("--pmc-summarize", nargs="+", metavar="DB",
@@ -644,6 +646,110 @@ def main():
             del fr
         log("configs: " + ", ".join(f"{k} {v['frames_per_s']}" for k, v in configs.items()))
 
+    # ------------------------------------------------------------ beyond the step: prior variants, colour
+    # likelihood, minimum cut (640x480 clip, seed 2; segmentations from the generator's masks)
+    extras = None
+    if "extras" not in skip:
+        from paper_1008_0502_amd.api import MinCut
+        extras = {}
+        NT = 30
+        px = H * W
+        S = torch.empty((g.Hc, g.Wc), dtype=torch.float32, device=dev)
+        P = torch.empty((H, W), dtype=torch.float32, device=dev)
+        segp = [None] + [masks[t - 1].data_ptr() for t in range(1, NT)]
+        for vname, vp in (("dt_prediction", Params(f_mode=1)), ("stochastic_map", Params(ssm_q=1e-3, ssm_r=1e-1)),
+                          ("dt_prediction_and_stochastic_map", Params(f_mode=1, ssm_q=1e-3, ssm_r=1e-1))):
+            cx = Context(H, W, vp)
+            lib, ch = cx.lib, cx._handle
+            lib.sp_set_stream(ch, stream)
+
+            def vstep(i, lib=lib, ch=ch):
+                t = i % NT
+                if t == 0:
+                    lib.sp_reset(ch)
+                if lib.sp_step(ch, fp[t], fp[t - 1] if t else None, segp[t], S.data_ptr(), None, P.data_ptr(),
+                               None, None, None):
+                    raise RuntimeError(lib.sp_last_error().decode())
+
+            timed(vstep, NT)
+            nv = 300
+            dv = timed(vstep, nv)
+            rec = {"frames_per_s": round(nv / dv, 2), "ms_per_frame": round(dv / nv * 1e3, 5)}
+            if "profile" not in skip:
+                profile_enable(cx, True)
+                timed(vstep, NT)
+                pr = profile_read(cx)
+                profile_enable(cx, False)
+                if "k_dt" in pr:
+                    ms, cnt = pr["k_dt"]
+                    rec["k_dt_avg_us"] = round(ms / cnt * 1e3, 3)
+                    rec["k_dt_alg_GBps"] = round(5.0 * px / (ms / cnt * 1e-3) / 1e9, 2)   # 1 B in, 4 B out per px
+            extras[vname] = rec
+            cx.close()
+        # colour likelihood on the plain prior of frame 10
+        cx = Context(H, W, Params())
+        Pg = cx.run_clip(frames[:11])["pi"][10].contiguous()
+        U0 = torch.zeros((2, H, W), dtype=torch.float32, device=dev)
+        lib, ch = cx.lib, cx._handle
+        lib.sp_set_stream(ch, stream)
+
+        def gstep(_):
+            if lib.sp_colour_likelihood(ch, fp[10], Pg.data_ptr(), U0.data_ptr(), None):
+                raise RuntimeError(lib.sp_last_error().decode())
+
+        timed(gstep, 5)
+        ng = 50
+        dg = timed(gstep, ng)
+        rec = {"calls_per_s": round(ng / dg, 2), "ms_per_call": round(dg / ng * 1e3, 4), "components": 3,
+               "em_iterations": 10}
+        if "profile" not in skip:
+            profile_enable(cx, True)
+            timed(gstep, 10)
+            pr = profile_read(cx)
+            profile_enable(cx, False)
+            per_px = {"k_gmm_acc": 7.0, "k_gmm_psi": 19.0}   # RGB + prior read; RGB read + unary read and written
+            rec["kernels"] = {k: {"avg_us": round(v[0] / v[1] * 1e3, 3), "launches_per_call": v[1] / 10,
+                                  "alg_GBps": (round(per_px[k] * px / (v[0] / v[1] * 1e-3) / 1e9, 2)
+                                               if k in per_px else None)} for k, v in pr.items()}
+        extras["colour_likelihood"] = rec
+        cx.close()
+        # minimum cut: the closed loop (each cut is the next frame's segmentation) and the cut alone
+        cx = Context(H, W, Params())
+        mc = MinCut(H, W)
+        lib, ch = cx.lib, cx._handle
+        lib.sp_set_stream(ch, stream)
+        Uc = torch.empty((2, H, W), dtype=torch.float32, device=dev)
+        PWc = torch.empty((4, H, W), dtype=torch.float32, device=dev)
+        Bc = torch.empty((1,), dtype=torch.float32, device=dev)
+        lab = [torch.zeros((H, W), dtype=torch.uint8, device=dev) for _ in range(2)]
+        flow = torch.empty((1,), dtype=torch.int64, device=dev)
+        cut_s = [0.0]
+
+        def loop_step(i):
+            t = i % NT
+            if t == 0:
+                lib.sp_reset(ch)
+            seg = lab[(t + 1) % 2].data_ptr() if t else None
+            if lib.sp_step(ch, fp[t], fp[t - 1] if t else None, seg, S.data_ptr(), None, P.data_ptr(),
+                           Uc.data_ptr(), PWc.data_ptr(), Bc.data_ptr()):
+                raise RuntimeError(lib.sp_last_error().decode())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mc.cut(Uc, PWc, 256.0, lab[t % 2], flow)
+            torch.cuda.synchronize()
+            cut_s[0] += time.perf_counter() - t0
+
+        timed(loop_step, 5)
+        cut_s[0] = 0.0
+        nl = NT
+        dl = timed(loop_step, nl)
+        extras["min_cut_closed_loop"] = {"frames_per_s": round(nl / dl, 2), "ms_per_frame": round(dl / nl * 1e3, 4),
+                                         "cut_ms_per_frame": round(cut_s[0] / nl * 1e3, 4), "scale": 256.0,
+                                         "object_px_last": int(lab[(nl - 1) % 2].sum().item())}
+        mc.close()
+        cx.close()
+        log("extras: " + json.dumps(extras))
+
     cpu = None
     if "cpu" not in skip:
         log("cpu baseline (oracle)")
@@ -678,6 +784,7 @@ def main():
         "fwd_bwd_batched16_640x480": fbb,
         "configs": configs,
         "batched_mixed64": mixed,
+        "beyond_the_step_640x480": extras,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),
     }
