@@ -23,6 +23,8 @@ paper (Sections 3-6) and from the readings taken where the paper is silent:
                   by EM with every pixel weighted by the prior (Sections 4, 5, 8.1).
 * mincut.py    -- the minimum cut of the MRF (Section 4) on integer capacities: maximum
                   flow and the labelling with the largest object among the minimum cuts.
+* pixel_adjoint.py -- the adjoint of the whole chain through the saliency model to the
+                  frames' pixels (N, centre-surround, Gabor, pyramid, features).
 
 Parity status: every function is pinned by the CPU tests (constant images, Gabor
 closed form, Kalman steady state, brute-force loops, adjoint dot products, gauge
@@ -35,7 +37,7 @@ from .saliency import (OracleParams, Geometry, geometry, colour_max, features, b
                        saliency)
 from .prior import (observation, kalman_gains, prior_clip, mrf_weights, border_mask,
                     run_clip)
-from . import gmm, mincut, variants
+from . import gmm, mincut, pixel_adjoint, variants
 from .adjoint import (mse_mask_loss, prior_chain_forward, prior_chain_backward, blur_adjoint,
                       upsample_adjoint, finite_difference_grad)
 

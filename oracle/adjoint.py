@@ -97,13 +97,14 @@ def prior_chain_forward(C: np.ndarray, w: Sequence[float], Q: float, R: float,
 
 
 def prior_chain_backward(tape: Dict, C: np.ndarray, grad_pi: np.ndarray,
-                         p: OracleParams) -> Tuple[np.ndarray, float, float]:
+                         p: OracleParams, want_gS: bool = False):
     """Reverse sweep of the prior chain.
 
     nu_t = dl/dpi_t + (1 - K_{t+1}) G^T nut_{t+1} (when step t+1 read pi_t), nut_t = nu_t off
     the border ring; dL/dq_t = K_t nut_t; dL/dK_t = sum nut_t (q_t - f_t);
     dL/dS_t = up^T(dL/dq_t on unclamped pixels) / m - [x = x*] sum(g_s S_t) / m^2;
-    dL/dw_k = sum_t sum_x dL/dS_t C_{k,t}; then the scalar sweep of K_t(P_{t-1}, Q, R)."""
+    dL/dw_k = sum_t sum_x dL/dS_t C_{k,t}; then the scalar sweep of K_t(P_{t-1}, Q, R).
+    Returns (dL/dw, dL/dQ, dL/dR), and with want_gS also the list of dL/dS_t."""
     T = len(tape["pi"])
     K, P = tape["K"], tape["P"]
     Q, R = tape["Q"], tape["R"]
@@ -112,6 +113,7 @@ def prior_chain_backward(tape: Dict, C: np.ndarray, grad_pi: np.ndarray,
     Hc, Wc = tape["S"][0].shape
     grad_w = np.zeros(C.shape[1])
     gK = np.zeros(T)
+    gS_all = [np.zeros((Hc, Wc)) for _ in range(T)]
     nut_next = None
     for t in range(T - 1, -1, -1):
         nu = np.array(grad_pi[t], dtype=np.float64)
@@ -130,6 +132,7 @@ def prior_chain_backward(tape: Dict, C: np.ndarray, grad_pi: np.ndarray,
             gS = gs / m
             gS.flat[info["xstar"]] -= float((gs * S).sum()) / (m * m)
             grad_w += np.tensordot(C[t], gS, axes=([1, 2], [0, 1]))
+            gS_all[t] = gS
         nut_next = nut
     # scalar sweep: K_t = a_t / (a_t + R), a_t = P_{t-1} + Q, P_t = R K_t, P_0 = R
     gQ, gR = 0.0, 0.0
@@ -143,6 +146,8 @@ def prior_chain_backward(tape: Dict, C: np.ndarray, grad_pi: np.ndarray,
         gQ += ga
         gP = ga
     gR += gP
+    if want_gS:
+        return grad_w, gQ, gR, gS_all
     return grad_w, gQ, gR
 
 

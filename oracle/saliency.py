@@ -85,19 +85,22 @@ def colour_max(rgb: np.ndarray) -> int:
     return int(rgb.astype(np.int64).sum(axis=2).max())
 
 
-def features(rgb: np.ndarray, rgb_prev: Optional[np.ndarray], smax: int) -> Dict[str, np.ndarray]:
+def features(rgb: np.ndarray, rgb_prev: Optional[np.ndarray], smax: int,
+             chrom: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """Level-0 intensity, red-green and blue-yellow opponents, and frame-difference motion.
 
     I = (r+g+b)/3 with r, g, b in [0, 1].  Colours are normalised by I only where the
     pixel is bright enough: 10*(R8+G8+B8) > max over the frame (an integer test);
     elsewhere r' = g' = b' = 0.  Broadly tuned channels R, G, B, Y are clamped at 0
     and combined into RG = R - G and BY = B - Y.  Motion is |I_t - I_{t-1}| (0 for the
-    first frame)."""
+    first frame).  A given chrom mask replaces the threshold test (an integer decision,
+    constant under small changes of real-valued frames)."""
     f = rgb.astype(np.float64) / 255.0
     r, g, b = f[..., 0], f[..., 1], f[..., 2]
     inten = (r + g + b) / 3.0
-    s8 = rgb.astype(np.int64).sum(axis=2)
-    chrom = 10 * s8 > smax
+    if chrom is None:
+        s8 = rgb.astype(np.int64).sum(axis=2)
+        chrom = 10 * s8 > smax
     safe = np.where(chrom, inten, 1.0)
     rp = np.where(chrom, r / safe, 0.0)
     gp = np.where(chrom, g / safe, 0.0)
@@ -215,16 +218,22 @@ def normalise(X: np.ndarray, flat_tol: float = 1e-5, block: int = 8) -> np.ndarr
 
 
 # -- O8/O9: across-scale sum, conspicuity, saliency (Section 7.2 "weighted addition")
+def chromatic_mask(rgb: np.ndarray) -> np.ndarray:
+    """The pixels bright enough for colour normalisation: 10 (R8+G8+B8) > max (R8+G8+B8)."""
+    s8 = np.asarray(rgb).astype(np.int64).sum(axis=2)
+    return 10 * s8 > int(s8.max())
+
+
 def saliency(rgb: np.ndarray, rgb_prev: Optional[np.ndarray], p: OracleParams,
-             want_intermediate: bool = False):
+             want_intermediate: bool = False, chrom: Optional[np.ndarray] = None):
     """Saliency map S (at level c_max) and the conspicuity maps C_k of one frame.
 
     Returns (S, C) with C of shape [8][H_cmax][W_cmax] in CHANNELS order; with
     want_intermediate also a dict of every stage (for stage-isolated parity)."""
     H, W = rgb.shape[:2]
     geo = geometry(H, W, p)
-    smax = colour_max(rgb)
-    feats = features(rgb, rgb_prev, smax)
+    smax = colour_max(rgb) if chrom is None else -1
+    feats = features(rgb, rgb_prev, smax, chrom)
     base = {k: pyramid(feats[k], geo.top) for k in ("I", "RG", "BY", "M")}
     used = geo.used_levels
     orient = {}
