@@ -92,7 +92,8 @@ def alg_bytes_per_stream(g, mrf: bool, prior_copy: bool):
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sp_kernels.hip", "sp_gmm.hip", "sp_mincut.hip", "sp_device.h", "sp_internal.h", "sp_kernels.h",
+    for f in ("sp_kernels.hip", "sp_gmm.hip", "sp_mincut.hip", "sp_pixadj.hip", "sp_device.h", "sp_internal.h",
+              "sp_kernels.h",
               "sp_host.cpp"):
         with open(os.path.join(ROOT, "paper_1008_0502_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())

@@ -237,6 +237,21 @@ int sp_step(sp_ctx* ctx, const uint8_t* rgb_t, const uint8_t* rgb_prev, const ui
 int saliency_backward(sp_ctx* ctx, const float* grad_prior, int32_t T, float* grad_w, float* grad_q,
                       float* grad_r);
 
+/* Pixel-level adjoint: dL/d frame for every frame of the clip, through the saliency model
+ * (N(.), the across-scale sum, centre-surround, the Gabor maps, the pyramid and the level-0
+ * features of Section 3 / Section 7.2); the motion feature also carries gradient to the
+ * previous frame.  Run saliency_backward for the clip first: this call continues from its
+ * dL/dS of every frame.  The frames' maps are recomputed from the frames.
+ *   frames       [T][H][W][3] uint8 (device): the clip the forward ran, in order.
+ *   grad_frames  [T][H][W][3] float (device): receives dL/d(frame value), per unit of the
+ *                0..255 scale (the frames taken as real numbers).
+ * Non-differentiable points: the chromatic mask and colour maximum are held fixed; the
+ * global minimum and maximum and each 8x8 block maximum of an N(.) input take the gradient
+ * at their first row-major position; a map at or below flat_tol passes none; |.| has
+ * sign(0) = 0; max(0, .) passes nothing at 0; min(r', g') passes to r' on ties.
+ * SP_ESTATE unless saliency_backward of these T steps ran last on this tape. */
+int saliency_backward_frames(sp_ctx* ctx, const uint8_t* frames, int32_t T, float* grad_frames);
+
 /* Fitting loss helper: loss = mean over [T][H][W] of (prior - mask)^2 and its gradient.
  *   prior [T][H][W] float, mask [T][H][W] uint8 {0,1}, loss [1] float,
  *   grad_prior [T][H][W] float or NULL. */
@@ -323,7 +338,7 @@ int sp_batch_backward(sp_batch* b, const float* const* grad_prior, int32_t T, fl
  * 65536 pairs).  sp_profile_read synchronises the stream and returns, per kernel kind
  * 0..SP_NKINDS-1, the summed device time in ms and the number of launches since the
  * last read (arrays of length n >= SP_NKINDS), then clears the record. */
-#define SP_NKINDS 28
+#define SP_NKINDS 29
 int sp_profile_enable(sp_ctx* ctx, int32_t enable);
 int sp_profile_read(sp_ctx* ctx, int32_t n, float* total_ms, int32_t* launches);
 /* The same measurement hook for a batch: while enabled, sp_batch_step launches the

@@ -97,7 +97,10 @@ def features(rgb: np.ndarray, rgb_prev: Optional[np.ndarray], smax: int,
     constant under small changes of real-valued frames)."""
     f = rgb.astype(np.float64) / 255.0
     r, g, b = f[..., 0], f[..., 1], f[..., 2]
-    inten = (r + g + b) / 3.0
+    # I = (r + g + b) / 3 evaluated as (R8 + G8 + B8) / 765: one rounding of the byte sum,
+    # so pixels with equal sums get bitwise equal intensities (and equal frames zero motion)
+    s8f = rgb.astype(np.float64).sum(axis=2)
+    inten = s8f / 765.0
     if chrom is None:
         s8 = rgb.astype(np.int64).sum(axis=2)
         chrom = 10 * s8 > smax
@@ -112,8 +115,7 @@ def features(rgb: np.ndarray, rgb_prev: Optional[np.ndarray], smax: int,
     if rgb_prev is None:
         M = np.zeros_like(inten)
     else:
-        fp = rgb_prev.astype(np.float64) / 255.0
-        M = np.abs(inten - (fp[..., 0] + fp[..., 1] + fp[..., 2]) / 3.0)
+        M = np.abs(s8f - rgb_prev.astype(np.float64).sum(axis=2)) / 765.0
     return {"I": inten, "RG": R - G, "BY": B - Y, "M": M}
 
 

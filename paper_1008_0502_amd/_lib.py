@@ -14,7 +14,7 @@ SP_OK, SP_EINVAL, SP_ESHAPE, SP_ENOMEM, SP_EHIP, SP_ESTATE = 0, -1, -2, -3, -4, 
 ERROR_NAMES = {SP_EINVAL: "SP_EINVAL", SP_ESHAPE: "SP_ESHAPE", SP_ENOMEM: "SP_ENOMEM",
                SP_EHIP: "SP_EHIP", SP_ESTATE: "SP_ESTATE"}
 MAX_LEVELS = 12
-NKINDS = 28
+NKINDS = 29
 
 c_int32 = ctypes.c_int32
 c_float = ctypes.c_float
@@ -86,6 +86,7 @@ SIGNATURES = [
     ("sp_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                           c_void_p, c_void_p]),
     ("saliency_backward", c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    ("saliency_backward_frames", c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
     ("sp_mse_mask_loss", c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     ("sp_state_size", c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
     ("sp_get_state", c_int32, [c_void_p, c_void_p, c_size_t]),

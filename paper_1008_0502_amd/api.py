@@ -318,6 +318,17 @@ class Context:
               "saliency_backward")
         return gw, gq, gr
 
+    def saliency_backward_frames(self, frames: torch.Tensor) -> torch.Tensor:
+        """dL/d frames [T][H][W][3] float32 after saliency_backward of the same clip."""
+        g = self.geometry
+        T = frames.shape[0]
+        _need(frames, "frames", torch.uint8, (T, g.H, g.W, 3), self.device)
+        out = torch.empty((T, g.H, g.W, 3), dtype=torch.float32, device=self.device)
+        self._bind_stream()
+        check(self.lib.saliency_backward_frames(self._handle, _ptr(frames), int(T), _ptr(out)),
+              "saliency_backward_frames")
+        return out
+
     def mse_mask_loss(self, prior: torch.Tensor, mask: torch.Tensor, want_grad: bool = True):
         g = self.geometry
         T = prior.shape[0]

@@ -20,7 +20,7 @@ ARCH = os.environ.get("SALPRIOR_ARCH", "gfx950")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function"]
-SOURCES = ["sp_kernels.hip", "sp_gmm.hip", "sp_mincut.hip", "sp_host.cpp"]
+SOURCES = ["sp_kernels.hip", "sp_gmm.hip", "sp_mincut.hip", "sp_pixadj.hip", "sp_host.cpp"]
 
 
 def _hipcc() -> str:

@@ -594,6 +594,29 @@ struct sp_ctx {
   int ssm_cur = 0;
   int64_t ssm_t = 0;              // maps filtered since the reset
   double ssm_P = 0.0;             // variance of the stochastic map
+  // pixel-level adjoint (contexts with a tape): workspace planes and static launch tables
+  struct PixAdj {
+    float* gS = nullptr;                 // [Hc][Wc] dL/dS of the frame
+    float* gfbar = nullptr;              // [8][Hc][Wc]
+    float* gN[SP_MAXL] = {};             // [8][H_l][W_l] dL/dN(F) at centre levels below c_max
+    float* F[SP_MAXP] = {};              // [8][H_c][W_c] per pair: F, then dL/dF, then sign(D) dL/dF
+    float* gX[SP_MAXL] = {};             // [8][H_l][W_l] dL/d(channel maps) per level 0..top
+    size_t gX_floats = 0;                // floats of gX, followed by amax
+    uint32_t* amax = nullptr;            // [n_pairs][8] scale of each centre-surround pair (float bits)
+    float* taps = nullptr;               // [4][2R+1][2R+1] Gabor taps
+    PaMap* maps_fbar = nullptr;          // [8]
+    PaMap* maps_F = nullptr;             // [8 n_pairs]
+    PaPlane* tab_gn[SP_MAXL] = {};       // [8] per centre level below c_max
+    PaPlane* tab_cs[SP_MAXP] = {};       // [8] per pair: centre-surround map and adjoint
+    PaPlane* tab_up[SP_MAXP] = {};       // [8] per pair: up-sample transpose
+    PaPlane* tab_gab[SP_MAXL] = {};      // [1] per used level
+    PaPlane* tab_pyr[SP_MAXL] = {};      // [4] per level 1..top: to the level below
+    float** gc[SP_MAXP] = {};            // [8] per pair: dL/dX(c) planes
+    int64_t gen = -1;                    // tape generation of the last saliency_backward
+    int T = 0;                           // and its clip length
+  } pa;
+  int32_t* pa_bpos = nullptr;     // block-maximum positions of every N(.) adjoint map
+  float* pa_sc = nullptr;         // [maps][8] scalars of every N(.) adjoint map
   // colour likelihood
   GmmState* gmm_state = nullptr;
   double* gmm_part = nullptr;     // [2 M 10][gmm_tiles] FP64 moments per tile
@@ -672,6 +695,167 @@ void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& 
   v.clear();
   add_tiles(v, s, 0, g.Hl[g.c_max], g.Wl[g.c_max]);
   push(which == PROG_ALL ? JOB_CONSP : JOB_CONSP_DOT, v);
+}
+
+// 8x8 blocks of every map of the N(.) adjoint: the 8 across-scale sums and every pair's 8
+// centre-surround maps.
+size_t pixadj_nblocks(const Geo& g) {
+  auto nblk = [&](int l) { return (size_t)((g.Hl[l] + 7) / 8) * ((g.Wl[l] + 7) / 8); };
+  size_t n = SP_NCH * nblk(g.c_max);
+  for (int p = 0; p < g.n_pairs; ++p) n += SP_NCH * nblk(g.pc[p]);
+  return n;
+}
+
+// Workspace of the pixel-level adjoint, taken from the context's arena (both layout passes).
+void pixadj_layout(sp_ctx* c, Bump& b) {
+  const Geo& g = c->g;
+  auto& A = c->pa;
+  auto n_l = [&](int l) { return (size_t)g.Hl[l] * g.Wl[l]; };
+  const int Hc = g.Hl[g.c_max], Wc = g.Wl[g.c_max];
+  A.gS = b.take<float>((size_t)Hc * Wc);
+  A.gfbar = b.take<float>((size_t)SP_NCH * Hc * Wc);
+  for (int l = g.c_min; l < g.c_max; ++l) A.gN[l] = b.take<float>(SP_NCH * n_l(l));
+  for (int p = 0; p < g.n_pairs; ++p) A.F[p] = b.take<float>(SP_NCH * n_l(g.pc[p]));
+  A.gX_floats = 0;
+  for (int l = 0; l <= g.top; ++l) A.gX_floats += SP_NCH * n_l(l);
+  float* gx = b.take<float>(A.gX_floats + (size_t)SP_NCH * g.n_pairs);
+  for (int l = 0; l <= g.top; ++l) {
+    A.gX[l] = gx;
+    if (gx) gx += SP_NCH * n_l(l);
+  }
+  A.amax = reinterpret_cast<uint32_t*>(gx);
+  const int K = 2 * SP_PA_R + 1;
+  A.taps = b.take<float>((size_t)4 * K * K);
+  A.maps_fbar = b.take<PaMap>(SP_NCH);
+  A.maps_F = b.take<PaMap>((size_t)SP_NCH * g.n_pairs);
+  for (int l = g.c_min; l < g.c_max; ++l) A.tab_gn[l] = b.take<PaPlane>(SP_NCH);
+  for (int p = 0; p < g.n_pairs; ++p) {
+    A.tab_cs[p] = b.take<PaPlane>(SP_NCH);
+    A.tab_up[p] = b.take<PaPlane>(SP_NCH);
+    A.gc[p] = b.take<float*>(SP_NCH);
+  }
+  for (int l = 1; l <= g.top; ++l) {
+    if (g.used & (1u << l)) A.tab_gab[l] = b.take<PaPlane>(1);
+    A.tab_pyr[l] = b.take<PaPlane>(4);
+  }
+  c->pa_bpos = b.take<int32_t>(pixadj_nblocks(g) + 64);
+  c->pa_sc = b.take<float>((size_t)SP_PA_SC * SP_NCH * (1 + g.n_pairs));
+}
+
+// Static launch tables of the pixel-level adjoint (pointers into the forward's own maps and
+// the workspace; every frame reuses them).
+hipError_t pixadj_upload(sp_ctx* c) {
+  const Geo& g = c->g;
+  const StreamDesc& sd = c->h_sd;
+  auto& A = c->pa;
+  auto n_l = [&](int l) { return (size_t)g.Hl[l] * g.Wl[l]; };
+  const int cm = g.c_max;
+  // channel k of level l in the forward's maps (I, RG, BY, O0..O135, M)
+  auto chan = [&](int k, int l) -> const float* {
+    if (k == 0) return sd.base[l];
+    if (k == 1 || k == 2) return sd.base[l] + (size_t)k * n_l(l);
+    if (k == 7) return sd.base[l] + (size_t)BASE_M * n_l(l);
+    return sd.gab[l] + (size_t)(k - 3) * n_l(l);
+  };
+  std::vector<char> blob;
+  std::vector<std::pair<void*, std::vector<char>>> ups;
+  auto put = [&](void* dst, const void* src, size_t bytes) {
+    ups.emplace_back(dst, std::vector<char>((const char*)src, (const char*)src + bytes));
+  };
+  // Gabor taps, the 2-D kernel of each orientation in FP64, stored FP32
+  {
+    const int R = c->p.gabor_radius, K = 2 * SP_PA_R + 1;
+    std::vector<float> taps((size_t)4 * K * K, 0.f);
+    const double s2 = 2.0 * (double)c->p.gabor_sigma * (double)c->p.gabor_sigma;
+    for (int th = 0; th < 4; ++th) {
+      const double a = th * M_PI / 4.0;
+      double se = 0, sec = 0;
+      for (int v = -R; v <= R; ++v)
+        for (int u = -R; u <= R; ++u) {
+          const double e = std::exp(-(double)(u * u + v * v) / s2);
+          se += e;
+          sec += e * std::cos(2.0 * M_PI * (u * std::cos(a) + v * std::sin(a)) / (double)c->p.gabor_lambda);
+        }
+      const double c0 = sec / se;
+      for (int v = -R; v <= R; ++v)
+        for (int u = -R; u <= R; ++u) {
+          const double e = std::exp(-(double)(u * u + v * v) / s2);
+          const double h = e * std::cos(2.0 * M_PI * (u * std::cos(a) + v * std::sin(a)) / (double)c->p.gabor_lambda) - c0 * e;
+          taps[((size_t)th * K + (v + R)) * K + (u + R)] = (float)h;
+        }
+    }
+    put(A.taps, taps.data(), taps.size() * sizeof(float));
+  }
+  // N(.) adjoint maps: the 8 across-scale sums, then every pair's 8 centre-surround maps
+  int32_t* bpos = c->pa_bpos;
+  float* sc = c->pa_sc;
+  auto nblk = [&](int l) { return ((g.Hl[l] + 7) / 8) * ((g.Wl[l] + 7) / 8); };
+  {
+    std::vector<PaMap> m(SP_NCH);
+    const size_t pl = n_l(cm);
+    for (int k = 0; k < SP_NCH; ++k) {
+      m[k] = PaMap{sd.fbar + k * pl, A.gS, A.gfbar + k * pl, bpos, sc, g.Hl[cm], g.Wl[cm], c->p.weights[k], 0};
+      bpos += nblk(cm);
+      sc += SP_PA_SC;
+    }
+    put(A.maps_fbar, m.data(), m.size() * sizeof(PaMap));
+  }
+  {
+    std::vector<PaMap> m((size_t)SP_NCH * g.n_pairs);
+    for (int p = 0; p < g.n_pairs; ++p) {
+      const int cl = g.pc[p];
+      const size_t pl = n_l(cl);
+      for (int k = 0; k < SP_NCH; ++k) {
+        const float* gn = cl == cm ? A.gfbar + k * pl : A.gN[cl] + k * pl;
+        m[(size_t)p * SP_NCH + k] = PaMap{A.F[p] + k * pl, gn, A.F[p] + k * pl, bpos, sc, g.Hl[cl], g.Wl[cl], 1.f, 0};
+        bpos += nblk(cl);
+        sc += SP_PA_SC;
+      }
+    }
+    put(A.maps_F, m.data(), m.size() * sizeof(PaMap));
+  }
+  // dL/dN at centre levels below c_max: pyramid-step transposes from c_max down
+  for (int l = cm - 1; l >= g.c_min; --l) {
+    std::vector<PaPlane> t(SP_NCH);
+    for (int k = 0; k < SP_NCH; ++k) {
+      const float* src = (l + 1 == cm) ? A.gfbar + k * n_l(cm) : A.gN[l + 1] + k * n_l(l + 1);
+      t[k] = PaPlane{src, nullptr, A.gN[l] + k * n_l(l), nullptr, g.Hl[l], g.Wl[l], g.Hl[l + 1], g.Wl[l + 1], 0, 0};
+    }
+    put(A.tab_gn[l], t.data(), t.size() * sizeof(PaPlane));
+  }
+  // centre-surround maps, their adjoint and the up-sample transpose, per pair
+  for (int p = 0; p < g.n_pairs; ++p) {
+    const int cl = g.pc[p], sl = g.ps[p];
+    std::vector<PaPlane> cs(SP_NCH), up(SP_NCH);
+    std::vector<float*> gc(SP_NCH);
+    for (int k = 0; k < SP_NCH; ++k) {
+      float* Fk = A.F[p] + k * n_l(cl);
+      cs[k] = PaPlane{chan(k, cl), chan(k, sl), Fk, A.amax + (size_t)p * SP_NCH + k, g.Hl[cl], g.Wl[cl], g.Hl[sl], g.Wl[sl], sl - cl, 0};
+      up[k] = PaPlane{Fk, nullptr, A.gX[sl] + k * n_l(sl), nullptr, g.Hl[cl], g.Wl[cl], g.Hl[sl], g.Wl[sl], sl - cl, 0};
+      gc[k] = A.gX[cl] + k * n_l(cl);
+    }
+    put(A.tab_cs[p], cs.data(), cs.size() * sizeof(PaPlane));
+    put(A.tab_up[p], up.data(), up.size() * sizeof(PaPlane));
+    put(A.gc[p], gc.data(), gc.size() * sizeof(float*));
+  }
+  // Gabor transposes at the used levels; pyramid-step transposes of the base channels
+  for (int l = 1; l <= g.top; ++l) {
+    if (A.tab_gab[l]) {
+      PaPlane t{A.gX[l] + 3 * n_l(l), nullptr, A.gX[l], nullptr, g.Hl[l], g.Wl[l], 0, 0, c->p.gabor_radius, 0};
+      put(A.tab_gab[l], &t, sizeof t);
+    }
+    const int ks[4] = {0, 1, 2, 7};
+    std::vector<PaPlane> t(4);
+    for (int j = 0; j < 4; ++j)
+      t[j] = PaPlane{A.gX[l] + ks[j] * n_l(l), nullptr, A.gX[l - 1] + ks[j] * n_l(l - 1), nullptr, g.Hl[l - 1],
+                     g.Wl[l - 1], g.Hl[l], g.Wl[l], 0, 0};
+    put(A.tab_pyr[l], t.data(), t.size() * sizeof(PaPlane));
+  }
+  for (auto& u : ups) {
+    const hipError_t e = hipMemcpyAsync(u.first, u.second.data(), u.second.size(), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipStreamSynchronize(c->stream);
 }
 
 // Phases of one stream's forward saliency map (stream index 0), appended to `js` with
@@ -809,6 +993,7 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
       c->d_rsd = b.take<StreamDesc>(c->CH);
       c->d_rio = b.take<StepIO>(c->cap);
       for (int i = 0; i < c->CH; ++i) layout_stream(rsd[i], g, *p, b, g.c_min + 1, false);
+      pixadj_layout(c, b);
     }
     if (pass == 0) {
       c->arena_bytes = b.off + 256;
@@ -836,6 +1021,7 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
         if (e == hipSuccess)
           e = hipMemcpyAsync(c->d_rio, rio.data(), sizeof(StepIO) * c->cap, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = pixadj_upload(c);
       }
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) {
@@ -1467,6 +1653,69 @@ int saliency_backward(sp_ctx* c, const float* grad_prior, int32_t T, float* grad
     return sp_launch_bwd_final(nullptr, &fin, 1, T, c->K_tape, c->P_tape, c->p.q, c->p.r, c->p.flat_tol, c->stream);
   });
   if (e != hipSuccess) return fail(SP_EHIP, "adjoint reduction launch: %s", hipGetErrorString(e));
+  c->pa.gen = c->tape_gen;
+  c->pa.T = T;
+  return SP_OK;
+}
+
+int saliency_backward_frames(sp_ctx* c, const uint8_t* frames, int32_t T, float* grad_frames) {
+  g_err.clear();
+  if (!c || !frames || !grad_frames) return fail(SP_EINVAL, "NULL argument");
+  if (c->cap <= 0) return fail(SP_ESTATE, "context was created without a tape (record_tape = 0)");
+  if (c->pa.gen != c->tape_gen || c->pa.T != T || T != c->t)
+    return fail(SP_ESTATE, "saliency_backward of this %d-step clip must run first", T);
+  const Geo& g = c->g;
+  auto& A = c->pa;
+  const size_t HW = (size_t)g.H * g.W, HW3 = 3 * HW;
+  const int cm = g.c_max;
+  const size_t plc = (size_t)g.Hl[cm] * g.Wl[cm];
+  auto n_l = [&](int l) { return (int)((size_t)g.Hl[l] * g.Wl[l]); };
+  auto ok = [&](hipError_t e, const char* what) -> int {
+    if (e != hipSuccess) return fail(SP_EHIP, "pixel adjoint (%s): %s", what, hipGetErrorString(e));
+    return SP_OK;
+  };
+  int maxF = 0;
+  for (int p = 0; p < g.n_pairs; ++p) maxF = std::max(maxF, n_l(g.pc[p]));
+  for (int t = 0; t < T; ++t) {
+    // the frame's forward maps, recomputed into the context's buffers
+    StepIO io;
+    std::memset(&io, 0, sizeof io);
+    io.rgb = frames + (size_t)t * HW3;
+    io.rgb_prev = t ? frames + (size_t)(t - 1) * HW3 : nullptr;
+    io.S_out = c->S_scratch;
+    for (const Phase& ph0 : c->fwd) {
+      Phase ph = ph0;
+      if (ph.kind == JOB_RGB) ph.flag = 0;
+      int rc = run_phase(c, ph, c->d_sd, nullptr, &io, ph.n);
+      if (rc) return rc;
+    }
+    int rc = SP_OK;
+    const hipError_t e = timed(c, JOB_PIX_ADJ, [&]() -> hipError_t {
+      hipError_t r = sp_pa_gs(c->gs_all + (size_t)t * plc, c->S_tape + (size_t)t * plc, c->ms_tape + 2 * (size_t)t,
+                              (int)plc, c->p.flat_tol, A.gS, c->stream);
+      if (r == hipSuccess) r = sp_pa_nadjoint(A.maps_fbar, SP_NCH, (int)plc, c->p.flat_tol, c->stream);
+      for (int l = cm - 1; l >= g.c_min && r == hipSuccess; --l)
+        r = sp_pa_plane(0, A.tab_gn[l], SP_NCH, n_l(l), 0, nullptr, nullptr, c->stream);
+      // dL/dX and the pairs' scales start at zero
+      if (r == hipSuccess) r = sp_pa_zero(A.gX[0], A.gX_floats + (size_t)SP_NCH * g.n_pairs, c->stream);
+      for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
+        r = sp_pa_plane(1, A.tab_cs[p], SP_NCH, n_l(g.pc[p]), 0, nullptr, nullptr, c->stream);
+      if (r == hipSuccess) r = sp_pa_nadjoint(A.maps_F, SP_NCH * g.n_pairs, maxF, c->p.flat_tol, c->stream);
+      for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
+        r = sp_pa_plane(2, A.tab_cs[p], SP_NCH, n_l(g.pc[p]), 0, A.gc[p], nullptr, c->stream);
+      for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
+        r = sp_pa_plane(3, A.tab_up[p], SP_NCH, n_l(g.ps[p]), 0, nullptr, nullptr, c->stream);
+      for (int l = g.top; l >= 1 && r == hipSuccess; --l) {
+        if (A.tab_gab[l]) r = sp_pa_plane(4, A.tab_gab[l], 1, n_l(l), 0, nullptr, A.taps, c->stream);
+        if (r == hipSuccess) r = sp_pa_plane(0, A.tab_pyr[l], 4, n_l(l - 1), 1, nullptr, nullptr, c->stream);
+      }
+      if (r == hipSuccess)
+        r = sp_pa_feat(io.rgb, io.rgb_prev, c->h_sd.rgb_max_part, c->h_sd.n_rgb, A.gX[0], (int)HW,
+                       grad_frames + (size_t)t * HW3, t ? grad_frames + (size_t)(t - 1) * HW3 : nullptr, c->stream);
+      return r;
+    });
+    if ((rc = ok(e, "launch"))) return rc;
+  }
   return SP_OK;
 }
 
@@ -1558,7 +1807,8 @@ const char* sp_kernel_name(int32_t k) {
                                          "k_consp", "k_smax", "k_kalman", "k_mrf", "k_bwd_nu", "k_bwd_gs",
                                          "k_consp_dot", "k_loss", "k_pyr_tail", "k_pyr_tail", "k_csfinal", "k_csg", "k_csmix",
                                          "k_bwd_final", "k_dt", "k_manual", "k_gmm_acc", "k_gmm_fit",
-                                         "k_gmm_psi", "k_cut_init", "k_cut_relabel", "k_cut_push"};
+                                         "k_gmm_psi", "k_cut_init", "k_cut_relabel", "k_cut_push",
+                                         "k_pixel_adjoint"};
   return (k >= 0 && k < SP_NKINDS) ? names[k] : "";
 }
 

@@ -55,6 +55,7 @@ enum JobKind : int32_t {
   JOB_CUT_INIT,     // minimum cut: integer capacities and the saturated t-link flow (timing id only)
   JOB_CUT_RELABEL,  // minimum cut: distances to the sink in the residual graph (timing id only)
   JOB_CUT_PUSH,     // minimum cut: push / relabel cycles (timing id only)
+  JOB_PIX_ADJ,      // pixel-level adjoint of one frame (timing id only)
   JOB_NKINDS
 };
 
@@ -356,3 +357,27 @@ struct CutIO {
   int32_t reset;           // relabel pass: start from the sink's neighbours (1) or from the heights (0)
   int32_t pad;
 };
+
+// Pixel-level adjoint (dL/d frame): one map of the N(.) adjoint.
+struct PaMap {
+  const float* X;          // [h][w] the map N was applied to
+  const float* g;          // [h][w] dL/dN before the factor gs
+  float* out;              // [h][w] dL/dX (may be the storage of X: the apply pass does not read X)
+  int32_t* bpos;           // [nb] first position of each 8x8 block maximum
+  float* sc;               // [8] A/range, gb/range, g(min), g(max), argmin, argmax (int bits), flat, nb
+  int32_t h, w;
+  float gs;
+  int32_t pad;
+};
+// A plane pair of a gather pass (pyramid-step transpose, centre-surround, up-sample transpose).
+struct PaPlane {
+  const float* a;          // input plane(s)
+  const float* b;
+  float* out;
+  uint32_t* amax;          // centre-surround: the pair's scale max |X(c)|, |X(s)| (float bits)
+  int32_t ha, wa, hb, wb;  // sizes of a and b (b: the surround level of a centre-surround pair)
+  int32_t d;               // level offset of the pair
+  int32_t pad;
+};
+#define SP_PA_R 8          // largest Gabor radius of the adjoint's 2-D taps
+#define SP_PA_SC 8         // floats of the statistics of one N(.) adjoint map

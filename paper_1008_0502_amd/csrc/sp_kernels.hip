@@ -513,7 +513,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
     fI[u] = I;
     fRG[u] = rg;
     fBY[u] = by;
-    fM[u] = prev ? fabsf(I - (float)pv[u] * (1.f / 765.f)) : 0.f;
+    // |I_t - I_{t-1}| from the byte sums: exactly zero where they agree (an FMA-contracted
+    // difference of the two rounded intensities would leave the rounding error of I)
+    fM[u] = prev ? (float)abs(S8 - (int)pv[u]) * (1.f / 765.f) : 0.f;
   }
   float beta = 0.f;
   const int H1 = sd.Hl[1], W1 = sd.Wl[1];

@@ -1,13 +1,14 @@
 """CPU pins of the pixel-level adjoint oracle (oracle/pixel_adjoint.py): dot-product tests
 of the pyramid-step and Gabor transposes, central differences of N(.), of the features, of
 the whole saliency map and of the clip loss in random directions (real-valued frames, so
-no kink lies within the step), and planted mistakes that must turn a pin red."""
+no kink lies within the step), central differences on a motion plateau (the sign band of
+|D|), and planted mistakes that must turn a pin red."""
 import numpy as np
 import pytest
 
 import oracle as O
 from oracle import pixel_adjoint as PA
-from oracle.saliency import CHANNELS, chromatic_mask
+from oracle.saliency import CHANNELS, ORIENTATIONS_DEG, chromatic_mask
 
 
 def _dot(a, b):
@@ -48,6 +49,25 @@ def test_normalise_vjp_matches_central_differences(H, W, seed):
         assert _fd(f, X, v, 1e-7) == pytest.approx(_dot(g, v), rel=1e-6, abs=1e-9)
 
 
+def _band_stats(rgb, prev, p, chrom):
+    """Over every centre-surround pair and channel: the smallest |D| / scale above the sign
+    band, and the number of positions at or below it whose D is not exactly zero."""
+    _, _, inter = O.saliency(rgb, prev, p, want_intermediate=True, chrom=chrom)
+    geo, base, orient = inter["geometry"], inter["base"], inter["orient"]
+    maps = dict(base, **{n: orient[th] for n, th in zip(("O0", "O45", "O90", "O135"), ORIENTATIONS_DEG)})
+    above, tiny = np.inf, 0
+    for name in CHANNELS:
+        for c, s in geo.pairs:
+            D = maps[name][c] - O.upsample(maps[name][s], s - c, *geo.sizes[c])
+            scale = max(np.abs(maps[name][c]).max(), np.abs(maps[name][s]).max())
+            if scale == 0:
+                continue
+            r = np.abs(D) / scale
+            above = min(above, float(r[r > PA.SIGN_BAND].min(initial=np.inf)))
+            tiny += int(np.sum((r <= PA.SIGN_BAND) & (D != 0)))
+    return above, tiny
+
+
 def _real_frames(rng, T, H, W):
     base = rng.random((H, W, 3)) * 200 + 20
     return np.stack([np.clip(base + rng.normal(size=(H, W, 3)) * (8 + 4 * t), 0.5, 254.5) for t in range(T)])
@@ -69,7 +89,7 @@ def test_feature_vjp_matches_central_differences():
         assert _fd(lambda z: f(fr[1], z), fr[0], v, 1e-5) == pytest.approx(_dot(gp, v), rel=1e-7, abs=1e-12)
 
 
-@pytest.mark.parametrize("H,W,seed,centers,deltas", [(40, 48, 0, (1, 2), (2, 3)), (36, 33, 1, (2,), (2, 3))])
+@pytest.mark.parametrize("H,W,seed,centers,deltas", [(40, 48, 3, (1, 2), (2, 3)), (36, 33, 1, (2,), (2, 3))])
 def test_saliency_vjp_matches_central_differences(H, W, seed, centers, deltas):
     rng = np.random.default_rng(seed)
     p = O.OracleParams(centers=centers, deltas=deltas, weights=tuple(rng.random(8) + 0.5))
@@ -77,6 +97,9 @@ def test_saliency_vjp_matches_central_differences(H, W, seed, centers, deltas):
     chrom = chromatic_mask(np.rint(fr[1]).astype(np.uint8))
     S0, _ = O.saliency(fr[1], fr[0], p, chrom=chrom)
     gS = rng.normal(size=S0.shape)
+    # no centre-surround difference of these frames lies inside the sign band, so the
+    # convention there does not enter and the exact derivative is the one to match
+    assert _band_stats(fr[1], fr[0], p, chrom)[1] == 0
     g, gp = PA.saliency_vjp(fr[1], fr[0], gS, p, chrom)
     for _ in range(2):
         v = rng.normal(size=fr[1].shape)
@@ -93,7 +116,8 @@ def test_clip_gradient_matches_central_differences():
     masks = np.zeros((T, H, W), np.uint8)
     masks[:, 12:26, 15:33] = 1
     p = O.OracleParams(q=2e-3, r=5e-2)
-    loss, grad = PA.frame_gradients(fr, masks, p)
+    # a few differences of these frames fall inside the sign band: the exact derivative
+    loss, grad = PA.frame_gradients(fr, masks, p, sign_band=0.0)
     chroms = [chromatic_mask(fr[t]) for t in range(T)]
     for _ in range(2):
         v = rng.normal(size=fr.shape)
@@ -103,6 +127,69 @@ def test_clip_gradient_matches_central_differences():
         assert fd == pytest.approx(_dot(grad, v), rel=1e-7)
     # every frame, including the last one, gets a gradient; the first also through motion
     assert all(np.abs(grad[t]).max() > 0 for t in range(T))
+
+
+def _motion_pyramid_int(s_t, s_prev, top):
+    """The motion map's pyramid in exact integers: level l holds 765 * 256^l * M_l (the
+    binomial taps 1 4 6 4 1 in each direction, clamp-to-edge, even rows and columns)."""
+    k = np.array([1, 4, 6, 4, 1], dtype=np.int64)
+    Z = [np.abs(s_t.astype(np.int64) - s_prev.astype(np.int64))]
+    for _ in range(top):
+        X = Z[-1]
+        H, W = X.shape
+        ys, xs = np.arange(H), np.arange(W)
+        B = np.zeros_like(X)
+        for i in range(5):
+            for j in range(5):
+                B += k[i] * k[j] * X[np.ix_(np.clip(ys + i - 2, 0, H - 1), np.clip(xs + j - 2, 0, W - 1))]
+        Z.append(B[::2, ::2])
+    return Z
+
+
+def _up_int(Z, d, Ht, Wt):
+    """4^d times the sample-aligned bilinear up-sample of Z (exact: the weights are k / 2^d)."""
+    Hs, Ws = Z.shape
+    n = 1 << d
+
+    def taps(m, size):
+        i = np.arange(m)
+        i0 = np.minimum(i >> d, size - 1)
+        a = np.where((i >> d) >= size - 1, 0, i & (n - 1))
+        return i0, np.minimum(i0 + 1, size - 1), a
+    y0, y1, ay = taps(Ht, Hs)
+    x0, x1, ax = taps(Wt, Ws)
+    ay, ax = ay[:, None], ax[None, :]
+    top = (n - ax) * Z[np.ix_(y0, x0)] + ax * Z[np.ix_(y0, x1)]
+    bot = (n - ax) * Z[np.ix_(y1, x0)] + ax * Z[np.ix_(y1, x1)]
+    return (n - ay) * top + ay * bot
+
+
+def test_sign_band_against_exact_motion_differences():
+    """A constant-colour object moving over a constant background makes the motion map a
+    plateau: D = M(c) - up M(s) vanishes there in exact arithmetic, while the FP64 maps leave
+    rounding residue of either sign.  The motion pyramid is exact in integers, so the sign of
+    every D can be taken exactly: the band must cover every exact zero, and outside it the
+    sign of the FP64 D must be the exact one."""
+    from paper_1008_0502_amd import synth
+    frames, _ = synth.Clip(synth.three_ellipse_spec(H=97, W=131, T=3, seed=2)).stack()
+    p = O.OracleParams()
+    _, _, inter = O.saliency(frames[2], frames[1], p, want_intermediate=True, chrom=chromatic_mask(frames[2]))
+    geo, M = inter["geometry"], inter["base"]["M"]
+    Z = _motion_pyramid_int(frames[2].astype(np.int64).sum(axis=2), frames[1].astype(np.int64).sum(axis=2), geo.top)
+    zeros = residue = plain_wrong = 0
+    for c, s in geo.pairs:
+        d = s - c
+        D = M[c] - O.upsample(M[s], d, *geo.sizes[c])
+        Dx = Z[c] * (256 ** d) * (4 ** d) - _up_int(Z[s], d, *geo.sizes[c])
+        band = PA.SIGN_BAND * max(np.abs(M[c]).max(), np.abs(M[s]).max())
+        assert np.all(np.abs(D[Dx == 0]) <= band)
+        out = np.abs(D) > band
+        assert np.array_equal(np.sign(D[out]), np.sign(Dx[out]))
+        zeros += int(np.sum(Dx == 0))
+        residue += int(np.sum((Dx == 0) & (D != 0)))
+        plain_wrong += int(np.sum(np.sign(D) != np.sign(Dx)))
+    # the case the band is for: exact zeros that FP64 leaves nonzero, where sign(D) is noise
+    assert zeros > 0 and residue > 0 and plain_wrong > 0
 
 
 def test_planted_mistakes_fail_the_pins(monkeypatch):
