@@ -247,8 +247,13 @@ int saliency_backward(sp_ctx* ctx, const float* grad_prior, int32_t T, float* gr
  *                0..255 scale (the frames taken as real numbers).
  * Non-differentiable points: the chromatic mask and colour maximum are held fixed; the
  * global minimum and maximum and each 8x8 block maximum of an N(.) input take the gradient
- * at their first row-major position; a map at or below flat_tol passes none; |.| has
- * sign(0) = 0; max(0, .) passes nothing at 0; min(r', g') passes to r' on ties.
+ * at the first row-major position within 2^-20 of the map's range of the extreme; a map at
+ * or below flat_tol passes none; the derivative of a centre-surround |D| is 0 where |D| is
+ * at most 2^-16 of the pair's largest |value| (below FP32's resolution of the maps; flat
+ * regions of both levels make D vanish identically) and sign(D) elsewhere; the feature
+ * branches are decided on the frame bytes (2R - G - B > 0 and its like, min(R, G) > B,
+ * R <= G for the min, the sign of the byte-sum difference for the motion, 0 on a tie);
+ * max(0, .) passes nothing at 0.
  * SP_ESTATE unless saliency_backward of these T steps ran last on this tape. */
 int saliency_backward_frames(sp_ctx* ctx, const uint8_t* frames, int32_t T, float* grad_frames);
 
