@@ -708,7 +708,7 @@ def main():
             timed(gstep, 10)
             pr = profile_read(cx)
             profile_enable(cx, False)
-            per_px = {"k_gmm_acc": 7.0, "k_gmm_psi": 19.0}   # RGB + prior read; RGB read + unary read and written
+            per_px = {"k_gmm_acc": 7.0, "k_gmm_psi": 19.0}   # RGB + prior read; RGB read + U0, U1 read and written
             rec["kernels"] = {k: {"avg_us": round(v[0] / v[1] * 1e3, 3), "launches_per_call": v[1] / 10,
                                   "alg_GBps": (round(per_px[k] * px / (v[0] / v[1] * 1e-3) / 1e9, 2)
                                                if k in per_px else None)} for k, v in pr.items()}
@@ -748,6 +748,34 @@ def main():
                                          "cut_ms_per_frame": round(cut_s[0] / nl * 1e3, 4), "scale": 256.0,
                                          "object_px_last": int(lab[(nl - 1) % 2].sum().item())}
         mc.close()
+        cx.close()
+        # pixel-level adjoint: dL/d frames of an 8-frame clip, after the adjoint of the weights
+        # (each call recomputes every frame's maps, then runs the adjoint kernels per frame)
+        TP = 8
+        cx = Context(H, W, Params(record_tape=TP))
+        out = cx.run_clip(frames[:TP])
+        _, gpi = cx.mse_mask_loss(out["pi"], masks[:TP])
+        cx.saliency_backward(gpi)
+        lib, ch = cx.lib, cx._handle
+        lib.sp_set_stream(ch, stream)
+        GF = torch.empty((TP, H, W, 3), dtype=torch.float32, device=dev)
+
+        def pstep(_):
+            if lib.saliency_backward_frames(ch, frames.data_ptr(), TP, GF.data_ptr()):
+                raise RuntimeError(lib.sp_last_error().decode())
+
+        timed(pstep, 2)
+        npa = 20
+        dpa = timed(pstep, npa)
+        rec = {"clip_frames": TP, "ms_per_clip": round(dpa / npa * 1e3, 4),
+               "frames_per_s": round(npa * TP / dpa, 2)}
+        if "profile" not in skip:
+            profile_enable(cx, True)
+            timed(pstep, 3)
+            pr = profile_read(cx)
+            profile_enable(cx, False)
+            rec["ms_per_clip_by_kind"] = {k: round(v[0] / 3, 4) for k, v in pr.items()}
+        extras["pixel_adjoint"] = rec
         cx.close()
         log("extras: " + json.dumps(extras))
 

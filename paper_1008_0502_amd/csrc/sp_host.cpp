@@ -1220,13 +1220,15 @@ int sp_colour_likelihood(sp_ctx* c, const uint8_t* rgb_t, const float* prior, fl
   GmmIO io{};
   io.rgb = rgb_t;
   io.prior = prior;
-  io.st = c->gmm_state;
-  io.part = c->gmm_part;
   io.unary = unary_inout;
   io.n = c->g.H * c->g.W;
   io.ntiles = c->gmm_tiles;
   io.reg = c->p.gmm_reg;
   const int iters = c->p.gmm_iters;
+  io.part_out = c->gmm_part;
+  io.part_in = c->gmm_part;
+  io.st_prev = c->gmm_state;
+  io.st_next = c->gmm_state;
   auto launch = [&](int phase, int kind, float* out) -> int {
     io.out = out;
     const hipError_t e = c->prof.timed(c->stream, kind, [&] { return sp_launch_gmm(phase, M, io, c->stream); });

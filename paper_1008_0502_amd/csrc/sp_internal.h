@@ -324,8 +324,10 @@ struct GmmState {
 struct GmmIO {
   const uint8_t* rgb;      // [n][3]
   const float* prior;      // [n] p(A = 1): the object's sample weights (1 - p: the background's)
-  GmmState* st;
-  double* part;            // [values][ntiles] FP64 moments per tile
+  const GmmState* st_prev; // mixtures the launch reads (the E-step's; the M-step's centres)
+  GmmState* st_next;       // mixtures a fit stores (may be st_prev: read before written)
+  const double* part_in;   // [values][ntiles] FP64 moments per tile, read by a fit
+  double* part_out;        // [values][ntiles] written by the moment passes
   float* unary;            // [2][n], psi added in place
   float* out;              // [2][M][10] alpha, mu, cov (xx, xy, xz, yy, yz, zz) or null
   int32_t n, ntiles;
