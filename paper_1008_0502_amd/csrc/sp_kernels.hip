@@ -1668,6 +1668,328 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg(const Job* __restrict__ jobs,
     }
   }
 }
+
+// The reduced-map job for pair set 1 ((r, d) = (1,2), (1,3), (0,2), (0,3) in the stream's
+// pair order; the default pairs), with a fixed geometry.  The region one level below c_max
+// is always the 35x35 block at (2 y0 - 2, 2 x0 - 2) and each footprint the block at the
+// region's (or the tile's) origin shifted down by d levels, staged from coordinates clamped
+// into their level: a replicated row or column holds exactly the value that clamp-to-edge
+// sampling reads there, and the up-sample taps of the region's rows and columns are taken
+// at the clamped coordinate (a per-workgroup table).  Every loop bound, reduction offset
+// and staging index is then a compile-time constant, for edge tiles too.  The arithmetic
+// and the order of every sum are those of k_csg, so the maps and statistics are the same.
+namespace cg1 {
+constexpr int T = SP_CA_T;             // c_max tile edge
+constexpr int N1 = 2 * T + 3;          // region edge one level below c_max
+constexpr int PW = CG_PW1;             // LDS row stride of the region: whole quads, region column cc at cc + 2
+constexpr int X1N = N1 * PW;
+constexpr int FN = 11 * 11 + 7 * 7 + 5 * 5 + 3 * 3;   // footprints of pairs 0..3, back to back
+constexpr int FQN = N1 * N1;
+constexpr int TTN = N1 * T;            // >= 11 * N1, the widest footprint table
+constexpr int PER_CH = X1N + T * T + FN + FQN + TTN;
+__host__ __device__ constexpr int fe(int p) { return p == 0 ? 11 : (p == 1 ? 7 : (p == 2 ? 5 : 3)); }
+__host__ __device__ constexpr int fo(int p) { return p == 0 ? 0 : (p == 1 ? 121 : (p == 2 ? 170 : 195)); }
+}  // namespace cg1
+
+template <int NC>
+__global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
+                                                   const StreamDesc* __restrict__ sds,
+                                                   const StepIO* __restrict__ ios, StepIO io0) {
+  using namespace cg1;
+  static_assert(PW == 40 && N1 == 35 && T == 16, "layout of the fixed-geometry job");
+  extern __shared__ __align__(16) float dyn[];
+  __shared__ float4 rtab[2][N1], ctab[2][N1];   // r = 1 pairs: taps (i0, i1 relative, w, 1 - w)
+  __shared__ float wred[4][NC][3];
+  const Job J = jobs[blockIdx.x];
+  const StreamDesc& sd = sds[J.stream];
+  const float* ckpt = IOF(ckpt);
+  const int k0 = J.a, cm = sd.c_max, c1 = cm - 1;
+  const int Hm = sd.Hl[cm], Wm = sd.Wl[cm], H1 = sd.Hl[c1], W1 = sd.Wl[c1];
+  const int y0 = J.y0, x0 = J.x0, ry0 = 2 * y0 - 2, rx0 = 2 * x0 - 2;
+  float* const X1 = dyn;                 // [NC][N1][PW]
+  float* const X0 = X1 + NC * X1N;       // [NC][T][T]
+  float* const FP = X0 + NC * T * T;     // [NC][FN]
+  float* const FQ = FP + NC * FN;        // [N1][N1][NC]
+  float* const TT = FQ + NC * FQN;       // [..][NC]
+  const int tid = threadIdx.x, wf = wave_first();
+  // ---- staging, one round trip
+  {
+    gp<const float> Xc[NC];
+    bool vec = (W1 & 3) == 0 && rx0 >= 2 && rx0 + PW - 2 <= W1;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      Xc[j] = G(chan_ptr(sd, ckpt, k0 + j, c1));
+      vec = vec && (reinterpret_cast<uintptr_t>(Xc[j]) & 15) == 0;
+    }
+    if (vec) {
+      constexpr int NQ = N1 * (PW / 4);
+#pragma unroll
+      for (int q0 = 0; q0 < NQ; q0 += SP_BLOCK) {
+        const int q = q0 + tid;
+        if (q < NQ) {
+          const int r = q / (PW / 4), cq = q - r * (PW / 4);
+          const uint32_t ob = ((uint32_t)clampi(ry0 + r, 0, H1 - 1) * (uint32_t)W1 + (uint32_t)(rx0 - 2 + 4 * cq)) * 4u;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) lds_load4_u(X1 + j * X1N + 4 * (q0 + wf), Xc[j], ob);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i0 = 0; i0 < X1N; i0 += SP_BLOCK) {
+        const int i = i0 + tid;
+        if (i < X1N) {
+          const int r = i / PW, cc = i - r * PW;
+          const uint32_t ob = ((uint32_t)clampi(ry0 + r, 0, H1 - 1) * (uint32_t)W1 +
+                               (uint32_t)clampi(rx0 - 2 + cc, 0, W1 - 1)) * 4u;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) lds_load_u(X1 + j * X1N + i0 + wf, Xc[j], ob);
+        }
+      }
+    }
+  }
+  {
+    gp<const float> Xc[NC];
+    bool vec = (Wm & 3) == 0 && x0 + T <= Wm;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      Xc[j] = G(chan_ptr(sd, ckpt, k0 + j, cm));
+      vec = vec && (reinterpret_cast<uintptr_t>(Xc[j]) & 15) == 0;
+    }
+    if (vec) {
+      if (tid < T * T / 4) {
+        const uint32_t ob = ((uint32_t)min(y0 + (tid >> 2), Hm - 1) * (uint32_t)Wm + (uint32_t)(x0 + 4 * (tid & 3))) * 4u;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) lds_load4_u(X0 + j * T * T + 4 * wf, Xc[j], ob);
+      }
+    } else {
+      const uint32_t ob = ((uint32_t)min(y0 + (tid >> 4), Hm - 1) * (uint32_t)Wm + (uint32_t)min(x0 + (tid & 15), Wm - 1)) * 4u;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) lds_load_u(X0 + j * T * T + wf, Xc[j], ob);
+    }
+  }
+  if (tid < FN) {
+    // element tid of a channel's footprint block: pair p, row i, column e of its fe(p) columns
+    int p, i, e;
+    if (tid < fo(1)) {
+      p = 0, i = tid / fe(0), e = tid - i * fe(0);
+    } else if (tid < fo(2)) {
+      p = 1, i = (tid - fo(1)) / fe(1), e = tid - fo(1) - i * fe(1);
+    } else if (tid < fo(3)) {
+      p = 2, i = (tid - fo(2)) / fe(2), e = tid - fo(2) - i * fe(2);
+    } else {
+      p = 3, i = (tid - fo(3)) / fe(3), e = tid - fo(3) - i * fe(3);
+    }
+    const int d = 2 + (p & 1), s = (p < 2 ? c1 : cm) + d;
+    const int oy = p < 2 ? ry0 : y0, ox = p < 2 ? rx0 : x0;
+    const int Hs = sd.Hl[s], Ws = sd.Wl[s];
+    const size_t off = (size_t)clampi((oy >> d) + i, 0, Hs - 1) * Ws + clampi((ox >> d) + e, 0, Ws - 1);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) lds_load(FP + j * FN + tid, chan_ptr(sd, ckpt, k0 + j, s) + off);
+  }
+  if (tid < 4 * N1) {
+    // taps of the region's rows (which = 0, 2) and columns (1, 3) for pairs 0 and 1, at the
+    // clamped coordinate, relative to the footprint's first (unclamped) row or column
+    const int which = tid / N1, k = tid - which * N1;
+    const int p = which >> 1, d = 2 + p, s = c1 + d;
+    const bool col = which & 1;
+    const int o = col ? rx0 : ry0;
+    const Tap t = bilinear_tap(clampi(o + k, 0, (col ? W1 : H1) - 1), d, col ? sd.Wl[s] : sd.Hl[s]);
+    const float4 v = make_float4(__int_as_float(t.i0 - (o >> d)), __int_as_float(t.i1 - (o >> d)), t.w, 1.f - t.w);
+    if (col)
+      ctab[p][k] = v;
+    else
+      rtab[p][k] = v;
+  }
+  lds_wait();
+  __syncthreads();
+  const gp<float> gmap = G(sd.gmap);
+  const size_t plane = (size_t)Hm * Wm;
+  const int lane = lane_id(), w = wave_id();
+  const int sy = (lane >> 2) & 3, sx = lane & 3;
+  // ---- pairs 2 and 3 (c = c_max): one wavefront per map covers the tile's four 8x8
+  // blocks (a 2x2 quad per lane, DPP inside each 16-lane row)
+  {
+    const int blk = lane >> 4, by = blk >> 1, bx = blk & 1;
+    const int qy = 8 * by + 2 * sy, qx = 8 * bx + 2 * sx;
+    bool bval[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bval[i] = 8 * (i >> 1) < J.th && 8 * (i & 1) < J.tw;
+    int m = 0;
+#pragma unroll
+    for (int p = 2; p < 4; ++p) {
+      const int d = 2 + (p & 1), s = cm + d;
+      int yl[2], xl[2];
+      Tap ty[2], tx[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        yl[u] = min(qy + u, J.th - 1);
+        xl[u] = min(qx + u, J.tw - 1);
+        ty[u] = bilinear_tap(y0 + yl[u], d, sd.Hl[s]);
+        tx[u] = bilinear_tap(x0 + xl[u], d, sd.Wl[s]);
+      }
+#pragma unroll
+      for (int j = 0; j < NC; ++j, ++m) {
+        if ((m & 3) != w) continue;   // wave-uniform
+        const float* B = X0 + j * T * T;
+        float mn = INFINITY, mx = 0.f;   // F >= 0
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            const float up = bilinear_lds(FP + j * FN + fo(p), fe(p), ty[u], tx[v], y0 >> d, x0 >> d);
+            const float F = fabsf(B[yl[u] * T + xl[v]] - up);
+            mn = fmin_nn(mn, F);
+            mx = fmax_nn(mx, F);
+            if (qy + u < J.th && qx + v < J.tw)
+              gmap[((size_t)p * SP_NCH + k0 + j) * plane + (size_t)(y0 + qy + u) * Wm + x0 + qx + v] = F;
+          }
+        row16_minmax_nn(mn, mx);
+        float bmn[4], bmx[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float rmn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i));
+          const float rmx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i));
+          bmn[i] = bval[i] ? rmn : INFINITY;
+          bmx[i] = bval[i] ? rmx : -INFINITY;
+        }
+        if (lane == 0) {
+          const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)(k0 + j) * sd.cs_nt[p] + J.tid);
+          out[0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
+          out[1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
+          out[2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) + ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
+        }
+      }
+    }
+  }
+  // ---- pairs 0 and 1 (c = c_max - 1), one at a time: the footprint's rows interpolated at
+  // the region's columns, the map on the region, its statistics on the pixels the tile owns
+  // (region rows and columns 2 .. 33; wavefront w: block row w, a 2x2 quad per lane), then
+  // REDUCE to the tile
+  {
+    const int oh = min(2 * T, H1 - 2 * y0), ow = min(2 * T, W1 - 2 * x0);
+    const int bxl = lane >> 4, qy = 8 * w + 2 * sy, qx = 8 * bxl + 2 * sx;
+    int ro[2], co[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      ro[u] = 2 + min(qy + u, oh - 1);
+      co[u] = 2 + min(qx + u, ow - 1);
+    }
+    const bool rowval = 8 * w < oh;
+    bool bval[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bval[i] = rowval && 8 * i < ow;
+    const int g1 = tid / N1, cc1 = tid - g1 * N1;   // map pass: region column cc1, rows g1 + 7 i
+    const int rc = tid & (T - 1), rq = tid >> 4;     // reduction: tile column rc, row group rq
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      constexpr int NTAB[2] = {fe(0) * N1, fe(1) * N1};
+#pragma unroll
+      for (int e0 = 0; e0 < NTAB[p]; e0 += SP_BLOCK) {
+        const int e = e0 + tid;
+        if (e < NTAB[p]) {
+          const int fr = e / N1, cc = e - fr * N1;
+          const float4 ct = ctab[p][cc];
+          const float* f0 = FP + fo(p) + fr * fe(p) + __float_as_int(ct.x);
+          const float* f1 = FP + fo(p) + fr * fe(p) + __float_as_int(ct.y);
+          float v[NC];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) v[j] = fmaf(ct.z, f1[j * FN], ct.w * f0[j * FN]);
+          lds_putv<NC>(TT + e * NC, v);
+        }
+      }
+      __syncthreads();
+      // the map on the region
+      if (g1 < 7) {
+        const float* xr = X1 + g1 * PW + cc1 + 2;
+        float* fq = FQ + (g1 * N1 + cc1) * NC;
+#pragma unroll
+        for (int i = 0; i < N1 / 7; ++i) {
+          const float4 rt = rtab[p][g1 + 7 * i];
+          float t0[NC], t1[NC], F[NC];
+          lds_getv<NC>(TT + (__float_as_int(rt.x) * N1 + cc1) * NC, t0);
+          lds_getv<NC>(TT + (__float_as_int(rt.y) * N1 + cc1) * NC, t1);
+#pragma unroll
+          for (int j = 0; j < NC; ++j) F[j] = fabsf(xr[j * X1N + 7 * i * PW] - fmaf(rt.z, t1[j], rt.w * t0[j]));
+          lds_putv<NC>(fq + 7 * i * N1 * NC, F);
+        }
+      }
+      __syncthreads();
+      // statistics of the owned pixels
+      {
+        float q[4][NC];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) lds_getv<NC>(FQ + (ro[u] * N1 + co[v]) * NC, q[2 * u + v]);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          float mn = fmin_nn(fmin_nn(q[0][j], q[1][j]), fmin_nn(q[2][j], q[3][j]));   // F >= 0
+          float mx = fmax_nn(fmax_nn(q[0][j], q[1][j]), fmax_nn(q[2][j], q[3][j]));
+          row16_minmax_nn(mn, mx);
+          float bmn[4], bmx[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float rmn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i));
+            const float rmx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i));
+            bmn[i] = bval[i] ? rmn : INFINITY;
+            bmx[i] = bval[i] ? rmx : -INFINITY;
+          }
+          if (lane == 0) {
+            wred[w][j][0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
+            wred[w][j][1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
+            wred[w][j][2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) +
+                            ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
+          }
+        }
+      }
+      // REDUCE to the tile: row pass (region rows x tile columns) into the table, then
+      // column pass; taps 2 rc .. 2 rc + 4 of the region (a replicated edge is the clamp)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int rr = rq + 16 * i;
+        if (rr < N1) {
+          float acc[NC];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[j] = 0.f;
+#pragma unroll
+          for (int t = 0; t < 5; ++t) {
+            float v[NC];
+            lds_getv<NC>(FQ + (rr * N1 + 2 * rc + t) * NC, v);
+#pragma unroll
+            for (int j = 0; j < NC; ++j) acc[j] = fmaf(binom(t - 2), v[j], acc[j]);
+          }
+          lds_putv<NC>(TT + (rr * T + rc) * NC, acc);
+        }
+      }
+      __syncthreads();
+      {
+        float acc[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[j] = 0.f;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          float v[NC];
+          lds_getv<NC>(TT + ((2 * rq + t) * T + rc) * NC, v);
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[j] = fmaf(binom(t - 2), v[j], acc[j]);
+        }
+        if (rq < J.th && rc < J.tw) {
+          const size_t o = (size_t)(y0 + rq) * Wm + x0 + rc;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) gmap[((size_t)p * SP_NCH + k0 + j) * plane + o] = acc[j];
+        }
+      }
+      if (tid < NC) {
+        const int j = tid;
+        const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)(k0 + j) * sd.cs_nt[p] + J.tid);
+        out[0] = fminf(fminf(wred[0][j][0], wred[1][j][0]), fminf(wred[2][j][0], wred[3][j][0]));
+        out[1] = fmaxf(fmaxf(wred[0][j][1], wred[1][j][1]), fmaxf(wred[2][j][1], wred[3][j][1]));
+        out[2] = (wred[0][j][2] + wred[1][j][2]) + (wred[2][j][2] + wred[3][j][2]);
+      }
+      __syncthreads();   // the map, the table and wred are reused by the next pair
+    }
+  }
+}
 #pragma clang diagnostic pop
 
 // F-bar_k on a 16x16 c_max tile = sum over pairs of N(reduced map), all 8 channels; then
@@ -2444,13 +2766,13 @@ hipError_t sp_launch(int kind, const Job* jobs, int n, const StreamDesc* sds, co
       const int nc = flag & 0xff, set = flag >> 8;
       if (set == 1) {
         if (nc == 8)
-          hipLaunchKernelGGL((k_csg<8, 1>), g, b, lds, st, jobs, sds, ios, io);
+          hipLaunchKernelGGL((k_csg1<8>), g, b, lds, st, jobs, sds, ios, io);
         else if (nc == 4)
-          hipLaunchKernelGGL((k_csg<4, 1>), g, b, lds, st, jobs, sds, ios, io);
+          hipLaunchKernelGGL((k_csg1<4>), g, b, lds, st, jobs, sds, ios, io);
         else if (nc == 2)
-          hipLaunchKernelGGL((k_csg<2, 1>), g, b, lds, st, jobs, sds, ios, io);
+          hipLaunchKernelGGL((k_csg1<2>), g, b, lds, st, jobs, sds, ios, io);
         else
-          hipLaunchKernelGGL((k_csg<1, 1>), g, b, lds, st, jobs, sds, ios, io);
+          hipLaunchKernelGGL((k_csg1<1>), g, b, lds, st, jobs, sds, ios, io);
       } else {
         if (nc == 8)
           hipLaunchKernelGGL((k_csg<8, 0>), g, b, lds, st, jobs, sds, ios, io);
@@ -2562,8 +2884,8 @@ hipError_t sp_csapply_reserve_lds(size_t bytes) {
                          reinterpret_cast<const void*>(&k_csapply<4>), reinterpret_cast<const void*>(&k_csapply<8>),
                          reinterpret_cast<const void*>(&k_csg<1, 0>),  reinterpret_cast<const void*>(&k_csg<2, 0>),
                          reinterpret_cast<const void*>(&k_csg<4, 0>),  reinterpret_cast<const void*>(&k_csg<8, 0>),
-                         reinterpret_cast<const void*>(&k_csg<1, 1>),  reinterpret_cast<const void*>(&k_csg<2, 1>),
-                         reinterpret_cast<const void*>(&k_csg<4, 1>),  reinterpret_cast<const void*>(&k_csg<8, 1>)};
+                         reinterpret_cast<const void*>(&k_csg1<1>),    reinterpret_cast<const void*>(&k_csg1<2>),
+                         reinterpret_cast<const void*>(&k_csg1<4>),    reinterpret_cast<const void*>(&k_csg1<8>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
