@@ -56,6 +56,29 @@ __device__ __forceinline__ void row16_minmax_nn(float& mn, float& mx) {
   mx = __uint_as_float(b);
 }
 
+// The four 16-lane rows' results of row16_minmax_nn combined across the wavefront: rows
+// whose block is not valid are set aside (min ignores them, max and sum count them as 0:
+// the values are >= 0), then two DPP broadcast steps (row 15 into the next row, then lane
+// 31 into rows 2 and 3) leave in lane 63 the minimum, the maximum and the sum of the row
+// maxima ((b2 + b3) + (b0 + b1)).  Every lane must be active.
+__device__ __forceinline__ void rows4_combine_nn(float mn, float mx, bool valid, float& omn, float& omx, float& osum) {
+  uint32_t a = valid ? __float_as_uint(mn) : 0xffffffffu, b = valid ? __float_as_uint(mx) : 0u;
+  float c = valid ? mx : 0.f;
+  asm volatile(
+      "s_nop 1\n"
+      "v_min_u32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n"
+      "v_max_u32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf\n"
+      "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0xa bank_mask:0xf\n"
+      "s_nop 1\n"
+      "v_min_u32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n"
+      "v_max_u32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf\n"
+      "v_add_f32_dpp %2, %2, %2 row_bcast:31 row_mask:0xc bank_mask:0xf\n"
+      : "+v"(a), "+v"(b), "+v"(c));
+  omn = a == 0xffffffffu ? INFINITY : __uint_as_float(a);
+  omx = __uint_as_float(b);
+  osum = c;
+}
+
 struct OpMax { __device__ static float f(float a, float b) { return fmaxf(a, b); } };
 struct OpMin { __device__ static float f(float a, float b) { return fminf(a, b); } };
 struct OpSum { __device__ static float f(float a, float b) { return a + b; } };

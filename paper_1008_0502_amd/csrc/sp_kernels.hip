@@ -1698,7 +1698,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
   using namespace cg1;
   static_assert(PW == 40 && N1 == 35 && T == 16, "layout of the fixed-geometry job");
   extern __shared__ __align__(16) float dyn[];
-  __shared__ float4 rtab[2][N1], ctab[2][N1];   // r = 1 pairs: taps (i0, i1 relative, w, 1 - w)
+  __shared__ float4 rtab[2][N1], ctab[2][N1];   // r = 1 pairs: taps (i0, i1 as offsets, w, 1 - w)
   __shared__ float wred[4][NC][3];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
@@ -1794,7 +1794,10 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
     const bool col = which & 1;
     const int o = col ? rx0 : ry0;
     const Tap t = bilinear_tap(clampi(o + k, 0, (col ? W1 : H1) - 1), d, col ? sd.Wl[s] : sd.Hl[s]);
-    const float4 v = make_float4(__int_as_float(t.i0 - (o >> d)), __int_as_float(t.i1 - (o >> d)), t.w, 1.f - t.w);
+    // rows: offsets of the table rows (footprint row * N1 * NC); columns: footprint columns
+    const int sc = col ? 1 : N1 * NC;
+    const float4 v = make_float4(__int_as_float((t.i0 - (o >> d)) * sc), __int_as_float((t.i1 - (o >> d)) * sc), t.w,
+                                 1.f - t.w);
     if (col)
       ctab[p][k] = v;
     else
@@ -1811,9 +1814,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
   {
     const int blk = lane >> 4, by = blk >> 1, bx = blk & 1;
     const int qy = 8 * by + 2 * sy, qx = 8 * bx + 2 * sx;
-    bool bval[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) bval[i] = 8 * (i >> 1) < J.th && 8 * (i & 1) < J.tw;
+    const bool bvalid = 8 * by < J.th && 8 * bx < J.tw;   // the lane's 8x8 block lies in the tile
     int m = 0;
 #pragma unroll
     for (int p = 2; p < 4; ++p) {
@@ -1844,19 +1845,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
               gmap[((size_t)p * SP_NCH + k0 + j) * plane + (size_t)(y0 + qy + u) * Wm + x0 + qx + v] = F;
           }
         row16_minmax_nn(mn, mx);
-        float bmn[4], bmx[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float rmn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i));
-          const float rmx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i));
-          bmn[i] = bval[i] ? rmn : INFINITY;
-          bmx[i] = bval[i] ? rmx : -INFINITY;
-        }
-        if (lane == 0) {
+        float tmn, tmx, tsum;
+        rows4_combine_nn(mn, mx, bvalid, tmn, tmx, tsum);
+        if (lane == 63) {
           const gp<float> out = G(sd.cs_part) + 3 * ((size_t)sd.cs_off[p] + (size_t)(k0 + j) * sd.cs_nt[p] + J.tid);
-          out[0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
-          out[1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
-          out[2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) + ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
+          out[0] = tmn;
+          out[1] = tmx;
+          out[2] = tsum;
         }
       }
     }
@@ -1874,10 +1869,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
       ro[u] = 2 + min(qy + u, oh - 1);
       co[u] = 2 + min(qx + u, ow - 1);
     }
-    const bool rowval = 8 * w < oh;
-    bool bval[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) bval[i] = rowval && 8 * i < ow;
+    const bool bvalid = 8 * w < oh && 8 * bxl < ow;   // the lane's 8x8 block of owned pixels
     const int g1 = tid / N1, cc1 = tid - g1 * N1;   // map pass: region column cc1, rows g1 + 7 i
     const int rc = tid & (T - 1), rq = tid >> 4;     // reduction: tile column rc, row group rq
 #pragma unroll
@@ -1906,8 +1898,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
         for (int i = 0; i < N1 / 7; ++i) {
           const float4 rt = rtab[p][g1 + 7 * i];
           float t0[NC], t1[NC], F[NC];
-          lds_getv<NC>(TT + (__float_as_int(rt.x) * N1 + cc1) * NC, t0);
-          lds_getv<NC>(TT + (__float_as_int(rt.y) * N1 + cc1) * NC, t1);
+          lds_getv<NC>(TT + __float_as_int(rt.x) + cc1 * NC, t0);
+          lds_getv<NC>(TT + __float_as_int(rt.y) + cc1 * NC, t1);
 #pragma unroll
           for (int j = 0; j < NC; ++j) F[j] = fabsf(xr[j * X1N + 7 * i * PW] - fmaf(rt.z, t1[j], rt.w * t0[j]));
           lds_putv<NC>(fq + 7 * i * N1 * NC, F);
@@ -1926,19 +1918,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
           float mn = fmin_nn(fmin_nn(q[0][j], q[1][j]), fmin_nn(q[2][j], q[3][j]));   // F >= 0
           float mx = fmax_nn(fmax_nn(q[0][j], q[1][j]), fmax_nn(q[2][j], q[3][j]));
           row16_minmax_nn(mn, mx);
-          float bmn[4], bmx[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float rmn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn), 16 * i));
-            const float rmx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), 16 * i));
-            bmn[i] = bval[i] ? rmn : INFINITY;
-            bmx[i] = bval[i] ? rmx : -INFINITY;
-          }
-          if (lane == 0) {
-            wred[w][j][0] = fminf(fminf(bmn[0], bmn[1]), fminf(bmn[2], bmn[3]));
-            wred[w][j][1] = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
-            wred[w][j][2] = ((bval[0] ? bmx[0] : 0.f) + (bval[1] ? bmx[1] : 0.f)) +
-                            ((bval[2] ? bmx[2] : 0.f) + (bval[3] ? bmx[3] : 0.f));
+          float tmn, tmx, tsum;
+          rows4_combine_nn(mn, mx, bvalid, tmn, tmx, tsum);
+          if (lane == 63) {
+            wred[w][j][0] = tmn;
+            wred[w][j][1] = tmx;
+            wred[w][j][2] = tsum;
           }
         }
       }
