@@ -921,12 +921,14 @@ __device__ __forceinline__ Foot footprint(int y0, int ny, int x0, int nx, int d,
   return f;
 }
 
+// Bilinear sample of a staged footprint, with explicit FMAs: every kernel that forms a
+// centre-surround map from LDS gives the same bits whatever the compiler contracts.
 __device__ __forceinline__ float bilinear_lds(const float* X, int ld, const Tap& ty, const Tap& tx, int fy0, int fx0) {
   const float* r0 = X + (ty.i0 - fy0) * ld - fx0;
   const float* r1 = X + (ty.i1 - fy0) * ld - fx0;
-  const float top = (1.f - tx.w) * r0[tx.i0] + tx.w * r0[tx.i1];
-  const float bot = (1.f - tx.w) * r1[tx.i0] + tx.w * r1[tx.i1];
-  return (1.f - ty.w) * top + ty.w * bot;
+  const float top = fmaf(tx.w, r0[tx.i1], (1.f - tx.w) * r0[tx.i0]);
+  const float bot = fmaf(tx.w, r1[tx.i1], (1.f - tx.w) * r1[tx.i0]);
+  return fmaf(ty.w, bot, (1.f - ty.w) * top);
 }
 
 __global__ __launch_bounds__(SP_BLOCK) void k_csstats(const Job* __restrict__ jobs,
@@ -1698,7 +1700,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
   using namespace cg1;
   static_assert(PW == 40 && N1 == 35 && T == 16, "layout of the fixed-geometry job");
   extern __shared__ __align__(16) float dyn[];
-  __shared__ float4 rtab[2][N1], ctab[2][N1];   // r = 1 pairs: taps (i0, i1 as offsets, w, 1 - w)
+  __shared__ float4 rtab[2][N1], ctab[2][N1];   // pairs 0, 1: taps (i0, i1 as offsets, w, 1 - w)
   __shared__ float wred[4][NC][3];
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
@@ -1767,24 +1769,18 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
       for (int j = 0; j < NC; ++j) lds_load_u(X0 + j * T * T + wf, Xc[j], ob);
     }
   }
-  if (tid < FN) {
-    // element tid of a channel's footprint block: pair p, row i, column e of its fe(p) columns
-    int p, i, e;
-    if (tid < fo(1)) {
-      p = 0, i = tid / fe(0), e = tid - i * fe(0);
-    } else if (tid < fo(2)) {
-      p = 1, i = (tid - fo(1)) / fe(1), e = tid - fo(1) - i * fe(1);
-    } else if (tid < fo(3)) {
-      p = 2, i = (tid - fo(2)) / fe(2), e = tid - fo(2) - i * fe(2);
-    } else {
-      p = 3, i = (tid - fo(3)) / fe(3), e = tid - fo(3) - i * fe(3);
-    }
-    const int d = 2 + (p & 1), s = (p < 2 ? c1 : cm) + d;
-    const int oy = p < 2 ? ry0 : y0, ox = p < 2 ? rx0 : x0;
-    const int Hs = sd.Hl[s], Ws = sd.Wl[s];
-    const size_t off = (size_t)clampi((oy >> d) + i, 0, Hs - 1) * Ws + clampi((ox >> d) + e, 0, Ws - 1);
+  // footprints, one pair at a time (uniform level and base; lane = element)
 #pragma unroll
-    for (int j = 0; j < NC; ++j) lds_load(FP + j * FN + tid, chan_ptr(sd, ckpt, k0 + j, s) + off);
+  for (int p = 0; p < 4; ++p) {
+    const int d = 2 + (p & 1), s = (p < 2 ? c1 : cm) + d;
+    const int oy = (p < 2 ? ry0 : y0) >> d, ox = (p < 2 ? rx0 : x0) >> d;
+    const int Hs = sd.Hl[s], Ws = sd.Wl[s];
+    if (tid < fe(p) * fe(p)) {
+      const int i = tid / fe(p), e = tid - i * fe(p);
+      const uint32_t ob = ((uint32_t)clampi(oy + i, 0, Hs - 1) * (uint32_t)Ws + (uint32_t)clampi(ox + e, 0, Ws - 1)) * 4u;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) lds_load_u(FP + j * FN + fo(p) + wf, G(chan_ptr(sd, ckpt, k0 + j, s)), ob);
+    }
   }
   if (tid < 4 * N1) {
     // taps of the region's rows (which = 0, 2) and columns (1, 3) for pairs 0 and 1, at the
@@ -1842,7 +1838,8 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
             mn = fmin_nn(mn, F);
             mx = fmax_nn(mx, F);
             if (qy + u < J.th && qx + v < J.tw)
-              gmap[((size_t)p * SP_NCH + k0 + j) * plane + (size_t)(y0 + qy + u) * Wm + x0 + qx + v] = F;
+              *at_bytes(gmap + ((size_t)p * SP_NCH + k0 + j) * plane,
+                        ((uint32_t)(y0 + qy + u) * (uint32_t)Wm + (uint32_t)(x0 + qx + v)) * 4u) = F;
           }
         row16_minmax_nn(mn, mx);
         float tmn, tmx, tsum;
@@ -1959,9 +1956,9 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
           for (int j = 0; j < NC; ++j) acc[j] = fmaf(binom(t - 2), v[j], acc[j]);
         }
         if (rq < J.th && rc < J.tw) {
-          const size_t o = (size_t)(y0 + rq) * Wm + x0 + rc;
+          const uint32_t ob = ((uint32_t)(y0 + rq) * (uint32_t)Wm + (uint32_t)(x0 + rc)) * 4u;
 #pragma unroll
-          for (int j = 0; j < NC; ++j) gmap[((size_t)p * SP_NCH + k0 + j) * plane + o] = acc[j];
+          for (int j = 0; j < NC; ++j) *at_bytes(gmap + ((size_t)p * SP_NCH + k0 + j) * plane, ob) = acc[j];
         }
       }
       if (tid < NC) {
