@@ -617,6 +617,8 @@ struct sp_ctx {
   } pa;
   int32_t* pa_bpos = nullptr;     // block-maximum positions of every N(.) adjoint map
   float* pa_sc = nullptr;         // [maps][8] scalars of every N(.) adjoint map
+  float2* pa_mm = nullptr;        // [maps][mm] (min, max) partials of every N(.) adjoint map
+  PaStrip* pa_strip = nullptr;    // [maps][strips] strip partials of every N(.) adjoint map
   // colour likelihood
   GmmState* gmm_state = nullptr;
   double* gmm_part = nullptr;     // [2 M 10][gmm_tiles] FP64 moments per tile
@@ -706,6 +708,22 @@ size_t pixadj_nblocks(const Geo& g) {
   return n;
 }
 
+// Largest N(.) adjoint map (pixels, rows) and the partials each map gets.
+struct PaDims {
+  int maxn, maxh;
+  size_t mm, strips;
+};
+PaDims pixadj_dims(const Geo& g) {
+  PaDims D{g.Hl[g.c_max] * g.Wl[g.c_max], g.Hl[g.c_max], 0, 0};
+  for (int p = 0; p < g.n_pairs; ++p) {
+    D.maxn = std::max(D.maxn, g.Hl[g.pc[p]] * g.Wl[g.pc[p]]);
+    D.maxh = std::max(D.maxh, g.Hl[g.pc[p]]);
+  }
+  D.mm = (size_t)(D.maxn + SP_PA_MMT - 1) / SP_PA_MMT;
+  D.strips = (size_t)(D.maxh + 7) / 8;
+  return D;
+}
+
 // Workspace of the pixel-level adjoint, taken from the context's arena (both layout passes).
 void pixadj_layout(sp_ctx* c, Bump& b) {
   const Geo& g = c->g;
@@ -740,6 +758,10 @@ void pixadj_layout(sp_ctx* c, Bump& b) {
   }
   c->pa_bpos = b.take<int32_t>(pixadj_nblocks(g) + 64);
   c->pa_sc = b.take<float>((size_t)SP_PA_SC * SP_NCH * (1 + g.n_pairs));
+  const size_t nmaps = (size_t)SP_NCH * (1 + g.n_pairs);
+  const PaDims D = pixadj_dims(g);
+  c->pa_mm = b.take<float2>(nmaps * D.mm);
+  c->pa_strip = b.take<PaStrip>(nmaps * D.strips);
 }
 
 // Static launch tables of the pixel-level adjoint (pointers into the forward's own maps and
@@ -789,14 +811,19 @@ hipError_t pixadj_upload(sp_ctx* c) {
   // N(.) adjoint maps: the 8 across-scale sums, then every pair's 8 centre-surround maps
   int32_t* bpos = c->pa_bpos;
   float* sc = c->pa_sc;
+  float2* mm = c->pa_mm;
+  PaStrip* strip = c->pa_strip;
+  const PaDims D = pixadj_dims(g);
   auto nblk = [&](int l) { return ((g.Hl[l] + 7) / 8) * ((g.Wl[l] + 7) / 8); };
   {
     std::vector<PaMap> m(SP_NCH);
     const size_t pl = n_l(cm);
     for (int k = 0; k < SP_NCH; ++k) {
-      m[k] = PaMap{sd.fbar + k * pl, A.gS, A.gfbar + k * pl, bpos, sc, g.Hl[cm], g.Wl[cm], c->p.weights[k], 0};
+      m[k] = PaMap{sd.fbar + k * pl, A.gS, A.gfbar + k * pl, bpos, sc, mm, strip, g.Hl[cm], g.Wl[cm], c->p.weights[k], 0};
       bpos += nblk(cm);
       sc += SP_PA_SC;
+      mm += D.mm;
+      strip += D.strips;
     }
     put(A.maps_fbar, m.data(), m.size() * sizeof(PaMap));
   }
@@ -807,9 +834,12 @@ hipError_t pixadj_upload(sp_ctx* c) {
       const size_t pl = n_l(cl);
       for (int k = 0; k < SP_NCH; ++k) {
         const float* gn = cl == cm ? A.gfbar + k * pl : A.gN[cl] + k * pl;
-        m[(size_t)p * SP_NCH + k] = PaMap{A.F[p] + k * pl, gn, A.F[p] + k * pl, bpos, sc, g.Hl[cl], g.Wl[cl], 1.f, 0};
+        m[(size_t)p * SP_NCH + k] = PaMap{A.F[p] + k * pl, gn, A.F[p] + k * pl, bpos, sc, mm, strip, g.Hl[cl], g.Wl[cl],
+                                          1.f, 0};
         bpos += nblk(cl);
         sc += SP_PA_SC;
+        mm += D.mm;
+        strip += D.strips;
       }
     }
     put(A.maps_F, m.data(), m.size() * sizeof(PaMap));
@@ -1695,20 +1725,22 @@ int saliency_backward_frames(sp_ctx* c, const uint8_t* frames, int32_t T, float*
     const hipError_t e = timed(c, JOB_PIX_ADJ, [&]() -> hipError_t {
       hipError_t r = sp_pa_gs(c->gs_all + (size_t)t * plc, c->S_tape + (size_t)t * plc, c->ms_tape + 2 * (size_t)t,
                               (int)plc, c->p.flat_tol, A.gS, c->stream);
-      if (r == hipSuccess) r = sp_pa_nadjoint(A.maps_fbar, SP_NCH, (int)plc, c->p.flat_tol, c->stream);
+      if (r == hipSuccess) r = sp_pa_nadjoint(A.maps_fbar, SP_NCH, (int)plc, g.Hl[cm], c->p.flat_tol, c->stream);
       for (int l = cm - 1; l >= g.c_min && r == hipSuccess; --l)
         r = sp_pa_plane(0, A.tab_gn[l], SP_NCH, n_l(l), 0, nullptr, nullptr, c->stream);
       // dL/dX and the pairs' scales start at zero
       if (r == hipSuccess) r = sp_pa_zero(A.gX[0], A.gX_floats + (size_t)SP_NCH * g.n_pairs, c->stream);
       for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
         r = sp_pa_plane(1, A.tab_cs[p], SP_NCH, n_l(g.pc[p]), 0, nullptr, nullptr, c->stream);
-      if (r == hipSuccess) r = sp_pa_nadjoint(A.maps_F, SP_NCH * g.n_pairs, maxF, c->p.flat_tol, c->stream);
+      if (r == hipSuccess)
+        r = sp_pa_nadjoint(A.maps_F, SP_NCH * g.n_pairs, maxF, pixadj_dims(g).maxh, c->p.flat_tol, c->stream);
       for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
         r = sp_pa_plane(2, A.tab_cs[p], SP_NCH, n_l(g.pc[p]), 0, A.gc[p], nullptr, c->stream);
       for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
         r = sp_pa_plane(3, A.tab_up[p], SP_NCH, n_l(g.ps[p]), 0, nullptr, nullptr, c->stream);
       for (int l = g.top; l >= 1 && r == hipSuccess; --l) {
-        if (A.tab_gab[l]) r = sp_pa_plane(4, A.tab_gab[l], 1, n_l(l), 0, nullptr, A.taps, c->stream);
+        if (A.tab_gab[l])
+          r = sp_pa_plane(4, A.tab_gab[l], 1, n_l(l), g.Wl[l], nullptr, A.taps, c->stream, c->p.gabor_radius);
         if (r == hipSuccess) r = sp_pa_plane(0, A.tab_pyr[l], 4, n_l(l - 1), 1, nullptr, nullptr, c->stream);
       }
       if (r == hipSuccess)

@@ -361,12 +361,19 @@ struct CutIO {
 };
 
 // Pixel-level adjoint (dL/d frame): one map of the N(.) adjoint.
+struct PaStrip {           // partial sums of one 8-row strip of an N(.) adjoint map
+  double sb, sgy, sg;      // block maxima of Y, g Y, g
+  int32_t jn, jx;          // first positions within the tie tolerance of the minimum and maximum
+};
+#define SP_PA_MMT 4096     // pixels of a min / max partial of an N(.) adjoint map
 struct PaMap {
   const float* X;          // [h][w] the map N was applied to
   const float* g;          // [h][w] dL/dN before the factor gs
   float* out;              // [h][w] dL/dX (may be the storage of X: the apply pass does not read X)
   int32_t* bpos;           // [nb] first position of each 8x8 block maximum
   float* sc;               // [8] A/range, gb/range, g(min), g(max), argmin, argmax (int bits), flat, nb
+  float2* mm;              // [ceil(h w / SP_PA_MMT)] (min, max) partials
+  PaStrip* strip;          // [ceil(h / 8)] strip partials
   int32_t h, w;
   float gs;
   int32_t pad;

@@ -55,9 +55,9 @@ hipError_t sp_launch_cut(int phase, const CutIO& io, hipStream_t st);
 // 3 up-sample transpose (subtracts), 4 Gabor transpose (taps: [4][2 SP_PA_R + 1]^2, radius = plane d).
 hipError_t sp_pa_gs(const float* gs, const float* S, const float* ms, int n, float flat_tol, float* gS,
                     hipStream_t st);
-hipError_t sp_pa_nadjoint(const PaMap* maps, int nmaps, int maxn, float flat_tol, hipStream_t st);
+hipError_t sp_pa_nadjoint(const PaMap* maps, int nmaps, int maxn, int maxh, float flat_tol, hipStream_t st);
 hipError_t sp_pa_plane(int kind, const PaPlane* tab, int nplanes, int maxn, int flag, float* const* gc,
-                       const float* taps, hipStream_t st);
+                       const float* taps, hipStream_t st, int gabor_r = 0);
 hipError_t sp_pa_feat(const uint8_t* rgb, const uint8_t* prev, const uint32_t* maxp, int nmax, const float* g0, int n,
                       float* gout, float* gprev, hipStream_t st);
 hipError_t sp_pa_zero(float* p, size_t n, hipStream_t st);

@@ -2288,11 +2288,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_kalman(const Job* __restrict__ job
 // distance to the nearest object in the pixel's column within R, a row pass the minimum of
 // v(x')^2 + (x - x')^2 over |x - x'| <= R.
 constexpr int DT_N = SP_DT_T + 2 * SP_DT_RMAX;
+constexpr int DT_W = (DT_N + 31) / 32;   // 32-bit words of a region column or row mask
 constexpr int DT_INF = 1 << 30;
 __global__ __launch_bounds__(SP_BLOCK) void k_dt(const Job* __restrict__ jobs, const StreamDesc* __restrict__ sds,
                                                  const StepIO* __restrict__ ios, StepIO io0) {
-  __shared__ uint8_t obj[DT_N * DT_N];
-  __shared__ int vd[SP_DT_T * DT_N];
+  __shared__ uint32_t cmask[DT_N][DT_W];       // per region column: bit r = object at region row r
+  __shared__ uint32_t rmask[SP_DT_T][DT_W];    // per tile row: bit c = an object within R in column c
+  __shared__ int vd[SP_DT_T * DT_N];           // squared column distance (or DT_INF) per tile row and region column
   const Job J = jobs[blockIdx.x];
   const StreamDesc& sd = sds[J.stream];
   const gp<const uint8_t> seg = G(IOF(seg_prev));
@@ -2301,46 +2303,90 @@ __global__ __launch_bounds__(SP_BLOCK) void k_dt(const Job* __restrict__ jobs, c
   const int H = sd.H, W = sd.W, R = sd.dt_r;
   const int nr = J.th + 2 * R, nc = J.tw + 2 * R;
   const int ry0 = J.y0 - R, rx0 = J.x0 - R;
-  {
-    Walk2 wk(threadIdx.x, nc);
-    for (int i0 = 0; i0 + (int)threadIdx.x < nr * nc; i0 += SP_BLOCK, wk.next()) {
-      const int y = ry0 + wk.r, x = rx0 + wk.c;
-      uint8_t o = 0;
-      if (y >= 0 && y < H && x >= 0 && x < W) {
-        const uint32_t k = (uint32_t)y * (uint32_t)W + (uint32_t)x;
-        o = seg ? (uint8_t)(seg[k] != 0) : (uint8_t)(pprev[k] > 0.5f);
-      }
-      obj[i0 + threadIdx.x] = o;
-    }
-  }
+  const int tid = threadIdx.x;
+  for (int i = tid; i < DT_N * DT_W; i += SP_BLOCK) (&cmask[0][0])[i] = 0u;
+  for (int i = tid; i < SP_DT_T * DT_W; i += SP_BLOCK) (&rmask[0][0])[i] = 0u;
   __syncthreads();
+  // the object pixels of the region (outside the frame: none), eight loads in flight per
+  // thread (unconditional, from clamped addresses, then selected); the source (segmentation
+  // bytes or the previous prior) is chosen outside the loop, so no branch splits a batch
+  auto stage = [&](auto is_obj) {
+    const int n = nr * nc;
+    Walk2 wk(tid, nc);
+    for (int i0 = 0; i0 < n; i0 += 8 * SP_BLOCK) {
+      int r[8], c[8];
+      bool o[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        r[k] = wk.r;
+        c[k] = wk.c;
+        wk.next();
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int y = ry0 + r[k], x = rx0 + c[k];
+        const uint32_t a = (uint32_t)clampi(y, 0, H - 1) * (uint32_t)W + (uint32_t)clampi(x, 0, W - 1);
+        o[k] = is_obj(a) && i0 + k * SP_BLOCK + tid < n && y >= 0 && y < H && x >= 0 && x < W;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (o[k]) atomicOr(&cmask[c[k]][r[k] >> 5], 1u << (r[k] & 31));
+    }
+  };
+  if (seg)
+    stage([&](uint32_t a) { return seg[a] != 0; });
+  else
+    stage([&](uint32_t a) { return pprev[a] > 0.5f; });
+  __syncthreads();
+  // column pass: the nearest object row at or above / at or below each tile row, from the
+  // column's mask (clz / ctz on the word holding the row, then the words before / after)
   const int R2 = R * R;
-  for (int c = threadIdx.x; c < nc; c += SP_BLOCK) {
-    int last = -DT_INF;   // region row of the nearest object at or above
-    for (int r = 0; r < R + J.th; ++r) {
-      if (obj[r * nc + c]) last = r;
-      if (r >= R) {
-        const int d = r - last;
-        vd[(r - R) * nc + c] = d <= R ? d * d : DT_INF;
+  for (int q = tid; q < J.th * nc; q += SP_BLOCK) {
+    const int t = q / nc, c = q - t * nc, rr = t + R;
+    const int w = rr >> 5, b = rr & 31;
+    int up = -DT_INF, dn = DT_INF;
+    uint32_t m = cmask[c][w] & (b == 31 ? 0xffffffffu : ((2u << b) - 1u));
+    for (int k = w; k >= 0; --k) {
+      if (k < w) m = cmask[c][k];
+      if (m) {
+        up = 32 * k + 31 - __clz(m);
+        break;
       }
     }
-    int next = DT_INF;    // region row of the nearest object at or below
-    for (int r = nr - 1; r >= R; --r) {
-      if (obj[r * nc + c]) next = r;
-      if (r < R + J.th) {
-        const int d = next - r;
-        int& v = vd[(r - R) * nc + c];
-        if (d <= R) v = min(v, d * d);
+    m = cmask[c][w] & ~((1u << b) - 1u);
+    for (int k = w; k < DT_W; ++k) {
+      if (k > w) m = cmask[c][k];
+      if (m) {
+        dn = 32 * k + __ffs(m) - 1;
+        break;
       }
     }
+    const int d = min(rr - up, dn - rr);
+    const bool near = d <= R;
+    vd[t * nc + c] = near ? d * d : DT_INF;
+    if (near) atomicOr(&rmask[t][c >> 5], 1u << (c & 31));
   }
   __syncthreads();
+  // row pass: min over |k| <= R of vd(x + k) + k^2 (exact squared distance within R), the
+  // search skipped when no column within R holds an object
   const float k2 = sd.dt_k;
-  Walk2 wk(threadIdx.x, J.tw);
-  for (int i0 = 0; i0 + (int)threadIdx.x < J.th * J.tw; i0 += SP_BLOCK, wk.next()) {
+  Walk2 wk(tid, J.tw);
+  for (int i0 = 0; i0 + tid < J.th * J.tw; i0 += SP_BLOCK, wk.next()) {
     const int* row = vd + wk.r * nc + wk.c + R;
-    int best = row[0];
-    for (int k = 1; k <= R && k * k < best; ++k) best = min(best, min(row[-k], row[k]) + k * k);
+    // columns wk.c .. wk.c + 2R of the region (the window around the pixel)
+    const int lo = wk.c, hi = wk.c + 2 * R;
+    bool any = false;
+    for (int k = lo >> 5; k <= hi >> 5; ++k) {
+      uint32_t m = rmask[wk.r][k];
+      if (k == lo >> 5) m &= ~((1u << (lo & 31)) - 1u);
+      if (k == hi >> 5 && (hi & 31) != 31) m &= (2u << (hi & 31)) - 1u;
+      any |= m != 0;
+    }
+    int best = DT_INF;
+    if (any) {
+      best = row[0];
+      for (int k = 1; k <= R && k * k < best; ++k) best = min(best, min(row[-k], row[k]) + k * k);
+    }
     const float f = best <= R2 ? __builtin_amdgcn_exp2f((float)best * k2) : 0.f;
     fout[(uint32_t)(J.y0 + wk.r) * (uint32_t)W + (uint32_t)(J.x0 + wk.c)] = f;
   }

@@ -36,10 +36,12 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_gs(const float* __restrict__ gs
   const int xs = __float_as_int(ms[1]);
   const bool flat = !(m > flat_tol);
   double acc = 0.0;
+#pragma unroll 8
   for (int i = threadIdx.x; i < n; i += SP_BLOCK) acc += (double)gs[i] * (double)S[i];
   const double dot = block_sum_d(acc, sh);
   const float corr = (float)(dot / ((double)m * (double)m));
   const float rm = 1.f / m;
+#pragma unroll 8
   for (int i = threadIdx.x; i < n; i += SP_BLOCK)
     gS[i] = flat ? 0.f : gs[i] * rm - (i == xs ? corr : 0.f);
 }
@@ -47,37 +49,118 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_gs(const float* __restrict__ gs
 // Tolerance (on the normalised map) within which values count as tied with an extreme.
 constexpr float kTie = 0x1p-20f;
 
-// Statistics of the N(.) adjoint of one map per workgroup.
-__global__ __launch_bounds__(SP_BLOCK) void k_pa_nstats(const PaMap* __restrict__ maps, float flat_tol) {
-  __shared__ float smn[SP_BLOCK], smx[SP_BLOCK];
-  __shared__ int imn[SP_BLOCK], imx[SP_BLOCK];
+// Statistics of the N(.) adjoint, in three launches over all maps: (1) the (min, max) of
+// tiles of SP_PA_MMT pixels; (2) per 8-row strip, with the map's range reduced from (1):
+// each 8x8 block's maximum of Y = (X - mn) / range and its first position (row-major)
+// within kTie of it, the strip's sums of the block maxima, g Y and g (FP64), and the first
+// positions within kTie of the minimum and the maximum; (3) per map, the scalars below.
+
+__device__ __forceinline__ int block_min_i(int v, int* sh4) {
+  v = wave_min_i(v);
+  __syncthreads();
+  if (lane_id() == 0) sh4[wave_id()] = v;
+  __syncthreads();
+  return min(min(sh4[0], sh4[1]), min(sh4[2], sh4[3]));
+}
+
+// The map's (min, max) from its tile partials (every thread gets them).
+__device__ __forceinline__ void map_range(const PaMap& M, float* sh4, float& mn, float& mx) {
+  const int nt = (M.h * M.w + SP_PA_MMT - 1) / SP_PA_MMT;
+  float a = INFINITY, b = -INFINITY;
+  for (int k = threadIdx.x; k < nt; k += SP_BLOCK) {
+    const float2 v = M.mm[k];
+    a = fminf(a, v.x);
+    b = fmaxf(b, v.y);
+  }
+  mn = block_reduce<OpMin>(a, sh4);
+  mx = block_reduce<OpMax>(b, sh4);
+}
+
+__global__ __launch_bounds__(SP_BLOCK) void k_pa_nmm(const PaMap* __restrict__ maps) {
+  __shared__ float sh4[4];
+  const PaMap M = maps[blockIdx.y];
+  const int n = M.h * M.w, base = blockIdx.x * SP_PA_MMT;
+  if (base >= n) return;   // uniform
+  float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < SP_PA_MMT / SP_BLOCK; ++k) {
+    const int i = base + k * SP_BLOCK + threadIdx.x;
+    const float v = M.X[min(i, n - 1)];
+    mn = i < n ? fminf(mn, v) : mn;
+    mx = i < n ? fmaxf(mx, v) : mx;
+  }
+  mn = block_reduce<OpMin>(mn, sh4);
+  mx = block_reduce<OpMax>(mx, sh4);
+  if (threadIdx.x == 0) M.mm[blockIdx.x] = make_float2(mn, mx);
+}
+
+__global__ __launch_bounds__(SP_BLOCK) void k_pa_nstrip(const PaMap* __restrict__ maps, float flat_tol) {
+  __shared__ float sh4[4];
+  __shared__ int shi[4];
+  __shared__ double sh[SP_BLOCK];
+  const PaMap M = maps[blockIdx.y];
+  if ((int)blockIdx.x >= (M.h + 7) >> 3) return;   // uniform
+  float mn, mx;
+  map_range(M, sh4, mn, mx);
+  const float rng = mx - mn;
+  if (!(rng > flat_tol)) return;   // uniform: a flat map passes no gradient
+  const float rr = 1.f / rng;
+  const int y0 = blockIdx.x * 8, nrow = min(8, M.h - y0), nbx = (M.w + 7) >> 3;
+  double sb = 0.0, sgy = 0.0, sg = 0.0;
+  int jn = 0x7fffffff, jx = 0x7fffffff;
+  // a thread takes column x of the strip; the eight columns of a block are eight
+  // consecutive lanes (the chunks of SP_BLOCK columns start at multiples of 8)
+  for (int x0 = 0; x0 < M.w; x0 += SP_BLOCK) {
+    const int x = x0 + threadIdx.x;
+    const bool cv = x < M.w;
+    float Y[8], cb = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const bool ok = cv && r < nrow;
+      const int i = (y0 + min(r, nrow - 1)) * M.w + min(x, M.w - 1);
+      const float v = (M.X[i] - mn) * rr;
+      Y[r] = ok ? v : -INFINITY;
+      cb = fmaxf(cb, Y[r]);
+      if (ok) {
+        const double g = (double)M.g[i] * (double)M.gs;
+        sgy += g * (double)v;
+        sg += g;
+        if (v <= kTie) jn = min(jn, i);
+        if (v >= 1.f - kTie) jx = min(jx, i);
+      }
+    }
+    // the block's maximum and its first position within kTie (row-major: smallest index)
+    float best = cb;
+    best = fmaxf(best, __shfl_xor(best, 1));
+    best = fmaxf(best, __shfl_xor(best, 2));
+    best = fmaxf(best, __shfl_xor(best, 4));
+    int cand = 0x7fffffff;
+#pragma unroll
+    for (int r = 7; r >= 0; --r)
+      if (Y[r] >= best - kTie) cand = (y0 + r) * M.w + x;
+    cand = min(cand, __shfl_xor(cand, 1));
+    cand = min(cand, __shfl_xor(cand, 2));
+    cand = min(cand, __shfl_xor(cand, 4));
+    if ((threadIdx.x & 7) == 0 && cv) {
+      M.bpos[(y0 >> 3) * nbx + (x >> 3)] = cand;
+      sb += (double)best;
+    }
+  }
+  sb = block_sum_d(sb, sh);
+  sgy = block_sum_d(sgy, sh);
+  sg = block_sum_d(sg, sh);
+  jn = block_min_i(jn, shi);
+  jx = block_min_i(jx, shi);
+  if (threadIdx.x == 0) M.strip[blockIdx.x] = PaStrip{sb, sgy, sg, jn, jx};
+}
+
+__global__ __launch_bounds__(SP_BLOCK) void k_pa_nfin(const PaMap* __restrict__ maps, float flat_tol) {
+  __shared__ float sh4[4];
+  __shared__ int shi[4];
   __shared__ double sh[SP_BLOCK];
   const PaMap M = maps[blockIdx.x];
-  const int n = M.h * M.w;
-  float mn = INFINITY, mx = -INFINITY;
-  int jn = 0x7fffffff, jx = 0x7fffffff;
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-    const float v = M.X[i];
-    if (v < mn) mn = v, jn = i;
-    if (v > mx) mx = v, jx = i;
-  }
-  smn[threadIdx.x] = mn;
-  smx[threadIdx.x] = mx;
-  imn[threadIdx.x] = jn;
-  imx[threadIdx.x] = jx;
-  __syncthreads();
-  for (int s = SP_BLOCK / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      const int o = threadIdx.x + s;
-      if (smn[o] < smn[threadIdx.x] || (smn[o] == smn[threadIdx.x] && imn[o] < imn[threadIdx.x]))
-        smn[threadIdx.x] = smn[o], imn[threadIdx.x] = imn[o];
-      if (smx[o] > smx[threadIdx.x] || (smx[o] == smx[threadIdx.x] && imx[o] < imx[threadIdx.x]))
-        smx[threadIdx.x] = smx[o], imx[threadIdx.x] = imx[o];
-    }
-    __syncthreads();
-  }
-  mn = smn[0];
-  mx = smx[0];
+  float mn, mx;
+  map_range(M, sh4, mn, mx);
   const float rng = mx - mn;
   if (!(rng > flat_tol)) {
     if (threadIdx.x == 0) {
@@ -86,54 +169,22 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_nstats(const PaMap* __restrict_
     }
     return;
   }
-  const float rr = 1.f / rng;
-  // the extremes take their gradient at the first position within kTie of them (on
-  // Y = (X - mn) / range): exact ties then resolve the same way whatever the rounding
-  int jn2 = 0x7fffffff, jx2 = 0x7fffffff;
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-    const float y = (M.X[i] - mn) * rr;
-    if (y <= kTie) jn2 = min(jn2, i);
-    if (y >= 1.f - kTie) jx2 = min(jx2, i);
-  }
-  __syncthreads();
-  imn[threadIdx.x] = jn2;
-  imx[threadIdx.x] = jx2;
-  __syncthreads();
-  for (int s = SP_BLOCK / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      imn[threadIdx.x] = min(imn[threadIdx.x], imn[threadIdx.x + s]);
-      imx[threadIdx.x] = min(imx[threadIdx.x], imx[threadIdx.x + s]);
-    }
-    __syncthreads();
-  }
-  const int gimn = imn[0], gimx = imx[0];
-  // block maxima of Y, each at the first position within kTie of it
-  const int nbx = (M.w + 7) >> 3, nby = (M.h + 7) >> 3, nb = nbx * nby;
-  double sb = 0.0;
-  for (int j = threadIdx.x; j < nb; j += SP_BLOCK) {
-    const int by = (j / nbx) * 8, bx = (j % nbx) * 8;
-    float best = -INFINITY;
-    for (int y = by; y < min(by + 8, M.h); ++y)
-      for (int x = bx; x < min(bx + 8, M.w); ++x) best = fmaxf(best, (M.X[y * M.w + x] - mn) * rr);
-    int bi = -1;
-    for (int y = by; y < min(by + 8, M.h) && bi < 0; ++y)
-      for (int x = bx; x < min(bx + 8, M.w); ++x)
-        if ((M.X[y * M.w + x] - mn) * rr >= best - kTie) {
-          bi = y * M.w + x;
-          break;
-        }
-    M.bpos[j] = bi;
-    sb += (double)best;
+  const int ns = (M.h + 7) >> 3;
+  double sb = 0.0, sgy = 0.0, sg = 0.0;
+  int jn = 0x7fffffff, jx = 0x7fffffff;
+  for (int k = threadIdx.x; k < ns; k += SP_BLOCK) {
+    const PaStrip p = M.strip[k];
+    sb += p.sb;
+    sgy += p.sgy;
+    sg += p.sg;
+    jn = min(jn, p.jn);
+    jx = min(jx, p.jx);
   }
   const double Sb = block_sum_d(sb, sh);
-  double sgy = 0.0, sg = 0.0;
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-    const double g = (double)M.g[i] * (double)M.gs;
-    sgy += g * (double)((M.X[i] - mn) * rr);
-    sg += g;
-  }
   const double Sgy = block_sum_d(sgy, sh);
   const double Sg = block_sum_d(sg, sh);
+  const int gimn = block_min_i(jn, shi), gimx = block_min_i(jx, shi);
+  const int nb = ((M.w + 7) >> 3) * ns;
   if (threadIdx.x == 0) {
     const double mbar = nb > 1 ? (Sb - 1.0) / (nb - 1) : 0.0;
     const double A = (1.0 - mbar) * (1.0 - mbar);
@@ -221,6 +272,7 @@ __device__ __forceinline__ float cs_diff(const PaPlane& P, int y, int x) {
 // the pair's scale max(max |X(c)|, max |X(s)|) by an atomic maximum on the float's bits
 // (order-preserving for non-negative floats; the slot starts at zero).
 __global__ __launch_bounds__(SP_BLOCK) void k_pa_csmap(const PaPlane* __restrict__ tab) {
+  __shared__ float red[SP_BLOCK / 64];
   const PaPlane P = tab[blockIdx.y];
   const int i = blockIdx.x * SP_BLOCK + threadIdx.x;
   float m = 0.f;
@@ -230,9 +282,15 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_csmap(const PaPlane* __restrict
     m = fabsf(P.a[i]);
     if (i < P.hb * P.wb) m = fmaxf(m, fabsf(P.b[i]));
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(P.amax, __float_as_uint(m));
+  // the workgroup's maximum, then one atomic per workgroup
+  m = wave_reduce<OpMax>(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = red[0];
+    for (int k = 1; k < SP_BLOCK / 64; ++k) t = fmaxf(t, red[k]);
+    atomicMax(P.amax, __float_as_uint(t));
+  }
 }
 
 // Derivative of |D| taken as 0 within this fraction of the pair's scale: there the sign of
@@ -281,39 +339,87 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_up_t(const PaPlane* __restrict_
   P.out[i] -= acc;
 }
 
-// dL/dI(l) += sum over the four orientations of the clamped Gabor correlation's transpose:
-// output (y, x) collects every tap (v, u) of every position (y', x') with
-// clamp(y' + v) = y and clamp(x' + u) = x.  a: the four orientation gradients of the level
-// at a plane stride of ha * wa; out: dL/dI(l); taps [4][2 SP_PA_R + 1][2 SP_PA_R + 1], the
-// radius R = d centred in each.
+// dL/dI(l) += sum over the four orientations of the clamped Gabor correlation's transpose.
+// With E(q) = sum_{v,u} h(v, u) gO(q - (v, u)) on the plane extended by the radius (gO zero
+// outside the level), the transpose at p is the sum of E(q) over the q that clamp to p: q = p
+// inside the level, the outside strip folded onto its border row or column.  One 16x16 tile
+// of p per workgroup: the four orientation gradients of the tile plus twice the radius are
+// staged in LDS (orientations interleaved), with the taps; E is computed once for each q the
+// tile's outputs need (the tile, plus the outside strips of a tile on the border), then each
+// output sums its fold set.  a: the four orientation gradients at a plane stride of ha * wa;
+// out: dL/dI(l); taps [4][2 SP_PA_R + 1]^2, tap (v, u) of radius R = d at row v + R and
+// column u + R of each.  RC: the radius when known at compile time (0: read from d).
+constexpr int GT = 16;
+constexpr int GN = GT + 4 * SP_PA_R;
+constexpr int GQ = GT + 2 * SP_PA_R;
+template <int RC>
 __global__ __launch_bounds__(SP_BLOCK) void k_pa_gabor_t(const PaPlane* __restrict__ tab, const float* __restrict__ taps) {
-  const PaPlane P = tab[blockIdx.y];
-  const int n = P.ha * P.wa;
-  const int i = blockIdx.x * SP_BLOCK + threadIdx.x;
-  if (i >= n) return;
-  const int y = i / P.wa, x = i - y * P.wa;
-  const int R = P.d;
-  constexpr int K = 2 * SP_PA_R + 1;   // row stride of the tap table (radius up to SP_PA_R)
-  float acc = 0.f;
-  for (int v = -R; v <= R; ++v) {
-    // rows y' with clamp(y' + v) = y
-    const int ylo = y == 0 ? 0 : max(0, y - v), yhi = y == P.ha - 1 ? P.ha - 1 : min(P.ha - 1, y - v);
-    if (ylo > yhi) continue;
-    for (int u = -R; u <= R; ++u) {
-      const int xlo = x == 0 ? 0 : max(0, x - u), xhi = x == P.wa - 1 ? P.wa - 1 : min(P.wa - 1, x - u);
-      if (xlo > xhi) continue;
-      float s4[4] = {0.f, 0.f, 0.f, 0.f};
-      for (int yy = ylo; yy <= yhi; ++yy)
-        for (int xx = xlo; xx <= xhi; ++xx) {
-          const int o = yy * P.wa + xx;
-#pragma unroll
-          for (int th = 0; th < 4; ++th) s4[th] += P.a[(size_t)th * n + o];
-        }
-#pragma unroll
-      for (int th = 0; th < 4; ++th) acc += taps[(th * K + (v + R)) * K + (u + R)] * s4[th];
+  __shared__ float4 go[GN * GN];
+  __shared__ float4 tp[(2 * SP_PA_R + 1) * (2 * SP_PA_R + 1)];
+  __shared__ float eq[GQ * GQ];
+  const PaPlane P = tab[0];
+  const int h = P.ha, w = P.wa, R = RC ? RC : P.d, K = 2 * R + 1;
+  const size_t n = (size_t)h * w;
+  const int ntx = (w + GT - 1) / GT;
+  const int ty0 = (blockIdx.x / ntx) * GT, tx0 = (blockIdx.x % ntx) * GT;
+  const int E = GT + 4 * R, oy = ty0 - 2 * R, ox = tx0 - 2 * R;
+  for (int i = threadIdx.x; i < E * E; i += SP_BLOCK) {
+    const int r = i / E, c = i - r * E, y = oy + r, x = ox + c;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (y >= 0 && y < h && x >= 0 && x < w) {
+      const size_t o = (size_t)y * w + x;
+      v = make_float4(P.a[o], P.a[n + o], P.a[2 * n + o], P.a[3 * n + o]);
     }
+    go[r * GN + c] = v;
   }
-  P.out[i] += acc;
+  constexpr int KT = 2 * SP_PA_R + 1;   // row stride of the global tap table
+  for (int i = threadIdx.x; i < K * K; i += SP_BLOCK) {
+    const int v = i / K, u = i - v * K;
+    const int o = v * KT + u;
+    tp[i] = make_float4(taps[o], taps[KT * KT + o], taps[2 * KT * KT + o], taps[3 * KT * KT + o]);
+  }
+  __syncthreads();
+  // the q the tile needs: its own positions, and the outside strips on the level's borders
+  const int th = min(GT, h - ty0), tw = min(GT, w - tx0);
+  const int qy0 = ty0 == 0 ? -R : ty0, qy1 = ty0 + th - 1 + (ty0 + th == h ? R : 0);
+  const int qx0 = tx0 == 0 ? -R : tx0, qx1 = tx0 + tw - 1 + (tx0 + tw == w ? R : 0);
+  const int nqx = qx1 - qx0 + 1, nq = (qy1 - qy0 + 1) * nqx;
+  for (int i = threadIdx.x; i < nq; i += SP_BLOCK) {
+    const int qy = qy0 + i / nqx, qx = qx0 + i % nqx;
+    const float4* g0 = go + (qy + R - oy) * GN + (qx + R - ox);   // q - (v - R, u - R) at g0 - v GN - u
+    float e = 0.f;
+#pragma unroll
+    for (int v = 0; v < (RC ? 2 * RC + 1 : 1); ++v) {
+      if (!RC) break;
+      const float4* gr = g0 - v * GN;
+      const float4* tr = tp + v * K;
+#pragma unroll
+      for (int u = 0; u < 2 * RC + 1; ++u) {
+        const float4 g = gr[-u], t = tr[u];
+        e = fmaf(t.x, g.x, fmaf(t.y, g.y, fmaf(t.z, g.z, fmaf(t.w, g.w, e))));
+      }
+    }
+    if (!RC) {
+      for (int v = 0; v < K; ++v) {
+        const float4* gr = g0 - v * GN;
+        const float4* tr = tp + v * K;
+        for (int u = 0; u < K; ++u) {
+          const float4 g = gr[-u], t = tr[u];
+          e = fmaf(t.x, g.x, fmaf(t.y, g.y, fmaf(t.z, g.z, fmaf(t.w, g.w, e))));
+        }
+      }
+    }
+    eq[(qy - qy0) * GQ + (qx - qx0)] = e;
+  }
+  __syncthreads();
+  const int py = ty0 + (int)(threadIdx.x >> 4), px = tx0 + (int)(threadIdx.x & 15);
+  if (py >= h || px >= w) return;
+  const int fy0 = py == 0 ? -R : py, fy1 = py == h - 1 ? h - 1 + R : py;
+  const int fx0 = px == 0 ? -R : px, fx1 = px == w - 1 ? w - 1 + R : px;
+  float acc = 0.f;
+  for (int qy = fy0; qy <= fy1; ++qy)
+    for (int qx = fx0; qx <= fx1; ++qx) acc += eq[(qy - qy0) * GQ + (qx - qx0)];
+  P.out[(size_t)py * w + px] += acc;
 }
 
 // Level-0 features back to the frame: g_frame[t] = own part; g_frame[t-1] += motion part.
@@ -321,14 +427,11 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_feat(const uint8_t* __restrict_
                                                       const uint32_t* __restrict__ maxp, int nmax,
                                                       const float* __restrict__ g0, int n,
                                                       float* __restrict__ gout, float* __restrict__ gprev) {
-  __shared__ uint32_t smax_sh;
-  if (threadIdx.x == 0) {
-    uint32_t m = 0;
-    for (int k = 0; k < nmax; ++k) m = max(m, maxp[k]);
-    smax_sh = m;
-  }
-  __syncthreads();
-  const uint32_t smax = smax_sh;
+  __shared__ float sh4[4];
+  // the frame's colour maximum from the partials (integers below 2^24: exact as floats)
+  uint32_t m = 0;
+  for (int k = threadIdx.x; k < nmax; k += SP_BLOCK) m = max(m, maxp[k]);
+  const uint32_t smax = (uint32_t)block_reduce<OpMax>((float)m, sh4);
   const int i = blockIdx.x * SP_BLOCK + threadIdx.x;
   if (i >= n) return;
   // channels of the level-0 block: I, RG, BY at planes 0-2, M at plane 7
@@ -386,14 +489,16 @@ hipError_t sp_pa_gs(const float* gs, const float* S, const float* ms, int n, flo
   hipLaunchKernelGGL(k_pa_gs, dim3(1), dim3(SP_BLOCK), 0, st, gs, S, ms, n, flat_tol, gS);
   return hipGetLastError();
 }
-hipError_t sp_pa_nadjoint(const PaMap* maps, int nmaps, int maxn, float flat_tol, hipStream_t st) {
+hipError_t sp_pa_nadjoint(const PaMap* maps, int nmaps, int maxn, int maxh, float flat_tol, hipStream_t st) {
   if (nmaps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pa_nstats, dim3(nmaps), dim3(SP_BLOCK), 0, st, maps, flat_tol);
+  hipLaunchKernelGGL(k_pa_nmm, dim3((maxn + SP_PA_MMT - 1) / SP_PA_MMT, nmaps), dim3(SP_BLOCK), 0, st, maps);
+  hipLaunchKernelGGL(k_pa_nstrip, dim3((maxh + 7) / 8, nmaps), dim3(SP_BLOCK), 0, st, maps, flat_tol);
+  hipLaunchKernelGGL(k_pa_nfin, dim3(nmaps), dim3(SP_BLOCK), 0, st, maps, flat_tol);
   hipLaunchKernelGGL(k_pa_napply, dim3(blocks(maxn), nmaps), dim3(SP_BLOCK), 0, st, maps);
   return hipGetLastError();
 }
 hipError_t sp_pa_plane(int kind, const PaPlane* tab, int nplanes, int maxn, int flag, float* const* gc,
-                       const float* taps, hipStream_t st) {
+                       const float* taps, hipStream_t st, int gabor_r) {
   if (nplanes <= 0 || maxn <= 0) return hipSuccess;
   const dim3 g(blocks(maxn), nplanes);
   switch (kind) {
@@ -401,7 +506,15 @@ hipError_t sp_pa_plane(int kind, const PaPlane* tab, int nplanes, int maxn, int 
     case 1: hipLaunchKernelGGL(k_pa_csmap, g, dim3(SP_BLOCK), 0, st, tab); break;
     case 2: hipLaunchKernelGGL(k_pa_csadj, g, dim3(SP_BLOCK), 0, st, tab, gc); break;
     case 3: hipLaunchKernelGGL(k_pa_up_t, g, dim3(SP_BLOCK), 0, st, tab); break;
-    case 4: hipLaunchKernelGGL(k_pa_gabor_t, g, dim3(SP_BLOCK), 0, st, tab, taps); break;
+    case 4: {   // flag: the level's width; maxn its size
+      const int w = flag, h = maxn / flag;
+      const dim3 grid(((h + GT - 1) / GT) * ((w + GT - 1) / GT));
+      if (gabor_r == 6)
+        hipLaunchKernelGGL(k_pa_gabor_t<6>, grid, dim3(SP_BLOCK), 0, st, tab, taps);
+      else
+        hipLaunchKernelGGL(k_pa_gabor_t<0>, grid, dim3(SP_BLOCK), 0, st, tab, taps);
+      break;
+    }
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
