@@ -2314,29 +2314,29 @@ __global__ __launch_bounds__(SP_BLOCK) void k_dt(const Job* __restrict__ jobs, c
     const int n = nr * nc;
     Walk2 wk(tid, nc);
     for (int i0 = 0; i0 < n; i0 += 8 * SP_BLOCK) {
-      int r[8], c[8];
-      bool o[8];
+      int r[8], c[8], in[8], ob[8];
+      uint32_t a[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         r[k] = wk.r;
         c[k] = wk.c;
         wk.next();
+        const int y = ry0 + r[k], x = rx0 + c[k];
+        a[k] = (uint32_t)clampi(y, 0, H - 1) * (uint32_t)W + (uint32_t)clampi(x, 0, W - 1);
+        // in the region and in the frame, as an integer (no short-circuit branch)
+        in[k] = (int)(i0 + k * SP_BLOCK + tid < n) & (int)((unsigned)y < (unsigned)H) & (int)((unsigned)x < (unsigned)W);
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int y = ry0 + r[k], x = rx0 + c[k];
-        const uint32_t a = (uint32_t)clampi(y, 0, H - 1) * (uint32_t)W + (uint32_t)clampi(x, 0, W - 1);
-        o[k] = is_obj(a) && i0 + k * SP_BLOCK + tid < n && y >= 0 && y < H && x >= 0 && x < W;
-      }
+      for (int k = 0; k < 8; ++k) ob[k] = is_obj(a[k]);   // all eight loads issued before any use
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (o[k]) atomicOr(&cmask[c[k]][r[k] >> 5], 1u << (r[k] & 31));
+        if (in[k] & ob[k]) atomicOr(&cmask[c[k]][r[k] >> 5], 1u << (r[k] & 31));
     }
   };
   if (seg)
-    stage([&](uint32_t a) { return seg[a] != 0; });
+    stage([&](uint32_t a) { return (int)(seg[a] != 0); });
   else
-    stage([&](uint32_t a) { return pprev[a] > 0.5f; });
+    stage([&](uint32_t a) { return (int)(pprev[a] > 0.5f); });
   __syncthreads();
   // column pass: the nearest object row at or above / at or below each tile row, from the
   // column's mask (clz / ctz on the word holding the row, then the words before / after)
@@ -2344,22 +2344,22 @@ __global__ __launch_bounds__(SP_BLOCK) void k_dt(const Job* __restrict__ jobs, c
   for (int q = tid; q < J.th * nc; q += SP_BLOCK) {
     const int t = q / nc, c = q - t * nc, rr = t + R;
     const int w = rr >> 5, b = rr & 31;
+    uint32_t cm[DT_W];
+#pragma unroll
+    for (int k = 0; k < DT_W; ++k) cm[k] = cmask[c][k];   // all words read together
+    const uint32_t lo = b == 31 ? 0xffffffffu : ((2u << b) - 1u), hi = ~((1u << b) - 1u);
+    // the highest object row at or above rr (the last nonzero word upward wins) and the
+    // lowest at or below (the last nonzero word downward wins), without data-dependent loops
     int up = -DT_INF, dn = DT_INF;
-    uint32_t m = cmask[c][w] & (b == 31 ? 0xffffffffu : ((2u << b) - 1u));
-    for (int k = w; k >= 0; --k) {
-      if (k < w) m = cmask[c][k];
-      if (m) {
-        up = 32 * k + 31 - __clz(m);
-        break;
-      }
+#pragma unroll
+    for (int k = 0; k < DT_W; ++k) {
+      const uint32_t m = k < w ? cm[k] : (k == w ? cm[k] & lo : 0u);
+      up = m ? 32 * k + 31 - __clz(m) : up;
     }
-    m = cmask[c][w] & ~((1u << b) - 1u);
-    for (int k = w; k < DT_W; ++k) {
-      if (k > w) m = cmask[c][k];
-      if (m) {
-        dn = 32 * k + __ffs(m) - 1;
-        break;
-      }
+#pragma unroll
+    for (int k = DT_W - 1; k >= 0; --k) {
+      const uint32_t m = k > w ? cm[k] : (k == w ? cm[k] & hi : 0u);
+      dn = m ? 32 * k + __ffs(m) - 1 : dn;
     }
     const int d = min(rr - up, dn - rr);
     const bool near = d <= R;
