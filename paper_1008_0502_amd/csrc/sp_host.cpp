@@ -684,8 +684,10 @@ void build_forward_jobs(std::vector<std::vector<Job>>& parts, std::vector<int>& 
     push(JOB_CSSTATS, v);
   }
   v.clear();
-  for (int p = 0; p < g.n_pairs; ++p) v.push_back(Job{s, p, 0, 0, 1, 1, p, JOB_CSFINAL});
-  push(JOB_CSFINAL, v);
+  if (!gp) {   // the reduced-map path's mix computes the N parameters itself
+    for (int p = 0; p < g.n_pairs; ++p) v.push_back(Job{s, p, 0, 0, 1, 1, p, JOB_CSFINAL});
+    push(JOB_CSFINAL, v);
+  }
   v.clear();
   if (gp) {
     add_tiles(v, s, 0, g.Hl[g.c_max], g.Wl[g.c_max], JOB_CSMIX);
@@ -2000,7 +2002,7 @@ void batch_adjoint_tables(sp_batch* b, int nc, size_t lds_a, size_t lds_g) {
     b->rec.push_back(b->jobs.add(JOB_CSG, nc | (set << 8), csg, nv));
     b->rec.back().lds = nc * lds_g;
   }
-  b->rec.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, nv));
+  if (!csf.empty()) b->rec.push_back(b->jobs.add(JOB_CSFINAL, 0, csf, nv));
   if (!csa.empty()) {
     b->rec.push_back(b->jobs.add(JOB_CSAPPLY, nc, csa, nv));
     b->rec.back().lds = nc * lds_a;
@@ -2033,7 +2035,8 @@ int batch_build_tables(sp_batch* b) {
   for (int i = 0; i < n; ++i) nc = std::min(nc, csapply_nc(b->geo[i], b->ca_nc));
   for (int i = 0; i < n; ++i) {
     const Geo& g = b->geo[i];
-    for (int p = 0; p < g.n_pairs; ++p) csf.push_back(Job{i, p, 0, 0, 1, 1, p, JOB_CSFINAL});
+    if (!gpath_ok(g))   // the reduced-map path's mix computes the N parameters itself
+      for (int p = 0; p < g.n_pairs; ++p) csf.push_back(Job{i, p, 0, 0, 1, 1, p, JOB_CSFINAL});
     rgb_jobs(rgb, i, b->h_sd[i], g);
     add_tiles(feat, i, 1, g.Hl[1], g.Wl[1], JOB_FEAT);
     std::vector<std::vector<Job>> mid;
@@ -2101,7 +2104,7 @@ int batch_build_tables(sp_batch* b) {
     b->phases.push_back(b->jobs.add(JOB_CSG, nc | (set << 8), order(csg), n));
     b->phases.back().lds = nc * lds_g;
   }
-  b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, order(csf), n));
+  if (!csf.empty()) b->phases.push_back(b->jobs.add(JOB_CSFINAL, 0, order(csf), n));
   if (!csa.empty()) {
     b->phases.push_back(b->jobs.add(JOB_CSAPPLY, nc, order(csa), n));
     b->phases.back().lds = nc * lds_a;

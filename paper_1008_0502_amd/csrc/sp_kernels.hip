@@ -1974,6 +1974,75 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csg1(const Job* __restrict__ jobs,
 }
 #pragma clang diagnostic pop
 
+// N(.) parameters of the eight maps of a pair from their per-tile partials, one wavefront:
+// lanes 8k..8k+7 take map k, lane 8k+j its tiles j, j+8, j+16, ...  The first 80 tiles are
+// requested at once by load(); finish() takes any further tiles one at a time, then the
+// eight lanes of each map combine by DPP in a fixed order, so the parameters are
+// reproducible bit for bit.  Other loads can be issued between the two calls.
+struct Part3 { float mn, mx, sb; };   // one tile's (min, max, sum of block maxima), 12 bytes
+
+struct PairNp {
+  static constexpr int C = 10;   // tiles per lane requested by load()
+  Part3 v[C];
+
+  __device__ void load(const StreamDesc& sd, int p) {
+    const int nt = sd.cs_nt[p], j = lane_id() & 7;
+    const gp<const float> part = G((const float*)sd.cs_part) + 3 * (size_t)sd.cs_off[p];   // uniform base
+    const uint32_t ko = (uint32_t)(lane_id() >> 3) * (uint32_t)nt;
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const uint32_t t = (uint32_t)min(j + 8 * u, nt - 1);
+      const gp<const Part3> q = (gp<const Part3>)at_bytes(part, 12u * (ko + t));
+      v[u].mn = q->mn;
+      v[u].mx = q->mx;
+      v[u].sb = q->sb;
+    }
+  }
+  // dst[k] = (mn, inv, scale) of map k, inv = scale = 0 for a flat map
+  __device__ void finish(const StreamDesc& sd, int p, float (*dst)[3]) {
+    const int nt = sd.cs_nt[p], c = sd.pc[p], nb = nblocks8(sd.Hl[c], sd.Wl[c]);
+    const int k = lane_id() >> 3, j = lane_id() & 7;
+    float mn = INFINITY, mx = -INFINITY;
+    double s = 0.0;
+    // a position past the last tile read the last tile again: harmless to the minimum and
+    // maximum, masked to +0 in the sum (sums of F >= 0 start at +0, so adding +0 is exact)
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int keep = -(int)(j + 8 * u < nt);
+      mn = fminf(mn, v[u].mn);
+      mx = fmaxf(mx, v[u].mx);
+      s += (double)__int_as_float(__float_as_int(v[u].sb) & keep);
+    }
+    if (nt > 8 * C) {   // large frames
+      const gp<const float> part = G((const float*)sd.cs_part) + 3 * (size_t)sd.cs_off[p];
+      const uint32_t ko = (uint32_t)k * (uint32_t)nt;
+      for (int t = 8 * C + j; t < nt; t += 8) {
+        const gp<const Part3> q = (gp<const Part3>)at_bytes(part, 12u * (ko + (uint32_t)t));
+        mn = fminf(mn, q->mn);
+        mx = fmaxf(mx, q->mx);
+        s += (double)q->sb;
+      }
+    }
+    // quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i with lane
+    // 7 - i of its eight)
+    mn = fminf(mn, dpp_f<0xB1>(mn));
+    mx = fmaxf(mx, dpp_f<0xB1>(mx));
+    s += dpp_d<0xB1>(s);
+    mn = fminf(mn, dpp_f<0x4E>(mn));
+    mx = fmaxf(mx, dpp_f<0x4E>(mx));
+    s += dpp_d<0x4E>(s);
+    mn = fminf(mn, dpp_f<0x141>(mn));
+    mx = fmaxf(mx, dpp_f<0x141>(mx));
+    s += dpp_d<0x141>(s);
+    const NParams q = make_nparams(mn, mx, s, nb, sd.flat_tol);
+    if (j == 0) {
+      dst[k][0] = q.mn;
+      dst[k][1] = q.flat ? 0.f : q.inv;
+      dst[k][2] = q.flat ? 0.f : q.scale;
+    }
+  }
+};
+
 // F-bar_k on a 16x16 c_max tile = sum over pairs of N(reduced map), all 8 channels; then
 // its partial statistics (one 8x8 block per wavefront).
 __global__ __launch_bounds__(SP_BLOCK) void k_csmix(const Job* __restrict__ jobs,
@@ -2005,12 +2074,21 @@ __global__ __launch_bounds__(SP_BLOCK) void k_csmix(const Job* __restrict__ jobs
       for (int k = 0; k < SP_NCH; ++k) g[u][k] = *at_bytes(G(sd.gmap + ((size_t)p * SP_NCH + k) * plane), ob);
     }
   };
-  load_group(0);
-  for (int i = threadIdx.x; i < np * SP_NCH; i += SP_BLOCK) {
-    const NParams q = load_np(G((const float*)sd.cs_np) + 4 * (size_t)i);
-    (&nps[0][0][0])[3 * i] = q.mn;
-    (&nps[0][0][0])[3 * i + 1] = q.flat ? 0.f : q.inv;
-    (&nps[0][0][0])[3 * i + 2] = q.flat ? 0.f : q.scale;
+  // the N parameters of every map, from the partials of the across-scale launch, one
+  // wavefront per pair: the first pair's partials are requested before the first group of
+  // maps and reduced while those are in flight
+  const int w0 = __builtin_amdgcn_readfirstlane(w);
+  {
+    PairNp q;
+    q.load(sd, min(w0, np - 1));   // a wavefront without a pair loads the last one's, unused
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the maps'
+    load_group(0);
+    if (w0 < np) q.finish(sd, w0, nps[w0]);
+  }
+  for (int p = w0 + SP_BLOCK / 64; p < np; p += SP_BLOCK / 64) {
+    PairNp q;
+    q.load(sd, p);
+    q.finish(sd, p, nps[p]);
   }
   __syncthreads();
   float acc[SP_NCH];
