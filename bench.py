@@ -397,7 +397,7 @@ def main():
               for i in range(16)]
         tabs = [Batch.pointer_table([f[t] for f in bf]) for t in range(2)]
         b = Batch([(H, W)] * 16, Params(), mrf=True)
-        # the launch shapes the autotuner picks for this workload (Kalman tile 32 x 64, XCD
+        # the launch shapes the autotuner picks for this workload (Kalman tile 40 x 64, XCD
         # order, two channels per across-scale workgroup), so the counters describe the timed run
         b.set_tune(64, True, 2)
         for i in range(5):

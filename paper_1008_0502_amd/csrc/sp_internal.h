@@ -13,7 +13,7 @@
 #define SP_MAXR 8           // largest Gabor radius
 #define SP_NCH 8            // channels: I, RG, BY, O0, O45, O90, O135, M
 #define SP_BLOCK 256        // threads per workgroup of every tiled kernel (4 wave64)
-#define SP_KAL_ROWS 32      // rows of a prior-update tile (its width is tuned: 16, 32 or 64)
+#define SP_KAL_ROWS 40      // rows of a prior-update tile (its width is tuned: 16, 32 or 64)
 #define SP_RGB_TR 32        // most rows of a colour-statistics tile (four wavefront bands)
 #define SP_RGB_TC 256       // most columns of a colour-statistics tile (4 pixels per lane)
 #define SP_NOALLOC_BYTES (64u << 20)   // device scratch of the allocation-free saliency entry point
