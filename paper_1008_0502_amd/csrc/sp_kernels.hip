@@ -466,6 +466,13 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
   const gbytes gprev = (gbytes)prev;
   uint32_t cv[NP], pv[NP];
   {
+    // A pixel's three bytes come from one 4-byte load (global loads need no alignment):
+    // at the pixel's own offset, or for the frame's last pixel at the offset one byte
+    // lower, shifted down, so no load reads past the frame.  One-pixel frames take the
+    // bytes one at a time.
+    typedef const __attribute__((address_space(1))) uint32_t __attribute__((aligned(1))) * gu32u;
+    const bool words = H * W >= 2;   // uniform
+    const uint32_t last = 3u * (uint32_t)(H * W) - 4u;
     uint32_t o[NP];   // byte offsets: frames hold at most 2^28 pixels
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
@@ -473,14 +480,31 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
       const int ry = i / RW, rx = i - ry * RW;
       const int y = clampi(Y0 + ry, 0, H - 1), x = clampi(X0 + rx, 0, W - 1);
       o[u] = ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 3u;
-      const gbytes c = at_bytes(grgb, o[u]);
-      cv[u] = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
     }
-    if (prev) {
+    if (words) {
+      uint32_t lo[NP];
 #pragma unroll
       for (int u = 0; u < NP; ++u) {
-        const gbytes c = at_bytes(gprev, o[u]);
-        pv[u] = (uint32_t)c[0] + (uint32_t)c[1] + (uint32_t)c[2];
+        lo[u] = min(o[u], last);
+        cv[u] = *(gu32u)at_bytes(grgb, lo[u]);
+      }
+      if (prev) {
+#pragma unroll
+        for (int u = 0; u < NP; ++u) pv[u] = *(gu32u)at_bytes(gprev, lo[u]);
+#pragma unroll
+        for (int u = 0; u < NP; ++u) pv[u] = rgb_sum(pv[u] >> ((o[u] - lo[u]) * 8u));   // the sum ignores the top byte
+      }
+#pragma unroll
+      for (int u = 0; u < NP; ++u) cv[u] = (cv[u] >> ((o[u] - lo[u]) * 8u)) & 0xffffffu;
+    } else {
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const gbytes c = at_bytes(grgb, o[u]);
+        cv[u] = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
+        if (prev) {
+          const gbytes q = at_bytes(gprev, o[u]);
+          pv[u] = (uint32_t)q[0] + (uint32_t)q[1] + (uint32_t)q[2];
+        }
       }
     }
   }
