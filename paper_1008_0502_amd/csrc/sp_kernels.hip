@@ -433,6 +433,14 @@ __device__ __forceinline__ void pairwise_at(const uint8_t* rgb, int H, int W, in
 // Squared colour distance of two packed pixels as a float.
 __device__ __forceinline__ float rgb_d2(uint32_t a, uint32_t b) { return (float)rgb_d2i(a, b); }
 
+// The same from the pixels' squared norms (each computed once): na + nb - 2 a.b, exact in
+// integers.
+__device__ __forceinline__ uint32_t sqnorm(uint32_t a) { return __builtin_amdgcn_udot4(a, a, 0u, false); }
+__device__ __forceinline__ float masked(float v, uint32_t m) { return __uint_as_float(__float_as_uint(v) & m); }
+__device__ __forceinline__ float d2_norms(uint32_t a, uint32_t na, uint32_t b, uint32_t nb) {
+  return (float)(na + nb - 2u * __builtin_amdgcn_udot4(a, b, 0u, false));
+}
+
 // Level-0 features of the region a level-1 tile needs, then one blur + decimation.
 // With io.pairwise set it also writes the pairwise capacities of the tile's level-0
 // pixels (rows 2*y0 .. 2*(y0+th)-1) from the same staged region: every E, S, SE, SW
@@ -441,7 +449,7 @@ __device__ __forceinline__ float rgb_d2(uint32_t a, uint32_t b) { return (float)
 // in two halves of the tile (TH/2 output rows, TH+3 region rows each), which keeps the
 // launch at 8 workgroups per CU.
 template <int TH, int TW>
-__global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
+__global__ __launch_bounds__(SP_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_feat(const Job* __restrict__ jobs,
                                                    const StreamDesc* __restrict__ sds,
                                                    const StepIO* __restrict__ ios, StepIO io0) {
   constexpr int RH = 2 * TH + 3, RW = 2 * TW + 3;   // region of the whole tile
@@ -566,44 +574,43 @@ __global__ __launch_bounds__(SP_BLOCK) void k_feat(const Job* __restrict__ jobs,
         beta = beta_from_share(sd, d2s, sh);   // synchronises the block before and after its reduction
       else
         __syncthreads();
-      // level-0 rows of this half: 2*y0 + r0 .. +TH-1 (region rows r0+2 .. r0+TH+1)
-      const int ylo = 2 * J.y0 + r0, yhi = min(min(H, 2 * (J.y0 + J.th)), ylo + TH);
-      const int xlo = 2 * J.x0, xhi = min(W, 2 * (J.x0 + J.tw));
-      const int cw = xhi - xlo, n = max(0, yhi - ylo) * cw;
-      const size_t plane = (size_t)H * W;
-      const gp<float> pw0 = pairw, pw1 = pairw + plane, pw2 = pairw + 2 * plane, pw3 = pairw + 3 * plane;
-      const CapK ck = cap_consts(beta, sd.lam, sd.potts);
-      // the walk also advances the row's byte offset in the output planes and its index in
-      // the staged region, so a pixel costs no multiply
-      Walk2 wk(threadIdx.x, cw);
-      uint32_t orow = (uint32_t)(ylo + wk.r) * (uint32_t)W * 4u;
-      int rrow = (ylo + wk.r - Y0 - r0) * RW;
-      const uint32_t ostep = (uint32_t)wk.dr * (uint32_t)W * 4u;
-      for (int i = threadIdx.x; i < n; i += SP_BLOCK) {
-        const int y = ylo + wk.r, x = xlo + wk.c;
-        const int r = rrow + (x - X0);
-        const uint32_t c0 = Pk[r];
-        const uint32_t ob = orow + (uint32_t)x * 4u;
-        const bool e = x + 1 < W, s = y + 1 < H;
-        // the staged region holds every neighbour (clamped at the frame edge), so all
-        // four capacities are computed and the ones that leave the frame are zeroed
-        const float cE = pair_cap(ck, rgb_d2(c0, Pk[r + 1]), false);
-        const float cS = pair_cap(ck, rgb_d2(c0, Pk[r + RW]), false);
-        const float cSE = pair_cap(ck, rgb_d2(c0, Pk[r + RW + 1]), true);
-        const float cSW = pair_cap(ck, rgb_d2(c0, Pk[r + RW - 1]), true);
-        st_stream(at_bytes(pw0, ob), e ? cE : 0.f);
-        st_stream(at_bytes(pw1, ob), s ? cS : 0.f);
-        st_stream(at_bytes(pw2, ob), (s && e) ? cSE : 0.f);
-        st_stream(at_bytes(pw3, ob), (s && x > 0) ? cSW : 0.f);
-        wk.r += wk.dr;
-        wk.c += wk.dc;
-        orow += ostep;
-        rrow += wk.dr * RW;
-        if (wk.c >= wk.w) {
-          wk.c -= wk.w;
-          ++wk.r;
-          orow += (uint32_t)W * 4u;
-          rrow += RW;
+      // level-0 rows of this half: 2*y0 + r0 .. +TH-1 (rows 2 .. TH+1 of the staged half),
+      // columns 2*x0 .. +2*TW-1 (region columns 2 .. 2*TW+1).  A thread takes one column and
+      // two consecutive rows: the pixel below its first is its second, and the first's south
+      // neighbours are the second's west, own and east pixels, so eight packed colours and
+      // their norms serve both.  The staged region holds every neighbour (clamped at the
+      // frame edge), so all capacities are computed and the ones that leave the frame zeroed.
+      static_assert(2 * TW == 32 && TH == 2 * (SP_BLOCK / 32), "one column and two rows per thread");
+      const int ylo = 2 * J.y0 + r0, nrow = min(min(H, 2 * (J.y0 + J.th)), ylo + TH) - ylo;
+      const int xlo = 2 * J.x0, cw = min(W, 2 * (J.x0 + J.tw)) - xlo;
+      const int c = threadIdx.x & 31, rr = 2 * (threadIdx.x >> 5);
+      if (c < cw && rr < nrow) {
+        const uint32_t p4 = (uint32_t)H * (uint32_t)W * 4u;   // bytes of a plane: four fit in 2^32
+        const CapK ck = cap_consts(beta, sd.lam, sd.potts);
+        const int x = xlo + c, y = ylo + rr;
+        const uint32_t* q = Pk + (rr + 2) * RW + c + 2;
+        const uint32_t a0 = q[0], a1 = q[1];                         // row y: x, x+1
+        const uint32_t b7 = q[RW - 1], b0 = q[RW], b1 = q[RW + 1];   // row y+1: x-1, x, x+1
+        const uint32_t c7 = q[2 * RW - 1], c0 = q[2 * RW], c1 = q[2 * RW + 1];
+        const uint32_t na0 = sqnorm(a0), nb0 = sqnorm(b0);
+        // capacities that leave the frame are zeroed by masks (selects would become branches)
+        const uint32_t me = x + 1 < W ? ~0u : 0u, mw = x > 0 ? ~0u : 0u;
+        const uint32_t ms0 = y + 1 < H ? ~0u : 0u, ms1 = y + 2 < H ? ~0u : 0u;
+        float v[8];
+        v[0] = masked(pair_cap(ck, d2_norms(a0, na0, a1, sqnorm(a1)), false), me);
+        v[1] = masked(pair_cap(ck, d2_norms(a0, na0, b0, nb0), false), ms0);
+        v[2] = masked(pair_cap(ck, d2_norms(a0, na0, b1, sqnorm(b1)), true), ms0 & me);
+        v[3] = masked(pair_cap(ck, d2_norms(a0, na0, b7, sqnorm(b7)), true), ms0 & mw);
+        v[4] = masked(pair_cap(ck, d2_norms(b0, nb0, b1, sqnorm(b1)), false), me);
+        v[5] = masked(pair_cap(ck, d2_norms(b0, nb0, c0, sqnorm(c0)), false), ms1);
+        v[6] = masked(pair_cap(ck, d2_norms(b0, nb0, c1, sqnorm(c1)), true), ms1 & me);
+        v[7] = masked(pair_cap(ck, d2_norms(b0, nb0, c7, sqnorm(c7)), true), ms1 & mw);
+        const uint32_t ob = ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 4u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) st_stream(at_bytes(pairw, ob + (uint32_t)k * p4), v[k]);
+        if (rr + 1 < nrow) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) st_stream(at_bytes(pairw, ob + (uint32_t)W * 4u + (uint32_t)k * p4), v[4 + k]);
         }
       }
       if (h == 0 && J.tid == 0 && threadIdx.x == 0 && IOF(beta_out)) G(IOF(beta_out))[0] = beta;
