@@ -291,6 +291,15 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
  * sp_batch_prior). */
 int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* prior_ptrs);
 
+/* n consecutive steps in one graph launch: the same kernels, in the same order and with the
+ * same results, as n calls of sp_batch_step(b, rgb_tables[k], NULL), without the idle time
+ * the device spends between two graph launches.  rgb_tables: HOST array of n (1..1024)
+ * DEVICE frame tables as in sp_batch_step (each must stay valid until its step has run).
+ * The graph is captured on the first call with a given n and kept; later calls re-point
+ * the steps whose table changed.  A tape (record_tape > 0) must have room for all n steps
+ * (else SP_ESTATE and no step runs).  Read the priors with sp_batch_prior afterwards. */
+int sp_batch_steps(sp_batch* b, int32_t n, const uint8_t* const* const* rgb_tables);
+
 /* Device pointer to stream i's current prior (valid until the next step). */
 int sp_batch_prior(sp_batch* b, int32_t i, const float** prior);
 /* Device pointers to stream i's saliency map [Hc][Wc] and, with SP_BATCH_MRF, its

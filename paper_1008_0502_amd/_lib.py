@@ -94,6 +94,7 @@ SIGNATURES = [
     ("sp_batch_create", c_int32, [ctypes.POINTER(sp_params), c_int32, ctypes.POINTER(c_int32),
                                   ctypes.POINTER(c_int32), c_int32, c_void_p, ctypes.POINTER(c_void_p)]),
     ("sp_batch_step", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("sp_batch_steps", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
     ("sp_batch_prior", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
     ("sp_batch_outputs", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                                    ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),

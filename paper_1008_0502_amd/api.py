@@ -559,6 +559,17 @@ class Batch:
             raise ValueError(f"prior_ptrs must be a device int64 tensor of {n} pointers")
         check(self.lib.sp_batch_step(self._handle, _ptr(rgb_ptrs), _ptr(prior_ptrs)), "sp_batch_step")
 
+    def steps(self, tables: Sequence[torch.Tensor]) -> None:
+        """Consecutive steps in one graph launch, step k reading the frames of tables[k]
+        (device int64 tensors of n pointers, see pointer_table): the same results as one
+        step() per table."""
+        n = len(self.sizes)
+        for t in tables:
+            if t.dtype != torch.int64 or t.numel() != n or not t.is_cuda:
+                raise ValueError(f"every table must be a device int64 tensor of {n} pointers")
+        arr = (ctypes.c_void_p * len(tables))(*[t.data_ptr() for t in tables])
+        check(self.lib.sp_batch_steps(self._handle, len(tables), arr), "sp_batch_steps")
+
     def reset(self) -> None:
         check(self.lib.sp_batch_reset(self._handle), "sp_batch_reset")
 

@@ -1919,6 +1919,14 @@ struct sp_batch {
   std::vector<Phase> phases;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // several consecutive steps in one graph (sp_batch_steps): captured for mn steps, step k's
+  // first node reading the frame table mtab[k]
+  hipGraph_t mgraph = nullptr;
+  hipGraphExec_t mexec = nullptr;
+  int mn = 0;
+  std::vector<hipGraphNode_t> mnodes;
+  std::vector<const uint8_t* const*> mtab;
+  std::vector<RgbNodeArgs> margs;
   long long steps = 0;
   Profiler prof;
   bool mrf = false;
@@ -2013,6 +2021,23 @@ void batch_adjoint_tables(sp_batch* b, int nc, size_t lds_a, size_t lds_g) {
 
 // (Re)builds the batch's phase program: one launch per phase over every stream.  Drops
 // the captured graph, which is captured again on the next step.
+// Drops the graph of several steps (recaptured by the next sp_batch_steps).
+void batch_drop_multi(sp_batch* b) {
+  if (b->mexec) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipGraphExecDestroy(b->mexec);
+    b->mexec = nullptr;
+  }
+  if (b->mgraph) {
+    (void)hipGraphDestroy(b->mgraph);
+    b->mgraph = nullptr;
+  }
+  b->mn = 0;
+  b->mnodes.clear();
+  b->mtab.clear();
+  b->margs.clear();
+}
+
 int batch_build_tables(sp_batch* b) {
   const int n = b->n;
   if (b->exec) {
@@ -2024,6 +2049,7 @@ int batch_build_tables(sp_batch* b) {
     (void)hipGraphDestroy(b->graph);
     b->graph = nullptr;
   }
+  batch_drop_multi(b);
   b->rgb_node = nullptr;
   b->in_node = nullptr;
   b->jobs.host.clear();
@@ -2149,11 +2175,11 @@ int batch_enqueue(sp_batch* b, hipStream_t st, const uint8_t* const* in_ptrs, hi
   return SP_OK;
 }
 
-// Points the captured graph's first node at this step's frame table.
-int batch_point_graph(sp_batch* b, const uint8_t* const* in_ptrs) {
-  if (in_ptrs == b->in_node) return SP_OK;
+// Points a step's first node (colour statistics + step start) of an instantiated graph at
+// the frame table in_ptrs; a holds the node's arguments.
+int point_rgb_node(sp_batch* b, hipGraphExec_t ex, hipGraphNode_t node, RgbNodeArgs& a,
+                   const uint8_t* const* in_ptrs) {
   const Phase& ph = b->phases.front();
-  RgbNodeArgs& a = b->rgb_args;
   a.jobs = b->jobs.dev + ph.off;
   a.sds = b->d_sd;
   a.ios = b->d_io;
@@ -2162,7 +2188,15 @@ int batch_point_graph(sp_batch* b, const uint8_t* const* in_ptrs) {
   a.bb = BatchBegin{in_ptrs, b->d_st, b->d_io, b->n, 0, b->p.q, b->p.r};
   hipKernelNodeParams kp;
   sp_batch_rgb_node_params(&a, ph.n, &kp);
-  HIPCHK(hipGraphExecKernelNodeSetParams(b->exec, b->rgb_node, &kp));
+  HIPCHK(hipGraphExecKernelNodeSetParams(ex, node, &kp));
+  return SP_OK;
+}
+
+// Points the captured graph's first node at this step's frame table.
+int batch_point_graph(sp_batch* b, const uint8_t* const* in_ptrs) {
+  if (in_ptrs == b->in_node) return SP_OK;
+  const int rc = point_rgb_node(b, b->exec, b->rgb_node, b->rgb_args, in_ptrs);
+  if (rc) return rc;
   b->in_node = in_ptrs;
   return SP_OK;
 }
@@ -2191,11 +2225,41 @@ int batch_capture(sp_batch* b, const uint8_t* const* in_ptrs) {
   return SP_OK;
 }
 
+// Captures n consecutive steps in one graph on the private stream, step k reading the
+// frame table tabs[k] until point_rgb_node points its first node elsewhere.
+int batch_capture_multi(sp_batch* b, int n, const uint8_t* const* const* tabs) {
+  batch_drop_multi(b);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  const bool was = b->prof.on;
+  b->prof.on = false;
+  std::vector<hipGraphNode_t> nodes((size_t)n, nullptr);
+  int rc = SP_OK;
+  for (int k = 0; k < n && rc == SP_OK; ++k) rc = batch_enqueue(b, b->cap_stream, tabs[k], &nodes[(size_t)k]);
+  b->prof.on = was;
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
+  if (rc) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(SP_EHIP, "graph capture: %s", hipGetErrorString(e));
+  b->mgraph = gr;
+  HIPCHK(hipGraphInstantiate(&b->mexec, b->mgraph, nullptr, nullptr, 0));
+  b->mn = n;
+  b->mnodes = nodes;
+  b->mtab.assign(tabs, tabs + n);
+  b->margs.assign((size_t)n, RgbNodeArgs{});
+  return SP_OK;
+}
+
 void batch_free(sp_batch* b) {
   if (!b) return;
   if (b->stream || b->arena) (void)hipStreamSynchronize(b->stream);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->mexec) (void)hipGraphExecDestroy(b->mexec);
+  if (b->mgraph) (void)hipGraphDestroy(b->mgraph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   b->prof.destroy();
   b->bstage.destroy();
@@ -2393,6 +2457,39 @@ int sp_batch_step(sp_batch* b, const uint8_t* const* rgb_ptrs, float* const* pri
     hipError_t e = sp_launch_batch_copy_out(b->n, b->d_st, b->d_sd, prior_ptrs, b->stream);
     if (e != hipSuccess) return fail(SP_EHIP, "copy-out launch: %s", hipGetErrorString(e));
   }
+  return SP_OK;
+}
+
+int sp_batch_steps(sp_batch* b, int32_t n, const uint8_t* const* const* rgb_tables) {
+  g_err.clear();
+  if (!b || !rgb_tables) return fail(SP_EINVAL, "batch and rgb_tables must not be NULL");
+  if (n < 1 || n > 1024) return fail(SP_EINVAL, "steps per call must be 1..1024 (got %d)", n);
+  for (int k = 0; k < n; ++k)
+    if (!rgb_tables[k]) return fail(SP_EINVAL, "frame table %d is NULL", k);
+  if (b->cap > 0 && b->steps + n > b->cap)
+    return fail(SP_ESTATE, "the tape holds %d frames per stream; %d steps after step %lld do not fit", b->cap, n,
+                (long long)b->steps);
+  if (b->prof.on) {   // measurement: every step's phases launched one by one with events
+    for (int k = 0; k < n; ++k) {
+      const int rc = batch_enqueue(b, b->stream, rgb_tables[k]);
+      if (rc) return rc;
+      b->steps += 1;
+    }
+    return SP_OK;
+  }
+  if (!b->mexec || b->mn != n) {
+    const int rc = batch_capture_multi(b, n, rgb_tables);
+    if (rc) return rc;
+  } else {
+    for (int k = 0; k < n; ++k)
+      if (rgb_tables[k] != b->mtab[(size_t)k]) {
+        const int rc = point_rgb_node(b, b->mexec, b->mnodes[(size_t)k], b->margs[(size_t)k], rgb_tables[k]);
+        if (rc) return rc;
+        b->mtab[(size_t)k] = rgb_tables[k];
+      }
+  }
+  HIPCHK(hipGraphLaunch(b->mexec, b->stream));
+  b->steps += n;
   return SP_OK;
 }
 

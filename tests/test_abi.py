@@ -140,6 +140,8 @@ def test_create_rejects_bad_shapes_and_nulls(lib):
     assert lib.sp_batch_mse_mask_loss(None, None, 1, None, None) == _lib.SP_EINVAL
     assert lib.sp_batch_set_weights(None, None, 1e-3, 1e-1) == _lib.SP_EINVAL
     assert lib.sp_batch_step_index(None) == -1 and lib.sp_batch_tape_generation(None) == -1
+    tabs = (ctypes.c_void_p * 2)(None, None)
+    assert lib.sp_batch_steps(None, 2, tabs) == _lib.SP_EINVAL
 
 
 def test_product_path_has_no_cpu_fallback():

@@ -156,3 +156,39 @@ def test_autotuner_keeps_results_identical():
     got = ctx.run_clip(clips[0])["pi"].cpu().numpy()
     assert np.array_equal(got, ref[0]), float(np.abs(got - ref[0]).max())
     ctx.close()
+
+
+def test_several_steps_per_graph_launch_equal_single_steps():
+    print("\n[case] sp_batch_steps (3 steps, 3 more with other tables, then 2) vs sp_batch_step, 3 streams with MRF",
+          flush=True)
+    torch = _torch()
+    import ctypes
+    from paper_1008_0502_amd.api import Batch, Params
+    sizes = [(240, 320), (120, 160), (97, 131)]
+    T = 8
+    clips = [torch.from_numpy(synth.Clip(synth.three_ellipse_spec(H=H, W=W, T=T, seed=90 + i)).stack()[0]).cuda()
+             for i, (H, W) in enumerate(sizes)]
+    tabs = [Batch.pointer_table([c[t] for c in clips]) for t in range(T)]
+    pp = Params()
+    multi = Batch(sizes, pp, mrf=True)
+    single = Batch(sizes, pp, mrf=True)
+
+    def state(b, i, H, W):
+        ptr = ctypes.c_void_p()
+        assert b.lib.sp_batch_prior(b._handle, i, ctypes.byref(ptr)) == 0
+        like = torch.empty((H, W), device="cuda")
+        pS, pU, pPW, pB = b.output_pointers(i)
+        return [_copy_from(ptr.value, like), _copy_from(pU, torch.empty((2, H, W), device="cuda")),
+                _copy_from(pPW, torch.empty((4, H, W), device="cuda")), _copy_from(pB, torch.empty((1,), device="cuda"))]
+
+    for grp in ([0, 1, 2], [3, 4, 5], [6, 7]):
+        multi.steps([tabs[k] for k in grp])
+        for k in grp:
+            single.step(tabs[k])
+        torch.cuda.synchronize()
+        for i, (H, W) in enumerate(sizes):
+            for name, x, y in zip(("prior", "unary", "pairwise", "beta"), state(multi, i, H, W),
+                                  state(single, i, H, W)):
+                assert torch.equal(x, y), (grp, i, name)
+    multi.close()
+    single.close()
