@@ -56,8 +56,9 @@ def _clips(specs):
     return fr, mk
 
 
-def batch_grads(specs, pp, T, autotune=False):
-    """Batched forward of T steps, per-stream loss and adjoint; host copies."""
+def batch_grads(specs, pp, T, autotune=False, per_launch=1):
+    """Batched forward of T steps (per_launch steps per graph launch), per-stream loss and
+    adjoint; host copies."""
     torch = _torch()
     from paper_1008_0502_amd.api import Batch
     fr, mk = _clips(specs)
@@ -67,8 +68,11 @@ def batch_grads(specs, pp, T, autotune=False):
     if autotune:
         print("[tune] " + b.autotune(tabs[0], steps=2).strip().replace("\n", "; "), flush=True)
     b.reset()
-    for t in range(T):
-        b.step(tabs[t])
+    for t0 in range(0, T, per_launch):
+        if per_launch == 1:
+            b.step(tabs[t0])
+        else:
+            b.steps(tabs[t0:t0 + per_launch])
     loss, grads = b.mse_mask_loss(mk, T)
     gw, gq, gr = b.backward(grads)
     torch.cuda.synchronize()
@@ -128,6 +132,21 @@ def test_batch_adjoint_mixed_sizes_two_chunks():
     refs = _oracle_pool.run(_oracle_pool.grad_job, jobs)
     for i in range(len(specs)):
         check_stream(i, got, plain_grads(fr[i], mk[i], pp, T), refs[i], "mixed")
+
+
+def test_batch_adjoint_with_several_steps_per_launch():
+    # the tape recorded by sp_batch_steps (4 + 4 + 2 steps) equals the one of single steps
+    T = 10
+    specs = [("single", 64, 80, T, 3), ("single", 48, 64, T, 8)]
+    banner(f"batched fwd+bwd: 64x80, 48x64 x {T} steps, four steps per graph launch vs one")
+    from paper_1008_0502_amd.api import Params
+    pp = Params(weights=W8, q=2e-3, r=5e-2)
+    one, _, _ = batch_grads(specs, pp, T)
+    four, _, _ = batch_grads(specs, pp, T, per_launch=4)
+    for key in ("loss", "gw", "gq", "gr"):
+        assert np.array_equal(one[key], four[key]), key
+    for i in range(len(specs)):
+        assert np.array_equal(one["pi"][i], four["pi"][i]), i
 
 
 def test_batch_adjoint_bench_shape():
