@@ -564,13 +564,15 @@ def main():
         bgw = torch.empty((NB, 8), dtype=torch.float32, device=dev)
         bgq = torch.empty(NB, dtype=torch.float32, device=dev)
         bgr = torch.empty(NB, dtype=torch.float32, device=dev)
-        tp = [t.data_ptr() for t in btabs]
+        # the clip's frame tables, eight steps per graph launch (sp_batch_steps)
+        tp = [(c_void_p * len(btabs[t0:t0 + 8]))(*[t.data_ptr() for t in btabs[t0:t0 + 8]])
+              for t0 in range(0, T_CLIP, 8)]
 
         def batch_fwd(_):
             if lib.sp_batch_reset(bh):
                 raise RuntimeError(lib.sp_last_error().decode())
-            for t in range(T_CLIP):
-                if lib.sp_batch_step(bh, tp[t], None):
+            for arr in tp:
+                if lib.sp_batch_steps(bh, len(arr), arr):
                     raise RuntimeError(lib.sp_last_error().decode())
 
         def batch_fb(_):
