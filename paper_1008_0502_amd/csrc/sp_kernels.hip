@@ -2174,16 +2174,24 @@ __device__ void consp_nparams(const StreamDesc& sd, NParams* np) {
   __syncthreads();
 }
 
-// Block max of S over the tile with the first row-major argmax -> partial slot.
+// Block max of S over the tile with the first row-major argmax -> partial slot.  Each
+// wavefront finds its maximum and the first index holding it; the block's first index of
+// its maximum is the least of those of the wavefronts whose maximum it is (one barrier).
 __device__ void smax_partial(float v, int idx, bool valid, gp<float> out, float* sh4, int* shi4) {
-  const float m = block_reduce<OpMax>(valid ? v : -INFINITY, sh4);
-  int cand = (valid && v == m) ? idx : 0x7fffffff;
-  cand = wave_min_i(cand);
-  if (lane_id() == 0) shi4[wave_id()] = cand;
+  const float wm = wave_reduce<OpMax>(valid ? v : -INFINITY);
+  const int cand = wave_min_i((valid && v == wm) ? idx : 0x7fffffff);
+  if (lane_id() == 0) {
+    sh4[wave_id()] = wm;
+    shi4[wave_id()] = cand;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
+    const float m = fmaxf(fmaxf(sh4[0], sh4[1]), fmaxf(sh4[2], sh4[3]));
+    int first = 0x7fffffff;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) first = sh4[w] == m ? min(first, shi4[w]) : first;
     out[0] = m;
-    out[1] = __int_as_float(min(min(shi4[0], shi4[1]), min(shi4[2], shi4[3])));
+    out[1] = __int_as_float(first);
   }
 }
 
