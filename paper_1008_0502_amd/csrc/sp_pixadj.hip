@@ -251,7 +251,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_reduce_t(const PaPlane* __restr
 
 // Bilinear sample-aligned tap of target position y at level offset d on n source samples.
 __device__ __forceinline__ void tap(int y, int d, int n, int& i0, int& i1, float& w) {
-  const float fy = fminf((float)y / (float)(1 << d), (float)(n - 1));
+  const float fy = fminf((float)y * __int_as_float((127 - d) << 23), (float)(n - 1));   // y * 2^-d, exact
   i0 = (int)fy;
   i1 = min(i0 + 1, n - 1);
   w = fy - (float)i0;
@@ -312,31 +312,44 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_csadj(const PaPlane* __restrict
 }
 
 // dL/dX(s) += up^T(-gD): the level-s element gathers every level-c element whose bilinear
-// taps read it.  Plane entry: a = gD (level c, ha x wa), out = dL/dX(s) (hb x wb).
+// taps read it, a window of at most 2^(d+1) + 1 rows and columns.  Plane entry: a = gD
+// (level c, ha x wa), out = dL/dX(s) (hb x wb).  Sixteen lanes (one DPP row) per level-s
+// element: lane j takes the window's rows j, j + 16, ..., each as the tap-weighted sum of
+// its columns, and the row adds the lanes' sums in a fixed order.
+constexpr int UPT_L = 16;   // lanes per level-s element
 __global__ __launch_bounds__(SP_BLOCK) void k_pa_up_t(const PaPlane* __restrict__ tab) {
   const PaPlane P = tab[blockIdx.y];
-  const int i = blockIdx.x * SP_BLOCK + threadIdx.x;
-  if (i >= P.hb * P.wb) return;
+  const int e = blockIdx.x * (SP_BLOCK / UPT_L) + (int)(threadIdx.x / UPT_L);
+  const int j = threadIdx.x & (UPT_L - 1);
+  const bool valid = e < P.hb * P.wb;   // every lane stays for the row's sum
+  const int i = valid ? e : 0;
   const int ys = i / P.wb, xs = i - ys * P.wb;
   const int st = 1 << P.d;
+  const int x_lo = max(0, (xs - 1) * st), x_hi = min(P.wa - 1, (xs + 1) * st);
   float acc = 0.f;
-  for (int y = max(0, (ys - 1) * st); y <= min(P.ha - 1, (ys + 1) * st); ++y) {
-    int y0, y1;
-    float wy;
-    tap(y, P.d, P.hb, y0, y1, wy);
-    const float ay = (y0 == ys ? 1.f - wy : 0.f) + (y1 == ys ? wy : 0.f);
-    if (ay == 0.f) continue;
-    float r = 0.f;
-    for (int x = max(0, (xs - 1) * st); x <= min(P.wa - 1, (xs + 1) * st); ++x) {
-      int x0, x1;
-      float wx;
-      tap(x, P.d, P.wb, x0, x1, wx);
-      const float ax = (x0 == xs ? 1.f - wx : 0.f) + (x1 == xs ? wx : 0.f);
-      r += ax * P.a[y * P.wa + x];
+  if (valid)
+    for (int y = max(0, (ys - 1) * st) + j; y <= min(P.ha - 1, (ys + 1) * st); y += UPT_L) {
+      int y0, y1;
+      float wy;
+      tap(y, P.d, P.hb, y0, y1, wy);
+      const float ay = (y0 == ys ? 1.f - wy : 0.f) + (y1 == ys ? wy : 0.f);
+      if (ay == 0.f) continue;
+      float r = 0.f;
+      for (int x = x_lo; x <= x_hi; ++x) {
+        int x0, x1;
+        float wx;
+        tap(x, P.d, P.wb, x0, x1, wx);
+        const float ax = (x0 == xs ? 1.f - wx : 0.f) + (x1 == xs ? wx : 0.f);
+        r += ax * P.a[y * P.wa + x];
+      }
+      acc += ay * r;
     }
-    acc += ay * r;
-  }
-  P.out[i] -= acc;
+  // the sixteen lanes' sums: pairs, quads, halves, the row (every lane ends with the total)
+  acc += dpp_f<0xB1>(acc);
+  acc += dpp_f<0x4E>(acc);
+  acc += dpp_f<0x141>(acc);
+  acc += dpp_f<0x140>(acc);
+  if (valid && j == 0) P.out[e] -= acc;
 }
 
 // dL/dI(l) += sum over the four orientations of the clamped Gabor correlation's transpose.
@@ -505,7 +518,7 @@ hipError_t sp_pa_plane(int kind, const PaPlane* tab, int nplanes, int maxn, int 
     case 0: hipLaunchKernelGGL(k_pa_reduce_t, g, dim3(SP_BLOCK), 0, st, tab, flag); break;
     case 1: hipLaunchKernelGGL(k_pa_csmap, g, dim3(SP_BLOCK), 0, st, tab); break;
     case 2: hipLaunchKernelGGL(k_pa_csadj, g, dim3(SP_BLOCK), 0, st, tab, gc); break;
-    case 3: hipLaunchKernelGGL(k_pa_up_t, g, dim3(SP_BLOCK), 0, st, tab); break;
+    case 3: hipLaunchKernelGGL(k_pa_up_t, dim3(blocks(maxn * UPT_L), nplanes), dim3(SP_BLOCK), 0, st, tab); break;
     case 4: {   // flag: the level's width; maxn its size
       const int w = flag, h = maxn / flag;
       const dim3 grid(((h + GT - 1) / GT) * ((w + GT - 1) / GT));
