@@ -1740,11 +1740,21 @@ int saliency_backward_frames(sp_ctx* c, const uint8_t* frames, int32_t T, float*
         r = sp_pa_plane(2, A.tab_cs[p], SP_NCH, n_l(g.pc[p]), 0, A.gc[p], nullptr, c->stream);
       for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
         r = sp_pa_plane(3, A.tab_up[p], SP_NCH, n_l(g.ps[p]), 0, nullptr, nullptr, c->stream);
-      for (int l = g.top; l >= 1 && r == hipSuccess; --l) {
-        if (A.tab_gab[l])
-          r = sp_pa_plane(4, A.tab_gab[l], 1, n_l(l), g.Wl[l], nullptr, A.taps, c->stream, c->p.gabor_radius);
-        if (r == hipSuccess) r = sp_pa_plane(0, A.tab_pyr[l], 4, n_l(l - 1), 1, nullptr, nullptr, c->stream);
+      // the Gabor transposes of every used level at once (each reads its level's orientation
+      // gradients, complete here, and adds into that level's intensity gradient), then the
+      // pyramid-step transposes from the top level down
+      if (r == hipSuccess) {
+        PaGabLevels L{};
+        int max_tiles = 0;
+        for (int l = g.top; l >= 1; --l)
+          if (A.tab_gab[l]) {
+            L.tab[L.n++] = A.tab_gab[l];
+            max_tiles = std::max(max_tiles, ((g.Hl[l] + 15) / 16) * ((g.Wl[l] + 15) / 16));
+          }
+        r = sp_pa_gabor(L, max_tiles, A.taps, c->stream, c->p.gabor_radius);
       }
+      for (int l = g.top; l >= 1 && r == hipSuccess; --l)
+        r = sp_pa_plane(0, A.tab_pyr[l], 4, n_l(l - 1), 1, nullptr, nullptr, c->stream);
       if (r == hipSuccess)
         r = sp_pa_feat(io.rgb, io.rgb_prev, c->h_sd.rgb_max_part, c->h_sd.n_rgb, A.gX[0], (int)HW,
                        grad_frames + (size_t)t * HW3, t ? grad_frames + (size_t)(t - 1) * HW3 : nullptr, c->stream);

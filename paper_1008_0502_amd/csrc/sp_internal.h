@@ -388,5 +388,11 @@ struct PaPlane {
   int32_t d;               // level offset of the pair
   int32_t pad;
 };
+
+// The Gabor transposes of several levels in one launch: level blockIdx.y's plane table.
+struct PaGabLevels {
+  const PaPlane* tab[SP_MAXL];
+  int32_t n;
+};
 #define SP_PA_R 8          // largest Gabor radius of the adjoint's 2-D taps
 #define SP_PA_SC 8         // floats of the statistics of one N(.) adjoint map

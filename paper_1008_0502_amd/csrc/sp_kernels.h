@@ -52,12 +52,14 @@ hipError_t sp_launch_gmm(int phase, int M, const GmmIO& io, hipStream_t st);
 hipError_t sp_launch_cut(int phase, const CutIO& io, hipStream_t st);
 // Pixel-level adjoint passes (sp_pixadj.hip).  sp_pa_plane kinds: 0 pyramid-step transpose
 // (flag: accumulate), 1 centre-surround map, 2 centre-surround adjoint (adds to gc[plane]),
-// 3 up-sample transpose (subtracts), 4 Gabor transpose (taps: [4][2 SP_PA_R + 1]^2, radius = plane d).
+// 3 up-sample transpose (subtracts).  sp_pa_gabor: the Gabor transposes of every level in
+// L (taps: [4][2 SP_PA_R + 1]^2, radius = plane d), max_tiles the most 16x16 tiles of a level.
 hipError_t sp_pa_gs(const float* gs, const float* S, const float* ms, int n, float flat_tol, float* gS,
                     hipStream_t st);
 hipError_t sp_pa_nadjoint(const PaMap* maps, int nmaps, int maxn, int maxh, float flat_tol, hipStream_t st);
 hipError_t sp_pa_plane(int kind, const PaPlane* tab, int nplanes, int maxn, int flag, float* const* gc,
                        const float* taps, hipStream_t st, int gabor_r = 0);
+hipError_t sp_pa_gabor(const PaGabLevels& L, int max_tiles, const float* taps, hipStream_t st, int gabor_r);
 hipError_t sp_pa_feat(const uint8_t* rgb, const uint8_t* prev, const uint32_t* maxp, int nmax, const float* g0, int n,
                       float* gout, float* gprev, hipStream_t st);
 hipError_t sp_pa_zero(float* p, size_t n, hipStream_t st);

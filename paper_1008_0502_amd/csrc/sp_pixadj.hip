@@ -366,14 +366,15 @@ constexpr int GT = 16;
 constexpr int GN = GT + 4 * SP_PA_R;
 constexpr int GQ = GT + 2 * SP_PA_R;
 template <int RC>
-__global__ __launch_bounds__(SP_BLOCK) void k_pa_gabor_t(const PaPlane* __restrict__ tab, const float* __restrict__ taps) {
+__global__ __launch_bounds__(SP_BLOCK) void k_pa_gabor_t(PaGabLevels L, const float* __restrict__ taps) {
   __shared__ float4 go[GN * GN];
   __shared__ float4 tp[(2 * SP_PA_R + 1) * (2 * SP_PA_R + 1)];
   __shared__ float eq[GQ * GQ];
-  const PaPlane P = tab[0];
+  const PaPlane P = *L.tab[blockIdx.y];   // the level of this workgroup (one launch for every level)
   const int h = P.ha, w = P.wa, R = RC ? RC : P.d, K = 2 * R + 1;
   const size_t n = (size_t)h * w;
   const int ntx = (w + GT - 1) / GT;
+  if ((int)blockIdx.x >= ntx * ((h + GT - 1) / GT)) return;   // the level has fewer tiles
   const int ty0 = (blockIdx.x / ntx) * GT, tx0 = (blockIdx.x % ntx) * GT;
   const int E = GT + 4 * R, oy = ty0 - 2 * R, ox = tx0 - 2 * R;
   for (int i = threadIdx.x; i < E * E; i += SP_BLOCK) {
@@ -519,17 +520,17 @@ hipError_t sp_pa_plane(int kind, const PaPlane* tab, int nplanes, int maxn, int 
     case 1: hipLaunchKernelGGL(k_pa_csmap, g, dim3(SP_BLOCK), 0, st, tab); break;
     case 2: hipLaunchKernelGGL(k_pa_csadj, g, dim3(SP_BLOCK), 0, st, tab, gc); break;
     case 3: hipLaunchKernelGGL(k_pa_up_t, dim3(blocks(maxn * UPT_L), nplanes), dim3(SP_BLOCK), 0, st, tab); break;
-    case 4: {   // flag: the level's width; maxn its size
-      const int w = flag, h = maxn / flag;
-      const dim3 grid(((h + GT - 1) / GT) * ((w + GT - 1) / GT));
-      if (gabor_r == 6)
-        hipLaunchKernelGGL(k_pa_gabor_t<6>, grid, dim3(SP_BLOCK), 0, st, tab, taps);
-      else
-        hipLaunchKernelGGL(k_pa_gabor_t<0>, grid, dim3(SP_BLOCK), 0, st, tab, taps);
-      break;
-    }
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+hipError_t sp_pa_gabor(const PaGabLevels& L, int max_tiles, const float* taps, hipStream_t st, int gabor_r) {
+  if (L.n <= 0 || max_tiles <= 0) return hipSuccess;
+  const dim3 grid(max_tiles, L.n);
+  if (gabor_r == 6)
+    hipLaunchKernelGGL(k_pa_gabor_t<6>, grid, dim3(SP_BLOCK), 0, st, L, taps);
+  else
+    hipLaunchKernelGGL(k_pa_gabor_t<0>, grid, dim3(SP_BLOCK), 0, st, L, taps);
   return hipGetLastError();
 }
 hipError_t sp_pa_feat(const uint8_t* rgb, const uint8_t* prev, const uint32_t* maxp, int nmax, const float* g0, int n,
