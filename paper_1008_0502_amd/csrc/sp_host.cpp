@@ -612,6 +612,13 @@ struct sp_ctx {
     PaPlane* tab_gab[SP_MAXL] = {};      // [1] per used level
     PaPlane* tab_pyr[SP_MAXL] = {};      // [4] per level 1..top: to the level below
     float** gc[SP_MAXP] = {};            // [8] per pair: dL/dX(c) planes
+    // pairs grouped so that no two of a group share a centre level (cs: the adjoint adds to
+    // dL/dX(c)) or a surround level (up: the transpose adds to dL/dX(s)); each group's
+    // tables are contiguous, the cs groups one after another, so one launch covers a group
+    // (cs maps: every pair)
+    int cs_first[SP_MAXP] = {}, cs_count[SP_MAXP] = {}, n_cs = 0;   // pair index of the first table, pairs
+    int up_first[SP_MAXP] = {}, up_count[SP_MAXP] = {}, n_up = 0;
+    int cs_order[SP_MAXP] = {}, up_order[SP_MAXP] = {};              // pairs in table order
     int64_t gen = -1;                    // tape generation of the last saliency_backward
     int T = 0;                           // and its clip length
   } pa;
@@ -749,10 +756,38 @@ void pixadj_layout(sp_ctx* c, Bump& b) {
   A.maps_fbar = b.take<PaMap>(SP_NCH);
   A.maps_F = b.take<PaMap>((size_t)SP_NCH * g.n_pairs);
   for (int l = g.c_min; l < g.c_max; ++l) A.tab_gn[l] = b.take<PaPlane>(SP_NCH);
-  for (int p = 0; p < g.n_pairs; ++p) {
-    A.tab_cs[p] = b.take<PaPlane>(SP_NCH);
-    A.tab_up[p] = b.take<PaPlane>(SP_NCH);
-    A.gc[p] = b.take<float*>(SP_NCH);
+  {
+    // group round r: the pairs that are the r-th of their centre (surround) level
+    auto groups = [&](bool by_surround, int* order, int* first, int* count, int& ng) {
+      int round[SP_MAXP], nr = 0, k = 0;
+      for (int p = 0; p < g.n_pairs; ++p) {
+        int r = 0;
+        for (int q = 0; q < p; ++q) r += (by_surround ? g.ps[q] == g.ps[p] : g.pc[q] == g.pc[p]) ? 1 : 0;
+        round[p] = r;
+        nr = std::max(nr, r + 1);
+      }
+      ng = nr;
+      for (int r = 0; r < nr; ++r) {
+        first[r] = k;
+        count[r] = 0;
+        for (int p = 0; p < g.n_pairs; ++p)
+          if (round[p] == r) {
+            order[k++] = p;
+            ++count[r];
+          }
+      }
+    };
+    groups(false, A.cs_order, A.cs_first, A.cs_count, A.n_cs);
+    groups(true, A.up_order, A.up_first, A.up_count, A.n_up);
+    PaPlane* cs = b.take<PaPlane>((size_t)SP_NCH * g.n_pairs);
+    PaPlane* up = b.take<PaPlane>((size_t)SP_NCH * g.n_pairs);
+    float** gc = b.take<float*>((size_t)SP_NCH * g.n_pairs);
+    for (int k = 0; k < g.n_pairs; ++k) {
+      const int pc = A.cs_order[k], pu = A.up_order[k];
+      A.tab_cs[pc] = cs ? cs + (size_t)k * SP_NCH : nullptr;
+      A.gc[pc] = gc ? gc + (size_t)k * SP_NCH : nullptr;
+      A.tab_up[pu] = up ? up + (size_t)k * SP_NCH : nullptr;
+    }
   }
   for (int l = 1; l <= g.top; ++l) {
     if (g.used & (1u << l)) A.tab_gab[l] = b.take<PaPlane>(1);
@@ -1732,14 +1767,28 @@ int saliency_backward_frames(sp_ctx* c, const uint8_t* frames, int32_t T, float*
         r = sp_pa_plane(0, A.tab_gn[l], SP_NCH, n_l(l), 0, nullptr, nullptr, c->stream);
       // dL/dX and the pairs' scales start at zero
       if (r == hipSuccess) r = sp_pa_zero(A.gX[0], A.gX_floats + (size_t)SP_NCH * g.n_pairs, c->stream);
-      for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
-        r = sp_pa_plane(1, A.tab_cs[p], SP_NCH, n_l(g.pc[p]), 0, nullptr, nullptr, c->stream);
+      // maps of every pair in one launch, then the adjoint and the up-sample transpose one
+      // group at a time (a group's pairs write different levels)
+      auto group_n = [&](const int* order, int first, int count, bool surround) {
+        int mx = 0;
+        for (int k = first; k < first + count; ++k) mx = std::max(mx, n_l(surround ? g.ps[order[k]] : g.pc[order[k]]));
+        return mx;
+      };
+      if (r == hipSuccess)
+        r = sp_pa_plane(1, A.tab_cs[A.cs_order[0]], SP_NCH * g.n_pairs, group_n(A.cs_order, 0, g.n_pairs, false), 0,
+                        nullptr, nullptr, c->stream);
       if (r == hipSuccess)
         r = sp_pa_nadjoint(A.maps_F, SP_NCH * g.n_pairs, maxF, pixadj_dims(g).maxh, c->p.flat_tol, c->stream);
-      for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
-        r = sp_pa_plane(2, A.tab_cs[p], SP_NCH, n_l(g.pc[p]), 0, A.gc[p], nullptr, c->stream);
-      for (int p = 0; p < g.n_pairs && r == hipSuccess; ++p)
-        r = sp_pa_plane(3, A.tab_up[p], SP_NCH, n_l(g.ps[p]), 0, nullptr, nullptr, c->stream);
+      for (int q = 0; q < A.n_cs && r == hipSuccess; ++q) {
+        const int p0 = A.cs_order[A.cs_first[q]];
+        r = sp_pa_plane(2, A.tab_cs[p0], SP_NCH * A.cs_count[q], group_n(A.cs_order, A.cs_first[q], A.cs_count[q], false),
+                        0, A.gc[p0], nullptr, c->stream);
+      }
+      for (int q = 0; q < A.n_up && r == hipSuccess; ++q) {
+        const int p0 = A.up_order[A.up_first[q]];
+        r = sp_pa_plane(3, A.tab_up[p0], SP_NCH * A.up_count[q], group_n(A.up_order, A.up_first[q], A.up_count[q], true),
+                        0, nullptr, nullptr, c->stream);
+      }
       // the Gabor transposes of every used level at once (each reads its level's orientation
       // gradients, complete here, and adds into that level's intensity gradient), then the
       // pyramid-step transposes from the top level down
