@@ -602,7 +602,7 @@ struct sp_ctx {
     float* F[SP_MAXP] = {};              // [8][H_c][W_c] per pair: F, then dL/dF, then sign(D) dL/dF
     float* gX[SP_MAXL] = {};             // [8][H_l][W_l] dL/d(channel maps) per level 0..top
     size_t gX_floats = 0;                // floats of gX, followed by amax
-    uint32_t* amax = nullptr;            // [n_pairs][8] scale of each centre-surround pair (float bits)
+    uint32_t* amax = nullptr;            // [n_pairs][8][SP_PA_AMAX] scale of each centre-surround pair (float bits)
     float* taps = nullptr;               // [4][2R+1][2R+1] Gabor taps
     PaMap* maps_fbar = nullptr;          // [8]
     PaMap* maps_F = nullptr;             // [8 n_pairs]
@@ -745,7 +745,7 @@ void pixadj_layout(sp_ctx* c, Bump& b) {
   for (int p = 0; p < g.n_pairs; ++p) A.F[p] = b.take<float>(SP_NCH * n_l(g.pc[p]));
   A.gX_floats = 0;
   for (int l = 0; l <= g.top; ++l) A.gX_floats += SP_NCH * n_l(l);
-  float* gx = b.take<float>(A.gX_floats + (size_t)SP_NCH * g.n_pairs);
+  float* gx = b.take<float>(A.gX_floats + (size_t)SP_NCH * g.n_pairs * SP_PA_AMAX);
   for (int l = 0; l <= g.top; ++l) {
     A.gX[l] = gx;
     if (gx) gx += SP_NCH * n_l(l);
@@ -897,7 +897,8 @@ hipError_t pixadj_upload(sp_ctx* c) {
     std::vector<float*> gc(SP_NCH);
     for (int k = 0; k < SP_NCH; ++k) {
       float* Fk = A.F[p] + k * n_l(cl);
-      cs[k] = PaPlane{chan(k, cl), chan(k, sl), Fk, A.amax + (size_t)p * SP_NCH + k, g.Hl[cl], g.Wl[cl], g.Hl[sl], g.Wl[sl], sl - cl, 0};
+      cs[k] = PaPlane{chan(k, cl), chan(k, sl), Fk, A.amax + ((size_t)p * SP_NCH + k) * SP_PA_AMAX, g.Hl[cl], g.Wl[cl],
+                      g.Hl[sl], g.Wl[sl], sl - cl, 0};
       up[k] = PaPlane{Fk, nullptr, A.gX[sl] + k * n_l(sl), nullptr, g.Hl[cl], g.Wl[cl], g.Hl[sl], g.Wl[sl], sl - cl, 0};
       gc[k] = A.gX[cl] + k * n_l(cl);
     }
@@ -1766,7 +1767,7 @@ int saliency_backward_frames(sp_ctx* c, const uint8_t* frames, int32_t T, float*
       for (int l = cm - 1; l >= g.c_min && r == hipSuccess; --l)
         r = sp_pa_plane(0, A.tab_gn[l], SP_NCH, n_l(l), 0, nullptr, nullptr, c->stream);
       // dL/dX and the pairs' scales start at zero
-      if (r == hipSuccess) r = sp_pa_zero(A.gX[0], A.gX_floats + (size_t)SP_NCH * g.n_pairs, c->stream);
+      if (r == hipSuccess) r = sp_pa_zero(A.gX[0], A.gX_floats + (size_t)SP_NCH * g.n_pairs * SP_PA_AMAX, c->stream);
       // maps of every pair in one launch, then the adjoint and the up-sample transpose one
       // group at a time (a group's pairs write different levels)
       auto group_n = [&](const int* order, int first, int count, bool surround) {

@@ -383,13 +383,16 @@ struct PaPlane {
   const float* a;          // input plane(s)
   const float* b;
   float* out;
-  uint32_t* amax;          // centre-surround: the pair's scale max |X(c)|, |X(s)| (float bits)
+  uint32_t* amax;          // centre-surround: the pair's scale max |X(c)|, |X(s)| (float bits), as the
+                           // maximum of SP_PA_AMAX slots (workgroup b takes slot b mod SP_PA_AMAX)
   int32_t ha, wa, hb, wb;  // sizes of a and b (b: the surround level of a centre-surround pair)
   int32_t d;               // level offset of the pair
   int32_t pad;
 };
 
 // The Gabor transposes of several levels in one launch: level blockIdx.y's plane table.
+#define SP_PA_AMAX 16   // atomic-maximum slots of a pair's scale (fewer workgroups per address)
+
 struct PaGabLevels {
   const PaPlane* tab[SP_MAXL];
   int32_t n;

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_csmap(const PaPlane* __restrict
   if (threadIdx.x == 0) {
     float t = red[0];
     for (int k = 1; k < SP_BLOCK / 64; ++k) t = fmaxf(t, red[k]);
-    atomicMax(P.amax, __float_as_uint(t));
+    atomicMax(P.amax + (blockIdx.x & (SP_PA_AMAX - 1)), __float_as_uint(t));
   }
 }
 
@@ -305,7 +305,10 @@ __global__ __launch_bounds__(SP_BLOCK) void k_pa_csadj(const PaPlane* __restrict
   if (i >= P.ha * P.wa) return;
   const int y = i / P.wa, x = i - y * P.wa;
   const float D = cs_diff(P, y, x);
-  const float band = kSignBand * __uint_as_float(*P.amax);
+  uint32_t am = 0;   // the pair's scale: the largest of its slots (all >= 0, compared as bits)
+#pragma unroll
+  for (int k = 0; k < SP_PA_AMAX; ++k) am = max(am, P.amax[k]);
+  const float band = kSignBand * __uint_as_float(am);
   const float gd = D > band ? P.out[i] : (D < -band ? -P.out[i] : 0.f);
   P.out[i] = gd;
   gc[blockIdx.y][i] += gd;
