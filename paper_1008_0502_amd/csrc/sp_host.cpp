@@ -598,6 +598,7 @@ struct sp_ctx {
   struct PixAdj {
     float* gS = nullptr;                 // [Hc][Wc] dL/dS of the frame
     float* gfbar = nullptr;              // [8][Hc][Wc]
+    double* gs_part = nullptr;           // per-workgroup partials of sum gs S
     float* gN[SP_MAXL] = {};             // [8][H_l][W_l] dL/dN(F) at centre levels below c_max
     float* F[SP_MAXP] = {};              // [8][H_c][W_c] per pair: F, then dL/dF, then sign(D) dL/dF
     float* gX[SP_MAXL] = {};             // [8][H_l][W_l] dL/d(channel maps) per level 0..top
@@ -740,6 +741,7 @@ void pixadj_layout(sp_ctx* c, Bump& b) {
   auto n_l = [&](int l) { return (size_t)g.Hl[l] * g.Wl[l]; };
   const int Hc = g.Hl[g.c_max], Wc = g.Wl[g.c_max];
   A.gS = b.take<float>((size_t)Hc * Wc);
+  A.gs_part = b.take<double>(((size_t)Hc * Wc + SP_BLOCK - 1) / SP_BLOCK);
   A.gfbar = b.take<float>((size_t)SP_NCH * Hc * Wc);
   for (int l = g.c_min; l < g.c_max; ++l) A.gN[l] = b.take<float>(SP_NCH * n_l(l));
   for (int p = 0; p < g.n_pairs; ++p) A.F[p] = b.take<float>(SP_NCH * n_l(g.pc[p]));
@@ -1762,7 +1764,7 @@ int saliency_backward_frames(sp_ctx* c, const uint8_t* frames, int32_t T, float*
     int rc = SP_OK;
     const hipError_t e = timed(c, JOB_PIX_ADJ, [&]() -> hipError_t {
       hipError_t r = sp_pa_gs(c->gs_all + (size_t)t * plc, c->S_tape + (size_t)t * plc, c->ms_tape + 2 * (size_t)t,
-                              (int)plc, c->p.flat_tol, A.gS, c->stream);
+                              (int)plc, c->p.flat_tol, A.gS, A.gs_part, c->stream);
       if (r == hipSuccess) r = sp_pa_nadjoint(A.maps_fbar, SP_NCH, (int)plc, g.Hl[cm], c->p.flat_tol, c->stream);
       for (int l = cm - 1; l >= g.c_min && r == hipSuccess; --l)
         r = sp_pa_plane(0, A.tab_gn[l], SP_NCH, n_l(l), 0, nullptr, nullptr, c->stream);

@@ -55,7 +55,7 @@ hipError_t sp_launch_cut(int phase, const CutIO& io, hipStream_t st);
 // 3 up-sample transpose (subtracts).  sp_pa_gabor: the Gabor transposes of every level in
 // L (taps: [4][2 SP_PA_R + 1]^2, radius = plane d), max_tiles the most 16x16 tiles of a level.
 hipError_t sp_pa_gs(const float* gs, const float* S, const float* ms, int n, float flat_tol, float* gS,
-                    hipStream_t st);
+                    double* part, hipStream_t st);   // part: (n + 255) / 256 doubles of scratch
 hipError_t sp_pa_nadjoint(const PaMap* maps, int nmaps, int maxn, int maxh, float flat_tol, hipStream_t st);
 hipError_t sp_pa_plane(int kind, const PaPlane* tab, int nplanes, int maxn, int flag, float* const* gc,
                        const float* taps, hipStream_t st, int gabor_r = 0);

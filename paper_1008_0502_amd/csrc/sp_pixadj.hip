@@ -27,23 +27,38 @@ __device__ __forceinline__ float kb(int i) {   // i in -2..2
   return i == 0 ? 0.375f : ((i == 1 || i == -1) ? 0.25f : 0.0625f);
 }
 
-// dL/dS = gs / m - [x = x*] sum(gs S) / m^2 (one workgroup; zero when S was flat).
+// dL/dS = gs / m - [x = x*] sum(gs S) / m^2 (zero when S was flat), in two launches.
 __global__ __launch_bounds__(SP_BLOCK) void k_pa_gs(const float* __restrict__ gs, const float* __restrict__ S,
                                                     const float* __restrict__ ms, int n, float flat_tol,
-                                                    float* __restrict__ gS) {
+                                                    float* __restrict__ gS, double* __restrict__ part) {
+  // every workgroup: SP_BLOCK elements of gs / m and its FP64 partial of sum gs S; the
+  // element at the argmax is left to k_pa_gs_fix
   __shared__ double sh[SP_BLOCK];
   const float m = ms[0];
   const int xs = __float_as_int(ms[1]);
   const bool flat = !(m > flat_tol);
+  const int i = blockIdx.x * SP_BLOCK + threadIdx.x;
+  const float g = i < n ? gs[i] : 0.f;
+  const double dot = block_sum_d(i < n ? (double)g * (double)S[i] : 0.0, sh);
+  if (i < n && i != xs) gS[i] = flat ? 0.f : g * (1.f / m);
+  if (threadIdx.x == 0) part[blockIdx.x] = dot;
+}
+
+// The argmax element of gS: gs / m - (sum gs S) / m^2, the sum from the workgroups' partials
+// in a fixed order.
+__global__ __launch_bounds__(SP_BLOCK) void k_pa_gs_fix(const float* __restrict__ gs, const float* __restrict__ ms,
+                                                        int n, int nparts, float flat_tol, float* __restrict__ gS,
+                                                        const double* __restrict__ part) {
+  __shared__ double sh[SP_BLOCK];
   double acc = 0.0;
-#pragma unroll 8
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK) acc += (double)gs[i] * (double)S[i];
+  for (int k = threadIdx.x; k < nparts; k += SP_BLOCK) acc += part[k];
   const double dot = block_sum_d(acc, sh);
-  const float corr = (float)(dot / ((double)m * (double)m));
-  const float rm = 1.f / m;
-#pragma unroll 8
-  for (int i = threadIdx.x; i < n; i += SP_BLOCK)
-    gS[i] = flat ? 0.f : gs[i] * rm - (i == xs ? corr : 0.f);
+  const int xs = __float_as_int(ms[1]);
+  if (threadIdx.x == 0 && xs >= 0 && xs < n) {   // an index outside the map was written by k_pa_gs
+    const float m = ms[0];
+    const float corr = (float)(dot / ((double)m * (double)m));
+    gS[xs] = !(m > flat_tol) ? 0.f : gs[xs] * (1.f / m) - corr;
+  }
 }
 
 // Tolerance (on the normalised map) within which values count as tied with an extreme.
@@ -502,8 +517,10 @@ inline int blocks(long long n) { return (int)((n + SP_BLOCK - 1) / SP_BLOCK); }
 }  // namespace
 
 hipError_t sp_pa_gs(const float* gs, const float* S, const float* ms, int n, float flat_tol, float* gS,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_pa_gs, dim3(1), dim3(SP_BLOCK), 0, st, gs, S, ms, n, flat_tol, gS);
+                    double* part, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pa_gs, dim3(blocks(n)), dim3(SP_BLOCK), 0, st, gs, S, ms, n, flat_tol, gS, part);
+  hipLaunchKernelGGL(k_pa_gs_fix, dim3(1), dim3(SP_BLOCK), 0, st, gs, ms, n, blocks(n), flat_tol, gS, part);
   return hipGetLastError();
 }
 hipError_t sp_pa_nadjoint(const PaMap* maps, int nmaps, int maxn, int maxh, float flat_tol, hipStream_t st) {
