@@ -2081,8 +2081,6 @@ void batch_adjoint_tables(sp_batch* b, int nc, size_t lds_a, size_t lds_g) {
   b->rec.push_back(b->jobs.add(JOB_CONSP_DOT, 0, dot, nv));
 }
 
-// (Re)builds the batch's phase program: one launch per phase over every stream.  Drops
-// the captured graph, which is captured again on the next step.
 // Drops the graph of several steps (recaptured by the next sp_batch_steps).
 void batch_drop_multi(sp_batch* b) {
   if (b->mexec) {
@@ -2100,6 +2098,8 @@ void batch_drop_multi(sp_batch* b) {
   b->margs.clear();
 }
 
+// (Re)builds the batch's phase program: one launch per phase over every stream.  Drops
+// the captured graphs, which are captured again on the next step.
 int batch_build_tables(sp_batch* b) {
   const int n = b->n;
   if (b->exec) {
@@ -2746,7 +2746,9 @@ int sp_batch_set_weights(sp_batch* b, const float* w, double q, double r) {
   HIPCHK(hipMemcpy(b->d_sd, b->h_sd.data(), sizeof(StreamDesc) * b->n, hipMemcpyHostToDevice));
   if (b->d_rsd)
     HIPCHK(hipMemcpy(b->d_rsd, b->h_rsd.data(), sizeof(StreamDesc) * b->h_rsd.size(), hipMemcpyHostToDevice));
-  b->in_node = nullptr;   // the graph's first node carries Q and R: point it again at the next step
+  // each step's first node carries Q and R: point every one of them again at its next launch
+  b->in_node = nullptr;
+  for (auto& t : b->mtab) t = nullptr;
   if (b->steps > 0) b->tape_ok = false;
   b->tape_gen += 1;
   return SP_OK;

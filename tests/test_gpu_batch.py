@@ -192,3 +192,43 @@ def test_several_steps_per_graph_launch_equal_single_steps():
                 assert torch.equal(x, y), (grp, i, name)
     multi.close()
     single.close()
+
+
+def test_new_variances_reach_a_reused_several_step_graph():
+    print("\n[case] sp_batch_steps with the same tables before and after sp_batch_set_weights, 2 streams", flush=True)
+    torch = _torch()
+    import ctypes
+    from paper_1008_0502_amd.api import Batch, Params
+    sizes = [(120, 160), (97, 131)]
+    clips = [torch.from_numpy(synth.Clip(synth.three_ellipse_spec(H=H, W=W, T=2, seed=140 + i)).stack()[0]).cuda()
+             for i, (H, W) in enumerate(sizes)]
+    tabs = [Batch.pointer_table([c[t] for c in clips]) for t in range(2)]
+    pp = Params()
+    multi, single, kept = (Batch(sizes, pp) for _ in range(3))
+
+    def prior(b, i, H, W):
+        ptr = ctypes.c_void_p()
+        assert b.lib.sp_batch_prior(b._handle, i, ctypes.byref(ptr)) == 0
+        return _copy_from(ptr.value, torch.empty((H, W), device="cuda"))
+
+    multi.steps(tabs)
+    kept.steps(tabs)
+    for t in tabs:
+        single.step(t)
+    # the Kalman variances live in each step's first graph node; the same tables again must
+    # still run with the new ones (the weights of the maps are changed as well)
+    w2 = [1.0, 0.5, 0.5, 1.0, 0.25, 0.25, 0.25, 0.25]
+    for b in (multi, single):
+        b.set_weights(w2, 0.5 * pp.q + 1e-3, 4.0 * pp.r)
+    multi.steps(tabs)
+    kept.set_weights(list(pp.weights), pp.q, pp.r)
+    kept.steps(tabs)
+    for t in tabs:
+        single.step(t)
+    torch.cuda.synchronize()
+    for i, (H, W) in enumerate(sizes):
+        a, s, k = prior(multi, i, H, W), prior(single, i, H, W), prior(kept, i, H, W)
+        assert torch.equal(a, s), i
+        assert not torch.equal(a, k), i   # the change is visible at all
+    for b in (multi, single, kept):
+        b.close()
