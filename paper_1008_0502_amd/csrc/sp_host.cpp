@@ -1862,7 +1862,9 @@ int sp_set_state(sp_ctx* c, const void* buf, size_t bytes) {
   double sc[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(sc, (const char*)buf + HW * sizeof(float), sizeof sc, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (!(sc[0] >= 0) || !std::isfinite(sc[1]) || sc[1] < 0) return fail(SP_EINVAL, "state buffer holds an invalid header");
+  // the step count must be a whole number that an int64_t holds
+  if (!(sc[0] >= 0 && sc[0] < 9.0e18) || sc[0] != std::floor(sc[0]) || !std::isfinite(sc[1]) || sc[1] < 0)
+    return fail(SP_EINVAL, "state buffer holds an invalid header");
   HIPCHK(hipMemcpyAsync(c->pi_state[c->cur], buf, HW * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   c->t = (int64_t)sc[0];
   c->P = sc[1];

@@ -222,6 +222,17 @@ def test_determinism_and_state_resume():
         ctx.saliency_forward(fr[t], fr[t - 1], S)
         assert np.array_equal(ctx.prior_update(S).cpu().numpy(), tail[t - 5])
     assert np.array_equal(np.stack(tail), a[5:])
+    # a header whose step count is not a whole number an int64 holds is refused, and the
+    # context keeps its state
+    from paper_1008_0502_amd._lib import SalpriorError
+    hw = 120 * 160 * 4
+    for bad in (2.5, 1e19, -1.0, float("nan")):
+        hdr = torch.tensor([bad, 0.0], dtype=torch.float64).view(torch.uint8).to(state.device)
+        broken = state.clone()
+        broken[hw:hw + 16] = hdr
+        with pytest.raises(SalpriorError):
+            ctx.set_state(broken)
+        assert ctx.step_index == 10, bad
     ctx.close()
 
 
