@@ -176,7 +176,7 @@ def test_autograd_function_fits_weights():
     assert e <= 1e-3
     # a few projected gradient steps on the weights lower the loss
     opt = torch.optim.SGD([w], lr=20.0)
-    l0 = float(loss)
+    l0 = float(loss.detach())
     for _ in range(5):
         opt.zero_grad()
         pi = SaliencyPrior.apply(ctx, fr, w, q.detach(), r.detach())
@@ -185,7 +185,7 @@ def test_autograd_function_fits_weights():
         opt.step()
         with torch.no_grad():
             w.clamp_(min=0.0)
-    assert float(l) < l0
+    assert float(l.detach()) < l0
     ctx.close()
 
 
