@@ -580,7 +580,7 @@ struct sp_ctx {
   float* gk_part = nullptr;       // [cap][n_lvl0_tiles]
   float* dot_part = nullptr;      // [cap][n_cmax_tiles][8]
   float* cx = nullptr;            // [cap][8]
-  double* gK_scratch = nullptr;   // [cap]
+  double* gK_scratch = nullptr;   // [cap] dL/dK_t, then [cap][8] the steps' shares of dL/dw
   int n_lvl0_tiles = 0;
   int CH = 0;                     // frames per recompute chunk
   StreamDesc* d_rsd = nullptr;    // [CH] recompute streams
@@ -1059,7 +1059,7 @@ int sp_create(const sp_params* p, int32_t H, int32_t W, void* hip_stream, sp_ctx
       c->gk_part = b.take<float>((size_t)c->cap * c->n_lvl0_tiles);
       c->dot_part = b.take<float>((size_t)c->cap * c->h_sd.n_cmax_tiles * SP_NCH);
       c->cx = b.take<float>((size_t)c->cap * SP_NCH);
-      c->gK_scratch = b.take<double>(c->cap);
+      c->gK_scratch = b.take<double>((size_t)c->cap * (1 + SP_NCH));
       c->d_rsd = b.take<StreamDesc>(c->CH);
       c->d_rio = b.take<StepIO>(c->cap);
       for (int i = 0; i < c->CH; ++i) layout_stream(rsd[i], g, *p, b, g.c_min + 1, false);
@@ -2410,7 +2410,7 @@ int sp_batch_create(const sp_params* p, int32_t n, const int32_t* H, const int32
         a.gk_part = bm.take<float>(cap * a.n_lvl0_tiles);
         a.dot_part = bm.take<float>(cap * b->h_sd[i].n_cmax_tiles * SP_NCH);
         a.cx = bm.take<float>(cap * SP_NCH);
-        a.gK = bm.take<double>(cap);
+        a.gK = bm.take<double>((size_t)cap * (1 + SP_NCH));
         a.loss_part = bm.take<float>(b->loss_nblk);
       }
     }

@@ -180,7 +180,7 @@ struct BwdFin {
   const float* cx;           // [T][8] C_k at the argmax
   const float* ms;           // [T][2] max S and argmax
   const float* w;            // [8] channel weights
-  double* gK;                // [T] scratch
+  double* gK;                // scratch: [T] dL/dK_t, then [T][8] each step's share of dL/dw
   float* grad_w;             // [8]
   float* grad_q;             // [1]
   float* grad_r;             // [1]

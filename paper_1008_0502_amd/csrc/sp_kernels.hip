@@ -2685,36 +2685,47 @@ __global__ __launch_bounds__(SP_BLOCK) void k_consp_dot(const Job* __restrict__ 
 // workgroup per stream (tab[blockIdx.x]; tab null: the single stream `one`).  Every
 // stream of a launch ran the same T steps with the same Q and R, so the gains Kd and
 // variances Pd are shared.
-__global__ __launch_bounds__(SP_BLOCK) void k_bwd_final(const BwdFin* __restrict__ tab, BwdFin one, int T,
-                                                        const double* __restrict__ Kd,
-                                                        const double* __restrict__ Pd, double Q, double R,
-                                                        float flat_tol) {
+// One step t (blockIdx.x) of stream blockIdx.y: dL/dK_t from its tile partials, and the
+// step's share of dL/dw (zero-weight steps, where max S is flat, have none), each sum in a
+// fixed order.  The steps are independent, so they run side by side.
+__global__ __launch_bounds__(SP_BLOCK) void k_bwd_step(const BwdFin* __restrict__ tab, BwdFin one, int T,
+                                                       float flat_tol) {
   __shared__ double sh256[SP_BLOCK];
-  __shared__ double gw[SP_NCH];
-  const BwdFin F = tab ? tab[blockIdx.x] : one;
-  if (threadIdx.x < SP_NCH) gw[threadIdx.x] = 0.0;
-  __syncthreads();
-  for (int t = 0; t < T; ++t) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < F.n_lvl0_tiles; i += SP_BLOCK) s += (double)F.gk_part[(size_t)t * F.n_lvl0_tiles + i];
-    s = block_sum_d(s, sh256);
-    if (threadIdx.x == 0) F.gK[t] = s;
-    double A[SP_NCH];
-    for (int k = 0; k < SP_NCH; ++k) {
-      double a = 0.0;
-      for (int i = threadIdx.x; i < F.n_cmax_tiles; i += SP_BLOCK)
-        a += (double)F.dot_part[((size_t)t * F.n_cmax_tiles + i) * SP_NCH + k];
-      A[k] = block_sum_d(a, sh256);
-    }
-    const double m = (double)F.ms[2 * t];
-    if (threadIdx.x == 0 && m > (double)flat_tol) {
-      double Bs = 0.0;
-      for (int k = 0; k < SP_NCH; ++k) Bs += (double)F.w[k] * A[k];
-      for (int k = 0; k < SP_NCH; ++k) gw[k] += A[k] / m - (double)F.cx[(size_t)t * SP_NCH + k] * Bs / (m * m);
-    }
-    __syncthreads();
+  const BwdFin F = tab ? tab[blockIdx.y] : one;
+  const int t = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < F.n_lvl0_tiles; i += SP_BLOCK) s += (double)F.gk_part[(size_t)t * F.n_lvl0_tiles + i];
+  s = block_sum_d(s, sh256);
+  if (threadIdx.x == 0) F.gK[t] = s;
+  double A[SP_NCH];
+  for (int k = 0; k < SP_NCH; ++k) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < F.n_cmax_tiles; i += SP_BLOCK)
+      a += (double)F.dot_part[((size_t)t * F.n_cmax_tiles + i) * SP_NCH + k];
+    A[k] = block_sum_d(a, sh256);
   }
+  const double m = (double)F.ms[2 * t];
+  if (threadIdx.x == 0 && m > (double)flat_tol) {
+    double Bs = 0.0;
+    for (int k = 0; k < SP_NCH; ++k) Bs += (double)F.w[k] * A[k];
+    double* gw = F.gK + T + (size_t)t * SP_NCH;
+    for (int k = 0; k < SP_NCH; ++k) gw[k] = A[k] / m - (double)F.cx[(size_t)t * SP_NCH + k] * Bs / (m * m);
+  }
+}
+
+// Per stream (blockIdx.x): dL/dw as the sum of the steps' shares in step order, then the
+// reverse sweep of the scalar gain recursion for dL/dQ and dL/dR (FP64, one thread).
+__global__ void k_bwd_final(const BwdFin* __restrict__ tab, BwdFin one, int T, const double* __restrict__ Kd,
+                            const double* __restrict__ Pd, double Q, double R, float flat_tol) {
+  const BwdFin F = tab ? tab[blockIdx.x] : one;
   if (threadIdx.x == 0) {
+    double gw[SP_NCH];
+    for (int k = 0; k < SP_NCH; ++k) gw[k] = 0.0;
+    for (int t = 0; t < T; ++t)
+      if ((double)F.ms[2 * t] > (double)flat_tol) {
+        const double* g = F.gK + T + (size_t)t * SP_NCH;
+        for (int k = 0; k < SP_NCH; ++k) gw[k] += g[k];
+      }
     double gQ = 0.0, gR = 0.0, gP = 0.0;
     for (int t = T - 1; t >= 1; --t) {
       const double g = F.gK[t] + R * gP;
@@ -2973,9 +2984,13 @@ hipError_t sp_launch_consp_dot(const Job* jobs, int n, const StreamDesc* sds, co
 hipError_t sp_launch_bwd_final(const BwdFin* tab, const BwdFin* one, int n_streams, int T, const double* Kd,
                                const double* Pd, double Q, double R, float flat_tol, hipStream_t st) {
   if (n_streams <= 0) return hipSuccess;
+  if (T <= 0) return hipErrorInvalidValue;
   BwdFin z{};
-  hipLaunchKernelGGL(k_bwd_final, dim3(n_streams), dim3(SP_BLOCK), 0, st, tab, one ? *one : z, T, Kd, Pd, Q, R,
-                     flat_tol);
+  const BwdFin& o = one ? *one : z;
+  hipLaunchKernelGGL(k_bwd_step, dim3(T, n_streams), dim3(SP_BLOCK), 0, st, tab, o, T, flat_tol);
+  hipError_t e = chk();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bwd_final, dim3(n_streams), dim3(64), 0, st, tab, o, T, Kd, Pd, Q, R, flat_tol);
   return chk();
 }
 
