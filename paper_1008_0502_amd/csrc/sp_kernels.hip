@@ -2713,19 +2713,20 @@ __global__ __launch_bounds__(SP_BLOCK) void k_bwd_step(const BwdFin* __restrict_
   }
 }
 
-// Per stream (blockIdx.x): dL/dw as the sum of the steps' shares in step order, then the
-// reverse sweep of the scalar gain recursion for dL/dQ and dL/dR (FP64, one thread).
+// Per stream (blockIdx.x): dL/dw as the sum of the steps' shares in step order (a thread
+// per weight), and the reverse sweep of the scalar gain recursion for dL/dQ and dL/dR
+// (FP64, one thread).
 __global__ void k_bwd_final(const BwdFin* __restrict__ tab, BwdFin one, int T, const double* __restrict__ Kd,
                             const double* __restrict__ Pd, double Q, double R, float flat_tol) {
   const BwdFin F = tab ? tab[blockIdx.x] : one;
-  if (threadIdx.x == 0) {
-    double gw[SP_NCH];
-    for (int k = 0; k < SP_NCH; ++k) gw[k] = 0.0;
+  if ((int)threadIdx.x < SP_NCH) {   // thread k: dL/dw_k over the steps in order
+    const int k = threadIdx.x;
+    double gw = 0.0;
     for (int t = 0; t < T; ++t)
-      if ((double)F.ms[2 * t] > (double)flat_tol) {
-        const double* g = F.gK + T + (size_t)t * SP_NCH;
-        for (int k = 0; k < SP_NCH; ++k) gw[k] += g[k];
-      }
+      if ((double)F.ms[2 * t] > (double)flat_tol) gw += F.gK[T + (size_t)t * SP_NCH + k];
+    F.grad_w[k] = (float)gw;
+  }
+  if (threadIdx.x == 0) {
     double gQ = 0.0, gR = 0.0, gP = 0.0;
     for (int t = T - 1; t >= 1; --t) {
       const double g = F.gK[t] + R * gP;
@@ -2740,7 +2741,6 @@ __global__ void k_bwd_final(const BwdFin* __restrict__ tab, BwdFin one, int T, c
     gR += gP;
     *F.grad_q = (float)gQ;
     *F.grad_r = (float)gR;
-    for (int k = 0; k < SP_NCH; ++k) F.grad_w[k] = (float)gw[k];
   }
 }
 
@@ -2754,10 +2754,39 @@ __global__ __launch_bounds__(SP_BLOCK) void k_loss(const LossIO* __restrict__ ta
   const float inv_n = (float)(1.0 / (double)n);
   float acc = 0.f;
   const size_t stride = (size_t)gridDim.x * SP_BLOCK;
-  for (size_t i = (size_t)blockIdx.x * SP_BLOCK + threadIdx.x; i < n; i += stride) {
-    const float d = L.prior[i] - (float)L.mask[i];
-    acc += d * d;
-    if (L.grad) L.grad[i] = 2.f * d * inv_n;
+  const bool quads = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(L.prior) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(L.mask) & 3) == 0 && (reinterpret_cast<uintptr_t>(L.grad) & 15) == 0;
+  if (quads) {
+    // four consecutive elements per thread: one 16-byte prior load, one 4-byte mask load,
+    // one 16-byte gradient store
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const gp<const v4f> P4 = G(reinterpret_cast<const v4f*>(L.prior));
+    const gp<const uint32_t> M4 = G(reinterpret_cast<const uint32_t*>(L.mask));
+    const gp<v4f> G4 = G(reinterpret_cast<v4f*>(L.grad));
+    for (size_t q = (size_t)blockIdx.x * SP_BLOCK + threadIdx.x; q < (n >> 2); q += stride) {
+      const v4f p = P4[q];
+      const uint32_t m = M4[q];
+      const float d0 = p.x - (float)(m & 0xffu), d1 = p.y - (float)((m >> 8) & 0xffu);
+      const float d2 = p.z - (float)((m >> 16) & 0xffu), d3 = p.w - (float)(m >> 24);
+      acc += d0 * d0;
+      acc += d1 * d1;
+      acc += d2 * d2;
+      acc += d3 * d3;
+      if (L.grad) {
+        v4f g;
+        g.x = 2.f * d0 * inv_n;
+        g.y = 2.f * d1 * inv_n;
+        g.z = 2.f * d2 * inv_n;
+        g.w = 2.f * d3 * inv_n;
+        G4[q] = g;
+      }
+    }
+  } else {
+    for (size_t i = (size_t)blockIdx.x * SP_BLOCK + threadIdx.x; i < n; i += stride) {
+      const float d = L.prior[i] - (float)L.mask[i];
+      acc += d * d;
+      if (L.grad) L.grad[i] = 2.f * d * inv_n;
+    }
   }
   acc = block_reduce<OpSum>(acc, sh4);
   if (threadIdx.x == 0) L.part[blockIdx.x] = acc;
